@@ -1,0 +1,228 @@
+"""Seeded synthetic pencils (A, B) and start blocks for non-Hermitian FEAST.
+
+This module only draws random numbers and assembles input matrices.  It holds
+none of the eigensolver's arithmetic (no quadrature, no factorisation, no
+filter, no Rayleigh-Ritz), so both the CPU oracle and the GPU path can take
+their inputs from here without sharing any of the method.
+
+The problem is the generalized eigenproblem A x = lambda B x with n x n
+complex A, B, B invertible and B^-1 A diagonalizable (paper, Section 2,
+eqn:eigendecomposition).  The paper's own matrices (QC324/QC2534, the Benzene
+FEM pencils, the transport pencil) are not available, so these pencils stand
+in for them: dense complex non-Hermitian pencils with a prescribed spectrum,
+and complex-symmetric pencils with an absorbing (complex) diagonal term as in
+the paper's Section 5.5 applications.
+
+Every array is complex128, column-major (Fortran order), so that a torch
+tensor made from it with ``torch.from_numpy(M.T).T`` style transposition is not
+needed: callers pass ``np.asfortranarray`` data straight to the C-ABI.
+
+Seeds: configuration i uses base seed 140428910 + i; pencil j of a batch uses
+``default_rng([base, j])``; the start block uses ``default_rng([base, 10**6])``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+BASE_SEED = 140428910
+
+
+def base_seed(cfg: int) -> int:
+    return BASE_SEED + cfg
+
+
+def complex_gaussian(rng: np.random.Generator, shape) -> np.ndarray:
+    """i.i.d. complex Gaussian with E|g|^2 = 1 (real and imaginary parts ~ N(0, 1/2))."""
+    s = math.sqrt(0.5)
+    return (rng.standard_normal(shape) * s + 1j * (rng.standard_normal(shape) * s)).astype(np.complex128)
+
+
+def start_block(cfg: int, n: int, p: int, salt: int = 10**6) -> np.ndarray:
+    """Random start block U0 (n x p), column-major complex128."""
+    rng = np.random.default_rng([base_seed(cfg), salt])
+    return np.asfortranarray(complex_gaussian(rng, (n, p)))
+
+
+# ---------------------------------------------------------------------------
+# spectra
+# ---------------------------------------------------------------------------
+
+def uniform_disk(rng, count, radius):
+    """Area-uniform points in |z| < radius."""
+    r = radius * np.sqrt(rng.random(count))
+    th = 2.0 * np.pi * rng.random(count)
+    return r * np.exp(1j * th)
+
+
+def uniform_annulus(rng, count, r_in, r_out):
+    """Area-uniform points in r_in < |z| < r_out."""
+    u = rng.random(count)
+    r = np.sqrt(r_in * r_in + u * (r_out * r_out - r_in * r_in))
+    th = 2.0 * np.pi * rng.random(count)
+    return r * np.exp(1j * th)
+
+
+def prescribed_spectrum(rng, n, m, r_inside=0.8, r_in=1.5, r_out=5.0, min_abs=1e-3):
+    """m eigenvalues area-uniform in |z| < r_inside and n - m in the annulus r_in < |z| < r_out.
+
+    Inside draws with |z| < min_abs are redrawn so that relative residuals
+    ||Ax - lambda Bx|| / (|lambda| ||Bx||) stay well defined."""
+    inside = uniform_disk(rng, m, r_inside)
+    while m and np.any(np.abs(inside) < min_abs):
+        bad = np.abs(inside) < min_abs
+        inside[bad] = uniform_disk(rng, int(bad.sum()), r_inside)
+    outside = uniform_annulus(rng, n - m, r_in, r_out)
+    return np.concatenate([inside, outside])
+
+
+def clipped_gaussian_basis(rng, n, cond_max=1e3):
+    """Complex Gaussian V whose singular values are clipped to sigma_1 / cond_max (cond(V) <= cond_max)."""
+    G = complex_gaussian(rng, (n, n))
+    Us, s, Wh = np.linalg.svd(G)
+    s2 = np.maximum(s, s[0] / cond_max)
+    if np.all(s2 == s):
+        return G
+    return (Us * s2) @ Wh
+
+
+@dataclasses.dataclass
+class Pencil:
+    """A synthetic pencil with its contour and subspace size.
+
+    A, B: n x n complex128, column-major.  B is None for B = I.
+    lam: prescribed eigenvalues (None when the spectrum is not prescribed).
+    center, radius, aspect: the contour (an ellipse; aspect 1 is a circle).
+    q: number of contour nodes (= number of node factorisations).
+    m0: subspace size p.  m: number of eigenvalues inside (None if unknown)."""
+    A: np.ndarray
+    B: Optional[np.ndarray]
+    lam: Optional[np.ndarray]
+    center: complex
+    radius: float
+    aspect: float
+    q: int
+    m0: int
+    m: Optional[int]
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[0]
+
+    def B_or_identity(self) -> np.ndarray:
+        return np.eye(self.n, dtype=np.complex128) if self.B is None else self.B
+
+
+def prescribed_pencil(rng, n, lam, B=None, cond_max=1e3):
+    """A with B^-1 A = V diag(lam) V^-1 (A = B V diag(lam) V^-1, or V diag(lam) V^-1 if B is None)."""
+    V = clipped_gaussian_basis(rng, n, cond_max)
+    A = (V * lam) @ np.linalg.inv(V)
+    if B is not None:
+        A = B @ A
+    return np.asfortranarray(A), V
+
+
+# ---------------------------------------------------------------------------
+# the five workloads
+# ---------------------------------------------------------------------------
+
+def c0(n: int = 200, m: int = 10, seed_cfg: int = 0, q: int = 16, m0: int = 16) -> Pencil:
+    """Plain FP64 workload: B = I, A = V diag(lam) V^-1 with m eigenvalues in |z| < 0.8 and n - m
+    in 1.5 < |z| < 5; unit circle at 0, q trapezoid nodes, m0 = 16."""
+    rng = np.random.default_rng([base_seed(seed_cfg), 0])
+    lam = prescribed_spectrum(rng, n, m)
+    A, _ = prescribed_pencil(rng, n, lam)
+    return Pencil(A, None, lam, 0j, 1.0, 1.0, q, m0, m, name=f"c0_n{n}")
+
+
+def complex_symmetric_pencil(rng, n, absorb=0.05, bscale=0.05):
+    """A = (G + G^T)/(2 sqrt n) + i diag(absorb (j/n)^2), B = I + bscale (H + H^H)/sqrt n (HPD)."""
+    G = complex_gaussian(rng, (n, n))
+    A = (G + G.T) / (2.0 * math.sqrt(n))
+    del G
+    j = np.arange(1, n + 1, dtype=np.float64)
+    A[np.diag_indices(n)] += 1j * absorb * (j / n) ** 2
+    H = complex_gaussian(rng, (n, n))
+    B = bscale * (H + H.conj().T) / math.sqrt(n)
+    del H
+    B[np.diag_indices(n)] += 1.0
+    return np.asfortranarray(A), np.asfortranarray(B)
+
+
+def c1(n: int = 4096, radius: Optional[float] = None, seed_cfg: int = 1, q: int = 24, m0: int = 64,
+       m: Optional[int] = None) -> Pencil:
+    """Single complex-symmetric generalized pencil, circle at 0.5+0.2i.
+
+    The radius is an input: the stated radius (0.3) encloses far more
+    eigenvalues than m0 = 64 can hold, so the workload uses the radius R*
+    placed in the middle of the gap after the 48th eigenvalue nearest to the
+    center (computed once from the brute-force spectrum and stored with the
+    golden data)."""
+    rng = np.random.default_rng([base_seed(seed_cfg), 0])
+    A, B = complex_symmetric_pencil(rng, n)
+    return Pencil(A, B, None, 0.5 + 0.2j, 0.3 if radius is None else radius, 1.0, q, m0, m, name=f"c1_n{n}")
+
+
+def c3(n: int = 8192, radius: Optional[float] = None, seed_cfg: int = 3, q: int = 32, m0: int = 128,
+       m: Optional[int] = None) -> Pencil:
+    """The same construction as c1 with its own seed; circle at 0, 32 nodes, m0 = 128."""
+    rng = np.random.default_rng([base_seed(seed_cfg), 0])
+    A, B = complex_symmetric_pencil(rng, n)
+    return Pencil(A, B, None, 0j, 0.5 if radius is None else radius, 1.0, q, m0, m, name=f"c3_n{n}")
+
+
+def c2_sizes(count: int = 64, seed_cfg: int = 2, n_lo: int = 256, n_hi: int = 2048):
+    """(n_i, m_i) of the batched workload: n_i ~ U{n_lo..n_hi}, m_i ~ U{8..32}."""
+    rng = np.random.default_rng([base_seed(seed_cfg), 10**6 + 1])
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    ms = rng.integers(8, 33, size=count)
+    return [int(x) for x in ns], [int(x) for x in ms]
+
+
+def c2_pencil(j: int, n: int, m: int, seed_cfg: int = 2, q: int = 16) -> Pencil:
+    """Pencil j of the batched workload: B = I + 0.1 (H + H^H)/(2 sqrt n), A = B V diag(lam) V^-1."""
+    rng = np.random.default_rng([base_seed(seed_cfg), j])
+    lam = prescribed_spectrum(rng, n, m)
+    H = complex_gaussian(rng, (n, n))
+    B = 0.1 * (H + H.conj().T) / (2.0 * math.sqrt(n))
+    B[np.diag_indices(n)] += 1.0
+    B = np.asfortranarray(B)
+    A, _ = prescribed_pencil(rng, n, lam, B=B)
+    m0 = 16 if m <= 16 else 32
+    return Pencil(A, B, lam, 0j, 1.0, 1.0, q, m0, m, name=f"c2_{j}_n{n}")
+
+
+def c2(count: int = 64, seed_cfg: int = 2, n_lo: int = 256, n_hi: int = 2048):
+    ns, ms = c2_sizes(count, seed_cfg, n_lo, n_hi)
+    return [c2_pencil(j, ns[j], ms[j], seed_cfg) for j in range(count)]
+
+
+def c4_pencil(j: int, n: int = 512, seed_cfg: int = 4, m: Optional[int] = None, q: int = 16,
+              m0: int = 64) -> Pencil:
+    """Pencil j of the learned-m0 workload: lam = c + R mu with mu drawn as in c0 (m inside 0.8,
+    the rest in 1.5 < |mu| < 5), c area-uniform in |c| < 2, R ~ U[0.2, 1.5], m ~ U{0..48}, B = I."""
+    rng = np.random.default_rng([base_seed(seed_cfg), j])
+    if m is None:
+        m = int(rng.integers(0, 49))
+    c = complex(uniform_disk(rng, 1, 2.0)[0])
+    R = float(rng.uniform(0.2, 1.5))
+    mu = prescribed_spectrum(rng, n, m, min_abs=0.0)
+    lam = c + R * mu
+    A, _ = prescribed_pencil(rng, n, lam)
+    return Pencil(A, None, lam, c, R, 1.0, q, m0, m, name=f"c4_{j}_n{n}")
+
+
+def rademacher_complex(rng, shape) -> np.ndarray:
+    """Probe vectors with entries (+-1 +- i)/sqrt 2, E[v v^H] = I."""
+    re = rng.integers(0, 2, size=shape) * 2 - 1
+    im = rng.integers(0, 2, size=shape) * 2 - 1
+    return np.asfortranarray((re + 1j * im) / math.sqrt(2.0))
+
+
+def probe_block(cfg: int, j: int, n: int, count: int = 8) -> np.ndarray:
+    rng = np.random.default_rng([base_seed(cfg), 2 * 10**6 + j])
+    return rademacher_complex(rng, (n, count))
