@@ -1,0 +1,174 @@
+/*
+ * feast_mi355x.h - C ABI of the MI355X (gfx950) non-Hermitian FEAST accelerator.
+ *
+ * Problem (paper Section 2, eqn:eigendecomposition): A x = lambda B x with n x n
+ * complex A, B, A != 0, B invertible, B^-1 A diagonalizable.  Wanted: the m
+ * eigenvalues strictly inside a domain C bounded by the ellipse
+ *     phi(t) = c + R (cos(pi/2 (1+t)) + i a sin(pi/2 (1+t))),  t in [-1, 3]
+ * (eqn:ellipses; horizontal semi-axis R, vertical semi-axis a R), and their
+ * right (and for Bi-FEAST left) eigenvectors.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are column-major, interleaved complex double (re, im), i.e. the
+ *     layout of C99 double _Complex and torch.complex128.  Leading dimensions
+ *     are in elements.
+ *   - A, B, U, V, Q, X, Y, workspace are DEVICE pointers owned by the caller.
+ *     The library never allocates device memory: the caller provides one
+ *     workspace of feast_workspace_size() bytes (256-byte aligned) that holds
+ *     the node factorisations, pivots and every intermediate block.
+ *   - stream is a hipStream_t; all device work is enqueued on it.  Calls that
+ *     return results to the host synchronise that stream (stated per call).
+ *   - Return codes follow LAPACK's info convention: 0 = success, -i = argument i
+ *     is invalid, positive values are the FEAST_E* codes below.  A context is
+ *     not thread safe; distinct contexts on distinct streams may run
+ *     concurrently.
+ */
+#ifndef FEAST_MI355X_H
+#define FEAST_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define FEAST_OK 0
+#define FEAST_ENOCONV 1          /* max_iter reached without meeting the stopping rule        */
+#define FEAST_ERANK 2            /* rank check: subspace size too small for the eigenvalue count */
+#define FEAST_EIR 3              /* iterative refinement did not converge for some node        */
+#define FEAST_EDEVICE 4          /* a HIP call failed                                           */
+#define FEAST_EWORKSPACE 5       /* workspace missing, too small or misaligned                 */
+#define FEAST_EREDUCED 6         /* reduced eigenproblem failed (QR iteration did not converge) */
+#define FEAST_EUNSUPPORTED 7     /* option combination not supported                            */
+#define FEAST_ESINGULAR 1000     /* 1000 + k: node system k has an exactly zero pivot, i.e. an
+                                    eigenvalue sits on a quadrature node (the paper assumes no
+                                    eigenvalue lies on the contour, Section 2)                   */
+
+/* ---- contour and options ------------------------------------------------ */
+typedef enum { FEAST_RULE_TRAPEZOID = 0, FEAST_RULE_GAUSS_LEGENDRE = 1 } feast_rule;
+typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1, FEAST_FP16_IR = 2 } feast_precision;
+typedef enum { FEAST_R = 0, FEAST_BI = 1 } feast_variant;
+
+/* The domain C and its quadrature (Section 3).  q is the number of contour
+ * nodes, i.e. of node factorisations: q = 2(K-1) for a K-point trapezoid rule
+ * and q = 2K for a K-point Gauss-Legendre rule on [-1, 1] (q even, q >= 2). */
+typedef struct {
+    double c_re, c_im;   /* center c                                   */
+    double radius;       /* R > 0, horizontal semi-axis               */
+    double aspect;       /* a > 0, vertical semi-axis is a R          */
+    int q;               /* number of nodes                           */
+    int rule;            /* feast_rule                                */
+} feast_contour;
+
+typedef struct {
+    int precision;       /* feast_precision of the node factorisations and solves            */
+    int variant;         /* feast_variant: R-FEAST (right projector) or Bi-FEAST (both)       */
+    int max_iter;        /* FEAST iterations, default 30                                       */
+    double tol;          /* stop when every candidate has ||Ax - lBx|| / (|l| ||Bx||) <= tol
+                            and the candidate count repeats; default 1e-10                     */
+    double candidate_tol;/* a Ritz pair inside C is a candidate when ||Ax - lBx||/||x|| is at
+                            most this (Section 5 preamble); default 1e-4                        */
+    int ir_max;          /* refinement sweeps per solve (FP32/FP16 modes), default 10          */
+    double ir_tol;       /* refinement stops when ||R_k||_F <= ir_tol (||T_k||_1 ||Y_k||_F +
+                            ||rhs||_F); 0 selects 8 sqrt(n) u64                                 */
+} feast_options;
+
+/* Fills *o with the defaults listed above (FP64, R-FEAST). */
+void feast_default_options(feast_options* o);
+
+/* ---- a1: nodes and weights (host only) ----------------------------------
+ * Nodes phi_j and weights sigma_j of the rational filter
+ *     rho(mu) = sum_j sigma_j / (phi_j - mu)          (eqn:quadrature_for_pi)
+ * obtained by folding the Cauchy integral of eqn:cauchy_contour onto [-1, 1]
+ * (eqn:pi) and merging coincident nodes.  z and sigma are HOST arrays of 2q
+ * doubles (interleaved re, im).  Returns 0, or -1 for an invalid contour. */
+int feast_contour_nodes(const feast_contour* contour, double* z, double* sigma);
+
+/* ---- workspace ------------------------------------------------------------
+ * Bytes of device workspace feast_setup needs for an n x n pencil, subspace
+ * size m0, with (has_B = 1) or without (B = I) a B matrix. */
+int feast_workspace_size(int n, int m0, const feast_contour* contour, const feast_options* opts,
+                         int has_B, size_t* bytes);
+
+typedef struct feast_ctx feast_ctx;
+
+/* ---- a2 + a3: node assembly and factorisation -----------------------------
+ * Creates a context for the pencil (A, B) (B = NULL means B = I), assembles
+ * every node matrix T_k = phi_k B - A in the working precision and factors it
+ * (LU with partial pivoting, pivot = largest |re| + |im|, lowest row on ties).
+ * The factorisations stay resident in the workspace for the life of the
+ * context: each node system is factored once for the whole run (Section 5.5).
+ * A and B must stay valid and unchanged until feast_destroy.
+ * Synchronises the stream once to read the zero-pivot flags.
+ * Returns 0, -i for invalid arguments, FEAST_ESINGULAR + k, FEAST_EWORKSPACE,
+ * FEAST_EDEVICE. */
+int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb,
+                const feast_contour* contour, int m0, const feast_options* opts,
+                void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- a4 - a7: one application of the approximate spectral projector --------
+ * side = 0 (right, eqn:Rasp):
+ *     Q = rho(M) U = sum_k sigma_k (phi_k B - A)^-1 (B U)
+ * side = 1 (left, eqn:quadf_surMconj):
+ *     Q = B^-H rho(M)^H B^H U = sum_k conj(sigma_k) (phi_k B - A)^-H (B^H U)
+ * U and Q are device n x ncols blocks (ncols <= m0).  In the FP32/FP16 modes
+ * every node solve is refined in FP64 (see feast_options.ir_*).  Asynchronous
+ * in FP64 mode; the refinement modes synchronise once per sweep.
+ * Returns 0, -i, FEAST_EIR (a node's refinement stalled), FEAST_EDEVICE. */
+int feast_filter(feast_ctx* ctx, int side, int ncols, const void* U, int ldu, void* Q, int ldq);
+
+/* Solve of one node system: Y = T_k^-1 R (side 0) or T_k^-H R (side 1), with
+ * the same refinement as feast_filter.  R and Y are device n x ncols blocks. */
+int feast_node_solve(feast_ctx* ctx, int k, int side, int ncols, const void* R, int ldr, void* Y,
+                     int ldy);
+
+/* ---- a8: the FEAST iteration ----------------------------------------------
+ * Runs Algorithm R-FEAST (variant FEAST_R) or Bi-FEAST (FEAST_BI) of Section 4
+ * from the start block U0 (device n x m0).  After each filter the basis is
+ * orthonormalised (shifted Cholesky-QR, FP64); the reduced m0 x m0 problem is
+ * solved on the host; candidates are Ritz pairs inside C with paper-form
+ * residual <= candidate_tol.  Stops when all candidates have relative residual
+ * <= tol and the count repeats (an empty set counts once no Ritz value lies
+ * inside in two consecutive iterations).  Synchronous.
+ *
+ * Results (caller-owned buffers):
+ *   lambda      host, 2*m0 doubles: candidate eigenvalues first
+ *   resid       host, m0 doubles: relative residuals of the candidates
+ *   X           device n x m0 (ldx): candidate right eigenvectors in the first
+ *               m columns, unit 2-norm
+ *   Y           device n x m0 (ldy), Bi-FEAST only (may be NULL): left
+ *               eigenvectors with Y^H B X = I on the candidates
+ *   history     host, max_iter x 4 doubles or NULL: per iteration the candidate
+ *               count, max relative residual, trace real and imaginary part
+ * Returns 0, FEAST_ENOCONV (results of the last iteration are still written),
+ * FEAST_EREDUCED, FEAST_EDEVICE. */
+typedef struct {
+    int m;               /* number of candidates                */
+    int iterations;
+    int converged;
+    double* lambda;
+    double* resid;
+    void* X; int ldx;
+    void* Y; int ldy;
+    double* history;
+} feast_result;
+
+int feast_iterate(feast_ctx* ctx, const void* U0, int ldu0, feast_result* result);
+
+/* ---- host reduced eigensolver (exposed for testing) ----------------------
+ * Solves the p x p generalized problem Ah w = l Bh w (host, column-major
+ * complex double) by reduction to B^-1 A, Hessenberg form and shifted QR.
+ * lam: 2p doubles; W: right eigenvectors (unit 2-norm columns); Z (may be NULL):
+ * left eigenvectors scaled so that Z^H Bh W = I.  Returns 0, -i,
+ * FEAST_EREDUCED. */
+int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z);
+
+void feast_destroy(feast_ctx* ctx);
+const char* feast_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEAST_MI355X_H */

@@ -1,0 +1,291 @@
+"""ctypes binding of libfeast_mi355x.so (declared in include/feast_mi355x.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.  PyTorch is used
+for device memory (the workspace and the matrices) and for the current HIP stream.  Matrices
+are complex128 torch tensors in column-major layout (``t.stride(0) == 1``); use
+``to_device(array)`` to upload a NumPy array that way.
+
+If the library has not been built, importing works but every call raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+FEAST_OK = 0
+FEAST_ENOCONV = 1
+FEAST_ERANK = 2
+FEAST_EIR = 3
+FEAST_EDEVICE = 4
+FEAST_EWORKSPACE = 5
+FEAST_EREDUCED = 6
+FEAST_EUNSUPPORTED = 7
+FEAST_ESINGULAR = 1000
+
+RULES = {"trapezoid": 0, "gauss-legendre": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2}
+VARIANTS = {"R": 0, "Bi": 1}
+
+EXPORTED = [
+    "feast_default_options", "feast_contour_nodes", "feast_workspace_size", "feast_setup",
+    "feast_filter", "feast_node_solve", "feast_iterate", "feast_reduced_eig", "feast_destroy",
+    "feast_strerror",
+]
+
+
+class Contour(ctypes.Structure):
+    _fields_ = [("c_re", ctypes.c_double), ("c_im", ctypes.c_double), ("radius", ctypes.c_double),
+                ("aspect", ctypes.c_double), ("q", ctypes.c_int), ("rule", ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
+                ("ir_tol", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("lambda_", ctypes.c_void_p), ("resid", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("ldx", ctypes.c_int),
+                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int), ("history", ctypes.c_void_p)]
+
+
+class FeastError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} (code {code})")
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.lib_path()
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_1404_2891_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(path)
+        vp, ip, i, d = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double
+        L.feast_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.feast_default_options.restype = None
+        L.feast_contour_nodes.argtypes = [ctypes.POINTER(Contour), vp, vp]
+        L.feast_contour_nodes.restype = i
+        L.feast_workspace_size.argtypes = [i, i, ctypes.POINTER(Contour), ctypes.POINTER(Options), i,
+                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.feast_workspace_size.restype = i
+        L.feast_setup.argtypes = [ctypes.POINTER(vp), i, vp, i, vp, i, ctypes.POINTER(Contour), i,
+                                  ctypes.POINTER(Options), vp, ctypes.c_size_t, vp]
+        L.feast_setup.restype = i
+        L.feast_filter.argtypes = [vp, i, i, vp, i, vp, i]
+        L.feast_filter.restype = i
+        L.feast_node_solve.argtypes = [vp, i, i, i, vp, i, vp, i]
+        L.feast_node_solve.restype = i
+        L.feast_iterate.argtypes = [vp, vp, i, ctypes.POINTER(Result)]
+        L.feast_iterate.restype = i
+        L.feast_reduced_eig.argtypes = [i, vp, vp, vp, vp, vp]
+        L.feast_reduced_eig.restype = i
+        L.feast_destroy.argtypes = [vp]
+        L.feast_destroy.restype = None
+        L.feast_strerror.argtypes = [i]
+        L.feast_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().feast_strerror(code).decode()
+
+
+def _check(code: int, what: str, ok=(FEAST_OK,)):
+    if code not in ok:
+        raise FeastError(code, what)
+    return code
+
+
+def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid") -> Contour:
+    center = complex(center)
+    return Contour(center.real, center.imag, float(radius), float(aspect), int(q), RULES[rule])
+
+
+def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
+                 ir_tol=0.0) -> Options:
+    o = Options()
+    lib().feast_default_options(ctypes.byref(o))
+    o.precision = PRECISIONS[precision]
+    o.variant = VARIANTS[variant]
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.candidate_tol = float(candidate_tol)
+    o.ir_max = int(ir_max)
+    o.ir_tol = float(ir_tol)
+    return o
+
+
+def contour_nodes(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid"):
+    """(z, sigma) of the filter, computed by the library (host)."""
+    C = make_contour(center, radius, aspect, q, rule)
+    z = np.zeros(q, dtype=np.complex128)
+    s = np.zeros(q, dtype=np.complex128)
+    _check(lib().feast_contour_nodes(ctypes.byref(C), z.ctypes.data, s.ctypes.data), "feast_contour_nodes")
+    return z, s
+
+
+def reduced_eig(Ah: np.ndarray, Bh: np.ndarray, left: bool = False):
+    """Host reduced eigensolver of the library: (lam, W[, Z])."""
+    p = Ah.shape[0]
+    Ah = np.asfortranarray(Ah, dtype=np.complex128)
+    Bh = np.asfortranarray(Bh, dtype=np.complex128)
+    lam = np.zeros(p, dtype=np.complex128)
+    W = np.zeros((p, p), dtype=np.complex128, order="F")
+    Z = np.zeros((p, p), dtype=np.complex128, order="F") if left else None
+    _check(lib().feast_reduced_eig(p, Ah.ctypes.data, Bh.ctypes.data, lam.ctypes.data, W.ctypes.data,
+                                   Z.ctypes.data if left else None), "feast_reduced_eig")
+    return (lam, W, Z) if left else (lam, W)
+
+
+def workspace_size(n, m0, contour: Contour, options: Options, has_B: bool) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().feast_workspace_size(n, m0, ctypes.byref(contour), ctypes.byref(options), int(has_B),
+                                      ctypes.byref(out)), "feast_workspace_size")
+    return out.value
+
+
+# ---------------------------------------------------------------------------
+# torch glue
+# ---------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    """Upload a complex NumPy array as a column-major complex128 tensor."""
+    torch = _torch()
+    a = np.asfortranarray(a, dtype=np.complex128)
+    t = torch.from_numpy(a)  # strides (1, n) for Fortran order
+    return t.to(device)
+
+
+def empty_cm(n, k, device="cuda"):
+    torch = _torch()
+    return torch.empty((k, n), dtype=torch.complex128, device=device).T
+
+
+def _ld(t) -> int:
+    if t.dtype != _torch().complex128:
+        raise TypeError("expected complex128")
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError("expected a column-major 2-D tensor (stride(0) == 1)")
+    return max(t.stride(1), t.shape[0])
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+@dataclasses.dataclass
+class IterateResult:
+    lam: np.ndarray          # candidate eigenvalues
+    resid: np.ndarray        # their relative residuals
+    X: object                # device tensor n x m (candidate right eigenvectors)
+    Y: Optional[object]      # device tensor n x m (left eigenvectors, Bi-FEAST)
+    iterations: int
+    converged: bool
+    history: np.ndarray      # iterations x 4: count, max relative residual, trace re, trace im
+    code: int
+    ritz: np.ndarray         # all m0 Ritz values (candidates first)
+
+
+class Feast:
+    """One pencil: node factorisations resident on the device for the life of the object."""
+
+    def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
+                 precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0):
+        torch = _torch()
+        self.n = A.shape[0]
+        self.m0 = m0
+        self.q = q
+        self.A, self.B = A, B
+        self.contour = make_contour(center, radius, aspect, q, rule)
+        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol)
+        nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        self._ctx = ctypes.c_void_p(None)
+        code = lib().feast_setup(ctypes.byref(self._ctx), self.n, A.data_ptr(), _ld(A),
+                                 None if B is None else B.data_ptr(), 0 if B is None else _ld(B),
+                                 ctypes.byref(self.contour), m0, ctypes.byref(self.options),
+                                 self.workspace.data_ptr(), nbytes, _stream())
+        if code != 0:
+            self.setup_code = code
+            self.close()
+            raise FeastError(code, "feast_setup")
+        self.setup_code = 0
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            lib().feast_destroy(self._ctx)
+        self._ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def filter(self, U, side=0, out=None):
+        """Q = rho(M) U (side 0) or the left filter B^-H rho(M)^H B^H U (side 1)."""
+        k = U.shape[1]
+        Q = empty_cm(self.n, k, U.device) if out is None else out
+        code = lib().feast_filter(self._ctx, side, k, U.data_ptr(), _ld(U), Q.data_ptr(), _ld(Q))
+        _check(code, "feast_filter")
+        return Q
+
+    def node_solve(self, k, R, side=0):
+        Y = empty_cm(self.n, R.shape[1], R.device)
+        _check(lib().feast_node_solve(self._ctx, k, side, R.shape[1], R.data_ptr(), _ld(R), Y.data_ptr(), _ld(Y)),
+               "feast_node_solve")
+        return Y
+
+    def iterate(self, U0) -> IterateResult:
+        torch = _torch()
+        p = self.m0
+        lam = np.zeros(p, dtype=np.complex128)
+        resid = np.zeros(p, dtype=np.float64)
+        hist = np.full((self.options.max_iter, 4), np.nan)
+        X = empty_cm(self.n, p, U0.device)
+        Y = empty_cm(self.n, p, U0.device) if self.options.variant == 1 else None
+        r = Result()
+        r.lambda_ = lam.ctypes.data
+        r.resid = resid.ctypes.data
+        r.X = X.data_ptr()
+        r.ldx = _ld(X)
+        r.Y = Y.data_ptr() if Y is not None else None
+        r.ldy = _ld(Y) if Y is not None else 0
+        r.history = hist.ctypes.data
+        code = lib().feast_iterate(self._ctx, U0.data_ptr(), _ld(U0), ctypes.byref(r))
+        _check(code, "feast_iterate", ok=(FEAST_OK, FEAST_ENOCONV))
+        m = r.m
+        return IterateResult(lam[:m].copy(), resid[:m].copy(), X[:, :m], None if Y is None else Y[:, :m],
+                             r.iterations, bool(r.converged), hist[: r.iterations].copy(), code, lam.copy())

@@ -1,0 +1,676 @@
+// C ABI and host driver of the non-Hermitian FEAST accelerator.
+//
+// feast_setup   : nodes and weights (Section 3), node assembly T_k = phi_k B - A and one LU per
+//                 node kept for the whole run (Section 5.5).
+// feast_filter  : rho(M) U (eqn:Rasp) or its conjugate-transposed twin (eqn:quadf_surMconj): the
+//                 right-hand side B U (or B^H U), q batched multi-RHS solves, optional FP64
+//                 iterative refinement of each solve, and the weighted sum over the nodes.
+// feast_iterate : Algorithms R-FEAST and Bi-FEAST (Section 4) with the basis orthonormalised
+//                 after the filter (shifted Cholesky-QR), the reduced problem solved on the host,
+//                 and the candidate / stopping rule of the Section 5 preamble.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "gemm.h"
+#include "hostla.h"
+#include "lu.h"
+#include "solve.h"
+
+using namespace fm;
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr int NB = 64;          // block size of the factorisation and of the solves
+constexpr size_t ALIGN = 256;
+
+struct Bump {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = align_up(off, ALIGN);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int splitk_for(int K) { return std::max(1, std::min(64, K / 256)); }
+
+}  // namespace
+
+struct feast_ctx {
+    int n = 0, m0 = 0, q = 0, nsteps = 0;
+    long ldf = 0;
+    Prec prec = Prec::F64;
+    feast_contour C{};
+    feast_options o{};
+    hipStream_t st = nullptr;
+    const z64* A = nullptr; long lda = 0;
+    const z64* B = nullptr; long ldb = 0;
+    std::vector<z64> z, sig;
+    std::vector<double> norm1;
+    // device
+    z64 *z_d = nullptr, *wR = nullptr, *wL = nullptr, *negz = nullptr, *negzc = nullptr, *ones = nullptr;
+    double *norm1_d = nullptr, *colsum = nullptr;
+    LUStore lu;
+    void *Yw = nullptr, *Xw = nullptr, *Ow = nullptr;
+    z64 *Y64 = nullptr, *R64 = nullptr;
+    double* nrm_d = nullptr;         // 2q + 1 doubles
+    int* mask_d = nullptr;
+    z64 *BU = nullptr, *QAB = nullptr, *XAB = nullptr, *T1 = nullptr, *Vb = nullptr, *Pb = nullptr;
+    z64 *G_d = nullptr, *Rinv_d = nullptr, *AhBh = nullptr, *W_d = nullptr, *Z_d = nullptr, *lam_d = nullptr;
+    double* norms_d = nullptr;
+    int* idx_d = nullptr;
+    void* partial = nullptr;
+    // host staging (pinned)
+    char* h = nullptr;
+    size_t hbytes = 0;
+    // refinement statistics of the last filter
+    int ir_sweeps = 0;
+    double ir_relres = 0.0;
+};
+
+namespace {
+
+size_t elem_bytes(Prec p) { return p == Prec::F64 ? sizeof(z64) : sizeof(c32); }
+
+void layout(feast_ctx* c, Bump& b, bool has_B) {
+    const int n = c->n, p = c->m0, q = c->q;
+    const size_t E = elem_bytes(c->prec);
+    const size_t np = (size_t)n * p;
+    c->z_d = b.take<z64>(q);
+    c->wR = b.take<z64>(q);
+    c->wL = b.take<z64>(q);
+    c->negz = b.take<z64>(q);
+    c->negzc = b.take<z64>(q);
+    c->ones = b.take<z64>(q);
+    c->norm1_d = b.take<double>(q);
+    c->lu.F = b.take<char>((size_t)q * n * c->ldf * E);
+    c->lu.ipiv = b.take<int>((size_t)q * n);
+    c->lu.perm = b.take<int>((size_t)q * n);
+    c->lu.iperm = b.take<int>((size_t)q * n);
+    c->lu.Linv = b.take<char>((size_t)q * c->nsteps * NB * NB * E);
+    c->lu.Uinv = b.take<char>((size_t)q * c->nsteps * NB * NB * E);
+    c->lu.info = b.take<int>(q);
+    c->lu.tmp = b.take<char>((size_t)q * NB * n * E);
+    c->Yw = b.take<char>((size_t)q * np * E);
+    c->Xw = b.take<char>((size_t)q * np * E);
+    c->Ow = b.take<char>((size_t)q * np * E);
+    if (c->prec != Prec::F64) {
+        c->colsum = b.take<double>((size_t)q * n);
+        c->Y64 = b.take<z64>((size_t)q * np);
+        c->R64 = b.take<z64>((size_t)q * np);
+    }
+    c->nrm_d = b.take<double>(2 * q + 2);
+    c->mask_d = b.take<int>(q);
+    c->BU = b.take<z64>(np);
+    c->QAB = b.take<z64>(3 * np);
+    c->XAB = b.take<z64>(3 * np);
+    c->T1 = b.take<z64>(np);
+    if (c->o.variant == FEAST_BI) {
+        c->Vb = b.take<z64>(np);
+        c->Pb = b.take<z64>(np);
+    }
+    c->G_d = b.take<z64>((size_t)p * p);
+    c->Rinv_d = b.take<z64>((size_t)p * p);
+    c->AhBh = b.take<z64>((size_t)2 * p * p);
+    c->W_d = b.take<z64>((size_t)p * p);
+    c->Z_d = b.take<z64>((size_t)p * p);
+    c->lam_d = b.take<z64>(p);
+    c->norms_d = b.take<double>(3 * p);
+    c->idx_d = b.take<int>(p);
+    c->partial = b.take<z64>(gemm_partial_elems(p, 2 * p, 1, splitk_for(n)));
+    (void)has_B;
+}
+
+void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_options* o) {
+    c->n = n;
+    c->m0 = m0;
+    c->q = C->q;
+    c->C = *C;
+    c->o = *o;
+    c->prec = o->precision == FEAST_FP64 ? Prec::F64 : (o->precision == FEAST_FP32_IR ? Prec::F32 : Prec::F16);
+    c->nsteps = ceil_div(n, NB);
+    c->ldf = (long)align_up((size_t)n, 8);
+    c->lu.n = n;
+    c->lu.q = C->q;
+    c->lu.nb = NB;
+    c->lu.nsteps = c->nsteps;
+    c->lu.ldf = c->ldf;
+    c->lu.sF = (long)n * c->ldf;
+    c->lu.spiv = n;
+}
+
+int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
+    if (n < 1) return -1;
+    if (!C || C->q < 2 || C->q % 2 || !(C->radius > 0) || !(C->aspect > 0) ||
+        (C->rule != FEAST_RULE_TRAPEZOID && C->rule != FEAST_RULE_GAUSS_LEGENDRE))
+        return -2;
+    if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI))
+        return -3;
+    if (m0 < 1 || m0 > n) return -4;
+    if (o->precision == FEAST_FP16_IR) return FEAST_EUNSUPPORTED;
+    return 0;
+}
+
+template <typename T>
+Rows<T> rows(void* p, const feast_ctx* c) {
+    Rows<T> r;
+    r.p = (cplx<T>*)p;
+    r.ld = c->m0;
+    r.s = (long)c->n * c->m0;
+    return r;
+}
+
+// A view of nodes [k0, k0 + qv) of the factorisations.
+LUStore node_view(const feast_ctx* c, int k0, int qv) {
+    LUStore v = c->lu;
+    const size_t E = elem_bytes(c->prec);
+    v.F = (char*)c->lu.F + (size_t)k0 * c->lu.sF * E;
+    v.ipiv = c->lu.ipiv + (size_t)k0 * c->lu.spiv;
+    v.perm = c->lu.perm + (size_t)k0 * c->lu.spiv;
+    v.iperm = c->lu.iperm + (size_t)k0 * c->lu.spiv;
+    v.Linv = (char*)c->lu.Linv + (size_t)k0 * c->nsteps * NB * NB * E;
+    v.Uinv = (char*)c->lu.Uinv + (size_t)k0 * c->nsteps * NB * NB * E;
+    v.q = qv;
+    return v;
+}
+
+int d2h(feast_ctx* c, void* host, const void* dev, size_t bytes) {
+    FM_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->st));
+    FM_HIP(hipStreamSynchronize(c->st));
+    return 0;
+}
+
+// Host-to-device through the pinned staging area (synchronises so the staging can be reused).
+int h2d(feast_ctx* c, void* dev, const void* host, size_t bytes) {
+    if (bytes > c->hbytes) return FEAST_EWORKSPACE;
+    std::memcpy(c->h, host, bytes);
+    FM_HIP(hipMemcpyAsync(dev, c->h, bytes, hipMemcpyHostToDevice, c->st));
+    FM_HIP(hipStreamSynchronize(c->st));
+    return 0;
+}
+
+// Solves for nodes [k0, k0+qv): O_k = T_k^-1 rhs (side 0) or T_k^-H rhs (side 1) for a shared
+// column-major FP64 rhs, then out = sum_k w_k O_k (column-major FP64).  In the refinement
+// modes the low-precision solve is followed by FP64 refinement sweeps.
+template <typename T>
+int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rhs, long ldr, const z64* w, z64* out,
+                long ldo) {
+    const int n = c->n;
+    hipStream_t st = c->st;
+    LUStore v = node_view(c, k0, qv);
+    Rows<T> Y = rows<T>(c->Yw, c), X = rows<T>(c->Xw, c), O = rows<T>(c->Ow, c);
+    const int* perm = side == 0 ? v.perm : nullptr;
+    const int* back = side == 0 ? nullptr : v.iperm;
+    FM_TRY(gather_rows<T>(Y, n, ncols, qv, rhs, ldr, 0, false, perm, v.spiv, st));
+    FM_TRY(trsolve<T>(v, side, ncols, Y, X, O, st));
+    c->ir_sweeps = 0;
+    c->ir_relres = 0.0;
+    if (std::is_same<T, double>::value) {
+        FM_TRY(accumulate<T>(out, ldo, O, n, ncols, qv, back, v.spiv, w, st));
+        return 0;
+    }
+    // FP64 iterative refinement of every node solve
+    Rows<double> Y64 = rows<double>(c->Y64, c), R64 = rows<double>(c->R64, c);
+    FM_TRY(rows_to_f64<T>(Y64, O, n, ncols, qv, back, v.spiv, false, nullptr, st));
+    double* nrm = c->nrm_d;  // [0, qv): ||R_k||, [qv, 2qv): ||Y_k||, [2qv]: ||rhs||
+    FM_TRY(fro_norm_cm(rhs, ldr, n, ncols, nrm + 2 * qv, st));
+    const double u64 = 0.5 * 2.220446049250313e-16;
+    const double ir_tol = c->o.ir_tol > 0 ? c->o.ir_tol : 8.0 * std::sqrt((double)n) * u64;
+    std::vector<int> active(qv, 1);
+    std::vector<double> prev(qv, INFINITY), hn(2 * qv + 1);
+    const z64* negz = (side == 0 ? c->negz : c->negzc) + k0;
+    for (int sweep = 0;; ++sweep) {
+        // R_k = rhs - T_k Y_k with T_k = z_k B - A (side 0) or its conjugate transpose (side 1)
+        FM_TRY(broadcast_rows(R64, rhs, ldr, n, ncols, qv, st));
+        if (c->B) {
+            GemmOp g;
+            g.A = c->B; g.lda = c->ldb; g.sA = 0; g.rowA = side != 0; g.conjA = side != 0;
+            g.B = Y64.p; g.ldb = Y64.ld; g.sB = Y64.s; g.rowB = true;
+            g.C = R64.p; g.ldc = R64.ld; g.sC = R64.s; g.rowC = true;
+            g.M = n; g.N = ncols; g.K = n; g.batch = qv;
+            g.alpha_b = negz; g.beta = z64(1.0);
+            FM_TRY(gemm<double>(g, st));
+        } else {
+            FM_TRY(axpy_rows(R64, Y64, negz, n, ncols, qv, st));
+        }
+        GemmOp g;
+        g.A = c->A; g.lda = c->lda; g.sA = 0; g.rowA = side != 0; g.conjA = side != 0;
+        g.B = Y64.p; g.ldb = Y64.ld; g.sB = Y64.s; g.rowB = true;
+        g.C = R64.p; g.ldc = R64.ld; g.sC = R64.s; g.rowC = true;
+        g.M = n; g.N = ncols; g.K = n; g.batch = qv;
+        g.alpha = z64(1.0); g.beta = z64(1.0);
+        FM_TRY(gemm<double>(g, st));
+        FM_TRY(fro_norms(R64, n, ncols, qv, nrm, st));
+        FM_TRY(fro_norms(Y64, n, ncols, qv, nrm + qv, st));
+        FM_TRY(d2h(c, hn.data(), nrm, (2 * qv + 1) * sizeof(double)));
+        int n_active = 0;
+        double worst = 0.0;
+        for (int k = 0; k < qv; ++k) {
+            const double scale = c->norm1[k0 + k] * hn[qv + k] + hn[2 * qv];
+            const double rel = hn[k] / scale;
+            worst = std::max(worst, rel);
+            if (!active[k]) continue;
+            if (hn[k] <= ir_tol * scale || hn[k] > 0.5 * prev[k]) {
+                active[k] = 0;
+            } else {
+                ++n_active;
+            }
+            prev[k] = hn[k];
+        }
+        c->ir_sweeps = sweep;
+        c->ir_relres = worst;
+        if (n_active == 0 || sweep >= c->o.ir_max) break;
+        FM_TRY(h2d(c, c->mask_d, active.data(), qv * sizeof(int)));
+        FM_TRY(gather_rows<T>(Y, n, ncols, qv, R64.p, R64.ld, R64.s, true, perm, v.spiv, st));
+        FM_TRY(trsolve<T>(v, side, ncols, Y, X, O, st));
+        FM_TRY(rows_to_f64<T>(Y64, O, n, ncols, qv, back, v.spiv, true, c->mask_d, st));
+    }
+    FM_TRY(accumulate<double>(out, ldo, Y64, n, ncols, qv, nullptr, v.spiv, w, st));
+    if (c->ir_relres > 1e-6) return FEAST_EIR;
+    return 0;
+}
+
+int apply(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rhs, long ldr, const z64* w, z64* out,
+          long ldo) {
+    if (c->prec == Prec::F64) return apply_nodes<double>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo);
+    return apply_nodes<float>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo);
+}
+
+// out (n x ncols, column-major) = op(B) U, op = N (side 0) or H (side 1)
+int apply_B(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* out, long ldo) {
+    GemmOp g;
+    g.A = c->B; g.lda = c->ldb; g.rowA = side != 0; g.conjA = side != 0;
+    g.B = U; g.ldb = ldu;
+    g.C = out; g.ldc = ldo;
+    g.M = c->n; g.N = ncols; g.K = c->n;
+    return gemm<double>(g, c->st);
+}
+
+// C (p x N, column-major, ld p) = X^H Y for column-major n x p X and n x N Y (split-K over n)
+int gram(feast_ctx* c, const z64* X, long ldx, const z64* Y, long ldy, int N, z64* C) {
+    GemmOp g;
+    g.A = X; g.lda = ldx; g.rowA = true; g.conjA = true;
+    g.B = Y; g.ldb = ldy;
+    g.C = C; g.ldc = c->m0;
+    g.M = c->m0; g.N = N; g.K = c->n;
+    g.splitk = splitk_for(c->n);
+    g.partial = c->partial;
+    return gemm<double>(g, c->st);
+}
+
+// Y (n x p) = X (n x p) M (p x p, device); all column-major.
+int right_mult(feast_ctx* c, const z64* X, long ldx, const z64* M, z64* Y, long ldy, int batch = 1, long sxy = 0) {
+    GemmOp g;
+    g.A = X; g.lda = ldx; g.sA = sxy;
+    g.B = M; g.ldb = c->m0; g.sB = 0;
+    g.C = Y; g.ldc = ldy; g.sC = sxy;
+    g.M = c->n; g.N = c->m0; g.K = c->m0; g.batch = batch;
+    return gemm<double>(g, c->st);
+}
+
+host::Mat to_mat(const z64* a, int p) {
+    host::Mat M(p);
+    for (int i = 0; i < p * p; ++i) M.a[i] = cd(a[i].re, a[i].im);
+    return M;
+}
+
+void from_mat(const host::Mat& M, z64* a) {
+    for (size_t i = 0; i < M.a.size(); ++i) a[i] = z64(M.a[i].real(), M.a[i].imag());
+}
+
+// Orthonormal basis of span(Q) in place (n x p, ld n): shifted Cholesky-QR followed by two
+// plain Cholesky-QR passes, each pass Q <- Q R^-1 with R^H R = Q^H Q (+ shift on the first).
+int orthonormalize(feast_ctx* c, z64* Q) {
+    const int n = c->n, p = c->m0;
+    std::vector<z64> hg((size_t)p * p);
+    z64* src = Q;
+    z64* dst = c->T1;
+    for (int pass = 0; pass < 3; ++pass) {
+        FM_TRY(gram(c, src, n, src, n, p, c->G_d));
+        FM_TRY(d2h(c, hg.data(), c->G_d, hg.size() * sizeof(z64)));
+        host::Mat G = to_mat(hg.data(), p), R;
+        double tr = 0.0;
+        for (int i = 0; i < p; ++i) tr += G(i, i).real();
+        if (!(tr > 0.0) || !std::isfinite(tr)) return FEAST_EREDUCED;
+        double shift = pass == 0 ? 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * tr : 0.0;
+        bool ok = false;
+        for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
+            host::Mat Gs = G;
+            for (int i = 0; i < p; ++i) Gs(i, i) += shift;
+            ok = host::cholesky_upper(Gs, R);
+            shift = shift > 0 ? shift * 100.0 : 1e-15 * tr;
+        }
+        if (!ok) return FEAST_EREDUCED;
+        from_mat(host::inverse_upper(R), hg.data());
+        FM_TRY(h2d(c, c->Rinv_d, hg.data(), hg.size() * sizeof(z64)));
+        FM_TRY(right_mult(c, src, n, c->Rinv_d, dst, n));
+        std::swap(src, dst);
+    }
+    if (src != Q) FM_TRY(copy_cm(Q, n, src, n, n, p, c->st));
+    return 0;
+}
+
+bool inside(cd lam, const feast_contour& C) {
+    const double x = (lam.real() - C.c_re) / C.radius, y = (lam.imag() - C.c_im) / (C.aspect * C.radius);
+    return x * x + y * y < 1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void feast_default_options(feast_options* o) {
+    if (!o) return;
+    o->precision = FEAST_FP64;
+    o->variant = FEAST_R;
+    o->max_iter = 30;
+    o->tol = 1e-10;
+    o->candidate_tol = 1e-4;
+    o->ir_max = 10;
+    o->ir_tol = 0.0;
+}
+
+int feast_workspace_size(int n, int m0, const feast_contour* C, const feast_options* o, int has_B, size_t* bytes) {
+    FM_TRY(check_args(n, m0, C, o));
+    if (!bytes) return -6;
+    feast_ctx c;
+    fill_dims(&c, n, m0, C, o);
+    Bump b;
+    layout(&c, b, has_B != 0);
+    *bytes = align_up(b.off, ALIGN);
+    return 0;
+}
+
+int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C,
+                int m0, const feast_options* o, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!ctx) return -1;
+    *ctx = nullptr;
+    int rc = check_args(n, m0, C, o);
+    if (rc) return rc < 0 ? (rc == -1 ? -2 : rc == -2 ? -7 : rc == -3 ? -9 : -8) : rc;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (B && ldb < n) return -6;
+    if (!workspace || ((uintptr_t)workspace % ALIGN)) return FEAST_EWORKSPACE;
+    feast_ctx* c = new feast_ctx;
+    fill_dims(c, n, m0, C, o);
+    c->st = (hipStream_t)stream;
+    c->A = (const z64*)A; c->lda = lda;
+    c->B = (const z64*)B; c->ldb = ldb;
+    Bump b;
+    b.base = (char*)workspace;
+    layout(c, b, B != nullptr);
+    if (b.off > workspace_bytes) {
+        delete c;
+        return FEAST_EWORKSPACE;
+    }
+    const int q = C->q, p = m0;
+    c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
+    if (hipHostMalloc((void**)&c->h, c->hbytes, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return FEAST_EDEVICE;
+    }
+    *ctx = c;
+    // a1: nodes and weights
+    std::vector<double> zz(2 * q), ss(2 * q);
+    if (feast_contour_nodes(C, zz.data(), ss.data()) != 0) return -7;
+    c->z.resize(q);
+    c->sig.resize(q);
+    std::vector<z64> tab(6 * q);
+    for (int k = 0; k < q; ++k) {
+        const z64 zk(zz[2 * k], zz[2 * k + 1]), sk(ss[2 * k], ss[2 * k + 1]);
+        c->z[k] = zk;
+        c->sig[k] = sk;
+        tab[k] = zk;
+        tab[q + k] = sk;
+        tab[2 * q + k] = conj(sk);
+        tab[3 * q + k] = -zk;
+        tab[4 * q + k] = -conj(zk);
+        tab[5 * q + k] = z64(1.0);
+    }
+    // the six tables are contiguous in the layout up to 256-byte alignment; copy them one by one
+    z64* dst[6] = {c->z_d, c->wR, c->wL, c->negz, c->negzc, c->ones};
+    for (int t = 0; t < 6; ++t) FM_TRY(h2d(c, dst[t], tab.data() + t * q, q * sizeof(z64)));
+    // a2 + a3: assemble and factor every node
+    if (c->prec == Prec::F64) {
+        FM_TRY(assemble_nodes<double>(c->lu, c->A, lda, c->B, ldb, c->z_d, c->st));
+        FM_TRY(factor_nodes<double>(c->lu, c->st));
+    } else {
+        FM_TRY(assemble_nodes<float>(c->lu, c->A, lda, c->B, ldb, c->z_d, c->st));
+        FM_TRY(factor_nodes<float>(c->lu, c->st));
+        FM_TRY(node_norm1(c->A, lda, c->B, ldb, n, c->z_d, q, c->colsum, c->norm1_d, c->st));
+        c->norm1.resize(q);
+        FM_TRY(d2h(c, c->norm1.data(), c->norm1_d, q * sizeof(double)));
+    }
+    std::vector<int> info(q);
+    FM_TRY(d2h(c, info.data(), c->lu.info, q * sizeof(int)));
+    for (int k = 0; k < q; ++k)
+        if (info[k]) return FEAST_ESINGULAR + k;
+    return 0;
+}
+
+int feast_filter(feast_ctx* c, int side, int ncols, const void* U, int ldu, void* Q, int ldq) {
+    if (!c) return -1;
+    if (side != 0 && side != 1) return -2;
+    if (ncols < 1 || ncols > c->m0) return -3;
+    if (!U) return -4;
+    if (ldu < c->n) return -5;
+    if (!Q) return -6;
+    if (ldq < c->n) return -7;
+    const z64* rhs = (const z64*)U;
+    long ldr = ldu;
+    if (c->B) {
+        FM_TRY(apply_B(c, side, ncols, (const z64*)U, ldu, c->BU, c->n));
+        rhs = c->BU;
+        ldr = c->n;
+    }
+    return apply(c, 0, c->q, side, ncols, rhs, ldr, side == 0 ? c->wR : c->wL, (z64*)Q, ldq);
+}
+
+int feast_node_solve(feast_ctx* c, int k, int side, int ncols, const void* R, int ldr, void* Y, int ldy) {
+    if (!c) return -1;
+    if (k < 0 || k >= c->q) return -2;
+    if (side != 0 && side != 1) return -3;
+    if (ncols < 1 || ncols > c->m0) return -4;
+    if (!R) return -5;
+    if (ldr < c->n) return -6;
+    if (!Y) return -7;
+    if (ldy < c->n) return -8;
+    return apply(c, k, 1, side, ncols, (const z64*)R, ldr, c->ones, (z64*)Y, ldy);
+}
+
+int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z) {
+    if (p < 1) return -1;
+    if (!Ah) return -2;
+    if (!Bh) return -3;
+    if (!lam) return -4;
+    if (!W) return -5;
+    host::Mat Am = to_mat((const z64*)Ah, p), Bm = to_mat((const z64*)Bh, p), Binv;
+    if (!host::inverse(Bm, Binv)) return FEAST_EREDUCED;
+    std::vector<cd> l;
+    host::Mat Wm;
+    if (!host::eig(host::matmul(Binv, Am), l, Wm)) return FEAST_EREDUCED;
+    for (int i = 0; i < p; ++i) {
+        lam[2 * i] = l[i].real();
+        lam[2 * i + 1] = l[i].imag();
+    }
+    from_mat(Wm, (z64*)W);
+    if (Z) {
+        host::Mat BW = host::matmul(Bm, Wm), BWinv;
+        if (!host::inverse(BW, BWinv)) return FEAST_EREDUCED;
+        from_mat(host::conj_transpose(BWinv), (z64*)Z);
+    }
+    return 0;
+}
+
+int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
+    if (!c) return -1;
+    if (!U0) return -2;
+    if (ldu0 < c->n) return -3;
+    if (!res || !res->lambda || !res->resid || !res->X || res->ldx < c->n) return -4;
+    const bool bi = c->o.variant == FEAST_BI;
+    if (bi && res->Y && res->ldy < c->n) return -4;
+    const int n = c->n, p = c->m0;
+    const long np = (long)n * p;
+    hipStream_t st = c->st;
+    z64* Q = c->QAB;
+    z64* AQ = c->QAB + np;
+    z64* BQ = c->QAB + 2 * np;
+    z64* U = c->XAB;
+    z64* BU_ = c->XAB + 2 * np;
+    FM_TRY(copy_cm(U, n, (const z64*)U0, ldu0, n, p, st));
+    std::vector<z64> hbuf((size_t)2 * p * p), hW((size_t)p * p), hZ((size_t)p * p), hlam(p);
+    std::vector<double> hn(3 * p);
+    if (bi) {
+        // V0 = B U0 (U0^H B^H B U0)^-1, so that V0^H B U0 = I
+        const z64* BU0 = U;
+        if (c->B) {
+            FM_TRY(apply_B(c, 0, p, U, n, c->T1, n));
+            BU0 = c->T1;
+        }
+        FM_TRY(gram(c, BU0, n, BU0, n, p, c->G_d));
+        FM_TRY(d2h(c, hbuf.data(), c->G_d, (size_t)p * p * sizeof(z64)));
+        host::Mat Gi;
+        if (!host::inverse(to_mat(hbuf.data(), p), Gi)) return FEAST_EREDUCED;
+        from_mat(Gi, hbuf.data());
+        FM_TRY(h2d(c, c->Rinv_d, hbuf.data(), (size_t)p * p * sizeof(z64)));
+        FM_TRY(right_mult(c, BU0, n, c->Rinv_d, c->Vb, n));
+    }
+    int prev_count = -1, prev_inside = -1;
+    cd prev_trace(0.0, 0.0);
+    std::vector<int> order;
+    std::vector<double> rel(p), paper(p);
+    std::vector<cd> lam(p);
+    int count = 0;
+    bool done = false;
+    int it = 1;
+    for (; it <= c->o.max_iter; ++it) {
+        // filter and orthonormalise (Q = orth(rho(M) U); Bi-FEAST also P = orth(left filter of V))
+        FM_TRY(feast_filter(c, 0, p, U, n, Q, n));
+        FM_TRY(orthonormalize(c, Q));
+        if (bi) {
+            FM_TRY(feast_filter(c, 1, p, c->Vb, n, c->Pb, n));
+            FM_TRY(orthonormalize(c, c->Pb));
+        }
+        // Rayleigh-Ritz: A^ = W^H A Q, B^ = W^H B Q with W = Q (R-FEAST) or P (Bi-FEAST)
+        {
+            GemmOp g;
+            g.A = c->A; g.lda = c->lda; g.B = Q; g.ldb = n; g.C = AQ; g.ldc = n;
+            g.M = n; g.N = p; g.K = n;
+            FM_TRY(gemm<double>(g, st));
+        }
+        if (c->B) {
+            FM_TRY(apply_B(c, 0, p, Q, n, BQ, n));
+        } else {
+            FM_TRY(copy_cm(BQ, n, Q, n, n, p, st));
+        }
+        FM_TRY(gram(c, bi ? c->Pb : Q, n, AQ, n, 2 * p, c->AhBh));
+        FM_TRY(d2h(c, hbuf.data(), c->AhBh, (size_t)2 * p * p * sizeof(z64)));
+        int rc = feast_reduced_eig(p, (const double*)hbuf.data(), (const double*)(hbuf.data() + (size_t)p * p),
+                                   (double*)hlam.data(), (double*)hW.data(), bi ? (double*)hZ.data() : nullptr);
+        if (rc) return rc;
+        FM_TRY(h2d(c, c->W_d, hW.data(), hW.size() * sizeof(z64)));
+        FM_TRY(h2d(c, c->lam_d, hlam.data(), hlam.size() * sizeof(z64)));
+        // Ritz vectors X = Q W with A X = (A Q) W and B X = (B Q) W
+        FM_TRY(right_mult(c, c->QAB, n, c->W_d, c->XAB, n, 3, np));
+        if (bi) {
+            FM_TRY(h2d(c, c->Z_d, hZ.data(), hZ.size() * sizeof(z64)));
+            FM_TRY(right_mult(c, c->Pb, n, c->Z_d, c->T1, n));
+            // restore V^H B U = I: V <- V (U^H B^H V)^-1
+            FM_TRY(gram(c, BU_, n, c->T1, n, p, c->G_d));
+            FM_TRY(d2h(c, hbuf.data(), c->G_d, (size_t)p * p * sizeof(z64)));
+            host::Mat Gi;
+            if (!host::inverse(to_mat(hbuf.data(), p), Gi)) return FEAST_EREDUCED;
+            from_mat(Gi, hbuf.data());
+            FM_TRY(h2d(c, c->Rinv_d, hbuf.data(), (size_t)p * p * sizeof(z64)));
+            FM_TRY(right_mult(c, c->T1, n, c->Rinv_d, c->Vb, n));
+        }
+        FM_TRY(ritz_residual_norms(U, U + np, BU_, n, n, p, c->lam_d, c->norms_d, st));
+        FM_TRY(d2h(c, hn.data(), c->norms_d, hn.size() * sizeof(double)));
+        count = 0;
+        int n_inside = 0;
+        cd trace(0.0, 0.0);
+        double maxrel = 0.0;
+        order.clear();
+        std::vector<int> rest;
+        for (int j = 0; j < p; ++j) {
+            lam[j] = cd(hlam[j].re, hlam[j].im);
+            paper[j] = hn[j] / hn[2 * p + j];
+            rel[j] = hn[j] / (std::abs(lam[j]) * hn[p + j]);
+            const bool fin = std::isfinite(lam[j].real()) && std::isfinite(lam[j].imag()) && std::isfinite(paper[j]);
+            const bool in = fin && inside(lam[j], c->C);
+            n_inside += in;
+            if (in && paper[j] <= c->o.candidate_tol) {
+                ++count;
+                trace += lam[j];
+                maxrel = std::max(maxrel, rel[j]);
+                order.push_back(j);
+            } else {
+                rest.push_back(j);
+            }
+        }
+        if (res->history) {
+            double* h = res->history + 4 * (it - 1);
+            h[0] = count;
+            h[1] = count ? maxrel : NAN;
+            h[2] = trace.real();
+            h[3] = trace.imag();
+        }
+        if (prev_count >= 0 && count == prev_count)
+            done = count == 0 ? (n_inside == 0 && prev_inside == 0) : (maxrel <= c->o.tol);
+        prev_count = count;
+        prev_inside = n_inside;
+        prev_trace = trace;
+        if (done || it == c->o.max_iter) {
+            order.insert(order.end(), rest.begin(), rest.end());
+            break;
+        }
+    }
+    if (it > c->o.max_iter) it = c->o.max_iter;
+    // outputs: candidates first
+    for (int c2 = 0; c2 < p; ++c2) {
+        const int j = order[c2];
+        res->lambda[2 * c2] = lam[j].real();
+        res->lambda[2 * c2 + 1] = lam[j].imag();
+        res->resid[c2] = rel[j];
+    }
+    FM_TRY(h2d(c, c->idx_d, order.data(), p * sizeof(int)));
+    FM_TRY(gather_cols((z64*)res->X, res->ldx, U, n, n, p, c->idx_d, st));
+    if (bi && res->Y) FM_TRY(gather_cols((z64*)res->Y, res->ldy, c->Vb, n, n, p, c->idx_d, st));
+    FM_HIP(hipStreamSynchronize(st));
+    res->m = count;
+    res->iterations = it;
+    res->converged = done;
+    return done ? 0 : FEAST_ENOCONV;
+}
+
+void feast_destroy(feast_ctx* c) {
+    if (!c) return;
+    if (c->h) (void)hipHostFree(c->h);
+    delete c;
+}
+
+const char* feast_strerror(int code) {
+    if (code == 0) return "success";
+    if (code < 0) return "invalid argument";
+    if (code >= FEAST_ESINGULAR) return "zero pivot in a node factorisation (eigenvalue on a quadrature node)";
+    switch (code) {
+        case FEAST_ENOCONV: return "maximum number of FEAST iterations reached";
+        case FEAST_ERANK: return "subspace too small for the eigenvalue count";
+        case FEAST_EIR: return "iterative refinement did not converge";
+        case FEAST_EDEVICE: return "HIP runtime error";
+        case FEAST_EWORKSPACE: return "workspace missing, misaligned or too small";
+        case FEAST_EREDUCED: return "reduced eigenproblem failed";
+        case FEAST_EUNSUPPORTED: return "unsupported option";
+    }
+    return "unknown error";
+}
+
+}  // extern "C"

@@ -1,0 +1,37 @@
+// Batched complex GEMM on the CDNA4 matrix cores.
+#pragma once
+
+#include "common.h"
+
+namespace fm {
+
+// One batched product C_b = alpha_b op(A_b) op(B_b) + beta C_b, b = 0..batch-1.
+//
+// Element (i, k) of op(A) is A[i*lda + k] when rowA, else A[i + k*lda], conjugated
+// when conjA; likewise (k, j) of op(B) is B[k*ldb + j] when rowB, else B[k + j*ldb];
+// and C(i, j) is C[i*ldc + j] when rowC, else C[i + j*ldc].  Strides step between
+// batch entries (0 shares an operand).  alpha_b, when set, is a device array of
+// batch complex doubles used instead of alpha.  A and C must not overlap.
+struct GemmOp {
+    const void* A = nullptr; long lda = 0; long sA = 0; bool rowA = false; bool conjA = false;
+    const void* B = nullptr; long ldb = 0; long sB = 0; bool rowB = false; bool conjB = false;
+    void* C = nullptr;       long ldc = 0; long sC = 0; bool rowC = false;
+    int M = 0, N = 0, K = 0, batch = 1;
+    z64 alpha = z64(1.0), beta = z64(0.0);
+    const z64* alpha_b = nullptr;
+    // split-K: when splitk > 1, partials go to `partial` (splitk * batch * M * N elements of the
+    // compute type) and a second kernel reduces them; requires alpha_b == nullptr.
+    int splitk = 1;
+    void* partial = nullptr;
+};
+
+// T = double (complex128 operands, FP64 MFMA) or float (complex64, FP32 MFMA).
+template <typename T>
+int gemm(const GemmOp& op, hipStream_t stream);
+
+// Number of partial elements gemm needs for a split-K product.
+inline size_t gemm_partial_elems(int M, int N, int batch, int splitk) {
+    return (size_t)M * N * batch * splitk;
+}
+
+}  // namespace fm

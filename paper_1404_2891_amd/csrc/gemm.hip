@@ -1,0 +1,270 @@
+// Batched complex GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).
+//
+// A complex product is four real products (re*re - im*im, re*im + im*re), so each 16x16x4
+// complex block update is four real MFMAs: 8 real flops per complex multiply-add, the
+// LAPACK count.  A workgroup of 256 threads (4 wave64s) owns a BM x BN tile of C; waves are
+// laid out WM x WN over the tile, each owning RB x CB blocks of 16 x 16.  Operand tiles
+// of depth BK = 16 are staged through LDS as separate real / imaginary planes in k-major
+// order, so the 16 lanes of an MFMA row group read consecutive addresses; the next tile
+// is fetched into registers while the current one is consumed.
+#include "gemm.h"
+
+namespace fm {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct AccT;
+template <> struct AccT<double> { typedef d4 type; };
+template <> struct AccT<float> { typedef f4 type; };
+
+__device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+constexpr int BK = 16;
+constexpr int PAD = 2;
+
+template <typename T>
+struct Params {
+    const cplx<T>* A; long lda, sA;
+    const cplx<T>* B; long ldb, sB;
+    cplx<T>* C; long ldc, sC;
+    int M, N, K, batch, splitk, kchunk, tiles_m;
+    T ar, ai, br, bi;
+    const z64* alpha_b;
+    int conjA, conjB;
+    cplx<T>* partial;
+};
+
+template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC>
+__global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
+    constexpr int BM = WM * RB * 16, BN = WN * CB * 16, NT = 64 * WM * WN;
+    constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
+    static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile not divisible");
+    typedef typename AccT<T>::type acc_t;
+
+    __shared__ T As[2][BK][BM + PAD];
+    __shared__ T Bs[2][BK][BN + PAD];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int tm = blockIdx.x % p.tiles_m, tn = blockIdx.x / p.tiles_m;
+    const int b = blockIdx.z % p.batch, s = blockIdx.z / p.batch;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int kbeg = s * p.kchunk;
+    const int kend = min(p.K, kbeg + p.kchunk);
+    const cplx<T>* __restrict__ A = p.A + b * p.sA;
+    const cplx<T>* __restrict__ B = p.B + b * p.sB;
+    const T sa = p.conjA ? T(-1) : T(1), sb = p.conjB ? T(-1) : T(1);
+
+    cplx<T> ra[EA], rb[EB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) {
+            const int idx = tid + e * NT;
+            const int k = RA ? idx % BK : idx / BM;
+            const int i = RA ? idx / BK : idx % BM;
+            const int gi = m0 + i, gk = k0 + k;
+            cplx<T> v(T(0), T(0));
+            if (gi < p.M && gk < kend) v = RA ? A[(long)gi * p.lda + gk] : A[gi + (long)gk * p.lda];
+            ra[e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int idx = tid + e * NT;
+            const int j = RBm ? idx % BN : idx / BK;
+            const int k = RBm ? idx / BN : idx % BK;
+            const int gj = n0 + j, gk = k0 + k;
+            cplx<T> v(T(0), T(0));
+            if (gj < p.N && gk < kend) v = RBm ? B[(long)gk * p.ldb + gj] : B[gk + (long)gj * p.ldb];
+            rb[e] = v;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) {
+            const int idx = tid + e * NT;
+            const int k = RA ? idx % BK : idx / BM;
+            const int i = RA ? idx / BK : idx % BM;
+            As[0][k][i] = ra[e].re;
+            As[1][k][i] = sa * ra[e].im;
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int idx = tid + e * NT;
+            const int j = RBm ? idx % BN : idx / BK;
+            const int k = RBm ? idx / BN : idx % BK;
+            Bs[0][k][j] = rb[e].re;
+            Bs[1][k][j] = sb * rb[e].im;
+        }
+    };
+
+    acc_t cre[RB][CB], cim[RB][CB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            cre[r][c] = acc_t{0, 0, 0, 0};
+            cim[r][c] = acc_t{0, 0, 0, 0};
+        }
+
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const int k = kk * 4 + (lane >> 4);
+            T are[RB], aim[RB], bre[CB], bim[CB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int i = wm * RB * 16 + r * 16 + (lane & 15);
+                are[r] = As[0][k][i];
+                aim[r] = As[1][k][i];
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int j = wn * CB * 16 + c * 16 + (lane & 15);
+                bre[c] = Bs[0][k][j];
+                bim[c] = Bs[1][k][j];
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    cre[r][c] = mfma4(are[r], bre[c], cre[r][c]);
+                    cre[r][c] = mfma4(-aim[r], bim[c], cre[r][c]);
+                    cim[r][c] = mfma4(are[r], bim[c], cim[r][c]);
+                    cim[r][c] = mfma4(aim[r], bre[c], cim[r][c]);
+                }
+        }
+    }
+
+    // epilogue: lane l holds rows 4*(l/16) + v, column l%16 of each 16 x 16 block
+    T ar = p.ar, ai = p.ai;
+    if (p.alpha_b) {
+        ar = T(p.alpha_b[b].re);
+        ai = T(p.alpha_b[b].im);
+    }
+    cplx<T>* __restrict__ C = p.C + b * p.sC;
+    const bool has_beta = (p.br != T(0) || p.bi != T(0));
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = m0 + wm * RB * 16 + r * 16 + 4 * (lane >> 4) + v;
+                const int j = n0 + wn * CB * 16 + c * 16 + (lane & 15);
+                if (i < p.M && j < p.N) {
+                    const T xr = cre[r][c][v], xi = cim[r][c][v];
+                    if (p.splitk > 1) {
+                        p.partial[(((long)s * p.batch + b) * p.N + j) * p.M + i] = cplx<T>(xr, xi);
+                    } else {
+                        T yr = ar * xr - ai * xi, yi = ar * xi + ai * xr;
+                        cplx<T>* cp = RC ? &C[(long)i * p.ldc + j] : &C[i + (long)j * p.ldc];
+                        if (has_beta) {
+                            const cplx<T> o = *cp;
+                            yr += p.br * o.re - p.bi * o.im;
+                            yi += p.br * o.im + p.bi * o.re;
+                        }
+                        *cp = cplx<T>(yr, yi);
+                    }
+                }
+            }
+}
+
+// C = alpha * sum_s partial_s + beta * C
+template <typename T, bool RC>
+__global__ void splitk_reduce(Params<T> p) {
+    const long total = (long)p.M * p.N * p.batch;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        const int i = t % p.M;
+        const int j = (t / p.M) % p.N;
+        const int b = t / ((long)p.M * p.N);
+        T xr = 0, xi = 0;
+        for (int s = 0; s < p.splitk; ++s) {
+            const cplx<T> v = p.partial[(((long)s * p.batch + b) * p.N + j) * p.M + i];
+            xr += v.re;
+            xi += v.im;
+        }
+        T yr = p.ar * xr - p.ai * xi, yi = p.ar * xi + p.ai * xr;
+        cplx<T>* cp = p.C + b * p.sC + (RC ? (long)i * p.ldc + j : i + (long)j * p.ldc);
+        if (p.br != T(0) || p.bi != T(0)) {
+            const cplx<T> o = *cp;
+            yr += p.br * o.re - p.bi * o.im;
+            yi += p.br * o.im + p.bi * o.re;
+        }
+        *cp = cplx<T>(yr, yi);
+    }
+}
+
+template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC>
+void launch_cfg(Params<T> p, hipStream_t st) {
+    constexpr int BM = WM * RB * 16, BN = WN * CB * 16;
+    p.tiles_m = ceil_div(p.M, BM);
+    dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.splitk);
+    hipLaunchKernelGGL((cgemm_kernel<T, WM, WN, RB, CB, RA, RBm, RC>), grid, dim3(64 * WM * WN), 0, st, p);
+}
+
+template <typename T, bool RA, bool RBm, bool RC>
+void launch_layout(Params<T> p, hipStream_t st) {
+    if (p.N <= 16)
+        launch_cfg<T, 4, 1, 1, 1, RA, RBm, RC>(p, st);
+    else if (p.N <= 32)
+        launch_cfg<T, 4, 1, 1, 2, RA, RBm, RC>(p, st);
+    else
+        launch_cfg<T, 2, 2, 2, 2, RA, RBm, RC>(p, st);
+}
+
+}  // namespace
+
+template <typename T>
+int gemm(const GemmOp& op, hipStream_t st) {
+    if (op.M <= 0 || op.N <= 0 || op.batch <= 0) return 0;
+    if (op.splitk > 1 && (op.alpha_b || !op.partial)) return FEAST_EUNSUPPORTED;
+    Params<T> p;
+    p.A = (const cplx<T>*)op.A; p.lda = op.lda; p.sA = op.sA;
+    p.B = (const cplx<T>*)op.B; p.ldb = op.ldb; p.sB = op.sB;
+    p.C = (cplx<T>*)op.C; p.ldc = op.ldc; p.sC = op.sC;
+    p.M = op.M; p.N = op.N; p.K = op.K; p.batch = op.batch;
+    p.splitk = op.splitk > 1 ? op.splitk : 1;
+    p.kchunk = p.splitk > 1 ? (int)align_up((size_t)ceil_div(op.K, p.splitk), BK) : (op.K > 0 ? op.K : 0);
+    if (p.splitk > 1) p.splitk = ceil_div(op.K, p.kchunk);
+    p.ar = T(op.alpha.re); p.ai = T(op.alpha.im);
+    p.br = T(op.beta.re); p.bi = T(op.beta.im);
+    p.alpha_b = op.alpha_b;
+    p.conjA = op.conjA; p.conjB = op.conjB;
+    p.partial = (cplx<T>*)op.partial;
+    p.tiles_m = 1;
+    const int code = (op.rowA ? 4 : 0) | (op.rowB ? 2 : 0) | (op.rowC ? 1 : 0);
+    switch (code) {
+        case 0: launch_layout<T, false, false, false>(p, st); break;
+        case 1: launch_layout<T, false, false, true>(p, st); break;
+        case 2: launch_layout<T, false, true, false>(p, st); break;
+        case 3: launch_layout<T, false, true, true>(p, st); break;
+        case 4: launch_layout<T, true, false, false>(p, st); break;
+        case 5: launch_layout<T, true, false, true>(p, st); break;
+        case 6: launch_layout<T, true, true, false>(p, st); break;
+        case 7: launch_layout<T, true, true, true>(p, st); break;
+    }
+    FM_LAUNCH_CHECK();
+    if (p.splitk > 1) {
+        const long total = (long)p.M * p.N * p.batch;
+        const int blocks = (int)std::min<long>(4096, (total + 255) / 256);
+        if (op.rowC)
+            hipLaunchKernelGGL((splitk_reduce<T, true>), dim3(blocks), dim3(256), 0, st, p);
+        else
+            hipLaunchKernelGGL((splitk_reduce<T, false>), dim3(blocks), dim3(256), 0, st, p);
+        FM_LAUNCH_CHECK();
+    }
+    return 0;
+}
+
+template int gemm<double>(const GemmOp&, hipStream_t);
+template int gemm<float>(const GemmOp&, hipStream_t);
+
+}  // namespace fm

@@ -1,0 +1,39 @@
+// Small dense complex linear algebra on the host for the m0 x m0 reduced problems.
+#pragma once
+
+#include <complex>
+#include <vector>
+
+namespace fm {
+namespace host {
+
+using cd = std::complex<double>;
+
+// Column-major square matrix helper: element (i, j) at a[i + j * n].
+struct Mat {
+    int n = 0;
+    std::vector<cd> a;
+    Mat() = default;
+    explicit Mat(int n_) : n(n_), a((size_t)n_ * n_, cd(0.0, 0.0)) {}
+    cd& operator()(int i, int j) { return a[i + (size_t)j * n]; }
+    const cd& operator()(int i, int j) const { return a[i + (size_t)j * n]; }
+};
+
+Mat matmul(const Mat& A, const Mat& B);
+Mat conj_transpose(const Mat& A);
+
+// Upper R with R^H R = G (Hermitian positive definite); false if a pivot is not positive.
+bool cholesky_upper(const Mat& G, Mat& R);
+// Inverse of an upper triangular matrix.
+Mat inverse_upper(const Mat& R);
+// Inverse of a general matrix by LU with partial pivoting; false if singular.
+bool inverse(const Mat& A, Mat& Ainv);
+
+// Eigen-decomposition of a general complex matrix M = W diag(lam) W^-1: Householder reduction to
+// Hessenberg form, single-shift QR with Wilkinson shifts to complex Schur form, eigenvectors by
+// back substitution on the triangular factor.  W has unit 2-norm columns.  False if the QR
+// iteration does not converge.
+bool eig(const Mat& M, std::vector<cd>& lam, Mat& W);
+
+}  // namespace host
+}  // namespace fm

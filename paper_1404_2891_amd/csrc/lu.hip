@@ -1,0 +1,301 @@
+// Node assembly and blocked LU with partial pivoting of all contour-node systems.
+//
+// Factorisations are stored row-major (element (i, j) at F[i * ldf + j]) so that the row
+// interchanges of partial pivoting move contiguous memory and a panel row is one coalesced
+// load.  Every kernel is batched over the q nodes of a pencil (blockIdx.y or blockIdx.x).
+//
+// Right-looking blocked LU, block size nb, per step s (columns j0 = s nb .. j0 + w):
+//   panel   : pivot search (largest |re| + |im|, lowest row on ties), row swap, scaling and
+//             rank-1 updates of the n - j0 by w panel;
+//   trtri   : inverse of the unit lower diagonal block L_ss;
+//   swap    : the panel's interchanges applied to all other columns, and the swapped U12
+//             rows copied to a staging buffer;
+//   gemm    : U12 = L_ss^-1 * staged rows;
+//   gemm    : A22 -= L21 * U12 (the MFMA trailing update, where the flops are).
+// After the last step the inverses of the diagonal blocks of U are formed and the pivots are
+// combined into a permutation, so that the solves are products with precomputed blocks.
+#include <climits>
+
+#include "gemm.h"
+#include "lu.h"
+
+namespace fm {
+namespace {
+
+constexpr int NBMAX = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void assemble_kernel(cplx<T>* F, long ldf, long sF, int n, int q,
+                                                       const z64* __restrict__ A, long lda,
+                                                       const z64* __restrict__ B, long ldb,
+                                                       const z64* __restrict__ z) {
+    __shared__ z64 ta[32][33], tb[32][33];
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int jj = ty; jj < 32; jj += 8) {
+        const int i = bi + tx, j = bj + jj;
+        if (i < n && j < n) {
+            ta[jj][tx] = A[i + (long)j * lda];
+            tb[jj][tx] = B ? B[i + (long)j * ldb] : z64(i == j ? 1.0 : 0.0, 0.0);
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < q; ++k) {
+        const z64 zk = z[k];
+        for (int ii = ty; ii < 32; ii += 8) {
+            const int i = bi + ii, j = bj + tx;
+            if (i < n && j < n) {
+                const z64 v = zk * tb[tx][ii] - ta[tx][ii];
+                F[k * sF + (long)i * ldf + j] = cplx<T>(v);
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ inline cplx<T> shfl_c(cplx<T> v, int src) {
+    return cplx<T>(__shfl(v.re, src), __shfl(v.im, src));
+}
+
+// Panel factorisation of rows j0..n-1, columns j0..j0+w-1 of one node per workgroup.
+// Lane c of every wave holds column c of the row it is processing; the four waves sweep
+// interleaved rows.  Per column j one sweep applies the rank-1 update of column j - 1 and
+// searches column j for the pivot.
+template <typename T>
+__global__ __launch_bounds__(256) void panel_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
+                                                    int* ipiv0, long spiv, int* info) {
+    const int k = blockIdx.x;
+    cplx<T>* F = F0 + k * sF;
+    int* ipiv = ipiv0 + k * spiv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool act = lane < w;
+    __shared__ T sval[4];
+    __shared__ int srow[4];
+
+    cplx<T> prow(T(0), T(0)), invp(T(0), T(0));
+    for (int j = 0; j <= w; ++j) {
+        T best = T(-1);
+        int brow = INT_MAX;
+        for (int r0 = j0 + j + wave; r0 < n; r0 += 16) {
+            cplx<T> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = r0 + 4 * u;
+                v[u] = (act && r < n) ? F[(long)r * ldf + j0 + lane] : cplx<T>(T(0), T(0));
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = r0 + 4 * u;
+                if (r >= n) break;
+                if (j > 0) {
+                    const cplx<T> l = shfl_c(v[u], j - 1) * invp;
+                    if (lane == j - 1)
+                        v[u] = l;
+                    else if (lane > j - 1)
+                        v[u] = v[u] - l * prow;
+                    if (act && lane >= j - 1) F[(long)r * ldf + j0 + lane] = v[u];
+                }
+                if (j < w && lane == j) {
+                    const T a = abs1(v[u]);
+                    if (a > best) {
+                        best = a;
+                        brow = r;
+                    }
+                }
+            }
+        }
+        if (j == w) break;
+        if (lane == j) {
+            sval[wave] = best;
+            srow[wave] = brow;
+        }
+        __syncthreads();
+        T pv = sval[0];
+        int pr = srow[0];
+#pragma unroll
+        for (int t = 1; t < 4; ++t)
+            if (sval[t] > pv || (sval[t] == pv && srow[t] < pr)) {
+                pv = sval[t];
+                pr = srow[t];
+            }
+        if (pv <= T(0)) pr = j0 + j;  // exactly zero column: no interchange, flagged below
+        cplx<T>* rj = F + (long)(j0 + j) * ldf + j0;
+        cplx<T>* rp = F + (long)pr * ldf + j0;
+        const cplx<T> yv = act ? rp[lane] : cplx<T>(T(0), T(0));
+        const cplx<T> xv = act ? rj[lane] : cplx<T>(T(0), T(0));
+        __syncthreads();
+        if (wave == 0 && act && pr != j0 + j) {
+            rj[lane] = yv;
+            rp[lane] = xv;
+        }
+        prow = yv;
+        const cplx<T> piv = shfl_c(yv, j);
+        if (pv <= T(0)) {
+            invp = cplx<T>(T(0), T(0));
+            if (threadIdx.x == 0 && info[k] == 0) info[k] = j0 + j + 1;
+        } else {
+            invp = cdiv(cplx<T>(T(1), T(0)), piv);
+        }
+        if (threadIdx.x == 0) ipiv[j0 + j] = pr;
+        __syncthreads();
+    }
+}
+
+// Row interchanges of step (j0, w) applied to the columns outside the panel; the swapped rows
+// j0..j0+w-1 of the columns right of the panel are copied to tmp (row-major, ld n).
+template <typename T>
+__global__ __launch_bounds__(256) void swap_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
+                                                   const int* ipiv0, long spiv, cplx<T>* tmp0, long stmp) {
+    const int k = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncols = n - w;
+    if (t >= ncols) return;
+    const int c = t < j0 ? t : t + w;
+    cplx<T>* F = F0 + k * sF;
+    const int* ipiv = ipiv0 + k * spiv;
+    for (int j = 0; j < w; ++j) {
+        const int r = ipiv[j0 + j];
+        if (r != j0 + j) {
+            const cplx<T> a = F[(long)(j0 + j) * ldf + c];
+            const cplx<T> b = F[(long)r * ldf + c];
+            F[(long)(j0 + j) * ldf + c] = b;
+            F[(long)r * ldf + c] = a;
+        }
+    }
+    if (c >= j0 + w) {
+        cplx<T>* tmp = tmp0 + k * stmp;
+        for (int j = 0; j < w; ++j) tmp[(long)j * n + (c - j0 - w)] = F[(long)(j0 + j) * ldf + c];
+    }
+}
+
+// Inverses of diagonal blocks: UPPER = false -> unit lower part of block s, UPPER = true -> upper
+// part with its diagonal.  One wave per (block, node); thread j forms column j of the inverse.
+template <typename T, bool UPPER>
+__global__ __launch_bounds__(64) void trtri_kernel(const cplx<T>* F0, long ldf, long sF, int n, int nb,
+                                                   int nsteps, int s_first, cplx<T>* Inv0) {
+    __shared__ cplx<T> M[NBMAX][NBMAX + 1];
+    __shared__ cplx<T> X[NBMAX][NBMAX + 1];
+    const int s = s_first + blockIdx.x, k = blockIdx.y;
+    const int j0 = s * nb, w = min(nb, n - j0);
+    const cplx<T>* F = F0 + k * sF;
+    const int j = threadIdx.x;
+    for (int i = 0; i < w; ++i) {
+        if (j < w) M[i][j] = F[(long)(j0 + i) * ldf + j0 + j];
+    }
+    for (int i = 0; i < nb; ++i) X[i][j] = cplx<T>(T(0), T(0));
+    __syncthreads();
+    if (j < w) {
+        if (!UPPER) {
+            for (int i = j; i < w; ++i) {
+                cplx<T> acc(i == j ? T(1) : T(0), T(0));
+                for (int kk = j; kk < i; ++kk) acc = acc - M[i][kk] * X[kk][j];
+                X[i][j] = acc;
+            }
+        } else {
+            for (int i = j; i >= 0; --i) {
+                cplx<T> acc(i == j ? T(1) : T(0), T(0));
+                for (int kk = i + 1; kk <= j; ++kk) acc = acc - M[i][kk] * X[kk][j];
+                X[i][j] = cdiv(acc, M[i][i]);
+            }
+        }
+    }
+    __syncthreads();
+    cplx<T>* Inv = Inv0 + ((long)k * nsteps + s) * nb * nb;
+    for (int i = 0; i < nb; ++i) Inv[(long)i * nb + j] = X[i][j];
+}
+
+// Combined permutation of the sequential interchanges: row i of P T is row perm[i] of T.
+__global__ __launch_bounds__(256) void perm_kernel(const int* ipiv0, int* perm0, int* iperm0, long spiv, int n) {
+    extern __shared__ int sp[];
+    const int k = blockIdx.x;
+    const int* ipiv = ipiv0 + k * spiv;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sp[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < n; ++j) {
+            const int r = ipiv[j];
+            const int a = sp[j];
+            sp[j] = sp[r];
+            sp[r] = a;
+        }
+    }
+    __syncthreads();
+    int* perm = perm0 + k * spiv;
+    int* iperm = iperm0 + k * spiv;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        perm[i] = sp[i];
+        iperm[sp[i]] = i;
+    }
+}
+
+__global__ void zero_ints(int* p, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = 0;
+}
+
+}  // namespace
+
+template <typename T>
+int assemble_nodes(const LUStore& s, const z64* A, long lda, const z64* B, long ldb, const z64* z_dev,
+                   hipStream_t st) {
+    dim3 grid(ceil_div(s.n, 32), ceil_div(s.n, 32));
+    hipLaunchKernelGGL((assemble_kernel<T>), grid, dim3(256), 0, st, (cplx<T>*)s.F, s.ldf, s.sF, s.n, s.q, A, lda,
+                       B, ldb, z_dev);
+    FM_LAUNCH_CHECK();
+    return 0;
+}
+
+template <typename T>
+int factor_nodes(const LUStore& s, hipStream_t st) {
+    const int n = s.n, q = s.q, nb = s.nb;
+    if (nb > NBMAX || nb % 16) return FEAST_EUNSUPPORTED;
+    cplx<T>* F = (cplx<T>*)s.F;
+    cplx<T>* Linv = (cplx<T>*)s.Linv;
+    cplx<T>* tmp = (cplx<T>*)s.tmp;
+    hipLaunchKernelGGL(zero_ints, dim3(ceil_div(q, 256)), dim3(256), 0, st, s.info, q);
+    FM_LAUNCH_CHECK();
+    for (int step = 0; step < s.nsteps; ++step) {
+        const int j0 = step * nb, w = std::min(nb, n - j0);
+        hipLaunchKernelGGL((panel_kernel<T>), dim3(q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, s.ipiv, s.spiv,
+                           s.info);
+        FM_LAUNCH_CHECK();
+        hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF, n,
+                           nb, s.nsteps, step, Linv);
+        FM_LAUNCH_CHECK();
+        if (n - w > 0) {
+            hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(n - w, 256), q), dim3(256), 0, st, F, s.ldf, s.sF, n,
+                               j0, w, (const int*)s.ipiv, s.spiv, tmp, (long)nb * n);
+            FM_LAUNCH_CHECK();
+        }
+        const int nr = n - j0 - w;
+        if (nr > 0) {
+            GemmOp u12;  // U12 = L_ss^-1 * tmp
+            u12.A = Linv + (long)step * nb * nb; u12.lda = nb; u12.sA = (long)s.nsteps * nb * nb; u12.rowA = true;
+            u12.B = tmp; u12.ldb = n; u12.sB = (long)nb * n; u12.rowB = true;
+            u12.C = F + (long)j0 * s.ldf + j0 + w; u12.ldc = s.ldf; u12.sC = s.sF; u12.rowC = true;
+            u12.M = w; u12.N = nr; u12.K = w; u12.batch = q;
+            FM_TRY(gemm<T>(u12, st));
+            GemmOp upd;  // A22 -= L21 * U12
+            upd.A = F + (long)(j0 + w) * s.ldf + j0; upd.lda = s.ldf; upd.sA = s.sF; upd.rowA = true;
+            upd.B = F + (long)j0 * s.ldf + j0 + w; upd.ldb = s.ldf; upd.sB = s.sF; upd.rowB = true;
+            upd.C = F + (long)(j0 + w) * s.ldf + j0 + w; upd.ldc = s.ldf; upd.sC = s.sF; upd.rowC = true;
+            upd.M = nr; upd.N = nr; upd.K = w; upd.batch = q;
+            upd.alpha = z64(-1.0); upd.beta = z64(1.0);
+            FM_TRY(gemm<T>(upd, st));
+        }
+    }
+    hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(s.nsteps, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF,
+                       n, nb, s.nsteps, 0, (cplx<T>*)s.Uinv);
+    FM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(perm_kernel, dim3(q), dim3(256), n * sizeof(int), st, (const int*)s.ipiv, s.perm, s.iperm,
+                       s.spiv, n);
+    FM_LAUNCH_CHECK();
+    return 0;
+}
+
+template int assemble_nodes<double>(const LUStore&, const z64*, long, const z64*, long, const z64*, hipStream_t);
+template int assemble_nodes<float>(const LUStore&, const z64*, long, const z64*, long, const z64*, hipStream_t);
+template int factor_nodes<double>(const LUStore&, hipStream_t);
+template int factor_nodes<float>(const LUStore&, hipStream_t);
+
+}  // namespace fm

@@ -1,0 +1,68 @@
+// Multi-right-hand-side node solves, accumulation of the filter and small helper kernels.
+#pragma once
+
+#include "common.h"
+#include "lu.h"
+
+namespace fm {
+
+// Per-node row-major block of n rows: node k, element (i, j) at P[k * s + i * ld + j].
+template <typename T>
+struct Rows {
+    cplx<T>* p = nullptr;
+    long ld = 0, s = 0;
+    Rows<T> at_row(long r) const { Rows<T> o = *this; o.p = p + r * ld; return o; }
+};
+
+// Y_k[i][j] = src(map_k(i), j) in precision T, where src is either one column-major FP64 block
+// shared by all nodes (src_rows == false: src[r + j * ld_src]) or a per-node row-major FP64 block
+// (src_rows == true: src[k * s_src + r * ld_src + j]); map_k is perm + k * spiv or the identity.
+template <typename T>
+int gather_rows(Rows<T> Y, int n, int ncols, int q, const z64* src, long ld_src, long s_src, bool src_rows,
+                const int* map, long spiv, hipStream_t st);
+
+// Blocked triangular solves with the factorisations in s, batched over the q nodes.
+// side 0: O = U^-1 L^-1 Y (Y already row-permuted by P), side 1: O = L^-H U^-H Y (the caller
+// applies P^T afterwards).  Y is overwritten; X is scratch; all blocks n x ncols.
+template <typename T>
+int trsolve(const LUStore& s, int side, int ncols, Rows<T> Y, Rows<T> X, Rows<T> O, hipStream_t st);
+
+// D_k[i][j] (=, +=) O_k[map_k(i)][j] converted to FP64; mask (device, q ints, may be null) skips
+// nodes whose flag is zero.
+template <typename T>
+int rows_to_f64(Rows<double> D, const Rows<T>& O, int n, int ncols, int q, const int* map, long spiv, bool add,
+                const int* mask, hipStream_t st);
+
+// Q[i + j * ldq] = sum_k w_k O_k[map_k(i)][j]  (the weighted accumulation of the filter)
+template <typename T>
+int accumulate(z64* Q, long ldq, const Rows<T>& O, int n, int ncols, int q, const int* map, long spiv,
+               const z64* w, hipStream_t st);
+
+// R_k[i][j] = src[i + j * ld]  (right-hand side copied to every node, FP64 row-major)
+int broadcast_rows(Rows<double> R, const z64* src, long ld, int n, int ncols, int q, hipStream_t st);
+
+// out[k] = ||Y_k||_F over an n x ncols row-major block (FP64)
+int fro_norms(const Rows<double>& Y, int n, int ncols, int q, double* out, hipStream_t st);
+
+// out = ||M||_F of a column-major n x ncols block
+int fro_norm_cm(const z64* M, long ld, int n, int ncols, double* out, hipStream_t st);
+
+// norm1[k] = max_j sum_i |z_k B_ij - A_ij|  (1-norm of each node matrix, FP64)
+int node_norm1(const z64* A, long lda, const z64* B, long ldb, int n, const z64* z, int q, double* colsum_scratch,
+               double* norm1, hipStream_t st);
+
+// Per column j of n x p column-major blocks X, AX, BX: out[j] = ||AX_j - lam_j BX_j||,
+// out[p + j] = ||BX_j||, out[2p + j] = ||X_j||.
+int ritz_residual_norms(const z64* X, const z64* AX, const z64* BX, long ld, int n, int p, const z64* lam,
+                        double* out, hipStream_t st);
+
+// R_k += alpha_k Y_k (row-major FP64 blocks; alpha is a device array of q values)
+int axpy_rows(Rows<double> R, const Rows<double>& Y, const z64* alpha, int n, int ncols, int q, hipStream_t st);
+
+// dst[:, c] = src[:, idx[c]] for c < ncols (column-major FP64; idx on the device)
+int gather_cols(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, const int* idx, hipStream_t st);
+
+// Column-major copy dst = src (n x ncols).
+int copy_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, hipStream_t st);
+
+}  // namespace fm
