@@ -1,0 +1,228 @@
+#!/usr/bin/env python
+"""Benchmark: FEAST iterations/s and time-to-1e-10 residual on one MI355X.
+
+Workload (default): the complex-symmetric generalized pencil of size n = 4096
+(A = (G + G^T)/(2 sqrt n) + i diag(0.05 (j/n)^2), B = I + 0.05 (H + H^H)/sqrt n,
+seeded), circle centered at 0.5+0.2i with the radius R* stored in
+tests/golden/spectrum_c1.json, q = 24 trapezoid nodes, m0 = 64, R-FEAST.
+
+One step = one complete solve from resident inputs: node assembly, all q node
+factorisations, then FEAST iterations until every candidate has relative
+residual <= 1e-10 (count repeated).  ms_per_step is therefore the
+time-to-1e-10; value is whole-job FEAST iterations per second.  The headline
+mode is FP32 LU + FP64 refinement; the same solve in plain FP64 is timed beside
+it.  Per-phase device times come from HIP events the library records on its
+stream around each launch; the roofline object uses the dominant phase.
+
+    python bench.py [--steps K] [--warmup W] [--mode fp32|fp64] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FEAST iterations/s & time-to-1e-10 residual: mixed-prec batched vs FP64"
+PEAK = {"fp64": 78.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X published)
+HBM_PEAK = 8000.0                              # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_workload(name):
+    import pencils
+    with open(os.path.join(ROOT, "tests", "golden", f"spectrum_{name}.json")) as f:
+        g = json.load(f)
+    builder = {"c1": pencils.c1, "c3": pencils.c3}[name]
+    P = builder(radius=g["radius"])
+    ref = np.array([complex(a, b) for a, b in g["nearest"]])[: g["m"]]
+    cfg = int(name[1])
+    U0 = pencils.start_block(cfg, P.n, P.m0)
+    return P, U0, ref, g
+
+
+def match_err(got, ref):
+    from scipy.optimize import linear_sum_assignment
+    if len(got) != len(ref):
+        return float("inf")
+    C = np.abs(got[:, None] - ref[None, :]) / np.abs(ref)[None, :]
+    r, c = linear_sum_assignment(C)
+    return float(C[r, c].max())
+
+
+def run_steps(fm, torch, A, B, U0, P, mode, steps, warmup, ws, timing):
+    kw = dict(center=P.center, radius=P.radius, aspect=1.0, q=P.q, m0=P.m0, precision=mode, workspace=ws)
+    results = []
+    for _ in range(warmup):
+        with fm.Feast(A, B, timing=False, **kw) as F:
+            F.iterate(U0)
+    torch.cuda.synchronize()
+    phases = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F = fm.Feast(A, B, timing=timing, **kw)
+        r = F.iterate(U0)
+        results.append(r)
+        if timing:
+            ph = F.timing()
+            if phases is None:
+                phases = {k: dict(v) for k, v in ph.items()}
+            else:
+                for k, v in ph.items():
+                    for f in ("ms", "flops", "launches"):
+                        phases[k][f] += v[f]
+        F.close()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, results, phases
+
+
+def cpu_baseline(P, U0, iters, sample_nodes=4):
+    """The oracle (NumPy/SciPy, FP64) timed on a bounded sample of the same workload: a few of the
+    q node factorisations and solves plus one Rayleigh-Ritz step, scaled to q nodes and the
+    iteration count of the solve."""
+    import scipy.linalg
+    from oracle import feast as ofeast
+    from oracle import quadrature as oq
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("internal_api") == "openblas"] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    z, s = oq.nodes_and_weights(P.center, P.radius, 1.0, "trapezoid", P.q)
+    t0 = time.perf_counter()
+    lus = [scipy.linalg.lu_factor(ofeast.node_matrix(P.A, P.B, zk)) for zk in z[:sample_nodes]]
+    t_lu = (time.perf_counter() - t0) / sample_nodes
+    t0 = time.perf_counter()
+    BU = P.B @ U0
+    t_bu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Y = [scipy.linalg.lu_solve(lu, BU) for lu in lus]
+    t_solve = (time.perf_counter() - t0) / sample_nodes
+    Q = sum(sk * yk for sk, yk in zip(s[:sample_nodes], Y))
+    t0 = time.perf_counter()
+    Qo = ofeast.orthonormalize(Q)
+    Ah = Qo.conj().T @ (P.A @ Qo)
+    Bh = Qo.conj().T @ (P.B @ Qo)
+    lam, W = scipy.linalg.eig(Ah, Bh)
+    X = Qo @ W
+    ofeast.residuals(P.A, P.B, lam, X)
+    t_rr = time.perf_counter() - t0
+    total = P.q * t_lu + iters * (t_bu + P.q * t_solve + t_rr)
+    return dict(value=iters / total, unit="FEAST iterations/s", cores=int(cores), kind="oracle",
+                time_to_1e10_s=total,
+                sample=f"{sample_nodes} of {P.q} node LUs and solves, one B U and one Rayleigh-Ritz step "
+                       f"(n={P.n}, m0={P.m0}), scaled to {P.q} nodes and {iters} iterations",
+                measured_s=dict(lu_per_node=t_lu, solve_per_node=t_solve, bu=t_bu, rayleigh_ritz=t_rr))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one MI355X: the path is a single-GPU build (see DESIGN.md for how it "
+              "would shard over contour nodes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1404_2891_amd as fm
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = "cuda:0"
+    P, U0h, ref, g = load_workload(args.workload)
+    log(f"workload {P.name}: n={P.n} q={P.q} m0={P.m0} R*={P.radius:.6g} m={g['m']}")
+    A = fm.to_device(P.A, dev)
+    B = fm.to_device(P.B, dev)
+    U0 = fm.to_device(U0h, dev)
+    nbytes = max(fm.workspace_size(P.n, P.m0, fm.binding.make_contour(P.center, P.radius, 1.0, P.q),
+                                   fm.binding.make_options(m), True) for m in ("fp32", "fp64"))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32") if m != args.mode])
+    out = {}
+    for mode in modes:
+        steps = args.steps if mode == args.mode else max(1, min(args.steps, 2))
+        wall, results, phases = run_steps(fm, torch, A, B, U0, P, mode, steps, args.warmup, ws, timing=True)
+        iters = sum(r.iterations for r in results)
+        errs = [match_err(r.lam, ref) for r in results]
+        out[mode] = dict(ms_per_step=1e3 * wall / steps, iters_per_s=iters / wall, iterations=results[0].iterations,
+                         converged=all(r.converged for r in results), m=len(results[0].lam),
+                         max_resid=float(max(r.resid.max() for r in results)), eig_err_vs_oracle=max(errs),
+                         ir_sweeps=results[0].ir_sweeps,
+                         phases={k: dict(ms=v["ms"] / steps, launches=v["launches"] // steps,
+                                         tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None)
+                                 for k, v in phases.items()})
+        log(f"{mode}: {out[mode]['ms_per_step']:.1f} ms/solve, {out[mode]['iterations']} iterations, "
+            f"m={out[mode]['m']}, err {out[mode]['eig_err_vs_oracle']:.1e}")
+        for k, v in out[mode]["phases"].items():
+            log(f"   {k:14s} {v['ms']:9.2f} ms  {v['launches']:6d} launches  {v['tflops']} TF/s")
+
+    head = out[args.mode]
+    # dominant phase of the headline mode and its roofline
+    dom = max(head["phases"], key=lambda k: head["phases"][k]["ms"])
+    ph_all = None
+    kw = dict(center=P.center, radius=P.radius, aspect=1.0, q=P.q, m0=P.m0, precision=args.mode, workspace=ws)
+    with fm.Feast(A, B, timing=True, **kw) as F:
+        F.iterate(U0)
+        ph_all = F.timing()
+    dph = ph_all[dom]
+    prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else "fp32"
+    achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12 if dph["ms"] > 0 else 0.0
+    roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
+                    frac=achieved / PEAK[prec_of_phase], traffic=None, kernel_phase=dom,
+                    avg_launch_ms=dph["ms"] / max(1, dph["launches"]),
+                    flops_per_launch=dph["flops"] / max(1, dph["launches"]))
+    lu = ph_all["lu_update"]
+    lu_roof = dict(achieved=lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0,
+                   peak=PEAK[args.mode], unit="TFLOP/s", avg_launch_ms=lu["ms"] / max(1, lu["launches"]))
+    lu_roof["frac"] = lu_roof["achieved"] / lu_roof["peak"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(P, U0h, out.get("fp64", head)["iterations"])
+
+    line = {
+        "metric": METRIC,
+        "value": head["iters_per_s"],
+        "unit": "FEAST iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.mode == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"complex-symmetric generalized pencil n={P.n}, circle c={P.center}, "
+                               f"R*={P.radius:.6g} (m={g['m']} inside), q={P.q} trapezoid nodes, m0={P.m0}, "
+                               f"R-FEAST, tol 1e-10",
+                   "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
+                   "step": "setup (assembly + q LUs) + iterations to 1e-10"},
+        "time_to_1e10_s": head["ms_per_step"] / 1e3,
+        "iterations": head["iterations"],
+        "eig_err_vs_oracle": head["eig_err_vs_oracle"],
+        "modes": out,
+        "speedup_vs_fp64": (out["fp64"]["ms_per_step"] / head["ms_per_step"]) if "fp64" in out else None,
+        "roofline": roofline,
+        "lu_update_roofline": lu_roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

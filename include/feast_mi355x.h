@@ -71,8 +71,11 @@ typedef struct {
     double candidate_tol;/* a Ritz pair inside C is a candidate when ||Ax - lBx||/||x|| is at
                             most this (Section 5 preamble); default 1e-4                        */
     int ir_max;          /* refinement sweeps per solve (FP32/FP16 modes), default 10          */
-    double ir_tol;       /* refinement stops when ||R_k||_F <= ir_tol (||T_k||_1 ||Y_k||_F +
-                            ||rhs||_F); 0 selects 8 sqrt(n) u64                                 */
+    double ir_tol;       /* refinement of a node solve stops when the correction satisfies
+                            ||D_k||_F <= ir_tol ||Y_k||_F, or when corrections stop halving;
+                            0 selects sqrt(n) u64 for feast_filter / feast_node_solve and an
+                            adaptive target inside feast_iterate                              */
+    int timing;          /* 1: record HIP events around every phase launch (see feast_timing_*) */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */
@@ -114,7 +117,10 @@ int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, i
  * side = 1 (left, eqn:quadf_surMconj):
  *     Q = B^-H rho(M)^H B^H U = sum_k conj(sigma_k) (phi_k B - A)^-H (B^H U)
  * U and Q are device n x ncols blocks (ncols <= m0).  In the FP32/FP16 modes
- * every node solve is refined in FP64 (see feast_options.ir_*).  Asynchronous
+ * every node solve is refined in FP64 until the correction is below ir_tol
+ * relative to the solution (ir_tol = 0: sqrt(n) u64, i.e. FP64 accuracy) or
+ * stops halving; feast_iterate instead sets the target from the residual the
+ * iteration has reached, tightening it as it converges.  Asynchronous
  * in FP64 mode; the refinement modes synchronise once per sweep.
  * Returns 0, -i, FEAST_EIR (a node's refinement stalled), FEAST_EDEVICE. */
 int feast_filter(feast_ctx* ctx, int side, int ncols, const void* U, int ldu, void* Q, int ldq);
@@ -153,6 +159,7 @@ typedef struct {
     void* X; int ldx;
     void* Y; int ldy;
     double* history;
+    int ir_sweeps;       /* output: refinement sweeps summed over all filters (FP32/FP16 modes) */
 } feast_result;
 
 int feast_iterate(feast_ctx* ctx, const void* U0, int ldu0, feast_result* result);
@@ -164,6 +171,23 @@ int feast_iterate(feast_ctx* ctx, const void* U0, int ldu0, feast_result* result
  * left eigenvectors scaled so that Z^H Bh W = I.  Returns 0, -i,
  * FEAST_EREDUCED. */
 int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z);
+
+/* ---- measurement --------------------------------------------------------
+ * With feast_options.timing = 1 the context records a pair of HIP events on its
+ * stream around every launch of each phase below; feast_timing_read returns the
+ * summed device time (synchronising on the last event), the algorithmic flops
+ * of those launches (8 real flops per complex multiply-add) and the launch
+ * count.  Phases: the LU trailing update (8 (n-j0-w)^2 w q flops per launch),
+ * the panel factorisations, the other LU steps (swaps, diagonal-block
+ * inverses, U12), the multi-RHS node solves (8 n^2 ncols q per launch group),
+ * the FP64 refinement residuals, and the Rayleigh-Ritz products. */
+enum {
+    FEAST_PHASE_LU_UPDATE = 0, FEAST_PHASE_LU_PANEL = 1, FEAST_PHASE_LU_OTHER = 2,
+    FEAST_PHASE_SOLVE = 3, FEAST_PHASE_REFINE = 4, FEAST_PHASE_RR = 5, FEAST_PHASE_COUNT = 6
+};
+typedef struct { double ms; double flops; long launches; } feast_phase_time;
+int feast_timing_read(feast_ctx* ctx, int phase, feast_phase_time* out);
+int feast_timing_reset(feast_ctx* ctx);
 
 void feast_destroy(feast_ctx* ctx);
 const char* feast_strerror(int code);

@@ -36,7 +36,7 @@ VARIANTS = {"R": 0, "Bi": 1}
 EXPORTED = [
     "feast_default_options", "feast_contour_nodes", "feast_workspace_size", "feast_setup",
     "feast_filter", "feast_node_solve", "feast_iterate", "feast_reduced_eig", "feast_destroy",
-    "feast_strerror",
+    "feast_strerror", "feast_timing_read", "feast_timing_reset",
 ]
 
 
@@ -48,14 +48,22 @@ class Contour(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
-                ("ir_tol", ctypes.c_double)]
+                ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int)]
+
+
+class PhaseTime(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("flops", ctypes.c_double), ("launches", ctypes.c_long)]
+
+
+PHASES = ["lu_update", "lu_panel", "lu_other", "solve", "refine", "rayleigh_ritz"]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("iterations", ctypes.c_int), ("converged", ctypes.c_int),
                 ("lambda_", ctypes.c_void_p), ("resid", ctypes.c_void_p),
                 ("X", ctypes.c_void_p), ("ldx", ctypes.c_int),
-                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int), ("history", ctypes.c_void_p)]
+                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int), ("history", ctypes.c_void_p),
+                ("ir_sweeps", ctypes.c_int)]
 
 
 class FeastError(RuntimeError):
@@ -101,6 +109,10 @@ def lib():
         L.feast_reduced_eig.restype = i
         L.feast_destroy.argtypes = [vp]
         L.feast_destroy.restype = None
+        L.feast_timing_read.argtypes = [vp, i, ctypes.POINTER(PhaseTime)]
+        L.feast_timing_read.restype = i
+        L.feast_timing_reset.argtypes = [vp]
+        L.feast_timing_reset.restype = i
         L.feast_strerror.argtypes = [i]
         L.feast_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -123,7 +135,7 @@ def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid") -> C
 
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0) -> Options:
+                 ir_tol=0.0, timing=False) -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -133,6 +145,7 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.candidate_tol = float(candidate_tol)
     o.ir_max = int(ir_max)
     o.ir_tol = float(ir_tol)
+    o.timing = int(bool(timing))
     return o
 
 
@@ -210,22 +223,29 @@ class IterateResult:
     history: np.ndarray      # iterations x 4: count, max relative residual, trace re, trace im
     code: int
     ritz: np.ndarray         # all m0 Ritz values (candidates first)
+    ir_sweeps: int = 0       # refinement sweeps summed over the run
 
 
 class Feast:
     """One pencil: node factorisations resident on the device for the life of the object."""
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
-                 precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0):
+                 precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
+                 timing=False, workspace=None):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
         self.q = q
         self.A, self.B = A, B
         self.contour = make_contour(center, radius, aspect, q, rule)
-        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol)
+        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        if workspace is not None:
+            if workspace.numel() < nbytes or workspace.data_ptr() % 256:
+                raise ValueError("workspace too small or misaligned")
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
         self._ctx = ctypes.c_void_p(None)
         code = lib().feast_setup(ctypes.byref(self._ctx), self.n, A.data_ptr(), _ld(A),
                                  None if B is None else B.data_ptr(), 0 if B is None else _ld(B),
@@ -262,6 +282,18 @@ class Feast:
         _check(code, "feast_filter")
         return Q
 
+    def timing(self) -> dict:
+        """Per-phase device time (ms), algorithmic flops and launch counts (needs timing=True)."""
+        out = {}
+        for i, name in enumerate(PHASES):
+            t = PhaseTime()
+            _check(lib().feast_timing_read(self._ctx, i, ctypes.byref(t)), "feast_timing_read")
+            out[name] = dict(ms=t.ms, flops=t.flops, launches=t.launches)
+        return out
+
+    def timing_reset(self):
+        _check(lib().feast_timing_reset(self._ctx), "feast_timing_reset")
+
     def node_solve(self, k, R, side=0):
         Y = empty_cm(self.n, R.shape[1], R.device)
         _check(lib().feast_node_solve(self._ctx, k, side, R.shape[1], R.data_ptr(), _ld(R), Y.data_ptr(), _ld(Y)),
@@ -288,4 +320,5 @@ class Feast:
         _check(code, "feast_iterate", ok=(FEAST_OK, FEAST_ENOCONV))
         m = r.m
         return IterateResult(lam[:m].copy(), resid[:m].copy(), X[:, :m], None if Y is None else Y[:, :m],
-                             r.iterations, bool(r.converged), hist[: r.iterations].copy(), code, lam.copy())
+                             r.iterations, bool(r.converged), hist[: r.iterations].copy(), code, lam.copy(),
+                             r.ir_sweeps)

@@ -19,6 +19,7 @@
 #include "hostla.h"
 #include "lu.h"
 #include "solve.h"
+#include "timing.h"
 
 using namespace fm;
 using cd = std::complex<double>;
@@ -71,9 +72,12 @@ struct feast_ctx {
     // host staging (pinned)
     char* h = nullptr;
     size_t hbytes = 0;
-    // refinement statistics of the last filter
+    // refinement: forward-error target of the next filter, statistics of the last one
+    double ir_target = 0.0;
     int ir_sweeps = 0;
     double ir_relres = 0.0;
+    long ir_sweeps_total = 0;
+    Timer timer;
 };
 
 namespace {
@@ -209,26 +213,34 @@ int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rh
     Rows<T> Y = rows<T>(c->Yw, c), X = rows<T>(c->Xw, c), O = rows<T>(c->Ow, c);
     const int* perm = side == 0 ? v.perm : nullptr;
     const int* back = side == 0 ? nullptr : v.iperm;
+    const double solve_flops = 8.0 * n * (double)n * ncols * qv;
     FM_TRY(gather_rows<T>(Y, n, ncols, qv, rhs, ldr, 0, false, perm, v.spiv, st));
+    c->timer.start(PH_SOLVE, st);
     FM_TRY(trsolve<T>(v, side, ncols, Y, X, O, st));
+    c->timer.stop(PH_SOLVE, st, solve_flops);
     c->ir_sweeps = 0;
     c->ir_relres = 0.0;
     if (std::is_same<T, double>::value) {
         FM_TRY(accumulate<T>(out, ldo, O, n, ncols, qv, back, v.spiv, w, st));
         return 0;
     }
-    // FP64 iterative refinement of every node solve
+    // FP64 iterative refinement of every node solve: R_k = rhs - T_k Y_k in FP64, correction
+    // D_k = solve_low(R_k), Y_k += D_k.  A node stops when ||D_k|| <= tol ||Y_k|| (the correction
+    // estimates the forward error of the previous iterate) or when the corrections stop halving.
     Rows<double> Y64 = rows<double>(c->Y64, c), R64 = rows<double>(c->R64, c);
     FM_TRY(rows_to_f64<T>(Y64, O, n, ncols, qv, back, v.spiv, false, nullptr, st));
-    double* nrm = c->nrm_d;  // [0, qv): ||R_k||, [qv, 2qv): ||Y_k||, [2qv]: ||rhs||
-    FM_TRY(fro_norm_cm(rhs, ldr, n, ncols, nrm + 2 * qv, st));
-    const double u64 = 0.5 * 2.220446049250313e-16;
-    const double ir_tol = c->o.ir_tol > 0 ? c->o.ir_tol : 8.0 * std::sqrt((double)n) * u64;
-    std::vector<int> active(qv, 1);
-    std::vector<double> prev(qv, INFINITY), hn(2 * qv + 1);
+    double* nrm = c->nrm_d;  // [0, qv): ||D_k||, [qv, 2qv): ||Y_k||
+    const double fwd_tol = c->ir_target;
+    std::vector<int> active(qv, 1), uploaded(qv, 0);
+    std::vector<double> prev(qv, INFINITY), hn(2 * qv);
     const z64* negz = (side == 0 ? c->negz : c->negzc) + k0;
-    for (int sweep = 0;; ++sweep) {
+    int sweep = 0;
+    double worst = 0.0;
+    bool stalled = false;
+    while (sweep < c->o.ir_max) {
+        ++sweep;
         // R_k = rhs - T_k Y_k with T_k = z_k B - A (side 0) or its conjugate transpose (side 1)
+        c->timer.start(PH_REFINE, st);
         FM_TRY(broadcast_rows(R64, rhs, ldr, n, ncols, qv, st));
         if (c->B) {
             GemmOp g;
@@ -248,33 +260,42 @@ int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rh
         g.M = n; g.N = ncols; g.K = n; g.batch = qv;
         g.alpha = z64(1.0); g.beta = z64(1.0);
         FM_TRY(gemm<double>(g, st));
-        FM_TRY(fro_norms(R64, n, ncols, qv, nrm, st));
-        FM_TRY(fro_norms(Y64, n, ncols, qv, nrm + qv, st));
-        FM_TRY(d2h(c, hn.data(), nrm, (2 * qv + 1) * sizeof(double)));
-        int n_active = 0;
-        double worst = 0.0;
-        for (int k = 0; k < qv; ++k) {
-            const double scale = c->norm1[k0 + k] * hn[qv + k] + hn[2 * qv];
-            const double rel = hn[k] / scale;
-            worst = std::max(worst, rel);
-            if (!active[k]) continue;
-            if (hn[k] <= ir_tol * scale || hn[k] > 0.5 * prev[k]) {
-                active[k] = 0;
-            } else {
-                ++n_active;
-            }
-            prev[k] = hn[k];
-        }
-        c->ir_sweeps = sweep;
-        c->ir_relres = worst;
-        if (n_active == 0 || sweep >= c->o.ir_max) break;
-        FM_TRY(h2d(c, c->mask_d, active.data(), qv * sizeof(int)));
+        c->timer.stop(PH_REFINE, st, solve_flops * (c->B ? 2.0 : 1.0));
         FM_TRY(gather_rows<T>(Y, n, ncols, qv, R64.p, R64.ld, R64.s, true, perm, v.spiv, st));
+        c->timer.start(PH_SOLVE, st);
         FM_TRY(trsolve<T>(v, side, ncols, Y, X, O, st));
+        c->timer.stop(PH_SOLVE, st, solve_flops);
+        if (active != uploaded) {
+            FM_TRY(h2d(c, c->mask_d, active.data(), qv * sizeof(int)));
+            uploaded = active;
+        }
+        FM_TRY(fro_norms<T>(O, n, ncols, qv, nrm, st));
+        FM_TRY(fro_norms<double>(Y64, n, ncols, qv, nrm + qv, st));
         FM_TRY(rows_to_f64<T>(Y64, O, n, ncols, qv, back, v.spiv, true, c->mask_d, st));
+        FM_TRY(d2h(c, hn.data(), nrm, 2 * qv * sizeof(double)));
+        int n_active = 0;
+        worst = 0.0;
+        for (int k = 0; k < qv; ++k) {
+            const double ratio = hn[k] / std::max(hn[qv + k], 1e-300);
+            if (active[k]) {
+                if (ratio <= fwd_tol) {
+                    active[k] = 0;
+                } else if (hn[k] > 0.5 * prev[k]) {
+                    active[k] = 0;
+                    if (ratio > 1e-6) stalled = true;
+                } else {
+                    ++n_active;
+                }
+                prev[k] = hn[k];
+            }
+            worst = std::max(worst, ratio);
+        }
+        if (n_active == 0) break;
     }
+    c->ir_sweeps = sweep;
+    c->ir_relres = worst;
     FM_TRY(accumulate<double>(out, ldo, Y64, n, ncols, qv, nullptr, v.spiv, w, st));
-    if (c->ir_relres > 1e-6) return FEAST_EIR;
+    if (stalled) return FEAST_EIR;
     return 0;
 }
 
@@ -358,6 +379,24 @@ int orthonormalize(feast_ctx* c, z64* Q) {
     return 0;
 }
 
+double full_accuracy_target(const feast_ctx* c) { return 1.1102230246251565e-16 * std::sqrt((double)c->n); }
+
+double default_ir_target(const feast_ctx* c) { return c->o.ir_tol > 0 ? c->o.ir_tol : full_accuracy_target(c); }
+
+// rhs = op(B) U (or U itself when B = I), then the node solves and the weighted sum.
+int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* Q, long ldq) {
+    const z64* rhs = U;
+    long ldr = ldu;
+    if (c->B) {
+        FM_TRY(apply_B(c, side, ncols, U, ldu, c->BU, c->n));
+        rhs = c->BU;
+        ldr = c->n;
+    }
+    const int rc = apply(c, 0, c->q, side, ncols, rhs, ldr, side == 0 ? c->wR : c->wL, Q, ldq);
+    c->ir_sweeps_total += c->ir_sweeps;
+    return rc;
+}
+
 bool inside(cd lam, const feast_contour& C) {
     const double x = (lam.real() - C.c_re) / C.radius, y = (lam.imag() - C.c_im) / (C.aspect * C.radius);
     return x * x + y * y < 1.0;
@@ -376,6 +415,24 @@ void feast_default_options(feast_options* o) {
     o->candidate_tol = 1e-4;
     o->ir_max = 10;
     o->ir_tol = 0.0;
+    o->timing = 0;
+}
+
+int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
+    if (!c) return -1;
+    if (phase < 0 || phase >= PH_COUNT) return -2;
+    if (!out) return -3;
+    out->ms = c->timer.ms((Phase)phase);
+    out->flops = c->timer.flops[phase];
+    out->launches = c->timer.launches[phase];
+    return 0;
+}
+
+int feast_timing_reset(feast_ctx* c) {
+    if (!c) return -1;
+    FM_HIP(hipStreamSynchronize(c->st));
+    c->timer.reset();
+    return 0;
 }
 
 int feast_workspace_size(int n, int m0, const feast_contour* C, const feast_options* o, int has_B, size_t* bytes) {
@@ -402,6 +459,10 @@ int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, i
     feast_ctx* c = new feast_ctx;
     fill_dims(c, n, m0, C, o);
     c->st = (hipStream_t)stream;
+    if (o->timing) {
+        c->timer.on = true;
+        c->lu.timer = &c->timer;
+    }
     c->A = (const z64*)A; c->lda = lda;
     c->B = (const z64*)B; c->ldb = ldb;
     Bump b;
@@ -464,14 +525,8 @@ int feast_filter(feast_ctx* c, int side, int ncols, const void* U, int ldu, void
     if (ldu < c->n) return -5;
     if (!Q) return -6;
     if (ldq < c->n) return -7;
-    const z64* rhs = (const z64*)U;
-    long ldr = ldu;
-    if (c->B) {
-        FM_TRY(apply_B(c, side, ncols, (const z64*)U, ldu, c->BU, c->n));
-        rhs = c->BU;
-        ldr = c->n;
-    }
-    return apply(c, 0, c->q, side, ncols, rhs, ldr, side == 0 ? c->wR : c->wL, (z64*)Q, ldq);
+    c->ir_target = default_ir_target(c);
+    return filter_impl(c, side, ncols, (const z64*)U, ldu, (z64*)Q, ldq);
 }
 
 int feast_node_solve(feast_ctx* c, int k, int side, int ncols, const void* R, int ldr, void* Y, int ldy) {
@@ -483,6 +538,7 @@ int feast_node_solve(feast_ctx* c, int k, int side, int ncols, const void* R, in
     if (ldr < c->n) return -6;
     if (!Y) return -7;
     if (ldy < c->n) return -8;
+    c->ir_target = default_ir_target(c);
     return apply(c, k, 1, side, ncols, (const z64*)R, ldr, c->ones, (z64*)Y, ldy);
 }
 
@@ -545,6 +601,8 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
     }
     int prev_count = -1, prev_inside = -1;
     cd prev_trace(0.0, 0.0);
+    double res_prev = NAN, res_last = NAN;   // max relative candidate residual, two last iterations
+    c->ir_sweeps_total = 0;
     std::vector<int> order;
     std::vector<double> rel(p), paper(p);
     std::vector<cd> lam(p);
@@ -553,13 +611,25 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
     int it = 1;
     for (; it <= c->o.max_iter; ++it) {
         // filter and orthonormalise (Q = orth(rho(M) U); Bi-FEAST also P = orth(left filter of V))
-        FM_TRY(feast_filter(c, 0, p, U, n, Q, n));
+        // refinement target: loose while the iteration is far from converged, tightening with the
+        // residual it is expected to reach next; full accuracy when the decrease stalls
+        if (c->o.ir_tol > 0) {
+            c->ir_target = c->o.ir_tol;
+        } else if (!(res_last > 0)) {
+            c->ir_target = 1e-6;
+        } else if (res_prev > 0 && res_last < 0.1 * res_prev) {
+            c->ir_target = std::max(full_accuracy_target(c), 1e-3 * res_last * (res_last / res_prev));
+        } else {
+            c->ir_target = full_accuracy_target(c);
+        }
+        FM_TRY(filter_impl(c, 0, p, U, n, Q, n));
         FM_TRY(orthonormalize(c, Q));
         if (bi) {
-            FM_TRY(feast_filter(c, 1, p, c->Vb, n, c->Pb, n));
+            FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n));
             FM_TRY(orthonormalize(c, c->Pb));
         }
         // Rayleigh-Ritz: A^ = W^H A Q, B^ = W^H B Q with W = Q (R-FEAST) or P (Bi-FEAST)
+        c->timer.start(PH_RR, st);
         {
             GemmOp g;
             g.A = c->A; g.lda = c->lda; g.B = Q; g.ldb = n; g.C = AQ; g.ldc = n;
@@ -572,6 +642,7 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
             FM_TRY(copy_cm(BQ, n, Q, n, n, p, st));
         }
         FM_TRY(gram(c, bi ? c->Pb : Q, n, AQ, n, 2 * p, c->AhBh));
+        c->timer.stop(PH_RR, st, 8.0 * n * (double)n * p * (c->B ? 2.0 : 1.0) + 16.0 * n * (double)p * p);
         FM_TRY(d2h(c, hbuf.data(), c->AhBh, (size_t)2 * p * p * sizeof(z64)));
         int rc = feast_reduced_eig(p, (const double*)hbuf.data(), (const double*)(hbuf.data() + (size_t)p * p),
                                    (double*)hlam.data(), (double*)hW.data(), bi ? (double*)hZ.data() : nullptr);
@@ -628,6 +699,8 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
         prev_count = count;
         prev_inside = n_inside;
         prev_trace = trace;
+        res_prev = res_last;
+        res_last = count ? maxrel : NAN;
         if (done || it == c->o.max_iter) {
             order.insert(order.end(), rest.begin(), rest.end());
             break;
@@ -646,6 +719,7 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
     if (bi && res->Y) FM_TRY(gather_cols((z64*)res->Y, res->ldy, c->Vb, n, n, p, c->idx_d, st));
     FM_HIP(hipStreamSynchronize(st));
     res->m = count;
+    res->ir_sweeps = (int)c->ir_sweeps_total;
     res->iterations = it;
     res->converged = done;
     return done ? 0 : FEAST_ENOCONV;

@@ -23,6 +23,9 @@ struct GemmOp {
     // compute type) and a second kernel reduces them; requires alpha_b == nullptr.
     int splitk = 1;
     void* partial = nullptr;
+    // kind 1 selects a separate kernel instance (same code) for the LU trailing update, so that
+    // profilers can attribute it
+    int kind = 0;
 };
 
 // T = double (complex128 operands, FP64 MFMA) or float (complex64, FP32 MFMA).

@@ -25,6 +25,12 @@ __device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfm
 constexpr int BK = 16;
 constexpr int PAD = 2;
 
+// Row of the 16 x 16 output block held in accumulator element v of lane l (column l % 16):
+// the FP32 instruction stores rows 4 (l / 16) + v, the FP64 one rows l / 16 + 4 v.
+template <typename T> __device__ inline int out_row(int lane, int v);
+template <> __device__ inline int out_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ inline int out_row<double>(int lane, int v) { return (lane >> 4) + 4 * v; }
+
 template <typename T>
 struct Params {
     const cplx<T>* A; long lda, sA;
@@ -37,7 +43,7 @@ struct Params {
     cplx<T>* partial;
 };
 
-template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC>
+template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC, int KIND>
 __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     constexpr int BM = WM * RB * 16, BN = WN * CB * 16, NT = 64 * WM * WN;
     constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
@@ -143,7 +149,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
         }
     }
 
-    // epilogue: lane l holds rows 4*(l/16) + v, column l%16 of each 16 x 16 block
+    // epilogue: lane l holds column l % 16 of each 16 x 16 block, rows out_row<T>(l, v)
     T ar = p.ar, ai = p.ai;
     if (p.alpha_b) {
         ar = T(p.alpha_b[b].re);
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
         for (int c = 0; c < CB; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = m0 + wm * RB * 16 + r * 16 + 4 * (lane >> 4) + v;
+                const int i = m0 + wm * RB * 16 + r * 16 + out_row<T>(lane, v);
                 const int j = n0 + wn * CB * 16 + c * 16 + (lane & 15);
                 if (i < p.M && j < p.N) {
                     const T xr = cre[r][c][v], xi = cim[r][c][v];
@@ -202,12 +208,12 @@ __global__ void splitk_reduce(Params<T> p) {
     }
 }
 
-template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC>
+template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC, int KIND = 0>
 void launch_cfg(Params<T> p, hipStream_t st) {
     constexpr int BM = WM * RB * 16, BN = WN * CB * 16;
     p.tiles_m = ceil_div(p.M, BM);
     dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.splitk);
-    hipLaunchKernelGGL((cgemm_kernel<T, WM, WN, RB, CB, RA, RBm, RC>), grid, dim3(64 * WM * WN), 0, st, p);
+    hipLaunchKernelGGL((cgemm_kernel<T, WM, WN, RB, CB, RA, RBm, RC, KIND>), grid, dim3(64 * WM * WN), 0, st, p);
 }
 
 template <typename T, bool RA, bool RBm, bool RC>
@@ -240,6 +246,12 @@ int gemm(const GemmOp& op, hipStream_t st) {
     p.conjA = op.conjA; p.conjB = op.conjB;
     p.partial = (cplx<T>*)op.partial;
     p.tiles_m = 1;
+    if (op.kind == 1) {  // LU trailing update: all operands row-major
+        if (!(op.rowA && op.rowB && op.rowC) || p.splitk > 1) return FEAST_EUNSUPPORTED;
+        launch_cfg<T, 2, 2, 2, 2, true, true, true, 1>(p, st);
+        FM_LAUNCH_CHECK();
+        return 0;
+    }
     const int code = (op.rowA ? 4 : 0) | (op.rowB ? 2 : 0) | (op.rowC ? 1 : 0);
     switch (code) {
         case 0: launch_layout<T, false, false, false>(p, st); break;

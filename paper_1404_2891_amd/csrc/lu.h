@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "timing.h"
 
 namespace fm {
 
@@ -18,6 +19,7 @@ struct LUStore {
     int* info = nullptr;         // q ints: 0, or first zero-pivot column + 1
     void* tmp = nullptr;         // q * nb * n elements: swapped U12 rows awaiting the block inverse
     int n = 0, q = 0, nb = 0, nsteps = 0;
+    Timer* timer = nullptr;      // optional per-phase timing
 };
 
 // T_k = z_k B - A for every node (A, B column-major complex128; B == nullptr means I), written to

@@ -256,9 +256,12 @@ int factor_nodes(const LUStore& s, hipStream_t st) {
     FM_LAUNCH_CHECK();
     for (int step = 0; step < s.nsteps; ++step) {
         const int j0 = step * nb, w = std::min(nb, n - j0);
+        if (s.timer) s.timer->start(PH_LU_PANEL, st);
         hipLaunchKernelGGL((panel_kernel<T>), dim3(q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, s.ipiv, s.spiv,
                            s.info);
         FM_LAUNCH_CHECK();
+        if (s.timer) s.timer->stop(PH_LU_PANEL, st, 0.0);
+        if (s.timer) s.timer->start(PH_LU_OTHER, st);
         hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF, n,
                            nb, s.nsteps, step, Linv);
         FM_LAUNCH_CHECK();
@@ -275,13 +278,19 @@ int factor_nodes(const LUStore& s, hipStream_t st) {
             u12.C = F + (long)j0 * s.ldf + j0 + w; u12.ldc = s.ldf; u12.sC = s.sF; u12.rowC = true;
             u12.M = w; u12.N = nr; u12.K = w; u12.batch = q;
             FM_TRY(gemm<T>(u12, st));
+            if (s.timer) s.timer->stop(PH_LU_OTHER, st, 0.0);
             GemmOp upd;  // A22 -= L21 * U12
             upd.A = F + (long)(j0 + w) * s.ldf + j0; upd.lda = s.ldf; upd.sA = s.sF; upd.rowA = true;
             upd.B = F + (long)j0 * s.ldf + j0 + w; upd.ldb = s.ldf; upd.sB = s.sF; upd.rowB = true;
             upd.C = F + (long)(j0 + w) * s.ldf + j0 + w; upd.ldc = s.ldf; upd.sC = s.sF; upd.rowC = true;
             upd.M = nr; upd.N = nr; upd.K = w; upd.batch = q;
             upd.alpha = z64(-1.0); upd.beta = z64(1.0);
+            upd.kind = 1;
+            if (s.timer) s.timer->start(PH_LU_UPDATE, st);
             FM_TRY(gemm<T>(upd, st));
+            if (s.timer) s.timer->stop(PH_LU_UPDATE, st, 8.0 * nr * (double)nr * w * q);
+        } else if (s.timer) {
+            s.timer->stop(PH_LU_OTHER, st, 0.0);
         }
     }
     hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(s.nsteps, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF,

@@ -41,8 +41,9 @@ int accumulate(z64* Q, long ldq, const Rows<T>& O, int n, int ncols, int q, cons
 // R_k[i][j] = src[i + j * ld]  (right-hand side copied to every node, FP64 row-major)
 int broadcast_rows(Rows<double> R, const z64* src, long ld, int n, int ncols, int q, hipStream_t st);
 
-// out[k] = ||Y_k||_F over an n x ncols row-major block (FP64)
-int fro_norms(const Rows<double>& Y, int n, int ncols, int q, double* out, hipStream_t st);
+// out[k] = ||Y_k||_F over an n x ncols row-major block, accumulated in FP64
+template <typename T>
+int fro_norms(const Rows<T>& Y, int n, int ncols, int q, double* out, hipStream_t st);
 
 // out = ||M||_F of a column-major n x ncols block
 int fro_norm_cm(const z64* M, long ld, int n, int ncols, double* out, hipStream_t st);

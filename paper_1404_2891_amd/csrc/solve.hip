@@ -82,13 +82,14 @@ __device__ inline double block_max(double v, double* sh) {
     return s;
 }
 
-__global__ __launch_bounds__(256) void fro_rows_kernel(const z64* __restrict__ Y, long ld, long s, int n, int ncols,
+template <typename T>
+__global__ __launch_bounds__(256) void fro_rows_kernel(const cplx<T>* __restrict__ Y, long ld, long s, int n, int ncols,
                                                        double* out) {
     __shared__ double sh[4];
     const int k = blockIdx.x;
     double acc = 0.0;
     for (long t = threadIdx.x; t < (long)n * ncols; t += blockDim.x) {
-        const z64 v = Y[k * s + (t / ncols) * ld + t % ncols];
+        const z64 v(Y[k * s + (t / ncols) * ld + t % ncols]);
         acc += v.re * v.re + v.im * v.im;
     }
     acc = block_sum(acc, sh);
@@ -277,8 +278,9 @@ int broadcast_rows(Rows<double> R, const z64* src, long ld, int n, int ncols, in
     return 0;
 }
 
-int fro_norms(const Rows<double>& Y, int n, int ncols, int q, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(fro_rows_kernel, dim3(q), dim3(256), 0, st, (const z64*)Y.p, Y.ld, Y.s, n, ncols, out);
+template <typename T>
+int fro_norms(const Rows<T>& Y, int n, int ncols, int q, double* out, hipStream_t st) {
+    hipLaunchKernelGGL((fro_rows_kernel<T>), dim3(q), dim3(256), 0, st, (const cplx<T>*)Y.p, Y.ld, Y.s, n, ncols, out);
     FM_LAUNCH_CHECK();
     return 0;
 }
@@ -329,7 +331,8 @@ int copy_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, hipS
     template int trsolve<T>(const LUStore&, int, int, Rows<T>, Rows<T>, Rows<T>, hipStream_t);                      \
     template int rows_to_f64<T>(Rows<double>, const Rows<T>&, int, int, int, const int*, long, bool, const int*,    \
                                 hipStream_t);                                                                       \
-    template int accumulate<T>(z64*, long, const Rows<T>&, int, int, int, const int*, long, const z64*, hipStream_t);
+    template int accumulate<T>(z64*, long, const Rows<T>&, int, int, int, const int*, long, const z64*, hipStream_t); \
+    template int fro_norms<T>(const Rows<T>&, int, int, int, double*, hipStream_t);
 FM_INST(double)
 FM_INST(float)
 

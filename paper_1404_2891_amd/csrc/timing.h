@@ -1,0 +1,74 @@
+// Optional per-phase device timing with HIP events recorded on the launching stream.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace fm {
+
+enum Phase { PH_LU_UPDATE = 0, PH_LU_PANEL = 1, PH_LU_OTHER = 2, PH_SOLVE = 3, PH_REFINE = 4, PH_RR = 5, PH_COUNT = 6 };
+
+struct Timer {
+    bool on = false;
+    struct Span { hipEvent_t a, b; };
+    std::vector<Span> open[PH_COUNT];
+    std::vector<hipEvent_t> pool;
+    double flops[PH_COUNT] = {0};
+    long launches[PH_COUNT] = {0};
+    hipEvent_t cur_a[PH_COUNT] = {nullptr};
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void start(Phase p, hipStream_t st) {
+        if (!on) return;
+        cur_a[p] = get();
+        if (cur_a[p]) (void)hipEventRecord(cur_a[p], st);
+    }
+    void stop(Phase p, hipStream_t st, double fl) {
+        if (!on || !cur_a[p]) return;
+        hipEvent_t b = get();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        open[p].push_back({cur_a[p], b});
+        cur_a[p] = nullptr;
+        flops[p] += fl;
+        launches[p] += 1;
+    }
+    // Total milliseconds of phase p (synchronises on its last event).
+    double ms(Phase p) {
+        double tot = 0.0;
+        if (open[p].empty()) return 0.0;
+        (void)hipEventSynchronize(open[p].back().b);
+        for (auto& s : open[p]) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, s.a, s.b) == hipSuccess) tot += t;
+        }
+        return tot;
+    }
+    void reset() {
+        for (int p = 0; p < PH_COUNT; ++p) {
+            for (auto& s : open[p]) {
+                pool.push_back(s.a);
+                pool.push_back(s.b);
+            }
+            open[p].clear();
+            flops[p] = 0;
+            launches[p] = 0;
+        }
+    }
+    ~Timer() {
+        reset();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace fm
