@@ -65,6 +65,7 @@ struct feast_ctx {
     double* nrm_d = nullptr;         // 2q + 1 doubles
     int* mask_d = nullptr;
     z64 *BU = nullptr, *QAB = nullptr, *XAB = nullptr, *T1 = nullptr, *Vb = nullptr, *Pb = nullptr;
+    z64 *Eb = nullptr, *ElB = nullptr, *BhV = nullptr, *rho_d = nullptr;
     z64 *G_d = nullptr, *Rinv_d = nullptr, *AhBh = nullptr, *W_d = nullptr, *Z_d = nullptr, *lam_d = nullptr;
     double* norms_d = nullptr;
     int* idx_d = nullptr;
@@ -103,6 +104,7 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->lu.Uinv = b.take<char>((size_t)q * c->nsteps * NB * NB * E);
     c->lu.info = b.take<int>(q);
     c->lu.tmp = b.take<char>((size_t)q * NB * n * E);
+    c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
     c->Yw = b.take<char>((size_t)q * np * E);
     c->Xw = b.take<char>((size_t)q * np * E);
     c->Ow = b.take<char>((size_t)q * np * E);
@@ -117,9 +119,13 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->QAB = b.take<z64>(3 * np);
     c->XAB = b.take<z64>(3 * np);
     c->T1 = b.take<z64>(np);
+    c->Eb = b.take<z64>(np);
+    c->rho_d = b.take<z64>(p);
     if (c->o.variant == FEAST_BI) {
         c->Vb = b.take<z64>(np);
         c->Pb = b.take<z64>(np);
+        c->ElB = b.take<z64>(np);
+        c->BhV = b.take<z64>(np);
     }
     c->G_d = b.take<z64>((size_t)p * p);
     c->Rinv_d = b.take<z64>((size_t)p * p);
@@ -201,12 +207,26 @@ int h2d(feast_ctx* c, void* dev, const void* host, size_t bytes) {
     return 0;
 }
 
+// Shifted residual form of the filter (low-precision modes): for any block U and diagonal L,
+//     sum_k s_k T_k^-1 B U = U rho(L) + sum_k s_k T_k^-1 (E D_k),  E = A U - B U L,
+//     D_k = diag(1 / (z_k - l_j)),
+// because B U - T_k U D_k = E D_k.  This is one FP64 refinement step of every node solve from
+// the initial iterate U D_k, whose residual is E D_k; with (L, U) the current Ritz pairs E is
+// the Ritz residual block, so the low-precision solve only acts on a block that shrinks as the
+// iteration converges.  The left filter uses conj(s_k), T_k^-H, conj(D_k) and E = A^H V - B^H V L^H.
+struct Shifted {
+    const z64* U = nullptr;      // n x ncols, column-major, ld n
+    const z64* E = nullptr;      // residual block, column-major, ld n
+    const z64* lam = nullptr;    // ncols shifts l_j (device)
+    const z64* rho = nullptr;    // rho(l_j) (side 0) or conj(rho(l_j)) (side 1) (device)
+};
+
 // Solves for nodes [k0, k0+qv): O_k = T_k^-1 rhs (side 0) or T_k^-H rhs (side 1) for a shared
 // column-major FP64 rhs, then out = sum_k w_k O_k (column-major FP64).  In the refinement
 // modes the low-precision solve is followed by FP64 refinement sweeps.
 template <typename T>
 int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rhs, long ldr, const z64* w, z64* out,
-                long ldo) {
+                long ldo, const Shifted* sh = nullptr) {
     const int n = c->n;
     hipStream_t st = c->st;
     LUStore v = node_view(c, k0, qv);
@@ -214,14 +234,20 @@ int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rh
     const int* perm = side == 0 ? v.perm : nullptr;
     const int* back = side == 0 ? nullptr : v.iperm;
     const double solve_flops = 8.0 * n * (double)n * ncols * qv;
-    FM_TRY(gather_rows<T>(Y, n, ncols, qv, rhs, ldr, 0, false, perm, v.spiv, st));
+    if (sh) {
+        FM_TRY(gather_rows<T>(Y, n, ncols, qv, sh->E, n, 0, false, perm, v.spiv, st, (side == 0 ? c->z_d : c->z_d) + k0,
+                              sh->lam, side != 0));
+    } else {
+        FM_TRY(gather_rows<T>(Y, n, ncols, qv, rhs, ldr, 0, false, perm, v.spiv, st));
+    }
     c->timer.start(PH_SOLVE, st);
     FM_TRY(trsolve<T>(v, side, ncols, Y, X, O, st));
     c->timer.stop(PH_SOLVE, st, solve_flops);
     c->ir_sweeps = 0;
     c->ir_relres = 0.0;
-    if (std::is_same<T, double>::value) {
-        FM_TRY(accumulate<T>(out, ldo, O, n, ncols, qv, back, v.spiv, w, st));
+    if (std::is_same<T, double>::value || sh || c->ir_target >= 1e-3) {
+        FM_TRY(accumulate<T>(out, ldo, O, n, ncols, qv, back, v.spiv, w, st, sh ? sh->U : nullptr, n,
+                             sh ? sh->rho : nullptr));
         return 0;
     }
     // FP64 iterative refinement of every node solve: R_k = rhs - T_k Y_k in FP64, correction
@@ -300,9 +326,9 @@ int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rh
 }
 
 int apply(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rhs, long ldr, const z64* w, z64* out,
-          long ldo) {
-    if (c->prec == Prec::F64) return apply_nodes<double>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo);
-    return apply_nodes<float>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo);
+          long ldo, const Shifted* sh = nullptr) {
+    if (c->prec == Prec::F64) return apply_nodes<double>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo, sh);
+    return apply_nodes<float>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo, sh);
 }
 
 // out (n x ncols, column-major) = op(B) U, op = N (side 0) or H (side 1)
@@ -384,7 +410,12 @@ double full_accuracy_target(const feast_ctx* c) { return 1.1102230246251565e-16 
 double default_ir_target(const feast_ctx* c) { return c->o.ir_tol > 0 ? c->o.ir_tol : full_accuracy_target(c); }
 
 // rhs = op(B) U (or U itself when B = I), then the node solves and the weighted sum.
-int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* Q, long ldq) {
+int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* Q, long ldq,
+                const Shifted* sh = nullptr) {
+    if (sh) {
+        const int rc = apply(c, 0, c->q, side, ncols, nullptr, 0, side == 0 ? c->wR : c->wL, Q, ldq, sh);
+        return rc;
+    }
     const z64* rhs = U;
     long ldr = ldu;
     if (c->B) {
@@ -616,16 +647,54 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
         if (c->o.ir_tol > 0) {
             c->ir_target = c->o.ir_tol;
         } else if (!(res_last > 0)) {
-            c->ir_target = 1e-6;
+            c->ir_target = 1e-3;   // first iteration(s): a plain low-precision filter is enough
         } else if (res_prev > 0 && res_last < 0.1 * res_prev) {
             c->ir_target = std::max(full_accuracy_target(c), 1e-3 * res_last * (res_last / res_prev));
         } else {
             c->ir_target = full_accuracy_target(c);
         }
-        FM_TRY(filter_impl(c, 0, p, U, n, Q, n));
+        // low-precision modes after the first iteration: shifted residual form with the Ritz pairs
+        // of the previous iteration (U = X there, A X and B X already formed)
+        const bool shifted = c->prec != Prec::F64 && c->o.ir_tol == 0 && it > 1;
+        Shifted shR, shL;
+        if (shifted) {
+            std::vector<z64> rho(p);
+            for (int j = 0; j < p; ++j) {
+                z64 acc(0.0, 0.0);
+                for (int k = 0; k < c->q; ++k) acc = acc + cdiv(c->sig[k], c->z[k] - hlam[j]);
+                rho[j] = acc;
+            }
+            FM_TRY(h2d(c, c->rho_d, rho.data(), p * sizeof(z64)));
+            FM_TRY(residual_block(c->Eb, U + np, BU_, n, n, p, c->lam_d, false, st));
+            shR.U = U; shR.E = c->Eb; shR.lam = c->lam_d; shR.rho = c->rho_d;
+        }
+        FM_TRY(filter_impl(c, 0, p, U, n, Q, n, shifted ? &shR : nullptr));
         FM_TRY(orthonormalize(c, Q));
         if (bi) {
-            FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n));
+            if (shifted) {
+                // E_L = A^H V - B^H V conj(L), rho conjugated
+                GemmOp g;
+                g.A = c->A; g.lda = c->lda; g.rowA = true; g.conjA = true;
+                g.B = c->Vb; g.ldb = n; g.C = c->ElB; g.ldc = n; g.M = n; g.N = p; g.K = n;
+                FM_TRY(gemm<double>(g, st));
+                if (c->B) {
+                    FM_TRY(apply_B(c, 1, p, c->Vb, n, c->BhV, n));
+                } else {
+                    FM_TRY(copy_cm(c->BhV, n, c->Vb, n, n, p, st));
+                }
+                FM_TRY(residual_block(c->ElB, c->ElB, c->BhV, n, n, p, c->lam_d, true, st));
+                std::vector<z64> rho(p);
+                for (int j = 0; j < p; ++j) {
+                    z64 acc(0.0, 0.0);
+                    for (int k = 0; k < c->q; ++k) acc = acc + cdiv(c->sig[k], c->z[k] - hlam[j]);
+                    rho[j] = conj(acc);
+                }
+                FM_TRY(h2d(c, c->T1, rho.data(), p * sizeof(z64)));   // T1 is free until orthonormalize
+                shL.U = c->Vb; shL.E = c->ElB; shL.lam = c->lam_d; shL.rho = c->T1;
+                FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n, &shL));
+            } else {
+                FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n));
+            }
             FM_TRY(orthonormalize(c, c->Pb));
         }
         // Rayleigh-Ritz: A^ = W^H A Q, B^ = W^H B Q with W = Q (R-FEAST) or P (Bi-FEAST)

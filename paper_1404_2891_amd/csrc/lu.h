@@ -20,7 +20,22 @@ struct LUStore {
     void* tmp = nullptr;         // q * nb * n elements: swapped U12 rows awaiting the block inverse
     int n = 0, q = 0, nb = 0, nsteps = 0;
     Timer* timer = nullptr;      // optional per-phase timing
+    // pivot-candidate slots of the multi-workgroup panel: q * pW * 2 values, rows and rows of
+    // nb elements, plus q * 2 copies of row j0 + j (see panel_slot_bytes)
+    void* pslots = nullptr;
+    int pW = 0;
 };
+
+// Rows owned by one workgroup of the multi-workgroup panel factorisation.
+constexpr int PANEL_ROWS = 64;
+
+inline size_t panel_slot_bytes(int n, int q, int nb, size_t real_bytes, int* pW) {
+    const int W = (n + PANEL_ROWS - 1) / PANEL_ROWS;
+    if (pW) *pW = W;
+    const size_t a = ((size_t)q * W * 2 * real_bytes + 255) / 256 * 256;
+    const size_t b = ((size_t)q * W * 2 * sizeof(int) + 255) / 256 * 256;
+    return a + b + ((size_t)q * W * 2 * nb + (size_t)q * 2 * nb) * 2 * real_bytes;
+}
 
 // T_k = z_k B - A for every node (A, B column-major complex128; B == nullptr means I), written to
 // the row-major factor storage in precision T.

@@ -141,6 +141,115 @@ __global__ __launch_bounds__(256) void panel_kernel(cplx<T>* F0, long ldf, long 
     }
 }
 
+// Multi-workgroup panel factorisation, one launch per column step j = 0 .. w.
+// Workgroup g of node k owns rows j0 + g R .. j0 + (g + 1) R - 1.  Launch j
+//   1. (j > 0) reduces the W pivot candidates of column j - 1 published by launch j - 1
+//      (largest |re| + |im|, lowest row on ties; every workgroup computes the same winner),
+//      interchanges rows j0 + j - 1 and the pivot row from their published copies, and applies
+//      the scaling and rank-1 update of column j - 1 to its rows below;
+//   2. (j < w) searches column j of its rows and publishes its candidate and that row's data.
+// Candidates are double-buffered by column parity; kernel boundaries order everything, so there
+// is no inter-workgroup waiting.
+template <typename T>
+__global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
+                                                         int j, int R, int W, int* ipiv0, long spiv, int* info,
+                                                         T* cval, int* crow, cplx<T>* cdata, cplx<T>* rowj) {
+    const int k = blockIdx.y, g = blockIdx.x;
+    cplx<T>* F = F0 + k * sF;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool act = lane < w;
+    const int rbeg = j0 + g * R, rend = min(n, rbeg + R);
+    const long cb = (long)k * W * 2;        // candidate slots of node k: [W][2]
+    __shared__ T sval[4];
+    __shared__ int srow[4];
+
+    cplx<T> prow(T(0), T(0)), invp(T(0), T(0));
+    if (j > 0) {
+        const int par = (j - 1) & 1;
+        T pv = T(-1);
+        int pr = INT_MAX, win = 0;
+        for (int t = 0; t < W; ++t) {
+            const T v = cval[cb + t * 2 + par];
+            const int r = crow[cb + t * 2 + par];
+            if (v > pv || (v == pv && r < pr)) {
+                pv = v;
+                pr = r;
+                win = t;
+            }
+        }
+        if (pv <= T(0)) pr = j0 + j - 1;
+        const cplx<T> zero(T(0), T(0));
+        const cplx<T>* rj_old = rowj + ((long)k * 2 + par) * w;
+        if (pv > T(0)) prow = act ? cdata[((cb + win * 2 + par)) * w + lane] : zero;
+        else prow = act ? rj_old[lane] : zero;
+        const int rj = j0 + j - 1;
+        if (wave == 0 && act && pr != rj) {
+            if (rj >= rbeg && rj < rend) F[(long)rj * ldf + j0 + lane] = prow;
+            if (pr >= rbeg && pr < rend) F[(long)pr * ldf + j0 + lane] = rj_old[lane];
+        }
+        const cplx<T> piv = shfl_c(prow, j - 1);
+        if (pv <= T(0)) {
+            if (g == 0 && threadIdx.x == 0 && info[k] == 0) info[k] = rj + 1;
+        } else {
+            invp = cdiv(cplx<T>(T(1), T(0)), piv);
+        }
+        if (g == 0 && threadIdx.x == 0) ipiv0[k * spiv + rj] = pr;
+        __syncthreads();
+    }
+    T best = T(-1);
+    int brow = INT_MAX;
+    for (int r0 = max(rbeg, j0 + j) + wave; r0 < rend; r0 += 16) {
+        cplx<T> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + 4 * u;
+            v[u] = (act && r < rend) ? F[(long)r * ldf + j0 + lane] : cplx<T>(T(0), T(0));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + 4 * u;
+            if (r >= rend) break;
+            if (j > 0) {
+                const cplx<T> l = shfl_c(v[u], j - 1) * invp;
+                if (lane == j - 1)
+                    v[u] = l;
+                else if (lane > j - 1)
+                    v[u] = v[u] - l * prow;
+                if (act && lane >= j - 1) F[(long)r * ldf + j0 + lane] = v[u];
+            }
+            if (j < w && lane == j) {
+                const T a = abs1(v[u]);
+                if (a > best) {
+                    best = a;
+                    brow = r;
+                }
+            }
+        }
+    }
+    if (j == w) return;
+    if (lane == j) {
+        sval[wave] = best;
+        srow[wave] = brow;
+    }
+    __syncthreads();
+    T pv = sval[0];
+    int pr = srow[0];
+#pragma unroll
+    for (int t = 1; t < 4; ++t)
+        if (sval[t] > pv || (sval[t] == pv && srow[t] < pr)) {
+            pv = sval[t];
+            pr = srow[t];
+        }
+    const int par = j & 1;
+    if (threadIdx.x == 0) {
+        cval[cb + g * 2 + par] = pv;
+        crow[cb + g * 2 + par] = pr;
+    }
+    if (wave == 0 && act && pv >= T(0)) cdata[(cb + g * 2 + par) * w + lane] = F[(long)pr * ldf + j0 + lane];
+    const int rjn = j0 + j;
+    if (wave == 1 && act && rjn >= rbeg && rjn < rend) rowj[((long)k * 2 + par) * w + lane] = F[(long)rjn * ldf + j0 + lane];
+}
+
 // Row interchanges of step (j0, w) applied to the columns outside the panel; the swapped rows
 // j0..j0+w-1 of the columns right of the panel are copied to tmp (row-major, ld n).
 template <typename T>
@@ -257,9 +366,22 @@ int factor_nodes(const LUStore& s, hipStream_t st) {
     for (int step = 0; step < s.nsteps; ++step) {
         const int j0 = step * nb, w = std::min(nb, n - j0);
         if (s.timer) s.timer->start(PH_LU_PANEL, st);
-        hipLaunchKernelGGL((panel_kernel<T>), dim3(q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, s.ipiv, s.spiv,
-                           s.info);
-        FM_LAUNCH_CHECK();
+        if (s.pslots && n - j0 > PANEL_ROWS) {
+            const int W = ceil_div(n - j0, PANEL_ROWS);
+            T* cval = (T*)s.pslots;
+            int* crow = (int*)((char*)s.pslots + align_up((size_t)q * s.pW * 2 * sizeof(T), 256));
+            cplx<T>* cdata = (cplx<T>*)((char*)crow + align_up((size_t)q * s.pW * 2 * sizeof(int), 256));
+            cplx<T>* rowj = cdata + (size_t)q * s.pW * 2 * nb;
+            for (int j = 0; j <= w; ++j) {
+                hipLaunchKernelGGL((panel_step_kernel<T>), dim3(W, q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, j,
+                                   PANEL_ROWS, W, s.ipiv, s.spiv, s.info, cval, crow, cdata, rowj);
+                FM_LAUNCH_CHECK();
+            }
+        } else {
+            hipLaunchKernelGGL((panel_kernel<T>), dim3(q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, s.ipiv, s.spiv,
+                               s.info);
+            FM_LAUNCH_CHECK();
+        }
         if (s.timer) s.timer->stop(PH_LU_PANEL, st, 0.0);
         if (s.timer) s.timer->start(PH_LU_OTHER, st);
         hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF, n,

@@ -17,9 +17,12 @@ struct Rows {
 // Y_k[i][j] = src(map_k(i), j) in precision T, where src is either one column-major FP64 block
 // shared by all nodes (src_rows == false: src[r + j * ld_src]) or a per-node row-major FP64 block
 // (src_rows == true: src[k * s_src + r * ld_src + j]); map_k is perm + k * spiv or the identity.
+// With zs != nullptr every column j of node k is also scaled by d_kj = 1/(zs[k] - lam[j])
+// (conj_scale: by conj(d_kj)).
 template <typename T>
 int gather_rows(Rows<T> Y, int n, int ncols, int q, const z64* src, long ld_src, long s_src, bool src_rows,
-                const int* map, long spiv, hipStream_t st);
+                const int* map, long spiv, hipStream_t st, const z64* zs = nullptr, const z64* lam = nullptr,
+                bool conj_scale = false);
 
 // Blocked triangular solves with the factorisations in s, batched over the q nodes.
 // side 0: O = U^-1 L^-1 Y (Y already row-permuted by P), side 1: O = L^-H U^-H Y (the caller
@@ -33,10 +36,15 @@ template <typename T>
 int rows_to_f64(Rows<double> D, const Rows<T>& O, int n, int ncols, int q, const int* map, long spiv, bool add,
                 const int* mask, hipStream_t st);
 
-// Q[i + j * ldq] = sum_k w_k O_k[map_k(i)][j]  (the weighted accumulation of the filter)
+// Q[i + j * ldq] = X[i + j * ldx] r[j] + sum_k w_k O_k[map_k(i)][j]  (the weighted accumulation of the
+// filter; the X r term only when X != nullptr)
 template <typename T>
 int accumulate(z64* Q, long ldq, const Rows<T>& O, int n, int ncols, int q, const int* map, long spiv,
-               const z64* w, hipStream_t st);
+               const z64* w, hipStream_t st, const z64* X = nullptr, long ldx = 0, const z64* r = nullptr);
+
+// E[i + j * ld] = AX[i + j * ld] - lam_j BX[i + j * ld]  (conj_lam: conj(lam_j))
+int residual_block(z64* E, const z64* AX, const z64* BX, long ld, int n, int p, const z64* lam, bool conj_lam,
+                   hipStream_t st);
 
 // R_k[i][j] = src[i + j * ld]  (right-hand side copied to every node, FP64 row-major)
 int broadcast_rows(Rows<double> R, const z64* src, long ld, int n, int ncols, int q, hipStream_t st);

@@ -12,14 +12,30 @@ namespace {
 
 template <typename T>
 __global__ void gather_kernel(cplx<T>* Y, long ldy, long sy, int n, int ncols, const z64* __restrict__ src, long ld_src,
-                              long s_src, int src_rows, const int* __restrict__ map, long spiv) {
+                              long s_src, int src_rows, const int* __restrict__ map, long spiv,
+                              const z64* __restrict__ zs, const z64* __restrict__ lam, int conj_scale) {
     const int k = blockIdx.y;
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= (long)n * ncols) return;
     const int i = t / ncols, j = t % ncols;
     const int r = map ? map[k * spiv + i] : i;
-    const z64 v = src_rows ? src[k * s_src + (long)r * ld_src + j] : src[r + (long)j * ld_src];
+    z64 v = src_rows ? src[k * s_src + (long)r * ld_src + j] : src[r + (long)j * ld_src];
+    if (zs) {
+        z64 d = cdiv(z64(1.0, 0.0), zs[k] - lam[j]);
+        if (conj_scale) d = conj(d);
+        v = v * d;
+    }
     Y[k * sy + (long)i * ldy + j] = cplx<T>(v);
+}
+
+__global__ void residual_block_kernel(z64* E, const z64* __restrict__ AX, const z64* __restrict__ BX, long ld, int n,
+                                      int p, const z64* __restrict__ lam, int conj_lam) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)n * p) return;
+    const int i = t % n, j = t / n;
+    const long o = i + (long)j * ld;
+    const z64 l = conj_lam ? conj(lam[j]) : lam[j];
+    E[o] = AX[o] - l * BX[o];
 }
 
 template <typename T>
@@ -38,11 +54,12 @@ __global__ void to_f64_kernel(z64* D, long ldd, long sd, const cplx<T>* __restri
 
 template <typename T>
 __global__ void accumulate_kernel(z64* Q, long ldq, const cplx<T>* __restrict__ O, long ldo, long so, int n, int ncols,
-                                  int q, const int* __restrict__ map, long spiv, const z64* __restrict__ w) {
+                                  int q, const int* __restrict__ map, long spiv, const z64* __restrict__ w,
+                                  const z64* __restrict__ X, long ldx, const z64* __restrict__ xr) {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= (long)n * ncols) return;
     const int i = t / ncols, j = t % ncols;
-    z64 acc(0.0, 0.0);
+    z64 acc = X ? X[i + (long)j * ldx] * xr[j] : z64(0.0, 0.0);
     for (int k = 0; k < q; ++k) {
         const int r = map ? map[k * spiv + i] : i;
         acc = acc + w[k] * z64(O[k * so + (long)r * ldo + j]);
@@ -191,9 +208,9 @@ inline dim3 grid1(long count, int q = 1) { return dim3((unsigned)((count + 255) 
 
 template <typename T>
 int gather_rows(Rows<T> Y, int n, int ncols, int q, const z64* src, long ld_src, long s_src, bool src_rows,
-                const int* map, long spiv, hipStream_t st) {
+                const int* map, long spiv, hipStream_t st, const z64* zs, const z64* lam, bool conj_scale) {
     hipLaunchKernelGGL((gather_kernel<T>), grid1((long)n * ncols, q), dim3(256), 0, st, Y.p, Y.ld, Y.s, n, ncols, src,
-                       ld_src, s_src, (int)src_rows, map, spiv);
+                       ld_src, s_src, (int)src_rows, map, spiv, zs, lam, (int)conj_scale);
     FM_LAUNCH_CHECK();
     return 0;
 }
@@ -264,9 +281,17 @@ int rows_to_f64(Rows<double> D, const Rows<T>& O, int n, int ncols, int q, const
 
 template <typename T>
 int accumulate(z64* Q, long ldq, const Rows<T>& O, int n, int ncols, int q, const int* map, long spiv, const z64* w,
-               hipStream_t st) {
+               hipStream_t st, const z64* X, long ldx, const z64* r) {
     hipLaunchKernelGGL((accumulate_kernel<T>), grid1((long)n * ncols), dim3(256), 0, st, Q, ldq, (const cplx<T>*)O.p,
-                       O.ld, O.s, n, ncols, q, map, spiv, w);
+                       O.ld, O.s, n, ncols, q, map, spiv, w, X, ldx, r);
+    FM_LAUNCH_CHECK();
+    return 0;
+}
+
+int residual_block(z64* E, const z64* AX, const z64* BX, long ld, int n, int p, const z64* lam, bool conj_lam,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(residual_block_kernel, grid1((long)n * p), dim3(256), 0, st, E, AX, BX, ld, n, p, lam,
+                       (int)conj_lam);
     FM_LAUNCH_CHECK();
     return 0;
 }
@@ -327,11 +352,13 @@ int copy_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, hipS
 }
 
 #define FM_INST(T)                                                                                                  \
-    template int gather_rows<T>(Rows<T>, int, int, int, const z64*, long, long, bool, const int*, long, hipStream_t); \
+    template int gather_rows<T>(Rows<T>, int, int, int, const z64*, long, long, bool, const int*, long, hipStream_t,  \
+                                const z64*, const z64*, bool);                                                      \
     template int trsolve<T>(const LUStore&, int, int, Rows<T>, Rows<T>, Rows<T>, hipStream_t);                      \
     template int rows_to_f64<T>(Rows<double>, const Rows<T>&, int, int, int, const int*, long, bool, const int*,    \
                                 hipStream_t);                                                                       \
-    template int accumulate<T>(z64*, long, const Rows<T>&, int, int, int, const int*, long, const z64*, hipStream_t); \
+    template int accumulate<T>(z64*, long, const Rows<T>&, int, int, int, const int*, long, const z64*, hipStream_t,  \
+                               const z64*, long, const z64*);                                                      \
     template int fro_norms<T>(const Rows<T>&, int, int, int, double*, hipStream_t);
 FM_INST(double)
 FM_INST(float)
