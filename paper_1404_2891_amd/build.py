@@ -35,7 +35,10 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, *COMMON, "-x", "c++", "-c", path, "-o", obj]
+        # plain complex multiply/divide formulas (no NaN-recovery library calls) for the small
+        # host-side reduced problems
+        cmd = [HIPCC, *COMMON, "-fcx-limited-range", "-ffp-contract=fast", "-fno-math-errno", "-march=x86-64-v3",
+               "-x", "c++", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

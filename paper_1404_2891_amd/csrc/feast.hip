@@ -105,6 +105,7 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->lu.info = b.take<int>(q);
     c->lu.tmp = b.take<char>((size_t)q * NB * n * E);
     c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
+
     c->Yw = b.take<char>((size_t)q * np * E);
     c->Xw = b.take<char>((size_t)q * np * E);
     c->Ow = b.take<char>((size_t)q * np * E);
@@ -537,9 +538,6 @@ int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, i
     } else {
         FM_TRY(assemble_nodes<float>(c->lu, c->A, lda, c->B, ldb, c->z_d, c->st));
         FM_TRY(factor_nodes<float>(c->lu, c->st));
-        FM_TRY(node_norm1(c->A, lda, c->B, ldb, n, c->z_d, q, c->colsum, c->norm1_d, c->st));
-        c->norm1.resize(q);
-        FM_TRY(d2h(c, c->norm1.data(), c->norm1_d, q * sizeof(double)));
     }
     std::vector<int> info(q);
     FM_TRY(d2h(c, info.data(), c->lu.info, q * sizeof(int)));

@@ -15,6 +15,7 @@
 // After the last step the inverses of the diagonal blocks of U are formed and the pivots are
 // combined into a permutation, so that the solves are products with precomputed blocks.
 #include <climits>
+#include <vector>
 
 #include "gemm.h"
 #include "lu.h"
@@ -154,80 +155,101 @@ template <typename T>
 __global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
                                                          int j, int R, int W, int* ipiv0, long spiv, int* info,
                                                          T* cval, int* crow, cplx<T>* cdata, cplx<T>* rowj) {
+    constexpr int U = PANEL_ROWS / 4;          // rows per wave, all held in registers
     const int k = blockIdx.y, g = blockIdx.x;
     cplx<T>* F = F0 + k * sF;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool act = lane < w;
     const int rbeg = j0 + g * R, rend = min(n, rbeg + R);
-    const long cb = (long)k * W * 2;        // candidate slots of node k: [W][2]
+    const int rfirst = max(rbeg, j0 + j);      // rows still to be updated / searched
+    const long cb = (long)k * W * 2;           // candidate slots of node k: [W][2]
+    const cplx<T> zero(T(0), T(0));
     __shared__ T sval[4];
     __shared__ int srow[4];
 
-    cplx<T> prow(T(0), T(0)), invp(T(0), T(0));
+    // 1. this wave's rows rfirst + wave + 4u (independent of the pivot: issued first)
+    cplx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = rfirst + wave + 4 * u;
+        v[u] = (act && r < rend) ? F[(long)r * ldf + j0 + lane] : zero;
+    }
     if (j > 0) {
+        // 2. winner of column j - 1: lanes scan slots lane, lane + 64, ..., butterfly argmax
+        //    (largest |re| + |im|, lowest row on ties); every wave gets the same winner
         const int par = (j - 1) & 1;
         T pv = T(-1);
         int pr = INT_MAX, win = 0;
-        for (int t = 0; t < W; ++t) {
-            const T v = cval[cb + t * 2 + par];
+        for (int t = lane; t < W; t += 64) {
+            const T cv = cval[cb + t * 2 + par];
             const int r = crow[cb + t * 2 + par];
-            if (v > pv || (v == pv && r < pr)) {
-                pv = v;
+            if (cv > pv || (cv == pv && r < pr)) {
+                pv = cv;
                 pr = r;
                 win = t;
             }
         }
-        if (pv <= T(0)) pr = j0 + j - 1;
-        const cplx<T> zero(T(0), T(0));
-        const cplx<T>* rj_old = rowj + ((long)k * 2 + par) * w;
-        if (pv > T(0)) prow = act ? cdata[((cb + win * 2 + par)) * w + lane] : zero;
-        else prow = act ? rj_old[lane] : zero;
-        const int rj = j0 + j - 1;
-        if (wave == 0 && act && pr != rj) {
-            if (rj >= rbeg && rj < rend) F[(long)rj * ldf + j0 + lane] = prow;
-            if (pr >= rbeg && pr < rend) F[(long)pr * ldf + j0 + lane] = rj_old[lane];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const T v2 = __shfl_xor(pv, o);
+            const int r2 = __shfl_xor(pr, o);
+            const int w2 = __shfl_xor(win, o);
+            if (v2 > pv || (v2 == pv && r2 < pr)) {
+                pv = v2;
+                pr = r2;
+                win = w2;
+            }
         }
-        const cplx<T> piv = shfl_c(prow, j - 1);
-        if (pv <= T(0)) {
-            if (g == 0 && threadIdx.x == 0 && info[k] == 0) info[k] = rj + 1;
-        } else {
-            invp = cdiv(cplx<T>(T(1), T(0)), piv);
+        const int rj = j0 + j - 1;
+        if (pv <= T(0)) pr = rj;  // exactly zero column: no interchange, flagged below
+        // 3. published copies of the pivot row and of row rj (both before the interchange)
+        const cplx<T> rjv = act ? rowj[((long)k * 2 + par) * w + lane] : zero;
+        const cplx<T> prow = (pv > T(0)) ? (act ? cdata[(cb + win * 2 + par) * w + lane] : zero) : rjv;
+        // 4. interchange: row rj takes the pivot row, the pivot row takes row rj
+        if (pr != rj) {
+            if (wave == 0 && act && rj >= rbeg && rj < rend) F[(long)rj * ldf + j0 + lane] = prow;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (rfirst + wave + 4 * u == pr) v[u] = rjv;
+        }
+        cplx<T> invp = zero;
+        if (pv > T(0)) {
+            invp = cdiv(cplx<T>(T(1), T(0)), shfl_c(prow, j - 1));
+        } else if (g == 0 && threadIdx.x == 0 && info[k] == 0) {
+            info[k] = rj + 1;
         }
         if (g == 0 && threadIdx.x == 0) ipiv0[k * spiv + rj] = pr;
-        __syncthreads();
-    }
-    T best = T(-1);
-    int brow = INT_MAX;
-    for (int r0 = max(rbeg, j0 + j) + wave; r0 < rend; r0 += 16) {
-        cplx<T> v[4];
+        // 5. scaling and rank-1 update of column j - 1 on the rows below; the row that received row
+        //    rj in the interchange is stored in full (its columns left of j - 1 changed too)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = r0 + 4 * u;
-            v[u] = (act && r < rend) ? F[(long)r * ldf + j0 + lane] : cplx<T>(T(0), T(0));
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = r0 + 4 * u;
-            if (r >= rend) break;
-            if (j > 0) {
+        for (int u = 0; u < U; ++u) {
+            const int r = rfirst + wave + 4 * u;
+            if (r < rend) {
                 const cplx<T> l = shfl_c(v[u], j - 1) * invp;
                 if (lane == j - 1)
                     v[u] = l;
                 else if (lane > j - 1)
                     v[u] = v[u] - l * prow;
-                if (act && lane >= j - 1) F[(long)r * ldf + j0 + lane] = v[u];
-            }
-            if (j < w && lane == j) {
-                const T a = abs1(v[u]);
-                if (a > best) {
-                    best = a;
-                    brow = r;
-                }
+                if (act && (lane >= j - 1 || (r == pr && pr != rj))) F[(long)r * ldf + j0 + lane] = v[u];
             }
         }
     }
     if (j == w) return;
-    if (lane == j) {
+    // 6. candidate of column j among this workgroup's rows
+    T best = T(-1);
+    int brow = INT_MAX;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = rfirst + wave + 4 * u;
+        if (r < rend) {
+            const T a = abs1(shfl_c(v[u], j));
+            if (a > best) {
+                best = a;
+                brow = r;
+            }
+        }
+    }
+    if (lane == 0) {
         sval[wave] = best;
         srow[wave] = brow;
     }
@@ -245,9 +267,14 @@ __global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, 
         cval[cb + g * 2 + par] = pv;
         crow[cb + g * 2 + par] = pr;
     }
-    if (wave == 0 && act && pv >= T(0)) cdata[(cb + g * 2 + par) * w + lane] = F[(long)pr * ldf + j0 + lane];
+    // 7. publish the candidate row and row j0 + j from registers
     const int rjn = j0 + j;
-    if (wave == 1 && act && rjn >= rbeg && rjn < rend) rowj[((long)k * 2 + par) * w + lane] = F[(long)rjn * ldf + j0 + lane];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = rfirst + wave + 4 * u;
+        if (pv >= T(0) && r == pr && act) cdata[(cb + g * 2 + par) * w + lane] = v[u];
+        if (r == rjn && act) rowj[((long)k * 2 + par) * w + lane] = v[u];
+    }
 }
 
 // Row interchanges of step (j0, w) applied to the columns outside the panel; the swapped rows
@@ -354,6 +381,49 @@ int assemble_nodes(const LUStore& s, const z64* A, long lda, const z64* B, long 
     return 0;
 }
 
+// Panel factorisation of step (j0, w) of every node on stream st.
+template <typename T>
+int panel(const LUStore& s, int j0, int w, hipStream_t st) {
+    const int n = s.n, q = s.q, nb = s.nb;
+    cplx<T>* F = (cplx<T>*)s.F;
+    if (s.pslots && n - j0 > PANEL_ROWS) {
+        const int W = ceil_div(n - j0, PANEL_ROWS);
+        T* cval = (T*)s.pslots;
+        int* crow = (int*)((char*)s.pslots + align_up((size_t)q * s.pW * 2 * sizeof(T), 256));
+        cplx<T>* cdata = (cplx<T>*)((char*)crow + align_up((size_t)q * s.pW * 2 * sizeof(int), 256));
+        cplx<T>* rowj = cdata + (size_t)q * s.pW * 2 * nb;
+        for (int j = 0; j <= w; ++j) {
+            hipLaunchKernelGGL((panel_step_kernel<T>), dim3(W, q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, j,
+                               PANEL_ROWS, W, s.ipiv, s.spiv, s.info, cval, crow, cdata, rowj);
+            FM_LAUNCH_CHECK();
+        }
+    } else {
+        hipLaunchKernelGGL((panel_kernel<T>), dim3(q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, s.ipiv, s.spiv,
+                           s.info);
+        FM_LAUNCH_CHECK();
+    }
+    return 0;
+}
+
+// A22 -= L21 * U12 restricted to columns [c0, c0 + nc) of the trailing matrix of step (j0, w).
+template <typename T>
+int trailing_update(const LUStore& s, int j0, int w, int c0, int nc, hipStream_t st) {
+    const int nr = s.n - j0 - w;
+    if (nr <= 0 || nc <= 0) return 0;
+    cplx<T>* F = (cplx<T>*)s.F;
+    GemmOp upd;
+    upd.A = F + (long)(j0 + w) * s.ldf + j0; upd.lda = s.ldf; upd.sA = s.sF; upd.rowA = true;
+    upd.B = F + (long)j0 * s.ldf + c0; upd.ldb = s.ldf; upd.sB = s.sF; upd.rowB = true;
+    upd.C = F + (long)(j0 + w) * s.ldf + c0; upd.ldc = s.ldf; upd.sC = s.sF; upd.rowC = true;
+    upd.M = nr; upd.N = nc; upd.K = w; upd.batch = s.q;
+    upd.alpha = z64(-1.0); upd.beta = z64(1.0);
+    upd.kind = 1;
+    if (s.timer) s.timer->start(PH_LU_UPDATE, st);
+    FM_TRY(gemm<T>(upd, st));
+    if (s.timer) s.timer->stop(PH_LU_UPDATE, st, 8.0 * nr * (double)nc * w * s.q);
+    return 0;
+}
+
 template <typename T>
 int factor_nodes(const LUStore& s, hipStream_t st) {
     const int n = s.n, q = s.q, nb = s.nb;
@@ -363,26 +433,12 @@ int factor_nodes(const LUStore& s, hipStream_t st) {
     cplx<T>* tmp = (cplx<T>*)s.tmp;
     hipLaunchKernelGGL(zero_ints, dim3(ceil_div(q, 256)), dim3(256), 0, st, s.info, q);
     FM_LAUNCH_CHECK();
+    if (s.timer) s.timer->start(PH_LU_PANEL, st);
+    FM_TRY(panel<T>(s, 0, std::min(nb, n), st));
+    if (s.timer) s.timer->stop(PH_LU_PANEL, st, 0.0);
     for (int step = 0; step < s.nsteps; ++step) {
         const int j0 = step * nb, w = std::min(nb, n - j0);
-        if (s.timer) s.timer->start(PH_LU_PANEL, st);
-        if (s.pslots && n - j0 > PANEL_ROWS) {
-            const int W = ceil_div(n - j0, PANEL_ROWS);
-            T* cval = (T*)s.pslots;
-            int* crow = (int*)((char*)s.pslots + align_up((size_t)q * s.pW * 2 * sizeof(T), 256));
-            cplx<T>* cdata = (cplx<T>*)((char*)crow + align_up((size_t)q * s.pW * 2 * sizeof(int), 256));
-            cplx<T>* rowj = cdata + (size_t)q * s.pW * 2 * nb;
-            for (int j = 0; j <= w; ++j) {
-                hipLaunchKernelGGL((panel_step_kernel<T>), dim3(W, q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, j,
-                                   PANEL_ROWS, W, s.ipiv, s.spiv, s.info, cval, crow, cdata, rowj);
-                FM_LAUNCH_CHECK();
-            }
-        } else {
-            hipLaunchKernelGGL((panel_kernel<T>), dim3(q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, s.ipiv, s.spiv,
-                               s.info);
-            FM_LAUNCH_CHECK();
-        }
-        if (s.timer) s.timer->stop(PH_LU_PANEL, st, 0.0);
+        const int jn = j0 + w, wn = std::min(nb, n - jn);
         if (s.timer) s.timer->start(PH_LU_OTHER, st);
         hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF, n,
                            nb, s.nsteps, step, Linv);
@@ -400,20 +456,13 @@ int factor_nodes(const LUStore& s, hipStream_t st) {
             u12.C = F + (long)j0 * s.ldf + j0 + w; u12.ldc = s.ldf; u12.sC = s.sF; u12.rowC = true;
             u12.M = w; u12.N = nr; u12.K = w; u12.batch = q;
             FM_TRY(gemm<T>(u12, st));
-            if (s.timer) s.timer->stop(PH_LU_OTHER, st, 0.0);
-            GemmOp upd;  // A22 -= L21 * U12
-            upd.A = F + (long)(j0 + w) * s.ldf + j0; upd.lda = s.ldf; upd.sA = s.sF; upd.rowA = true;
-            upd.B = F + (long)j0 * s.ldf + j0 + w; upd.ldb = s.ldf; upd.sB = s.sF; upd.rowB = true;
-            upd.C = F + (long)(j0 + w) * s.ldf + j0 + w; upd.ldc = s.ldf; upd.sC = s.sF; upd.rowC = true;
-            upd.M = nr; upd.N = nr; upd.K = w; upd.batch = q;
-            upd.alpha = z64(-1.0); upd.beta = z64(1.0);
-            upd.kind = 1;
-            if (s.timer) s.timer->start(PH_LU_UPDATE, st);
-            FM_TRY(gemm<T>(upd, st));
-            if (s.timer) s.timer->stop(PH_LU_UPDATE, st, 8.0 * nr * (double)nr * w * q);
-        } else if (s.timer) {
-            s.timer->stop(PH_LU_OTHER, st, 0.0);
         }
+        if (s.timer) s.timer->stop(PH_LU_OTHER, st, 0.0);
+        if (nr <= 0) break;
+        FM_TRY(trailing_update<T>(s, j0, w, jn, nr, st));
+        if (s.timer) s.timer->start(PH_LU_PANEL, st);
+        FM_TRY(panel<T>(s, jn, wn, st));
+        if (s.timer) s.timer->stop(PH_LU_PANEL, st, 0.0);
     }
     hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(s.nsteps, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF,
                        n, nb, s.nsteps, 0, (cplx<T>*)s.Uinv);
