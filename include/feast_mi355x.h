@@ -180,10 +180,13 @@ int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, do
  * count.  Phases: the LU trailing update (8 (n-j0-w)^2 w q flops per launch),
  * the panel factorisations, the other LU steps (swaps, diagonal-block
  * inverses, U12), the multi-RHS node solves (8 n^2 ncols q per launch group),
- * the FP64 refinement residuals, and the Rayleigh-Ritz products. */
+ * the FP64 refinement residuals, and the Rayleigh-Ritz products.  Two more
+ * report host wall time: the reduced eigenproblem (with its transfers) and the
+ * orthonormalisation passes. */
 enum {
     FEAST_PHASE_LU_UPDATE = 0, FEAST_PHASE_LU_PANEL = 1, FEAST_PHASE_LU_OTHER = 2,
-    FEAST_PHASE_SOLVE = 3, FEAST_PHASE_REFINE = 4, FEAST_PHASE_RR = 5, FEAST_PHASE_COUNT = 6
+    FEAST_PHASE_SOLVE = 3, FEAST_PHASE_REFINE = 4, FEAST_PHASE_RR = 5,
+    FEAST_PHASE_HOST_REDUCED = 6, FEAST_PHASE_HOST_ORTHO = 7, FEAST_PHASE_COUNT = 8
 };
 typedef struct { double ms; double flops; long launches; } feast_phase_time;
 int feast_timing_read(feast_ctx* ctx, int phase, feast_phase_time* out);

@@ -55,7 +55,8 @@ class PhaseTime(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("flops", ctypes.c_double), ("launches", ctypes.c_long)]
 
 
-PHASES = ["lu_update", "lu_panel", "lu_other", "solve", "refine", "rayleigh_ritz"]
+PHASES = ["lu_update", "lu_panel", "lu_other", "solve", "refine", "rayleigh_ritz", "host_reduced_eig",
+          "orthonormalize"]
 
 
 class Result(ctypes.Structure):

@@ -19,6 +19,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libfeast_mi355x.so"
 SOURCES = ["gemm.hip", "lu.hip", "solve.hip", "feast.hip", "contour.cpp", "hostla.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
 ARCH = "gfx950"
 # packed FP32 instructions are kept out of the generated code (see the design notes)
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -35,10 +36,10 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS, "-c", path, "-o", obj]
     else:
-        # plain complex multiply/divide formulas (no NaN-recovery library calls) for the small
-        # host-side reduced problems
-        cmd = [HIPCC, *COMMON, "-fcx-limited-range", "-ffp-contract=fast", "-fno-math-errno", "-march=x86-64-v3",
-               "-x", "c++", "-c", path, "-o", obj]
+        # host-only sources: g++, with plain complex multiply/divide formulas (no NaN-recovery
+        # library calls) for the small reduced problems
+        cmd = [CXX, "-O3", "-std=c++17", "-fPIC", "-Wall", "-fcx-limited-range", "-ffp-contract=fast",
+               "-fno-math-errno", "-march=x86-64-v3", "-I/opt/rocm/include", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

@@ -9,6 +9,7 @@
 //                 after the filter (shifted Cholesky-QR), the reduced problem solved on the host,
 //                 and the candidate / stopping rule of the Section 5 preamble.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -376,7 +377,16 @@ void from_mat(const host::Mat& M, z64* a) {
 
 // Orthonormal basis of span(Q) in place (n x p, ld n): shifted Cholesky-QR followed by two
 // plain Cholesky-QR passes, each pass Q <- Q R^-1 with R^H R = Q^H Q (+ shift on the first).
+int orthonormalize_impl(feast_ctx* c, z64* Q);
+
 int orthonormalize(feast_ctx* c, z64* Q) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = orthonormalize_impl(c, Q);
+    c->timer.add_host(PH_HOST_ORTHO, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    return rc;
+}
+
+int orthonormalize_impl(feast_ctx* c, z64* Q) {
     const int n = c->n, p = c->m0;
     std::vector<z64> hg((size_t)p * p);
     z64* src = Q;
@@ -571,17 +581,21 @@ int feast_node_solve(feast_ctx* c, int k, int side, int ncols, const void* R, in
     return apply(c, k, 1, side, ncols, (const z64*)R, ldr, c->ones, (z64*)Y, ldy);
 }
 
-int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z) {
-    if (p < 1) return -1;
-    if (!Ah) return -2;
-    if (!Bh) return -3;
-    if (!lam) return -4;
-    if (!W) return -5;
+}  // extern "C"
+
+namespace {
+// Reduced problem Ah w = l Bh w; with identity_B the basis is orthonormal and B = I, so Bh = I to
+// rounding and B^-1 A is Ah itself.
+int reduced_eig_impl(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z, bool identity_B) {
     host::Mat Am = to_mat((const z64*)Ah, p), Bm = to_mat((const z64*)Bh, p), Binv;
-    if (!host::inverse(Bm, Binv)) return FEAST_EREDUCED;
     std::vector<cd> l;
     host::Mat Wm;
-    if (!host::eig(host::matmul(Binv, Am), l, Wm)) return FEAST_EREDUCED;
+    if (identity_B) {
+        if (!host::eig(Am, l, Wm)) return FEAST_EREDUCED;
+    } else {
+        if (!host::inverse(Bm, Binv)) return FEAST_EREDUCED;
+        if (!host::eig(host::matmul(Binv, Am), l, Wm)) return FEAST_EREDUCED;
+    }
     for (int i = 0; i < p; ++i) {
         lam[2 * i] = l[i].real();
         lam[2 * i + 1] = l[i].imag();
@@ -593,6 +607,18 @@ int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, do
         from_mat(host::conj_transpose(BWinv), (z64*)Z);
     }
     return 0;
+}
+}  // namespace
+
+extern "C" {
+
+int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z) {
+    if (p < 1) return -1;
+    if (!Ah) return -2;
+    if (!Bh) return -3;
+    if (!lam) return -4;
+    if (!W) return -5;
+    return reduced_eig_impl(p, Ah, Bh, lam, W, Z, false);
 }
 
 int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
@@ -710,10 +736,14 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
         }
         FM_TRY(gram(c, bi ? c->Pb : Q, n, AQ, n, 2 * p, c->AhBh));
         c->timer.stop(PH_RR, st, 8.0 * n * (double)n * p * (c->B ? 2.0 : 1.0) + 16.0 * n * (double)p * p);
+        const auto t_red = std::chrono::steady_clock::now();
         FM_TRY(d2h(c, hbuf.data(), c->AhBh, (size_t)2 * p * p * sizeof(z64)));
-        int rc = feast_reduced_eig(p, (const double*)hbuf.data(), (const double*)(hbuf.data() + (size_t)p * p),
-                                   (double*)hlam.data(), (double*)hW.data(), bi ? (double*)hZ.data() : nullptr);
+        int rc = reduced_eig_impl(p, (const double*)hbuf.data(), (const double*)(hbuf.data() + (size_t)p * p),
+                                  (double*)hlam.data(), (double*)hW.data(), bi ? (double*)hZ.data() : nullptr,
+                                  !bi && c->B == nullptr);
         if (rc) return rc;
+        c->timer.add_host(PH_HOST_REDUCED,
+                          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_red).count());
         FM_TRY(h2d(c, c->W_d, hW.data(), hW.size() * sizeof(z64)));
         FM_TRY(h2d(c, c->lam_d, hlam.data(), hlam.size() * sizeof(z64)));
         // Ritz vectors X = Q W with A X = (A Q) W and B X = (B Q) W

@@ -64,10 +64,12 @@ Mat inverse_upper(const Mat& R) {
 }
 
 bool inverse(const Mat& A, Mat& Ainv) {
+    // Gauss-Jordan with partial pivoting; every inner loop runs down a column (contiguous)
     const int n = A.n;
     Mat M = A;
     Ainv = Mat(n);
     for (int i = 0; i < n; ++i) Ainv(i, i) = 1.0;
+    std::vector<cd> col(n);
     for (int k = 0; k < n; ++k) {
         int p = k;
         double best = std::abs(M(k, k));
@@ -76,7 +78,7 @@ bool inverse(const Mat& A, Mat& Ainv) {
                 best = std::abs(M(i, k));
                 p = i;
             }
-        if (best == 0.0) return false;
+        if (best == 0.0 || !std::isfinite(best)) return false;
         if (p != k)
             for (int j = 0; j < n; ++j) {
                 std::swap(M(k, j), M(p, j));
@@ -87,15 +89,18 @@ bool inverse(const Mat& A, Mat& Ainv) {
             M(k, j) *= inv;
             Ainv(k, j) *= inv;
         }
-        for (int i = 0; i < n; ++i) {
-            if (i == k) continue;
-            const cd f = M(i, k);
-            if (f == cd(0.0, 0.0)) continue;
+        for (int i = 0; i < n; ++i) col[i] = M(i, k);
+        col[k] = 0.0;
+        auto eliminate = [&](Mat& X) {
             for (int j = 0; j < n; ++j) {
-                M(i, j) -= f * M(k, j);
-                Ainv(i, j) -= f * Ainv(k, j);
+                const cd f = X(k, j);
+                if (f == cd(0.0, 0.0)) continue;
+                cd* c = &X(0, j);
+                for (int i = 0; i < n; ++i) c[i] -= col[i] * f;
             }
-        }
+        };
+        eliminate(M);
+        eliminate(Ainv);
     }
     return true;
 }
@@ -105,7 +110,7 @@ namespace {
 // H <- P H P and Z <- Z P, P = I - 2 v v^H / |v|^2 acting on indices k+1 .. n-1.
 void hessenberg(Mat& H, Mat& Z) {
     const int n = H.n;
-    std::vector<cd> v(n);
+    std::vector<cd> v(n), work(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;
         double alpha = 0.0;
@@ -126,18 +131,24 @@ void hessenberg(Mat& H, Mat& Z) {
             s *= f2;
             for (int i = 0; i < m; ++i) H(k + 1 + i, j) -= s * v[i];
         }
-        for (int i = 0; i < n; ++i) {
-            cd s(0.0, 0.0);
-            for (int j = 0; j < m; ++j) s += H(i, k + 1 + j) * v[j];
-            s *= f2;
-            for (int j = 0; j < m; ++j) H(i, k + 1 + j) -= s * std::conj(v[j]);
-        }
-        for (int i = 0; i < n; ++i) {
-            cd s(0.0, 0.0);
-            for (int j = 0; j < m; ++j) s += Z(i, k + 1 + j) * v[j];
-            s *= f2;
-            for (int j = 0; j < m; ++j) Z(i, k + 1 + j) -= s * std::conj(v[j]);
-        }
+        // right application M <- M - f2 (M v) v^H, as a column-ordered matrix-vector product and a
+        // rank-1 update (contiguous in column-major storage)
+        auto right = [&](Mat& M) {
+            std::vector<cd>& wv = work;
+            std::fill(wv.begin(), wv.end(), cd(0.0, 0.0));
+            for (int j = 0; j < m; ++j) {
+                const cd vj = v[j];
+                const cd* col = &M(0, k + 1 + j);
+                for (int i = 0; i < n; ++i) wv[i] += col[i] * vj;
+            }
+            for (int j = 0; j < m; ++j) {
+                const cd cj = f2 * std::conj(v[j]);
+                cd* col = &M(0, k + 1 + j);
+                for (int i = 0; i < n; ++i) col[i] -= wv[i] * cj;
+            }
+        };
+        right(H);
+        right(Z);
         for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
     }
 }

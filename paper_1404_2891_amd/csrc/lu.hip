@@ -151,11 +151,11 @@ __global__ __launch_bounds__(256) void panel_kernel(cplx<T>* F0, long ldf, long 
 //   2. (j < w) searches column j of its rows and publishes its candidate and that row's data.
 // Candidates are double-buffered by column parity; kernel boundaries order everything, so there
 // is no inter-workgroup waiting.
-template <typename T>
+template <typename T, int U>
 __global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
                                                          int j, int R, int W, int* ipiv0, long spiv, int* info,
                                                          T* cval, int* crow, cplx<T>* cdata, cplx<T>* rowj) {
-    constexpr int U = PANEL_ROWS / 4;          // rows per wave, all held in registers
+    // U rows per wave (R = 4 U rows per workgroup), all held in registers
     const int k = blockIdx.y, g = blockIdx.x;
     cplx<T>* F = F0 + k * sF;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -172,7 +172,8 @@ __global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int r = rfirst + wave + 4 * u;
-        v[u] = (act && r < rend) ? F[(long)r * ldf + j0 + lane] : zero;
+        v[u] = zero;
+        if (act && r < rend) v[u] = F[(long)r * ldf + j0 + lane];
     }
     if (j > 0) {
         // 2. winner of column j - 1: lanes scan slots lane, lane + 64, ..., butterfly argmax
@@ -203,8 +204,13 @@ __global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, 
         const int rj = j0 + j - 1;
         if (pv <= T(0)) pr = rj;  // exactly zero column: no interchange, flagged below
         // 3. published copies of the pivot row and of row rj (both before the interchange)
-        const cplx<T> rjv = act ? rowj[((long)k * 2 + par) * w + lane] : zero;
-        const cplx<T> prow = (pv > T(0)) ? (act ? cdata[(cb + win * 2 + par) * w + lane] : zero) : rjv;
+        cplx<T> rjv = zero;
+        if (act) rjv = rowj[((long)k * 2 + par) * w + lane];
+        cplx<T> prow = rjv;
+        if (pv > T(0)) {
+            prow = zero;
+            if (act) prow = cdata[(cb + win * 2 + par) * w + lane];
+        }
         // 4. interchange: row rj takes the pivot row, the pivot row takes row rj
         if (pr != rj) {
             if (wave == 0 && act && rj >= rbeg && rj < rend) F[(long)rj * ldf + j0 + lane] = prow;
@@ -393,8 +399,8 @@ int panel(const LUStore& s, int j0, int w, hipStream_t st) {
         cplx<T>* cdata = (cplx<T>*)((char*)crow + align_up((size_t)q * s.pW * 2 * sizeof(int), 256));
         cplx<T>* rowj = cdata + (size_t)q * s.pW * 2 * nb;
         for (int j = 0; j <= w; ++j) {
-            hipLaunchKernelGGL((panel_step_kernel<T>), dim3(W, q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, j,
-                               PANEL_ROWS, W, s.ipiv, s.spiv, s.info, cval, crow, cdata, rowj);
+            hipLaunchKernelGGL((panel_step_kernel<T, PANEL_ROWS / 4>), dim3(W, q), dim3(256), 0, st, F, s.ldf, s.sF,
+                               n, j0, w, j, PANEL_ROWS, W, s.ipiv, s.spiv, s.info, cval, crow, cdata, rowj);
             FM_LAUNCH_CHECK();
         }
     } else {

@@ -7,7 +7,13 @@
 
 namespace fm {
 
-enum Phase { PH_LU_UPDATE = 0, PH_LU_PANEL = 1, PH_LU_OTHER = 2, PH_SOLVE = 3, PH_REFINE = 4, PH_RR = 5, PH_COUNT = 6 };
+enum Phase {
+    PH_LU_UPDATE = 0, PH_LU_PANEL = 1, PH_LU_OTHER = 2, PH_SOLVE = 3, PH_REFINE = 4, PH_RR = 5,
+    PH_HOST_REDUCED = 6,   // host: reduced eigenproblem (wall time, includes its transfers)
+    PH_HOST_ORTHO = 7,     // host + device: orthonormalisation passes (wall time)
+    PH_COUNT = 8
+};
+inline bool is_host_phase(int p) { return p >= PH_HOST_REDUCED; }
 
 struct Timer {
     bool on = false;
@@ -44,7 +50,14 @@ struct Timer {
         launches[p] += 1;
     }
     // Total milliseconds of phase p (synchronises on its last event).
+    double host_ms[PH_COUNT] = {0};
+    void add_host(Phase p, double ms_) {
+        if (!on) return;
+        host_ms[p] += ms_;
+        launches[p] += 1;
+    }
     double ms(Phase p) {
+        if (is_host_phase(p)) return host_ms[p];
         double tot = 0.0;
         if (open[p].empty()) return 0.0;
         (void)hipEventSynchronize(open[p].back().b);
@@ -63,6 +76,7 @@ struct Timer {
             open[p].clear();
             flops[p] = 0;
             launches[p] = 0;
+            host_ms[p] = 0;
         }
     }
     ~Timer() {

@@ -197,3 +197,31 @@ def test_iterate_full_size_complex_symmetric(prec):
         r = np.linalg.norm(P.A @ x - res.lam[j] * (P.B @ x)) / (abs(res.lam[j]) * np.linalg.norm(P.B @ x))
         assert r < 1e-9
     F.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bifeast_full_size_n8192(prec):
+    """n = 8192 complex-symmetric generalized pencil, q = 32, m0 = 128, Bi-FEAST (right and left
+    solves from one factorisation per node), radius R* from the golden spectrum: the candidates are
+    the m eigenvalues inside (oracle shift-invert reference) to 1e-10 relative; sampled right and left
+    eigenvectors are checked on the host."""
+    g = golden_spectrum("c3")
+    P = pencils.c3(radius=g["radius"])
+    U0 = pencils.start_block(3, P.n, P.m0)
+    F = fm().Feast(upload(P.A), upload(P.B), P.center, P.radius, 1.0, P.q, P.m0, precision=prec, variant="Bi")
+    res = F.iterate(upload(U0))
+    ref = g["nearest"][: g["m"]]
+    assert res.converged, res.history
+    assert len(res.lam) == g["m"]
+    assert match_eigs(res.lam, ref) < 1e-10
+    assert np.all(res.resid <= 1e-10)
+    X = host(res.X)
+    Y = host(res.Y)
+    for j in (0, len(res.lam) // 2, len(res.lam) - 1):
+        lam = res.lam[j]
+        x, y = X[:, j], Y[:, j]
+        r = np.linalg.norm(P.A @ x - lam * (P.B @ x)) / (abs(lam) * np.linalg.norm(P.B @ x))
+        rl = np.linalg.norm(P.A.conj().T @ y - np.conj(lam) * (P.B.conj().T @ y)) / (
+            abs(lam) * np.linalg.norm(P.B.conj().T @ y))
+        assert r < 1e-9 and rl < 1e-8, (j, r, rl)
+    F.close()
