@@ -27,7 +27,8 @@ using cd = std::complex<double>;
 
 namespace {
 
-constexpr int NB = 64;          // block size of the factorisation and of the solves
+constexpr int NB = 64;          // block size of the factorisation
+constexpr int NBS = 256;        // block size of the multi-RHS solves
 constexpr size_t ALIGN = 256;
 
 struct Bump {
@@ -104,7 +105,11 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->lu.Linv = b.take<char>((size_t)q * c->nsteps * NB * NB * E);
     c->lu.Uinv = b.take<char>((size_t)q * c->nsteps * NB * NB * E);
     c->lu.info = b.take<int>(q);
-    c->lu.tmp = b.take<char>((size_t)q * NB * n * E);
+    c->lu.tmp = b.take<char>((size_t)q * lu_tmp_elems(n, NB, NBS) * E);
+    if (n > NB) {
+        c->lu.LinvS = b.take<char>((size_t)q * c->lu.nsbs * NBS * NBS * E);
+        c->lu.UinvS = b.take<char>((size_t)q * c->lu.nsbs * NBS * NBS * E);
+    }
     c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
 
     c->Yw = b.take<char>((size_t)q * np * E);
@@ -157,6 +162,8 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->lu.ldf = c->ldf;
     c->lu.sF = (long)n * c->ldf;
     c->lu.spiv = n;
+    c->lu.nbs = NBS;
+    c->lu.nsbs = ceil_div(n, NBS);
 }
 
 int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
@@ -190,6 +197,10 @@ LUStore node_view(const feast_ctx* c, int k0, int qv) {
     v.iperm = c->lu.iperm + (size_t)k0 * c->lu.spiv;
     v.Linv = (char*)c->lu.Linv + (size_t)k0 * c->nsteps * NB * NB * E;
     v.Uinv = (char*)c->lu.Uinv + (size_t)k0 * c->nsteps * NB * NB * E;
+    if (c->lu.LinvS) {
+        v.LinvS = (char*)c->lu.LinvS + (size_t)k0 * c->lu.nsbs * NBS * NBS * E;
+        v.UinvS = (char*)c->lu.UinvS + (size_t)k0 * c->lu.nsbs * NBS * NBS * E;
+    }
     v.q = qv;
     return v;
 }

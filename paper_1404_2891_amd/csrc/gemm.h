@@ -17,6 +17,8 @@ struct GemmOp {
     const void* B = nullptr; long ldb = 0; long sB = 0; bool rowB = false; bool conjB = false;
     void* C = nullptr;       long ldc = 0; long sC = 0; bool rowC = false;
     int M = 0, N = 0, K = 0, batch = 1;
+    // optional second batch dimension (entry (b, b2) at b * s + b2 * s2)
+    int batch2 = 1; long sA2 = 0, sB2 = 0, sC2 = 0;
     z64 alpha = z64(1.0), beta = z64(0.0);
     const z64* alpha_b = nullptr;
     // split-K: when splitk > 1, partials go to `partial` (splitk * batch * M * N elements of the

@@ -37,6 +37,7 @@ struct Params {
     const cplx<T>* B; long ldb, sB;
     cplx<T>* C; long ldc, sC;
     int M, N, K, batch, splitk, kchunk, tiles_m;
+    int batch2; long sA2, sB2, sC2;
     T ar, ai, br, bi;
     const z64* alpha_b;
     int conjA, conjB;
@@ -56,12 +57,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int tm = blockIdx.x % p.tiles_m, tn = blockIdx.x / p.tiles_m;
-    const int b = blockIdx.z % p.batch, s = blockIdx.z / p.batch;
+    const int b = blockIdx.z % p.batch, s = (blockIdx.z / p.batch) % p.splitk;
+    const int b2 = blockIdx.z / (p.batch * p.splitk);
     const int m0 = tm * BM, n0 = tn * BN;
     const int kbeg = s * p.kchunk;
     const int kend = min(p.K, kbeg + p.kchunk);
-    const cplx<T>* __restrict__ A = p.A + b * p.sA;
-    const cplx<T>* __restrict__ B = p.B + b * p.sB;
+    const cplx<T>* __restrict__ A = p.A + b * p.sA + b2 * p.sA2;
+    const cplx<T>* __restrict__ B = p.B + b * p.sB + b2 * p.sB2;
     const T sa = p.conjA ? T(-1) : T(1), sb = p.conjB ? T(-1) : T(1);
 
     cplx<T> ra[EA], rb[EB];
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
         ar = T(p.alpha_b[b].re);
         ai = T(p.alpha_b[b].im);
     }
-    cplx<T>* __restrict__ C = p.C + b * p.sC;
+    cplx<T>* __restrict__ C = p.C + b * p.sC + b2 * p.sC2;
     const bool has_beta = (p.br != T(0) || p.bi != T(0));
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -212,7 +214,7 @@ template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC
 void launch_cfg(Params<T> p, hipStream_t st) {
     constexpr int BM = WM * RB * 16, BN = WN * CB * 16;
     p.tiles_m = ceil_div(p.M, BM);
-    dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.splitk);
+    dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.splitk * p.batch2);
     hipLaunchKernelGGL((cgemm_kernel<T, WM, WN, RB, CB, RA, RBm, RC, KIND>), grid, dim3(64 * WM * WN), 0, st, p);
 }
 
@@ -231,12 +233,14 @@ void launch_layout(Params<T> p, hipStream_t st) {
 template <typename T>
 int gemm(const GemmOp& op, hipStream_t st) {
     if (op.M <= 0 || op.N <= 0 || op.batch <= 0) return 0;
-    if (op.splitk > 1 && (op.alpha_b || !op.partial)) return FEAST_EUNSUPPORTED;
+    if (op.splitk > 1 && (op.alpha_b || !op.partial || op.batch2 > 1)) return FEAST_EUNSUPPORTED;
+    if (op.batch2 < 1) return 0;
     Params<T> p;
     p.A = (const cplx<T>*)op.A; p.lda = op.lda; p.sA = op.sA;
     p.B = (const cplx<T>*)op.B; p.ldb = op.ldb; p.sB = op.sB;
     p.C = (cplx<T>*)op.C; p.ldc = op.ldc; p.sC = op.sC;
     p.M = op.M; p.N = op.N; p.K = op.K; p.batch = op.batch;
+    p.batch2 = op.batch2; p.sA2 = op.sA2; p.sB2 = op.sB2; p.sC2 = op.sC2;
     p.splitk = op.splitk > 1 ? op.splitk : 1;
     p.kchunk = p.splitk > 1 ? (int)align_up((size_t)ceil_div(op.K, p.splitk), BK) : (op.K > 0 ? op.K : 0);
     if (p.splitk > 1) p.splitk = ceil_div(op.K, p.kchunk);

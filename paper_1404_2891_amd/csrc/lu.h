@@ -24,7 +24,18 @@ struct LUStore {
     // nb elements, plus q * 2 copies of row j0 + j (see panel_slot_bytes)
     void* pslots = nullptr;
     int pW = 0;
+    // inverses of the nbs x nbs diagonal blocks used by the solves (nbs = 4 nb), composed from
+    // the nb x nb ones after the factorisation; block s of node k at (k * nsbs + s) * nbs * nbs
+    int nbs = 0, nsbs = 0;
+    void* LinvS = nullptr; void* UinvS = nullptr;
 };
+
+// Elements of the LU staging buffer per node: the panel swaps need nb * n, the composition of the
+// solve-block inverses 128 * 128 per solve block.
+inline size_t lu_tmp_elems(int n, int nb, int nbs) {
+    const size_t a = (size_t)nb * n, b = (size_t)((n + nbs - 1) / nbs) * 128 * 128;
+    return a > b ? a : b;
+}
 
 // Rows owned by one workgroup of the multi-workgroup panel factorisation.
 constexpr int PANEL_ROWS = 64;

@@ -370,6 +370,28 @@ __global__ __launch_bounds__(256) void perm_kernel(const int* ipiv0, int* perm0,
     }
 }
 
+// Solve-block inverses, initial state: the nb x nb diagonal inverses placed on the diagonal of
+// each nbs x nbs block, zeros elsewhere (the off-diagonal parts are composed afterwards).
+template <typename T>
+__global__ void init_solve_inv_kernel(cplx<T>* LS, cplx<T>* US, const cplx<T>* __restrict__ L64,
+                                      const cplx<T>* __restrict__ U64, int nb, int nbs, int nsteps, int nsbs) {
+    const int k = blockIdx.z, sblk = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbs * nbs) return;
+    const int i = t / nbs, j = t % nbs;
+    const long o = ((long)k * nsbs + sblk) * nbs * nbs + t;
+    const int bi = i / nb, bj = j / nb;
+    const int t64 = sblk * (nbs / nb) + bi;
+    cplx<T> l(T(0), T(0)), u(T(0), T(0));
+    if (bi == bj && t64 < nsteps) {
+        const long src = ((long)k * nsteps + t64) * nb * nb + (long)(i % nb) * nb + (j % nb);
+        l = L64[src];
+        u = U64[src];
+    }
+    LS[o] = l;
+    US[o] = u;
+}
+
 __global__ void zero_ints(int* p, int count) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) p[t] = 0;
@@ -430,6 +452,81 @@ int trailing_update(const LUStore& s, int j0, int w, int c0, int nc, hipStream_t
     return 0;
 }
 
+// One recursive-doubling step for the pair of h x h blocks at offset o inside solve blocks
+// b0 .. b0 + nblk - 1 of every node (second half of size h2 <= h):
+//   lower:  X21 = -X22 L21 X11,   upper:  Y12 = -Y11 U12 Y22.
+template <typename T>
+int compose_pair(const LUStore& s, int h, int h2, int o, int b0, int nblk, hipStream_t st) {
+    const int NBS = s.nbs;
+    const long sblk = (long)NBS * NBS, snode = (long)s.nsbs * sblk;
+    const long tslot = 128L * 128, tnode = (long)s.nsbs * tslot;
+    cplx<T>* F = (cplx<T>*)s.F;
+    cplx<T>* LS = (cplx<T>*)s.LinvS + b0 * sblk;
+    cplx<T>* US = (cplx<T>*)s.UinvS + b0 * sblk;
+    cplx<T>* tmp = (cplx<T>*)s.tmp + b0 * tslot;
+    const long j0 = (long)b0 * NBS + o;
+    const long fstep = (long)NBS * (s.ldf + 1);     // F stride from one solve block to the next
+    auto base = [&](GemmOp& g) {
+        g.batch = nblk; g.batch2 = s.q;
+        g.rowA = g.rowB = g.rowC = true;
+    };
+    {   // T = L21 X11  (h2 x h)
+        GemmOp g; base(g);
+        g.A = F + (j0 + h) * s.ldf + j0; g.lda = s.ldf; g.sA = fstep; g.sA2 = s.sF;
+        g.B = LS + (long)o * NBS + o; g.ldb = NBS; g.sB = sblk; g.sB2 = snode;
+        g.C = tmp; g.ldc = 128; g.sC = tslot; g.sC2 = tnode;
+        g.M = h2; g.N = h; g.K = h;
+        FM_TRY(gemm<T>(g, st));
+    }
+    {   // X21 = -X22 T
+        GemmOp g; base(g);
+        g.A = LS + (long)(o + h) * NBS + (o + h); g.lda = NBS; g.sA = sblk; g.sA2 = snode;
+        g.B = tmp; g.ldb = 128; g.sB = tslot; g.sB2 = tnode;
+        g.C = LS + (long)(o + h) * NBS + o; g.ldc = NBS; g.sC = sblk; g.sC2 = snode;
+        g.M = h2; g.N = h; g.K = h2; g.alpha = z64(-1.0);
+        FM_TRY(gemm<T>(g, st));
+    }
+    {   // T = U12 Y22  (h x h2)
+        GemmOp g; base(g);
+        g.A = F + j0 * s.ldf + j0 + h; g.lda = s.ldf; g.sA = fstep; g.sA2 = s.sF;
+        g.B = US + (long)(o + h) * NBS + (o + h); g.ldb = NBS; g.sB = sblk; g.sB2 = snode;
+        g.C = tmp; g.ldc = 128; g.sC = tslot; g.sC2 = tnode;
+        g.M = h; g.N = h2; g.K = h2;
+        FM_TRY(gemm<T>(g, st));
+    }
+    {   // Y12 = -Y11 T
+        GemmOp g; base(g);
+        g.A = US + (long)o * NBS + o; g.lda = NBS; g.sA = sblk; g.sA2 = snode;
+        g.B = tmp; g.ldb = 128; g.sB = tslot; g.sB2 = tnode;
+        g.C = US + (long)o * NBS + (o + h); g.ldc = NBS; g.sC = sblk; g.sC2 = snode;
+        g.M = h; g.N = h2; g.K = h; g.alpha = z64(-1.0);
+        FM_TRY(gemm<T>(g, st));
+    }
+    return 0;
+}
+
+// Inverses of the nbs x nbs diagonal blocks of L and U, by recursive doubling from the nb x nb ones.
+template <typename T>
+int build_solve_inverses(const LUStore& s, hipStream_t st) {
+    const int n = s.n, NBS = s.nbs, nb = s.nb;
+    hipLaunchKernelGGL((init_solve_inv_kernel<T>), dim3(ceil_div(NBS * NBS, 256), s.nsbs, s.q), dim3(256), 0, st,
+                       (cplx<T>*)s.LinvS, (cplx<T>*)s.UinvS, (const cplx<T>*)s.Linv, (const cplx<T>*)s.Uinv, nb, NBS,
+                       s.nsteps, s.nsbs);
+    FM_LAUNCH_CHECK();
+    for (int h = nb; h < NBS; h *= 2) {
+        for (int o = 0; o < NBS; o += 2 * h) {
+            // blocks whose whole pair lies inside the matrix, then the one with a partial second half
+            const int nfull = n >= o + 2 * h ? std::min(s.nsbs, (n - o - 2 * h) / NBS + 1) : 0;
+            if (nfull > 0) FM_TRY(compose_pair<T>(s, h, h, o, 0, nfull, st));
+            if (nfull < s.nsbs) {
+                const int h2 = n - (nfull * NBS + o + h);
+                if (h2 > 0 && h2 < h) FM_TRY(compose_pair<T>(s, h, h2, o, nfull, 1, st));
+            }
+        }
+    }
+    return 0;
+}
+
 template <typename T>
 int factor_nodes(const LUStore& s, hipStream_t st) {
     const int n = s.n, q = s.q, nb = s.nb;
@@ -476,6 +573,11 @@ int factor_nodes(const LUStore& s, hipStream_t st) {
     hipLaunchKernelGGL(perm_kernel, dim3(q), dim3(256), n * sizeof(int), st, (const int*)s.ipiv, s.perm, s.iperm,
                        s.spiv, n);
     FM_LAUNCH_CHECK();
+    if (s.LinvS && s.UinvS && s.nbs > nb) {
+        if (s.timer) s.timer->start(PH_LU_OTHER, st);
+        FM_TRY(build_solve_inverses<T>(s, st));
+        if (s.timer) s.timer->stop(PH_LU_OTHER, st, 0.0);
+    }
     return 0;
 }
 

@@ -217,11 +217,13 @@ int gather_rows(Rows<T> Y, int n, int ncols, int q, const z64* src, long ld_src,
 
 template <typename T>
 int trsolve(const LUStore& s, int side, int ncols, Rows<T> Y, Rows<T> X, Rows<T> O, hipStream_t st) {
-    const int n = s.n, nb = s.nb, q = s.q;
+    // block size of the sweeps: the composed solve blocks when present, else the LU blocks
+    const bool big = s.LinvS && s.UinvS && s.nbs > s.nb;
+    const int n = s.n, nb = big ? s.nbs : s.nb, q = s.q, nsteps = big ? s.nsbs : s.nsteps;
     const cplx<T>* F = (const cplx<T>*)s.F;
-    const cplx<T>* Linv = (const cplx<T>*)s.Linv;
-    const cplx<T>* Uinv = (const cplx<T>*)s.Uinv;
-    const long sinv = (long)s.nsteps * nb * nb;
+    const cplx<T>* Linv = (const cplx<T>*)(big ? s.LinvS : s.Linv);
+    const cplx<T>* Uinv = (const cplx<T>*)(big ? s.UinvS : s.Uinv);
+    const long sinv = (long)nsteps * nb * nb;
     auto base = [&](GemmOp& g, const Rows<T>& b, const Rows<T>& c) {
         g.B = b.p; g.ldb = b.ld; g.sB = b.s; g.rowB = true;
         g.C = c.p; g.ldc = c.ld; g.sC = c.s; g.rowC = true;
@@ -229,7 +231,7 @@ int trsolve(const LUStore& s, int side, int ncols, Rows<T> Y, Rows<T> X, Rows<T>
     };
     const bool ct = side != 0;
     // forward sweep: L (side 0) or U^H (side 1), lower triangular
-    for (int step = 0; step < s.nsteps; ++step) {
+    for (int step = 0; step < nsteps; ++step) {
         const int j0 = step * nb, w = std::min(nb, n - j0);
         GemmOp g1;
         g1.A = (ct ? Uinv : Linv) + (long)step * nb * nb; g1.lda = nb; g1.sA = sinv;
@@ -249,7 +251,7 @@ int trsolve(const LUStore& s, int side, int ncols, Rows<T> Y, Rows<T> X, Rows<T>
         }
     }
     // backward sweep: U (side 0) or L^H (side 1), upper triangular
-    for (int step = s.nsteps - 1; step >= 0; --step) {
+    for (int step = nsteps - 1; step >= 0; --step) {
         const int j0 = step * nb, w = std::min(nb, n - j0);
         GemmOp g3;
         g3.A = (ct ? Linv : Uinv) + (long)step * nb * nb; g3.lda = nb; g3.sA = sinv;
