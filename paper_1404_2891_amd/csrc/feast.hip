@@ -68,13 +68,29 @@ struct feast_ctx {
     int* mask_d = nullptr;
     z64 *BU = nullptr, *QAB = nullptr, *XAB = nullptr, *T1 = nullptr, *Vb = nullptr, *Pb = nullptr;
     z64 *Eb = nullptr, *ElB = nullptr, *BhV = nullptr, *rho_d = nullptr;
+    z64 *T2 = nullptr, *GL_d = nullptr, *RinvL_d = nullptr, *rhoL_d = nullptr, *Ginv_d = nullptr;
     z64 *G_d = nullptr, *Rinv_d = nullptr, *AhBh = nullptr, *W_d = nullptr, *Z_d = nullptr, *lam_d = nullptr;
     double* norms_d = nullptr;
     int* idx_d = nullptr;
     void* partial = nullptr;
-    // host staging (pinned)
+    // host staging (pinned): h for synchronous transfers, pin for the asynchronous slots of the
+    // iteration engine (each slot has one purpose, so enqueued copies never overwrite each other)
     char* h = nullptr;
     size_t hbytes = 0;
+    struct Pinned {
+        z64* G[2] = {nullptr, nullptr};      // Gram matrices, right / left (p x p)
+        z64* Rinv[2] = {nullptr, nullptr};   // R^-1 of the Cholesky factors
+        z64* AhBh = nullptr;                 // reduced pair (2 p x p)
+        z64* W = nullptr;                    // right vectors of the reduced problem
+        z64* Z = nullptr;                    // left vectors
+        z64* lam = nullptr;                  // Ritz values (p)
+        z64* rho[2] = {nullptr, nullptr};    // rho(lambda_j) for the shifted filters
+        z64* G2 = nullptr;                   // V0 Gram / biorthogonality matrix
+        z64* G2inv = nullptr;
+        double* norms = nullptr;             // 3 p residual norms
+        int* idx = nullptr;                  // output column order (p)
+    } pin;
+    char* pin_base = nullptr;
     // refinement: forward-error target of the next filter, statistics of the last one
     double ir_target = 0.0;
     int ir_sweeps = 0;
@@ -128,11 +144,16 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->T1 = b.take<z64>(np);
     c->Eb = b.take<z64>(np);
     c->rho_d = b.take<z64>(p);
+    c->Ginv_d = b.take<z64>((size_t)p * p);
     if (c->o.variant == FEAST_BI) {
         c->Vb = b.take<z64>(np);
         c->Pb = b.take<z64>(np);
         c->ElB = b.take<z64>(np);
         c->BhV = b.take<z64>(np);
+        c->T2 = b.take<z64>(np);
+        c->GL_d = b.take<z64>((size_t)p * p);
+        c->RinvL_d = b.take<z64>((size_t)p * p);
+        c->rhoL_d = b.take<z64>(p);
     }
     c->G_d = b.take<z64>((size_t)p * p);
     c->Rinv_d = b.take<z64>((size_t)p * p);
@@ -386,58 +407,15 @@ void from_mat(const host::Mat& M, z64* a) {
     for (size_t i = 0; i < M.a.size(); ++i) a[i] = z64(M.a[i].real(), M.a[i].imag());
 }
 
-// Orthonormal basis of span(Q) in place (n x p, ld n): shifted Cholesky-QR followed by two
-// plain Cholesky-QR passes, each pass Q <- Q R^-1 with R^H R = Q^H Q (+ shift on the first).
-int orthonormalize_impl(feast_ctx* c, z64* Q);
-
-int orthonormalize(feast_ctx* c, z64* Q) {
-    const auto t0 = std::chrono::steady_clock::now();
-    const int rc = orthonormalize_impl(c, Q);
-    c->timer.add_host(PH_HOST_ORTHO, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
-    return rc;
-}
-
-int orthonormalize_impl(feast_ctx* c, z64* Q) {
-    const int n = c->n, p = c->m0;
-    std::vector<z64> hg((size_t)p * p);
-    z64* src = Q;
-    z64* dst = c->T1;
-    for (int pass = 0; pass < 3; ++pass) {
-        FM_TRY(gram(c, src, n, src, n, p, c->G_d));
-        FM_TRY(d2h(c, hg.data(), c->G_d, hg.size() * sizeof(z64)));
-        host::Mat G = to_mat(hg.data(), p), R;
-        double tr = 0.0;
-        for (int i = 0; i < p; ++i) tr += G(i, i).real();
-        if (!(tr > 0.0) || !std::isfinite(tr)) return FEAST_EREDUCED;
-        double shift = pass == 0 ? 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * tr : 0.0;
-        bool ok = false;
-        for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
-            host::Mat Gs = G;
-            for (int i = 0; i < p; ++i) Gs(i, i) += shift;
-            ok = host::cholesky_upper(Gs, R);
-            shift = shift > 0 ? shift * 100.0 : 1e-15 * tr;
-        }
-        if (!ok) return FEAST_EREDUCED;
-        from_mat(host::inverse_upper(R), hg.data());
-        FM_TRY(h2d(c, c->Rinv_d, hg.data(), hg.size() * sizeof(z64)));
-        FM_TRY(right_mult(c, src, n, c->Rinv_d, dst, n));
-        std::swap(src, dst);
-    }
-    if (src != Q) FM_TRY(copy_cm(Q, n, src, n, n, p, c->st));
-    return 0;
-}
-
 double full_accuracy_target(const feast_ctx* c) { return 1.1102230246251565e-16 * std::sqrt((double)c->n); }
 
 double default_ir_target(const feast_ctx* c) { return c->o.ir_tol > 0 ? c->o.ir_tol : full_accuracy_target(c); }
 
-// rhs = op(B) U (or U itself when B = I), then the node solves and the weighted sum.
+// rhs = op(B) U (or U itself when B = I), then the node solves and the weighted sum; with sh the
+// shifted residual form (sh->E, sh->U) replaces the right-hand side.
 int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* Q, long ldq,
                 const Shifted* sh = nullptr) {
-    if (sh) {
-        const int rc = apply(c, 0, c->q, side, ncols, nullptr, 0, side == 0 ? c->wR : c->wL, Q, ldq, sh);
-        return rc;
-    }
+    if (sh) return apply(c, 0, c->q, side, ncols, nullptr, 0, side == 0 ? c->wR : c->wL, Q, ldq, sh);
     const z64* rhs = U;
     long ldr = ldu;
     if (c->B) {
@@ -448,6 +426,101 @@ int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* 
     const int rc = apply(c, 0, c->q, side, ncols, rhs, ldr, side == 0 ? c->wR : c->wL, Q, ldq);
     c->ir_sweeps_total += c->ir_sweeps;
     return rc;
+}
+
+// ---- context creation (host), factorisation (enqueue only) and the zero-pivot check ----------
+
+int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C, int m0,
+               const feast_options* o, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!ctx) return -1;
+    *ctx = nullptr;
+    int rc = check_args(n, m0, C, o);
+    if (rc) return rc < 0 ? (rc == -1 ? -2 : rc == -2 ? -7 : rc == -3 ? -9 : -8) : rc;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (B && ldb < n) return -6;
+    if (!workspace || ((uintptr_t)workspace % ALIGN)) return FEAST_EWORKSPACE;
+    feast_ctx* c = new feast_ctx;
+    fill_dims(c, n, m0, C, o);
+    c->st = stream;
+    if (o->timing) {
+        c->timer.on = true;
+        c->lu.timer = &c->timer;
+    }
+    c->A = (const z64*)A; c->lda = lda;
+    c->B = (const z64*)B; c->ldb = ldb;
+    Bump b;
+    b.base = (char*)workspace;
+    layout(c, b, B != nullptr);
+    if (b.off > workspace_bytes) {
+        delete c;
+        return FEAST_EWORKSPACE;
+    }
+    const int q = C->q, p = m0;
+    c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
+    const size_t pp = (size_t)p * p;
+    const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp;
+    const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
+    if (hipHostMalloc((void**)&c->h, c->hbytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->pin_base, pin_bytes, hipHostMallocDefault) != hipSuccess) {
+        if (c->h) (void)hipHostFree(c->h);
+        delete c;
+        return FEAST_EDEVICE;
+    }
+    z64* t = (z64*)c->pin_base;
+    c->pin.G[0] = t; t += pp;
+    c->pin.G[1] = t; t += pp;
+    c->pin.Rinv[0] = t; t += pp;
+    c->pin.Rinv[1] = t; t += pp;
+    c->pin.AhBh = t; t += 2 * pp;
+    c->pin.W = t; t += pp;
+    c->pin.Z = t; t += pp;
+    c->pin.lam = t; t += p;
+    c->pin.rho[0] = t; t += p;
+    c->pin.rho[1] = t; t += p;
+    c->pin.G2 = t; t += pp;
+    c->pin.G2inv = t; t += pp;
+    c->pin.norms = (double*)t;
+    c->pin.idx = (int*)(c->pin.norms + 3 * p);
+    *ctx = c;
+    // a1: nodes and weights
+    std::vector<double> zz(2 * q), ss(2 * q);
+    if (feast_contour_nodes(C, zz.data(), ss.data()) != 0) return -7;
+    c->z.resize(q);
+    c->sig.resize(q);
+    std::vector<z64> tab(6 * q);
+    for (int k = 0; k < q; ++k) {
+        const z64 zk(zz[2 * k], zz[2 * k + 1]), sk(ss[2 * k], ss[2 * k + 1]);
+        c->z[k] = zk;
+        c->sig[k] = sk;
+        tab[k] = zk;
+        tab[q + k] = sk;
+        tab[2 * q + k] = conj(sk);
+        tab[3 * q + k] = -zk;
+        tab[4 * q + k] = -conj(zk);
+        tab[5 * q + k] = z64(1.0);
+    }
+    z64* dst[6] = {c->z_d, c->wR, c->wL, c->negz, c->negzc, c->ones};
+    for (int k = 0; k < 6; ++k) FM_TRY(h2d(c, dst[k], tab.data() + k * q, q * sizeof(z64)));
+    return 0;
+}
+
+// a2 + a3: assemble and factor every node (enqueue only, no host synchronisation)
+int ctx_factor_enqueue(feast_ctx* c) {
+    if (c->prec == Prec::F64) {
+        FM_TRY(assemble_nodes<double>(c->lu, c->A, c->lda, c->B, c->ldb, c->z_d, c->st));
+        return factor_nodes<double>(c->lu, c->st);
+    }
+    FM_TRY(assemble_nodes<float>(c->lu, c->A, c->lda, c->B, c->ldb, c->z_d, c->st));
+    return factor_nodes<float>(c->lu, c->st);
+}
+
+int ctx_check_info(feast_ctx* c) {
+    std::vector<int> info(c->q);
+    FM_TRY(d2h(c, info.data(), c->lu.info, c->q * sizeof(int)));
+    for (int k = 0; k < c->q; ++k)
+        if (info[k]) return FEAST_ESINGULAR + k;
+    return 0;
 }
 
 bool inside(cd lam, const feast_contour& C) {
@@ -501,70 +574,9 @@ int feast_workspace_size(int n, int m0, const feast_contour* C, const feast_opti
 
 int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C,
                 int m0, const feast_options* o, void* workspace, size_t workspace_bytes, void* stream) {
-    if (!ctx) return -1;
-    *ctx = nullptr;
-    int rc = check_args(n, m0, C, o);
-    if (rc) return rc < 0 ? (rc == -1 ? -2 : rc == -2 ? -7 : rc == -3 ? -9 : -8) : rc;
-    if (!A) return -3;
-    if (lda < n) return -4;
-    if (B && ldb < n) return -6;
-    if (!workspace || ((uintptr_t)workspace % ALIGN)) return FEAST_EWORKSPACE;
-    feast_ctx* c = new feast_ctx;
-    fill_dims(c, n, m0, C, o);
-    c->st = (hipStream_t)stream;
-    if (o->timing) {
-        c->timer.on = true;
-        c->lu.timer = &c->timer;
-    }
-    c->A = (const z64*)A; c->lda = lda;
-    c->B = (const z64*)B; c->ldb = ldb;
-    Bump b;
-    b.base = (char*)workspace;
-    layout(c, b, B != nullptr);
-    if (b.off > workspace_bytes) {
-        delete c;
-        return FEAST_EWORKSPACE;
-    }
-    const int q = C->q, p = m0;
-    c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
-    if (hipHostMalloc((void**)&c->h, c->hbytes, hipHostMallocDefault) != hipSuccess) {
-        delete c;
-        return FEAST_EDEVICE;
-    }
-    *ctx = c;
-    // a1: nodes and weights
-    std::vector<double> zz(2 * q), ss(2 * q);
-    if (feast_contour_nodes(C, zz.data(), ss.data()) != 0) return -7;
-    c->z.resize(q);
-    c->sig.resize(q);
-    std::vector<z64> tab(6 * q);
-    for (int k = 0; k < q; ++k) {
-        const z64 zk(zz[2 * k], zz[2 * k + 1]), sk(ss[2 * k], ss[2 * k + 1]);
-        c->z[k] = zk;
-        c->sig[k] = sk;
-        tab[k] = zk;
-        tab[q + k] = sk;
-        tab[2 * q + k] = conj(sk);
-        tab[3 * q + k] = -zk;
-        tab[4 * q + k] = -conj(zk);
-        tab[5 * q + k] = z64(1.0);
-    }
-    // the six tables are contiguous in the layout up to 256-byte alignment; copy them one by one
-    z64* dst[6] = {c->z_d, c->wR, c->wL, c->negz, c->negzc, c->ones};
-    for (int t = 0; t < 6; ++t) FM_TRY(h2d(c, dst[t], tab.data() + t * q, q * sizeof(z64)));
-    // a2 + a3: assemble and factor every node
-    if (c->prec == Prec::F64) {
-        FM_TRY(assemble_nodes<double>(c->lu, c->A, lda, c->B, ldb, c->z_d, c->st));
-        FM_TRY(factor_nodes<double>(c->lu, c->st));
-    } else {
-        FM_TRY(assemble_nodes<float>(c->lu, c->A, lda, c->B, ldb, c->z_d, c->st));
-        FM_TRY(factor_nodes<float>(c->lu, c->st));
-    }
-    std::vector<int> info(q);
-    FM_TRY(d2h(c, info.data(), c->lu.info, q * sizeof(int)));
-    for (int k = 0; k < q; ++k)
-        if (info[k]) return FEAST_ESINGULAR + k;
-    return 0;
+    FM_TRY(ctx_create(ctx, n, A, lda, B, ldb, C, m0, o, workspace, workspace_bytes, (hipStream_t)stream));
+    FM_TRY(ctx_factor_enqueue(*ctx));
+    return ctx_check_info(*ctx);
 }
 
 int feast_filter(feast_ctx* c, int side, int ncols, const void* U, int ldu, void* Q, int ldq) {
@@ -619,6 +631,374 @@ int reduced_eig_impl(int p, const double* Ah, const double* Bh, double* lam, dou
     }
     return 0;
 }
+// ---- the FEAST iteration as phases -----------------------------------------------------------
+//
+// Algorithm R-FEAST / Bi-FEAST (Section 4) split at its host steps.  Each e_* phase only enqueues
+// device work and asynchronous copies on the context's stream (through the pinned slots); each h_*
+// phase runs on the host after the stream has been synchronised.  drive() runs any number of
+// contexts through the phases in lockstep, so many pencils share every synchronisation point and
+// their device work overlaps on their own streams.
+
+struct Run {
+    feast_ctx* c = nullptr;
+    const z64* U0 = nullptr;
+    long ldu0 = 0;
+    feast_result* res = nullptr;
+    int it = 0;
+    bool active = true;
+    bool finishing = false;
+    int rc = 0;
+    int prev_count = -1, prev_inside = -1;
+    double res_prev = NAN, res_last = NAN;
+    bool done = false;
+    int count = 0;
+    std::vector<int> order;
+    std::vector<double> rel, paper;
+    std::vector<cd> lam;
+};
+
+bool is_bi(const feast_ctx* c) { return c->o.variant == FEAST_BI; }
+
+// device pointers of the blocks of one side of the iteration
+z64* side_X(feast_ctx* c, int side) { return side == 0 ? c->QAB : c->Pb; }
+z64* side_T(feast_ctx* c, int side) { return side == 0 ? c->T1 : c->T2; }
+z64* side_G(feast_ctx* c, int side) { return side == 0 ? c->G_d : c->GL_d; }
+z64* side_Rinv(feast_ctx* c, int side) { return side == 0 ? c->Rinv_d : c->RinvL_d; }
+
+int d2h_async(feast_ctx* c, void* host, const void* dev, size_t bytes) {
+    FM_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->st));
+    return 0;
+}
+int h2d_async(feast_ctx* c, void* dev, const void* host, size_t bytes) {
+    FM_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->st));
+    return 0;
+}
+
+z64 rho_at(const feast_ctx* c, z64 l) {
+    z64 acc(0.0, 0.0);
+    for (int k = 0; k < c->q; ++k) acc = acc + cdiv(c->sig[k], c->z[k] - l);
+    return acc;
+}
+
+// start: U = U0; Bi-FEAST also V0 = B U0 (U0^H B^H B U0)^-1 (Gram matrix to the host)
+int e_begin(Run& r) {
+    feast_ctx* c = r.c;
+    const int n = c->n, p = c->m0;
+    c->ir_sweeps_total = 0;
+    FM_TRY(copy_cm(c->XAB, n, r.U0, r.ldu0, n, p, c->st));
+    if (is_bi(c)) {
+        const z64* BU0 = c->XAB;
+        if (c->B) {
+            FM_TRY(apply_B(c, 0, p, c->XAB, n, c->T1, n));
+            BU0 = c->T1;
+        }
+        FM_TRY(gram(c, BU0, n, BU0, n, p, c->G_d));
+        FM_TRY(d2h_async(c, c->pin.G2, c->G_d, (size_t)p * p * sizeof(z64)));
+    }
+    return 0;
+}
+
+int h_begin(Run& r) {
+    feast_ctx* c = r.c;
+    if (!is_bi(c)) return 0;
+    const int p = c->m0;
+    host::Mat Gi;
+    if (!host::inverse(to_mat(c->pin.G2, p), Gi)) return FEAST_EREDUCED;
+    from_mat(Gi, c->pin.G2inv);
+    FM_TRY(h2d_async(c, c->Ginv_d, c->pin.G2inv, (size_t)p * p * sizeof(z64)));
+    return right_mult(c, c->B ? c->T1 : c->XAB, c->n, c->Ginv_d, c->Vb, c->n);
+}
+
+// filter(s), then the first Gram matrix of the orthonormalisation
+int e_filter(Run& r) {
+    feast_ctx* c = r.c;
+    const int n = c->n, p = c->m0;
+    const long np = (long)n * p;
+    hipStream_t st = c->st;
+    ++r.it;
+    // refinement target: loose while far from convergence, tightening with the residual the
+    // iteration is expected to reach next, full accuracy when the decrease stalls
+    if (c->o.ir_tol > 0) {
+        c->ir_target = c->o.ir_tol;
+    } else if (!(r.res_last > 0)) {
+        c->ir_target = 1e-3;
+    } else if (r.res_prev > 0 && r.res_last < 0.1 * r.res_prev) {
+        c->ir_target = std::max(full_accuracy_target(c), 1e-3 * r.res_last * (r.res_last / r.res_prev));
+    } else {
+        c->ir_target = full_accuracy_target(c);
+    }
+    z64* U = c->XAB;
+    const bool shifted = c->prec != Prec::F64 && c->o.ir_tol == 0 && r.it > 1;
+    if (shifted) {
+        for (int j = 0; j < p; ++j) c->pin.rho[0][j] = rho_at(c, c->pin.lam[j]);
+        FM_TRY(h2d_async(c, c->rho_d, c->pin.rho[0], p * sizeof(z64)));
+        FM_TRY(residual_block(c->Eb, U + np, U + 2 * np, n, n, p, c->lam_d, false, st));
+        Shifted sh;
+        sh.U = U; sh.E = c->Eb; sh.lam = c->lam_d; sh.rho = c->rho_d;
+        FM_TRY(filter_impl(c, 0, p, U, n, c->QAB, n, &sh));
+    } else {
+        FM_TRY(filter_impl(c, 0, p, U, n, c->QAB, n));
+    }
+    FM_TRY(gram(c, c->QAB, n, c->QAB, n, p, c->G_d));
+    FM_TRY(d2h_async(c, c->pin.G[0], c->G_d, (size_t)p * p * sizeof(z64)));
+    if (is_bi(c)) {
+        if (shifted) {
+            // E_L = A^H V - B^H V conj(L), conj(rho)
+            GemmOp g;
+            g.A = c->A; g.lda = c->lda; g.rowA = true; g.conjA = true;
+            g.B = c->Vb; g.ldb = n; g.C = c->ElB; g.ldc = n; g.M = n; g.N = p; g.K = n;
+            FM_TRY(gemm<double>(g, st));
+            if (c->B) {
+                FM_TRY(apply_B(c, 1, p, c->Vb, n, c->BhV, n));
+            } else {
+                FM_TRY(copy_cm(c->BhV, n, c->Vb, n, n, p, st));
+            }
+            FM_TRY(residual_block(c->ElB, c->ElB, c->BhV, n, n, p, c->lam_d, true, st));
+            for (int j = 0; j < p; ++j) c->pin.rho[1][j] = conj(c->pin.rho[0][j]);
+            FM_TRY(h2d_async(c, c->rhoL_d, c->pin.rho[1], p * sizeof(z64)));
+            Shifted sh;
+            sh.U = c->Vb; sh.E = c->ElB; sh.lam = c->lam_d; sh.rho = c->rhoL_d;
+            FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n, &sh));
+        } else {
+            FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n));
+        }
+        FM_TRY(gram(c, c->Pb, n, c->Pb, n, p, c->GL_d));
+        FM_TRY(d2h_async(c, c->pin.G[1], c->GL_d, (size_t)p * p * sizeof(z64)));
+    }
+    return 0;
+}
+
+// host: Cholesky of the Gram matrix (shifted on pass 0), R^-1 to the device
+int h_chol(Run& r, int pass) {
+    feast_ctx* c = r.c;
+    const int n = c->n, p = c->m0;
+    for (int side = 0; side < (is_bi(c) ? 2 : 1); ++side) {
+        host::Mat G = to_mat(c->pin.G[side], p), R;
+        double tr = 0.0;
+        for (int i = 0; i < p; ++i) tr += G(i, i).real();
+        if (!(tr > 0.0) || !std::isfinite(tr)) return FEAST_EREDUCED;
+        double shift = pass == 0 ? 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * tr : 0.0;
+        bool ok = false;
+        for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
+            host::Mat Gs = G;
+            for (int i = 0; i < p; ++i) Gs(i, i) += shift;
+            ok = host::cholesky_upper(Gs, R);
+            shift = shift > 0 ? shift * 100.0 : 1e-15 * tr;
+        }
+        if (!ok) return FEAST_EREDUCED;
+        from_mat(host::inverse_upper(R), c->pin.Rinv[side]);
+        FM_TRY(h2d_async(c, side_Rinv(c, side), c->pin.Rinv[side], (size_t)p * p * sizeof(z64)));
+    }
+    return 0;
+}
+
+// device: basis <- basis R^-1 (shifted Cholesky-QR, three passes alternating between the block and
+// its temporary); after the last pass the Rayleigh-Ritz products and the reduced pair to the host
+int e_orth(Run& r, int pass) {
+    feast_ctx* c = r.c;
+    const int n = c->n, p = c->m0;
+    const long np = (long)n * p;
+    hipStream_t st = c->st;
+    for (int side = 0; side < (is_bi(c) ? 2 : 1); ++side) {
+        z64* X = side_X(c, side);
+        z64* T = side_T(c, side);
+        z64* src = (pass == 1) ? T : X;
+        z64* dst = (pass == 1) ? X : T;
+        FM_TRY(right_mult(c, src, n, side_Rinv(c, side), dst, n));
+        if (pass < 2) {
+            FM_TRY(gram(c, dst, n, dst, n, p, side_G(c, side)));
+            FM_TRY(d2h_async(c, c->pin.G[side], side_G(c, side), (size_t)p * p * sizeof(z64)));
+        } else {
+            FM_TRY(copy_cm(X, n, T, n, n, p, st));
+        }
+    }
+    if (pass < 2) return 0;
+    // Rayleigh-Ritz: A^ = W^H A Q, B^ = W^H B Q with W = Q (R-FEAST) or P (Bi-FEAST)
+    z64* Q = c->QAB;
+    c->timer.start(PH_RR, st);
+    {
+        GemmOp g;
+        g.A = c->A; g.lda = c->lda; g.B = Q; g.ldb = n; g.C = Q + np; g.ldc = n;
+        g.M = n; g.N = p; g.K = n;
+        FM_TRY(gemm<double>(g, st));
+    }
+    if (c->B) {
+        FM_TRY(apply_B(c, 0, p, Q, n, Q + 2 * np, n));
+    } else {
+        FM_TRY(copy_cm(Q + 2 * np, n, Q, n, n, p, st));
+    }
+    FM_TRY(gram(c, is_bi(c) ? c->Pb : Q, n, Q + np, n, 2 * p, c->AhBh));
+    c->timer.stop(PH_RR, st, 8.0 * n * (double)n * p * (c->B ? 2.0 : 1.0) + 16.0 * n * (double)p * p);
+    return d2h_async(c, c->pin.AhBh, c->AhBh, (size_t)2 * p * p * sizeof(z64));
+}
+
+// host: the reduced problem; W, Ritz values (and Z) to the device
+int h_eig(Run& r) {
+    feast_ctx* c = r.c;
+    const int p = c->m0;
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = reduced_eig_impl(p, (const double*)c->pin.AhBh, (const double*)(c->pin.AhBh + (size_t)p * p),
+                              (double*)c->pin.lam, (double*)c->pin.W, is_bi(c) ? (double*)c->pin.Z : nullptr,
+                              !is_bi(c) && c->B == nullptr);
+    if (rc) return rc;
+    c->timer.add_host(PH_HOST_REDUCED,
+                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    FM_TRY(h2d_async(c, c->W_d, c->pin.W, (size_t)p * p * sizeof(z64)));
+    FM_TRY(h2d_async(c, c->lam_d, c->pin.lam, p * sizeof(z64)));
+    if (is_bi(c)) FM_TRY(h2d_async(c, c->Z_d, c->pin.Z, (size_t)p * p * sizeof(z64)));
+    return 0;
+}
+
+// device: Ritz vectors X = Q W, A X, B X (one batched product), Bi-FEAST's V update and its
+// biorthogonality Gram matrix, the residual norms
+int e_ritz(Run& r) {
+    feast_ctx* c = r.c;
+    const int n = c->n, p = c->m0;
+    const long np = (long)n * p;
+    FM_TRY(right_mult(c, c->QAB, n, c->W_d, c->XAB, n, 3, np));
+    if (is_bi(c)) {
+        FM_TRY(right_mult(c, c->Pb, n, c->Z_d, c->T1, n));
+        FM_TRY(gram(c, c->XAB + 2 * np, n, c->T1, n, p, c->G_d));   // U^H B^H V
+        FM_TRY(d2h_async(c, c->pin.G2, c->G_d, (size_t)p * p * sizeof(z64)));
+    }
+    FM_TRY(ritz_residual_norms(c->XAB, c->XAB + np, c->XAB + 2 * np, n, n, p, c->lam_d, c->norms_d, c->st));
+    return d2h_async(c, c->pin.norms, c->norms_d, 3 * p * sizeof(double));
+}
+
+// host: candidates (inside, paper-form residual <= candidate_tol), history, stopping rule;
+// Bi-FEAST: the inverse that restores V^H B U = I
+int h_conv(Run& r) {
+    feast_ctx* c = r.c;
+    const int p = c->m0;
+    const double* hn = c->pin.norms;
+    r.lam.assign(p, cd(0.0, 0.0));
+    r.rel.assign(p, 0.0);
+    r.paper.assign(p, 0.0);
+    r.order.clear();
+    std::vector<int> rest;
+    int count = 0, n_inside = 0;
+    cd trace(0.0, 0.0);
+    double maxrel = 0.0;
+    for (int j = 0; j < p; ++j) {
+        r.lam[j] = cd(c->pin.lam[j].re, c->pin.lam[j].im);
+        r.paper[j] = hn[j] / hn[2 * p + j];
+        r.rel[j] = hn[j] / (std::abs(r.lam[j]) * hn[p + j]);
+        const bool fin = std::isfinite(r.lam[j].real()) && std::isfinite(r.lam[j].imag()) && std::isfinite(r.paper[j]);
+        const bool in = fin && inside(r.lam[j], c->C);
+        n_inside += in;
+        if (in && r.paper[j] <= c->o.candidate_tol) {
+            ++count;
+            trace += r.lam[j];
+            maxrel = std::max(maxrel, r.rel[j]);
+            r.order.push_back(j);
+        } else {
+            rest.push_back(j);
+        }
+    }
+    if (r.res->history) {
+        double* h = r.res->history + 4 * (r.it - 1);
+        h[0] = count;
+        h[1] = count ? maxrel : NAN;
+        h[2] = trace.real();
+        h[3] = trace.imag();
+    }
+    if (r.prev_count >= 0 && count == r.prev_count)
+        r.done = count == 0 ? (n_inside == 0 && r.prev_inside == 0) : (maxrel <= c->o.tol);
+    r.prev_count = count;
+    r.prev_inside = n_inside;
+    r.res_prev = r.res_last;
+    r.res_last = count ? maxrel : NAN;
+    r.count = count;
+    r.finishing = r.done || r.it >= c->o.max_iter;
+    if (r.finishing) {
+        r.order.insert(r.order.end(), rest.begin(), rest.end());
+        for (int j = 0; j < p; ++j) c->pin.idx[j] = r.order[j];
+    }
+    if (is_bi(c)) {
+        host::Mat Gi;
+        if (!host::inverse(to_mat(c->pin.G2, p), Gi)) return FEAST_EREDUCED;
+        from_mat(Gi, c->pin.G2inv);
+        FM_TRY(h2d_async(c, c->Ginv_d, c->pin.G2inv, (size_t)p * p * sizeof(z64)));
+    }
+    return 0;
+}
+
+// device: Bi-FEAST V <- V (U^H B^H V)^-1; when finishing, candidates-first outputs
+int e_post(Run& r) {
+    feast_ctx* c = r.c;
+    const int n = c->n, p = c->m0;
+    if (is_bi(c)) FM_TRY(right_mult(c, c->T1, n, c->Ginv_d, c->Vb, n));
+    if (!r.finishing) return 0;
+    FM_TRY(h2d_async(c, c->idx_d, c->pin.idx, p * sizeof(int)));
+    FM_TRY(gather_cols((z64*)r.res->X, r.res->ldx, c->XAB, n, n, p, c->idx_d, c->st));
+    if (is_bi(c) && r.res->Y) FM_TRY(gather_cols((z64*)r.res->Y, r.res->ldy, c->Vb, n, n, p, c->idx_d, c->st));
+    return 0;
+}
+
+// host, after the final synchronisation: the host-side results
+void h_finish(Run& r) {
+    feast_ctx* c = r.c;
+    const int p = c->m0;
+    for (int k = 0; k < p; ++k) {
+        const int j = r.order[k];
+        r.res->lambda[2 * k] = r.lam[j].real();
+        r.res->lambda[2 * k + 1] = r.lam[j].imag();
+        r.res->resid[k] = r.rel[j];
+    }
+    r.res->m = r.count;
+    r.res->ir_sweeps = (int)c->ir_sweeps_total;
+    r.res->iterations = r.it;
+    r.res->converged = r.done;
+    r.rc = r.done ? 0 : FEAST_ENOCONV;
+    r.active = false;
+}
+
+int sync_runs(std::vector<Run*>& runs) {
+    for (Run* r : runs)
+        if (r->active) FM_HIP(hipStreamSynchronize(r->c->st));
+    return 0;
+}
+
+// Runs every active Run through one phase; a failing run stops with its code.
+template <typename F>
+void each(std::vector<Run*>& runs, F f) {
+    for (Run* r : runs) {
+        if (!r->active) continue;
+        const int rc = f(*r);
+        if (rc) {
+            r->rc = rc;
+            r->active = false;
+        }
+    }
+}
+
+int drive(std::vector<Run*>& runs) {
+    each(runs, [](Run& r) { return e_begin(r); });
+    FM_TRY(sync_runs(runs));
+    each(runs, [](Run& r) { return h_begin(r); });
+    for (;;) {
+        bool any = false;
+        for (Run* r : runs) any |= r->active;
+        if (!any) break;
+        each(runs, [](Run& r) { return e_filter(r); });
+        FM_TRY(sync_runs(runs));
+        for (int pass = 0; pass < 3; ++pass) {
+            each(runs, [pass](Run& r) { return h_chol(r, pass); });
+            each(runs, [pass](Run& r) { return e_orth(r, pass); });
+            FM_TRY(sync_runs(runs));
+        }
+        each(runs, [](Run& r) { return h_eig(r); });
+        each(runs, [](Run& r) { return e_ritz(r); });
+        FM_TRY(sync_runs(runs));
+        each(runs, [](Run& r) { return h_conv(r); });
+        each(runs, [](Run& r) { return e_post(r); });
+        FM_TRY(sync_runs(runs));
+        for (Run* r : runs)
+            if (r->active && r->finishing) h_finish(*r);
+    }
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -637,205 +1017,21 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
     if (!U0) return -2;
     if (ldu0 < c->n) return -3;
     if (!res || !res->lambda || !res->resid || !res->X || res->ldx < c->n) return -4;
-    const bool bi = c->o.variant == FEAST_BI;
-    if (bi && res->Y && res->ldy < c->n) return -4;
-    const int n = c->n, p = c->m0;
-    const long np = (long)n * p;
-    hipStream_t st = c->st;
-    z64* Q = c->QAB;
-    z64* AQ = c->QAB + np;
-    z64* BQ = c->QAB + 2 * np;
-    z64* U = c->XAB;
-    z64* BU_ = c->XAB + 2 * np;
-    FM_TRY(copy_cm(U, n, (const z64*)U0, ldu0, n, p, st));
-    std::vector<z64> hbuf((size_t)2 * p * p), hW((size_t)p * p), hZ((size_t)p * p), hlam(p);
-    std::vector<double> hn(3 * p);
-    if (bi) {
-        // V0 = B U0 (U0^H B^H B U0)^-1, so that V0^H B U0 = I
-        const z64* BU0 = U;
-        if (c->B) {
-            FM_TRY(apply_B(c, 0, p, U, n, c->T1, n));
-            BU0 = c->T1;
-        }
-        FM_TRY(gram(c, BU0, n, BU0, n, p, c->G_d));
-        FM_TRY(d2h(c, hbuf.data(), c->G_d, (size_t)p * p * sizeof(z64)));
-        host::Mat Gi;
-        if (!host::inverse(to_mat(hbuf.data(), p), Gi)) return FEAST_EREDUCED;
-        from_mat(Gi, hbuf.data());
-        FM_TRY(h2d(c, c->Rinv_d, hbuf.data(), (size_t)p * p * sizeof(z64)));
-        FM_TRY(right_mult(c, BU0, n, c->Rinv_d, c->Vb, n));
-    }
-    int prev_count = -1, prev_inside = -1;
-    cd prev_trace(0.0, 0.0);
-    double res_prev = NAN, res_last = NAN;   // max relative candidate residual, two last iterations
-    c->ir_sweeps_total = 0;
-    std::vector<int> order;
-    std::vector<double> rel(p), paper(p);
-    std::vector<cd> lam(p);
-    int count = 0;
-    bool done = false;
-    int it = 1;
-    for (; it <= c->o.max_iter; ++it) {
-        // filter and orthonormalise (Q = orth(rho(M) U); Bi-FEAST also P = orth(left filter of V))
-        // refinement target: loose while the iteration is far from converged, tightening with the
-        // residual it is expected to reach next; full accuracy when the decrease stalls
-        if (c->o.ir_tol > 0) {
-            c->ir_target = c->o.ir_tol;
-        } else if (!(res_last > 0)) {
-            c->ir_target = 1e-3;   // first iteration(s): a plain low-precision filter is enough
-        } else if (res_prev > 0 && res_last < 0.1 * res_prev) {
-            c->ir_target = std::max(full_accuracy_target(c), 1e-3 * res_last * (res_last / res_prev));
-        } else {
-            c->ir_target = full_accuracy_target(c);
-        }
-        // low-precision modes after the first iteration: shifted residual form with the Ritz pairs
-        // of the previous iteration (U = X there, A X and B X already formed)
-        const bool shifted = c->prec != Prec::F64 && c->o.ir_tol == 0 && it > 1;
-        Shifted shR, shL;
-        if (shifted) {
-            std::vector<z64> rho(p);
-            for (int j = 0; j < p; ++j) {
-                z64 acc(0.0, 0.0);
-                for (int k = 0; k < c->q; ++k) acc = acc + cdiv(c->sig[k], c->z[k] - hlam[j]);
-                rho[j] = acc;
-            }
-            FM_TRY(h2d(c, c->rho_d, rho.data(), p * sizeof(z64)));
-            FM_TRY(residual_block(c->Eb, U + np, BU_, n, n, p, c->lam_d, false, st));
-            shR.U = U; shR.E = c->Eb; shR.lam = c->lam_d; shR.rho = c->rho_d;
-        }
-        FM_TRY(filter_impl(c, 0, p, U, n, Q, n, shifted ? &shR : nullptr));
-        FM_TRY(orthonormalize(c, Q));
-        if (bi) {
-            if (shifted) {
-                // E_L = A^H V - B^H V conj(L), rho conjugated
-                GemmOp g;
-                g.A = c->A; g.lda = c->lda; g.rowA = true; g.conjA = true;
-                g.B = c->Vb; g.ldb = n; g.C = c->ElB; g.ldc = n; g.M = n; g.N = p; g.K = n;
-                FM_TRY(gemm<double>(g, st));
-                if (c->B) {
-                    FM_TRY(apply_B(c, 1, p, c->Vb, n, c->BhV, n));
-                } else {
-                    FM_TRY(copy_cm(c->BhV, n, c->Vb, n, n, p, st));
-                }
-                FM_TRY(residual_block(c->ElB, c->ElB, c->BhV, n, n, p, c->lam_d, true, st));
-                std::vector<z64> rho(p);
-                for (int j = 0; j < p; ++j) {
-                    z64 acc(0.0, 0.0);
-                    for (int k = 0; k < c->q; ++k) acc = acc + cdiv(c->sig[k], c->z[k] - hlam[j]);
-                    rho[j] = conj(acc);
-                }
-                FM_TRY(h2d(c, c->T1, rho.data(), p * sizeof(z64)));   // T1 is free until orthonormalize
-                shL.U = c->Vb; shL.E = c->ElB; shL.lam = c->lam_d; shL.rho = c->T1;
-                FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n, &shL));
-            } else {
-                FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n));
-            }
-            FM_TRY(orthonormalize(c, c->Pb));
-        }
-        // Rayleigh-Ritz: A^ = W^H A Q, B^ = W^H B Q with W = Q (R-FEAST) or P (Bi-FEAST)
-        c->timer.start(PH_RR, st);
-        {
-            GemmOp g;
-            g.A = c->A; g.lda = c->lda; g.B = Q; g.ldb = n; g.C = AQ; g.ldc = n;
-            g.M = n; g.N = p; g.K = n;
-            FM_TRY(gemm<double>(g, st));
-        }
-        if (c->B) {
-            FM_TRY(apply_B(c, 0, p, Q, n, BQ, n));
-        } else {
-            FM_TRY(copy_cm(BQ, n, Q, n, n, p, st));
-        }
-        FM_TRY(gram(c, bi ? c->Pb : Q, n, AQ, n, 2 * p, c->AhBh));
-        c->timer.stop(PH_RR, st, 8.0 * n * (double)n * p * (c->B ? 2.0 : 1.0) + 16.0 * n * (double)p * p);
-        const auto t_red = std::chrono::steady_clock::now();
-        FM_TRY(d2h(c, hbuf.data(), c->AhBh, (size_t)2 * p * p * sizeof(z64)));
-        int rc = reduced_eig_impl(p, (const double*)hbuf.data(), (const double*)(hbuf.data() + (size_t)p * p),
-                                  (double*)hlam.data(), (double*)hW.data(), bi ? (double*)hZ.data() : nullptr,
-                                  !bi && c->B == nullptr);
-        if (rc) return rc;
-        c->timer.add_host(PH_HOST_REDUCED,
-                          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_red).count());
-        FM_TRY(h2d(c, c->W_d, hW.data(), hW.size() * sizeof(z64)));
-        FM_TRY(h2d(c, c->lam_d, hlam.data(), hlam.size() * sizeof(z64)));
-        // Ritz vectors X = Q W with A X = (A Q) W and B X = (B Q) W
-        FM_TRY(right_mult(c, c->QAB, n, c->W_d, c->XAB, n, 3, np));
-        if (bi) {
-            FM_TRY(h2d(c, c->Z_d, hZ.data(), hZ.size() * sizeof(z64)));
-            FM_TRY(right_mult(c, c->Pb, n, c->Z_d, c->T1, n));
-            // restore V^H B U = I: V <- V (U^H B^H V)^-1
-            FM_TRY(gram(c, BU_, n, c->T1, n, p, c->G_d));
-            FM_TRY(d2h(c, hbuf.data(), c->G_d, (size_t)p * p * sizeof(z64)));
-            host::Mat Gi;
-            if (!host::inverse(to_mat(hbuf.data(), p), Gi)) return FEAST_EREDUCED;
-            from_mat(Gi, hbuf.data());
-            FM_TRY(h2d(c, c->Rinv_d, hbuf.data(), (size_t)p * p * sizeof(z64)));
-            FM_TRY(right_mult(c, c->T1, n, c->Rinv_d, c->Vb, n));
-        }
-        FM_TRY(ritz_residual_norms(U, U + np, BU_, n, n, p, c->lam_d, c->norms_d, st));
-        FM_TRY(d2h(c, hn.data(), c->norms_d, hn.size() * sizeof(double)));
-        count = 0;
-        int n_inside = 0;
-        cd trace(0.0, 0.0);
-        double maxrel = 0.0;
-        order.clear();
-        std::vector<int> rest;
-        for (int j = 0; j < p; ++j) {
-            lam[j] = cd(hlam[j].re, hlam[j].im);
-            paper[j] = hn[j] / hn[2 * p + j];
-            rel[j] = hn[j] / (std::abs(lam[j]) * hn[p + j]);
-            const bool fin = std::isfinite(lam[j].real()) && std::isfinite(lam[j].imag()) && std::isfinite(paper[j]);
-            const bool in = fin && inside(lam[j], c->C);
-            n_inside += in;
-            if (in && paper[j] <= c->o.candidate_tol) {
-                ++count;
-                trace += lam[j];
-                maxrel = std::max(maxrel, rel[j]);
-                order.push_back(j);
-            } else {
-                rest.push_back(j);
-            }
-        }
-        if (res->history) {
-            double* h = res->history + 4 * (it - 1);
-            h[0] = count;
-            h[1] = count ? maxrel : NAN;
-            h[2] = trace.real();
-            h[3] = trace.imag();
-        }
-        if (prev_count >= 0 && count == prev_count)
-            done = count == 0 ? (n_inside == 0 && prev_inside == 0) : (maxrel <= c->o.tol);
-        prev_count = count;
-        prev_inside = n_inside;
-        prev_trace = trace;
-        res_prev = res_last;
-        res_last = count ? maxrel : NAN;
-        if (done || it == c->o.max_iter) {
-            order.insert(order.end(), rest.begin(), rest.end());
-            break;
-        }
-    }
-    if (it > c->o.max_iter) it = c->o.max_iter;
-    // outputs: candidates first
-    for (int c2 = 0; c2 < p; ++c2) {
-        const int j = order[c2];
-        res->lambda[2 * c2] = lam[j].real();
-        res->lambda[2 * c2 + 1] = lam[j].imag();
-        res->resid[c2] = rel[j];
-    }
-    FM_TRY(h2d(c, c->idx_d, order.data(), p * sizeof(int)));
-    FM_TRY(gather_cols((z64*)res->X, res->ldx, U, n, n, p, c->idx_d, st));
-    if (bi && res->Y) FM_TRY(gather_cols((z64*)res->Y, res->ldy, c->Vb, n, n, p, c->idx_d, st));
-    FM_HIP(hipStreamSynchronize(st));
-    res->m = count;
-    res->ir_sweeps = (int)c->ir_sweeps_total;
-    res->iterations = it;
-    res->converged = done;
-    return done ? 0 : FEAST_ENOCONV;
+    if (c->o.variant == FEAST_BI && res->Y && res->ldy < c->n) return -4;
+    Run r;
+    r.c = c;
+    r.U0 = (const z64*)U0;
+    r.ldu0 = ldu0;
+    r.res = res;
+    std::vector<Run*> runs{&r};
+    FM_TRY(drive(runs));
+    return r.rc;
 }
 
 void feast_destroy(feast_ctx* c) {
     if (!c) return;
     if (c->h) (void)hipHostFree(c->h);
+    if (c->pin_base) (void)hipHostFree(c->pin_base);
     delete c;
 }
 
