@@ -195,6 +195,53 @@ int feast_timing_reset(feast_ctx* ctx);
 void feast_destroy(feast_ctx* ctx);
 const char* feast_strerror(int code);
 
+/* ---- a9: batches of pencils -------------------------------------------------
+ * Many independent pencils, each with its own contour and subspace size (the
+ * outermost of the levels of parallelism listed in Section 6, independent
+ * target domains, here also of different pencils): the count of pencils is
+ * `count`, pencil b is (A[b], B[b]) of order n[b] (B == NULL or B[b] == NULL
+ * means B = I), with contour C[b] and subspace size m0[b].  All pencils share
+ * the options and the number of nodes q (FEAST_EUNSUPPORTED otherwise).
+ *
+ * feast_batch_workspace_size: device workspace bytes for the batch (has_B may
+ * be NULL: every pencil has a B).
+ *
+ * feast_batch_setup: one context per pencil, each with a stream of its own.
+ * The assembly and factorisation of every node of every pencil run as one
+ * graph launch on `stream`: each kernel of the sequence covers all (pencil,
+ * node) pairs, so the batch takes the launches of its largest pencil.  The
+ * factorisations and the results are those of feast_setup on each pencil
+ * alone (the same kernels per pair).  info (may be NULL, count ints) receives
+ * each pencil's code (0, FEAST_ESINGULAR + k, ...).  Synchronises `stream`.
+ * Returns 0 or the first nonzero member code, -i, FEAST_EWORKSPACE,
+ * FEAST_EDEVICE; on failure nothing is left allocated.
+ *
+ * feast_batch_member: the context of pencil i, for feast_filter,
+ * feast_node_solve or feast_iterate on that pencil alone (NULL when i is out
+ * of range).  The batch owns it: do not pass it to feast_destroy.
+ *
+ * feast_batch_iterate: runs feast_iterate on every pencil, all of them in
+ * lockstep through the phases of the iteration (device work of the pencils
+ * overlaps on their streams, one host synchronisation per phase for the whole
+ * batch).  U0[b] (ldu0[b]) is pencil b's start block, written on `stream`;
+ * results[b] as for feast_iterate.  member_rc (may be NULL) receives each
+ * pencil's code.  Synchronous.  Returns 0 or the first nonzero member code.
+ *
+ * feast_batch_factor_ms: device time of the factorisation graph launch (HIP
+ * events on `stream`). */
+typedef struct feast_batch feast_batch;
+int feast_batch_workspace_size(int count, const int* n, const int* m0, const feast_contour* C,
+                               const feast_options* opts, const int* has_B, size_t* bytes);
+int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* const* A,
+                      const int* lda, const void* const* B, const int* ldb, const feast_contour* C,
+                      const int* m0, const feast_options* opts, void* workspace,
+                      size_t workspace_bytes, void* stream, int* info);
+feast_ctx* feast_batch_member(feast_batch* batch, int i);
+int feast_batch_iterate(feast_batch* batch, const void* const* U0, const int* ldu0,
+                        feast_result* results, int* member_rc);
+int feast_batch_factor_ms(feast_batch* batch, double* ms);
+void feast_batch_destroy(feast_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,8 @@ EXPORTED = [
     "feast_default_options", "feast_contour_nodes", "feast_workspace_size", "feast_setup",
     "feast_filter", "feast_node_solve", "feast_iterate", "feast_reduced_eig", "feast_destroy",
     "feast_strerror", "feast_timing_read", "feast_timing_reset",
+    "feast_batch_workspace_size", "feast_batch_setup", "feast_batch_member", "feast_batch_iterate",
+    "feast_batch_factor_ms", "feast_batch_destroy",
 ]
 
 
@@ -116,6 +118,20 @@ def lib():
         L.feast_timing_reset.restype = i
         L.feast_strerror.argtypes = [i]
         L.feast_strerror.restype = ctypes.c_char_p
+        L.feast_batch_workspace_size.argtypes = [i, vp, vp, vp, ctypes.POINTER(Options), vp,
+                                                 ctypes.POINTER(ctypes.c_size_t)]
+        L.feast_batch_workspace_size.restype = i
+        L.feast_batch_setup.argtypes = [ctypes.POINTER(vp), i, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options),
+                                        vp, ctypes.c_size_t, vp, vp]
+        L.feast_batch_setup.restype = i
+        L.feast_batch_member.argtypes = [vp, i]
+        L.feast_batch_member.restype = vp
+        L.feast_batch_iterate.argtypes = [vp, vp, vp, vp, vp]
+        L.feast_batch_iterate.restype = i
+        L.feast_batch_factor_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.feast_batch_factor_ms.restype = i
+        L.feast_batch_destroy.argtypes = [vp]
+        L.feast_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -302,24 +318,133 @@ class Feast:
         return Y
 
     def iterate(self, U0) -> IterateResult:
-        torch = _torch()
-        p = self.m0
-        lam = np.zeros(p, dtype=np.complex128)
-        resid = np.zeros(p, dtype=np.float64)
-        hist = np.full((self.options.max_iter, 4), np.nan)
-        X = empty_cm(self.n, p, U0.device)
-        Y = empty_cm(self.n, p, U0.device) if self.options.variant == 1 else None
-        r = Result()
-        r.lambda_ = lam.ctypes.data
-        r.resid = resid.ctypes.data
-        r.X = X.data_ptr()
-        r.ldx = _ld(X)
-        r.Y = Y.data_ptr() if Y is not None else None
-        r.ldy = _ld(Y) if Y is not None else 0
-        r.history = hist.ctypes.data
-        code = lib().feast_iterate(self._ctx, U0.data_ptr(), _ld(U0), ctypes.byref(r))
+        buf = _ResultBuffers(self.n, self.m0, self.options, U0.device)
+        code = lib().feast_iterate(self._ctx, U0.data_ptr(), _ld(U0), ctypes.byref(buf.r))
         _check(code, "feast_iterate", ok=(FEAST_OK, FEAST_ENOCONV))
-        m = r.m
-        return IterateResult(lam[:m].copy(), resid[:m].copy(), X[:, :m], None if Y is None else Y[:, :m],
-                             r.iterations, bool(r.converged), hist[: r.iterations].copy(), code, lam.copy(),
-                             r.ir_sweeps)
+        return buf.result(code)
+
+
+class _ResultBuffers:
+    """Caller-owned result buffers of one pencil (host arrays and device blocks)."""
+
+    def __init__(self, n, p, options: Options, device):
+        self.lam = np.zeros(p, dtype=np.complex128)
+        self.resid = np.zeros(p, dtype=np.float64)
+        self.hist = np.full((options.max_iter, 4), np.nan)
+        self.X = empty_cm(n, p, device)
+        self.Y = empty_cm(n, p, device) if options.variant == 1 else None
+        r = Result()
+        r.lambda_ = self.lam.ctypes.data
+        r.resid = self.resid.ctypes.data
+        r.X = self.X.data_ptr()
+        r.ldx = _ld(self.X)
+        r.Y = self.Y.data_ptr() if self.Y is not None else None
+        r.ldy = _ld(self.Y) if self.Y is not None else 0
+        r.history = self.hist.ctypes.data
+        self.r = r
+
+    def result(self, code) -> IterateResult:
+        r, m = self.r, self.r.m
+        return IterateResult(self.lam[:m].copy(), self.resid[:m].copy(), self.X[:, :m],
+                             None if self.Y is None else self.Y[:, :m], r.iterations, bool(r.converged),
+                             self.hist[: r.iterations].copy(), code, self.lam.copy(), r.ir_sweeps)
+
+
+def _ptr_array(values, ctype):
+    arr = (ctype * len(values))(*values)
+    return arr, ctypes.cast(arr, ctypes.c_void_p)
+
+
+class FeastBatch:
+    """Many pencils factored by one graph launch and iterated in lockstep.
+
+    pencils: list of (A, B) device tensors (B may be None); contours: list of (center, radius, aspect)
+    or one tuple for all; m0: list or one int.  All pencils share q, the rule and the options."""
+
+    def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
+                 variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None):
+        torch = _torch()
+        count = len(pencils)
+        self.count = count
+        self.pencils = pencils
+        self.n = [int(A.shape[0]) for A, _ in pencils]
+        self.m0 = list(m0) if isinstance(m0, (list, tuple)) else [int(m0)] * count
+        if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
+            contours = [contours] * count
+        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, False)
+        C = (Contour * count)(*[make_contour(c, r, a, q, rule) for (c, r, a) in contours])
+        self._C = C
+        n_arr, n_p = _ptr_array(self.n, ctypes.c_int)
+        m_arr, m_p = _ptr_array(self.m0, ctypes.c_int)
+        hb_arr, hb_p = _ptr_array([int(B is not None) for _, B in pencils], ctypes.c_int)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().feast_batch_workspace_size(count, n_p, m_p, ctypes.cast(C, ctypes.c_void_p),
+                                                ctypes.byref(self.options), hb_p, ctypes.byref(nbytes)),
+               "feast_batch_workspace_size")
+        nbytes = nbytes.value
+        if workspace is not None:
+            if workspace.numel() < nbytes or workspace.data_ptr() % 256:
+                raise ValueError("workspace too small or misaligned")
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=pencils[0][0].device)
+        a_arr, a_p = _ptr_array([A.data_ptr() for A, _ in pencils], ctypes.c_void_p)
+        lda_arr, lda_p = _ptr_array([_ld(A) for A, _ in pencils], ctypes.c_int)
+        b_arr, b_p = _ptr_array([0 if B is None else B.data_ptr() for _, B in pencils], ctypes.c_void_p)
+        ldb_arr, ldb_p = _ptr_array([0 if B is None else _ld(B) for _, B in pencils], ctypes.c_int)
+        self.info = np.zeros(count, dtype=np.int32)
+        self._b = ctypes.c_void_p(None)
+        code = lib().feast_batch_setup(ctypes.byref(self._b), count, n_p, a_p, lda_p, b_p, ldb_p,
+                                       ctypes.cast(C, ctypes.c_void_p), m_p, ctypes.byref(self.options),
+                                       self.workspace.data_ptr(), nbytes, _stream(), self.info.ctypes.data)
+        if code != 0:
+            self._b = ctypes.c_void_p(None)
+            err = FeastError(code, "feast_batch_setup")
+            err.info = self.info.copy()
+            raise err
+
+    def factor_ms(self) -> float:
+        out = ctypes.c_double(0.0)
+        _check(lib().feast_batch_factor_ms(self._b, ctypes.byref(out)), "feast_batch_factor_ms")
+        return out.value
+
+    def member_filter(self, i, U, side=0):
+        """feast_filter on pencil i alone."""
+        c = lib().feast_batch_member(self._b, i)
+        if not c:
+            raise IndexError(i)
+        Q = empty_cm(self.n[i], U.shape[1], U.device)
+        _check(lib().feast_filter(c, side, U.shape[1], U.data_ptr(), _ld(U), Q.data_ptr(), _ld(Q)), "feast_filter")
+        return Q
+
+    def iterate(self, U0s):
+        """feast_iterate on every pencil in lockstep; returns (list of IterateResult, member codes)."""
+        bufs = [_ResultBuffers(self.n[i], self.m0[i], self.options, U0s[i].device) for i in range(self.count)]
+        res = (Result * self.count)(*[b.r for b in bufs])
+        u_arr, u_p = _ptr_array([U.data_ptr() for U in U0s], ctypes.c_void_p)
+        ld_arr, ld_p = _ptr_array([_ld(U) for U in U0s], ctypes.c_int)
+        rcs = np.zeros(self.count, dtype=np.int32)
+        code = lib().feast_batch_iterate(self._b, u_p, ld_p, ctypes.cast(res, ctypes.c_void_p), rcs.ctypes.data)
+        _check(code, "feast_batch_iterate", ok=(FEAST_OK, FEAST_ENOCONV))
+        out = []
+        for i, b in enumerate(bufs):
+            b.r = res[i]
+            out.append(b.result(int(rcs[i])))
+        return out, rcs
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            lib().feast_batch_destroy(self._b)
+        self._b = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -62,6 +62,9 @@ struct feast_ctx {
     z64 *z_d = nullptr, *wR = nullptr, *wL = nullptr, *negz = nullptr, *negzc = nullptr, *ones = nullptr;
     double *norm1_d = nullptr, *colsum = nullptr;
     LUStore lu;
+    LUDev* lu_dev = nullptr;          // device descriptor of this pencil's factor storage
+    GemmGroup* lu_groups = nullptr;   // grouped-product members of its factorisation
+    int lu_ngroups = 0;
     void *Yw = nullptr, *Xw = nullptr, *Ow = nullptr;
     z64 *Y64 = nullptr, *R64 = nullptr;
     double* nrm_d = nullptr;         // 2q + 1 doubles
@@ -127,6 +130,8 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
         c->lu.UinvS = b.take<char>((size_t)q * c->lu.nsbs * NBS * NBS * E);
     }
     c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
+    c->lu_dev = b.take<LUDev>(1);
+    c->lu_groups = b.take<GemmGroup>(c->lu_ngroups);
 
     c->Yw = b.take<char>((size_t)q * np * E);
     c->Xw = b.take<char>((size_t)q * np * E);
@@ -185,6 +190,13 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->lu.spiv = n;
     c->lu.nbs = NBS;
     c->lu.nsbs = ceil_div(n, NBS);
+    // grouped-product members of the factorisation (a count that depends on the dimensions only)
+    LUSet one;
+    one.s = &c->lu;
+    one.count = 1;
+    std::vector<GemmGroup> plan;
+    lu_plan<double>(one, plan);
+    c->lu_ngroups = (int)plan.size();
 }
 
 int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
@@ -430,6 +442,17 @@ int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* 
 
 // ---- context creation (host), factorisation (enqueue only) and the zero-pivot check ----------
 
+// The factorisation of this pencil alone, as a set of one.
+LUSet ctx_set(feast_ctx* c) {
+    LUSet one;
+    one.s = &c->lu;
+    one.count = 1;
+    one.dev = c->lu_dev;
+    one.groups = c->lu_groups;
+    one.timer = c->lu.timer;
+    return one;
+}
+
 int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C, int m0,
                const feast_options* o, void* workspace, size_t workspace_bytes, hipStream_t stream) {
     if (!ctx) return -1;
@@ -458,6 +481,7 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     }
     const int q = C->q, p = m0;
     c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
+    c->hbytes = std::max<size_t>(c->hbytes, (size_t)c->lu_ngroups * sizeof(GemmGroup) + sizeof(LUDev));
     const size_t pp = (size_t)p * p;
     const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp;
     const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
@@ -502,17 +526,27 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     }
     z64* dst[6] = {c->z_d, c->wR, c->wL, c->negz, c->negzc, c->ones};
     for (int k = 0; k < 6; ++k) FM_TRY(h2d(c, dst[k], tab.data() + k * q, q * sizeof(z64)));
+    // descriptor and grouped-product table of the factorisation of this pencil alone
+    c->lu.A = c->A; c->lu.lda = c->lda;
+    c->lu.B = c->B; c->lu.ldb = c->ldb;
+    c->lu.z = c->z_d;
+    const LUDev d = lu_dev(c->lu, elem_bytes(c->prec) / 2);
+    FM_TRY(h2d(c, c->lu_dev, &d, sizeof(LUDev)));
+    std::vector<GemmGroup> plan;
+    LUSet one = ctx_set(c);
+    if (c->prec == Prec::F64)
+        lu_plan<double>(one, plan);
+    else
+        lu_plan<float>(one, plan);
+    if ((int)plan.size() != c->lu_ngroups) return FEAST_EUNSUPPORTED;
+    if (!plan.empty()) FM_TRY(h2d(c, c->lu_groups, plan.data(), plan.size() * sizeof(GemmGroup)));
     return 0;
 }
 
 // a2 + a3: assemble and factor every node (enqueue only, no host synchronisation)
 int ctx_factor_enqueue(feast_ctx* c) {
-    if (c->prec == Prec::F64) {
-        FM_TRY(assemble_nodes<double>(c->lu, c->A, c->lda, c->B, c->ldb, c->z_d, c->st));
-        return factor_nodes<double>(c->lu, c->st);
-    }
-    FM_TRY(assemble_nodes<float>(c->lu, c->A, c->lda, c->B, c->ldb, c->z_d, c->st));
-    return factor_nodes<float>(c->lu, c->st);
+    const LUSet one = ctx_set(c);
+    return c->prec == Prec::F64 ? lu_factor_set<double>(one, c->st) : lu_factor_set<float>(one, c->st);
 }
 
 int ctx_check_info(feast_ctx* c) {
@@ -1050,5 +1084,248 @@ const char* feast_strerror(int code) {
     }
     return "unknown error";
 }
+
+}  // extern "C"
+
+// ---- batches of pencils ------------------------------------------------------------------------
+//
+// A batch holds one context per pencil, each on a stream of its own (default priority).  The
+// assembly and factorisation of every pencil run as one set: each launch of the sequence covers all
+// (pencil, node) pairs, so a batch of pencils of different orders takes as many launches as its
+// largest member; the sequence is captured once into a graph and launched with one call.  The
+// iteration drives all members through its phases in lockstep: their device work overlaps on their
+// streams and they share every host synchronisation.
+
+struct feast_batch {
+    int count = 0;
+    Prec prec = Prec::F64;
+    std::vector<feast_ctx*> ctx;
+    std::vector<hipStream_t> streams;
+    std::vector<LUStore> stores;
+    hipStream_t user = nullptr;
+    LUDev* dev = nullptr;
+    GemmGroup* groups = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float factor_ms = 0.0f;
+};
+
+namespace {
+
+// Workspace of a batch: the set's descriptors and grouped-product table, then one slice per member.
+struct BatchLayout {
+    size_t dev_off = 0, groups_off = 0, ngroups = 0;
+    std::vector<size_t> off, bytes;
+    size_t total = 0;
+};
+
+int batch_layout(int count, const int* n, const int* m0, const feast_contour* C, const feast_options* o,
+                 const int* has_B, BatchLayout& L) {
+    if (count < 1) return -2;
+    if (!n || !m0 || !C) return -3;
+    L.off.assign(count, 0);
+    L.bytes.assign(count, 0);
+    for (int b = 0; b < count; ++b) {
+        if (C[b].q != C[0].q) return FEAST_EUNSUPPORTED;
+        FM_TRY(feast_workspace_size(n[b], m0[b], &C[b], o, has_B ? has_B[b] : 1, &L.bytes[b]));
+        feast_ctx c;
+        fill_dims(&c, n[b], m0[b], &C[b], o);
+        L.ngroups += c.lu_ngroups;
+    }
+    size_t off = 0;
+    L.dev_off = off;
+    off = align_up(off + (size_t)count * sizeof(LUDev), ALIGN);
+    L.groups_off = off;
+    off = align_up(off + L.ngroups * sizeof(GemmGroup), ALIGN);
+    for (int b = 0; b < count; ++b) {
+        L.off[b] = off;
+        off = align_up(off + L.bytes[b], ALIGN);
+    }
+    L.total = off;
+    return 0;
+}
+
+void batch_free(feast_batch* bt) {
+    if (!bt) return;
+    for (feast_ctx* c : bt->ctx) feast_destroy(c);
+    for (hipStream_t s : bt->streams)
+        if (s) (void)hipStreamDestroy(s);
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    delete bt;
+}
+
+// Captures the set's factorisation sequence on a private stream into a graph.
+int batch_capture(feast_batch* bt, const LUSet& S) {
+    hipStream_t cap = nullptr;
+    FM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    int rc = 0;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return FEAST_EDEVICE;
+    }
+    rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S, cap) : lu_factor_set<float>(S, cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : FEAST_EDEVICE;
+    }
+    bt->graph = g;
+    FM_HIP(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int feast_batch_workspace_size(int count, const int* n, const int* m0, const feast_contour* C, const feast_options* o,
+                               const int* has_B, size_t* bytes) {
+    if (!bytes) return -7;
+    BatchLayout L;
+    FM_TRY(batch_layout(count, n, m0, C, o, has_B, L));
+    *bytes = L.total;
+    return 0;
+}
+
+int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* const* A, const int* lda,
+                      const void* const* B, const int* ldb, const feast_contour* C, const int* m0,
+                      const feast_options* o, void* workspace, size_t workspace_bytes, void* stream, int* info) {
+    if (!batch) return -1;
+    *batch = nullptr;
+    if (!A || !lda) return -4;
+    if (!workspace || ((uintptr_t)workspace % ALIGN)) return FEAST_EWORKSPACE;
+    std::vector<int> hasB(count > 0 ? count : 0);
+    for (int b = 0; b < count; ++b) hasB[b] = B && B[b] ? 1 : 0;
+    BatchLayout L;
+    FM_TRY(batch_layout(count, n, m0, C, o, hasB.data(), L));
+    if (L.total > workspace_bytes) return FEAST_EWORKSPACE;
+    feast_batch* bt = new feast_batch;
+    bt->count = count;
+    bt->user = (hipStream_t)stream;
+    bt->prec = o->precision == FEAST_FP64 ? Prec::F64 : Prec::F32;
+    char* base = (char*)workspace;
+    bt->dev = (LUDev*)(base + L.dev_off);
+    bt->groups = (GemmGroup*)(base + L.groups_off);
+    int rc = 0;
+    // members: contexts with streams of their own (ctx_create only uploads the node tables and
+    // descriptors of the member, synchronously on its stream)
+    for (int b = 0; b < count && !rc; ++b) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            rc = FEAST_EDEVICE;
+            break;
+        }
+        bt->streams.push_back(s);
+        feast_ctx* c = nullptr;
+        rc = ctx_create(&c, n[b], A[b], lda[b], B ? B[b] : nullptr, ldb ? ldb[b] : 0, &C[b], m0[b], o,
+                        base + L.off[b], L.bytes[b], s);
+        if (c) bt->ctx.push_back(c);
+        if (info) info[b] = rc;
+    }
+    // the set: descriptors and grouped-product table of all members, uploaded once
+    if (!rc) {
+        bt->stores.resize(count);
+        std::vector<LUDev> devs(count);
+        for (int b = 0; b < count; ++b) {
+            bt->stores[b] = bt->ctx[b]->lu;
+            bt->stores[b].timer = nullptr;
+            devs[b] = lu_dev(bt->stores[b], bt->prec == Prec::F64 ? 8 : 4);
+        }
+        LUSet S;
+        S.s = bt->stores.data();
+        S.count = count;
+        S.dev = bt->dev;
+        S.groups = bt->groups;
+        std::vector<GemmGroup> plan;
+        if (bt->prec == Prec::F64)
+            lu_plan<double>(S, plan);
+        else
+            lu_plan<float>(S, plan);
+        if (plan.size() != L.ngroups) rc = FEAST_EUNSUPPORTED;
+        if (!rc && (hipMemcpy(bt->dev, devs.data(), count * sizeof(LUDev), hipMemcpyHostToDevice) != hipSuccess ||
+                    (!plan.empty() && hipMemcpy(bt->groups, plan.data(), plan.size() * sizeof(GemmGroup),
+                                                hipMemcpyHostToDevice) != hipSuccess)))
+            rc = FEAST_EDEVICE;
+        if (!rc) rc = batch_capture(bt, S);
+    }
+    // one launch of the graph on the caller's stream, timed, then the zero-pivot checks
+    if (!rc) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+            hipEventRecord(e0, bt->user) != hipSuccess || hipGraphLaunch(bt->exec, bt->user) != hipSuccess ||
+            hipEventRecord(e1, bt->user) != hipSuccess || hipStreamSynchronize(bt->user) != hipSuccess ||
+            hipEventElapsedTime(&bt->factor_ms, e0, e1) != hipSuccess)
+            rc = FEAST_EDEVICE;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    if (!rc) {
+        for (int b = 0; b < count; ++b) {
+            const int r = ctx_check_info(bt->ctx[b]);
+            if (info) info[b] = r;
+            if (r && !rc) rc = r;
+        }
+    }
+    if (rc) {
+        batch_free(bt);
+        return rc;
+    }
+    *batch = bt;
+    return 0;
+}
+
+feast_ctx* feast_batch_member(feast_batch* bt, int i) {
+    if (!bt || i < 0 || i >= bt->count) return nullptr;
+    return bt->ctx[i];
+}
+
+int feast_batch_factor_ms(feast_batch* bt, double* ms) {
+    if (!bt) return -1;
+    if (!ms) return -2;
+    *ms = bt->factor_ms;
+    return 0;
+}
+
+int feast_batch_iterate(feast_batch* bt, const void* const* U0, const int* ldu0, feast_result* res, int* member_rc) {
+    if (!bt) return -1;
+    if (!U0 || !ldu0) return -2;
+    if (!res) return -4;
+    std::vector<Run> runs(bt->count);
+    std::vector<Run*> ptrs;
+    for (int b = 0; b < bt->count; ++b) {
+        feast_ctx* c = bt->ctx[b];
+        if (!U0[b] || ldu0[b] < c->n) return -2;
+        feast_result* r = &res[b];
+        if (!r->lambda || !r->resid || !r->X || r->ldx < c->n) return -4;
+        if (c->o.variant == FEAST_BI && r->Y && r->ldy < c->n) return -4;
+        runs[b].c = c;
+        runs[b].U0 = (const z64*)U0[b];
+        runs[b].ldu0 = ldu0[b];
+        runs[b].res = r;
+        ptrs.push_back(&runs[b]);
+    }
+    // member streams start after the caller's stream (the start blocks were written there) and the
+    // caller's stream continues after them
+    hipEvent_t ev = nullptr;
+    FM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    int rc = 0;
+    if (hipEventRecord(ev, bt->user) != hipSuccess) rc = FEAST_EDEVICE;
+    for (int b = 0; b < bt->count && !rc; ++b)
+        if (hipStreamWaitEvent(bt->streams[b], ev, 0) != hipSuccess) rc = FEAST_EDEVICE;
+    if (!rc) rc = drive(ptrs);
+    for (int b = 0; b < bt->count && !rc; ++b)
+        if (hipStreamSynchronize(bt->streams[b]) != hipSuccess) rc = FEAST_EDEVICE;
+    (void)hipEventDestroy(ev);
+    for (int b = 0; b < bt->count; ++b) {
+        if (member_rc) member_rc[b] = runs[b].rc;
+        if (!rc && runs[b].rc) rc = runs[b].rc;
+    }
+    return rc;
+}
+
+void feast_batch_destroy(feast_batch* bt) { batch_free(bt); }
 
 }  // extern "C"

@@ -5,6 +5,16 @@
 
 namespace fm {
 
+// One member of a grouped product: the operands, strides and sizes that differ between members
+// (for instance one per pencil of a batch of factorisations of different orders).
+struct GemmGroup {
+    const void* A; const void* B; void* C;
+    long lda, ldb, ldc;
+    long sA, sB, sC;        // batch strides
+    long sA2, sB2, sC2;     // second batch strides
+    int M, N, K, batch;
+};
+
 // One batched product C_b = alpha_b op(A_b) op(B_b) + beta C_b, b = 0..batch-1.
 //
 // Element (i, k) of op(A) is A[i*lda + k] when rowA, else A[i + k*lda], conjugated
@@ -28,6 +38,11 @@ struct GemmOp {
     // kind 1 selects a separate kernel instance (same code) for the LU trailing update, so that
     // profilers can attribute it
     int kind = 0;
+    // grouped product: when groups != nullptr (a device array of ngroups members), each member
+    // supplies its own operands, strides, M, N, K and batch, and M, N, K, batch above are the
+    // maxima over the members (they size the grid).  Requires splitk == 1 and alpha_b == nullptr.
+    const GemmGroup* groups = nullptr;
+    int ngroups = 0;
 };
 
 // T = double (complex128 operands, FP64 MFMA) or float (complex64, FP32 MFMA).

@@ -42,6 +42,8 @@ struct Params {
     const z64* alpha_b;
     int conjA, conjB;
     cplx<T>* partial;
+    const GemmGroup* groups;   // grouped product (member = blockIdx.z / (batch * batch2))
+    int ngroups;
 };
 
 template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC, int KIND>
@@ -57,13 +59,33 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int tm = blockIdx.x % p.tiles_m, tn = blockIdx.x / p.tiles_m;
-    const int b = blockIdx.z % p.batch, s = (blockIdx.z / p.batch) % p.splitk;
-    const int b2 = blockIdx.z / (p.batch * p.splitk);
+    int b = blockIdx.z % p.batch, s = (blockIdx.z / p.batch) % p.splitk;
+    int b2 = blockIdx.z / (p.batch * p.splitk);
     const int m0 = tm * BM, n0 = tn * BN;
+    const cplx<T>* pA = p.A;
+    const cplx<T>* pB = p.B;
+    cplx<T>* pC = p.C;
+    long lda = p.lda, ldb = p.ldb, ldc = p.ldc;
+    long sA = p.sA, sB = p.sB, sC = p.sC, sA2 = p.sA2, sB2 = p.sB2, sC2 = p.sC2;
+    int M = p.M, N = p.N, K = p.K;
+    if (p.groups) {
+        // member of a grouped product (splitk == 1): its own operands and sizes; workgroups
+        // outside the member's tiles or batch leave at once
+        const int per = p.batch * p.batch2;
+        const GemmGroup& g = p.groups[blockIdx.z / per];
+        b = (blockIdx.z % per) % p.batch;
+        b2 = (blockIdx.z % per) / p.batch;
+        s = 0;
+        M = g.M; N = g.N; K = g.K;
+        if (b >= g.batch || m0 >= M || n0 >= N) return;
+        pA = (const cplx<T>*)g.A; pB = (const cplx<T>*)g.B; pC = (cplx<T>*)g.C;
+        lda = g.lda; ldb = g.ldb; ldc = g.ldc;
+        sA = g.sA; sB = g.sB; sC = g.sC; sA2 = g.sA2; sB2 = g.sB2; sC2 = g.sC2;
+    }
     const int kbeg = s * p.kchunk;
-    const int kend = min(p.K, kbeg + p.kchunk);
-    const cplx<T>* __restrict__ A = p.A + b * p.sA + b2 * p.sA2;
-    const cplx<T>* __restrict__ B = p.B + b * p.sB + b2 * p.sB2;
+    const int kend = p.groups ? K : min(K, kbeg + p.kchunk);
+    const cplx<T>* __restrict__ A = pA + b * sA + b2 * sA2;
+    const cplx<T>* __restrict__ B = pB + b * sB + b2 * sB2;
     const T sa = p.conjA ? T(-1) : T(1), sb = p.conjB ? T(-1) : T(1);
 
     cplx<T> ra[EA], rb[EB];
@@ -75,7 +97,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
             const int i = RA ? idx / BK : idx % BM;
             const int gi = m0 + i, gk = k0 + k;
             cplx<T> v(T(0), T(0));
-            if (gi < p.M && gk < kend) v = RA ? A[(long)gi * p.lda + gk] : A[gi + (long)gk * p.lda];
+            if (gi < M && gk < kend) v = RA ? A[(long)gi * lda + gk] : A[gi + (long)gk * lda];
             ra[e] = v;
         }
 #pragma unroll
@@ -85,7 +107,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
             const int k = RBm ? idx / BN : idx % BK;
             const int gj = n0 + j, gk = k0 + k;
             cplx<T> v(T(0), T(0));
-            if (gj < p.N && gk < kend) v = RBm ? B[(long)gk * p.ldb + gj] : B[gk + (long)gj * p.ldb];
+            if (gj < N && gk < kend) v = RBm ? B[(long)gk * ldb + gj] : B[gk + (long)gj * ldb];
             rb[e] = v;
         }
     };
@@ -157,7 +179,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
         ar = T(p.alpha_b[b].re);
         ai = T(p.alpha_b[b].im);
     }
-    cplx<T>* __restrict__ C = p.C + b * p.sC + b2 * p.sC2;
+    cplx<T>* __restrict__ C = pC + b * sC + b2 * sC2;
     const bool has_beta = (p.br != T(0) || p.bi != T(0));
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -167,13 +189,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
             for (int v = 0; v < 4; ++v) {
                 const int i = m0 + wm * RB * 16 + r * 16 + out_row<T>(lane, v);
                 const int j = n0 + wn * CB * 16 + c * 16 + (lane & 15);
-                if (i < p.M && j < p.N) {
+                if (i < M && j < N) {
                     const T xr = cre[r][c][v], xi = cim[r][c][v];
                     if (p.splitk > 1) {
-                        p.partial[(((long)s * p.batch + b) * p.N + j) * p.M + i] = cplx<T>(xr, xi);
+                        p.partial[(((long)s * p.batch + b) * N + j) * M + i] = cplx<T>(xr, xi);
                     } else {
                         T yr = ar * xr - ai * xi, yi = ar * xi + ai * xr;
-                        cplx<T>* cp = RC ? &C[(long)i * p.ldc + j] : &C[i + (long)j * p.ldc];
+                        cplx<T>* cp = RC ? &C[(long)i * ldc + j] : &C[i + (long)j * ldc];
                         if (has_beta) {
                             const cplx<T> o = *cp;
                             yr += p.br * o.re - p.bi * o.im;
@@ -214,7 +236,7 @@ template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC
 void launch_cfg(Params<T> p, hipStream_t st) {
     constexpr int BM = WM * RB * 16, BN = WN * CB * 16;
     p.tiles_m = ceil_div(p.M, BM);
-    dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.splitk * p.batch2);
+    dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.splitk * p.batch2 * (p.groups ? p.ngroups : 1));
     hipLaunchKernelGGL((cgemm_kernel<T, WM, WN, RB, CB, RA, RBm, RC, KIND>), grid, dim3(64 * WM * WN), 0, st, p);
 }
 
@@ -249,7 +271,13 @@ int gemm(const GemmOp& op, hipStream_t st) {
     p.alpha_b = op.alpha_b;
     p.conjA = op.conjA; p.conjB = op.conjB;
     p.partial = (cplx<T>*)op.partial;
+    p.groups = op.groups;
+    p.ngroups = op.ngroups;
     p.tiles_m = 1;
+    if (op.groups) {
+        if (op.ngroups <= 0) return 0;
+        if (p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;
+    }
     if (op.kind == 1) {  // LU trailing update: all operands row-major
         if (!(op.rowA && op.rowB && op.rowC) || p.splitk > 1) return FEAST_EUNSUPPORTED;
         launch_cfg<T, 2, 2, 2, 2, true, true, true, 1>(p, st);

@@ -1,7 +1,10 @@
 // Node assembly and batched LU with partial pivoting (one factorisation per contour node).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
+#include "gemm.h"
 #include "timing.h"
 
 namespace fm {
@@ -17,7 +20,7 @@ struct LUStore {
     int* ipiv = nullptr; int* perm = nullptr; int* iperm = nullptr; long spiv = 0;
     void* Linv = nullptr; void* Uinv = nullptr;
     int* info = nullptr;         // q ints: 0, or first zero-pivot column + 1
-    void* tmp = nullptr;         // q * nb * n elements: swapped U12 rows awaiting the block inverse
+    void* tmp = nullptr;         // q * lu_tmp_elems elements: swapped U12 rows, composition scratch
     int n = 0, q = 0, nb = 0, nsteps = 0;
     Timer* timer = nullptr;      // optional per-phase timing
     // pivot-candidate slots of the multi-workgroup panel: q * pW * 2 values, rows and rows of
@@ -28,6 +31,10 @@ struct LUStore {
     // the nb x nb ones after the factorisation; block s of node k at (k * nsbs + s) * nbs * nbs
     int nbs = 0, nsbs = 0;
     void* LinvS = nullptr; void* UinvS = nullptr;
+    // the pencil (column-major complex128, B == nullptr means I) and the q nodes (device)
+    const z64* A = nullptr; long lda = 0;
+    const z64* B = nullptr; long ldb = 0;
+    const z64* z = nullptr;
 };
 
 // Elements of the LU staging buffer per node: the panel swaps need nb * n, the composition of the
@@ -48,15 +55,44 @@ inline size_t panel_slot_bytes(int n, int q, int nb, size_t real_bytes, int* pW)
     return a + b + ((size_t)q * W * 2 * nb + (size_t)q * 2 * nb) * 2 * real_bytes;
 }
 
-// T_k = z_k B - A for every node (A, B column-major complex128; B == nullptr means I), written to
-// the row-major factor storage in precision T.
-template <typename T>
-int assemble_nodes(const LUStore& s, const z64* A, long lda, const z64* B, long ldb, const z64* z_dev,
-                   hipStream_t st);
+// Device copy of what the factorisation kernels read of one member of a set (one pencil).
+struct LUDev {
+    void* F; long ldf, sF;
+    int* ipiv; int* perm; int* iperm; long spiv;
+    void* Linv; void* Uinv; int* info; void* tmp; long stmp;
+    void* cval; int* crow; void* cdata; void* rowj; int pW;
+    void* LinvS; void* UinvS;
+    const z64* A; long lda; const z64* B; long ldb; const z64* z;
+    int n, nsteps, nsbs;
+};
 
-// In-place blocked right-looking LU with partial pivoting of all q node matrices, followed by the
-// diagonal-block inverses and the combined permutations.
+// A set of pencils factored together: every kernel of the factorisation covers all (pencil, node)
+// pairs of the set in one launch (grid z = pencil), members whose order n leaves them without work
+// at a step exit at once.  All members share q, nb, nbs and the precision.  dev is a device array
+// of count descriptors; groups a device table of the grouped-product members that the sequence
+// of launches consumes in order (lu_plan fills it).
+struct LUSet {
+    const LUStore* s = nullptr;
+    int count = 0;
+    LUDev* dev = nullptr;
+    GemmGroup* groups = nullptr;
+    Timer* timer = nullptr;
+};
+
+// Descriptor of one member (real_bytes: 4 or 8, the precision of the storage).
+LUDev lu_dev(const LUStore& s, size_t real_bytes);
+
+// Grouped-product members the factorisation of the set needs, in launch order (host values to
+// upload into LUSet::groups before lu_factor_set runs).  The count depends only on the orders n,
+// q, nb and nbs; for a set it is the sum of its members' counts.
 template <typename T>
-int factor_nodes(const LUStore& s, hipStream_t st);
+void lu_plan(const LUSet& S, std::vector<GemmGroup>& out);
+
+// a2 + a3 for every member: T_k = z_k B - A written to the row-major storage in precision T,
+// then the in-place blocked right-looking LU with partial pivoting of all q node matrices, the
+// diagonal-block inverses and the combined permutations.  Enqueue only: no host synchronisation,
+// no memory set or copy calls (the sequence can be captured into a graph).
+template <typename T>
+int lu_factor_set(const LUSet& S, hipStream_t st);
 
 }  // namespace fm

@@ -2,7 +2,8 @@
 //
 // Factorisations are stored row-major (element (i, j) at F[i * ldf + j]) so that the row
 // interchanges of partial pivoting move contiguous memory and a panel row is one coalesced
-// load.  Every kernel is batched over the q nodes of a pencil (blockIdx.y or blockIdx.x).
+// load.  Every kernel covers all q nodes of every pencil of a set (grid z = pencil, y or x = node),
+// so that one launch per step serves a whole batch of pencils of different orders.
 //
 // Right-looking blocked LU, block size nb, per step s (columns j0 = s nb .. j0 + w):
 //   panel   : pivot search (largest |re| + |im|, lowest row on ties), row swap, scaling and
@@ -26,32 +27,42 @@ namespace {
 constexpr int NBMAX = 64;
 
 template <typename T>
-__global__ __launch_bounds__(256) void assemble_kernel(cplx<T>* F, long ldf, long sF, int n, int q,
-                                                       const z64* __restrict__ A, long lda,
-                                                       const z64* __restrict__ B, long ldb,
-                                                       const z64* __restrict__ z) {
-    __shared__ z64 ta[32][33], tb[32][33];
+__global__ __launch_bounds__(256) void assemble_kernel(const LUDev* __restrict__ dv, int q) {
+    const LUDev& d = dv[blockIdx.z];
+    const int n = d.n;
     const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    if (bi >= n || bj >= n) return;
+    __shared__ z64 ta[32][33], tb[32][33];
+    const z64* __restrict__ A = d.A;
+    const z64* __restrict__ B = d.B;
+    cplx<T>* F = (cplx<T>*)d.F;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int jj = ty; jj < 32; jj += 8) {
         const int i = bi + tx, j = bj + jj;
         if (i < n && j < n) {
-            ta[jj][tx] = A[i + (long)j * lda];
-            tb[jj][tx] = B ? B[i + (long)j * ldb] : z64(i == j ? 1.0 : 0.0, 0.0);
+            ta[jj][tx] = A[i + (long)j * d.lda];
+            tb[jj][tx] = B ? B[i + (long)j * d.ldb] : z64(i == j ? 1.0 : 0.0, 0.0);
         }
     }
     __syncthreads();
     for (int k = 0; k < q; ++k) {
-        const z64 zk = z[k];
+        const z64 zk = d.z[k];
         for (int ii = ty; ii < 32; ii += 8) {
             const int i = bi + ii, j = bj + tx;
             if (i < n && j < n) {
                 const z64 v = zk * tb[tx][ii] - ta[tx][ii];
-                F[k * sF + (long)i * ldf + j] = cplx<T>(v);
+                F[k * d.sF + (long)i * d.ldf + j] = cplx<T>(v);
             }
         }
     }
 }
+
+// Step (j0, w) of member d: w = min(nb, n - j0), or 0 when the member has no such step.
+__device__ inline int step_width(const LUDev& d, int j0, int nb) { return d.n > j0 ? min(nb, d.n - j0) : 0; }
+
+// The single-workgroup panel serves the trailing rows of at most PANEL_ROWS rows, the
+// multi-workgroup one the taller panels.
+__device__ inline bool multi_panel(const LUDev& d, int j0) { return d.cval != nullptr && d.n - j0 > PANEL_ROWS; }
 
 template <typename T>
 __device__ inline cplx<T> shfl_c(cplx<T> v, int src) {
@@ -63,11 +74,15 @@ __device__ inline cplx<T> shfl_c(cplx<T> v, int src) {
 // interleaved rows.  Per column j one sweep applies the rank-1 update of column j - 1 and
 // searches column j for the pivot.
 template <typename T>
-__global__ __launch_bounds__(256) void panel_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
-                                                    int* ipiv0, long spiv, int* info) {
-    const int k = blockIdx.x;
-    cplx<T>* F = F0 + k * sF;
-    int* ipiv = ipiv0 + k * spiv;
+__global__ __launch_bounds__(256) void panel_kernel(const LUDev* __restrict__ dv, int j0, int nb) {
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    if (w == 0 || multi_panel(d, j0)) return;
+    const int k = blockIdx.x, n = d.n;
+    const long ldf = d.ldf;
+    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
+    int* ipiv = d.ipiv + k * d.spiv;
+    int* info = d.info;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool act = lane < w;
     __shared__ T sval[4];
@@ -152,17 +167,29 @@ __global__ __launch_bounds__(256) void panel_kernel(cplx<T>* F0, long ldf, long 
 // Candidates are double-buffered by column parity; kernel boundaries order everything, so there
 // is no inter-workgroup waiting.
 template <typename T, int U>
-__global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
-                                                         int j, int R, int W, int* ipiv0, long spiv, int* info,
-                                                         T* cval, int* crow, cplx<T>* cdata, cplx<T>* rowj) {
+__global__ __launch_bounds__(256) void panel_step_kernel(const LUDev* __restrict__ dv, int j0, int nb, int j) {
     // U rows per wave (R = 4 U rows per workgroup), all held in registers
+    constexpr int R = 4 * U;
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    if (w == 0 || !multi_panel(d, j0) || j > w) return;
+    const int n = d.n, W = (n - j0 + R - 1) / R;
     const int k = blockIdx.y, g = blockIdx.x;
-    cplx<T>* F = F0 + k * sF;
+    if (g >= W) return;
+    const long ldf = d.ldf;
+    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
+    int* ipiv0 = d.ipiv;
+    const long spiv = d.spiv;
+    int* info = d.info;
+    T* cval = (T*)d.cval;
+    int* crow = d.crow;
+    cplx<T>* cdata = (cplx<T>*)d.cdata;
+    cplx<T>* rowj = (cplx<T>*)d.rowj;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool act = lane < w;
     const int rbeg = j0 + g * R, rend = min(n, rbeg + R);
     const int rfirst = max(rbeg, j0 + j);      // rows still to be updated / searched
-    const long cb = (long)k * W * 2;           // candidate slots of node k: [W][2]
+    const long cb = (long)k * d.pW * 2;        // candidate slots of node k: [pW][2]
     const cplx<T> zero(T(0), T(0));
     __shared__ T sval[4];
     __shared__ int srow[4];
@@ -286,15 +313,17 @@ __global__ __launch_bounds__(256) void panel_step_kernel(cplx<T>* F0, long ldf, 
 // Row interchanges of step (j0, w) applied to the columns outside the panel; the swapped rows
 // j0..j0+w-1 of the columns right of the panel are copied to tmp (row-major, ld n).
 template <typename T>
-__global__ __launch_bounds__(256) void swap_kernel(cplx<T>* F0, long ldf, long sF, int n, int j0, int w,
-                                                   const int* ipiv0, long spiv, cplx<T>* tmp0, long stmp) {
-    const int k = blockIdx.y;
+__global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv, int j0, int nb) {
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    const int k = blockIdx.y, n = d.n;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int ncols = n - w;
-    if (t >= ncols) return;
+    if (w == 0 || t >= ncols) return;
     const int c = t < j0 ? t : t + w;
-    cplx<T>* F = F0 + k * sF;
-    const int* ipiv = ipiv0 + k * spiv;
+    const long ldf = d.ldf;
+    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
+    const int* ipiv = d.ipiv + k * d.spiv;
     for (int j = 0; j < w; ++j) {
         const int r = ipiv[j0 + j];
         if (r != j0 + j) {
@@ -305,7 +334,7 @@ __global__ __launch_bounds__(256) void swap_kernel(cplx<T>* F0, long ldf, long s
         }
     }
     if (c >= j0 + w) {
-        cplx<T>* tmp = tmp0 + k * stmp;
+        cplx<T>* tmp = (cplx<T>*)d.tmp + k * d.stmp;
         for (int j = 0; j < w; ++j) tmp[(long)j * n + (c - j0 - w)] = F[(long)(j0 + j) * ldf + c];
     }
 }
@@ -313,13 +342,17 @@ __global__ __launch_bounds__(256) void swap_kernel(cplx<T>* F0, long ldf, long s
 // Inverses of diagonal blocks: UPPER = false -> unit lower part of block s, UPPER = true -> upper
 // part with its diagonal.  One wave per (block, node); thread j forms column j of the inverse.
 template <typename T, bool UPPER>
-__global__ __launch_bounds__(64) void trtri_kernel(const cplx<T>* F0, long ldf, long sF, int n, int nb,
-                                                   int nsteps, int s_first, cplx<T>* Inv0) {
+__global__ __launch_bounds__(64) void trtri_kernel(const LUDev* __restrict__ dv, int nb, int s_first) {
+    const LUDev& d = dv[blockIdx.z];
+    const int s = s_first + blockIdx.x, k = blockIdx.y;
+    if (s >= d.nsteps) return;
     __shared__ cplx<T> M[NBMAX][NBMAX + 1];
     __shared__ cplx<T> X[NBMAX][NBMAX + 1];
-    const int s = s_first + blockIdx.x, k = blockIdx.y;
+    const int n = d.n, nsteps = d.nsteps;
+    const long ldf = d.ldf;
     const int j0 = s * nb, w = min(nb, n - j0);
-    const cplx<T>* F = F0 + k * sF;
+    const cplx<T>* F = (const cplx<T>*)d.F + k * d.sF;
+    cplx<T>* Inv0 = (cplx<T>*)(UPPER ? d.Uinv : d.Linv);
     const int j = threadIdx.x;
     for (int i = 0; i < w; ++i) {
         if (j < w) M[i][j] = F[(long)(j0 + i) * ldf + j0 + j];
@@ -347,10 +380,14 @@ __global__ __launch_bounds__(64) void trtri_kernel(const cplx<T>* F0, long ldf, 
 }
 
 // Combined permutation of the sequential interchanges: row i of P T is row perm[i] of T.
-__global__ __launch_bounds__(256) void perm_kernel(const int* ipiv0, int* perm0, int* iperm0, long spiv, int n) {
+__global__ __launch_bounds__(256) void perm_kernel(const LUDev* __restrict__ dv) {
     extern __shared__ int sp[];
-    const int k = blockIdx.x;
-    const int* ipiv = ipiv0 + k * spiv;
+    const LUDev& d = dv[blockIdx.z];
+    const int k = blockIdx.x, n = d.n;
+    const long spiv = d.spiv;
+    const int* ipiv = d.ipiv + k * spiv;
+    int* perm0 = d.perm;
+    int* iperm0 = d.iperm;
     for (int i = threadIdx.x; i < n; i += blockDim.x) sp[i] = i;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -373,11 +410,17 @@ __global__ __launch_bounds__(256) void perm_kernel(const int* ipiv0, int* perm0,
 // Solve-block inverses, initial state: the nb x nb diagonal inverses placed on the diagonal of
 // each nbs x nbs block, zeros elsewhere (the off-diagonal parts are composed afterwards).
 template <typename T>
-__global__ void init_solve_inv_kernel(cplx<T>* LS, cplx<T>* US, const cplx<T>* __restrict__ L64,
-                                      const cplx<T>* __restrict__ U64, int nb, int nbs, int nsteps, int nsbs) {
-    const int k = blockIdx.z, sblk = blockIdx.y;
+__global__ void init_solve_inv_kernel(const LUDev* __restrict__ dv, int q, int nb, int nbs) {
+    const LUDev& d = dv[blockIdx.z / q];
+    const int k = blockIdx.z % q, sblk = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nbs * nbs) return;
+    const int nsteps = d.nsteps, nsbs = d.nsbs;
+    // members of order <= nb have no solve-block inverses (none are allocated for them)
+    if (d.LinvS == nullptr || d.UinvS == nullptr || t >= nbs * nbs || sblk >= nsbs) return;
+    cplx<T>* LS = (cplx<T>*)d.LinvS;
+    cplx<T>* US = (cplx<T>*)d.UinvS;
+    const cplx<T>* __restrict__ L64 = (const cplx<T>*)d.Linv;
+    const cplx<T>* __restrict__ U64 = (const cplx<T>*)d.Uinv;
     const int i = t / nbs, j = t % nbs;
     const long o = ((long)k * nsbs + sblk) * nbs * nbs + t;
     const int bi = i / nb, bj = j / nb;
@@ -392,198 +435,291 @@ __global__ void init_solve_inv_kernel(cplx<T>* LS, cplx<T>* US, const cplx<T>* _
     US[o] = u;
 }
 
-__global__ void zero_ints(int* p, int count) {
+__global__ void zero_info(const LUDev* __restrict__ dv, int q) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < count) p[t] = 0;
+    if (t < q) dv[blockIdx.z].info[t] = 0;
+}
+
+
+// Members with solve-block inverses (formed when the order exceeds one factorisation block).
+bool has_solve_blocks(const LUStore& s) { return s.n > s.nb && s.nbs > s.nb; }
+
+// One pass over the launch sequence of a set: records the grouped-product members (rec != nullptr)
+// or launches everything, consuming S.groups in the same order.
+template <typename T>
+struct SetRun {
+    const LUSet& S;
+    hipStream_t st;
+    std::vector<GemmGroup>* rec;
+    size_t off = 0;
+    int q = 0, nb = 0, nbs = 0, nmax = 0, nsteps_max = 0, nsbs_max = 0;
+
+    SetRun(const LUSet& s, hipStream_t stream, std::vector<GemmGroup>* r) : S(s), st(stream), rec(r) {
+        q = S.s[0].q;
+        nb = S.s[0].nb;
+        nbs = S.s[0].nbs;
+        for (int b = 0; b < S.count; ++b) {
+            nmax = std::max(nmax, S.s[b].n);
+            nsteps_max = std::max(nsteps_max, S.s[b].nsteps);
+            nsbs_max = std::max(nsbs_max, S.s[b].nsbs);
+        }
+    }
+    bool launching() const { return rec == nullptr; }
+    void start(Phase ph) {
+        if (launching() && S.timer) S.timer->start(ph, st);
+    }
+    void stop(Phase ph, double flops) {
+        if (launching() && S.timer) S.timer->stop(ph, st, flops);
+    }
+    // one grouped product over the members in g (members without work already left out)
+    int grouped(const std::vector<GemmGroup>& g, GemmOp op) {
+        if (g.empty()) return 0;
+        if (rec) {
+            rec->insert(rec->end(), g.begin(), g.end());
+            return 0;
+        }
+        op.M = op.N = op.K = op.batch = 0;
+        for (const GemmGroup& x : g) {
+            op.M = std::max(op.M, x.M);
+            op.N = std::max(op.N, x.N);
+            op.K = std::max(op.K, x.K);
+            op.batch = std::max(op.batch, x.batch);
+        }
+        op.groups = S.groups + off;
+        op.ngroups = (int)g.size();
+        off += g.size();
+        return gemm<T>(op, st);
+    }
+};
+
+GemmGroup member(const void* A, long lda, long sA, long sA2, const void* B, long ldb, long sB, long sB2, void* C,
+                 long ldc, long sC, long sC2, int M, int N, int K, int batch) {
+    GemmGroup g;
+    g.A = A; g.lda = lda; g.sA = sA; g.sA2 = sA2;
+    g.B = B; g.ldb = ldb; g.sB = sB; g.sB2 = sB2;
+    g.C = C; g.ldc = ldc; g.sC = sC; g.sC2 = sC2;
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    return g;
+}
+
+// Panel factorisation of step j0 of every member: the single-workgroup kernel for members with at
+// most PANEL_ROWS rows left, one multi-workgroup launch per column for the others.
+template <typename T>
+int panel(SetRun<T>& R, int j0) {
+    if (!R.launching()) return 0;
+    const LUSet& S = R.S;
+    bool single = false;
+    int wmax = -1, Wmax = 0;
+    for (int b = 0; b < S.count; ++b) {
+        const LUStore& s = S.s[b];
+        if (s.n <= j0) continue;
+        const int w = std::min(R.nb, s.n - j0);
+        if (s.pslots && s.n - j0 > PANEL_ROWS) {
+            wmax = std::max(wmax, w);
+            Wmax = std::max(Wmax, ceil_div(s.n - j0, PANEL_ROWS));
+        } else {
+            single = true;
+        }
+    }
+    if (single) {
+        hipLaunchKernelGGL((panel_kernel<T>), dim3(R.q, 1, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb);
+        FM_LAUNCH_CHECK();
+    }
+    for (int j = 0; j <= wmax; ++j) {
+        hipLaunchKernelGGL((panel_step_kernel<T, PANEL_ROWS / 4>), dim3(Wmax, R.q, S.count), dim3(256), 0, R.st, S.dev,
+                           j0, R.nb, j);
+        FM_LAUNCH_CHECK();
+    }
+    return 0;
+}
+
+// Inverses of the nbs x nbs diagonal blocks of L and U of every member, by recursive doubling from
+// the nb x nb ones.  For the pair of h x h blocks at offset o inside a solve block (second half of
+// size h2 <= h):  lower  X21 = -X22 L21 X11,  upper  Y12 = -Y11 U12 Y22.  Per member the solve
+// blocks whose pair lies inside the matrix form one batch, the block with a partial second half
+// another.
+template <typename T>
+int build_solve_inverses(SetRun<T>& R) {
+    const LUSet& S = R.S;
+    const int NBS = R.nbs, nb = R.nb, q = R.q;
+    bool any = false;
+    for (int b = 0; b < S.count; ++b) any = any || has_solve_blocks(S.s[b]);
+    if (!any) return 0;
+    if (R.launching()) {
+        hipLaunchKernelGGL((init_solve_inv_kernel<T>), dim3(ceil_div(NBS * NBS, 256), R.nsbs_max, q * S.count), dim3(256),
+                           0, R.st, S.dev, q, nb, NBS);
+        FM_LAUNCH_CHECK();
+    }
+    const long sblk = (long)NBS * NBS, tslot = 128L * 128;
+    for (int h = nb; h < NBS; h *= 2) {
+        for (int o = 0; o < NBS; o += 2 * h) {
+            std::vector<GemmGroup> g1, g2, g3, g4;
+            for (int b = 0; b < S.count; ++b) {
+                const LUStore& s = S.s[b];
+                if (!has_solve_blocks(s)) continue;
+                const int n = s.n;
+                const int nfull = n >= o + 2 * h ? std::min(s.nsbs, (n - o - 2 * h) / NBS + 1) : 0;
+                int parts[2][3] = {{0, nfull, h}, {nfull, 0, 0}};   // (first block, blocks, h2)
+                if (nfull < s.nsbs) {
+                    const int h2 = n - (nfull * NBS + o + h);
+                    if (h2 > 0 && h2 < h) {
+                        parts[1][1] = 1;
+                        parts[1][2] = h2;
+                    }
+                }
+                const long snode = (long)s.nsbs * sblk, tnode = (long)s.nsbs * tslot;
+                const long fstep = (long)NBS * (s.ldf + 1);     // F stride from one solve block to the next
+                for (auto& pt : parts) {
+                    const int b0 = pt[0], nblk = pt[1], h2 = pt[2];
+                    if (nblk <= 0) continue;
+                    cplx<T>* F = (cplx<T>*)s.F;
+                    cplx<T>* LS = (cplx<T>*)s.LinvS + b0 * sblk;
+                    cplx<T>* US = (cplx<T>*)s.UinvS + b0 * sblk;
+                    cplx<T>* tmp = (cplx<T>*)s.tmp + b0 * tslot;
+                    const long j0 = (long)b0 * NBS + o;
+                    // T = L21 X11 (h2 x h);  X21 = -X22 T;  T = U12 Y22 (h x h2);  Y12 = -Y11 T
+                    g1.push_back(member(F + (j0 + h) * s.ldf + j0, s.ldf, fstep, s.sF, LS + (long)o * NBS + o, NBS,
+                                        sblk, snode, tmp, 128, tslot, tnode, h2, h, h, nblk));
+                    g2.push_back(member(LS + (long)(o + h) * NBS + (o + h), NBS, sblk, snode, tmp, 128, tslot, tnode,
+                                        LS + (long)(o + h) * NBS + o, NBS, sblk, snode, h2, h, h2, nblk));
+                    g3.push_back(member(F + j0 * s.ldf + j0 + h, s.ldf, fstep, s.sF, US + (long)(o + h) * NBS + (o + h),
+                                        NBS, sblk, snode, tmp, 128, tslot, tnode, h, h2, h2, nblk));
+                    g4.push_back(member(US + (long)o * NBS + o, NBS, sblk, snode, tmp, 128, tslot, tnode,
+                                        US + (long)o * NBS + (o + h), NBS, sblk, snode, h, h2, h, nblk));
+                }
+            }
+            GemmOp op;
+            op.rowA = op.rowB = op.rowC = true;
+            op.batch2 = q;
+            FM_TRY(R.grouped(g1, op));
+            GemmOp neg = op;
+            neg.alpha = z64(-1.0);
+            FM_TRY(R.grouped(g2, neg));
+            FM_TRY(R.grouped(g3, op));
+            FM_TRY(R.grouped(g4, neg));
+        }
+    }
+    return 0;
+}
+
+template <typename T>
+int run_set(SetRun<T>& R) {
+    const LUSet& S = R.S;
+    const int q = R.q, nb = R.nb, P = S.count;
+    if (nb > NBMAX || nb % 16) return FEAST_EUNSUPPORTED;
+    for (int b = 0; b < P; ++b)
+        if (S.s[b].q != q || S.s[b].nb != nb || S.s[b].nbs != R.nbs) return FEAST_EUNSUPPORTED;
+    if (R.launching()) {
+        hipLaunchKernelGGL(zero_info, dim3(ceil_div(q, 256), 1, P), dim3(256), 0, R.st, S.dev, q);
+        FM_LAUNCH_CHECK();
+        const int t = ceil_div(R.nmax, 32);
+        hipLaunchKernelGGL((assemble_kernel<T>), dim3(t, t, P), dim3(256), 0, R.st, S.dev, q);
+        FM_LAUNCH_CHECK();
+    }
+    R.start(PH_LU_PANEL);
+    FM_TRY(panel<T>(R, 0));
+    R.stop(PH_LU_PANEL, 0.0);
+    for (int step = 0; step < R.nsteps_max; ++step) {
+        const int j0 = step * nb;
+        std::vector<GemmGroup> u12, upd;
+        int swap_cols = 0;
+        double flops = 0.0;
+        for (int b = 0; b < P; ++b) {
+            const LUStore& s = S.s[b];
+            if (s.n <= j0) continue;
+            const int w = std::min(nb, s.n - j0), jn = j0 + w, nr = s.n - jn;
+            swap_cols = std::max(swap_cols, s.n - w);
+            if (nr <= 0) continue;
+            cplx<T>* F = (cplx<T>*)s.F;
+            // U12 = L_ss^-1 * (swapped rows staged in tmp)
+            u12.push_back(member((cplx<T>*)s.Linv + (long)step * nb * nb, nb, (long)s.nsteps * nb * nb, 0, s.tmp, s.n,
+                                 (long)nb * s.n, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0, w, nr, w, q));
+            // A22 -= L21 * U12
+            upd.push_back(member(F + (long)jn * s.ldf + j0, s.ldf, s.sF, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0,
+                                 F + (long)jn * s.ldf + jn, s.ldf, s.sF, 0, nr, nr, w, q));
+            flops += 8.0 * nr * (double)nr * w * q;
+        }
+        R.start(PH_LU_OTHER);
+        if (R.launching()) {
+            hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q, P), dim3(64), 0, R.st, S.dev, nb, step);
+            FM_LAUNCH_CHECK();
+            if (swap_cols > 0) {
+                hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(swap_cols, 256), q, P), dim3(256), 0, R.st, S.dev,
+                                   j0, nb);
+                FM_LAUNCH_CHECK();
+            }
+        }
+        GemmOp op;
+        op.rowA = op.rowB = op.rowC = true;
+        FM_TRY(R.grouped(u12, op));
+        R.stop(PH_LU_OTHER, 0.0);
+        if (upd.empty()) break;
+        GemmOp up = op;
+        up.alpha = z64(-1.0);
+        up.beta = z64(1.0);
+        up.kind = 1;
+        R.start(PH_LU_UPDATE);
+        FM_TRY(R.grouped(upd, up));
+        R.stop(PH_LU_UPDATE, flops);
+        R.start(PH_LU_PANEL);
+        FM_TRY(panel<T>(R, j0 + nb));
+        R.stop(PH_LU_PANEL, 0.0);
+    }
+    if (R.launching()) {
+        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(R.nsteps_max, q, P), dim3(64), 0, R.st, S.dev, nb, 0);
+        FM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(perm_kernel, dim3(q, 1, P), dim3(256), R.nmax * sizeof(int), R.st, S.dev);
+        FM_LAUNCH_CHECK();
+    }
+    R.start(PH_LU_OTHER);
+    FM_TRY(build_solve_inverses<T>(R));
+    R.stop(PH_LU_OTHER, 0.0);
+    return 0;
 }
 
 }  // namespace
 
-template <typename T>
-int assemble_nodes(const LUStore& s, const z64* A, long lda, const z64* B, long ldb, const z64* z_dev,
-                   hipStream_t st) {
-    dim3 grid(ceil_div(s.n, 32), ceil_div(s.n, 32));
-    hipLaunchKernelGGL((assemble_kernel<T>), grid, dim3(256), 0, st, (cplx<T>*)s.F, s.ldf, s.sF, s.n, s.q, A, lda,
-                       B, ldb, z_dev);
-    FM_LAUNCH_CHECK();
-    return 0;
-}
-
-// Panel factorisation of step (j0, w) of every node on stream st.
-template <typename T>
-int panel(const LUStore& s, int j0, int w, hipStream_t st) {
-    const int n = s.n, q = s.q, nb = s.nb;
-    cplx<T>* F = (cplx<T>*)s.F;
-    if (s.pslots && n - j0 > PANEL_ROWS) {
-        const int W = ceil_div(n - j0, PANEL_ROWS);
-        T* cval = (T*)s.pslots;
-        int* crow = (int*)((char*)s.pslots + align_up((size_t)q * s.pW * 2 * sizeof(T), 256));
-        cplx<T>* cdata = (cplx<T>*)((char*)crow + align_up((size_t)q * s.pW * 2 * sizeof(int), 256));
-        cplx<T>* rowj = cdata + (size_t)q * s.pW * 2 * nb;
-        for (int j = 0; j <= w; ++j) {
-            hipLaunchKernelGGL((panel_step_kernel<T, PANEL_ROWS / 4>), dim3(W, q), dim3(256), 0, st, F, s.ldf, s.sF,
-                               n, j0, w, j, PANEL_ROWS, W, s.ipiv, s.spiv, s.info, cval, crow, cdata, rowj);
-            FM_LAUNCH_CHECK();
-        }
-    } else {
-        hipLaunchKernelGGL((panel_kernel<T>), dim3(q), dim3(256), 0, st, F, s.ldf, s.sF, n, j0, w, s.ipiv, s.spiv,
-                           s.info);
-        FM_LAUNCH_CHECK();
+LUDev lu_dev(const LUStore& s, size_t real_bytes) {
+    LUDev d{};
+    d.F = s.F; d.ldf = s.ldf; d.sF = s.sF;
+    d.ipiv = s.ipiv; d.perm = s.perm; d.iperm = s.iperm; d.spiv = s.spiv;
+    d.Linv = s.Linv; d.Uinv = s.Uinv; d.info = s.info;
+    d.tmp = s.tmp; d.stmp = (long)s.nb * s.n;
+    d.cval = nullptr; d.crow = nullptr; d.cdata = nullptr; d.rowj = nullptr;
+    d.pW = s.pW;
+    if (s.pslots) {
+        const size_t a = align_up((size_t)s.q * s.pW * 2 * real_bytes, 256);
+        const size_t b = align_up((size_t)s.q * s.pW * 2 * sizeof(int), 256);
+        d.cval = s.pslots;
+        d.crow = (int*)((char*)s.pslots + a);
+        d.cdata = (char*)s.pslots + a + b;
+        d.rowj = (char*)d.cdata + (size_t)s.q * s.pW * 2 * s.nb * 2 * real_bytes;
     }
-    return 0;
-}
-
-// A22 -= L21 * U12 restricted to columns [c0, c0 + nc) of the trailing matrix of step (j0, w).
-template <typename T>
-int trailing_update(const LUStore& s, int j0, int w, int c0, int nc, hipStream_t st) {
-    const int nr = s.n - j0 - w;
-    if (nr <= 0 || nc <= 0) return 0;
-    cplx<T>* F = (cplx<T>*)s.F;
-    GemmOp upd;
-    upd.A = F + (long)(j0 + w) * s.ldf + j0; upd.lda = s.ldf; upd.sA = s.sF; upd.rowA = true;
-    upd.B = F + (long)j0 * s.ldf + c0; upd.ldb = s.ldf; upd.sB = s.sF; upd.rowB = true;
-    upd.C = F + (long)(j0 + w) * s.ldf + c0; upd.ldc = s.ldf; upd.sC = s.sF; upd.rowC = true;
-    upd.M = nr; upd.N = nc; upd.K = w; upd.batch = s.q;
-    upd.alpha = z64(-1.0); upd.beta = z64(1.0);
-    upd.kind = 1;
-    if (s.timer) s.timer->start(PH_LU_UPDATE, st);
-    FM_TRY(gemm<T>(upd, st));
-    if (s.timer) s.timer->stop(PH_LU_UPDATE, st, 8.0 * nr * (double)nc * w * s.q);
-    return 0;
-}
-
-// One recursive-doubling step for the pair of h x h blocks at offset o inside solve blocks
-// b0 .. b0 + nblk - 1 of every node (second half of size h2 <= h):
-//   lower:  X21 = -X22 L21 X11,   upper:  Y12 = -Y11 U12 Y22.
-template <typename T>
-int compose_pair(const LUStore& s, int h, int h2, int o, int b0, int nblk, hipStream_t st) {
-    const int NBS = s.nbs;
-    const long sblk = (long)NBS * NBS, snode = (long)s.nsbs * sblk;
-    const long tslot = 128L * 128, tnode = (long)s.nsbs * tslot;
-    cplx<T>* F = (cplx<T>*)s.F;
-    cplx<T>* LS = (cplx<T>*)s.LinvS + b0 * sblk;
-    cplx<T>* US = (cplx<T>*)s.UinvS + b0 * sblk;
-    cplx<T>* tmp = (cplx<T>*)s.tmp + b0 * tslot;
-    const long j0 = (long)b0 * NBS + o;
-    const long fstep = (long)NBS * (s.ldf + 1);     // F stride from one solve block to the next
-    auto base = [&](GemmOp& g) {
-        g.batch = nblk; g.batch2 = s.q;
-        g.rowA = g.rowB = g.rowC = true;
-    };
-    {   // T = L21 X11  (h2 x h)
-        GemmOp g; base(g);
-        g.A = F + (j0 + h) * s.ldf + j0; g.lda = s.ldf; g.sA = fstep; g.sA2 = s.sF;
-        g.B = LS + (long)o * NBS + o; g.ldb = NBS; g.sB = sblk; g.sB2 = snode;
-        g.C = tmp; g.ldc = 128; g.sC = tslot; g.sC2 = tnode;
-        g.M = h2; g.N = h; g.K = h;
-        FM_TRY(gemm<T>(g, st));
-    }
-    {   // X21 = -X22 T
-        GemmOp g; base(g);
-        g.A = LS + (long)(o + h) * NBS + (o + h); g.lda = NBS; g.sA = sblk; g.sA2 = snode;
-        g.B = tmp; g.ldb = 128; g.sB = tslot; g.sB2 = tnode;
-        g.C = LS + (long)(o + h) * NBS + o; g.ldc = NBS; g.sC = sblk; g.sC2 = snode;
-        g.M = h2; g.N = h; g.K = h2; g.alpha = z64(-1.0);
-        FM_TRY(gemm<T>(g, st));
-    }
-    {   // T = U12 Y22  (h x h2)
-        GemmOp g; base(g);
-        g.A = F + j0 * s.ldf + j0 + h; g.lda = s.ldf; g.sA = fstep; g.sA2 = s.sF;
-        g.B = US + (long)(o + h) * NBS + (o + h); g.ldb = NBS; g.sB = sblk; g.sB2 = snode;
-        g.C = tmp; g.ldc = 128; g.sC = tslot; g.sC2 = tnode;
-        g.M = h; g.N = h2; g.K = h2;
-        FM_TRY(gemm<T>(g, st));
-    }
-    {   // Y12 = -Y11 T
-        GemmOp g; base(g);
-        g.A = US + (long)o * NBS + o; g.lda = NBS; g.sA = sblk; g.sA2 = snode;
-        g.B = tmp; g.ldb = 128; g.sB = tslot; g.sB2 = tnode;
-        g.C = US + (long)o * NBS + (o + h); g.ldc = NBS; g.sC = sblk; g.sC2 = snode;
-        g.M = h; g.N = h2; g.K = h; g.alpha = z64(-1.0);
-        FM_TRY(gemm<T>(g, st));
-    }
-    return 0;
-}
-
-// Inverses of the nbs x nbs diagonal blocks of L and U, by recursive doubling from the nb x nb ones.
-template <typename T>
-int build_solve_inverses(const LUStore& s, hipStream_t st) {
-    const int n = s.n, NBS = s.nbs, nb = s.nb;
-    hipLaunchKernelGGL((init_solve_inv_kernel<T>), dim3(ceil_div(NBS * NBS, 256), s.nsbs, s.q), dim3(256), 0, st,
-                       (cplx<T>*)s.LinvS, (cplx<T>*)s.UinvS, (const cplx<T>*)s.Linv, (const cplx<T>*)s.Uinv, nb, NBS,
-                       s.nsteps, s.nsbs);
-    FM_LAUNCH_CHECK();
-    for (int h = nb; h < NBS; h *= 2) {
-        for (int o = 0; o < NBS; o += 2 * h) {
-            // blocks whose whole pair lies inside the matrix, then the one with a partial second half
-            const int nfull = n >= o + 2 * h ? std::min(s.nsbs, (n - o - 2 * h) / NBS + 1) : 0;
-            if (nfull > 0) FM_TRY(compose_pair<T>(s, h, h, o, 0, nfull, st));
-            if (nfull < s.nsbs) {
-                const int h2 = n - (nfull * NBS + o + h);
-                if (h2 > 0 && h2 < h) FM_TRY(compose_pair<T>(s, h, h2, o, nfull, 1, st));
-            }
-        }
-    }
-    return 0;
+    d.LinvS = s.LinvS; d.UinvS = s.UinvS;
+    d.A = s.A; d.lda = s.lda; d.B = s.B; d.ldb = s.ldb; d.z = s.z;
+    d.n = s.n; d.nsteps = s.nsteps; d.nsbs = s.nsbs;
+    return d;
 }
 
 template <typename T>
-int factor_nodes(const LUStore& s, hipStream_t st) {
-    const int n = s.n, q = s.q, nb = s.nb;
-    if (nb > NBMAX || nb % 16) return FEAST_EUNSUPPORTED;
-    cplx<T>* F = (cplx<T>*)s.F;
-    cplx<T>* Linv = (cplx<T>*)s.Linv;
-    cplx<T>* tmp = (cplx<T>*)s.tmp;
-    hipLaunchKernelGGL(zero_ints, dim3(ceil_div(q, 256)), dim3(256), 0, st, s.info, q);
-    FM_LAUNCH_CHECK();
-    if (s.timer) s.timer->start(PH_LU_PANEL, st);
-    FM_TRY(panel<T>(s, 0, std::min(nb, n), st));
-    if (s.timer) s.timer->stop(PH_LU_PANEL, st, 0.0);
-    for (int step = 0; step < s.nsteps; ++step) {
-        const int j0 = step * nb, w = std::min(nb, n - j0);
-        const int jn = j0 + w, wn = std::min(nb, n - jn);
-        if (s.timer) s.timer->start(PH_LU_OTHER, st);
-        hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF, n,
-                           nb, s.nsteps, step, Linv);
-        FM_LAUNCH_CHECK();
-        if (n - w > 0) {
-            hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(n - w, 256), q), dim3(256), 0, st, F, s.ldf, s.sF, n,
-                               j0, w, (const int*)s.ipiv, s.spiv, tmp, (long)nb * n);
-            FM_LAUNCH_CHECK();
-        }
-        const int nr = n - j0 - w;
-        if (nr > 0) {
-            GemmOp u12;  // U12 = L_ss^-1 * tmp
-            u12.A = Linv + (long)step * nb * nb; u12.lda = nb; u12.sA = (long)s.nsteps * nb * nb; u12.rowA = true;
-            u12.B = tmp; u12.ldb = n; u12.sB = (long)nb * n; u12.rowB = true;
-            u12.C = F + (long)j0 * s.ldf + j0 + w; u12.ldc = s.ldf; u12.sC = s.sF; u12.rowC = true;
-            u12.M = w; u12.N = nr; u12.K = w; u12.batch = q;
-            FM_TRY(gemm<T>(u12, st));
-        }
-        if (s.timer) s.timer->stop(PH_LU_OTHER, st, 0.0);
-        if (nr <= 0) break;
-        FM_TRY(trailing_update<T>(s, j0, w, jn, nr, st));
-        if (s.timer) s.timer->start(PH_LU_PANEL, st);
-        FM_TRY(panel<T>(s, jn, wn, st));
-        if (s.timer) s.timer->stop(PH_LU_PANEL, st, 0.0);
-    }
-    hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(s.nsteps, q), dim3(64), 0, st, (const cplx<T>*)F, s.ldf, s.sF,
-                       n, nb, s.nsteps, 0, (cplx<T>*)s.Uinv);
-    FM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(perm_kernel, dim3(q), dim3(256), n * sizeof(int), st, (const int*)s.ipiv, s.perm, s.iperm,
-                       s.spiv, n);
-    FM_LAUNCH_CHECK();
-    if (s.LinvS && s.UinvS && s.nbs > nb) {
-        if (s.timer) s.timer->start(PH_LU_OTHER, st);
-        FM_TRY(build_solve_inverses<T>(s, st));
-        if (s.timer) s.timer->stop(PH_LU_OTHER, st, 0.0);
-    }
-    return 0;
+void lu_plan(const LUSet& S, std::vector<GemmGroup>& out) {
+    out.clear();
+    if (S.count <= 0) return;
+    SetRun<T> R(S, nullptr, &out);
+    (void)run_set<T>(R);
 }
 
-template int assemble_nodes<double>(const LUStore&, const z64*, long, const z64*, long, const z64*, hipStream_t);
-template int assemble_nodes<float>(const LUStore&, const z64*, long, const z64*, long, const z64*, hipStream_t);
-template int factor_nodes<double>(const LUStore&, hipStream_t);
-template int factor_nodes<float>(const LUStore&, hipStream_t);
+template <typename T>
+int lu_factor_set(const LUSet& S, hipStream_t st) {
+    if (S.count <= 0) return 0;
+    if (!S.dev || !S.groups) return FEAST_EUNSUPPORTED;
+    SetRun<T> R(S, st, nullptr);
+    return run_set<T>(R);
+}
+
+template void lu_plan<double>(const LUSet&, std::vector<GemmGroup>&);
+template void lu_plan<float>(const LUSet&, std::vector<GemmGroup>&);
+template int lu_factor_set<double>(const LUSet&, hipStream_t);
+template int lu_factor_set<float>(const LUSet&, hipStream_t);
 
 }  // namespace fm

@@ -107,3 +107,38 @@ def test_workspace_size_scales():
     assert 24 * 4096 * 4096 * 16 < big < 1.3 * 24 * 4096 * 4096 * 16
     with pytest.raises(binding.FeastError):
         fm.workspace_size(10, 11, C, o64, False)   # m0 > n
+
+
+def _batch_size(ns, m0s, qs, opts, has_B):
+    count = len(ns)
+    C = (binding.Contour * count)(*[binding.make_contour(0j, 1.0, 1.0, q) for q in qs])
+    n_arr = (ctypes.c_int * count)(*ns)
+    m_arr = (ctypes.c_int * count)(*m0s)
+    hb = (ctypes.c_int * count)(*[int(h) for h in has_B])
+    out = ctypes.c_size_t(0)
+    code = fm.lib().feast_batch_workspace_size(count, ctypes.cast(n_arr, ctypes.c_void_p),
+                                               ctypes.cast(m_arr, ctypes.c_void_p), ctypes.cast(C, ctypes.c_void_p),
+                                               ctypes.byref(opts), ctypes.cast(hb, ctypes.c_void_p), ctypes.byref(out))
+    return code, out.value
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_workspace_is_members_plus_tables(prec):
+    """A batch needs every member's own workspace plus the set's descriptor and grouped-product
+    tables (a few hundred bytes per factorisation step)."""
+    o = binding.make_options(prec)
+    ns, m0s = [256, 1000, 65, 2048, 300], [16, 32, 16, 32, 8]
+    code, total = _batch_size(ns, m0s, [16] * 5, o, [True] * 5)
+    assert code == 0
+    singles = sum(fm.workspace_size(n, m, binding.make_contour(0j, 1.0, 1.0, 16), o, True) for n, m in zip(ns, m0s))
+    assert singles <= total <= singles + 5 * 256 + 256 * (2 * sum(-(-n // 64) for n in ns) + 5 * 24) + 4096
+
+
+def test_batch_rejects_mixed_node_counts_and_bad_sizes():
+    o = binding.make_options("fp64")
+    code, _ = _batch_size([100, 200], [8, 8], [16, 24], o, [False, False])
+    assert code == binding.FEAST_EUNSUPPORTED
+    code, _ = _batch_size([100, 20], [8, 21], [16, 16], o, [False, False])
+    assert code < 0
+    out = ctypes.c_size_t(0)
+    assert fm.lib().feast_batch_workspace_size(0, None, None, None, ctypes.byref(o), None, ctypes.byref(out)) < 0
