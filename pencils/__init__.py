@@ -89,6 +89,47 @@ def clipped_gaussian_basis(rng, n, cond_max=1e3):
     return (Us * s2) @ Wh
 
 
+def gaussian_singular_values(rng, n):
+    """Singular values (descending) of an n x n complex Gaussian matrix (E|g|^2 = 1), drawn without
+    forming it: Householder bidiagonalisation shows that such a matrix has the singular values of
+    the real bidiagonal matrix with diagonal chi_{2(n-i)}/sqrt(2), i = 0..n-1, and superdiagonal
+    chi_{2(n-1-i)}/sqrt(2), i = 0..n-2 (the chi bidiagonal model of Dumitriu and Edelman).  They
+    are the square roots of the eigenvalues of the tridiagonal D^T D."""
+    import scipy.linalg
+    d = np.sqrt(rng.chisquare(2.0 * np.arange(n, 0, -1)) / 2.0)
+    e = np.sqrt(rng.chisquare(2.0 * np.arange(n - 1, 0, -1)) / 2.0) if n > 1 else np.zeros(0)
+    diag = d * d + np.concatenate([[0.0], e * e])
+    w = scipy.linalg.eigvalsh_tridiagonal(diag, d[:-1] * e) if n > 1 else diag
+    return np.sqrt(np.maximum(w, 0.0))[::-1]
+
+
+def haar_unitary(G, xp=np):
+    """Haar-distributed unitary from a complex Gaussian G: Q of G = QR with the phases of diag(R)
+    moved into Q (Mezzadri's construction).  xp is numpy or torch."""
+    Q, R = xp.linalg.qr(G)
+    d = xp.diagonal(R) if xp is np else xp.diagonal(R, 0)
+    ph = d / xp.abs(d)
+    return Q * ph[None, :]
+
+
+def factored_gaussian_basis(rng, n, cond_max=1e3, device=None):
+    """V with the distribution of clipped_gaussian_basis, as factors (U, s, W) with V = U diag(s) W^H
+    and V^-1 = W diag(1/s) U^H: a complex Gaussian matrix is bi-unitarily invariant, so its singular
+    vectors are Haar unitaries independent of its singular values, which are drawn through the chi
+    bidiagonal model.  With device set (a torch device), the QR factorisations run there and U, W are
+    torch tensors."""
+    G1 = complex_gaussian(rng, (n, n))
+    G2 = complex_gaussian(rng, (n, n))
+    s = gaussian_singular_values(rng, n)
+    s = np.maximum(s, s[0] / cond_max)
+    if device is None:
+        return haar_unitary(G1), s, haar_unitary(G2)
+    import torch
+    U = haar_unitary(torch.from_numpy(G1).to(device), torch)
+    W = haar_unitary(torch.from_numpy(G2).to(device), torch)
+    return U, torch.from_numpy(s).to(device=device, dtype=torch.complex128), W
+
+
 @dataclasses.dataclass
 class Pencil:
     """A synthetic pencil with its contour and subspace size.
@@ -183,17 +224,33 @@ def c2_sizes(count: int = 64, seed_cfg: int = 2, n_lo: int = 256, n_hi: int = 20
     return [int(x) for x in ns], [int(x) for x in ms]
 
 
-def c2_pencil(j: int, n: int, m: int, seed_cfg: int = 2, q: int = 16) -> Pencil:
-    """Pencil j of the batched workload: B = I + 0.1 (H + H^H)/(2 sqrt n), A = B V diag(lam) V^-1."""
+def c2_pencil(j: int, n: int, m: int, seed_cfg: int = 2, q: int = 16, device=None) -> Pencil:
+    """Pencil j of the batched workload: B = I + 0.1 (H + H^H)/(2 sqrt n), A = B V diag(lam) V^-1 with
+    V distributed as the clipped complex Gaussian basis (cond <= 1e3), built from its factors so that
+    no SVD or inverse is formed.  With device set (a torch device) the products run there and A, B
+    are column-major complex128 torch tensors on it (same draws, same pencil up to rounding)."""
     rng = np.random.default_rng([base_seed(seed_cfg), j])
     lam = prescribed_spectrum(rng, n, m)
     H = complex_gaussian(rng, (n, n))
-    B = 0.1 * (H + H.conj().T) / (2.0 * math.sqrt(n))
-    B[np.diag_indices(n)] += 1.0
-    B = np.asfortranarray(B)
-    A, _ = prescribed_pencil(rng, n, lam, B=B)
+    U, sv, W = factored_gaussian_basis(rng, n, 1e3, device)
     m0 = 16 if m <= 16 else 32
-    return Pencil(A, B, lam, 0j, 1.0, 1.0, q, m0, m, name=f"c2_{j}_n{n}")
+    if device is None:
+        B = 0.1 * (H + H.conj().T) / (2.0 * math.sqrt(n))
+        B[np.diag_indices(n)] += 1.0
+        Vl = (U * sv) @ (W.conj().T * lam)           # V diag(lam), V = U diag(s) W^H
+        Vinv = (W / sv) @ U.conj().T
+        A = B @ (Vl @ Vinv)
+        return Pencil(np.asfortranarray(A), np.asfortranarray(B), lam, 0j, 1.0, 1.0, q, m0, m, name=f"c2_{j}_n{n}")
+    import torch
+    Ht = torch.from_numpy(H).to(device)
+    B = 0.1 * (Ht + Ht.conj().T) / (2.0 * math.sqrt(n))
+    B.diagonal().add_(1.0)
+    lt = torch.from_numpy(lam).to(device)
+    Vl = (U * sv[None, :]) @ (W.conj().T * lt[None, :])
+    Vinv = (W / sv[None, :]) @ U.conj().T
+    A = B @ (Vl @ Vinv)
+    col = lambda X: X.T.contiguous().T                # column-major storage
+    return Pencil(col(A), col(B), lam, 0j, 1.0, 1.0, q, m0, m, name=f"c2_{j}_n{n}")
 
 
 def c2(count: int = 64, seed_cfg: int = 2, n_lo: int = 256, n_hi: int = 2048):
