@@ -48,6 +48,13 @@ extern "C" {
 
 /* ---- contour and options ------------------------------------------------ */
 typedef enum { FEAST_RULE_TRAPEZOID = 0, FEAST_RULE_GAUSS_LEGENDRE = 1 } feast_rule;
+/* Node factorisations and solves: FEAST_FP64 throughout; FEAST_FP32_IR with
+ * complex64 factorisations and FP64 refinement; FEAST_FP16_IR with complex64
+ * storage and panels but trailing updates on FP16 matrix cores (FP32
+ * accumulation, U12 of every step scaled by a power of two from its largest
+ * component), FP64 refinement, and FP32 factorisations substituted when the
+ * refinement stalls (feast_result.escalated).  The filter is computed to FP64
+ * accuracy in every mode. */
 typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1, FEAST_FP16_IR = 2 } feast_precision;
 typedef enum { FEAST_R = 0, FEAST_BI = 1 } feast_variant;
 
@@ -160,6 +167,7 @@ typedef struct {
     void* Y; int ldy;
     double* history;
     int ir_sweeps;       /* output: refinement sweeps summed over all filters (FP32/FP16 modes) */
+    int escalated;       /* output: 1 if FP16 factorisations were replaced by FP32 ones */
 } feast_result;
 
 int feast_iterate(feast_ctx* ctx, const void* U0, int ldu0, feast_result* result);

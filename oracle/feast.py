@@ -248,13 +248,14 @@ def refinement_threshold(T, Y, rhs, ir_tol=None):
     return ir_tol * (np.linalg.norm(T, 1) * np.linalg.norm(Y) + np.linalg.norm(rhs))
 
 
-def solve_refined(T, rhs, low_dtype=np.complex64, ir_max=10, ir_tol=None):
+def solve_refined(T, rhs, low_dtype=np.complex64, ir_max=10, ir_tol=None, factor=None):
     """Low-precision LU of T, FP64 iterative refinement of T Y = rhs.
 
     Y_0 = solve_low(rhs); repeat R = rhs - T Y (FP64), Y += solve_low(R) until
-    ||R|| is below the threshold, or stops halving, or ir_max sweeps.
+    ||R|| is below the threshold, or stops halving, or ir_max sweeps.  factor(T) may supply the
+    low-precision factorisation in lu_factor layout (default: LAPACK in low_dtype).
     Returns (Y, sweeps, residual norms)."""
-    lu = scipy.linalg.lu_factor(T.astype(low_dtype))
+    lu = factor(T) if factor is not None else scipy.linalg.lu_factor(T.astype(low_dtype))
 
     def solve_low(b):
         return scipy.linalg.lu_solve(lu, b.astype(low_dtype)).astype(np.complex128)

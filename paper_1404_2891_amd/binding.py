@@ -66,7 +66,7 @@ class Result(ctypes.Structure):
                 ("lambda_", ctypes.c_void_p), ("resid", ctypes.c_void_p),
                 ("X", ctypes.c_void_p), ("ldx", ctypes.c_int),
                 ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int), ("history", ctypes.c_void_p),
-                ("ir_sweeps", ctypes.c_int)]
+                ("ir_sweeps", ctypes.c_int), ("escalated", ctypes.c_int)]
 
 
 class FeastError(RuntimeError):
@@ -241,6 +241,7 @@ class IterateResult:
     code: int
     ritz: np.ndarray         # all m0 Ritz values (candidates first)
     ir_sweeps: int = 0       # refinement sweeps summed over the run
+    escalated: bool = False  # FP16 factorisations replaced by FP32 ones
 
 
 class Feast:
@@ -347,7 +348,8 @@ class _ResultBuffers:
         r, m = self.r, self.r.m
         return IterateResult(self.lam[:m].copy(), self.resid[:m].copy(), self.X[:, :m],
                              None if self.Y is None else self.Y[:, :m], r.iterations, bool(r.converged),
-                             self.hist[: r.iterations].copy(), code, self.lam.copy(), r.ir_sweeps)
+                             self.hist[: r.iterations].copy(), code, self.lam.copy(), r.ir_sweeps,
+                             bool(r.escalated))
 
 
 def _ptr_array(values, ctype):

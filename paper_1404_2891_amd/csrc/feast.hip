@@ -99,6 +99,7 @@ struct feast_ctx {
     int ir_sweeps = 0;
     double ir_relres = 0.0;
     long ir_sweeps_total = 0;
+    int escalated = 0;               // FP16 factorisations replaced by FP32 ones
     Timer timer;
 };
 
@@ -130,6 +131,7 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
         c->lu.UinvS = b.take<char>((size_t)q * c->lu.nsbs * NBS * NBS * E);
     }
     c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
+    if (c->prec == Prec::F16) c->lu.amax = b.take<int>(q);
     c->lu_dev = b.take<LUDev>(1);
     c->lu_groups = b.take<GemmGroup>(c->lu_ngroups);
 
@@ -190,12 +192,16 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->lu.spiv = n;
     c->lu.nbs = NBS;
     c->lu.nsbs = ceil_div(n, NBS);
+    c->lu.half = c->prec == Prec::F16;
     // grouped-product members of the factorisation (a count that depends on the dimensions only)
     LUSet one;
     one.s = &c->lu;
     one.count = 1;
     std::vector<GemmGroup> plan;
-    lu_plan<double>(one, plan);
+    if (c->prec == Prec::F64)
+        lu_plan<double>(one, plan);
+    else
+        lu_plan<float>(one, plan);
     c->lu_ngroups = (int)plan.size();
 }
 
@@ -207,7 +213,6 @@ int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
     if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI))
         return -3;
     if (m0 < 1 || m0 > n) return -4;
-    if (o->precision == FEAST_FP16_IR) return FEAST_EUNSUPPORTED;
     return 0;
 }
 
@@ -371,10 +376,28 @@ int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rh
     return 0;
 }
 
+int ctx_factor_enqueue(feast_ctx* c);
+int ctx_check_info(feast_ctx* c);
+
+// FP16 trailing updates leave factorisations that are only about FP16-accurate; when refinement
+// with them stalls (a node system too ill-conditioned for them), the nodes are factored again with
+// FP32 updates and the solve is repeated.
+int escalate(feast_ctx* c) {
+    c->lu.half = false;
+    c->escalated = 1;
+    FM_TRY(ctx_factor_enqueue(c));
+    return ctx_check_info(c);
+}
+
 int apply(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rhs, long ldr, const z64* w, z64* out,
           long ldo, const Shifted* sh = nullptr) {
     if (c->prec == Prec::F64) return apply_nodes<double>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo, sh);
-    return apply_nodes<float>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo, sh);
+    int rc = apply_nodes<float>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo, sh);
+    if (rc == FEAST_EIR && c->lu.half) {
+        FM_TRY(escalate(c));
+        rc = apply_nodes<float>(c, k0, qv, side, ncols, rhs, ldr, w, out, ldo, sh);
+    }
+    return rc;
 }
 
 // out (n x ncols, column-major) = op(B) U, op = N (side 0) or H (side 1)
@@ -944,6 +967,11 @@ int h_conv(Run& r) {
     r.res_last = count ? maxrel : NAN;
     r.count = count;
     r.finishing = r.done || r.it >= c->o.max_iter;
+    // FP16 factorisations too inaccurate for these node systems show as a residual that no longer
+    // halves per iteration: the nodes are factored again with FP32 updates and the run continues
+    if (c->lu.half && !r.finishing && r.it >= 3 && count > 0 && r.res_prev > 0 && std::isfinite(r.res_prev) &&
+        !(r.res_last < 0.5 * r.res_prev))
+        FM_TRY(escalate(c));
     if (r.finishing) {
         r.order.insert(r.order.end(), rest.begin(), rest.end());
         for (int j = 0; j < p; ++j) c->pin.idx[j] = r.order[j];
@@ -981,6 +1009,7 @@ void h_finish(Run& r) {
     }
     r.res->m = r.count;
     r.res->ir_sweeps = (int)c->ir_sweeps_total;
+    r.res->escalated = c->escalated;
     r.res->iterations = r.it;
     r.res->converged = r.done;
     r.rc = r.done ? 0 : FEAST_ENOCONV;

@@ -13,6 +13,7 @@ struct GemmGroup {
     long sA, sB, sC;        // batch strides
     long sA2, sB2, sC2;     // second batch strides
     int M, N, K, batch;
+    int* amax;              // per-batch slots (see GemmOp::amax), or nullptr
 };
 
 // One batched product C_b = alpha_b op(A_b) op(B_b) + beta C_b, b = 0..batch-1.
@@ -36,8 +37,15 @@ struct GemmOp {
     int splitk = 1;
     void* partial = nullptr;
     // kind 1 selects a separate kernel instance (same code) for the LU trailing update, so that
-    // profilers can attribute it
+    // profilers can attribute it.  kind 2 (complex64 operands, all row-major) is the trailing
+    // update on FP16 matrix cores: B_b is scaled by 2^-e, with 2^(e-1) <= amax[b] < 2^e, before its
+    // entries are rounded to FP16 (A's entries are bounded by partial pivoting), products accumulate
+    // in FP32 and the result is scaled back by 2^e, so the scaling itself is exact.
     int kind = 0;
+    // kind 0, complex64: when set, the largest |re|, |im| of the outputs of batch entry b is
+    // merged into amax[b] (bit pattern of a non-negative float, atomic max); the caller zeroes the
+    // slots beforehand.  kind 2: the scale source described above.
+    int* amax = nullptr;
     // grouped product: when groups != nullptr (a device array of ngroups members), each member
     // supplies its own operands, strides, M, N, K and batch, and M, N, K, batch above are the
     // maxima over the members (they size the grid).  Requires splitk == 1 and alpha_b == nullptr.

@@ -7,6 +7,8 @@
 // of depth BK = 16 are staged through LDS as separate real / imaginary planes in k-major
 // order, so the 16 lanes of an MFMA row group read consecutive addresses; the next tile
 // is fetched into registers while the current one is consumed.
+#include <type_traits>
+
 #include "gemm.h"
 
 namespace fm {
@@ -44,6 +46,7 @@ struct Params {
     cplx<T>* partial;
     const GemmGroup* groups;   // grouped product (member = blockIdx.z / (batch * batch2))
     int ngroups;
+    int* amax;
 };
 
 template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC, int KIND>
@@ -68,6 +71,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     long lda = p.lda, ldb = p.ldb, ldc = p.ldc;
     long sA = p.sA, sB = p.sB, sC = p.sC, sA2 = p.sA2, sB2 = p.sB2, sC2 = p.sC2;
     int M = p.M, N = p.N, K = p.K;
+    int* amax = p.amax;
     if (p.groups) {
         // member of a grouped product (splitk == 1): its own operands and sizes; workgroups
         // outside the member's tiles or batch leave at once
@@ -81,6 +85,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
         pA = (const cplx<T>*)g.A; pB = (const cplx<T>*)g.B; pC = (cplx<T>*)g.C;
         lda = g.lda; ldb = g.ldb; ldc = g.ldc;
         sA = g.sA; sB = g.sB; sC = g.sC; sA2 = g.sA2; sB2 = g.sB2; sC2 = g.sC2;
+        amax = g.amax;
     }
     const int kbeg = s * p.kchunk;
     const int kend = p.groups ? K : min(K, kbeg + p.kchunk);
@@ -181,6 +186,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     }
     cplx<T>* __restrict__ C = pC + b * sC + b2 * sC2;
     const bool has_beta = (p.br != T(0) || p.bi != T(0));
+    T omax = T(0);
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -202,7 +208,160 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
                             yi += p.br * o.im + p.bi * o.re;
                         }
                         *cp = cplx<T>(yr, yi);
+                        if (amax) omax = fmax(omax, fmax(fabs(yr), fabs(yi)));
                     }
+                }
+            }
+    if (std::is_same<T, float>::value && amax) {
+        // largest output component of the workgroup, merged into the batch entry's slot
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) omax = fmax(omax, __shfl_xor(omax, o));
+        if (lane == 0) atomicMax(amax + b, __float_as_int((float)omax));
+    }
+}
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+__device__ inline h8 neg8(h8 v) { return -v; }
+
+// Trailing update on FP16 matrix cores (v_mfma_f32_16x16x32_f16): C = beta C + alpha 2^e A (2^-e B)
+// with complex64 row-major operands, FP16 inputs and FP32 accumulation.  A 64 x 64 tile per
+// workgroup, waves 2 x 2 each owning 2 x 2 blocks of 16 x 16, depth 32 per stage.  LDS holds FP16
+// real / imaginary planes with k contiguous, so a lane fetches its 8 consecutive k of one row
+// (A) or column (B) in one 16-byte read: lane l supplies row l % 16, k = 8 (l / 16) .. + 7.
+__global__ __launch_bounds__(256) void cgemm_h16_kernel(Params<float> p) {
+    constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;
+    __shared__ __attribute__((aligned(16))) _Float16 As[2][BM][LDK];
+    __shared__ __attribute__((aligned(16))) _Float16 Bs[2][BN][LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int tm = blockIdx.x % p.tiles_m, tn = blockIdx.x / p.tiles_m;
+    int b = blockIdx.z % p.batch, b2 = blockIdx.z / p.batch;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const cplx<float>* pA = p.A;
+    const cplx<float>* pB = p.B;
+    cplx<float>* pC = p.C;
+    long lda = p.lda, ldb = p.ldb, ldc = p.ldc, sA = p.sA, sB = p.sB, sC = p.sC, sA2 = p.sA2, sB2 = p.sB2,
+         sC2 = p.sC2;
+    int M = p.M, N = p.N, K = p.K;
+    const int* amax = p.amax;
+    if (p.groups) {
+        const int per = p.batch * p.batch2;
+        const GemmGroup& g = p.groups[blockIdx.z / per];
+        b = (blockIdx.z % per) % p.batch;
+        b2 = (blockIdx.z % per) / p.batch;
+        M = g.M; N = g.N; K = g.K;
+        if (b >= g.batch || m0 >= M || n0 >= N) return;
+        pA = (const cplx<float>*)g.A; pB = (const cplx<float>*)g.B; pC = (cplx<float>*)g.C;
+        lda = g.lda; ldb = g.ldb; ldc = g.ldc;
+        sA = g.sA; sB = g.sB; sC = g.sC; sA2 = g.sA2; sB2 = g.sB2; sC2 = g.sC2;
+        amax = g.amax;
+    }
+    if (m0 >= M || n0 >= N) return;
+    const cplx<float>* __restrict__ A = pA + b * sA + b2 * sA2;
+    const cplx<float>* __restrict__ B = pB + b * sB + b2 * sB2;
+    // power-of-two scale of B: 2^(e-1) <= max < 2^e, so the scaled entries lie in (-1, 1)
+    int e = 0;
+    const float mx = amax ? __int_as_float(amax[b]) : 0.0f;
+    if (mx > 0.0f && mx <= 3.0e38f) (void)frexpf(mx, &e);
+    const float sc = ldexpf(1.0f, -e);
+
+    // global -> register mapping: A row ia, k = ka .. ka + 7; B row kb, columns jb .. jb + 7
+    const int ia = tid >> 2, ka = (tid & 3) * 8;
+    const int kb = tid >> 3, jb = (tid & 7) * 8;
+    cplx<float> ra[8], rb[8];
+    auto load = [&](int k0) {
+        const int gi = m0 + ia;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int gk = k0 + ka + u;
+            ra[u] = (gi < M && gk < K) ? A[(long)gi * lda + gk] : cplx<float>(0.0f, 0.0f);
+        }
+        const int gk = k0 + kb;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int gj = n0 + jb + u;
+            rb[u] = (gk < K && gj < N) ? B[(long)gk * ldb + gj] : cplx<float>(0.0f, 0.0f);
+        }
+    };
+    auto store = [&]() {
+        h8 are, aim;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            are[u] = (_Float16)ra[u].re;
+            aim[u] = (_Float16)ra[u].im;
+        }
+        *(h8*)&As[0][ia][ka] = are;
+        *(h8*)&As[1][ia][ka] = aim;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            Bs[0][jb + u][kb] = (_Float16)(rb[u].re * sc);
+            Bs[1][jb + u][kb] = (_Float16)(rb[u].im * sc);
+        }
+    };
+
+    f4 cre[2][2], cim[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            cre[r][c] = f4{0, 0, 0, 0};
+            cim[r][c] = f4{0, 0, 0, 0};
+        }
+    if (K > 0) load(0);
+    const int kq = (lane >> 4) * 8;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + BK < K) load(k0 + BK);
+        h8 are[2], aim[2], nim[2], bre[2], bim[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int i = wm * 32 + r * 16 + (lane & 15);
+            are[r] = *(const h8*)&As[0][i][kq];
+            aim[r] = *(const h8*)&As[1][i][kq];
+            nim[r] = neg8(aim[r]);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int j = wn * 32 + c * 16 + (lane & 15);
+            bre[c] = *(const h8*)&Bs[0][j][kq];
+            bim[c] = *(const h8*)&Bs[1][j][kq];
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(are[r], bre[c], cre[r][c], 0, 0, 0);
+                cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nim[r], bim[c], cre[r][c], 0, 0, 0);
+                cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(are[r], bim[c], cim[r][c], 0, 0, 0);
+                cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aim[r], bre[c], cim[r][c], 0, 0, 0);
+            }
+    }
+    // epilogue: lane l holds column l % 16, rows 4 (l / 16) + v of each block
+    const float post = ldexpf(1.0f, e);
+    const float ar = p.ar * post, ai = p.ai * post;
+    cplx<float>* __restrict__ C = pC + b * sC + b2 * sC2;
+    const bool has_beta = (p.br != 0.0f || p.bi != 0.0f);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = m0 + wm * 32 + r * 16 + 4 * (lane >> 4) + v;
+                const int j = n0 + wn * 32 + c * 16 + (lane & 15);
+                if (i < M && j < N) {
+                    const float xr = cre[r][c][v], xi = cim[r][c][v];
+                    float yr = ar * xr - ai * xi, yi = ar * xi + ai * xr;
+                    cplx<float>* cp = &C[(long)i * ldc + j];
+                    if (has_beta) {
+                        const cplx<float> o = *cp;
+                        yr += p.br * o.re - p.bi * o.im;
+                        yi += p.br * o.im + p.bi * o.re;
+                    }
+                    *cp = cplx<float>(yr, yi);
                 }
             }
 }
@@ -273,10 +432,23 @@ int gemm(const GemmOp& op, hipStream_t st) {
     p.partial = (cplx<T>*)op.partial;
     p.groups = op.groups;
     p.ngroups = op.ngroups;
+    p.amax = op.amax;
     p.tiles_m = 1;
     if (op.groups) {
         if (op.ngroups <= 0) return 0;
         if (p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;
+    }
+    if (op.kind == 2) {  // LU trailing update on FP16 matrix cores (complex64 storage only)
+        if constexpr (std::is_same<T, float>::value) {
+            if (!(op.rowA && op.rowB && op.rowC) || p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;
+            p.tiles_m = ceil_div(p.M, 64);
+            dim3 grid(p.tiles_m * ceil_div(p.N, 64), 1, p.batch * p.batch2 * (p.groups ? p.ngroups : 1));
+            hipLaunchKernelGGL(cgemm_h16_kernel, grid, dim3(256), 0, st, p);
+            FM_LAUNCH_CHECK();
+            return 0;
+        } else {
+            return FEAST_EUNSUPPORTED;
+        }
     }
     if (op.kind == 1) {  // LU trailing update: all operands row-major
         if (!(op.rowA && op.rowB && op.rowC) || p.splitk > 1) return FEAST_EUNSUPPORTED;

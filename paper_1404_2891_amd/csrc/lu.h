@@ -35,6 +35,10 @@ struct LUStore {
     const z64* A = nullptr; long lda = 0;
     const z64* B = nullptr; long ldb = 0;
     const z64* z = nullptr;
+    // FP16 trailing updates (complex64 storage): U12 of each step is scaled by a power of two
+    // taken from its largest component, recorded per node in amax (q ints, see GemmOp::amax)
+    bool half = false;
+    int* amax = nullptr;
 };
 
 // Elements of the LU staging buffer per node: the panel swaps need nb * n, the composition of the
@@ -63,6 +67,7 @@ struct LUDev {
     void* cval; int* crow; void* cdata; void* rowj; int pW;
     void* LinvS; void* UinvS;
     const z64* A; long lda; const z64* B; long ldb; const z64* z;
+    int* amax;
     int n, nsteps, nsbs;
 };
 

@@ -353,6 +353,8 @@ __global__ __launch_bounds__(64) void trtri_kernel(const LUDev* __restrict__ dv,
     const int j0 = s * nb, w = min(nb, n - j0);
     const cplx<T>* F = (const cplx<T>*)d.F + k * d.sF;
     cplx<T>* Inv0 = (cplx<T>*)(UPPER ? d.Uinv : d.Linv);
+    // the U12 scale slot of this node and step starts at zero (the U12 product merges into it)
+    if (!UPPER && d.amax && threadIdx.x == 0) d.amax[k] = 0;
     const int j = threadIdx.x;
     for (int i = 0; i < w; ++i) {
         if (j < w) M[i][j] = F[(long)(j0 + i) * ldf + j0 + j];
@@ -493,8 +495,9 @@ struct SetRun {
 };
 
 GemmGroup member(const void* A, long lda, long sA, long sA2, const void* B, long ldb, long sB, long sB2, void* C,
-                 long ldc, long sC, long sC2, int M, int N, int K, int batch) {
+                 long ldc, long sC, long sC2, int M, int N, int K, int batch, int* amax = nullptr) {
     GemmGroup g;
+    g.amax = amax;
     g.A = A; g.lda = lda; g.sA = sA; g.sA2 = sA2;
     g.B = B; g.ldb = ldb; g.sB = sB; g.sB2 = sB2;
     g.C = C; g.ldc = ldc; g.sC = sC; g.sC2 = sC2;
@@ -608,7 +611,9 @@ int run_set(SetRun<T>& R) {
     const int q = R.q, nb = R.nb, P = S.count;
     if (nb > NBMAX || nb % 16) return FEAST_EUNSUPPORTED;
     for (int b = 0; b < P; ++b)
-        if (S.s[b].q != q || S.s[b].nb != nb || S.s[b].nbs != R.nbs) return FEAST_EUNSUPPORTED;
+        if (S.s[b].q != q || S.s[b].nb != nb || S.s[b].nbs != R.nbs || S.s[b].half != S.s[0].half ||
+            (S.s[b].half && sizeof(T) != sizeof(float)) || (R.launching() && S.s[b].half && !S.s[b].amax))
+            return FEAST_EUNSUPPORTED;
     if (R.launching()) {
         hipLaunchKernelGGL(zero_info, dim3(ceil_div(q, 256), 1, P), dim3(256), 0, R.st, S.dev, q);
         FM_LAUNCH_CHECK();
@@ -631,12 +636,14 @@ int run_set(SetRun<T>& R) {
             swap_cols = std::max(swap_cols, s.n - w);
             if (nr <= 0) continue;
             cplx<T>* F = (cplx<T>*)s.F;
-            // U12 = L_ss^-1 * (swapped rows staged in tmp)
+            // U12 = L_ss^-1 * (swapped rows staged in tmp); with FP16 updates its largest component
+            // per node goes to amax
+            int* amax = s.half ? s.amax : nullptr;
             u12.push_back(member((cplx<T>*)s.Linv + (long)step * nb * nb, nb, (long)s.nsteps * nb * nb, 0, s.tmp, s.n,
-                                 (long)nb * s.n, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0, w, nr, w, q));
+                                 (long)nb * s.n, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0, w, nr, w, q, amax));
             // A22 -= L21 * U12
             upd.push_back(member(F + (long)jn * s.ldf + j0, s.ldf, s.sF, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0,
-                                 F + (long)jn * s.ldf + jn, s.ldf, s.sF, 0, nr, nr, w, q));
+                                 F + (long)jn * s.ldf + jn, s.ldf, s.sF, 0, nr, nr, w, q, amax));
             flops += 8.0 * nr * (double)nr * w * q;
         }
         R.start(PH_LU_OTHER);
@@ -657,7 +664,7 @@ int run_set(SetRun<T>& R) {
         GemmOp up = op;
         up.alpha = z64(-1.0);
         up.beta = z64(1.0);
-        up.kind = 1;
+        up.kind = S.s[0].half ? 2 : 1;
         R.start(PH_LU_UPDATE);
         FM_TRY(R.grouped(upd, up));
         R.stop(PH_LU_UPDATE, flops);
@@ -697,6 +704,7 @@ LUDev lu_dev(const LUStore& s, size_t real_bytes) {
     }
     d.LinvS = s.LinvS; d.UinvS = s.UinvS;
     d.A = s.A; d.lda = s.lda; d.B = s.B; d.ldb = s.ldb; d.z = s.z;
+    d.amax = s.half ? s.amax : nullptr;
     d.n = s.n; d.nsteps = s.nsteps; d.nsbs = s.nsbs;
     return d;
 }
