@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FEAST iterations/s & time-to-1e-10 residual: mixed-prec batched vs FP64"
-PEAK = {"fp64": 78.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X published)
+PEAK = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0}   # dense MFMA TFLOP/s (MI355X published)
 HBM_PEAK = 8000.0                              # GB/s
 
 
@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--mode", default="fp32", choices=["fp32", "fp64", "fp16"])
     ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2"])
     ap.add_argument("--count", type=int, default=64, help="pencils of the batched workload (c2)")
     ap.add_argument("--variant", default=None, choices=["R", "Bi"],
@@ -265,7 +265,7 @@ def main():
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32") if m != args.mode])
+    modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32", "fp16") if m != args.mode])
     out = {}
     for mode in modes:
         steps = args.steps if mode == args.mode else max(1, min(args.steps, 2))
@@ -276,7 +276,7 @@ def main():
         out[mode] = dict(ms_per_step=1e3 * wall / steps, iters_per_s=iters / wall, iterations=results[0].iterations,
                          converged=all(r.converged for r in results), m=len(results[0].lam),
                          max_resid=float(max(r.resid.max() for r in results)), eig_err_vs_oracle=max(errs),
-                         ir_sweeps=results[0].ir_sweeps,
+                         ir_sweeps=results[0].ir_sweeps, escalated_to_fp32=bool(results[0].escalated),
                          phases={k: dict(ms=v["ms"] / steps, launches=v["launches"] // steps,
                                          tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None)
                                  for k, v in phases.items()})
@@ -296,7 +296,8 @@ def main():
         F.iterate(U0)
         ph_all = F.timing()
     dph = ph_all[dom]
-    prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else "fp32"
+    prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else (
+        "fp16" if (args.mode == "fp16" and dom == "lu_update") else "fp32")
     achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12 if dph["ms"] > 0 else 0.0
     roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
                     frac=achieved / PEAK[prec_of_phase], traffic=None, kernel_phase=dom,
@@ -305,6 +306,7 @@ def main():
     lu = ph_all["lu_update"]
     lu_roof = dict(achieved=lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0,
                    peak=PEAK[args.mode], unit="TFLOP/s", avg_launch_ms=lu["ms"] / max(1, lu["launches"]))
+    # (with FP16 updates escalated to FP32 the last factorisation's updates ran in FP32)
     lu_roof["frac"] = lu_roof["achieved"] / lu_roof["peak"]
 
     cpu = None
@@ -319,12 +321,13 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if args.mode == "fp32" else "f64",
+        "dtype": {"fp32": "f32+f64", "fp16": "f16+f32+f64", "fp64": "f64"}[args.mode],
         "data": "synthetic",
         "config": {"workload": f"complex-symmetric generalized pencil n={P.n}, circle c={P.center}, "
                                f"R*={P.radius:.6g} (m={g['m']} inside), q={P.q} trapezoid nodes, m0={P.m0}, "
                                f"{variant}-FEAST, tol 1e-10",
-                   "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
+                   "mode": {"fp32": "FP32 LU + FP64 refinement", "fp16": "FP16-update LU + FP64 refinement",
+                            "fp64": "FP64"}[args.mode],
                    "step": "setup (assembly + q LUs) + iterations to 1e-10"},
         "time_to_1e10_s": head["ms_per_step"] / 1e3,
         "iterations": head["iterations"],

@@ -83,6 +83,11 @@ typedef struct {
                             0 selects sqrt(n) u64 for feast_filter / feast_node_solve and an
                             adaptive target inside feast_iterate                              */
     int timing;          /* 1: record HIP events around every phase launch (see feast_timing_*) */
+    int rank_check;      /* 1: after the first iteration, stop with FEAST_ERANK when the filtered
+                            block has no gap in its singular values (sigma_i / sigma_1 > 1e-6 for
+                            all m0 of them) and at least m0 - 2 Ritz values lie inside C: the
+                            subspace may be smaller than the eigenvalue count (Section 4 asks
+                            m0 >= m); the caller grows m0 and starts again */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */
@@ -168,6 +173,7 @@ typedef struct {
     double* history;
     int ir_sweeps;       /* output: refinement sweeps summed over all filters (FP32/FP16 modes) */
     int escalated;       /* output: 1 if FP16 factorisations were replaced by FP32 ones */
+    int rank;            /* output: numerical rank of the first filtered block (rank_check), else -1 */
 } feast_result;
 
 int feast_iterate(feast_ctx* ctx, const void* U0, int ldu0, feast_result* result);
@@ -202,6 +208,44 @@ int feast_timing_reset(feast_ctx* ctx);
 
 void feast_destroy(feast_ctx* ctx);
 const char* feast_strerror(int code);
+
+/* ---- a10: subspace size from stochastic trace features and a perceptron ------
+ * The filter's trace counts the eigenvalues inside C (Section 3: rho is close to
+ * 1 inside and to 0 outside), and for probe vectors v with E[v v^H] = I,
+ * E[v^H rho(M) v] = trace rho(M).  feast_probe_features applies the context's
+ * filter to the nprobe columns of V (device n x nprobe, column-major; nprobe <=
+ * m0) and writes 2 nprobe + 3 floats to `features` (host): Re, Im of v_j^H
+ * rho(M) v_j for each probe, then Re c, Im c and R of the contour.  The usual
+ * probe context has q = 8 nodes, FEAST_FP16_IR and ir_max = 0.  Synchronous.
+ *
+ * The estimator maps features to a count with a perceptron n_in -> hidden ->
+ * hidden -> 1 (ReLU), parameters (FP32, host, feast_mlp_param_count of them)
+ * in the order W1 (hidden x n_in), b1, W2 (hidden x hidden), b2, W3 (1 x
+ * hidden), b3, matrices row-major.  half = 1 rounds every product's operands to
+ * FP16 (FP32 accumulation), half = 0 keeps FP32.  X: device batch x n_in
+ * row-major FP32 features; t: device targets; y: device outputs.  Inputs are
+ * standardised per column with the moments feast_mlp_fit_standardization
+ * measured (identity until then).  feast_mlp_train_step: forward, mean squared
+ * error, backward and one Adam step with bias correction; loss (host, may be
+ * NULL) receives the batch loss.  feast_mlp_gradients: the gradients (device,
+ * param_count floats) without a step.  All enqueue on `stream`; functions that
+ * return a host value synchronise.  feast_m0_from_estimate: the subspace size
+ * used for an estimated count m: max(8, ceil(1.25 m) + 4) rounded up to a
+ * multiple of 8. */
+int feast_probe_features(feast_ctx* ctx, const void* V, int ldv, int nprobe, float* features);
+typedef struct feast_mlp feast_mlp;
+long feast_mlp_param_count(int n_in, int hidden);
+int feast_mlp_workspace_size(int n_in, int hidden, int max_batch, size_t* bytes);
+int feast_mlp_setup(feast_mlp** mlp, int n_in, int hidden, int max_batch, int half, const float* params,
+                    void* workspace, size_t workspace_bytes, void* stream);
+int feast_mlp_fit_standardization(feast_mlp* mlp, const float* X, int count);
+int feast_mlp_forward(feast_mlp* mlp, const float* X, int batch, float* y);
+int feast_mlp_gradients(feast_mlp* mlp, const float* X, const float* t, int batch, float* grad, double* loss);
+int feast_mlp_train_step(feast_mlp* mlp, const float* X, const float* t, int batch, double lr, double beta1,
+                         double beta2, double eps, double* loss);
+int feast_mlp_get_params(feast_mlp* mlp, float* params);
+int feast_m0_from_estimate(double m_hat);
+void feast_mlp_destroy(feast_mlp* mlp);
 
 /* ---- a9: batches of pencils -------------------------------------------------
  * Many independent pencils, each with its own contour and subspace size (the

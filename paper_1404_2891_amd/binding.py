@@ -39,6 +39,9 @@ EXPORTED = [
     "feast_strerror", "feast_timing_read", "feast_timing_reset",
     "feast_batch_workspace_size", "feast_batch_setup", "feast_batch_member", "feast_batch_iterate",
     "feast_batch_factor_ms", "feast_batch_destroy",
+    "feast_probe_features", "feast_mlp_param_count", "feast_mlp_workspace_size", "feast_mlp_setup",
+    "feast_mlp_fit_standardization", "feast_mlp_forward", "feast_mlp_gradients", "feast_mlp_train_step",
+    "feast_mlp_get_params", "feast_m0_from_estimate", "feast_mlp_destroy",
 ]
 
 
@@ -50,7 +53,7 @@ class Contour(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
-                ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int)]
+                ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int)]
 
 
 class PhaseTime(ctypes.Structure):
@@ -66,7 +69,7 @@ class Result(ctypes.Structure):
                 ("lambda_", ctypes.c_void_p), ("resid", ctypes.c_void_p),
                 ("X", ctypes.c_void_p), ("ldx", ctypes.c_int),
                 ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int), ("history", ctypes.c_void_p),
-                ("ir_sweeps", ctypes.c_int), ("escalated", ctypes.c_int)]
+                ("ir_sweeps", ctypes.c_int), ("escalated", ctypes.c_int), ("rank", ctypes.c_int)]
 
 
 class FeastError(RuntimeError):
@@ -132,6 +135,28 @@ def lib():
         L.feast_batch_factor_ms.restype = i
         L.feast_batch_destroy.argtypes = [vp]
         L.feast_batch_destroy.restype = None
+        L.feast_probe_features.argtypes = [vp, vp, i, i, vp]
+        L.feast_probe_features.restype = i
+        L.feast_mlp_param_count.argtypes = [i, i]
+        L.feast_mlp_param_count.restype = ctypes.c_long
+        L.feast_mlp_workspace_size.argtypes = [i, i, i, ctypes.POINTER(ctypes.c_size_t)]
+        L.feast_mlp_workspace_size.restype = i
+        L.feast_mlp_setup.argtypes = [ctypes.POINTER(vp), i, i, i, i, vp, vp, ctypes.c_size_t, vp]
+        L.feast_mlp_setup.restype = i
+        L.feast_mlp_fit_standardization.argtypes = [vp, vp, i]
+        L.feast_mlp_fit_standardization.restype = i
+        L.feast_mlp_forward.argtypes = [vp, vp, i, vp]
+        L.feast_mlp_forward.restype = i
+        L.feast_mlp_gradients.argtypes = [vp, vp, vp, i, vp, ctypes.POINTER(d)]
+        L.feast_mlp_gradients.restype = i
+        L.feast_mlp_train_step.argtypes = [vp, vp, vp, i, d, d, d, d, ctypes.POINTER(d)]
+        L.feast_mlp_train_step.restype = i
+        L.feast_mlp_get_params.argtypes = [vp, vp]
+        L.feast_mlp_get_params.restype = i
+        L.feast_m0_from_estimate.argtypes = [d]
+        L.feast_m0_from_estimate.restype = i
+        L.feast_mlp_destroy.argtypes = [vp]
+        L.feast_mlp_destroy.restype = None
         _lib = L
     return _lib
 
@@ -152,7 +177,7 @@ def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid") -> C
 
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0, timing=False) -> Options:
+                 ir_tol=0.0, timing=False, rank_check=False) -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -163,6 +188,7 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.ir_max = int(ir_max)
     o.ir_tol = float(ir_tol)
     o.timing = int(bool(timing))
+    o.rank_check = int(bool(rank_check))
     return o
 
 
@@ -242,6 +268,7 @@ class IterateResult:
     ritz: np.ndarray         # all m0 Ritz values (candidates first)
     ir_sweeps: int = 0       # refinement sweeps summed over the run
     escalated: bool = False  # FP16 factorisations replaced by FP32 ones
+    rank: int = -1           # numerical rank of the first filtered block (rank check)
 
 
 class Feast:
@@ -249,14 +276,15 @@ class Feast:
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
-                 timing=False, workspace=None):
+                 timing=False, workspace=None, rank_check=False):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
         self.q = q
         self.A, self.B = A, B
         self.contour = make_contour(center, radius, aspect, q, rule)
-        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing)
+        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
+                                    rank_check)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
         if workspace is not None:
             if workspace.numel() < nbytes or workspace.data_ptr() % 256:
@@ -321,8 +349,16 @@ class Feast:
     def iterate(self, U0) -> IterateResult:
         buf = _ResultBuffers(self.n, self.m0, self.options, U0.device)
         code = lib().feast_iterate(self._ctx, U0.data_ptr(), _ld(U0), ctypes.byref(buf.r))
-        _check(code, "feast_iterate", ok=(FEAST_OK, FEAST_ENOCONV))
+        _check(code, "feast_iterate", ok=(FEAST_OK, FEAST_ENOCONV, FEAST_ERANK))
         return buf.result(code)
+
+    def probe_features(self, V) -> np.ndarray:
+        """Stochastic trace features of this context's filter for the probe block V (device)."""
+        k = V.shape[1]
+        out = np.zeros(2 * k + 3, dtype=np.float32)
+        _check(lib().feast_probe_features(self._ctx, V.data_ptr(), _ld(V), k, out.ctypes.data),
+               "feast_probe_features")
+        return out
 
 
 class _ResultBuffers:
@@ -349,7 +385,7 @@ class _ResultBuffers:
         return IterateResult(self.lam[:m].copy(), self.resid[:m].copy(), self.X[:, :m],
                              None if self.Y is None else self.Y[:, :m], r.iterations, bool(r.converged),
                              self.hist[: r.iterations].copy(), code, self.lam.copy(), r.ir_sweeps,
-                             bool(r.escalated))
+                             bool(r.escalated), r.rank)
 
 
 def _ptr_array(values, ctype):
@@ -364,7 +400,8 @@ class FeastBatch:
     or one tuple for all; m0: list or one int.  All pencils share q, the rule and the options."""
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
-                 variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None):
+                 variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
+                 rank_check=False):
         torch = _torch()
         count = len(pencils)
         self.count = count
@@ -373,7 +410,8 @@ class FeastBatch:
         self.m0 = list(m0) if isinstance(m0, (list, tuple)) else [int(m0)] * count
         if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
             contours = [contours] * count
-        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, False)
+        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, False,
+                                    rank_check)
         C = (Contour * count)(*[make_contour(c, r, a, q, rule) for (c, r, a) in contours])
         self._C = C
         n_arr, n_p = _ptr_array(self.n, ctypes.c_int)
@@ -410,6 +448,15 @@ class FeastBatch:
         _check(lib().feast_batch_factor_ms(self._b, ctypes.byref(out)), "feast_batch_factor_ms")
         return out.value
 
+    def member_probe_features(self, i, V) -> np.ndarray:
+        c = lib().feast_batch_member(self._b, i)
+        if not c:
+            raise IndexError(i)
+        k = V.shape[1]
+        out = np.zeros(2 * k + 3, dtype=np.float32)
+        _check(lib().feast_probe_features(c, V.data_ptr(), _ld(V), k, out.ctypes.data), "feast_probe_features")
+        return out
+
     def member_filter(self, i, U, side=0):
         """feast_filter on pencil i alone."""
         c = lib().feast_batch_member(self._b, i)
@@ -427,7 +474,7 @@ class FeastBatch:
         ld_arr, ld_p = _ptr_array([_ld(U) for U in U0s], ctypes.c_int)
         rcs = np.zeros(self.count, dtype=np.int32)
         code = lib().feast_batch_iterate(self._b, u_p, ld_p, ctypes.cast(res, ctypes.c_void_p), rcs.ctypes.data)
-        _check(code, "feast_batch_iterate", ok=(FEAST_OK, FEAST_ENOCONV))
+        _check(code, "feast_batch_iterate", ok=(FEAST_OK, FEAST_ENOCONV, FEAST_ERANK))
         out = []
         for i, b in enumerate(bufs):
             b.r = res[i]
@@ -450,3 +497,72 @@ class FeastBatch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def m0_from_estimate(m_hat: float) -> int:
+    return int(lib().feast_m0_from_estimate(float(m_hat)))
+
+
+class MLP:
+    """The subspace-size estimator's perceptron on the device (parameters in the oracle's order)."""
+
+    def __init__(self, params: np.ndarray, n_in=19, hidden=256, max_batch=4096, half=True, device="cuda"):
+        torch = _torch()
+        self.n_in, self.hidden, self.max_batch = n_in, hidden, max_batch
+        self.np = int(lib().feast_mlp_param_count(n_in, hidden))
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        if params.size != self.np:
+            raise ValueError(f"expected {self.np} parameters")
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().feast_mlp_workspace_size(n_in, hidden, max_batch, ctypes.byref(nbytes)), "feast_mlp_workspace_size")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        self._m = ctypes.c_void_p(None)
+        _check(lib().feast_mlp_setup(ctypes.byref(self._m), n_in, hidden, max_batch, int(bool(half)),
+                                     params.ctypes.data, self.workspace.data_ptr(), nbytes.value, _stream()),
+               "feast_mlp_setup")
+
+    @staticmethod
+    def _f32(t):
+        torch = _torch()
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError("expected a contiguous float32 tensor")
+        return t.data_ptr()
+
+    def fit_standardization(self, X):
+        _check(lib().feast_mlp_fit_standardization(self._m, self._f32(X), X.shape[0]), "feast_mlp_fit_standardization")
+
+    def forward(self, X):
+        torch = _torch()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(lib().feast_mlp_forward(self._m, self._f32(X), X.shape[0], y.data_ptr()), "feast_mlp_forward")
+        return y
+
+    def gradients(self, X, t):
+        torch = _torch()
+        g = torch.empty(self.np, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_double(0.0)
+        _check(lib().feast_mlp_gradients(self._m, self._f32(X), self._f32(t), X.shape[0], g.data_ptr(),
+                                         ctypes.byref(loss)), "feast_mlp_gradients")
+        return g, loss.value
+
+    def train_step(self, X, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=False):
+        loss = ctypes.c_double(0.0)
+        _check(lib().feast_mlp_train_step(self._m, self._f32(X), self._f32(t), X.shape[0], lr, beta1, beta2, eps,
+                                          ctypes.byref(loss) if want_loss else None), "feast_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.np, dtype=np.float32)
+        _check(lib().feast_mlp_get_params(self._m, out.ctypes.data), "feast_mlp_get_params")
+        return out
+
+    def close(self):
+        if getattr(self, "_m", None) is not None and self._m.value:
+            lib().feast_mlp_destroy(self._m)
+        self._m = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -599,6 +599,7 @@ void feast_default_options(feast_options* o) {
     o->ir_max = 10;
     o->ir_tol = 0.0;
     o->timing = 0;
+    o->rank_check = 0;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -709,6 +710,8 @@ struct Run {
     double res_prev = NAN, res_last = NAN;
     bool done = false;
     int count = 0;
+    int rank = -1;            // numerical rank of the first filtered block (rank check)
+    bool rank_short = false;  // the rank check found the subspace too small
     std::vector<int> order;
     std::vector<double> rel, paper;
     std::vector<cd> lam;
@@ -831,6 +834,17 @@ int h_chol(Run& r, int pass) {
     const int n = c->n, p = c->m0;
     for (int side = 0; side < (is_bi(c) ? 2 : 1); ++side) {
         host::Mat G = to_mat(c->pin.G[side], p), R;
+        if (pass == 0 && side == 0 && r.it == 1 && c->o.rank_check) {
+            // numerical rank of the first filtered block Q: singular values sigma_i with
+            // sigma_i / sigma_1 > 1e-6, i.e. eigenvalues of Q^H Q above 1e-12 of the largest
+            std::vector<cd> ev;
+            host::Mat Wv;
+            if (!host::eig(G, ev, Wv)) return FEAST_EREDUCED;
+            double emax = 0.0;
+            for (const cd& e : ev) emax = std::max(emax, e.real());
+            r.rank = 0;
+            for (const cd& e : ev) r.rank += e.real() > 1e-12 * emax;
+        }
         double tr = 0.0;
         for (int i = 0; i < p; ++i) tr += G(i, i).real();
         if (!(tr > 0.0) || !std::isfinite(tr)) return FEAST_EREDUCED;
@@ -967,6 +981,14 @@ int h_conv(Run& r) {
     r.res_last = count ? maxrel : NAN;
     r.count = count;
     r.finishing = r.done || r.it >= c->o.max_iter;
+    // rank check after the first iteration: no gap in the singular values of the filtered block
+    // and (nearly) every Ritz value inside the contour mean the subspace may be smaller than the
+    // count (the slowly decaying filter keeps eigenvalues just outside above any fixed singular
+    // value threshold, so the rank alone over-reports)
+    if (c->o.rank_check && r.it == 1 && !r.done && r.rank >= p && n_inside >= p - 2) {
+        r.rank_short = true;
+        r.finishing = true;
+    }
     // FP16 factorisations too inaccurate for these node systems show as a residual that no longer
     // halves per iteration: the nodes are factored again with FP32 updates and the run continues
     if (c->lu.half && !r.finishing && r.it >= 3 && count > 0 && r.res_prev > 0 && std::isfinite(r.res_prev) &&
@@ -1010,9 +1032,10 @@ void h_finish(Run& r) {
     r.res->m = r.count;
     r.res->ir_sweeps = (int)c->ir_sweeps_total;
     r.res->escalated = c->escalated;
+    r.res->rank = r.rank;
     r.res->iterations = r.it;
     r.res->converged = r.done;
-    r.rc = r.done ? 0 : FEAST_ENOCONV;
+    r.rc = r.done ? 0 : (r.rank_short ? FEAST_ERANK : FEAST_ENOCONV);
     r.active = false;
 }
 
@@ -1112,6 +1135,64 @@ const char* feast_strerror(int code) {
         case FEAST_EUNSUPPORTED: return "unsupported option";
     }
     return "unknown error";
+}
+
+}  // extern "C"
+
+// ---- stochastic trace features of the filter ---------------------------------------------------
+
+namespace {
+
+// t_j = v_j^H q_j for the columns of two column-major n x k blocks (one workgroup per column)
+__global__ __launch_bounds__(256) void coldot_kernel(const z64* V, long ldv, const z64* Qm, long ldq, int n, z64* out) {
+    const int j = blockIdx.x;
+    __shared__ double sr[256], si[256];
+    double ar = 0.0, ai = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const z64 v = V[i + (long)j * ldv], q = Qm[i + (long)j * ldq];
+        ar += v.re * q.re + v.im * q.im;     // conj(v) q
+        ai += v.re * q.im - v.im * q.re;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sr[threadIdx.x] += sr[threadIdx.x + o];
+            si[threadIdx.x] += si[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = z64(sr[0], si[0]);
+}
+
+}  // namespace
+
+extern "C" {
+
+int feast_probe_features(feast_ctx* c, const void* V, int ldv, int nprobe, float* features) {
+    if (!c) return -1;
+    if (!V) return -2;
+    if (ldv < c->n) return -3;
+    if (nprobe < 1 || nprobe > c->m0) return -4;
+    if (!features) return -5;
+    const int n = c->n;
+    // Q = rho(M) V (the context's filter, nodes and precision)
+    c->ir_target = default_ir_target(c);
+    FM_TRY(filter_impl(c, 0, nprobe, (const z64*)V, ldv, c->QAB, n));
+    z64* t = (z64*)c->norms_d;   // 3 m0 doubles >= 2 nprobe
+    hipLaunchKernelGGL(coldot_kernel, dim3(nprobe), dim3(256), 0, c->st, (const z64*)V, (long)ldv, c->QAB, (long)n, n, t);
+    FM_LAUNCH_CHECK();
+    std::vector<z64> ht(nprobe);
+    FM_TRY(d2h(c, ht.data(), t, nprobe * sizeof(z64)));
+    for (int j = 0; j < nprobe; ++j) {
+        features[2 * j] = (float)ht[j].re;
+        features[2 * j + 1] = (float)ht[j].im;
+    }
+    features[2 * nprobe] = (float)c->C.c_re;
+    features[2 * nprobe + 1] = (float)c->C.c_im;
+    features[2 * nprobe + 2] = (float)c->C.radius;
+    return 0;
 }
 
 }  // extern "C"

@@ -259,9 +259,14 @@ def c2(count: int = 64, seed_cfg: int = 2, n_lo: int = 256, n_hi: int = 2048):
 
 
 def c4_pencil(j: int, n: int = 512, seed_cfg: int = 4, m: Optional[int] = None, q: int = 16,
-              m0: int = 64) -> Pencil:
+              m0: int = 64, basis: Optional[int] = None, device=None) -> Pencil:
     """Pencil j of the learned-m0 workload: lam = c + R mu with mu drawn as in c0 (m inside 0.8,
-    the rest in 1.5 < |mu| < 5), c area-uniform in |c| < 2, R ~ U[0.2, 1.5], m ~ U{0..48}, B = I."""
+    the rest in 1.5 < |mu| < 5), c area-uniform in |c| < 2, R ~ U[0.2, 1.5], m ~ U{0..48}, B = I.
+
+    basis=None draws the eigenvector basis for this pencil alone (clipped complex Gaussian);
+    basis=b takes basis b of a shared pool (c4_basis, distributed the same way), so that large
+    training sets need only their spectra drawn.  With device set (a torch device) A is built there
+    and returned as a column-major complex128 tensor."""
     rng = np.random.default_rng([base_seed(seed_cfg), j])
     if m is None:
         m = int(rng.integers(0, 49))
@@ -269,8 +274,41 @@ def c4_pencil(j: int, n: int = 512, seed_cfg: int = 4, m: Optional[int] = None, 
     R = float(rng.uniform(0.2, 1.5))
     mu = prescribed_spectrum(rng, n, m, min_abs=0.0)
     lam = c + R * mu
-    A, _ = prescribed_pencil(rng, n, lam)
+    if basis is None and device is None:
+        A, _ = prescribed_pencil(rng, n, lam)
+        return Pencil(A, None, lam, c, R, 1.0, q, m0, m, name=f"c4_{j}_n{n}")
+    if basis is None:
+        U, sv, W = factored_gaussian_basis(rng, n, 1e3, device)
+    else:
+        U, sv, W = c4_basis(basis, n, seed_cfg, device)
+    if device is None:
+        A = np.asfortranarray(((U * sv) @ (W.conj().T * lam)) @ ((W / sv) @ U.conj().T))
+    else:
+        import torch
+        lt = torch.from_numpy(lam).to(device)
+        A = ((U * sv[None, :]) @ (W.conj().T * lt[None, :])) @ ((W / sv[None, :]) @ U.conj().T)
+        A = A.T.contiguous().T
     return Pencil(A, None, lam, c, R, 1.0, q, m0, m, name=f"c4_{j}_n{n}")
+
+
+_C4_BASES = {}
+
+
+def c4_basis(b: int, n: int = 512, seed_cfg: int = 4, device=None):
+    """Basis b of the learned-m0 pool as factors (U, s, W), V = U diag(s) W^H (cached per device)."""
+    key = (b, n, seed_cfg, str(device))
+    if key not in _C4_BASES:
+        rng = np.random.default_rng([base_seed(seed_cfg), 3 * 10**6 + b])
+        _C4_BASES[key] = factored_gaussian_basis(rng, n, 1e3, device)
+    return _C4_BASES[key]
+
+
+def c4_split(kind: str, count: int):
+    """Pencil ids and basis ids of the training ("train") or held-out ("eval") pencils: the two
+    sets use disjoint pencil seeds and disjoint basis pools (16 training bases, 4 held-out)."""
+    if kind == "train":
+        return [(j, j % 16) for j in range(count)]
+    return [(10**6 + j, 16 + j % 4) for j in range(count)]
 
 
 def rademacher_complex(rng, shape) -> np.ndarray:

@@ -142,3 +142,14 @@ def test_batch_rejects_mixed_node_counts_and_bad_sizes():
     assert code < 0
     out = ctypes.c_size_t(0)
     assert fm.lib().feast_batch_workspace_size(0, None, None, None, ctypes.byref(o), None, ctypes.byref(out)) < 0
+
+
+def test_m0_rule_and_mlp_sizes():
+    """m0 = max(8, ceil(1.25 m) + 4) rounded up to a multiple of 8; the perceptron 19-256-256-1 has
+    71,425 parameters."""
+    for m_hat, m0 in [(0.0, 8), (-3.0, 8), (2.9, 8), (3.3, 16), (10.0, 24), (48.0, 64), (float("nan"), 8)]:
+        assert fm.m0_from_estimate(m_hat) == m0, (m_hat, m0)
+    assert fm.lib().feast_mlp_param_count(19, 256) == 256 * 19 + 256 + 256 * 256 + 256 + 256 + 1
+    out = ctypes.c_size_t(0)
+    assert fm.lib().feast_mlp_workspace_size(19, 256, 1024, ctypes.byref(out)) == 0
+    assert out.value >= 4 * (4 * 71425 + 4 * 1024 * 256)
