@@ -224,6 +224,112 @@ def bench_batch(args, fm, torch, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_m0(args, fm, torch, dev):
+    """Learned subspace size: probe features (8 Rademacher probes, 8-node FP16 filter) of training
+    pencils, the perceptron trained on their counts, then held-out pencils solved with m0 from
+    (a) the estimator, (b) a fixed m0 = 64, (c) 1.5 x the mean probe trace; every run uses the rank
+    check and doubles m0 on FEAST_ERANK.  Each strategy solves the held-out set as batches (one
+    factorisation graph, lockstep iterations) and is timed end to end, restarts included."""
+    import pencils
+    from oracle import mlp as omlp
+    n, ntr, nev = 512, args.count_train, args.count_eval
+    t0 = time.perf_counter()
+    V = fm.to_device(pencils.probe_block(4, 0, n), dev)
+    tr = [pencils.c4_pencil(j, n, basis=b, device=dev) for j, b in pencils.c4_split("train", ntr)]
+    ev = [pencils.c4_pencil(j, n, basis=b, device=dev) for j, b in pencils.c4_split("eval", nev)]
+    torch.cuda.synchronize()
+    log(f"{ntr} training and {nev} held-out pencils generated in {time.perf_counter() - t0:.1f} s")
+
+    def features(P):
+        out = []
+        for i in range(0, len(P), 128):
+            part = P[i:i + 128]
+            b = fm.FeastBatch([(p.A, None) for p in part], [(p.center, p.radius, 1.0) for p in part], m0=8, q=8,
+                              precision="fp16", ir_max=0)
+            out += [b.member_probe_features(k, V) for k in range(len(part))]
+            b.close()
+        return np.array(out)
+
+    t0 = time.perf_counter()
+    Xtr = features(tr)
+    torch.cuda.synchronize()
+    t_probe = (time.perf_counter() - t0) / ntr
+    Xev = features(ev)
+    log(f"probe features: {1e3 * t_probe:.2f} ms per pencil")
+    net = fm.MLP(omlp.flatten(omlp.init_params(np.random.default_rng(7))), half=True, max_batch=256, device=dev)
+    Xd = torch.from_numpy(Xtr.astype(np.float32)).to(dev)
+    yd = torch.from_numpy(np.array([p.m for p in tr], dtype=np.float32)).to(dev)
+    net.fit_standardization(Xd)
+    rng = np.random.default_rng(8)
+    t0 = time.perf_counter()
+    steps = 0
+    for epoch in range(args.epochs):
+        perm = torch.from_numpy(rng.permutation(ntr)).to(dev)
+        Xp, yp = Xd[perm].contiguous(), yd[perm].contiguous()
+        for b in range(0, ntr - 127, 128):
+            net.train_step(Xp[b:b + 128], yp[b:b + 128], lr=1e-3)
+            steps += 1
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    m_hat = net.forward(torch.from_numpy(Xev.astype(np.float32)).to(dev)).cpu().numpy().astype(np.float64)
+    y_ev = np.array([p.m for p in ev], dtype=np.float64)
+    log(f"training: {steps} Adam steps in {t_train:.1f} s; held-out mean |m_hat - m| = "
+        f"{np.mean(np.abs(m_hat - y_ev)):.2f}")
+    probe_mean = Xev[:, 0:16:2].mean(axis=1)
+    strategies = {
+        "estimator": [fm.m0_from_estimate(x) for x in m_hat],
+        "fixed_64": [64] * nev,
+        "probe_mean_x1.5": [max(8, int(np.ceil(1.5 * max(x, 0.0) / 8.0)) * 8) for x in probe_mean],
+    }
+    out = {}
+    for name, m0s in strategies.items():
+        m0s = list(m0s)
+        todo = list(range(nev))
+        restarts, iters, flops = 0, 0, 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        found = {}
+        while todo:
+            part = [ev[i] for i in todo]
+            b = fm.FeastBatch([(p.A, None) for p in part], [(p.center, p.radius, 1.0) for p in part],
+                              m0=[m0s[i] for i in todo], q=16, precision="fp32", rank_check=True)
+            U0s = [fm.to_device(pencils.start_block(4, n, m0s[i]), dev) for i in todo]
+            res, rcs = b.iterate(U0s)
+            b.close()
+            flops += len(todo) * 16 * (8.0 / 3.0) * n ** 3
+            nxt = []
+            for i, r, rc in zip(todo, res, rcs):
+                iters += r.iterations
+                flops += r.iterations * 8.0 * n * n * m0s[i] * 18
+                if rc == fm.binding.FEAST_ERANK and m0s[i] < n:
+                    m0s[i] = min(2 * m0s[i], n)
+                    restarts += 1
+                    nxt.append(i)
+                else:
+                    found[i] = r
+            todo = nxt
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ok = sum(1 for i, r in found.items() if r.converged and len(r.lam) == ev[i].m)
+        out[name] = dict(ms_per_pencil=1e3 * wall / nev, mean_m0=float(np.mean(m0s)), restarts=restarts,
+                         iterations=iters, gflop_per_pencil=flops / nev / 1e9, correct=ok)
+        log(f"{name}: {out[name]}")
+    line = {
+        "metric": "learned m0: FEAST time and work per held-out pencil (estimator vs fixed m0 and probe-mean rule)",
+        "value": out["fixed_64"]["ms_per_pencil"] / out["estimator"]["ms_per_pencil"],
+        "unit": "x (time per pencil, fixed m0 = 64 / estimator m0)",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f16 probes + f16/f32 MLP + f32+f64",
+        "config": {"workload": f"{ntr} training / {nev} held-out pencils, n={n}, B=I, random circles, "
+                               f"m ~ U{{0..48}}; probes: 8 Rademacher vectors, 8 nodes, FP16 updates; "
+                               f"MLP 19-256-256-1, {args.epochs} epochs; FEAST q=16 FP32+IR with rank check"},
+        "probe_ms_per_pencil": 1e3 * t_probe, "train_s": t_train,
+        "heldout_mean_abs_err": float(np.mean(np.abs(m_hat - y_ev))),
+        "heldout_rmse": float(np.sqrt(np.mean((m_hat - y_ev) ** 2))),
+        "strategies": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def pencils_start(p, j):
     import pencils
     return pencils.start_block(2, p.n, p.m0, salt=10**6 + j)
@@ -235,7 +341,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="fp32", choices=["fp32", "fp64", "fp16"])
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2", "c4"])
+    ap.add_argument("--count-train", type=int, default=4096, help="training pencils of the learned-m0 workload")
+    ap.add_argument("--count-eval", type=int, default=256, help="held-out pencils of the learned-m0 workload")
+    ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--count", type=int, default=64, help="pencils of the batched workload (c2)")
     ap.add_argument("--variant", default=None, choices=["R", "Bi"],
                     help="R-FEAST (default for the n=4096 workload) or Bi-FEAST (default for n=8192)")
@@ -253,6 +362,9 @@ def main():
     dev = "cuda:0"
     if args.workload == "c2":
         bench_batch(args, fm, torch, dev)
+        return
+    if args.workload == "c4":
+        bench_m0(args, fm, torch, dev)
         return
     variant = args.variant or ("Bi" if args.workload == "c3" else "R")
     P, U0h, ref, g = load_workload(args.workload)
