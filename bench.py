@@ -136,6 +136,16 @@ def load_batch(count=64, device=None):
     return [pencils.c2_pencil(j, ns[j], ms[j], device=device) for j in range(count)]
 
 
+def tune_panels(fm, q, modes, dev):
+    """Panel crossover for each storage precision in use (outside the timed region)."""
+    out = {}
+    for mode in sorted({("fp64" if m == "fp64" else "fp32") for m in modes}):
+        rows, table = fm.autotune(mode, q, device=dev)
+        out[mode] = dict(single_rows=rows, table=[[int(r), round(a, 4), round(b, 4)] for r, a, b in table])
+        log(f"panel tuning {mode}, q={q}: sweeping panel up to {rows} rows")
+    return out
+
+
 def bench_batch(args, fm, torch, dev):
     """Batched pencils: one graph launch factors every node of every pencil, then all pencils iterate
     in lockstep; timed beside the same pencils solved one at a time."""
@@ -176,6 +186,7 @@ def bench_batch(args, fm, torch, dev):
         return max(match_err(r.lam, ref) for r, ref in zip(res, refs))
 
     modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32") if m != args.mode])
+    tuning = tune_panels(fm, 16, modes, dev)
     out = {}
     for mode in modes:
         for _ in range(args.warmup):
@@ -216,6 +227,7 @@ def bench_batch(args, fm, torch, dev):
         "time_to_1e10_s": head["ms_per_step"] / 1e3,
         "eig_err_vs_oracle": head["eig_err_vs_oracle"],
         "batched_speedup_vs_one_at_a_time": head["batched_speedup"],
+        "panel_tuning": tuning,
         "speedup_vs_fp64": (out["fp64"]["ms_per_step"] / head["ms_per_step"]) if "fp64" in out else None,
         "modes": out,
         "roofline": roofline,
@@ -245,11 +257,13 @@ def bench_m0(args, fm, torch, dev):
         for i in range(0, len(P), 128):
             part = P[i:i + 128]
             b = fm.FeastBatch([(p.A, None) for p in part], [(p.center, p.radius, 1.0) for p in part], m0=8, q=8,
-                              precision="fp16", ir_max=0)
+                              precision=args.probe_precision, ir_max=0)
             out += [b.member_probe_features(k, V) for k in range(len(part))]
             b.close()
         return np.array(out)
 
+    tune_panels(fm, 8, ["fp32"], dev)
+    tune_panels(fm, 16, ["fp32"], dev)
     t0 = time.perf_counter()
     Xtr = features(tr)
     torch.cuda.synchronize()
@@ -320,7 +334,7 @@ def bench_m0(args, fm, torch, dev):
         "unit": "x (time per pencil, fixed m0 = 64 / estimator m0)",
         "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f16 probes + f16/f32 MLP + f32+f64",
         "config": {"workload": f"{ntr} training / {nev} held-out pencils, n={n}, B=I, random circles, "
-                               f"m ~ U{{0..48}}; probes: 8 Rademacher vectors, 8 nodes, FP16 updates; "
+                               f"m ~ U{{0..48}}; probes: 8 Rademacher vectors, 8 nodes, {args.probe_precision} LU; "
                                f"MLP 19-256-256-1, {args.epochs} epochs; FEAST q=16 FP32+IR with rank check"},
         "probe_ms_per_pencil": 1e3 * t_probe, "train_s": t_train,
         "heldout_mean_abs_err": float(np.mean(np.abs(m_hat - y_ev))),
@@ -345,6 +359,8 @@ def main():
     ap.add_argument("--count-train", type=int, default=4096, help="training pencils of the learned-m0 workload")
     ap.add_argument("--count-eval", type=int, default=256, help="held-out pencils of the learned-m0 workload")
     ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--probe-precision", default="fp32", choices=["fp32", "fp16"],
+                    help="factorisations of the 8-node probe filter of the learned-m0 workload")
     ap.add_argument("--count", type=int, default=64, help="pencils of the batched workload (c2)")
     ap.add_argument("--variant", default=None, choices=["R", "Bi"],
                     help="R-FEAST (default for the n=4096 workload) or Bi-FEAST (default for n=8192)")
@@ -378,6 +394,7 @@ def main():
     torch.cuda.synchronize()
 
     modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32", "fp16") if m != args.mode])
+    tuning = tune_panels(fm, P.q, modes, dev)
     out = {}
     for mode in modes:
         steps = args.steps if mode == args.mode else max(1, min(args.steps, 2))
@@ -448,6 +465,7 @@ def main():
         "speedup_vs_fp64": (out["fp64"]["ms_per_step"] / head["ms_per_step"]) if "fp64" in out else None,
         "roofline": roofline,
         "lu_update_roofline": lu_roof,
+        "panel_tuning": tuning,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -88,6 +88,11 @@ typedef struct {
                             all m0 of them) and at least m0 - 2 Ritz values lie inside C: the
                             subspace may be smaller than the eigenvalue count (Section 4 asks
                             m0 >= m); the caller grows m0 and starts again */
+    int pivoting;        /* row pivoting of the node factorisations: 0 (default) tournament
+                            pivoting of panels taller than the register panel (candidate rows
+                            chosen by partial-pivoting LUs of row blocks and a reduction tree,
+                            as in communication-avoiding LU; a few launches per panel), 1 exact
+                            partial pivoting (one launch per column, LAPACK's pivots) */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */
@@ -116,6 +121,7 @@ typedef struct feast_ctx feast_ctx;
  * The factorisations stay resident in the workspace for the life of the
  * context: each node system is factored once for the whole run (Section 5.5).
  * A and B must stay valid and unchanged until feast_destroy.
+ * Pivots: see feast_options.pivoting.
  * Synchronises the stream once to read the zero-pivot flags.
  * Returns 0, -i for invalid arguments, FEAST_ESINGULAR + k, FEAST_EWORKSPACE,
  * FEAST_EDEVICE. */
@@ -208,6 +214,26 @@ int feast_timing_reset(feast_ctx* ctx);
 
 void feast_destroy(feast_ctx* ctx);
 const char* feast_strerror(int code);
+
+/* ---- panel tuning -----------------------------------------------------------
+ * Panels of n - j0 rows run as one of three kernels: the register panel (the
+ * whole panel in one workgroup's registers, up to 128 rows in FP64 and 256 in
+ * FP32), a single-workgroup panel that sweeps the rows from memory once per
+ * column (one launch per panel), or the multi-workgroup panel (one launch per
+ * column).  The sweep-or-multi crossover depends on the precision and on q.
+ * feast_autotune times both on synthetic q-node panels of 256 .. 6144 rows
+ * and keeps the largest row count at which the sweep is no slower; the result
+ * applies to contexts and batches set up afterwards in this process and is
+ * written to cache_path (may be NULL) as "precision q rows" lines, which the
+ * library reads at first use from the file named by FEAST_TUNE_CACHE.  times
+ * (may be NULL) receives 10 triples (rows, sweep ms, multi ms).  Workspace:
+ * feast_autotune_workspace_size bytes (device).  Synchronous.  Every variant
+ * gives the same factorisation (same operations in the same order), so tuning
+ * changes time only.  feast_set_panel_rows sets an entry directly. */
+int feast_autotune_workspace_size(int q, int precision, size_t* bytes);
+int feast_autotune(int precision, int q, void* workspace, size_t workspace_bytes, void* stream,
+                   const char* cache_path, int* single_rows, double* times);
+int feast_set_panel_rows(int precision, int q, int single_rows);
 
 /* ---- a10: subspace size from stochastic trace features and a perceptron ------
  * The filter's trace counts the eigenvalues inside C (Section 3: rho is close to

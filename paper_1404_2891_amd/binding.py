@@ -42,6 +42,7 @@ EXPORTED = [
     "feast_probe_features", "feast_mlp_param_count", "feast_mlp_workspace_size", "feast_mlp_setup",
     "feast_mlp_fit_standardization", "feast_mlp_forward", "feast_mlp_gradients", "feast_mlp_train_step",
     "feast_mlp_get_params", "feast_m0_from_estimate", "feast_mlp_destroy",
+    "feast_autotune_workspace_size", "feast_autotune", "feast_set_panel_rows",
 ]
 
 
@@ -53,7 +54,8 @@ class Contour(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
-                ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int)]
+                ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int),
+                ("pivoting", ctypes.c_int)]
 
 
 class PhaseTime(ctypes.Structure):
@@ -157,6 +159,12 @@ def lib():
         L.feast_m0_from_estimate.restype = i
         L.feast_mlp_destroy.argtypes = [vp]
         L.feast_mlp_destroy.restype = None
+        L.feast_autotune_workspace_size.argtypes = [i, i, ctypes.POINTER(ctypes.c_size_t)]
+        L.feast_autotune_workspace_size.restype = i
+        L.feast_autotune.argtypes = [i, i, vp, ctypes.c_size_t, vp, ctypes.c_char_p, ctypes.POINTER(i), vp]
+        L.feast_autotune.restype = i
+        L.feast_set_panel_rows.argtypes = [i, i, i]
+        L.feast_set_panel_rows.restype = i
         _lib = L
     return _lib
 
@@ -176,8 +184,11 @@ def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid") -> C
     return Contour(center.real, center.imag, float(radius), float(aspect), int(q), RULES[rule])
 
 
+PIVOTING = {"tournament": 0, "partial": 1}
+
+
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0, timing=False, rank_check=False) -> Options:
+                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament") -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -189,6 +200,7 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.ir_tol = float(ir_tol)
     o.timing = int(bool(timing))
     o.rank_check = int(bool(rank_check))
+    o.pivoting = PIVOTING[pivoting]
     return o
 
 
@@ -276,7 +288,7 @@ class Feast:
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
-                 timing=False, workspace=None, rank_check=False):
+                 timing=False, workspace=None, rank_check=False, pivoting="tournament"):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
@@ -284,7 +296,7 @@ class Feast:
         self.A, self.B = A, B
         self.contour = make_contour(center, radius, aspect, q, rule)
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check)
+                                    rank_check, pivoting)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
         if workspace is not None:
             if workspace.numel() < nbytes or workspace.data_ptr() % 256:
@@ -401,7 +413,7 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False):
+                 rank_check=False, pivoting="tournament"):
         torch = _torch()
         count = len(pencils)
         self.count = count
@@ -411,7 +423,7 @@ class FeastBatch:
         if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
             contours = [contours] * count
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, False,
-                                    rank_check)
+                                    rank_check, pivoting)
         C = (Contour * count)(*[make_contour(c, r, a, q, rule) for (c, r, a) in contours])
         self._C = C
         n_arr, n_p = _ptr_array(self.n, ctypes.c_int)
@@ -566,3 +578,23 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def autotune(precision="fp32", q=16, cache_path=None, device="cuda"):
+    """Measure the sweeping/multi-workgroup panel crossover for (precision, q); returns
+    (single_rows, table of (rows, sweep ms, multi ms))."""
+    torch = _torch()
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().feast_autotune_workspace_size(q, PRECISIONS[precision], ctypes.byref(nbytes)),
+           "feast_autotune_workspace_size")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+    rows = ctypes.c_int(0)
+    times = np.zeros(30)
+    _check(lib().feast_autotune(PRECISIONS[precision], q, ws.data_ptr(), nbytes.value, _stream(),
+                                None if cache_path is None else str(cache_path).encode(), ctypes.byref(rows),
+                                times.ctypes.data), "feast_autotune")
+    return rows.value, times.reshape(10, 3)
+
+
+def set_panel_rows(precision, q, rows):
+    _check(lib().feast_set_panel_rows(PRECISIONS[precision], q, int(rows)), "feast_set_panel_rows")

@@ -12,7 +12,11 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -132,6 +136,10 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     }
     c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
     if (c->prec == Prec::F16) c->lu.amax = b.take<int>(q);
+    if (n > lu_reg_panel_rows(c->prec == Prec::F64)) {
+        c->lu.tcand = b.take<int>(tslu_cand_ints(n, q, c->prec == Prec::F64));
+        c->lu.ttop = b.take<char>((size_t)q * NB * NB * E);
+    }
     c->lu_dev = b.take<LUDev>(1);
     c->lu_groups = b.take<GemmGroup>(c->lu_ngroups);
 
@@ -193,6 +201,8 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->lu.nbs = NBS;
     c->lu.nsbs = ceil_div(n, NBS);
     c->lu.half = c->prec == Prec::F16;
+    c->lu.tslu = o->pivoting == 0;
+    c->lu.tW0 = tslu_leaf_blocks(n, c->prec == Prec::F64);
     // grouped-product members of the factorisation (a count that depends on the dimensions only)
     LUSet one;
     one.s = &c->lu;
@@ -210,7 +220,8 @@ int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
     if (!C || C->q < 2 || C->q % 2 || !(C->radius > 0) || !(C->aspect > 0) ||
         (C->rule != FEAST_RULE_TRAPEZOID && C->rule != FEAST_RULE_GAUSS_LEGENDRE))
         return -2;
-    if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI))
+    if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI) ||
+        o->pivoting < 0 || o->pivoting > 1)
         return -3;
     if (m0 < 1 || m0 > n) return -4;
     return 0;
@@ -369,6 +380,9 @@ int apply_nodes(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rh
         }
         if (n_active == 0) break;
     }
+    // FP16 factorisations must reach the target (otherwise the nodes are factored again in FP32,
+    // see escalate); FP32 ones are accepted once the correction is below 1e-6 of the solution
+    if (c->lu.half && worst > 1e3 * fwd_tol) stalled = true;
     c->ir_sweeps = sweep;
     c->ir_relres = worst;
     FM_TRY(accumulate<double>(out, ldo, Y64, n, ncols, qv, nullptr, v.spiv, w, st));
@@ -463,6 +477,56 @@ int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* 
     return rc;
 }
 
+// ---- panel tuning --------------------------------------------------------------------------------
+//
+// The crossover between the single-workgroup sweeping panel and the multi-workgroup panel depends
+// on the precision and on how many node panels run side by side (q); feast_autotune measures it and
+// records "precision q rows" lines in a cache file (FEAST_TUNE_CACHE names it), read once per
+// process.  Without an entry the default below applies.
+
+constexpr int DEFAULT_SINGLE_ROWS = 1024;
+
+struct TuneTable {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::pair<int, int>, int> rows;   // (precision, q) -> single_rows
+};
+
+TuneTable& tune_table() {
+    static TuneTable t;
+    return t;
+}
+
+int storage_precision(Prec p) { return p == Prec::F64 ? FEAST_FP64 : FEAST_FP32_IR; }
+
+void tune_load_locked(TuneTable& t) {
+    if (t.loaded) return;
+    t.loaded = true;
+    const char* path = std::getenv("FEAST_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    int prec, q, rows;
+    while (f >> prec >> q >> rows)
+        if (rows > 0) t.rows[{prec, q}] = rows;
+}
+
+int tuned_single_rows(Prec p, int q) {
+    TuneTable& t = tune_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    tune_load_locked(t);
+    const int prec = storage_precision(p);
+    auto it = t.rows.find({prec, q});
+    if (it != t.rows.end()) return it->second;
+    // nearest q measured for this precision
+    int best = DEFAULT_SINGLE_ROWS, dist = 1 << 30;
+    for (const auto& e : t.rows)
+        if (e.first.first == prec && std::abs(e.first.second - q) < dist) {
+            dist = std::abs(e.first.second - q);
+            best = e.second;
+        }
+    return best;
+}
+
 // ---- context creation (host), factorisation (enqueue only) and the zero-pivot check ----------
 
 // The factorisation of this pencil alone, as a set of one.
@@ -473,6 +537,7 @@ LUSet ctx_set(feast_ctx* c) {
     one.dev = c->lu_dev;
     one.groups = c->lu_groups;
     one.timer = c->lu.timer;
+    one.single_rows = tuned_single_rows(c->prec, c->q);
     return one;
 }
 
@@ -600,6 +665,7 @@ void feast_default_options(feast_options* o) {
     o->ir_tol = 0.0;
     o->timing = 0;
     o->rank_check = 0;
+    o->pivoting = 0;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -1349,6 +1415,7 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         S.count = count;
         S.dev = bt->dev;
         S.groups = bt->groups;
+        S.single_rows = tuned_single_rows(bt->prec, C[0].q);
         std::vector<GemmGroup> plan;
         if (bt->prec == Prec::F64)
             lu_plan<double>(S, plan);
@@ -1437,5 +1504,147 @@ int feast_batch_iterate(feast_batch* bt, const void* const* U0, const int* ldu0,
 }
 
 void feast_batch_destroy(feast_batch* bt) { batch_free(bt); }
+
+}  // extern "C"
+
+// ---- panel autotuning ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int TUNE_ROWS[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144};
+constexpr int TUNE_MAX_ROWS = 6144;
+
+struct TuneLayout {
+    size_t F, ipiv, info, slots, dev, total;
+};
+
+TuneLayout tune_layout(int q, bool dbl) {
+    const size_t E = dbl ? sizeof(z64) : sizeof(c32);
+    TuneLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, ALIGN);
+        return at;
+    };
+    L.F = take((size_t)q * TUNE_MAX_ROWS * NB * E);
+    L.ipiv = take((size_t)q * TUNE_MAX_ROWS * sizeof(int));
+    L.info = take((size_t)q * sizeof(int));
+    L.slots = take(panel_slot_bytes(TUNE_MAX_ROWS, q, NB, E / 2, nullptr));
+    L.dev = take(sizeof(LUDev));
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+int tune_panel(int q, char* ws, hipStream_t st, std::vector<double>& t_single, std::vector<double>& t_multi) {
+    const bool dbl = std::is_same<T, double>::value;
+    const TuneLayout L = tune_layout(q, dbl);
+    hipEvent_t e0, e1;
+    FM_HIP(hipEventCreate(&e0));
+    FM_HIP(hipEventCreate(&e1));
+    int rc = 0;
+    for (int rows : TUNE_ROWS) {
+        // an n x 64 matrix per node (the panel columns only), ldf = 64
+        LUStore s;
+        s.F = ws + L.F; s.ldf = NB; s.sF = (long)rows * NB;
+        s.ipiv = (int*)(ws + L.ipiv); s.spiv = rows;
+        s.info = (int*)(ws + L.info);
+        s.n = rows; s.q = q; s.nb = NB; s.nsteps = 1; s.nbs = NBS; s.nsbs = 1;
+        s.pslots = ws + L.slots;
+        (void)panel_slot_bytes(rows, q, NB, sizeof(T), &s.pW);
+        const LUDev d = lu_dev(s, sizeof(T));
+        if (hipMemcpyAsync(ws + L.dev, &d, sizeof(LUDev), hipMemcpyHostToDevice, st) != hipSuccess) rc = FEAST_EDEVICE;
+        LUSet S;
+        S.s = &s;
+        S.count = 1;
+        S.dev = (LUDev*)(ws + L.dev);
+        S.groups = nullptr;
+        double best[2] = {1e30, 1e30};
+        for (int variant = 0; variant < 2 && !rc; ++variant) {
+            S.single_rows = variant == 0 ? (1 << 30) : 0;   // all sweeping / all multi-workgroup
+            for (int rep = 0; rep < 3 && !rc; ++rep) {
+                rc = lu_fill_random(s.F, (long)q * rows * NB * 2, dbl, 1234 + rep, st);
+                float ms = 0.0f;
+                if (!rc && (hipEventRecord(e0, st) != hipSuccess)) rc = FEAST_EDEVICE;
+                if (!rc) rc = lu_panel_only<T>(S, 0, st);
+                if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = FEAST_EDEVICE;
+                if (!rc) best[variant] = std::min(best[variant], (double)ms);
+            }
+        }
+        t_single.push_back(best[0]);
+        t_multi.push_back(best[1]);
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int feast_autotune_workspace_size(int q, int precision, size_t* bytes) {
+    if (q < 1) return -1;
+    if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -2;
+    if (!bytes) return -3;
+    *bytes = tune_layout(q, precision == FEAST_FP64).total;
+    return 0;
+}
+
+int feast_autotune(int precision, int q, void* workspace, size_t workspace_bytes, void* stream, const char* cache_path,
+                   int* single_rows, double* times) {
+    if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -1;
+    if (q < 1) return -2;
+    const bool dbl = precision == FEAST_FP64;
+    if (!workspace || ((uintptr_t)workspace % ALIGN) || workspace_bytes < tune_layout(q, dbl).total)
+        return FEAST_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> ts, tm;
+    FM_TRY(dbl ? tune_panel<double>(q, (char*)workspace, st, ts, tm) : tune_panel<float>(q, (char*)workspace, st, ts, tm));
+    // largest measured row count up to which the sweeping panel is no slower (rows beyond the
+    // register panel's reach only)
+    int rows = lu_reg_panel_rows(dbl);
+    for (size_t i = 0; i < ts.size(); ++i) {
+        if (ts[i] <= tm[i])
+            rows = TUNE_ROWS[i];
+        else
+            break;
+    }
+    const int prec = dbl ? FEAST_FP64 : FEAST_FP32_IR;
+    {
+        TuneTable& t = tune_table();
+        std::lock_guard<std::mutex> lock(t.mu);
+        tune_load_locked(t);
+        t.rows[{prec, q}] = rows;
+        if (cache_path) {
+            std::ofstream f(cache_path, std::ios::trunc);
+            for (const auto& e : t.rows) f << e.first.first << " " << e.first.second << " " << e.second << "\n";
+            if (!f) return FEAST_EDEVICE;
+        }
+    }
+    if (single_rows) *single_rows = rows;
+    if (times)
+        for (size_t i = 0; i < ts.size(); ++i) {
+            times[3 * i] = TUNE_ROWS[i];
+            times[3 * i + 1] = ts[i];
+            times[3 * i + 2] = tm[i];
+        }
+    return 0;
+}
+
+int feast_set_panel_rows(int precision, int q, int single_rows) {
+    if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -1;
+    if (q < 1) return -2;
+    if (single_rows < 0) return -3;
+    TuneTable& t = tune_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    tune_load_locked(t);
+    t.rows[{precision == FEAST_FP64 ? FEAST_FP64 : FEAST_FP32_IR, q}] = single_rows;
+    return 0;
+}
 
 }  // extern "C"

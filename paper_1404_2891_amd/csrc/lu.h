@@ -39,7 +39,18 @@ struct LUStore {
     // taken from its largest component, recorded per node in amax (q ints, see GemmOp::amax)
     bool half = false;
     int* amax = nullptr;
+    // tournament pivoting of tall panels (tslu): candidate row lists, q x (2 tW0 64 + 64) ints
+    // (two levels of the reduction tree and the final winners), and the root's factored rows,
+    // q x nb x nb elements; tW0 = blocks of the widest leaf level
+    bool tslu = false;
+    int* tcand = nullptr;
+    void* ttop = nullptr;
+    int tW0 = 0;
 };
+
+// Leaf blocks of the tournament for panels of up to n rows (rows per leaf = register panel rows).
+inline int tslu_leaf_blocks(int n, bool dbl) { return (n + (dbl ? 128 : 256) - 1) / (dbl ? 128 : 256); }
+inline size_t tslu_cand_ints(int n, int q, bool dbl) { return (size_t)q * (2 * (size_t)tslu_leaf_blocks(n, dbl) * 64 + 64); }
 
 // Elements of the LU staging buffer per node: the panel swaps need nb * n, the composition of the
 // solve-block inverses 128 * 128 per solve block.
@@ -68,6 +79,7 @@ struct LUDev {
     void* LinvS; void* UinvS;
     const z64* A; long lda; const z64* B; long ldb; const z64* z;
     int* amax;
+    int* tcand; void* ttop; int tW0; int tslu;
     int n, nsteps, nsbs;
 };
 
@@ -82,6 +94,9 @@ struct LUSet {
     LUDev* dev = nullptr;
     GemmGroup* groups = nullptr;
     Timer* timer = nullptr;
+    // panels with more rows than the register panel holds and at most this many use the
+    // single-workgroup sweeping panel, taller ones the multi-workgroup panel (see lu_tuned_rows)
+    int single_rows = PANEL_ROWS;
 };
 
 // Descriptor of one member (real_bytes: 4 or 8, the precision of the storage).
@@ -99,5 +114,15 @@ void lu_plan(const LUSet& S, std::vector<GemmGroup>& out);
 // no memory set or copy calls (the sequence can be captured into a graph).
 template <typename T>
 int lu_factor_set(const LUSet& S, hipStream_t st);
+
+// Panel factorisation of step j0 alone for every member (the tuning runs time it).
+template <typename T>
+int lu_panel_only(const LUSet& S, int j0, hipStream_t st);
+
+// Fills `reals` FP64 (dbl) or FP32 values with deterministic pseudo-random numbers in [-0.5, 0.5).
+int lu_fill_random(void* p, long reals, bool dbl, unsigned long long seed, hipStream_t st);
+
+// Rows the register panel holds (128 in FP64, 256 in FP32).
+int lu_reg_panel_rows(bool dbl);
 
 }  // namespace fm

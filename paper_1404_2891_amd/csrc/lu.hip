@@ -60,9 +60,30 @@ __global__ __launch_bounds__(256) void assemble_kernel(const LUDev* __restrict__
 // Step (j0, w) of member d: w = min(nb, n - j0), or 0 when the member has no such step.
 __device__ inline int step_width(const LUDev& d, int j0, int nb) { return d.n > j0 ? min(nb, d.n - j0) : 0; }
 
-// The single-workgroup panel serves the trailing rows of at most PANEL_ROWS rows, the
-// multi-workgroup one the taller panels.
-__device__ inline bool multi_panel(const LUDev& d, int j0) { return d.cval != nullptr && d.n - j0 > PANEL_ROWS; }
+// Panel variants, by the number of rows n - j0 left: the register panel up to REG_ROWS<T> rows (one
+// workgroup, the whole panel in registers), the single-workgroup sweeping panel up to `single`
+// rows (tuned: it re-reads the panel from memory per column but needs one launch), and above that
+// the multi-workgroup panel (one launch per column).
+enum PanelVariant { PV_NONE = 0, PV_REG = 1, PV_SINGLE = 2, PV_MULTI = 3, PV_TSLU = 4 };
+
+template <typename T> struct RegPanel;
+template <> struct RegPanel<double> { static constexpr int U = 32; };   // 128 rows, 128 VGPRs of data
+template <> struct RegPanel<float> { static constexpr int U = 64; };    // 256 rows, 128 VGPRs of data
+
+template <typename T>
+__host__ __device__ inline int panel_variant(int n, int j0, bool has_slots, int single, bool tslu = false) {
+    const int rows = n - j0;
+    if (rows <= 0) return PV_NONE;
+    if (rows <= 4 * RegPanel<T>::U) return PV_REG;
+    if (tslu) return PV_TSLU;
+    if (rows <= single || !has_slots) return PV_SINGLE;
+    return PV_MULTI;
+}
+
+template <typename T>
+__device__ inline int member_variant(const LUDev& d, int j0, int single) {
+    return panel_variant<T>(d.n, j0, d.cval != nullptr, single, d.tslu != 0);
+}
 
 template <typename T>
 __device__ inline cplx<T> shfl_c(cplx<T> v, int src) {
@@ -74,10 +95,10 @@ __device__ inline cplx<T> shfl_c(cplx<T> v, int src) {
 // interleaved rows.  Per column j one sweep applies the rank-1 update of column j - 1 and
 // searches column j for the pivot.
 template <typename T>
-__global__ __launch_bounds__(256) void panel_kernel(const LUDev* __restrict__ dv, int j0, int nb) {
+__global__ __launch_bounds__(256) void panel_kernel(const LUDev* __restrict__ dv, int j0, int nb, int single) {
     const LUDev& d = dv[blockIdx.z];
     const int w = step_width(d, j0, nb);
-    if (w == 0 || multi_panel(d, j0)) return;
+    if (w == 0 || member_variant<T>(d, j0, single) != PV_SINGLE) return;
     const int k = blockIdx.x, n = d.n;
     const long ldf = d.ldf;
     cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
@@ -167,12 +188,13 @@ __global__ __launch_bounds__(256) void panel_kernel(const LUDev* __restrict__ dv
 // Candidates are double-buffered by column parity; kernel boundaries order everything, so there
 // is no inter-workgroup waiting.
 template <typename T, int U>
-__global__ __launch_bounds__(256) void panel_step_kernel(const LUDev* __restrict__ dv, int j0, int nb, int j) {
+__global__ __launch_bounds__(256) void panel_step_kernel(const LUDev* __restrict__ dv, int j0, int nb, int j,
+                                                         int single) {
     // U rows per wave (R = 4 U rows per workgroup), all held in registers
     constexpr int R = 4 * U;
     const LUDev& d = dv[blockIdx.z];
     const int w = step_width(d, j0, nb);
-    if (w == 0 || !multi_panel(d, j0) || j > w) return;
+    if (w == 0 || member_variant<T>(d, j0, single) != PV_MULTI || j > w) return;
     const int n = d.n, W = (n - j0 + R - 1) / R;
     const int k = blockIdx.y, g = blockIdx.x;
     if (g >= W) return;
@@ -307,6 +329,345 @@ __global__ __launch_bounds__(256) void panel_step_kernel(const LUDev* __restrict
         const int r = rfirst + wave + 4 * u;
         if (pv >= T(0) && r == pr && act) cdata[(cb + g * 2 + par) * w + lane] = v[u];
         if (r == rjn && act) rowj[((long)k * 2 + par) * w + lane] = v[u];
+    }
+}
+
+// Register panel: the whole panel (at most 4 U rows) of one node in the registers of one workgroup.
+// Wave v holds rows j0 + v + 4u, lane c column j0 + c.  Per column j: lane j of every wave finds
+// its best row (largest |re| + |im| at or below j0 + j, lowest row on ties), the four candidates
+// meet in LDS, the pivot row and row j0 + j trade places through LDS, and the rows below take the
+// scaling and rank-1 update; the same arithmetic as the sweeping and multi-workgroup panels, with
+// no memory traffic between the first load and the final store.
+template <typename T, int U>
+__global__ __launch_bounds__(256) void panel_reg_kernel(const LUDev* __restrict__ dv, int j0, int nb, int single) {
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    if (w == 0 || member_variant<T>(d, j0, single) != PV_REG) return;
+    const int k = blockIdx.x, n = d.n;
+    const long ldf = d.ldf;
+    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
+    int* ipiv = d.ipiv + k * d.spiv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool act = lane < w;
+    const cplx<T> zero(T(0), T(0));
+    __shared__ T sval[2][4];
+    __shared__ int srow[2][4];
+    __shared__ cplx<T> prow_s[2][64], xrow_s[2][64];
+
+    cplx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = j0 + wave + 4 * u;
+        v[u] = (act && r < n) ? F[(long)r * ldf + j0 + lane] : zero;
+    }
+    for (int j = 0; j < w; ++j) {
+        const int par = j & 1;
+        const int rj = j0 + j;
+        // candidate of this wave: lane j scans its rows at or below rj
+        T best = T(-1);
+        int brow = INT_MAX;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = j0 + wave + 4 * u;
+            if (lane == j && r >= rj && r < n) {
+                const T a = abs1(v[u]);
+                if (a > best) {
+                    best = a;
+                    brow = r;
+                }
+            }
+        }
+        if (lane == j) {
+            sval[par][wave] = best;
+            srow[par][wave] = brow;
+        }
+        __syncthreads();
+        T pv = sval[par][0];
+        int pr = srow[par][0];
+#pragma unroll
+        for (int t = 1; t < 4; ++t)
+            if (sval[par][t] > pv || (sval[par][t] == pv && srow[par][t] < pr)) {
+                pv = sval[par][t];
+                pr = srow[par][t];
+            }
+        if (pv <= T(0)) pr = rj;  // exactly zero column: no interchange, flagged below
+        // the pivot row and row rj through LDS
+        const int wp = (pr - j0) & 3, up = (pr - j0) >> 2;
+        const int wj = (rj - j0) & 3, uj = (rj - j0) >> 2;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (wave == wp && u == up) prow_s[par][lane] = v[u];
+            if (wave == wj && u == uj) xrow_s[par][lane] = v[u];
+        }
+        __syncthreads();
+        const cplx<T> prow = prow_s[par][lane];
+        if (pr != rj) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (wave == wj && u == uj) v[u] = prow;
+                if (wave == wp && u == up) v[u] = xrow_s[par][lane];
+            }
+        }
+        cplx<T> invp = zero;
+        if (pv > T(0)) {
+            invp = cdiv(cplx<T>(T(1), T(0)), shfl_c(prow, j));
+        } else if (threadIdx.x == 0 && d.info[k] == 0) {
+            d.info[k] = rj + 1;
+        }
+        if (threadIdx.x == 0) ipiv[rj] = pr;
+        // scaling and rank-1 update of the rows below rj
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = j0 + wave + 4 * u;
+            if (r > rj && r < n) {
+                const cplx<T> l = shfl_c(v[u], j) * invp;
+                if (lane == j)
+                    v[u] = l;
+                else if (lane > j)
+                    v[u] = v[u] - l * prow;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = j0 + wave + 4 * u;
+        if (act && r < n) F[(long)r * ldf + j0 + lane] = v[u];
+    }
+}
+
+// Tournament pivoting of a tall panel (communication-avoiding LU): the rows are split into blocks of
+// R = 4 U rows; each block chooses w candidate pivot rows by an LU with partial pivoting of its rows
+// in registers (largest |re| + |im|, lowest original row on ties), and a reduction tree merges G =
+// R / 64 candidate sets per workgroup the same way until one set of w rows remains, in pivot order.
+// Every level reads the original panel rows (the panel is not written until the tree is done).
+// Level `level` of node k of every member; its workgroup count follows from the member's rows.
+__device__ inline int tslu_width(int rows, int R, int G, int level) {
+    int W = (rows + R - 1) / R;
+    for (int l = 1; l <= level; ++l) W = W > 1 ? (W + G - 1) / G : 0;
+    return W;
+}
+
+template <typename T, int U>
+__global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv, int j0, int nb, int level, int single) {
+    constexpr int R = 4 * U, G = R / 64;
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
+    const int n = d.n, rows = n - j0;
+    const int W = tslu_width(rows, R, G, level);
+    const int g = blockIdx.x, k = blockIdx.y;
+    if (g >= W) return;
+    const bool root = W == 1;
+    const int Win = level > 0 ? tslu_width(rows, R, G, level - 1) : 0;
+    const long ldf = d.ldf;
+    const cplx<T>* F = (const cplx<T>*)d.F + k * d.sF;
+    int* cl = d.tcand + (long)k * (2L * d.tW0 * 64 + 64);
+    const int* in = cl + (long)((level - 1) & 1) * d.tW0 * 64;
+    int* out = root ? cl + 2L * d.tW0 * 64 : cl + (long)(level & 1) * d.tW0 * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool act = lane < w;
+    const cplx<T> zero(T(0), T(0));
+    __shared__ int rid[R];
+    __shared__ T sval[4];
+    __shared__ int sid[4], spos[4];
+    __shared__ cplx<T> prow_s[64], xrow_s[64];
+    __shared__ int nsel_s;
+
+    // original row of each position p (invalid: -1); position p = wave + 4 u
+    for (int p = threadIdx.x; p < R; p += blockDim.x) {
+        int row;
+        if (level == 0) {
+            row = j0 + g * R + p;
+            if (row >= n) row = -1;
+        } else {
+            const int idx = g * G * 64 + p;
+            row = idx < Win * 64 ? in[idx] : -1;
+        }
+        rid[p] = row;
+    }
+    if (threadIdx.x == 0) nsel_s = w;
+    __syncthreads();
+    cplx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = rid[wave + 4 * u];
+        v[u] = (act && r >= 0) ? F[(long)r * ldf + j0 + lane] : zero;
+    }
+    for (int j = 0; j < w; ++j) {
+        // candidate of this wave among valid positions >= j (lane j holds column j)
+        T best = T(-1);
+        int bid = INT_MAX, bpos = -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = wave + 4 * u;
+            const int r = rid[p];
+            if (lane == j && p >= j && r >= 0) {
+                const T a = abs1(v[u]);
+                if (a > best || (a == best && r < bid)) {
+                    best = a;
+                    bid = r;
+                    bpos = p;
+                }
+            }
+        }
+        if (lane == j) {
+            sval[wave] = best;
+            sid[wave] = bid;
+            spos[wave] = bpos;
+        }
+        __syncthreads();
+        T pv = sval[0];
+        int pid = sid[0], pp = spos[0];
+#pragma unroll
+        for (int t = 1; t < 4; ++t)
+            if (sval[t] > pv || (sval[t] == pv && sid[t] < pid)) {
+                pv = sval[t];
+                pid = sid[t];
+                pp = spos[t];
+            }
+        if (pv < T(0)) {   // no valid row left: the set supplies j candidates
+            if (threadIdx.x == 0) nsel_s = j;
+            __syncthreads();
+            break;
+        }
+        // positions j and pp trade rows (registers through LDS, row ids in LDS)
+        const int wp = pp & 3, up = pp >> 2, wj = j & 3, uj = j >> 2;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (wave == wp && u == up) prow_s[lane] = v[u];
+            if (wave == wj && u == uj) xrow_s[lane] = v[u];
+        }
+        __syncthreads();
+        const cplx<T> prow = prow_s[lane];
+        if (pp != j) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (wave == wj && u == uj) v[u] = prow;
+                if (wave == wp && u == up) v[u] = xrow_s[lane];
+            }
+            if (threadIdx.x == 0) {
+                const int t = rid[j];
+                rid[j] = rid[pp];
+                rid[pp] = t;
+            }
+        }
+        cplx<T> invp = zero;
+        if (pv > T(0))
+            invp = cdiv(cplx<T>(T(1), T(0)), shfl_c(prow, j));
+        else if (root && threadIdx.x == 0 && d.info[k] == 0)
+            d.info[k] = j0 + j + 1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = wave + 4 * u;
+            if (p > j) {
+                const cplx<T> l = shfl_c(v[u], j) * invp;
+                if (lane == j)
+                    v[u] = l;
+                else if (lane > j)
+                    v[u] = v[u] - l * prow;
+            }
+        }
+        __syncthreads();   // rid and the row buffers are rewritten by the next column
+    }
+    __syncthreads();
+    const int nsel = nsel_s;
+    for (int j = threadIdx.x; j < 64; j += blockDim.x) out[g * 64 + j] = j < nsel ? rid[j] : -1;
+    if (root) {
+        // factored rows of the winners (L11 \ U11 in pivot order)
+        cplx<T>* top = (cplx<T>*)d.ttop + (long)k * nb * nb;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = wave + 4 * u;
+            if (p < w && act) top[(long)p * nb + lane] = v[u];
+        }
+    }
+}
+
+// After the tournament: the winners' row interchanges as sequential swaps (ipiv), applied to the
+// panel columns, and the root's factored rows written on top.  One wave per (member, node).
+template <typename T>
+__global__ __launch_bounds__(64) void tslu_apply_kernel(const LUDev* __restrict__ dv, int j0, int nb, int single) {
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const long ldf = d.ldf;
+    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
+    const int* fin = d.tcand + (long)k * (2L * d.tW0 * 64 + 64) + 2L * d.tW0 * 64;
+    int* ipiv = d.ipiv + k * d.spiv;
+    __shared__ int pos[128], content[128], piv[64];
+    if (lane == 0) {
+        // touched positions: the panel's first w rows, then the winners outside them
+        int cnt = 0;
+        for (int j = 0; j < w; ++j) pos[cnt++] = j0 + j;
+        for (int j = 0; j < w; ++j) {
+            const int r = fin[j];
+            if (r >= j0 + w) pos[cnt++] = r;
+        }
+        for (int t = 0; t < cnt; ++t) content[t] = pos[t];
+        for (int j = 0; j < w; ++j) {
+            const int r = fin[j];
+            int tc = j;
+            if (r >= 0)
+                for (int t = 0; t < cnt; ++t)
+                    if (content[t] == r) {
+                        tc = t;
+                        break;
+                    }
+            piv[j] = pos[tc];
+            const int a = content[j];
+            content[j] = content[tc];
+            content[tc] = a;
+        }
+    }
+    __syncthreads();
+    if (lane < w) {
+        for (int j = 0; j < w; ++j) {
+            const int r = piv[j];
+            if (r != j0 + j) {
+                const cplx<T> a = F[(long)(j0 + j) * ldf + j0 + lane];
+                const cplx<T> b = F[(long)r * ldf + j0 + lane];
+                F[(long)(j0 + j) * ldf + j0 + lane] = b;
+                F[(long)r * ldf + j0 + lane] = a;
+            }
+        }
+        const cplx<T>* top = (const cplx<T>*)d.ttop + (long)k * nb * nb;
+        for (int j = 0; j < w; ++j) F[(long)(j0 + j) * ldf + j0 + lane] = top[(long)j * nb + lane];
+        ipiv[j0 + lane] = piv[lane];
+    }
+}
+
+// L21 = A21 U11^-1 in place for the rows below the panel's first w rows (64 rows per workgroup;
+// both operands staged in LDS, every row read before any is written).
+template <typename T>
+__global__ __launch_bounds__(256) void tslu_l21_kernel(const LUDev* __restrict__ dv, int j0, int nb, int step,
+                                                       int single) {
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
+    const int k = blockIdx.y, n = d.n;
+    const int r0 = j0 + w + blockIdx.x * 64;
+    if (r0 >= n) return;
+    const int nr = min(64, n - r0);
+    const long ldf = d.ldf;
+    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
+    const cplx<T>* Ui = (const cplx<T>*)d.Uinv + ((long)k * d.nsteps + step) * nb * nb;
+    __shared__ cplx<T> Us[64][65];
+    __shared__ cplx<T> As[64][65];
+    const cplx<T> zero(T(0), T(0));
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int i = e >> 6, c = e & 63;
+        Us[i][c] = (i < w && c < w) ? Ui[(long)i * nb + c] : zero;
+        As[i][c] = (i < nr && c < w) ? F[(long)(r0 + i) * ldf + j0 + c] : zero;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int i = e >> 6, c = e & 63;
+        if (i < nr && c < w) {
+            cplx<T> acc = zero;
+            for (int kk = 0; kk < w; ++kk) acc = acc + As[i][kk] * Us[kk][c];
+            F[(long)(r0 + i) * ldf + j0 + c] = acc;
+        }
     }
 }
 
@@ -505,33 +866,70 @@ GemmGroup member(const void* A, long lda, long sA, long sA2, const void* B, long
     return g;
 }
 
-// Panel factorisation of step j0 of every member: the single-workgroup kernel for members with at
-// most PANEL_ROWS rows left, one multi-workgroup launch per column for the others.
+// Panel factorisation of step j0 of every member with the variant its row count selects (see
+// panel_variant): one launch each for the register and sweeping panels, one launch per column for
+// the multi-workgroup panel.
 template <typename T>
 int panel(SetRun<T>& R, int j0) {
     if (!R.launching()) return 0;
     const LUSet& S = R.S;
-    bool single = false;
+    bool reg = false, single = false;
     int wmax = -1, Wmax = 0;
+    constexpr int TR = 4 * RegPanel<T>::U, TG = TR / 64;
+    std::vector<int> tw;   // tournament: widest level widths over the members
+    int below = 0;
     for (int b = 0; b < S.count; ++b) {
         const LUStore& s = S.s[b];
-        if (s.n <= j0) continue;
-        const int w = std::min(R.nb, s.n - j0);
-        if (s.pslots && s.n - j0 > PANEL_ROWS) {
-            wmax = std::max(wmax, w);
+        const int v = panel_variant<T>(s.n, j0, s.pslots != nullptr, S.single_rows, s.tslu && s.tcand);
+        if (v == PV_REG) reg = true;
+        if (v == PV_SINGLE) single = true;
+        if (v == PV_MULTI) {
+            wmax = std::max(wmax, std::min(R.nb, s.n - j0));
             Wmax = std::max(Wmax, ceil_div(s.n - j0, PANEL_ROWS));
-        } else {
-            single = true;
+        }
+        if (v == PV_TSLU) {
+            const int rows = s.n - j0;
+            int W = ceil_div(rows, TR);
+            for (int l = 0; W > 0; ++l) {
+                if ((int)tw.size() <= l) tw.push_back(0);
+                tw[l] = std::max(tw[l], W);
+                W = W > 1 ? ceil_div(W, TG) : 0;
+            }
+            below = std::max(below, rows - std::min(R.nb, rows));
         }
     }
+    if (reg) {
+        hipLaunchKernelGGL((panel_reg_kernel<T, RegPanel<T>::U>), dim3(R.q, 1, S.count), dim3(256), 0, R.st, S.dev, j0,
+                           R.nb, S.single_rows);
+        FM_LAUNCH_CHECK();
+    }
     if (single) {
-        hipLaunchKernelGGL((panel_kernel<T>), dim3(R.q, 1, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb);
+        hipLaunchKernelGGL((panel_kernel<T>), dim3(R.q, 1, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb,
+                           S.single_rows);
         FM_LAUNCH_CHECK();
     }
     for (int j = 0; j <= wmax; ++j) {
         hipLaunchKernelGGL((panel_step_kernel<T, PANEL_ROWS / 4>), dim3(Wmax, R.q, S.count), dim3(256), 0, R.st, S.dev,
-                           j0, R.nb, j);
+                           j0, R.nb, j, S.single_rows);
         FM_LAUNCH_CHECK();
+    }
+    if (!tw.empty()) {
+        for (int l = 0; l < (int)tw.size(); ++l) {
+            hipLaunchKernelGGL((tslu_kernel<T, RegPanel<T>::U>), dim3(tw[l], R.q, S.count), dim3(256), 0, R.st, S.dev,
+                               j0, R.nb, l, S.single_rows);
+            FM_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL((tslu_apply_kernel<T>), dim3(R.q, 1, S.count), dim3(64), 0, R.st, S.dev, j0, R.nb,
+                           S.single_rows);
+        FM_LAUNCH_CHECK();
+        // U11^-1 of this step (members without a tournament here recompute a finished block)
+        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(1, R.q, S.count), dim3(64), 0, R.st, S.dev, R.nb, j0 / R.nb);
+        FM_LAUNCH_CHECK();
+        if (below > 0) {
+            hipLaunchKernelGGL((tslu_l21_kernel<T>), dim3(ceil_div(below, 64), R.q, S.count), dim3(256), 0, R.st,
+                               S.dev, j0, R.nb, j0 / R.nb, S.single_rows);
+            FM_LAUNCH_CHECK();
+        }
     }
     return 0;
 }
@@ -705,9 +1103,47 @@ LUDev lu_dev(const LUStore& s, size_t real_bytes) {
     d.LinvS = s.LinvS; d.UinvS = s.UinvS;
     d.A = s.A; d.lda = s.lda; d.B = s.B; d.ldb = s.ldb; d.z = s.z;
     d.amax = s.half ? s.amax : nullptr;
+    d.tcand = s.tcand; d.ttop = s.ttop; d.tW0 = s.tW0; d.tslu = (s.tslu && s.tcand) ? 1 : 0;
     d.n = s.n; d.nsteps = s.nsteps; d.nsbs = s.nsbs;
     return d;
 }
+
+template <typename T>
+int lu_panel_only(const LUSet& S, int j0, hipStream_t st) {
+    if (S.count <= 0 || !S.dev) return FEAST_EUNSUPPORTED;
+    SetRun<T> R(S, st, nullptr);
+    return panel<T>(R, j0);
+}
+
+namespace {
+// deterministic pseudo-random fill (a 64-bit integer hash of the index) for tuning runs
+__global__ void fill_kernel(double* p, long count, unsigned long long seed) {
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    unsigned long long x = (unsigned long long)i * 0x9E3779B97F4A7C15ull + seed;
+    x ^= x >> 30; x *= 0xBF58476D1CE4E5B9ull; x ^= x >> 27; x *= 0x94D049BB133111EBull; x ^= x >> 31;
+    p[i] = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+__global__ void fill_kernel_f(float* p, long count, unsigned long long seed) {
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    unsigned long long x = (unsigned long long)i * 0x9E3779B97F4A7C15ull + seed;
+    x ^= x >> 30; x *= 0xBF58476D1CE4E5B9ull; x ^= x >> 27; x *= 0x94D049BB133111EBull; x ^= x >> 31;
+    p[i] = (float)((double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+}
+}  // namespace
+
+int lu_fill_random(void* p, long reals, bool dbl, unsigned long long seed, hipStream_t st) {
+    const unsigned blocks = (unsigned)((reals + 255) / 256);
+    if (dbl)
+        hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, (double*)p, reals, seed);
+    else
+        hipLaunchKernelGGL(fill_kernel_f, dim3(blocks), dim3(256), 0, st, (float*)p, reals, seed);
+    FM_LAUNCH_CHECK();
+    return 0;
+}
+
+int lu_reg_panel_rows(bool dbl) { return 4 * (dbl ? RegPanel<double>::U : RegPanel<float>::U); }
 
 template <typename T>
 void lu_plan(const LUSet& S, std::vector<GemmGroup>& out) {
@@ -725,6 +1161,8 @@ int lu_factor_set(const LUSet& S, hipStream_t st) {
     return run_set<T>(R);
 }
 
+template int lu_panel_only<double>(const LUSet&, int, hipStream_t);
+template int lu_panel_only<float>(const LUSet&, int, hipStream_t);
 template void lu_plan<double>(const LUSet&, std::vector<GemmGroup>&);
 template void lu_plan<float>(const LUSet&, std::vector<GemmGroup>&);
 template int lu_factor_set<double>(const LUSet&, hipStream_t);

@@ -153,3 +153,10 @@ def test_m0_rule_and_mlp_sizes():
     out = ctypes.c_size_t(0)
     assert fm.lib().feast_mlp_workspace_size(19, 256, 1024, ctypes.byref(out)) == 0
     assert out.value >= 4 * (4 * 71425 + 4 * 1024 * 256)
+
+
+def test_autotune_workspace_size():
+    out = ctypes.c_size_t(0)
+    assert fm.lib().feast_autotune_workspace_size(16, 1, ctypes.byref(out)) == 0
+    assert out.value >= 16 * 6144 * 64 * 8
+    assert fm.lib().feast_autotune_workspace_size(0, 1, ctypes.byref(out)) < 0

@@ -1,0 +1,88 @@
+"""Panel kernels.  With partial pivoting the three kernels (register, sweeping, multi-workgroup)
+perform the same operations in the same order, so the factorisations and every solve agree bit for
+bit whichever variant the tuning selects; the autotuner measures and records their crossover.
+Tournament pivoting (the default for tall panels) chooses other pivot rows, so its solves are
+checked against the oracle's partial-pivoting solves to the conditioning bound, at sizes whose
+reduction tree has one to six levels."""
+import numpy as np
+import pytest
+
+import pencils
+from oracle import feast
+from oracle import quadrature as Q
+from tests.gpu_common import device, random_pencil, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def fm():
+    import paper_1404_2891_amd as m
+    return m
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [300, 700])
+def test_panel_variants_agree_bitwise(prec, n):
+    import torch
+    A, B, lam = random_pencil(n, seed=n, with_B=True)
+    Ad, Bd = fm().to_device(A, device()), fm().to_device(B, device())
+    U = fm().to_device(pencils.complex_gaussian(np.random.default_rng(1), (n, 12)), device())
+    outs = []
+    try:
+        for rows in (0, 1 << 20):   # multi-workgroup above the register panel / sweeping everywhere
+            fm().set_panel_rows(prec, 8, rows)
+            F = fm().Feast(Ad, Bd, 0j, 1.0, 1.0, 8, 12, precision=prec, pivoting="partial")
+            outs.append(F.filter(U).clone())
+            F.close()
+    finally:
+        fm().set_panel_rows(prec, 8, 1024)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    z, s = Q.nodes_and_weights(0j, 1.0, 1.0, "trapezoid", 8)
+    ref = feast.filter_right(feast.factor_nodes(A, B, z), s, B, pencils.complex_gaussian(np.random.default_rng(1), (n, 12)))
+    assert rel_err(outs[0].cpu().numpy(), ref) < 1e-9
+
+
+def test_autotune_records_crossover(tmp_path):
+    path = tmp_path / "tune.txt"
+    rows, table = fm().autotune("fp32", 16, cache_path=path, device=device())
+    assert rows in [256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144]
+    assert np.all(table[:, 1] > 0) and np.all(table[:, 2] > 0)
+    line = [l.split() for l in path.read_text().splitlines()]
+    assert ["1", "16", str(rows)] in line
+    fm().set_panel_rows("fp32", 16, 1024)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [300, 700, 1100, 2500])
+def test_tournament_pivoting_solves_match_oracle(prec, n):
+    import scipy.linalg
+    A, B, lam = random_pencil(n, seed=2 * n + 1, with_B=True, m=max(1, n // 50))
+    q, m0 = 8, 6
+    F = fm().Feast(fm().to_device(A, device()), fm().to_device(B, device()), 0j, 1.0, 1.0, q, m0, precision=prec)
+    Fp = fm().Feast(fm().to_device(A, device()), fm().to_device(B, device()), 0j, 1.0, 1.0, q, m0, precision=prec,
+                    pivoting="partial")
+    z, s = Q.nodes_and_weights(0j, 1.0, 1.0, "trapezoid", q)
+    rhs = pencils.complex_gaussian(np.random.default_rng(n), (n, m0))
+    rd = fm().to_device(rhs, device())
+    for k in (0, 5):
+        T = feast.node_matrix(A, B, z[k])
+        kappa = np.linalg.cond(T) if n <= 1100 else 1e4
+        for side in (0, 1):
+            ref = scipy.linalg.lu_solve(scipy.linalg.lu_factor(T), rhs, trans=2 if side else 0)
+            tol = (50 if prec == "fp64" else 200) * kappa * 2.0 ** -53 * max(1, np.sqrt(n) / 4)
+            for G in (F, Fp):
+                got = G.node_solve(k, rd, side).cpu().numpy()
+                assert rel_err(got, ref) < tol, (k, side, rel_err(got, ref), tol)
+    F.close()
+    Fp.close()
+
+
+def test_tournament_pivoting_reports_zero_pivot():
+    """A tall panel with an exactly zero column (an eigenvalue on node 0): FEAST_ESINGULAR + 0."""
+    n = 600
+    d = np.linspace(1.5, 3.0, n).astype(np.complex128)
+    d[7] = 1.0
+    with pytest.raises(fm().FeastError) as e:
+        fm().Feast(fm().to_device(np.asfortranarray(np.diag(d)), device()), None, 0j, 1.0, 1.0, 16, 4)
+    assert e.value.code == fm().binding.FEAST_ESINGULAR + 0
