@@ -404,7 +404,8 @@ def main():
         errs = [match_err(r.lam, ref) for r in results]
         out[mode] = dict(ms_per_step=1e3 * wall / steps, iters_per_s=iters / wall, iterations=results[0].iterations,
                          converged=all(r.converged for r in results), m=len(results[0].lam),
-                         max_resid=float(max(r.resid.max() for r in results)), eig_err_vs_oracle=max(errs),
+                         max_resid=float(max((r.resid.max() if len(r.resid) else np.nan) for r in results)),
+                         eig_err_vs_oracle=max(errs),
                          ir_sweeps=results[0].ir_sweeps, escalated_to_fp32=bool(results[0].escalated),
                          phases={k: dict(ms=v["ms"] / steps, launches=v["launches"] // steps,
                                          tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None)

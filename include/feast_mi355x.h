@@ -88,11 +88,11 @@ typedef struct {
                             all m0 of them) and at least m0 - 2 Ritz values lie inside C: the
                             subspace may be smaller than the eigenvalue count (Section 4 asks
                             m0 >= m); the caller grows m0 and starts again */
-    int pivoting;        /* row pivoting of the node factorisations: 0 (default) tournament
-                            pivoting of panels taller than the register panel (candidate rows
+    int pivoting;        /* row pivoting of the node factorisations: 0 (default) partial
+                            pivoting (LAPACK's pivots); 1 tournament pivoting (candidate rows
                             chosen by partial-pivoting LUs of row blocks and a reduction tree,
-                            as in communication-avoiding LU; a few launches per panel), 1 exact
-                            partial pivoting (one launch per column, LAPACK's pivots) */
+                            as in communication-avoiding LU: a few launches per panel instead of
+                            one per column, but slower on MI355X as implemented here) */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */

@@ -184,11 +184,11 @@ def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid") -> C
     return Contour(center.real, center.imag, float(radius), float(aspect), int(q), RULES[rule])
 
 
-PIVOTING = {"tournament": 0, "partial": 1}
+PIVOTING = {"partial": 0, "tournament": 1}
 
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament") -> Options:
+                 ir_tol=0.0, timing=False, rank_check=False, pivoting="partial") -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -288,7 +288,7 @@ class Feast:
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
-                 timing=False, workspace=None, rank_check=False, pivoting="tournament"):
+                 timing=False, workspace=None, rank_check=False, pivoting="partial"):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
@@ -413,7 +413,7 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False, pivoting="tournament"):
+                 rank_check=False, pivoting="partial"):
         torch = _torch()
         count = len(pencils)
         self.count = count

@@ -136,7 +136,7 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     }
     c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
     if (c->prec == Prec::F16) c->lu.amax = b.take<int>(q);
-    if (n > lu_reg_panel_rows(c->prec == Prec::F64)) {
+    if (c->o.pivoting == 1) {
         c->lu.tcand = b.take<int>(tslu_cand_ints(n, q, c->prec == Prec::F64));
         c->lu.ttop = b.take<char>((size_t)q * NB * NB * E);
     }
@@ -201,7 +201,7 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->lu.nbs = NBS;
     c->lu.nsbs = ceil_div(n, NBS);
     c->lu.half = c->prec == Prec::F16;
-    c->lu.tslu = o->pivoting == 0;
+    c->lu.tslu = o->pivoting == 1;
     c->lu.tW0 = tslu_leaf_blocks(n, c->prec == Prec::F64);
     // grouped-product members of the factorisation (a count that depends on the dimensions only)
     LUSet one;
@@ -1057,8 +1057,9 @@ int h_conv(Run& r) {
     }
     // FP16 factorisations too inaccurate for these node systems show as a residual that no longer
     // halves per iteration: the nodes are factored again with FP32 updates and the run continues
-    if (c->lu.half && !r.finishing && r.it >= 3 && count > 0 && r.res_prev > 0 && std::isfinite(r.res_prev) &&
-        !(r.res_last < 0.5 * r.res_prev))
+    if (c->lu.half && !r.finishing && r.it >= 3 &&
+        ((count > 0 && r.res_prev > 0 && std::isfinite(r.res_prev) && !(r.res_last < 0.5 * r.res_prev)) ||
+         (count == 0 && n_inside > 0 && r.it >= 4)))
         FM_TRY(escalate(c));
     if (r.finishing) {
         r.order.insert(r.order.end(), rest.begin(), rest.end());

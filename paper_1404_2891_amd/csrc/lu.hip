@@ -74,8 +74,8 @@ template <typename T>
 __host__ __device__ inline int panel_variant(int n, int j0, bool has_slots, int single, bool tslu = false) {
     const int rows = n - j0;
     if (rows <= 0) return PV_NONE;
-    if (rows <= 4 * RegPanel<T>::U) return PV_REG;
     if (tslu) return PV_TSLU;
+    if (rows <= 4 * RegPanel<T>::U) return PV_REG;
     if (rows <= single || !has_slots) return PV_SINGLE;
     return PV_MULTI;
 }
@@ -435,21 +435,28 @@ __global__ __launch_bounds__(256) void panel_reg_kernel(const LUDev* __restrict_
     }
 }
 
-// Tournament pivoting of a tall panel (communication-avoiding LU): the rows are split into blocks of
-// R = 4 U rows; each block chooses w candidate pivot rows by an LU with partial pivoting of its rows
-// in registers (largest |re| + |im|, lowest original row on ties), and a reduction tree merges G =
-// R / 64 candidate sets per workgroup the same way until one set of w rows remains, in pivot order.
-// Every level reads the original panel rows (the panel is not written until the tree is done).
-// Level `level` of node k of every member; its workgroup count follows from the member's rows.
+// Tournament pivoting of a panel (communication-avoiding LU): the rows are split into blocks of R
+// rows; each block chooses w candidate pivot rows by an LU with partial pivoting of its rows, and a
+// reduction tree merges G = R / 64 candidate sets per workgroup the same way until one set of w
+// rows remains, in pivot order (largest |re| + |im|, lowest original row on ties).  Every level
+// reads the original panel rows (the panel is written only after the tree).
+//
+// In the local LUs each row lives in the registers of LPR lanes (one lane holds 64 / LPR of its
+// columns: LPR = 1 for FP32, 2 for FP64), so the pivot search of a column is a wave reduction and
+// the update of a row is register arithmetic against the pivot row broadcast through LDS.
+template <typename T> struct Tourn;
+template <> struct Tourn<double> { static constexpr int LPR = 2; };
+template <> struct Tourn<float> { static constexpr int LPR = 1; };
+
 __device__ inline int tslu_width(int rows, int R, int G, int level) {
     int W = (rows + R - 1) / R;
     for (int l = 1; l <= level; ++l) W = W > 1 ? (W + G - 1) / G : 0;
     return W;
 }
 
-template <typename T, int U>
+template <typename T>
 __global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv, int j0, int nb, int level, int single) {
-    constexpr int R = 4 * U, G = R / 64;
+    constexpr int LPR = Tourn<T>::LPR, CPL = 64 / LPR, RPW = 64 / LPR, R = 4 * RPW, G = R / 64;
     const LUDev& d = dv[blockIdx.z];
     const int w = step_width(d, j0, nb);
     if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
@@ -464,181 +471,176 @@ __global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv,
     int* cl = d.tcand + (long)k * (2L * d.tW0 * 64 + 64);
     const int* in = cl + (long)((level - 1) & 1) * d.tW0 * 64;
     int* out = root ? cl + 2L * d.tW0 * 64 : cl + (long)(level & 1) * d.tW0 * 64;
+    cplx<T>* top = (cplx<T>*)d.ttop + (long)k * nb * nb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool act = lane < w;
+    const int h = lane % LPR;                       // part of the row: columns h CPL .. h CPL + CPL - 1
+    const int p = wave * RPW + lane / LPR;          // row slot
     const cplx<T> zero(T(0), T(0));
-    __shared__ int rid[R];
-    __shared__ T sval[4];
-    __shared__ int sid[4], spos[4];
-    __shared__ cplx<T> prow_s[64], xrow_s[64];
-    __shared__ int nsel_s;
+    __shared__ cplx<T> prow[2][64];
+    __shared__ T rval[4];
+    __shared__ int rrow[4], rpos[4], sel[64];
 
-    // original row of each position p (invalid: -1); position p = wave + 4 u
-    for (int p = threadIdx.x; p < R; p += blockDim.x) {
-        int row;
-        if (level == 0) {
-            row = j0 + g * R + p;
-            if (row >= n) row = -1;
-        } else {
-            const int idx = g * G * 64 + p;
-            row = idx < Win * 64 ? in[idx] : -1;
-        }
-        rid[p] = row;
+    int row;
+    if (level == 0) {
+        row = j0 + g * R + p;
+        if (row >= n) row = -1;
+    } else {
+        const int idx = g * G * 64 + p;
+        row = idx < Win * 64 ? in[idx] : -1;
     }
-    if (threadIdx.x == 0) nsel_s = w;
-    __syncthreads();
-    cplx<T> v[U];
+    bool active = row >= 0;
+    cplx<T> a[CPL];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int r = rid[wave + 4 * u];
-        v[u] = (act && r >= 0) ? F[(long)r * ldf + j0 + lane] : zero;
+    for (int cc = 0; cc < CPL; ++cc) {
+        const int c = h * CPL + cc;
+        a[cc] = (active && c < w) ? F[(long)row * ldf + j0 + c] : zero;
     }
+    int nsel = w;
     for (int j = 0; j < w; ++j) {
-        // candidate of this wave among valid positions >= j (lane j holds column j)
-        T best = T(-1);
-        int bid = INT_MAX, bpos = -1;
+        const int par = j & 1, hj = j / CPL, jj = j % CPL;
+        // candidate of this wave: (largest value, lowest row)
+        T val = T(-1);
+        if (active && h == hj) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = wave + 4 * u;
-            const int r = rid[p];
-            if (lane == j && p >= j && r >= 0) {
-                const T a = abs1(v[u]);
-                if (a > best || (a == best && r < bid)) {
-                    best = a;
-                    bid = r;
-                    bpos = p;
-                }
+            for (int cc = 0; cc < CPL; ++cc)
+                if (cc == jj) val = abs1(a[cc]);
+        }
+        int key = (active && h == hj) ? row : INT_MAX;
+        int ps = p;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const T v2 = __shfl_xor(val, o);
+            const int r2 = __shfl_xor(key, o), p2 = __shfl_xor(ps, o);
+            if (v2 > val || (v2 == val && r2 < key)) {
+                val = v2;
+                key = r2;
+                ps = p2;
             }
         }
-        if (lane == j) {
-            sval[wave] = best;
-            sid[wave] = bid;
-            spos[wave] = bpos;
+        if (lane == 0) {
+            rval[wave] = val;
+            rrow[wave] = key;
+            rpos[wave] = ps;
         }
         __syncthreads();
-        T pv = sval[0];
-        int pid = sid[0], pp = spos[0];
+        T pv = rval[0];
+        int pr = rrow[0], pp = rpos[0];
 #pragma unroll
         for (int t = 1; t < 4; ++t)
-            if (sval[t] > pv || (sval[t] == pv && sid[t] < pid)) {
-                pv = sval[t];
-                pid = sid[t];
-                pp = spos[t];
+            if (rval[t] > pv || (rval[t] == pv && rrow[t] < pr)) {
+                pv = rval[t];
+                pr = rrow[t];
+                pp = rpos[t];
             }
-        if (pv < T(0)) {   // no valid row left: the set supplies j candidates
-            if (threadIdx.x == 0) nsel_s = j;
-            __syncthreads();
+        if (pv < T(0)) {   // no row left: the set supplies j candidates
+            nsel = j;
             break;
         }
-        // positions j and pp trade rows (registers through LDS, row ids in LDS)
-        const int wp = pp & 3, up = pp >> 2, wj = j & 3, uj = j >> 2;
+        // the winner publishes its row (and, at the root, its factored row) and leaves the set
+        if (p == pp) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (wave == wp && u == up) prow_s[lane] = v[u];
-            if (wave == wj && u == uj) xrow_s[lane] = v[u];
+            for (int cc = 0; cc < CPL; ++cc) {
+                const int c = h * CPL + cc;
+                prow[par][c] = a[cc];
+                if (root && c < w) top[(long)j * nb + c] = a[cc];
+            }
+            if (h == 0) sel[j] = row;
+            active = false;
         }
+        if (pv <= T(0) && root && threadIdx.x == 0 && d.info[k] == 0) d.info[k] = j0 + j + 1;
         __syncthreads();
-        const cplx<T> prow = prow_s[lane];
-        if (pp != j) {
+        // scaling and rank-1 update of the rows still in the set
+        const cplx<T> piv = prow[par][j];
+        const cplx<T> invp = pv > T(0) ? cdiv(cplx<T>(T(1), T(0)), piv) : zero;
+        cplx<T> l = zero;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (wave == wj && u == uj) v[u] = prow;
-                if (wave == wp && u == up) v[u] = xrow_s[lane];
-            }
-            if (threadIdx.x == 0) {
-                const int t = rid[j];
-                rid[j] = rid[pp];
-                rid[pp] = t;
+        for (int cc = 0; cc < CPL; ++cc)
+            if (cc == jj) l = a[cc] * invp;
+        if (LPR > 1) {
+            const int src = (lane - h) + hj;
+            l = cplx<T>(__shfl(l.re, src), __shfl(l.im, src));
+        }
+        if (active) {
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc) {
+                const int c = h * CPL + cc;
+                if (c == j)
+                    a[cc] = l;
+                else if (c > j)
+                    a[cc] = a[cc] - l * prow[par][c];
             }
         }
-        cplx<T> invp = zero;
-        if (pv > T(0))
-            invp = cdiv(cplx<T>(T(1), T(0)), shfl_c(prow, j));
-        else if (root && threadIdx.x == 0 && d.info[k] == 0)
-            d.info[k] = j0 + j + 1;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = wave + 4 * u;
-            if (p > j) {
-                const cplx<T> l = shfl_c(v[u], j) * invp;
-                if (lane == j)
-                    v[u] = l;
-                else if (lane > j)
-                    v[u] = v[u] - l * prow;
-            }
-        }
-        __syncthreads();   // rid and the row buffers are rewritten by the next column
     }
     __syncthreads();
-    const int nsel = nsel_s;
-    for (int j = threadIdx.x; j < 64; j += blockDim.x) out[g * 64 + j] = j < nsel ? rid[j] : -1;
-    if (root) {
-        // factored rows of the winners (L11 \ U11 in pivot order)
-        cplx<T>* top = (cplx<T>*)d.ttop + (long)k * nb * nb;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = wave + 4 * u;
-            if (p < w && act) top[(long)p * nb + lane] = v[u];
-        }
-    }
+    for (int j = threadIdx.x; j < 64; j += blockDim.x) out[g * 64 + j] = j < nsel ? sel[j] : -1;
 }
 
-// After the tournament: the winners' row interchanges as sequential swaps (ipiv), applied to the
-// panel columns, and the root's factored rows written on top.  One wave per (member, node).
+// After the tournament: the winners' row interchanges as sequential swaps (ipiv), the panel rows
+// they displace moved to their final places, and the root's factored rows written on top.
 template <typename T>
-__global__ __launch_bounds__(64) void tslu_apply_kernel(const LUDev* __restrict__ dv, int j0, int nb, int single) {
+__global__ __launch_bounds__(256) void tslu_apply_kernel(const LUDev* __restrict__ dv, int j0, int nb, int single) {
     const LUDev& d = dv[blockIdx.z];
     const int w = step_width(d, j0, nb);
     if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int k = blockIdx.x, tid = threadIdx.x;
     const long ldf = d.ldf;
     cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
     const int* fin = d.tcand + (long)k * (2L * d.tW0 * 64 + 64) + 2L * d.tW0 * 64;
     int* ipiv = d.ipiv + k * d.spiv;
     __shared__ int pos[128], content[128], piv[64];
-    if (lane == 0) {
-        // touched positions: the panel's first w rows, then the winners outside them
-        int cnt = 0;
-        for (int j = 0; j < w; ++j) pos[cnt++] = j0 + j;
+    __shared__ int cnt_s, tc_s;
+    __shared__ cplx<T> buf[64][64];
+    // touched positions: the panel's first w rows, then the winners below them
+    if (tid == 0) {
+        int cnt = w;
         for (int j = 0; j < w; ++j) {
             const int r = fin[j];
             if (r >= j0 + w) pos[cnt++] = r;
         }
-        for (int t = 0; t < cnt; ++t) content[t] = pos[t];
-        for (int j = 0; j < w; ++j) {
-            const int r = fin[j];
-            int tc = j;
-            if (r >= 0)
-                for (int t = 0; t < cnt; ++t)
-                    if (content[t] == r) {
-                        tc = t;
-                        break;
-                    }
+        cnt_s = cnt;
+    }
+    if (tid < w) pos[tid] = j0 + tid;
+    __syncthreads();
+    const int cnt = cnt_s;
+    if (tid < cnt) content[tid] = pos[tid];
+    __syncthreads();
+    for (int j = 0; j < w; ++j) {
+        const int r = fin[j];
+        if (tid == 0) tc_s = j;
+        __syncthreads();
+        if (tid < cnt && r >= 0 && content[tid] == r) tc_s = tid;
+        __syncthreads();
+        if (tid == 0) {
+            const int tc = tc_s;
             piv[j] = pos[tc];
             const int a = content[j];
             content[j] = content[tc];
             content[tc] = a;
         }
+        __syncthreads();
+    }
+    // rows displaced below the panel's first w rows: final content of position pos[t] (t >= w) is
+    // the original row content[t] (the panel itself is still unmodified)
+    const int nd = cnt - w;
+    for (int e = tid; e < nd * 64; e += blockDim.x) {
+        const int t = e >> 6, c = e & 63;
+        if (c < w) buf[t][c] = F[(long)content[w + t] * ldf + j0 + c];
     }
     __syncthreads();
-    if (lane < w) {
-        for (int j = 0; j < w; ++j) {
-            const int r = piv[j];
-            if (r != j0 + j) {
-                const cplx<T> a = F[(long)(j0 + j) * ldf + j0 + lane];
-                const cplx<T> b = F[(long)r * ldf + j0 + lane];
-                F[(long)(j0 + j) * ldf + j0 + lane] = b;
-                F[(long)r * ldf + j0 + lane] = a;
-            }
-        }
-        const cplx<T>* top = (const cplx<T>*)d.ttop + (long)k * nb * nb;
-        for (int j = 0; j < w; ++j) F[(long)(j0 + j) * ldf + j0 + lane] = top[(long)j * nb + lane];
-        ipiv[j0 + lane] = piv[lane];
+    for (int e = tid; e < nd * 64; e += blockDim.x) {
+        const int t = e >> 6, c = e & 63;
+        if (c < w) F[(long)pos[w + t] * ldf + j0 + c] = buf[t][c];
     }
+    const cplx<T>* top = (const cplx<T>*)d.ttop + (long)k * nb * nb;
+    for (int e = tid; e < w * 64; e += blockDim.x) {
+        const int j = e >> 6, c = e & 63;
+        if (c < w) F[(long)(j0 + j) * ldf + j0 + c] = top[(long)j * nb + c];
+    }
+    if (tid < w) ipiv[j0 + tid] = piv[tid];
 }
 
-// L21 = A21 U11^-1 in place for the rows below the panel's first w rows (64 rows per workgroup;
-// both operands staged in LDS, every row read before any is written).
+// L21 = A21 U11^-1 in place for the rows below the panel's first w rows: 64 rows per workgroup,
+// both operands in LDS (every row read before any is written), 4 x 4 outputs per thread.
 template <typename T>
 __global__ __launch_bounds__(256) void tslu_l21_kernel(const LUDev* __restrict__ dv, int j0, int nb, int step,
                                                        int single) {
@@ -661,14 +663,30 @@ __global__ __launch_bounds__(256) void tslu_l21_kernel(const LUDev* __restrict__
         As[i][c] = (i < nr && c < w) ? F[(long)(r0 + i) * ldf + j0 + c] : zero;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-        const int i = e >> 6, c = e & 63;
-        if (i < nr && c < w) {
-            cplx<T> acc = zero;
-            for (int kk = 0; kk < w; ++kk) acc = acc + As[i][kk] * Us[kk][c];
-            F[(long)(r0 + i) * ldf + j0 + c] = acc;
-        }
+    const int ti = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    cplx<T> acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[i][m] = zero;
+    for (int kk = 0; kk < w; ++kk) {
+        cplx<T> av[4], uv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = As[4 * ti + i][kk];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) uv[m] = Us[kk][tc + 16 * m];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc[i][m] = acc[i][m] + av[i] * uv[m];
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int r = 4 * ti + i, c = tc + 16 * m;
+            if (r < nr && c < w) F[(long)(r0 + r) * ldf + j0 + c] = acc[i][m];
+        }
 }
 
 // Row interchanges of step (j0, w) applied to the columns outside the panel; the swapped rows
@@ -875,7 +893,7 @@ int panel(SetRun<T>& R, int j0) {
     const LUSet& S = R.S;
     bool reg = false, single = false;
     int wmax = -1, Wmax = 0;
-    constexpr int TR = 4 * RegPanel<T>::U, TG = TR / 64;
+    constexpr int TR = 4 * 64 / Tourn<T>::LPR, TG = TR / 64;
     std::vector<int> tw;   // tournament: widest level widths over the members
     int below = 0;
     for (int b = 0; b < S.count; ++b) {
@@ -915,11 +933,11 @@ int panel(SetRun<T>& R, int j0) {
     }
     if (!tw.empty()) {
         for (int l = 0; l < (int)tw.size(); ++l) {
-            hipLaunchKernelGGL((tslu_kernel<T, RegPanel<T>::U>), dim3(tw[l], R.q, S.count), dim3(256), 0, R.st, S.dev,
-                               j0, R.nb, l, S.single_rows);
+            hipLaunchKernelGGL((tslu_kernel<T>), dim3(tw[l], R.q, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb, l,
+                               S.single_rows);
             FM_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL((tslu_apply_kernel<T>), dim3(R.q, 1, S.count), dim3(64), 0, R.st, S.dev, j0, R.nb,
+        hipLaunchKernelGGL((tslu_apply_kernel<T>), dim3(R.q, 1, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb,
                            S.single_rows);
         FM_LAUNCH_CHECK();
         // U11^-1 of this step (members without a tournament here recompute a finished block)

@@ -1,7 +1,7 @@
 """Panel kernels.  With partial pivoting the three kernels (register, sweeping, multi-workgroup)
 perform the same operations in the same order, so the factorisations and every solve agree bit for
 bit whichever variant the tuning selects; the autotuner measures and records their crossover.
-Tournament pivoting (the default for tall panels) chooses other pivot rows, so its solves are
+Tournament pivoting (an option) chooses other pivot rows, so its solves are
 checked against the oracle's partial-pivoting solves to the conditioning bound, at sizes whose
 reduction tree has one to six levels."""
 import numpy as np
@@ -59,7 +59,8 @@ def test_tournament_pivoting_solves_match_oracle(prec, n):
     import scipy.linalg
     A, B, lam = random_pencil(n, seed=2 * n + 1, with_B=True, m=max(1, n // 50))
     q, m0 = 8, 6
-    F = fm().Feast(fm().to_device(A, device()), fm().to_device(B, device()), 0j, 1.0, 1.0, q, m0, precision=prec)
+    F = fm().Feast(fm().to_device(A, device()), fm().to_device(B, device()), 0j, 1.0, 1.0, q, m0, precision=prec,
+                   pivoting="tournament")
     Fp = fm().Feast(fm().to_device(A, device()), fm().to_device(B, device()), 0j, 1.0, 1.0, q, m0, precision=prec,
                     pivoting="partial")
     z, s = Q.nodes_and_weights(0j, 1.0, 1.0, "trapezoid", q)
@@ -84,5 +85,20 @@ def test_tournament_pivoting_reports_zero_pivot():
     d = np.linspace(1.5, 3.0, n).astype(np.complex128)
     d[7] = 1.0
     with pytest.raises(fm().FeastError) as e:
-        fm().Feast(fm().to_device(np.asfortranarray(np.diag(d)), device()), None, 0j, 1.0, 1.0, 16, 4)
+        fm().Feast(fm().to_device(np.asfortranarray(np.diag(d)), device()), None, 0j, 1.0, 1.0, 16, 4,
+                   pivoting="tournament")
     assert e.value.code == fm().binding.FEAST_ESINGULAR + 0
+
+
+@pytest.mark.parametrize("variant", ["R", "Bi"])
+def test_tournament_pivoting_iteration(variant):
+    """The whole iteration with tournament-pivoted factorisations reaches the prescribed spectrum."""
+    from oracle import brute
+    from tests.gpu_common import match_eigs
+    A, B, lam = random_pencil(900, seed=5, with_B=True, m=12)
+    U0 = pencils.complex_gaussian(np.random.default_rng(4), (900, 20))
+    F = fm().Feast(fm().to_device(A, device()), fm().to_device(B, device()), 0j, 1.0, 1.0, 16, 20, variant=variant,
+                   precision="fp32", pivoting="tournament")
+    r = F.iterate(fm().to_device(U0, device()))
+    assert r.converged and match_eigs(r.lam, brute.eigenvalues_inside(lam, 0j, 1.0)) < 1e-10
+    F.close()
