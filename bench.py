@@ -50,6 +50,30 @@ def load_workload(name):
     return P, U0, ref, g
 
 
+def panel_bytes(n, q, elem, nb=64, reg_rows=None):
+    """Algorithmic bytes of the panel column steps of one factorisation and their launch count.
+
+    Launch j (0..w) of the panel at j0 reads and writes the columns >= j - 1 of rows >= j0 + j - 1
+    (the active part), for every node: 2 elem q (n - j0 - j') (w - j') bytes with j' = max(j - 1, 0).
+    Panels of at most reg_rows rows run as one register-panel launch reading and writing the whole
+    panel once."""
+    if reg_rows is None:
+        reg_rows = 64
+    total, launches = 0.0, 0
+    for j0 in range(0, n, nb):
+        w = min(nb, n - j0)
+        rows = n - j0
+        if rows <= reg_rows:
+            total += 2.0 * elem * q * rows * w
+            launches += 1
+            continue
+        for j in range(w + 1):
+            jp = max(j - 1, 0)
+            total += 2.0 * elem * q * (rows - jp) * (w - jp)
+            launches += 1
+    return total, launches
+
+
 def match_err(got, ref):
     from scipy.optimize import linear_sum_assignment
     if len(got) != len(ref):
@@ -186,7 +210,7 @@ def bench_batch(args, fm, torch, dev):
         return max(match_err(r.lam, ref) for r, ref in zip(res, refs))
 
     modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32") if m != args.mode])
-    tuning = tune_panels(fm, 16, modes, dev)
+    tuning = tune_panels(fm, 16, modes, dev) if args.tune else None
     out = {}
     for mode in modes:
         for _ in range(args.warmup):
@@ -262,8 +286,9 @@ def bench_m0(args, fm, torch, dev):
             b.close()
         return np.array(out)
 
-    tune_panels(fm, 8, ["fp32"], dev)
-    tune_panels(fm, 16, ["fp32"], dev)
+    if args.tune:
+        tune_panels(fm, 8, ["fp32"], dev)
+        tune_panels(fm, 16, ["fp32"], dev)
     t0 = time.perf_counter()
     Xtr = features(tr)
     torch.cuda.synchronize()
@@ -364,6 +389,7 @@ def main():
     ap.add_argument("--count", type=int, default=64, help="pencils of the batched workload (c2)")
     ap.add_argument("--variant", default=None, choices=["R", "Bi"],
                     help="R-FEAST (default for the n=4096 workload) or Bi-FEAST (default for n=8192)")
+    ap.add_argument("--tune", action="store_true", help="measure the panel-kernel crossover before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     args = ap.parse_args()
@@ -394,7 +420,7 @@ def main():
     torch.cuda.synchronize()
 
     modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32", "fp16") if m != args.mode])
-    tuning = tune_panels(fm, P.q, modes, dev)
+    tuning = tune_panels(fm, P.q, modes, dev) if args.tune else None
     out = {}
     for mode in modes:
         steps = args.steps if mode == args.mode else max(1, min(args.steps, 2))
@@ -426,13 +452,23 @@ def main():
         F.iterate(U0)
         ph_all = F.timing()
     dph = ph_all[dom]
-    prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else (
-        "fp16" if (args.mode == "fp16" and dom == "lu_update") else "fp32")
-    achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12 if dph["ms"] > 0 else 0.0
-    roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
-                    frac=achieved / PEAK[prec_of_phase], traffic=None, kernel_phase=dom,
-                    avg_launch_ms=dph["ms"] / max(1, dph["launches"]),
-                    flops_per_launch=dph["flops"] / max(1, dph["launches"]))
+    if dom == "lu_panel":
+        # the column steps of the panels: latency-bound launches that read and write the active part
+        # of the panel (HBM / infinity-cache traffic, no matrix-core work)
+        elem = 16 if args.mode == "fp64" else 8
+        nbytes, launches = panel_bytes(P.n, P.q, elem)
+        achieved = nbytes / (dph["ms"] * 1e-3) / 1e9
+        roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK, unit="GB/s", frac=achieved / HBM_PEAK,
+                        traffic=None, kernel="panel_step_kernel", kernel_phase=dom,
+                        avg_launch_ms=dph["ms"] / launches, bytes_per_launch=nbytes / launches, launches=launches)
+    else:
+        prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else (
+            "fp16" if (args.mode == "fp16" and dom == "lu_update") else "fp32")
+        achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12 if dph["ms"] > 0 else 0.0
+        roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
+                        frac=achieved / PEAK[prec_of_phase], traffic=None, kernel_phase=dom,
+                        avg_launch_ms=dph["ms"] / max(1, dph["launches"]),
+                        flops_per_launch=dph["flops"] / max(1, dph["launches"]))
     lu = ph_all["lu_update"]
     lu_roof = dict(achieved=lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0,
                    peak=PEAK[args.mode], unit="TFLOP/s", avg_launch_ms=lu["ms"] / max(1, lu["launches"]))

@@ -217,16 +217,17 @@ const char* feast_strerror(int code);
 
 /* ---- panel tuning -----------------------------------------------------------
  * Panels of n - j0 rows run as one of three kernels: the register panel (the
- * whole panel in one workgroup's registers, up to 128 rows in FP64 and 256 in
- * FP32), a single-workgroup panel that sweeps the rows from memory once per
+ * whole panel in one workgroup's registers, up to 64 rows), a single-workgroup panel that sweeps the rows from memory once per
  * column (one launch per panel), or the multi-workgroup panel (one launch per
  * column).  The sweep-or-multi crossover depends on the precision and on q.
  * feast_autotune times both on synthetic q-node panels of 256 .. 6144 rows
- * and keeps the largest row count at which the sweep is no slower; the result
+ * and keeps the largest row count at which the sweep is no slower (64 when it
+ * never is); the result
  * applies to contexts and batches set up afterwards in this process and is
  * written to cache_path (may be NULL) as "precision q rows" lines, which the
  * library reads at first use from the file named by FEAST_TUNE_CACHE.  times
- * (may be NULL) receives 10 triples (rows, sweep ms, multi ms).  Workspace:
+ * (may be NULL) receives 10 triples (rows, sweep ms, multi ms).  Without an
+ * entry, panels above the register panel use the multi-workgroup kernel.  Workspace:
  * feast_autotune_workspace_size bytes (device).  Synchronous.  Every variant
  * gives the same factorisation (same operations in the same order), so tuning
  * changes time only.  feast_set_panel_rows sets an entry directly. */

@@ -484,7 +484,7 @@ int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* 
 // records "precision q rows" lines in a cache file (FEAST_TUNE_CACHE names it), read once per
 // process.  Without an entry the default below applies.
 
-constexpr int DEFAULT_SINGLE_ROWS = 1024;
+constexpr int DEFAULT_SINGLE_ROWS = 0;   // measured: the sweeping panel never beats the multi-workgroup one
 
 struct TuneTable {
     std::mutex mu;

@@ -122,7 +122,7 @@ int lu_panel_only(const LUSet& S, int j0, hipStream_t st);
 // Fills `reals` FP64 (dbl) or FP32 values with deterministic pseudo-random numbers in [-0.5, 0.5).
 int lu_fill_random(void* p, long reals, bool dbl, unsigned long long seed, hipStream_t st);
 
-// Rows the register panel holds (128 in FP64, 256 in FP32).
+// Rows the register panel holds (64).
 int lu_reg_panel_rows(bool dbl);
 
 }  // namespace fm

@@ -66,9 +66,9 @@ __device__ inline int step_width(const LUDev& d, int j0, int nb) { return d.n > 
 // the multi-workgroup panel (one launch per column).
 enum PanelVariant { PV_NONE = 0, PV_REG = 1, PV_SINGLE = 2, PV_MULTI = 3, PV_TSLU = 4 };
 
-template <typename T> struct RegPanel;
-template <> struct RegPanel<double> { static constexpr int U = 32; };   // 128 rows, 128 VGPRs of data
-template <> struct RegPanel<float> { static constexpr int U = 64; };    // 256 rows, 128 VGPRs of data
+// (the register panel's cost per column grows with its row capacity, since every wave scans all
+// of its row slots: above 64 rows one multi-workgroup launch per column is faster, measured)
+template <typename T> struct RegPanel { static constexpr int U = PANEL_ROWS / 4; };   // 64 rows
 
 template <typename T>
 __host__ __device__ inline int panel_variant(int n, int j0, bool has_slots, int single, bool tslu = false) {

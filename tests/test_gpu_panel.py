@@ -35,7 +35,7 @@ def test_panel_variants_agree_bitwise(prec, n):
             outs.append(F.filter(U).clone())
             F.close()
     finally:
-        fm().set_panel_rows(prec, 8, 1024)
+        fm().set_panel_rows(prec, 8, 0)
     torch.cuda.synchronize()
     assert torch.equal(outs[0], outs[1])
     z, s = Q.nodes_and_weights(0j, 1.0, 1.0, "trapezoid", 8)
@@ -46,11 +46,11 @@ def test_panel_variants_agree_bitwise(prec, n):
 def test_autotune_records_crossover(tmp_path):
     path = tmp_path / "tune.txt"
     rows, table = fm().autotune("fp32", 16, cache_path=path, device=device())
-    assert rows in [256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144]
+    assert rows in [64, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144]
     assert np.all(table[:, 1] > 0) and np.all(table[:, 2] > 0)
     line = [l.split() for l in path.read_text().splitlines()]
     assert ["1", "16", str(rows)] in line
-    fm().set_panel_rows("fp32", 16, 1024)
+    fm().set_panel_rows("fp32", 16, 0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
