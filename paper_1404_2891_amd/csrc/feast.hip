@@ -49,6 +49,11 @@ struct Bump {
 
 int splitk_for(int K) { return std::max(1, std::min(64, K / 256)); }
 
+// n x n by n x m0 products (A Q, B Q, A^H V): with one 64 x 64 tile per workgroup they have only
+// (n / 64)(m0 / 64) workgroups, too few for 256 compute units when m0 = 64; up to this many K-splits
+// fill the chip
+constexpr int TALL_SPLITK = 4;
+
 }  // namespace
 
 struct feast_ctx {
@@ -80,6 +85,7 @@ struct feast_ctx {
     double* norms_d = nullptr;
     int* idx_d = nullptr;
     void* partial = nullptr;
+    void* partial2 = nullptr;        // split-K partials of the n x n by n x m0 products
     // host staging (pinned): h for synchronous transfers, pin for the asynchronous slots of the
     // iteration engine (each slot has one purpose, so enqueued copies never overwrite each other)
     char* h = nullptr;
@@ -179,6 +185,7 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->norms_d = b.take<double>(3 * p);
     c->idx_d = b.take<int>(p);
     c->partial = b.take<z64>(gemm_partial_elems(p, 2 * p, 1, splitk_for(n)));
+    c->partial2 = b.take<z64>(gemm_partial_elems(n, p, 1, TALL_SPLITK));
     (void)has_B;
 }
 
@@ -415,13 +422,24 @@ int apply(feast_ctx* c, int k0, int qv, int side, int ncols, const z64* rhs, lon
 }
 
 // out (n x ncols, column-major) = op(B) U, op = N (side 0) or H (side 1)
-int apply_B(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* out, long ldo) {
+// out (n x ncols) = op(M) U for an n x n column-major matrix M (op = N, or H when side != 0), split
+// over K when the product has fewer tiles than compute units
+int tall_product(feast_ctx* c, const z64* M, long ldm, int side, int ncols, const z64* U, long ldu, z64* out,
+                 long ldo) {
     GemmOp g;
-    g.A = c->B; g.lda = c->ldb; g.rowA = side != 0; g.conjA = side != 0;
+    g.A = M; g.lda = ldm; g.rowA = side != 0; g.conjA = side != 0;
     g.B = U; g.ldb = ldu;
     g.C = out; g.ldc = ldo;
     g.M = c->n; g.N = ncols; g.K = c->n;
+    const long tiles = (long)ceil_div(c->n, 64) * ceil_div(ncols, 64);
+    g.splitk = (int)std::max<long>(1, std::min<long>(TALL_SPLITK, 256 / std::max<long>(1, tiles)));
+    if (c->n < 1024) g.splitk = 1;
+    g.partial = c->partial2;
     return gemm<double>(g, c->st);
+}
+
+int apply_B(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* out, long ldo) {
+    return tall_product(c, c->B, c->ldb, side, ncols, U, ldu, out, ldo);
 }
 
 // C (p x N, column-major, ld p) = X^H Y for column-major n x p X and n x N Y (split-K over n)
@@ -870,10 +888,7 @@ int e_filter(Run& r) {
     if (is_bi(c)) {
         if (shifted) {
             // E_L = A^H V - B^H V conj(L), conj(rho)
-            GemmOp g;
-            g.A = c->A; g.lda = c->lda; g.rowA = true; g.conjA = true;
-            g.B = c->Vb; g.ldb = n; g.C = c->ElB; g.ldc = n; g.M = n; g.N = p; g.K = n;
-            FM_TRY(gemm<double>(g, st));
+            FM_TRY(tall_product(c, c->A, c->lda, 1, p, c->Vb, n, c->ElB, n));
             if (c->B) {
                 FM_TRY(apply_B(c, 1, p, c->Vb, n, c->BhV, n));
             } else {
@@ -953,12 +968,7 @@ int e_orth(Run& r, int pass) {
     // Rayleigh-Ritz: A^ = W^H A Q, B^ = W^H B Q with W = Q (R-FEAST) or P (Bi-FEAST)
     z64* Q = c->QAB;
     c->timer.start(PH_RR, st);
-    {
-        GemmOp g;
-        g.A = c->A; g.lda = c->lda; g.B = Q; g.ldb = n; g.C = Q + np; g.ldc = n;
-        g.M = n; g.N = p; g.K = n;
-        FM_TRY(gemm<double>(g, st));
-    }
+    FM_TRY(tall_product(c, c->A, c->lda, 0, p, Q, n, Q + np, n));
     if (c->B) {
         FM_TRY(apply_B(c, 0, p, Q, n, Q + 2 * np, n));
     } else {

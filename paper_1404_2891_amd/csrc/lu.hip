@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void panel_kernel(const LUDev* __restrict__ dv
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int r = r0 + 4 * u;
-                v[u] = (act && r < n) ? F[(long)r * ldf + j0 + lane] : cplx<T>(T(0), T(0));
+                v[u] = (act && lane + 1 >= j && r < n) ? F[(long)r * ldf + j0 + lane] : cplx<T>(T(0), T(0));
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void panel_kernel(const LUDev* __restrict__ dv
         const cplx<T> yv = act ? rp[lane] : cplx<T>(T(0), T(0));
         const cplx<T> xv = act ? rj[lane] : cplx<T>(T(0), T(0));
         __syncthreads();
-        if (wave == 0 && act && pr != j0 + j) {
+        if (wave == 0 && act && lane >= j && pr != j0 + j) {   // finished columns: deferred to swap_kernel
             rj[lane] = yv;
             rp[lane] = xv;
         }
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void panel_step_kernel(const LUDev* __restrict
     for (int u = 0; u < U; ++u) {
         const int r = rfirst + wave + 4 * u;
         v[u] = zero;
-        if (act && r < rend) v[u] = F[(long)r * ldf + j0 + lane];
+        if (act && lane + 1 >= j && r < rend) v[u] = F[(long)r * ldf + j0 + lane];   // active columns only
     }
     if (j > 0) {
         // 2. winner of column j - 1: lanes scan slots lane, lane + 64, ..., butterfly argmax
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void panel_step_kernel(const LUDev* __restrict
         }
         // 4. interchange: row rj takes the pivot row, the pivot row takes row rj
         if (pr != rj) {
-            if (wave == 0 && act && rj >= rbeg && rj < rend) F[(long)rj * ldf + j0 + lane] = prow;
+            if (wave == 0 && act && lane + 1 >= j && rj >= rbeg && rj < rend) F[(long)rj * ldf + j0 + lane] = prow;
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (rfirst + wave + 4 * u == pr) v[u] = rjv;
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) void panel_step_kernel(const LUDev* __restrict
                     v[u] = l;
                 else if (lane > j - 1)
                     v[u] = v[u] - l * prow;
-                if (act && (lane >= j - 1 || (r == pr && pr != rj))) F[(long)r * ldf + j0 + lane] = v[u];
+                if (act && lane >= j - 1) F[(long)r * ldf + j0 + lane] = v[u];
             }
         }
     }
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void panel_reg_kernel(const LUDev* __restrict_
         }
         __syncthreads();
         const cplx<T> prow = prow_s[par][lane];
-        if (pr != rj) {
+        if (pr != rj && lane >= j) {   // finished columns: deferred to swap_kernel
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (wave == wj && u == uj) v[u] = prow;
@@ -689,21 +689,23 @@ __global__ __launch_bounds__(256) void tslu_l21_kernel(const LUDev* __restrict__
         }
 }
 
-// Row interchanges of step (j0, w) applied to the columns outside the panel; the swapped rows
-// j0..j0+w-1 of the columns right of the panel are copied to tmp (row-major, ld n).
+// Row interchanges of step (j0, w) applied to the columns outside the panel, and to the panel's own
+// columns for the interchanges that came after each column was finished (the panel kernels only
+// swap the columns still active); the swapped rows j0..j0+w-1 of the columns right of the panel
+// are copied to tmp (row-major, ld n).  A tournament panel is written fully permuted already.
 template <typename T>
-__global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv, int j0, int nb) {
+__global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv, int j0, int nb, int single) {
     const LUDev& d = dv[blockIdx.z];
     const int w = step_width(d, j0, nb);
     const int k = blockIdx.y, n = d.n;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncols = n - w;
-    if (w == 0 || t >= ncols) return;
-    const int c = t < j0 ? t : t + w;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w == 0 || c >= n) return;
+    const bool in_panel = c >= j0 && c < j0 + w;
+    if (in_panel && member_variant<T>(d, j0, single) == PV_TSLU) return;
     const long ldf = d.ldf;
     cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
     const int* ipiv = d.ipiv + k * d.spiv;
-    for (int j = 0; j < w; ++j) {
+    for (int j = in_panel ? c - j0 + 1 : 0; j < w; ++j) {
         const int r = ipiv[j0 + j];
         if (r != j0 + j) {
             const cplx<T> a = F[(long)(j0 + j) * ldf + c];
@@ -1049,7 +1051,7 @@ int run_set(SetRun<T>& R) {
             const LUStore& s = S.s[b];
             if (s.n <= j0) continue;
             const int w = std::min(nb, s.n - j0), jn = j0 + w, nr = s.n - jn;
-            swap_cols = std::max(swap_cols, s.n - w);
+            swap_cols = std::max(swap_cols, s.n);
             if (nr <= 0) continue;
             cplx<T>* F = (cplx<T>*)s.F;
             // U12 = L_ss^-1 * (swapped rows staged in tmp); with FP16 updates its largest component
@@ -1064,13 +1066,12 @@ int run_set(SetRun<T>& R) {
         }
         R.start(PH_LU_OTHER);
         if (R.launching()) {
+            // interchanges first: the diagonal block's L part takes its deferred interchanges here
+            hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(swap_cols, 256), q, P), dim3(256), 0, R.st, S.dev, j0,
+                               nb, S.single_rows);
+            FM_LAUNCH_CHECK();
             hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q, P), dim3(64), 0, R.st, S.dev, nb, step);
             FM_LAUNCH_CHECK();
-            if (swap_cols > 0) {
-                hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(swap_cols, 256), q, P), dim3(256), 0, R.st, S.dev,
-                                   j0, nb);
-                FM_LAUNCH_CHECK();
-            }
         }
         GemmOp op;
         op.rowA = op.rowB = op.rowC = true;
