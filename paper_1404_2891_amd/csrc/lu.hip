@@ -721,9 +721,11 @@ __global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv,
 }
 
 // Inverses of diagonal blocks: UPPER = false -> unit lower part of block s, UPPER = true -> upper
-// part with its diagonal.  One wave per (block, node); thread j forms column j of the inverse.
+// part with its diagonal.  One workgroup per (block, node); four lanes form column j of the inverse
+// together (lanes 4 j .. 4 j + 3 of one wave), each summing every fourth term of a row's dot product,
+// combined by two butterfly shuffles; the column's entries follow one another through LDS.
 template <typename T, bool UPPER>
-__global__ __launch_bounds__(64) void trtri_kernel(const LUDev* __restrict__ dv, int nb, int s_first) {
+__global__ __launch_bounds__(256) void trtri_kernel(const LUDev* __restrict__ dv, int nb, int s_first) {
     const LUDev& d = dv[blockIdx.z];
     const int s = s_first + blockIdx.x, k = blockIdx.y;
     if (s >= d.nsteps) return;
@@ -736,30 +738,36 @@ __global__ __launch_bounds__(64) void trtri_kernel(const LUDev* __restrict__ dv,
     cplx<T>* Inv0 = (cplx<T>*)(UPPER ? d.Uinv : d.Linv);
     // the U12 scale slot of this node and step starts at zero (the U12 product merges into it)
     if (!UPPER && d.amax && threadIdx.x == 0) d.amax[k] = 0;
-    const int j = threadIdx.x;
-    for (int i = 0; i < w; ++i) {
-        if (j < w) M[i][j] = F[(long)(j0 + i) * ldf + j0 + j];
+    const cplx<T> zero(T(0), T(0));
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, c = e % nb;
+        M[i][c] = (i < w && c < w) ? F[(long)(j0 + i) * ldf + j0 + c] : zero;
+        X[i][c] = zero;
     }
-    for (int i = 0; i < nb; ++i) X[i][j] = cplx<T>(T(0), T(0));
     __syncthreads();
+    const int j = threadIdx.x >> 2, part = threadIdx.x & 3;
     if (j < w) {
         if (!UPPER) {
             for (int i = j; i < w; ++i) {
-                cplx<T> acc(i == j ? T(1) : T(0), T(0));
-                for (int kk = j; kk < i; ++kk) acc = acc - M[i][kk] * X[kk][j];
-                X[i][j] = acc;
+                cplx<T> acc = zero;
+                for (int kk = j + part; kk < i; kk += 4) acc = acc + M[i][kk] * X[kk][j];
+                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 1);
+                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 2);
+                if (part == 0) X[i][j] = cplx<T>(i == j ? T(1) : T(0), T(0)) - acc;
             }
         } else {
             for (int i = j; i >= 0; --i) {
-                cplx<T> acc(i == j ? T(1) : T(0), T(0));
-                for (int kk = i + 1; kk <= j; ++kk) acc = acc - M[i][kk] * X[kk][j];
-                X[i][j] = cdiv(acc, M[i][i]);
+                cplx<T> acc = zero;
+                for (int kk = i + 1 + part; kk <= j; kk += 4) acc = acc + M[i][kk] * X[kk][j];
+                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 1);
+                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 2);
+                if (part == 0) X[i][j] = cdiv(cplx<T>(i == j ? T(1) : T(0), T(0)) - acc, M[i][i]);
             }
         }
     }
     __syncthreads();
     cplx<T>* Inv = Inv0 + ((long)k * nsteps + s) * nb * nb;
-    for (int i = 0; i < nb; ++i) Inv[(long)i * nb + j] = X[i][j];
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Inv[e] = X[e / nb][e % nb];
 }
 
 // Combined permutation of the sequential interchanges: row i of P T is row perm[i] of T.
@@ -943,7 +951,7 @@ int panel(SetRun<T>& R, int j0) {
                            S.single_rows);
         FM_LAUNCH_CHECK();
         // U11^-1 of this step (members without a tournament here recompute a finished block)
-        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(1, R.q, S.count), dim3(64), 0, R.st, S.dev, R.nb, j0 / R.nb);
+        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(1, R.q, S.count), dim3(256), 0, R.st, S.dev, R.nb, j0 / R.nb);
         FM_LAUNCH_CHECK();
         if (below > 0) {
             hipLaunchKernelGGL((tslu_l21_kernel<T>), dim3(ceil_div(below, 64), R.q, S.count), dim3(256), 0, R.st,
@@ -1070,7 +1078,7 @@ int run_set(SetRun<T>& R) {
             hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(swap_cols, 256), q, P), dim3(256), 0, R.st, S.dev, j0,
                                nb, S.single_rows);
             FM_LAUNCH_CHECK();
-            hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q, P), dim3(64), 0, R.st, S.dev, nb, step);
+            hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q, P), dim3(256), 0, R.st, S.dev, nb, step);
             FM_LAUNCH_CHECK();
         }
         GemmOp op;
@@ -1090,7 +1098,7 @@ int run_set(SetRun<T>& R) {
         R.stop(PH_LU_PANEL, 0.0);
     }
     if (R.launching()) {
-        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(R.nsteps_max, q, P), dim3(64), 0, R.st, S.dev, nb, 0);
+        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(R.nsteps_max, q, P), dim3(256), 0, R.st, S.dev, nb, 0);
         FM_LAUNCH_CHECK();
         hipLaunchKernelGGL(perm_kernel, dim3(q, 1, P), dim3(256), R.nmax * sizeof(int), R.st, S.dev);
         FM_LAUNCH_CHECK();
