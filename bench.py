@@ -50,6 +50,25 @@ def load_workload(name):
     return P, U0, ref, g
 
 
+def measured_traffic(kernel, n, q, mode):
+    """HBM bytes per dispatch of `kernel` from the committed PMC record (profiles/pmc_traffic.json),
+    or None when the record is for another workload or the kernel's source has changed since."""
+    import hashlib
+    import re
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))[kernel]
+        src = open(os.path.join(ROOT, "paper_1404_2891_amd", "csrc", "lu.hip")).read()
+    except (OSError, KeyError, ValueError):
+        return None
+    m = re.search(r"template <typename T, int U>\n__global__ __launch_bounds__\(256\) void " + kernel + r".*?\n}\n", src,
+                  re.S)
+    if not m or hashlib.sha256(m.group(0).encode()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
+        return None
+    if (n, q, mode) != (4096, 24, "fp32"):
+        return None
+    return rec["bytes_per_dispatch"]
+
+
 def panel_bytes(n, q, elem, nb=64, reg_rows=None):
     """Algorithmic bytes of the panel column steps of one factorisation and their launch count.
 
@@ -459,7 +478,9 @@ def main():
         nbytes, launches = panel_bytes(P.n, P.q, elem)
         achieved = nbytes / (dph["ms"] * 1e-3) / 1e9
         roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK, unit="GB/s", frac=achieved / HBM_PEAK,
-                        traffic=None, kernel="panel_step_kernel", kernel_phase=dom,
+                        traffic=measured_traffic("panel_step_kernel", P.n, P.q, args.mode),
+                        traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
+                        kernel="panel_step_kernel", kernel_phase=dom,
                         avg_launch_ms=dph["ms"] / launches, bytes_per_launch=nbytes / launches, launches=launches)
     else:
         prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else (
