@@ -409,6 +409,9 @@ def main():
     ap.add_argument("--variant", default=None, choices=["R", "Bi"],
                     help="R-FEAST (default for the n=4096 workload) or Bi-FEAST (default for n=8192)")
     ap.add_argument("--tune", action="store_true", help="measure the panel-kernel crossover before timing")
+    ap.add_argument("--counters", action="store_true",
+                    help="run only a calibration kernel (elementwise multiply, 256 MiB in and out) and one "
+                         "factorisation of the workload, for hardware-counter runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     args = ap.parse_args()
@@ -421,6 +424,18 @@ def main():
     import paper_1404_2891_amd as fm
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = "cuda:0"
+    if args.counters:
+        x = torch.ones(64 * 2**20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.mul(x, 2.0, out=y)
+        torch.cuda.synchronize()
+        P, U0h, ref, g = load_workload(args.workload)
+        F = fm.Feast(fm.to_device(P.A, dev), fm.to_device(P.B, dev), P.center, P.radius, 1.0, P.q, P.m0,
+                     precision=args.mode)
+        torch.cuda.synchronize()
+        F.close()
+        log("counters run done")
+        return
     if args.workload == "c2":
         bench_batch(args, fm, torch, dev)
         return
