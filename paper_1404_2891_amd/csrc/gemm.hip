@@ -25,7 +25,10 @@ __device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_m
 __device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
 constexpr int BK = 16;
-constexpr int PAD = 2;
+// LDS row padding: the four k-rows a wave reads at once must cover the banks evenly.  FP32 rows of
+// BM + 8 words (8 mod 32 banks) give two accesses per bank, the minimum, for those reads and for the
+// tile stores; FP64 elements span two banks, so rows of BM + 2 already do.
+template <typename T> struct Pad { static constexpr int value = sizeof(T) == 4 ? 8 : 2; };
 
 // Row of the 16 x 16 output block held in accumulator element v of lane l (column l % 16):
 // the FP32 instruction stores rows 4 (l / 16) + v, the FP64 one rows l / 16 + 4 v.
@@ -56,6 +59,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile not divisible");
     typedef typename AccT<T>::type acc_t;
 
+    constexpr int PAD = Pad<T>::value;
     __shared__ T As[2][BK][BM + PAD];
     __shared__ T Bs[2][BK][BN + PAD];
 
@@ -166,15 +170,24 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
                 bre[c] = Bs[0][k][j];
                 bim[c] = Bs[1][k][j];
             }
+            // four passes over the blocks, so that consecutive matrix-core instructions never update
+            // the same accumulator
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    cre[r][c] = mfma4(are[r], bre[c], cre[r][c]);
-                    cre[r][c] = mfma4(-aim[r], bim[c], cre[r][c]);
-                    cim[r][c] = mfma4(are[r], bim[c], cim[r][c]);
-                    cim[r][c] = mfma4(aim[r], bre[c], cim[r][c]);
-                }
+                for (int c = 0; c < CB; ++c) cre[r][c] = mfma4(are[r], bre[c], cre[r][c]);
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cim[r][c] = mfma4(are[r], bim[c], cim[r][c]);
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cre[r][c] = mfma4(-aim[r], bim[c], cre[r][c]);
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cim[r][c] = mfma4(aim[r], bre[c], cim[r][c]);
         }
     }
 
