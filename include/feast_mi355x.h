@@ -93,6 +93,13 @@ typedef struct {
                             chosen by partial-pivoting LUs of row blocks and a reduction tree,
                             as in communication-avoiding LU: a few launches per panel instead of
                             one per column, but slower on MI355X as implemented here) */
+    int lookahead;       /* 0 (default): every launch on the caller's stream.  1: the trailing
+                            update of each factorisation step is split into the next panel's
+                            columns and the rest, and the next panel is factored on a second
+                            stream of the library's while the rest of the update runs (fork and
+                            join through events on the caller's stream).  Results are bitwise
+                            equal; on MI355X the panel and the update slow each other down about
+                            as much as they overlap, so it is off by default. */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */
@@ -297,7 +304,10 @@ void feast_mlp_destroy(feast_mlp* mlp);
  *
  * feast_batch_member: the context of pencil i, for feast_filter,
  * feast_node_solve or feast_iterate on that pencil alone (NULL when i is out
- * of range).  The batch owns it: do not pass it to feast_destroy.
+ * of range).  The batch owns it: do not pass it to feast_destroy.  Calls on a
+ * member run on the member's own stream, after the work already enqueued on
+ * the batch's `stream` (its inputs may be written there), and leave `stream`
+ * waiting for them (its outputs may be read there).
  *
  * feast_batch_iterate: runs feast_iterate on every pencil, all of them in
  * lockstep through the phases of the iteration (device work of the pencils

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libfeast_mi355x.so"
-SOURCES = ["gemm.hip", "lu.hip", "solve.hip", "feast.hip", "mlp.hip", "contour.cpp", "hostla.cpp"]
+SOURCES = ["tslu_f32.hip", "tslu_f64.hip", "gemm.hip", "lu.hip", "solve.hip", "feast.hip", "mlp.hip", "contour.cpp", "hostla.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 ARCH = "gfx950"

@@ -74,6 +74,15 @@ struct feast_ctx {
     LUDev* lu_dev = nullptr;          // device descriptor of this pencil's factor storage
     GemmGroup* lu_groups = nullptr;   // grouped-product members of its factorisation
     int lu_ngroups = 0;
+    // lookahead of the factorisation: a second stream and the fork/join events (created on the
+    // first factorisation when the options ask for it)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    // members of a batch: the batch's stream (possibly the null stream), which the public entry
+    // points order themselves against (see OuterOrder)
+    bool member = false;
+    hipStream_t outer = nullptr;
+    hipEvent_t outer_ev = nullptr;
     void *Yw = nullptr, *Xw = nullptr, *Ow = nullptr;
     z64 *Y64 = nullptr, *R64 = nullptr;
     double* nrm_d = nullptr;         // 2q + 1 doubles
@@ -556,7 +565,47 @@ LUSet ctx_set(feast_ctx* c) {
     one.groups = c->lu_groups;
     one.timer = c->lu.timer;
     one.single_rows = tuned_single_rows(c->prec, c->q);
+    one.side = c->side;
+    one.fork = c->fork;
+    one.join = c->join;
     return one;
+}
+
+// A public entry point called on a batch member: the member's stream starts after the work on the
+// batch's stream, and the batch's stream continues after the member's work.
+struct OuterOrder {
+    feast_ctx* c;
+    int rc = 0;
+    explicit OuterOrder(feast_ctx* cc) : c(cc) {
+        if (!c->member) return;
+        if (!c->outer_ev && hipEventCreateWithFlags(&c->outer_ev, hipEventDisableTiming) != hipSuccess) {
+            rc = FEAST_EDEVICE;
+            return;
+        }
+        if (hipEventRecord(c->outer_ev, c->outer) != hipSuccess || hipStreamWaitEvent(c->st, c->outer_ev, 0) != hipSuccess)
+            rc = FEAST_EDEVICE;
+    }
+    ~OuterOrder() {
+        if (!c->member || !c->outer_ev) return;
+        if (hipEventRecord(c->outer_ev, c->st) == hipSuccess) (void)hipStreamWaitEvent(c->outer, c->outer_ev, 0);
+    }
+};
+
+// Second stream and events of the lookahead (default priority; events without timing).
+int lookahead_create(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
+    if (*side) return 0;
+    FM_HIP(hipStreamCreateWithFlags(side, hipStreamNonBlocking));
+    FM_HIP(hipEventCreateWithFlags(fork, hipEventDisableTiming));
+    FM_HIP(hipEventCreateWithFlags(join, hipEventDisableTiming));
+    return 0;
+}
+
+void lookahead_destroy(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
+    if (*fork) (void)hipEventDestroy(*fork);
+    if (*join) (void)hipEventDestroy(*join);
+    if (*side) (void)hipStreamDestroy(*side);
+    *side = nullptr;
+    *fork = *join = nullptr;
 }
 
 int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C, int m0,
@@ -651,6 +700,7 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
 
 // a2 + a3: assemble and factor every node (enqueue only, no host synchronisation)
 int ctx_factor_enqueue(feast_ctx* c) {
+    if (c->o.lookahead) FM_TRY(lookahead_create(&c->side, &c->fork, &c->join));
     const LUSet one = ctx_set(c);
     return c->prec == Prec::F64 ? lu_factor_set<double>(one, c->st) : lu_factor_set<float>(one, c->st);
 }
@@ -684,6 +734,7 @@ void feast_default_options(feast_options* o) {
     o->timing = 0;
     o->rank_check = 0;
     o->pivoting = 0;
+    o->lookahead = 0;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -730,6 +781,8 @@ int feast_filter(feast_ctx* c, int side, int ncols, const void* U, int ldu, void
     if (!Q) return -6;
     if (ldq < c->n) return -7;
     c->ir_target = default_ir_target(c);
+    OuterOrder order(c);
+    if (order.rc) return order.rc;
     return filter_impl(c, side, ncols, (const z64*)U, ldu, (z64*)Q, ldq);
 }
 
@@ -743,6 +796,8 @@ int feast_node_solve(feast_ctx* c, int k, int side, int ncols, const void* R, in
     if (!Y) return -7;
     if (ldy < c->n) return -8;
     c->ir_target = default_ir_target(c);
+    OuterOrder order(c);
+    if (order.rc) return order.rc;
     return apply(c, k, 1, side, ncols, (const z64*)R, ldr, c->ones, (z64*)Y, ldy);
 }
 
@@ -1181,6 +1236,8 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
     if (ldu0 < c->n) return -3;
     if (!res || !res->lambda || !res->resid || !res->X || res->ldx < c->n) return -4;
     if (c->o.variant == FEAST_BI && res->Y && res->ldy < c->n) return -4;
+    OuterOrder order(c);
+    if (order.rc) return order.rc;
     Run r;
     r.c = c;
     r.U0 = (const z64*)U0;
@@ -1195,6 +1252,8 @@ void feast_destroy(feast_ctx* c) {
     if (!c) return;
     if (c->h) (void)hipHostFree(c->h);
     if (c->pin_base) (void)hipHostFree(c->pin_base);
+    lookahead_destroy(&c->side, &c->fork, &c->join);
+    if (c->outer_ev) (void)hipEventDestroy(c->outer_ev);
     delete c;
 }
 
@@ -1256,6 +1315,8 @@ int feast_probe_features(feast_ctx* c, const void* V, int ldv, int nprobe, float
     const int n = c->n;
     // Q = rho(M) V (the context's filter, nodes and precision)
     c->ir_target = default_ir_target(c);
+    OuterOrder order(c);
+    if (order.rc) return order.rc;
     FM_TRY(filter_impl(c, 0, nprobe, (const z64*)V, ldv, c->QAB, n));
     z64* t = (z64*)c->norms_d;   // 3 m0 doubles >= 2 nprobe
     hipLaunchKernelGGL(coldot_kernel, dim3(nprobe), dim3(256), 0, c->st, (const z64*)V, (long)ldv, c->QAB, (long)n, n, t);
@@ -1295,6 +1356,8 @@ struct feast_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float factor_ms = 0.0f;
+    hipStream_t side = nullptr;   // lookahead stream and events, forked from the capture stream
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -1339,6 +1402,7 @@ void batch_free(feast_batch* bt) {
         if (s) (void)hipStreamDestroy(s);
     if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
     if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    lookahead_destroy(&bt->side, &bt->fork, &bt->join);
     delete bt;
 }
 
@@ -1409,7 +1473,11 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         feast_ctx* c = nullptr;
         rc = ctx_create(&c, n[b], A[b], lda[b], B ? B[b] : nullptr, ldb ? ldb[b] : 0, &C[b], m0[b], o,
                         base + L.off[b], L.bytes[b], s);
-        if (c) bt->ctx.push_back(c);
+        if (c) {
+            c->member = true;
+            c->outer = bt->user;
+            bt->ctx.push_back(c);
+        }
         if (info) info[b] = rc;
     }
     // the set: descriptors and grouped-product table of all members, uploaded once
@@ -1427,6 +1495,12 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         S.dev = bt->dev;
         S.groups = bt->groups;
         S.single_rows = tuned_single_rows(bt->prec, C[0].q);
+        if (o->lookahead) {
+            rc = lookahead_create(&bt->side, &bt->fork, &bt->join);
+            S.side = bt->side;
+            S.fork = bt->fork;
+            S.join = bt->join;
+        }
         std::vector<GemmGroup> plan;
         if (bt->prec == Prec::F64)
             lu_plan<double>(S, plan);

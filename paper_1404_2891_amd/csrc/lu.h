@@ -48,8 +48,8 @@ struct LUStore {
     int tW0 = 0;
 };
 
-// Leaf blocks of the tournament for panels of up to n rows (rows per leaf = register panel rows).
-inline int tslu_leaf_blocks(int n, bool dbl) { return (n + (dbl ? 128 : 256) - 1) / (dbl ? 128 : 256); }
+// Leaf blocks of the tournament for panels of up to n rows (256 rows per leaf in both precisions).
+inline int tslu_leaf_blocks(int n, bool dbl) { (void)dbl; return (n + 255) / 256; }
 inline size_t tslu_cand_ints(int n, int q, bool dbl) { return (size_t)q * (2 * (size_t)tslu_leaf_blocks(n, dbl) * 64 + 64); }
 
 // Elements of the LU staging buffer per node: the panel swaps need nb * n, the composition of the
@@ -97,6 +97,12 @@ struct LUSet {
     // panels with more rows than the register panel holds and at most this many use the
     // single-workgroup sweeping panel, taller ones the multi-workgroup panel (see lu_tuned_rows)
     int single_rows = PANEL_ROWS;
+    // lookahead: with a side stream and two events (created without timing), the panel of step
+    // s + 1 runs on `side` while the part of step s's trailing update right of that panel runs on
+    // the launching stream (fork after the update of the panel's own columns, join before the
+    // interchanges of step s + 1); without them every launch stays on one stream
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // Descriptor of one member (real_bytes: 4 or 8, the precision of the storage).

@@ -20,6 +20,7 @@
 
 #include "gemm.h"
 #include "lu.h"
+#include "lu_dev.h"
 
 namespace fm {
 namespace {
@@ -55,39 +56,6 @@ __global__ __launch_bounds__(256) void assemble_kernel(const LUDev* __restrict__
             }
         }
     }
-}
-
-// Step (j0, w) of member d: w = min(nb, n - j0), or 0 when the member has no such step.
-__device__ inline int step_width(const LUDev& d, int j0, int nb) { return d.n > j0 ? min(nb, d.n - j0) : 0; }
-
-// Panel variants, by the number of rows n - j0 left: the register panel up to REG_ROWS<T> rows (one
-// workgroup, the whole panel in registers), the single-workgroup sweeping panel up to `single`
-// rows (tuned: it re-reads the panel from memory per column but needs one launch), and above that
-// the multi-workgroup panel (one launch per column).
-enum PanelVariant { PV_NONE = 0, PV_REG = 1, PV_SINGLE = 2, PV_MULTI = 3, PV_TSLU = 4 };
-
-// (the register panel's cost per column grows with its row capacity, since every wave scans all
-// of its row slots: above 64 rows one multi-workgroup launch per column is faster, measured)
-template <typename T> struct RegPanel { static constexpr int U = PANEL_ROWS / 4; };   // 64 rows
-
-template <typename T>
-__host__ __device__ inline int panel_variant(int n, int j0, bool has_slots, int single, bool tslu = false) {
-    const int rows = n - j0;
-    if (rows <= 0) return PV_NONE;
-    if (tslu) return PV_TSLU;
-    if (rows <= 4 * RegPanel<T>::U) return PV_REG;
-    if (rows <= single || !has_slots) return PV_SINGLE;
-    return PV_MULTI;
-}
-
-template <typename T>
-__device__ inline int member_variant(const LUDev& d, int j0, int single) {
-    return panel_variant<T>(d.n, j0, d.cval != nullptr, single, d.tslu != 0);
-}
-
-template <typename T>
-__device__ inline cplx<T> shfl_c(cplx<T> v, int src) {
-    return cplx<T>(__shfl(v.re, src), __shfl(v.im, src));
 }
 
 // Panel factorisation of rows j0..n-1, columns j0..j0+w-1 of one node per workgroup.
@@ -435,146 +403,6 @@ __global__ __launch_bounds__(256) void panel_reg_kernel(const LUDev* __restrict_
     }
 }
 
-// Tournament pivoting of a panel (communication-avoiding LU): the rows are split into blocks of R
-// rows; each block chooses w candidate pivot rows by an LU with partial pivoting of its rows, and a
-// reduction tree merges G = R / 64 candidate sets per workgroup the same way until one set of w
-// rows remains, in pivot order (largest |re| + |im|, lowest original row on ties).  Every level
-// reads the original panel rows (the panel is written only after the tree).
-//
-// In the local LUs each row lives in the registers of LPR lanes (one lane holds 64 / LPR of its
-// columns: LPR = 1 for FP32, 2 for FP64), so the pivot search of a column is a wave reduction and
-// the update of a row is register arithmetic against the pivot row broadcast through LDS.
-template <typename T> struct Tourn;
-template <> struct Tourn<double> { static constexpr int LPR = 2; };
-template <> struct Tourn<float> { static constexpr int LPR = 1; };
-
-__device__ inline int tslu_width(int rows, int R, int G, int level) {
-    int W = (rows + R - 1) / R;
-    for (int l = 1; l <= level; ++l) W = W > 1 ? (W + G - 1) / G : 0;
-    return W;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv, int j0, int nb, int level, int single) {
-    constexpr int LPR = Tourn<T>::LPR, CPL = 64 / LPR, RPW = 64 / LPR, R = 4 * RPW, G = R / 64;
-    const LUDev& d = dv[blockIdx.z];
-    const int w = step_width(d, j0, nb);
-    if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
-    const int n = d.n, rows = n - j0;
-    const int W = tslu_width(rows, R, G, level);
-    const int g = blockIdx.x, k = blockIdx.y;
-    if (g >= W) return;
-    const bool root = W == 1;
-    const int Win = level > 0 ? tslu_width(rows, R, G, level - 1) : 0;
-    const long ldf = d.ldf;
-    const cplx<T>* F = (const cplx<T>*)d.F + k * d.sF;
-    int* cl = d.tcand + (long)k * (2L * d.tW0 * 64 + 64);
-    const int* in = cl + (long)((level - 1) & 1) * d.tW0 * 64;
-    int* out = root ? cl + 2L * d.tW0 * 64 : cl + (long)(level & 1) * d.tW0 * 64;
-    cplx<T>* top = (cplx<T>*)d.ttop + (long)k * nb * nb;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int h = lane % LPR;                       // part of the row: columns h CPL .. h CPL + CPL - 1
-    const int p = wave * RPW + lane / LPR;          // row slot
-    const cplx<T> zero(T(0), T(0));
-    __shared__ cplx<T> prow[2][64];
-    __shared__ T rval[4];
-    __shared__ int rrow[4], rpos[4], sel[64];
-
-    int row;
-    if (level == 0) {
-        row = j0 + g * R + p;
-        if (row >= n) row = -1;
-    } else {
-        const int idx = g * G * 64 + p;
-        row = idx < Win * 64 ? in[idx] : -1;
-    }
-    bool active = row >= 0;
-    cplx<T> a[CPL];
-#pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) {
-        const int c = h * CPL + cc;
-        a[cc] = (active && c < w) ? F[(long)row * ldf + j0 + c] : zero;
-    }
-    int nsel = w;
-    for (int j = 0; j < w; ++j) {
-        const int par = j & 1, hj = j / CPL, jj = j % CPL;
-        // candidate of this wave: (largest value, lowest row)
-        T val = T(-1);
-        if (active && h == hj) {
-#pragma unroll
-            for (int cc = 0; cc < CPL; ++cc)
-                if (cc == jj) val = abs1(a[cc]);
-        }
-        int key = (active && h == hj) ? row : INT_MAX;
-        int ps = p;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const T v2 = __shfl_xor(val, o);
-            const int r2 = __shfl_xor(key, o), p2 = __shfl_xor(ps, o);
-            if (v2 > val || (v2 == val && r2 < key)) {
-                val = v2;
-                key = r2;
-                ps = p2;
-            }
-        }
-        if (lane == 0) {
-            rval[wave] = val;
-            rrow[wave] = key;
-            rpos[wave] = ps;
-        }
-        __syncthreads();
-        T pv = rval[0];
-        int pr = rrow[0], pp = rpos[0];
-#pragma unroll
-        for (int t = 1; t < 4; ++t)
-            if (rval[t] > pv || (rval[t] == pv && rrow[t] < pr)) {
-                pv = rval[t];
-                pr = rrow[t];
-                pp = rpos[t];
-            }
-        if (pv < T(0)) {   // no row left: the set supplies j candidates
-            nsel = j;
-            break;
-        }
-        // the winner publishes its row (and, at the root, its factored row) and leaves the set
-        if (p == pp) {
-#pragma unroll
-            for (int cc = 0; cc < CPL; ++cc) {
-                const int c = h * CPL + cc;
-                prow[par][c] = a[cc];
-                if (root && c < w) top[(long)j * nb + c] = a[cc];
-            }
-            if (h == 0) sel[j] = row;
-            active = false;
-        }
-        if (pv <= T(0) && root && threadIdx.x == 0 && d.info[k] == 0) d.info[k] = j0 + j + 1;
-        __syncthreads();
-        // scaling and rank-1 update of the rows still in the set
-        const cplx<T> piv = prow[par][j];
-        const cplx<T> invp = pv > T(0) ? cdiv(cplx<T>(T(1), T(0)), piv) : zero;
-        cplx<T> l = zero;
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc)
-            if (cc == jj) l = a[cc] * invp;
-        if (LPR > 1) {
-            const int src = (lane - h) + hj;
-            l = cplx<T>(__shfl(l.re, src), __shfl(l.im, src));
-        }
-        if (active) {
-#pragma unroll
-            for (int cc = 0; cc < CPL; ++cc) {
-                const int c = h * CPL + cc;
-                if (c == j)
-                    a[cc] = l;
-                else if (c > j)
-                    a[cc] = a[cc] - l * prow[par][c];
-            }
-        }
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < 64; j += blockDim.x) out[g * 64 + j] = j < nsel ? sel[j] : -1;
-}
-
 // After the tournament: the winners' row interchanges as sequential swaps (ipiv), the panel rows
 // they displace moved to their final places, and the root's factored rows written on top.
 template <typename T>
@@ -903,7 +731,7 @@ int panel(SetRun<T>& R, int j0) {
     const LUSet& S = R.S;
     bool reg = false, single = false;
     int wmax = -1, Wmax = 0;
-    constexpr int TR = 4 * 64 / Tourn<T>::LPR, TG = TR / 64;
+    constexpr int TR = TSLU_ROWS, TG = TR / 64;
     std::vector<int> tw;   // tournament: widest level widths over the members
     int below = 0;
     for (int b = 0; b < S.count; ++b) {
@@ -943,9 +771,7 @@ int panel(SetRun<T>& R, int j0) {
     }
     if (!tw.empty()) {
         for (int l = 0; l < (int)tw.size(); ++l) {
-            hipLaunchKernelGGL((tslu_kernel<T>), dim3(tw[l], R.q, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb, l,
-                               S.single_rows);
-            FM_LAUNCH_CHECK();
+            FM_TRY(tslu_local_launch<T>(dim3(tw[l], R.q, S.count), S.dev, j0, R.nb, l, S.single_rows, R.st));
         }
         hipLaunchKernelGGL((tslu_apply_kernel<T>), dim3(R.q, 1, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb,
                            S.single_rows);
@@ -1052,7 +878,8 @@ int run_set(SetRun<T>& R) {
     R.stop(PH_LU_PANEL, 0.0);
     for (int step = 0; step < R.nsteps_max; ++step) {
         const int j0 = step * nb;
-        std::vector<GemmGroup> u12, upd;
+        // the trailing update in two parts: the columns of the next panel, then the rest
+        std::vector<GemmGroup> u12, upd_next, upd_rest;
         int swap_cols = 0;
         double flops = 0.0;
         for (int b = 0; b < P; ++b) {
@@ -1067,9 +894,14 @@ int run_set(SetRun<T>& R) {
             int* amax = s.half ? s.amax : nullptr;
             u12.push_back(member((cplx<T>*)s.Linv + (long)step * nb * nb, nb, (long)s.nsteps * nb * nb, 0, s.tmp, s.n,
                                  (long)nb * s.n, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0, w, nr, w, q, amax));
-            // A22 -= L21 * U12
-            upd.push_back(member(F + (long)jn * s.ldf + j0, s.ldf, s.sF, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0,
-                                 F + (long)jn * s.ldf + jn, s.ldf, s.sF, 0, nr, nr, w, q, amax));
+            // A22 -= L21 * U12, columns jn .. jn + nn - 1 first, then the columns right of them
+            const int nn = std::min(nb, nr);
+            upd_next.push_back(member(F + (long)jn * s.ldf + j0, s.ldf, s.sF, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF,
+                                      0, F + (long)jn * s.ldf + jn, s.ldf, s.sF, 0, nr, nn, w, q, amax));
+            if (nr > nn)
+                upd_rest.push_back(member(F + (long)jn * s.ldf + j0, s.ldf, s.sF, 0, F + (long)j0 * s.ldf + jn + nn,
+                                          s.ldf, s.sF, 0, F + (long)jn * s.ldf + jn + nn, s.ldf, s.sF, 0, nr, nr - nn,
+                                          w, q, amax));
             flops += 8.0 * nr * (double)nr * w * q;
         }
         R.start(PH_LU_OTHER);
@@ -1085,17 +917,38 @@ int run_set(SetRun<T>& R) {
         op.rowA = op.rowB = op.rowC = true;
         FM_TRY(R.grouped(u12, op));
         R.stop(PH_LU_OTHER, 0.0);
-        if (upd.empty()) break;
+        if (upd_next.empty()) break;
         GemmOp up = op;
         up.alpha = z64(-1.0);
         up.beta = z64(1.0);
         up.kind = S.s[0].half ? 2 : 1;
+        // The next panel reads and writes only its own columns (rows >= j0 + nb), which upd_next
+        // finishes; upd_rest writes only the columns right of it and reads L21 and U12 of this step,
+        // which the panel leaves alone.  The interchanges of the next step touch both, after the join.
+        const bool ahead = R.launching() && S.side && S.fork && S.join;
         R.start(PH_LU_UPDATE);
-        FM_TRY(R.grouped(upd, up));
-        R.stop(PH_LU_UPDATE, flops);
-        R.start(PH_LU_PANEL);
-        FM_TRY(panel<T>(R, j0 + nb));
-        R.stop(PH_LU_PANEL, 0.0);
+        FM_TRY(R.grouped(upd_next, up));
+        if (ahead) {
+            hipStream_t main = R.st;
+            FM_HIP(hipEventRecord(S.fork, main));
+            FM_HIP(hipStreamWaitEvent(S.side, S.fork, 0));
+            R.st = S.side;
+            R.start(PH_LU_PANEL);
+            const int rc = panel<T>(R, j0 + nb);
+            R.stop(PH_LU_PANEL, 0.0);
+            R.st = main;
+            if (rc) return rc;
+            FM_HIP(hipEventRecord(S.join, S.side));
+            FM_TRY(R.grouped(upd_rest, up));
+            R.stop(PH_LU_UPDATE, flops);
+            FM_HIP(hipStreamWaitEvent(main, S.join, 0));
+        } else {
+            FM_TRY(R.grouped(upd_rest, up));
+            R.stop(PH_LU_UPDATE, flops);
+            R.start(PH_LU_PANEL);
+            FM_TRY(panel<T>(R, j0 + nb));
+            R.stop(PH_LU_PANEL, 0.0);
+        }
     }
     if (R.launching()) {
         hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(R.nsteps_max, q, P), dim3(256), 0, R.st, S.dev, nb, 0);
