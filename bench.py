@@ -103,7 +103,7 @@ def match_err(got, ref):
 
 
 def run_steps(fm, torch, A, B, U0, P, mode, steps, warmup, ws, timing, variant="R", lookahead=False,
-              pivoting="partial"):
+              pivoting="tournament"):
     kw = dict(center=P.center, radius=P.radius, aspect=1.0, q=P.q, m0=P.m0, precision=mode, workspace=ws,
               variant=variant, lookahead=lookahead, pivoting=pivoting)
     results = []
@@ -208,7 +208,8 @@ def bench_batch(args, fm, torch, dev):
 
     def batched(mode):
         t = time.perf_counter()
-        b = fm.FeastBatch(mats, (0j, 1.0, 1.0), m0=m0s, q=16, precision=mode, lookahead=args.lookahead)
+        b = fm.FeastBatch(mats, (0j, 1.0, 1.0), m0=m0s, q=16, precision=mode, lookahead=args.lookahead,
+                          pivoting=args.pivoting)
         t_setup = time.perf_counter() - t
         res, rcs = b.iterate(U0s)
         torch.cuda.synchronize()
@@ -221,7 +222,8 @@ def bench_batch(args, fm, torch, dev):
         t = time.perf_counter()
         res = []
         for (A, B), U0, m0 in zip(mats, U0s, m0s):
-            with fm.Feast(A, B, 0j, 1.0, 1.0, 16, m0, precision=mode, lookahead=args.lookahead) as F:
+            with fm.Feast(A, B, 0j, 1.0, 1.0, 16, m0, precision=mode, lookahead=args.lookahead,
+                         pivoting=args.pivoting) as F:
                 res.append(F.iterate(U0))
         torch.cuda.synchronize()
         return time.perf_counter() - t, res
@@ -267,7 +269,8 @@ def bench_batch(args, fm, torch, dev):
         "config": {"workload": f"{len(P)} pencils, n ~ U{{256..2048}}, prescribed spectra, unit circle, q=16, "
                                f"m0 in {{16, 32}}, R-FEAST, tol 1e-10, one factorisation graph",
                    "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
-                   "step": "batch setup (one graph: assembly + 16 LUs per pencil) + lockstep iterations to 1e-10"},
+                   "step": "batch setup (one graph: assembly + 16 LUs per pencil) + lockstep iterations to 1e-10",
+                   "pivoting": args.pivoting},
         "time_to_1e10_s": head["ms_per_step"] / 1e3,
         "eig_err_vs_oracle": head["eig_err_vs_oracle"],
         "batched_speedup_vs_one_at_a_time": head["batched_speedup"],
@@ -413,7 +416,7 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="run only a calibration kernel (elementwise multiply, 256 MiB in and out) and one "
                          "factorisation of the workload, for hardware-counter runs")
-    ap.add_argument("--pivoting", default="partial", choices=["partial", "tournament"])
+    ap.add_argument("--pivoting", default="tournament", choices=["tournament", "partial"])
     ap.add_argument("--lookahead", action="store_true",
                     help="factor each next panel on a second stream beside the rest of the trailing update")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -453,7 +456,8 @@ def main():
     B = fm.to_device(P.B, dev)
     U0 = fm.to_device(U0h, dev)
     nbytes = max(fm.workspace_size(P.n, P.m0, fm.binding.make_contour(P.center, P.radius, 1.0, P.q),
-                                   fm.binding.make_options(m, variant), True) for m in ("fp32", "fp64"))
+                                   fm.binding.make_options(m, variant, pivoting=args.pivoting), True)
+                   for m in ("fp32", "fp64"))
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 

@@ -88,11 +88,13 @@ typedef struct {
                             all m0 of them) and at least m0 - 2 Ritz values lie inside C: the
                             subspace may be smaller than the eigenvalue count (Section 4 asks
                             m0 >= m); the caller grows m0 and starts again */
-    int pivoting;        /* row pivoting of the node factorisations: 0 (default) partial
-                            pivoting (LAPACK's pivots); 1 tournament pivoting (candidate rows
-                            chosen by partial-pivoting LUs of row blocks and a reduction tree,
-                            as in communication-avoiding LU: a few launches per panel instead of
-                            one per column, but slower on MI355X as implemented here) */
+    int pivoting;        /* row pivoting of the node factorisations: 1 (default) tournament
+                            pivoting (the pivot rows of each 64-column panel chosen by
+                            partial-pivoting LUs of 256-row blocks and a reduction tree, as in
+                            communication-avoiding LU: a few launches per panel instead of one
+                            per column); 0 partial pivoting (LAPACK's pivots).  Both give
+                            backward-stable factors in practice; the solves agree with each
+                            other to the conditioning of the node systems. */
     int lookahead;       /* 0 (default): every launch on the caller's stream.  1: the trailing
                             update of each factorisation step is split into the next panel's
                             columns and the rest, and the next panel is factored on a second

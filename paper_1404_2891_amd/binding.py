@@ -188,7 +188,7 @@ PIVOTING = {"partial": 0, "tournament": 1}
 
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0, timing=False, rank_check=False, pivoting="partial", lookahead=False) -> Options:
+                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament", lookahead=False) -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -289,7 +289,7 @@ class Feast:
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
-                 timing=False, workspace=None, rank_check=False, pivoting="partial", lookahead=False):
+                 timing=False, workspace=None, rank_check=False, pivoting="tournament", lookahead=False):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
@@ -414,7 +414,7 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False, pivoting="partial", lookahead=False):
+                 rank_check=False, pivoting="tournament", lookahead=False):
         torch = _torch()
         count = len(pencils)
         self.count = count

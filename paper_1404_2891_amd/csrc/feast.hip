@@ -733,7 +733,7 @@ void feast_default_options(feast_options* o) {
     o->ir_tol = 0.0;
     o->timing = 0;
     o->rank_check = 0;
-    o->pivoting = 0;
+    o->pivoting = 1;
     o->lookahead = 0;
 }
 

@@ -34,8 +34,9 @@ def test_unrefined_solve_matches_fp16_emulation_level(n):
     above FP32), node by node."""
     A, B, lam = random_pencil(n, seed=n + 7, with_B=True, cond=3.0)
     q, m0 = 8, 6
-    F = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, q, m0, precision="fp16", ir_max=0)
-    F32 = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, q, m0, precision="fp32", ir_max=0)
+    # partial pivoting: the emulation factors with LAPACK's pivots
+    F = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, q, m0, precision="fp16", ir_max=0, pivoting="partial")
+    F32 = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, q, m0, precision="fp32", ir_max=0, pivoting="partial")
     z, s = Q.nodes_and_weights(0j, 1.0, 1.0, "trapezoid", q)
     rhs = pencils.complex_gaussian(np.random.default_rng(n), (n, m0))
     rd = upload(rhs)

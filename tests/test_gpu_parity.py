@@ -76,10 +76,11 @@ def test_singular_node_is_reported():
 @pytest.mark.parametrize("n,q,m0", [(64, 8, 8), (200, 16, 16), (321, 16, 5), (513, 24, 33)])
 @pytest.mark.parametrize("with_B", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_filter_matches_oracle(n, q, m0, with_B, prec):
+@pytest.mark.parametrize("pivoting", ["tournament", "partial"])
+def test_filter_matches_oracle(n, q, m0, with_B, prec, pivoting):
     A, B, lam = random_pencil(n, seed=3 * n + q, with_B=with_B)
     c, R = 0.02 - 0.01j, 1.0
-    F = fm().Feast(upload(A), upload(B), c, R, 1.0, q, m0, precision=prec)
+    F = fm().Feast(upload(A), upload(B), c, R, 1.0, q, m0, precision=prec, pivoting=pivoting)
     z, s = Q.nodes_and_weights(c, R, 1.0, "trapezoid", q)
     lus = feast.factor_nodes(A, B, z)
     U = pencils.complex_gaussian(np.random.default_rng(n), (n, m0))
