@@ -549,16 +549,21 @@ __global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv,
 }
 
 // Inverses of diagonal blocks: UPPER = false -> unit lower part of block s, UPPER = true -> upper
-// part with its diagonal.  One workgroup per (block, node); four lanes form column j of the inverse
-// together (lanes 4 j .. 4 j + 3 of one wave), each summing every fourth term of a row's dot product,
-// combined by two butterfly shuffles; the column's entries follow one another through LDS.
+// part with its diagonal.  One workgroup per (block, node), everything in LDS, by recursive
+// doubling: the eight 8 x 8 diagonal blocks are inverted by substitution (one column per thread),
+// then pairs of h x h blocks (h = 8, 16, 32) are joined with two products each,
+//   lower  X21 = -X22 (M21 X11),   upper  X12 = -X11 (M12 X22),
+// every output entry a dot product of length h.  A partial last block (w < nb) is extended by the
+// identity; the inverse is stored with zeros outside its w x w part.
 template <typename T, bool UPPER>
 __global__ __launch_bounds__(256) void trtri_kernel(const LUDev* __restrict__ dv, int nb, int s_first) {
+    static_assert(NBMAX == 64, "blocks of 64");
     const LUDev& d = dv[blockIdx.z];
     const int s = s_first + blockIdx.x, k = blockIdx.y;
     if (s >= d.nsteps) return;
     __shared__ cplx<T> M[NBMAX][NBMAX + 1];
     __shared__ cplx<T> X[NBMAX][NBMAX + 1];
+    __shared__ cplx<T> Tm[32 * 33];
     const int n = d.n, nsteps = d.nsteps;
     const long ldf = d.ldf;
     const int j0 = s * nb, w = min(nb, n - j0);
@@ -566,36 +571,65 @@ __global__ __launch_bounds__(256) void trtri_kernel(const LUDev* __restrict__ dv
     cplx<T>* Inv0 = (cplx<T>*)(UPPER ? d.Uinv : d.Linv);
     // the U12 scale slot of this node and step starts at zero (the U12 product merges into it)
     if (!UPPER && d.amax && threadIdx.x == 0) d.amax[k] = 0;
-    const cplx<T> zero(T(0), T(0));
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, c = e % nb;
-        M[i][c] = (i < w && c < w) ? F[(long)(j0 + i) * ldf + j0 + c] : zero;
+    const cplx<T> zero(T(0), T(0)), one(T(1), T(0));
+    for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
+        const int i = e >> 6, c = e & 63;
+        M[i][c] = (i < w && c < w) ? F[(long)(j0 + i) * ldf + j0 + c] : (i == c ? one : zero);
         X[i][c] = zero;
     }
     __syncthreads();
-    const int j = threadIdx.x >> 2, part = threadIdx.x & 3;
-    if (j < w) {
+    // 1. the 8 x 8 diagonal blocks, column j by thread j
+    if (threadIdx.x < 64) {
+        const int j = threadIdx.x, b0 = j & ~7;
         if (!UPPER) {
-            for (int i = j; i < w; ++i) {
+            X[j][j] = one;
+            for (int i = j + 1; i < b0 + 8; ++i) {
                 cplx<T> acc = zero;
-                for (int kk = j + part; kk < i; kk += 4) acc = acc + M[i][kk] * X[kk][j];
-                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 1);
-                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 2);
-                if (part == 0) X[i][j] = cplx<T>(i == j ? T(1) : T(0), T(0)) - acc;
+                for (int kk = j; kk < i; ++kk) acc = acc + M[i][kk] * X[kk][j];
+                X[i][j] = zero - acc;
             }
         } else {
-            for (int i = j; i >= 0; --i) {
+            X[j][j] = cdiv(one, M[j][j]);
+            for (int i = j - 1; i >= b0; --i) {
                 cplx<T> acc = zero;
-                for (int kk = i + 1 + part; kk <= j; kk += 4) acc = acc + M[i][kk] * X[kk][j];
-                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 1);
-                acc = acc + shfl_c(acc, (threadIdx.x & 63) ^ 2);
-                if (part == 0) X[i][j] = cdiv(cplx<T>(i == j ? T(1) : T(0), T(0)) - acc, M[i][i]);
+                for (int kk = i + 1; kk <= j; ++kk) acc = acc + M[i][kk] * X[kk][j];
+                X[i][j] = cdiv(zero - acc, M[i][i]);
             }
         }
     }
     __syncthreads();
+    // 2. doubling
+    for (int h = 8; h < 64; h *= 2) {
+        const int outs = (64 / (2 * h)) * h * h;   // entries of all pairs' h x h products
+        for (int e = threadIdx.x; e < outs; e += blockDim.x) {
+            const int p = e / (h * h), r = (e / h) % h, c = e % h, o = 2 * h * p;
+            cplx<T> acc = zero;
+            if (!UPPER)
+                for (int kk = 0; kk < h; ++kk) acc = acc + M[o + h + r][o + kk] * X[o + kk][o + c];
+            else
+                for (int kk = 0; kk < h; ++kk) acc = acc + M[o + r][o + h + kk] * X[o + h + kk][o + h + c];
+            Tm[p * h * h + r * h + c] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < outs; e += blockDim.x) {
+            const int p = e / (h * h), r = (e / h) % h, c = e % h, o = 2 * h * p;
+            const cplx<T>* Tp = Tm + p * h * h;
+            cplx<T> acc = zero;
+            if (!UPPER) {
+                for (int kk = 0; kk < h; ++kk) acc = acc + X[o + h + r][o + h + kk] * Tp[kk * h + c];
+                X[o + h + r][o + c] = zero - acc;
+            } else {
+                for (int kk = 0; kk < h; ++kk) acc = acc + X[o + r][o + kk] * Tp[kk * h + c];
+                X[o + r][o + h + c] = zero - acc;
+            }
+        }
+        __syncthreads();
+    }
     cplx<T>* Inv = Inv0 + ((long)k * nsteps + s) * nb * nb;
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) Inv[e] = X[e / nb][e % nb];
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, c = e % nb;
+        Inv[e] = (i < w && c < w) ? X[i][c] : zero;
+    }
 }
 
 // Combined permutation of the sequential interchanges: row i of P T is row perm[i] of T.
