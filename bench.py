@@ -102,10 +102,9 @@ def match_err(got, ref):
     return float(C[r, c].max())
 
 
-def run_steps(fm, torch, A, B, U0, P, mode, steps, warmup, ws, timing, variant="R", lookahead=False,
-              pivoting="tournament"):
+def run_steps(fm, torch, A, B, U0, P, mode, steps, warmup, ws, timing, variant="R", pivoting="tournament"):
     kw = dict(center=P.center, radius=P.radius, aspect=1.0, q=P.q, m0=P.m0, precision=mode, workspace=ws,
-              variant=variant, lookahead=lookahead, pivoting=pivoting)
+              variant=variant, pivoting=pivoting)
     results = []
     for _ in range(warmup):
         with fm.Feast(A, B, timing=False, **kw) as F:
@@ -208,8 +207,7 @@ def bench_batch(args, fm, torch, dev):
 
     def batched(mode):
         t = time.perf_counter()
-        b = fm.FeastBatch(mats, (0j, 1.0, 1.0), m0=m0s, q=16, precision=mode, lookahead=args.lookahead,
-                          pivoting=args.pivoting)
+        b = fm.FeastBatch(mats, (0j, 1.0, 1.0), m0=m0s, q=16, precision=mode, pivoting=args.pivoting)
         t_setup = time.perf_counter() - t
         res, rcs = b.iterate(U0s)
         torch.cuda.synchronize()
@@ -222,8 +220,7 @@ def bench_batch(args, fm, torch, dev):
         t = time.perf_counter()
         res = []
         for (A, B), U0, m0 in zip(mats, U0s, m0s):
-            with fm.Feast(A, B, 0j, 1.0, 1.0, 16, m0, precision=mode, lookahead=args.lookahead,
-                         pivoting=args.pivoting) as F:
+            with fm.Feast(A, B, 0j, 1.0, 1.0, 16, m0, precision=mode, pivoting=args.pivoting) as F:
                 res.append(F.iterate(U0))
         torch.cuda.synchronize()
         return time.perf_counter() - t, res
@@ -417,8 +414,6 @@ def main():
                     help="run only a calibration kernel (elementwise multiply, 256 MiB in and out) and one "
                          "factorisation of the workload, for hardware-counter runs")
     ap.add_argument("--pivoting", default="tournament", choices=["tournament", "partial"])
-    ap.add_argument("--lookahead", action="store_true",
-                    help="factor each next panel on a second stream beside the rest of the trailing update")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     args = ap.parse_args()
@@ -467,8 +462,7 @@ def main():
     for mode in modes:
         steps = args.steps if mode == args.mode else max(1, min(args.steps, 2))
         wall, results, phases = run_steps(fm, torch, A, B, U0, P, mode, steps, args.warmup, ws, timing=True,
-                                          variant=variant, lookahead=args.lookahead,
-                                          pivoting=args.pivoting)
+                                          variant=variant, pivoting=args.pivoting)
         iters = sum(r.iterations for r in results)
         errs = [match_err(r.lam, ref) for r in results]
         out[mode] = dict(ms_per_step=1e3 * wall / steps, iters_per_s=iters / wall, iterations=results[0].iterations,
@@ -490,7 +484,7 @@ def main():
     dom = max(device_phases, key=lambda k: head["phases"][k]["ms"])
     ph_all = None
     kw = dict(center=P.center, radius=P.radius, aspect=1.0, q=P.q, m0=P.m0, precision=args.mode, workspace=ws,
-              variant=variant, lookahead=args.lookahead, pivoting=args.pivoting)
+              variant=variant, pivoting=args.pivoting)
     with fm.Feast(A, B, timing=True, **kw) as F:
         F.iterate(U0)
         ph_all = F.timing()
@@ -540,7 +534,7 @@ def main():
                    "mode": {"fp32": "FP32 LU + FP64 refinement", "fp16": "FP16-update LU + FP64 refinement",
                             "fp64": "FP64"}[args.mode],
                    "step": "setup (assembly + q LUs) + iterations to 1e-10",
-                   "lookahead": args.lookahead, "pivoting": args.pivoting},
+                   "pivoting": args.pivoting},
         "time_to_1e10_s": head["ms_per_step"] / 1e3,
         "iterations": head["iterations"],
         "eig_err_vs_oracle": head["eig_err_vs_oracle"],

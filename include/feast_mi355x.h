@@ -95,13 +95,6 @@ typedef struct {
                             per column); 0 partial pivoting (LAPACK's pivots).  Both give
                             backward-stable factors in practice; the solves agree with each
                             other to the conditioning of the node systems. */
-    int lookahead;       /* 0 (default): every launch on the caller's stream.  1: the trailing
-                            update of each factorisation step is split into the next panel's
-                            columns and the rest, and the next panel is factored on a second
-                            stream of the library's while the rest of the update runs (fork and
-                            join through events on the caller's stream).  Results are bitwise
-                            equal; on MI355X the panel and the update slow each other down about
-                            as much as they overlap, so it is off by default. */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */

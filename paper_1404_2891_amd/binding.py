@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int),
-                ("pivoting", ctypes.c_int), ("lookahead", ctypes.c_int)]
+                ("pivoting", ctypes.c_int)]
 
 
 class PhaseTime(ctypes.Structure):
@@ -188,7 +188,7 @@ PIVOTING = {"partial": 0, "tournament": 1}
 
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament", lookahead=False) -> Options:
+                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament") -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -201,7 +201,6 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.timing = int(bool(timing))
     o.rank_check = int(bool(rank_check))
     o.pivoting = PIVOTING[pivoting]
-    o.lookahead = int(bool(lookahead))
     return o
 
 
@@ -289,7 +288,7 @@ class Feast:
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
-                 timing=False, workspace=None, rank_check=False, pivoting="tournament", lookahead=False):
+                 timing=False, workspace=None, rank_check=False, pivoting="tournament"):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
@@ -297,7 +296,7 @@ class Feast:
         self.A, self.B = A, B
         self.contour = make_contour(center, radius, aspect, q, rule)
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check, pivoting, lookahead)
+                                    rank_check, pivoting)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
         if workspace is not None:
             if workspace.numel() < nbytes or workspace.data_ptr() % 256:
@@ -414,7 +413,7 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False, pivoting="tournament", lookahead=False):
+                 rank_check=False, pivoting="tournament"):
         torch = _torch()
         count = len(pencils)
         self.count = count
@@ -424,7 +423,7 @@ class FeastBatch:
         if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
             contours = [contours] * count
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, False,
-                                    rank_check, pivoting, lookahead)
+                                    rank_check, pivoting)
         C = (Contour * count)(*[make_contour(c, r, a, q, rule) for (c, r, a) in contours])
         self._C = C
         n_arr, n_p = _ptr_array(self.n, ctypes.c_int)

@@ -74,10 +74,6 @@ struct feast_ctx {
     LUDev* lu_dev = nullptr;          // device descriptor of this pencil's factor storage
     GemmGroup* lu_groups = nullptr;   // grouped-product members of its factorisation
     int lu_ngroups = 0;
-    // lookahead of the factorisation: a second stream and the fork/join events (created on the
-    // first factorisation when the options ask for it)
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
     // members of a batch: the batch's stream (possibly the null stream), which the public entry
     // points order themselves against (see OuterOrder)
     bool member = false;
@@ -217,6 +213,7 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->lu.nbs = NBS;
     c->lu.nsbs = ceil_div(n, NBS);
     c->lu.half = c->prec == Prec::F16;
+    c->lu.paired = c->prec != Prec::F16;
     c->lu.tslu = o->pivoting == 1;
     c->lu.tW0 = tslu_leaf_blocks(n, c->prec == Prec::F64);
     // grouped-product members of the factorisation (a count that depends on the dimensions only)
@@ -565,9 +562,6 @@ LUSet ctx_set(feast_ctx* c) {
     one.groups = c->lu_groups;
     one.timer = c->lu.timer;
     one.single_rows = tuned_single_rows(c->prec, c->q);
-    one.side = c->side;
-    one.fork = c->fork;
-    one.join = c->join;
     return one;
 }
 
@@ -590,23 +584,6 @@ struct OuterOrder {
         if (hipEventRecord(c->outer_ev, c->st) == hipSuccess) (void)hipStreamWaitEvent(c->outer, c->outer_ev, 0);
     }
 };
-
-// Second stream and events of the lookahead (default priority; events without timing).
-int lookahead_create(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
-    if (*side) return 0;
-    FM_HIP(hipStreamCreateWithFlags(side, hipStreamNonBlocking));
-    FM_HIP(hipEventCreateWithFlags(fork, hipEventDisableTiming));
-    FM_HIP(hipEventCreateWithFlags(join, hipEventDisableTiming));
-    return 0;
-}
-
-void lookahead_destroy(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
-    if (*fork) (void)hipEventDestroy(*fork);
-    if (*join) (void)hipEventDestroy(*join);
-    if (*side) (void)hipStreamDestroy(*side);
-    *side = nullptr;
-    *fork = *join = nullptr;
-}
 
 int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C, int m0,
                const feast_options* o, void* workspace, size_t workspace_bytes, hipStream_t stream) {
@@ -700,7 +677,6 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
 
 // a2 + a3: assemble and factor every node (enqueue only, no host synchronisation)
 int ctx_factor_enqueue(feast_ctx* c) {
-    if (c->o.lookahead) FM_TRY(lookahead_create(&c->side, &c->fork, &c->join));
     const LUSet one = ctx_set(c);
     return c->prec == Prec::F64 ? lu_factor_set<double>(one, c->st) : lu_factor_set<float>(one, c->st);
 }
@@ -734,7 +710,6 @@ void feast_default_options(feast_options* o) {
     o->timing = 0;
     o->rank_check = 0;
     o->pivoting = 1;
-    o->lookahead = 0;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -1252,7 +1227,6 @@ void feast_destroy(feast_ctx* c) {
     if (!c) return;
     if (c->h) (void)hipHostFree(c->h);
     if (c->pin_base) (void)hipHostFree(c->pin_base);
-    lookahead_destroy(&c->side, &c->fork, &c->join);
     if (c->outer_ev) (void)hipEventDestroy(c->outer_ev);
     delete c;
 }
@@ -1356,8 +1330,6 @@ struct feast_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float factor_ms = 0.0f;
-    hipStream_t side = nullptr;   // lookahead stream and events, forked from the capture stream
-    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -1402,7 +1374,6 @@ void batch_free(feast_batch* bt) {
         if (s) (void)hipStreamDestroy(s);
     if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
     if (bt->graph) (void)hipGraphDestroy(bt->graph);
-    lookahead_destroy(&bt->side, &bt->fork, &bt->join);
     delete bt;
 }
 
@@ -1495,12 +1466,6 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         S.dev = bt->dev;
         S.groups = bt->groups;
         S.single_rows = tuned_single_rows(bt->prec, C[0].q);
-        if (o->lookahead) {
-            rc = lookahead_create(&bt->side, &bt->fork, &bt->join);
-            S.side = bt->side;
-            S.fork = bt->fork;
-            S.join = bt->join;
-        }
         std::vector<GemmGroup> plan;
         if (bt->prec == Prec::F64)
             lu_plan<double>(S, plan);

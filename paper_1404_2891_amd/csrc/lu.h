@@ -39,6 +39,10 @@ struct LUStore {
     // taken from its largest component, recorded per node in amax (q ints, see GemmOp::amax)
     bool half = false;
     int* amax = nullptr;
+    // trailing updates once per two panels (K = 2 nb); fixed when the launch sequence is planned
+    // (off for contexts that start with FP16 updates, which keep one update per panel also after
+    // an escalation to FP32 factors)
+    bool paired = false;
     // tournament pivoting of tall panels (tslu): candidate row lists, q x (2 tW0 64 + 64) ints
     // (two levels of the reduction tree and the final winners), and the root's factored rows,
     // q x nb x nb elements; tW0 = blocks of the widest leaf level
@@ -97,12 +101,6 @@ struct LUSet {
     // panels with more rows than the register panel holds and at most this many use the
     // single-workgroup sweeping panel, taller ones the multi-workgroup panel (see lu_tuned_rows)
     int single_rows = PANEL_ROWS;
-    // lookahead: with a side stream and two events (created without timing), the panel of step
-    // s + 1 runs on `side` while the part of step s's trailing update right of that panel runs on
-    // the launching stream (fork after the update of the panel's own columns, join before the
-    // interchanges of step s + 1); without them every launch stays on one stream
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // Descriptor of one member (real_bytes: 4 or 8, the precision of the storage).

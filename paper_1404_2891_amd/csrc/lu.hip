@@ -898,6 +898,7 @@ int run_set(SetRun<T>& R) {
     if (nb > NBMAX || nb % 16) return FEAST_EUNSUPPORTED;
     for (int b = 0; b < P; ++b)
         if (S.s[b].q != q || S.s[b].nb != nb || S.s[b].nbs != R.nbs || S.s[b].half != S.s[0].half ||
+            S.s[b].paired != S.s[0].paired ||
             (S.s[b].half && sizeof(T) != sizeof(float)) || (R.launching() && S.s[b].half && !S.s[b].amax))
             return FEAST_EUNSUPPORTED;
     if (R.launching()) {
@@ -910,33 +911,58 @@ int run_set(SetRun<T>& R) {
     R.start(PH_LU_PANEL);
     FM_TRY(panel<T>(R, 0));
     R.stop(PH_LU_PANEL, 0.0);
+    // Paired steps (FP32/FP64 storage): the trailing update runs once per two panels
+    // with K = 2 nb, which halves the traffic of the trailing matrix per flop.  The first step of a
+    // pair updates only the next panel's columns; the second step first brings its staged U12 rows
+    // up to date with the first step's L21 and U12 (tmp -= L U12), forms its own U12, and then
+    // updates everything right of and below both panels with [L21 L21'] [U12; U12'].
+    const bool paired = S.s[0].paired && !S.s[0].half;
     for (int step = 0; step < R.nsteps_max; ++step) {
         const int j0 = step * nb;
-        // the trailing update in two parts: the columns of the next panel, then the rest
-        std::vector<GemmGroup> u12, upd_next, upd_rest;
+        const bool second = paired && (step & 1);
+        std::vector<GemmGroup> pre, u12, upd_next, upd;
         int swap_cols = 0;
         double flops = 0.0;
+        bool more = false;   // some member has columns right of this panel
         for (int b = 0; b < P; ++b) {
             const LUStore& s = S.s[b];
             if (s.n <= j0) continue;
             const int w = std::min(nb, s.n - j0), jn = j0 + w, nr = s.n - jn;
             swap_cols = std::max(swap_cols, s.n);
             if (nr <= 0) continue;
+            more = true;
             cplx<T>* F = (cplx<T>*)s.F;
+            const long ldf = s.ldf, sF = s.sF;
+            if (second) {
+                // staged rows j0 .. jn of the columns right of this panel -= L (rows j0 .. jn, the
+                // previous panel's columns) * U12 of the previous step
+                const int jp = j0 - nb;
+                pre.push_back(member(F + (long)j0 * ldf + jp, ldf, sF, 0, F + (long)jp * ldf + jn, ldf, sF, 0, s.tmp,
+                                     s.n, (long)nb * s.n, 0, w, nr, nb, q));
+            }
             // U12 = L_ss^-1 * (swapped rows staged in tmp); with FP16 updates its largest component
             // per node goes to amax
             int* amax = s.half ? s.amax : nullptr;
             u12.push_back(member((cplx<T>*)s.Linv + (long)step * nb * nb, nb, (long)s.nsteps * nb * nb, 0, s.tmp, s.n,
-                                 (long)nb * s.n, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF, 0, w, nr, w, q, amax));
-            // A22 -= L21 * U12, columns jn .. jn + nn - 1 first, then the columns right of them
-            const int nn = std::min(nb, nr);
-            upd_next.push_back(member(F + (long)jn * s.ldf + j0, s.ldf, s.sF, 0, F + (long)j0 * s.ldf + jn, s.ldf, s.sF,
-                                      0, F + (long)jn * s.ldf + jn, s.ldf, s.sF, 0, nr, nn, w, q, amax));
-            if (nr > nn)
-                upd_rest.push_back(member(F + (long)jn * s.ldf + j0, s.ldf, s.sF, 0, F + (long)j0 * s.ldf + jn + nn,
-                                          s.ldf, s.sF, 0, F + (long)jn * s.ldf + jn + nn, s.ldf, s.sF, 0, nr, nr - nn,
-                                          w, q, amax));
-            flops += 8.0 * nr * (double)nr * w * q;
+                                 (long)nb * s.n, 0, F + (long)j0 * ldf + jn, ldf, sF, 0, w, nr, w, q, amax));
+            if (!paired) {
+                // A22 -= L21 * U12
+                upd.push_back(member(F + (long)jn * ldf + j0, ldf, sF, 0, F + (long)j0 * ldf + jn, ldf, sF, 0,
+                                     F + (long)jn * ldf + jn, ldf, sF, 0, nr, nr, w, q, amax));
+                flops += 8.0 * nr * (double)nr * w * q;
+            } else if (!second) {
+                // the next panel's columns only (the rest waits for the second step)
+                const int nn = std::min(nb, nr);
+                upd_next.push_back(member(F + (long)jn * ldf + j0, ldf, sF, 0, F + (long)j0 * ldf + jn, ldf, sF, 0,
+                                          F + (long)jn * ldf + jn, ldf, sF, 0, nr, nn, w, q));
+                flops += 8.0 * nr * (double)nn * w * q;
+            } else {
+                // both steps at once: rows and columns >= jn, K = nb + w over columns jp .. jn
+                const int jp = j0 - nb;
+                upd.push_back(member(F + (long)jn * ldf + jp, ldf, sF, 0, F + (long)jp * ldf + jn, ldf, sF, 0,
+                                     F + (long)jn * ldf + jn, ldf, sF, 0, nr, nr, nb + w, q));
+                flops += 8.0 * nr * (double)nr * (nb + w) * q;
+            }
         }
         R.start(PH_LU_OTHER);
         if (R.launching()) {
@@ -949,40 +975,21 @@ int run_set(SetRun<T>& R) {
         }
         GemmOp op;
         op.rowA = op.rowB = op.rowC = true;
-        FM_TRY(R.grouped(u12, op));
-        R.stop(PH_LU_OTHER, 0.0);
-        if (upd_next.empty()) break;
         GemmOp up = op;
         up.alpha = z64(-1.0);
         up.beta = z64(1.0);
+        FM_TRY(R.grouped(pre, up));
+        FM_TRY(R.grouped(u12, op));
+        R.stop(PH_LU_OTHER, 0.0);
+        if (!more) break;
         up.kind = S.s[0].half ? 2 : 1;
-        // The next panel reads and writes only its own columns (rows >= j0 + nb), which upd_next
-        // finishes; upd_rest writes only the columns right of it and reads L21 and U12 of this step,
-        // which the panel leaves alone.  The interchanges of the next step touch both, after the join.
-        const bool ahead = R.launching() && S.side && S.fork && S.join;
         R.start(PH_LU_UPDATE);
         FM_TRY(R.grouped(upd_next, up));
-        if (ahead) {
-            hipStream_t main = R.st;
-            FM_HIP(hipEventRecord(S.fork, main));
-            FM_HIP(hipStreamWaitEvent(S.side, S.fork, 0));
-            R.st = S.side;
-            R.start(PH_LU_PANEL);
-            const int rc = panel<T>(R, j0 + nb);
-            R.stop(PH_LU_PANEL, 0.0);
-            R.st = main;
-            if (rc) return rc;
-            FM_HIP(hipEventRecord(S.join, S.side));
-            FM_TRY(R.grouped(upd_rest, up));
-            R.stop(PH_LU_UPDATE, flops);
-            FM_HIP(hipStreamWaitEvent(main, S.join, 0));
-        } else {
-            FM_TRY(R.grouped(upd_rest, up));
-            R.stop(PH_LU_UPDATE, flops);
-            R.start(PH_LU_PANEL);
-            FM_TRY(panel<T>(R, j0 + nb));
-            R.stop(PH_LU_PANEL, 0.0);
-        }
+        FM_TRY(R.grouped(upd, up));
+        R.stop(PH_LU_UPDATE, flops);
+        R.start(PH_LU_PANEL);
+        FM_TRY(panel<T>(R, j0 + nb));
+        R.stop(PH_LU_PANEL, 0.0);
     }
     if (R.launching()) {
         hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(R.nsteps_max, q, P), dim3(256), 0, R.st, S.dev, nb, 0);

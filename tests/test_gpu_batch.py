@@ -10,8 +10,9 @@ import numpy as np
 import pytest
 
 import pencils
-from oracle import brute
-from tests.gpu_common import device, match_eigs
+from oracle import brute, feast
+from oracle import quadrature as Q
+from tests.gpu_common import device, match_eigs, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -125,3 +126,23 @@ def test_batch_reports_singular_member():
         fm().FeastBatch(dev, (0j, 1.0, 1.0), m0=[good.m0, 4], q=16)
     assert e.value.code == fm().binding.FEAST_ESINGULAR + 0
     assert list(e.value.info) == [0, fm().binding.FEAST_ESINGULAR + 0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_member_calls_are_ordered_on_the_batch_stream(prec):
+    """Members run on streams of their own; a member's filter starts after work already on the
+    caller's stream and the caller's stream waits for it, so its output can be read (cloned) on that
+    stream at once, with no device-wide synchronisation in between."""
+    sizes = [(300, 9), (64, 3), (1100, 20), (129, 5), (700, 12)]
+    P = [pencils.c2_pencil(j, n, m) for j, (n, m) in enumerate(sizes)]
+    dev = [(upload(p.A), upload(p.B)) for p in P]
+    batch = fm().FeastBatch(dev, (0j, 1.0, 1.0), m0=[p.m0 for p in P], q=16, precision=prec, ir_max=0)
+    z, s = Q.nodes_and_weights(0j, 1.0, 1.0, "trapezoid", 16)
+    for j, p in enumerate(P):
+        U0 = pencils.start_block(2, p.n, p.m0, salt=11 + j)
+        got = batch.member_filter(j, upload(U0)).clone().cpu().numpy()
+        ref = feast.filter_right(feast.factor_nodes(p.A, p.B, z), s, p.B, U0)
+        kappa = max(np.linalg.cond(feast.node_matrix(p.A, p.B, zk)) for zk in z)
+        tol = 200 * kappa * 2.0 ** -53 * max(1, np.sqrt(p.n) / 4) * (1 if prec == "fp64" else 2 ** 29)
+        assert rel_err(got, ref) < tol, (j, rel_err(got, ref), tol)
+    batch.close()
