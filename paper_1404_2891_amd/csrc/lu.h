@@ -39,7 +39,7 @@ struct LUStore {
     // taken from its largest component, recorded per node in amax (q ints, see GemmOp::amax)
     bool half = false;
     int* amax = nullptr;
-    // trailing updates once per two panels (K = 2 nb); fixed when the launch sequence is planned
+    // trailing updates once per group of panels (K = 4 nb); fixed when the launch sequence is planned
     // (off for contexts that start with FP16 updates, which keep one update per panel also after
     // an escalation to FP32 factors)
     bool paired = false;

@@ -26,6 +26,7 @@ namespace fm {
 namespace {
 
 constexpr int NBMAX = 64;
+constexpr int UPDATE_GROUP = 4;   // panels per trailing update (K = 4 nb)
 
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(const LUDev* __restrict__ dv, int q) {
@@ -911,16 +912,18 @@ int run_set(SetRun<T>& R) {
     R.start(PH_LU_PANEL);
     FM_TRY(panel<T>(R, 0));
     R.stop(PH_LU_PANEL, 0.0);
-    // Paired steps (FP32/FP64 storage): the trailing update runs once per two panels
-    // with K = 2 nb, which halves the traffic of the trailing matrix per flop.  The first step of a
-    // pair updates only the next panel's columns; the second step first brings its staged U12 rows
-    // up to date with the first step's L21 and U12 (tmp -= L U12), forms its own U12, and then
-    // updates everything right of and below both panels with [L21 L21'] [U12; U12'].
-    const bool paired = S.s[0].paired && !S.s[0].half;
+    // Grouped steps (FP32/FP64 storage): the trailing update runs once per G panels with K = G nb,
+    // which divides the traffic of the trailing matrix per flop by G.  Step i of a group (columns
+    // jg = j0 - i nb onwards belong to the group) first brings its staged U12 rows up to date with
+    // the group's earlier panels (tmp -= L(rows of this panel, columns jg .. j0) U12(rows jg .. j0)),
+    // forms its own U12, and then updates the next panel's columns with all of the group's panels
+    // so far (K = (i + 1) nb), or, at the group's last step, everything right of and below the group
+    // (K = G nb).  FP16-update contexts keep G = 1 (the FP16 scale of U12 is per step).
+    const int G = (S.s[0].paired && !S.s[0].half) ? UPDATE_GROUP : 1;
     for (int step = 0; step < R.nsteps_max; ++step) {
         const int j0 = step * nb;
-        const bool second = paired && (step & 1);
-        std::vector<GemmGroup> pre, u12, upd_next, upd;
+        const int i = step % G, jg = j0 - i * nb;
+        std::vector<GemmGroup> pre, u12, upd;
         int swap_cols = 0;
         double flops = 0.0;
         bool more = false;   // some member has columns right of this panel
@@ -933,36 +936,20 @@ int run_set(SetRun<T>& R) {
             more = true;
             cplx<T>* F = (cplx<T>*)s.F;
             const long ldf = s.ldf, sF = s.sF;
-            if (second) {
-                // staged rows j0 .. jn of the columns right of this panel -= L (rows j0 .. jn, the
-                // previous panel's columns) * U12 of the previous step
-                const int jp = j0 - nb;
-                pre.push_back(member(F + (long)j0 * ldf + jp, ldf, sF, 0, F + (long)jp * ldf + jn, ldf, sF, 0, s.tmp,
-                                     s.n, (long)nb * s.n, 0, w, nr, nb, q));
-            }
+            if (i > 0)
+                pre.push_back(member(F + (long)j0 * ldf + jg, ldf, sF, 0, F + (long)jg * ldf + jn, ldf, sF, 0, s.tmp,
+                                     s.n, (long)nb * s.n, 0, w, nr, i * nb, q));
             // U12 = L_ss^-1 * (swapped rows staged in tmp); with FP16 updates its largest component
             // per node goes to amax
             int* amax = s.half ? s.amax : nullptr;
             u12.push_back(member((cplx<T>*)s.Linv + (long)step * nb * nb, nb, (long)s.nsteps * nb * nb, 0, s.tmp, s.n,
                                  (long)nb * s.n, 0, F + (long)j0 * ldf + jn, ldf, sF, 0, w, nr, w, q, amax));
-            if (!paired) {
-                // A22 -= L21 * U12
-                upd.push_back(member(F + (long)jn * ldf + j0, ldf, sF, 0, F + (long)j0 * ldf + jn, ldf, sF, 0,
-                                     F + (long)jn * ldf + jn, ldf, sF, 0, nr, nr, w, q, amax));
-                flops += 8.0 * nr * (double)nr * w * q;
-            } else if (!second) {
-                // the next panel's columns only (the rest waits for the second step)
-                const int nn = std::min(nb, nr);
-                upd_next.push_back(member(F + (long)jn * ldf + j0, ldf, sF, 0, F + (long)j0 * ldf + jn, ldf, sF, 0,
-                                          F + (long)jn * ldf + jn, ldf, sF, 0, nr, nn, w, q));
-                flops += 8.0 * nr * (double)nn * w * q;
-            } else {
-                // both steps at once: rows and columns >= jn, K = nb + w over columns jp .. jn
-                const int jp = j0 - nb;
-                upd.push_back(member(F + (long)jn * ldf + jp, ldf, sF, 0, F + (long)jp * ldf + jn, ldf, sF, 0,
-                                     F + (long)jn * ldf + jn, ldf, sF, 0, nr, nr, nb + w, q));
-                flops += 8.0 * nr * (double)nr * (nb + w) * q;
-            }
+            // A22 -= [L21 of the group's panels] [their U12]: the next panel's columns within a group,
+            // all columns right of the group at its end
+            const int K = i * nb + w, nc = i < G - 1 ? std::min(nb, nr) : nr;
+            upd.push_back(member(F + (long)jn * ldf + jg, ldf, sF, 0, F + (long)jg * ldf + jn, ldf, sF, 0,
+                                 F + (long)jn * ldf + jn, ldf, sF, 0, nr, nc, K, q, amax));
+            flops += 8.0 * nr * (double)nc * K * q;
         }
         R.start(PH_LU_OTHER);
         if (R.launching()) {
@@ -984,7 +971,6 @@ int run_set(SetRun<T>& R) {
         if (!more) break;
         up.kind = S.s[0].half ? 2 : 1;
         R.start(PH_LU_UPDATE);
-        FM_TRY(R.grouped(upd_next, up));
         FM_TRY(R.grouped(upd, up));
         R.stop(PH_LU_UPDATE, flops);
         R.start(PH_LU_PANEL);
