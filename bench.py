@@ -50,23 +50,50 @@ def load_workload(name):
     return P, U0, ref, g
 
 
+# sources whose change voids a PMC traffic record, per record
+TRAFFIC_SOURCES = {"panel_step_kernel": ["lu.hip"], "lu_update": ["gemm.hip", "lu.hip"]}
+
+
+def sources_hash(names):
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_1404_2891_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel, n, q, mode):
     """HBM bytes per dispatch of `kernel` from the committed PMC record (profiles/pmc_traffic.json),
-    or None when the record is for another workload or the kernel's source has changed since."""
-    import hashlib
-    import re
+    or None when the record is for another workload or the sources behind it have changed since."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))[kernel]
-        src = open(os.path.join(ROOT, "paper_1404_2891_amd", "csrc", "lu.hip")).read()
+        digest = sources_hash(TRAFFIC_SOURCES[kernel])
     except (OSError, KeyError, ValueError):
         return None
-    m = re.search(r"template <typename T, int U>\n__global__ __launch_bounds__\(256\) void " + kernel + r".*?\n}\n", src,
-                  re.S)
-    if not m or hashlib.sha256(m.group(0).encode()).hexdigest()[:16] != rec["kernel_source_sha256_16"]:
-        return None
-    if (n, q, mode) != (4096, 24, "fp32"):
+    if digest != rec.get("sources_sha256_16") or (n, q, mode) != tuple(rec.get("n_q_mode", ())):
         return None
     return rec["bytes_per_dispatch"]
+
+
+def update_bytes(n, q, elem, nb=64, group=4):
+    """Algorithmic bytes of the trailing-update launches of one factorisation and their count.
+
+    Step s (i = s mod group, w = min(nb, n - j0), nr = n - j0 - w) updates nr rows by nc columns with
+    K = i nb + w (nc = min(nb, nr) inside a group, nr at its last step): it reads L21 (nr x K) and
+    U12 (K x nc) and reads and writes the block (nr x nc), for every node."""
+    total, launches = 0.0, 0
+    for step, j0 in enumerate(range(0, n, nb)):
+        i = step % group
+        w = min(nb, n - j0)
+        nr = n - j0 - w
+        if nr <= 0:
+            break
+        K = i * nb + w
+        nc = min(nb, nr) if i < group - 1 else nr
+        total += elem * q * (nr * K + K * nc + 2.0 * nr * nc)
+        launches += 1
+    return total, launches
 
 
 def panel_bytes(n, q, elem, nb=64, reg_rows=None):
@@ -500,6 +527,22 @@ def main():
                         traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
                         kernel="panel_step_kernel", kernel_phase=dom,
                         avg_launch_ms=dph["ms"] / launches, bytes_per_launch=nbytes / launches, launches=launches)
+    elif dom == "lu_update":
+        # the MFMA trailing update (grouped over four panels); algorithmic bytes per launch from its
+        # operand and block sizes, measured HBM traffic from the PMC record
+        prec_of_phase = "fp16" if args.mode == "fp16" else args.mode
+        elem = 16 if args.mode == "fp64" else 8
+        nbytes, launches = update_bytes(P.n, P.q, elem)
+        achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12
+        roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
+                        frac=achieved / PEAK[prec_of_phase],
+                        traffic=measured_traffic("lu_update", P.n, P.q, args.mode),
+                        traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
+                        kernel="cgemm_kernel (trailing update)", kernel_phase=dom,
+                        avg_launch_ms=dph["ms"] / max(1, dph["launches"]), launches=dph["launches"],
+                        flops_per_launch=dph["flops"] / max(1, dph["launches"]),
+                        algorithmic_bytes_per_launch=nbytes / max(1, launches),
+                        achieved_gbs=nbytes / max(1, launches) / (dph["ms"] / max(1, dph["launches"]) * 1e-3) / 1e9)
     else:
         prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else (
             "fp16" if (args.mode == "fp16" and dom == "lu_update") else "fp32")
