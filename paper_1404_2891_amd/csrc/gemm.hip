@@ -4,7 +4,7 @@
 // complex block update is four real MFMAs: 8 real flops per complex multiply-add, the
 // LAPACK count.  A workgroup of 256 threads (4 wave64s) owns a BM x BN tile of C; waves are
 // laid out WM x WN over the tile, each owning RB x CB blocks of 16 x 16.  Operand tiles
-// of depth BK = 16 are staged through LDS as separate real / imaginary planes in k-major
+// of depth BK (16 for FP32, 32 for FP64) are staged through LDS as separate real / imaginary planes in k-major
 // order, so the 16 lanes of an MFMA row group read consecutive addresses; the next tile
 // is fetched into registers while the current one is consumed.
 #include <type_traits>
@@ -24,7 +24,9 @@ template <> struct AccT<float> { typedef f4 type; };
 __device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-constexpr int BK = 16;
+// Depth of the staged operand tiles: 16 for FP32 (twice the registers for the prefetch cost more
+// occupancy than the fewer barriers gain, measured), 32 for FP64.
+template <typename T> struct Depth { static constexpr int value = sizeof(T) == 8 ? 32 : 16; };
 // LDS row padding: the four k-rows a wave reads at once must cover the banks evenly.  FP32 rows of
 // BM + 8 words (8 mod 32 banks) give two accesses per bank, the minimum, for those reads and for the
 // tile stores; FP64 elements span two banks, so rows of BM + 2 already do.
@@ -54,7 +56,7 @@ struct Params {
 
 template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC, int KIND>
 __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
-    constexpr int BM = WM * RB * 16, BN = WN * CB * 16, NT = 64 * WM * WN;
+    constexpr int BM = WM * RB * 16, BN = WN * CB * 16, NT = 64 * WM * WN, BK = Depth<T>::value;
     constexpr int EA = BM * BK / NT, EB = BK * BN / NT;
     static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile not divisible");
     typedef typename AccT<T>::type acc_t;
@@ -436,7 +438,7 @@ int gemm(const GemmOp& op, hipStream_t st) {
     p.M = op.M; p.N = op.N; p.K = op.K; p.batch = op.batch;
     p.batch2 = op.batch2; p.sA2 = op.sA2; p.sB2 = op.sB2; p.sC2 = op.sC2;
     p.splitk = op.splitk > 1 ? op.splitk : 1;
-    p.kchunk = p.splitk > 1 ? (int)align_up((size_t)ceil_div(op.K, p.splitk), BK) : (op.K > 0 ? op.K : 0);
+    p.kchunk = p.splitk > 1 ? (int)align_up((size_t)ceil_div(op.K, p.splitk), Depth<T>::value) : (op.K > 0 ? op.K : 0);
     if (p.splitk > 1) p.splitk = ceil_div(op.K, p.kchunk);
     p.ar = T(op.alpha.re); p.ai = T(op.alpha.im);
     p.br = T(op.beta.re); p.bi = T(op.beta.im);
