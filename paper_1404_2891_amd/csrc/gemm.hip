@@ -414,11 +414,16 @@ void launch_cfg(Params<T> p, hipStream_t st) {
     hipLaunchKernelGGL((cgemm_kernel<T, WM, WN, RB, CB, RA, RBm, RC, KIND>), grid, dim3(64 * WM * WN), 0, st, p);
 }
 
+// Tile by the width of C, and narrower tiles when 64 x 64 ones would leave most of the 256 compute
+// units idle (small products such as the solves' diagonal-block steps: 64 x 16 tiles give four
+// times the workgroups).
 template <typename T, bool RA, bool RBm, bool RC>
 void launch_layout(Params<T> p, hipStream_t st) {
-    if (p.N <= 16)
+    const long per_col = (long)p.batch * p.splitk * p.batch2 * (p.groups ? p.ngroups : 1) * ceil_div(p.M, 64);
+    const long wg64 = per_col * ceil_div(p.N, 64);
+    if (p.N <= 16 || (p.N > 32 && 2 * wg64 < 256))
         launch_cfg<T, 4, 1, 1, 1, RA, RBm, RC>(p, st);
-    else if (p.N <= 32)
+    else if (p.N <= 32 || wg64 < 256)
         launch_cfg<T, 4, 1, 1, 2, RA, RBm, RC>(p, st);
     else
         launch_cfg<T, 2, 2, 2, 2, RA, RBm, RC>(p, st);
