@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv,
 // every output entry a dot product of length h.  A partial last block (w < nb) is extended by the
 // identity; the inverse is stored with zeros outside its w x w part.
 template <typename T, bool UPPER>
-__global__ __launch_bounds__(256) void trtri_kernel(const LUDev* __restrict__ dv, int nb, int s_first) {
+__global__ __launch_bounds__(1024) void trtri_kernel(const LUDev* __restrict__ dv, int nb, int s_first) {
     static_assert(NBMAX == 64, "blocks of 64");
     const LUDev& d = dv[blockIdx.z];
     const int s = s_first + blockIdx.x, k = blockIdx.y;
@@ -812,7 +812,7 @@ int panel(SetRun<T>& R, int j0) {
                            S.single_rows);
         FM_LAUNCH_CHECK();
         // U11^-1 of this step (members without a tournament here recompute a finished block)
-        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(1, R.q, S.count), dim3(256), 0, R.st, S.dev, R.nb, j0 / R.nb);
+        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(1, R.q, S.count), dim3(1024), 0, R.st, S.dev, R.nb, j0 / R.nb);
         FM_LAUNCH_CHECK();
         if (below > 0) {
             hipLaunchKernelGGL((tslu_l21_kernel<T>), dim3(ceil_div(below, 64), R.q, S.count), dim3(256), 0, R.st,
@@ -957,7 +957,7 @@ int run_set(SetRun<T>& R) {
             hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(swap_cols, 256), q, P), dim3(256), 0, R.st, S.dev, j0,
                                nb, S.single_rows);
             FM_LAUNCH_CHECK();
-            hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q, P), dim3(256), 0, R.st, S.dev, nb, step);
+            hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q, P), dim3(1024), 0, R.st, S.dev, nb, step);
             FM_LAUNCH_CHECK();
         }
         GemmOp op;
@@ -978,7 +978,7 @@ int run_set(SetRun<T>& R) {
         R.stop(PH_LU_PANEL, 0.0);
     }
     if (R.launching()) {
-        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(R.nsteps_max, q, P), dim3(256), 0, R.st, S.dev, nb, 0);
+        hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(R.nsteps_max, q, P), dim3(1024), 0, R.st, S.dev, nb, 0);
         FM_LAUNCH_CHECK();
         hipLaunchKernelGGL(perm_kernel, dim3(q, 1, P), dim3(256), R.nmax * sizeof(int), R.st, S.dev);
         FM_LAUNCH_CHECK();
