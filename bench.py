@@ -364,6 +364,7 @@ def bench_m0(args, fm, torch, dev):
     probe_mean = Xev[:, 0:16:2].mean(axis=1)
     strategies = {
         "estimator": [fm.m0_from_estimate(x) for x in m_hat],
+        "estimator_margin12": [max(8, int(np.ceil((np.ceil(1.25 * max(x, 0.0)) + 12) / 8.0)) * 8) for x in m_hat],
         "fixed_64": [64] * nev,
         "probe_mean_x1.5": [max(8, int(np.ceil(1.5 * max(x, 0.0) / 8.0)) * 8) for x in probe_mean],
     }

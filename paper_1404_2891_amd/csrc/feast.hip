@@ -17,6 +17,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -1165,10 +1166,36 @@ void each(std::vector<Run*>& runs, F f) {
     }
 }
 
+// Host phase f on every active context, on up to 16 threads when there are several contexts: each
+// call touches only its own context (host buffers, timer) and enqueues only on its own stream.
+template <typename F>
+void each_host(std::vector<Run*>& runs, F f) {
+    std::vector<Run*> act;
+    for (Run* r : runs)
+        if (r->active) act.push_back(r);
+    const int nt = (int)std::min<size_t>({act.size(), (size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency())});
+    if (act.size() < 4 || nt < 2) {
+        each(runs, f);
+        return;
+    }
+    std::vector<int> rcs(act.size(), 0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (size_t i = t; i < act.size(); i += nt) rcs[i] = f(*act[i]);
+        });
+    for (auto& x : th) x.join();
+    for (size_t i = 0; i < act.size(); ++i)
+        if (rcs[i]) {
+            act[i]->rc = rcs[i];
+            act[i]->active = false;
+        }
+}
+
 int drive(std::vector<Run*>& runs) {
     each(runs, [](Run& r) { return e_begin(r); });
     FM_TRY(sync_runs(runs));
-    each(runs, [](Run& r) { return h_begin(r); });
+    each_host(runs, [](Run& r) { return h_begin(r); });
     for (;;) {
         bool any = false;
         for (Run* r : runs) any |= r->active;
@@ -1176,14 +1203,14 @@ int drive(std::vector<Run*>& runs) {
         each(runs, [](Run& r) { return e_filter(r); });
         FM_TRY(sync_runs(runs));
         for (int pass = 0; pass < 3; ++pass) {
-            each(runs, [pass](Run& r) { return h_chol(r, pass); });
+            each_host(runs, [pass](Run& r) { return h_chol(r, pass); });
             each(runs, [pass](Run& r) { return e_orth(r, pass); });
             FM_TRY(sync_runs(runs));
         }
-        each(runs, [](Run& r) { return h_eig(r); });
+        each_host(runs, [](Run& r) { return h_eig(r); });
         each(runs, [](Run& r) { return e_ritz(r); });
         FM_TRY(sync_runs(runs));
-        each(runs, [](Run& r) { return h_conv(r); });
+        each_host(runs, [](Run& r) { return h_conv(r); });
         each(runs, [](Run& r) { return e_post(r); });
         FM_TRY(sync_runs(runs));
         for (Run* r : runs)
