@@ -27,10 +27,21 @@ __device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfm
 // Depth of the staged operand tiles: 16 for FP32 (twice the registers for the prefetch cost more
 // occupancy than the fewer barriers gain, measured), 32 for FP64.
 template <typename T> struct Depth { static constexpr int value = sizeof(T) == 8 ? 32 : 16; };
-// LDS row padding: the four k-rows a wave reads at once must cover the banks evenly.  FP32 rows of
-// BM + 8 words (8 mod 32 banks) give two accesses per bank, the minimum, for those reads and for the
-// tile stores; FP64 elements span two banks, so rows of BM + 2 already do.
-template <typename T> struct Pad { static constexpr int value = sizeof(T) == 4 ? 8 : 2; };
+// LDS layout of the operand planes (rows of depth k, BM or BN columns).  The reads of one MFMA step
+// cover four k-rows x 16 columns, the stores of a row-major operand 16 k-rows x 2 columns per 32
+// lanes.  FP32 planes at least 32 columns wide are unpadded and XOR-swizzled: column i of row k is
+// kept at i ^ s(k), s(k) = 16 (k mod 2) + 2 floor(k / 2), which puts the 16 rows of a store on 16
+// distinct even banks (no conflict) and splits the four rows of a read over both halves of the 32
+// banks (two accesses per bank, the minimum for 64 lanes).  Narrower FP32 planes are padded to 8 mod
+// 32 words; FP64 elements span two banks and rows of BM + 2 spread them evenly.  The LU trailing
+// update (kind 1) keeps the padded layout: its LDS traffic is not what limits it, and the swizzled
+// addresses cost it more than the conflicts (96 against 100 TFLOP/s, measured), while the solves'
+// products gain from the swizzle (67.5 against 64 TFLOP/s).
+template <typename T, int DIM, bool SWZ = true> struct Lds {
+    static constexpr bool swizzle = SWZ && sizeof(T) == 4 && DIM % 32 == 0;
+    static constexpr int ld = swizzle ? DIM : DIM + (sizeof(T) == 4 ? 8 : 2);
+    __device__ static int col(int k, int i) { return swizzle ? i ^ (((k & 1) << 4) | ((k >> 1) << 1)) : i; }
+};
 
 // Row of the 16 x 16 output block held in accumulator element v of lane l (column l % 16):
 // the FP32 instruction stores rows 4 (l / 16) + v, the FP64 one rows l / 16 + 4 v.
@@ -61,9 +72,10 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile not divisible");
     typedef typename AccT<T>::type acc_t;
 
-    constexpr int PAD = Pad<T>::value;
-    __shared__ T As[2][BK][BM + PAD];
-    __shared__ T Bs[2][BK][BN + PAD];
+    typedef Lds<T, BM, KIND != 1> LA;
+    typedef Lds<T, BN, KIND != 1> LB;
+    __shared__ T As[2][BK][LA::ld];
+    __shared__ T Bs[2][BK][LB::ld];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -128,16 +140,16 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
             const int idx = tid + e * NT;
             const int k = RA ? idx % BK : idx / BM;
             const int i = RA ? idx / BK : idx % BM;
-            As[0][k][i] = ra[e].re;
-            As[1][k][i] = sa * ra[e].im;
+            As[0][k][LA::col(k, i)] = ra[e].re;
+            As[1][k][LA::col(k, i)] = sa * ra[e].im;
         }
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
             const int idx = tid + e * NT;
             const int j = RBm ? idx % BN : idx / BK;
             const int k = RBm ? idx / BN : idx % BK;
-            Bs[0][k][j] = rb[e].re;
-            Bs[1][k][j] = sb * rb[e].im;
+            Bs[0][k][LB::col(k, j)] = rb[e].re;
+            Bs[1][k][LB::col(k, j)] = sb * rb[e].im;
         }
     };
 
@@ -163,14 +175,14 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const int i = wm * RB * 16 + r * 16 + (lane & 15);
-                are[r] = As[0][k][i];
-                aim[r] = As[1][k][i];
+                are[r] = As[0][k][LA::col(k, i)];
+                aim[r] = As[1][k][LA::col(k, i)];
             }
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const int j = wn * CB * 16 + c * 16 + (lane & 15);
-                bre[c] = Bs[0][k][j];
-                bim[c] = Bs[1][k][j];
+                bre[c] = Bs[0][k][LB::col(k, j)];
+                bim[c] = Bs[1][k][LB::col(k, j)];
             }
             // four passes over the blocks, so that consecutive matrix-core instructions never update
             // the same accumulator
