@@ -417,37 +417,41 @@ __global__ __launch_bounds__(256) void tslu_apply_kernel(const LUDev* __restrict
     const int* fin = d.tcand + (long)k * (2L * d.tW0 * 64 + 64) + 2L * d.tW0 * 64;
     int* ipiv = d.ipiv + k * d.spiv;
     __shared__ int pos[128], content[128], piv[64];
-    __shared__ int cnt_s, tc_s;
+    __shared__ int cnt_s;
     __shared__ cplx<T> buf[64][64];
-    // touched positions: the panel's first w rows, then the winners below them
-    if (tid == 0) {
-        int cnt = w;
-        for (int j = 0; j < w; ++j) {
-            const int r = fin[j];
-            if (r >= j0 + w) pos[cnt++] = r;
-        }
-        cnt_s = cnt;
+    // touched positions: the panel's first w rows, then the winners below them (in winner order)
+    if (tid < 64) {
+        const int r = tid < w ? fin[tid] : -1;
+        const bool below = r >= j0 + w;
+        const unsigned long long m = __ballot(below);
+        if (below) pos[w + __popcll(m & ((1ull << tid) - 1))] = r;
+        if (tid < w) pos[tid] = j0 + tid;
+        if (tid == 0) cnt_s = w + __popcll(m);
     }
-    if (tid < w) pos[tid] = j0 + tid;
     __syncthreads();
     const int cnt = cnt_s;
-    if (tid < cnt) content[tid] = pos[tid];
-    __syncthreads();
-    for (int j = 0; j < w; ++j) {
-        const int r = fin[j];
-        if (tid == 0) tc_s = j;
-        __syncthreads();
-        if (tid < cnt && r >= 0 && content[tid] == r) tc_s = tid;
-        __syncthreads();
-        if (tid == 0) {
-            const int tc = tc_s;
-            piv[j] = pos[tc];
-            const int a = content[j];
-            content[j] = content[tc];
-            content[tc] = a;
+    // the sequential interchanges that bring the winners to the top, built by one wave without
+    // barriers: lane l holds the current content of positions l and l + 64
+    if (tid < 64) {
+        int c0 = tid < cnt ? pos[tid] : -1, c1 = tid + 64 < cnt ? pos[tid + 64] : -1;
+        for (int j = 0; j < w; ++j) {
+            const int r = fin[j];
+            const unsigned long long m0 = __ballot(r >= 0 && c0 == r), m1 = __ballot(r >= 0 && c1 == r);
+            const int tc = m0 ? __ffsll((long long)m0) - 1 : (m1 ? 64 + __ffsll((long long)m1) - 1 : j);
+            if (tid == 0) piv[j] = pos[tc];
+            const int cj = __shfl(c0, j);   // j < w <= 64
+            const int ct = tc < 64 ? __shfl(c0, tc) : __shfl(c1, tc - 64);
+            if (tid == j) c0 = ct;
+            if (tc < 64) {
+                if (tid == tc) c0 = cj;
+            } else if (tid == tc - 64) {
+                c1 = cj;
+            }
         }
-        __syncthreads();
+        if (tid < cnt) content[tid] = c0;
+        if (tid + 64 < cnt) content[tid + 64] = c1;
     }
+    __syncthreads();
     // rows displaced below the panel's first w rows: final content of position pos[t] (t >= w) is
     // the original row content[t] (the panel itself is still unmodified)
     const int nd = cnt - w;
