@@ -119,11 +119,11 @@ typedef struct feast_ctx feast_ctx;
 /* ---- a2 + a3: node assembly and factorisation -----------------------------
  * Creates a context for the pencil (A, B) (B = NULL means B = I), assembles
  * every node matrix T_k = phi_k B - A in the working precision and factors it
- * (LU with partial pivoting, pivot = largest |re| + |im|, lowest row on ties).
+ * (LU with row pivoting: tournament or partial, pivot = largest |re| + |im|,
+ * lowest row on ties, see feast_options.pivoting).
  * The factorisations stay resident in the workspace for the life of the
  * context: each node system is factored once for the whole run (Section 5.5).
  * A and B must stay valid and unchanged until feast_destroy.
- * Pivots: see feast_options.pivoting.
  * Synchronises the stream once to read the zero-pivot flags.
  * Returns 0, -i for invalid arguments, FEAST_ESINGULAR + k, FEAST_EWORKSPACE,
  * FEAST_EDEVICE. */

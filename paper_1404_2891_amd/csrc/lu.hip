@@ -1,18 +1,22 @@
-// Node assembly and blocked LU with partial pivoting of all contour-node systems.
+// Node assembly and blocked LU of all contour-node systems.
 //
-// Factorisations are stored row-major (element (i, j) at F[i * ldf + j]) so that the row
-// interchanges of partial pivoting move contiguous memory and a panel row is one coalesced
-// load.  Every kernel covers all q nodes of every pencil of a set (grid z = pencil, y or x = node),
-// so that one launch per step serves a whole batch of pencils of different orders.
+// Factorisations are stored row-major (element (i, j) at F[i * ldf + j]) so that row interchanges
+// move contiguous memory and a panel row is one coalesced load.  Every kernel covers all q nodes of
+// every pencil of a set (grid z = pencil, y or x = node), so that one launch per step serves a whole
+// batch of pencils of different orders.
 //
 // Right-looking blocked LU, block size nb, per step s (columns j0 = s nb .. j0 + w):
-//   panel   : pivot search (largest |re| + |im|, lowest row on ties), row swap, scaling and
-//             rank-1 updates of the n - j0 by w panel;
+//   panel   : the pivot rows and the factored n - j0 by w panel, by tournament pivoting (local
+//             partial-pivoting LUs of row blocks merged in a reduction tree, tslu_local.h; the
+//             default) or by partial pivoting over the whole column (one launch per column);
+//   swap    : the panel's interchanges applied to all other columns, and the swapped rows of the
+//             columns right of the panel staged in a buffer;
 //   trtri   : inverse of the unit lower diagonal block L_ss;
-//   swap    : the panel's interchanges applied to all other columns, and the swapped U12
-//             rows copied to a staging buffer;
+//   gemm    : the staged rows brought up to date with the earlier panels of the step's group;
 //   gemm    : U12 = L_ss^-1 * staged rows;
-//   gemm    : A22 -= L21 * U12 (the MFMA trailing update, where the flops are).
+//   gemm    : the MFMA trailing update, where the flops are: within a group of four steps only the
+//             next panel's columns, at the group's last step everything right of and below the
+//             group with K = 4 nb.
 // After the last step the inverses of the diagonal blocks of U are formed and the pivots are
 // combined into a permutation, so that the solves are products with precomputed blocks.
 #include <climits>
