@@ -554,6 +554,52 @@ int tuned_single_rows(Prec p, int q) {
 
 // ---- context creation (host), factorisation (enqueue only) and the zero-pivot check ----------
 
+// Pinned host buffers of destroyed contexts are kept for later contexts: pinning pages is slow,
+// and batches create and destroy many contexts.  A buffer is reused for a request of at least half
+// its size; at most 1 GiB stays pooled, the rest is released.
+struct PinnedPool {
+    std::mutex mu;
+    std::multimap<size_t, void*> idle;
+    std::map<void*, size_t> size_of;
+    size_t pooled = 0;
+    static constexpr size_t CAP = size_t(1) << 30;
+
+    void* get(size_t bytes) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = idle.lower_bound(bytes);
+            if (it != idle.end() && it->first <= 2 * bytes) {
+                void* p = it->second;
+                pooled -= it->first;
+                idle.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        std::lock_guard<std::mutex> g(mu);
+        size_of[p] = bytes;
+        return p;
+    }
+    void put(void* p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> g(mu);
+        const size_t b = size_of[p];
+        if (pooled + b > CAP) {
+            size_of.erase(p);
+            (void)hipHostFree(p);
+            return;
+        }
+        idle.emplace(b, p);
+        pooled += b;
+    }
+};
+
+PinnedPool& pinned_pool() {
+    static PinnedPool pool;
+    return pool;
+}
+
 // The factorisation of this pencil alone, as a set of one.
 LUSet ctx_set(feast_ctx* c) {
     LUSet one;
@@ -618,9 +664,10 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     const size_t pp = (size_t)p * p;
     const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp;
     const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
-    if (hipHostMalloc((void**)&c->h, c->hbytes, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->pin_base, pin_bytes, hipHostMallocDefault) != hipSuccess) {
-        if (c->h) (void)hipHostFree(c->h);
+    c->h = (char*)pinned_pool().get(c->hbytes);
+    c->pin_base = c->h ? (char*)pinned_pool().get(pin_bytes) : nullptr;
+    if (!c->h || !c->pin_base) {
+        pinned_pool().put(c->h);
         delete c;
         return FEAST_EDEVICE;
     }
@@ -1252,8 +1299,8 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
 
 void feast_destroy(feast_ctx* c) {
     if (!c) return;
-    if (c->h) (void)hipHostFree(c->h);
-    if (c->pin_base) (void)hipHostFree(c->pin_base);
+    pinned_pool().put(c->h);
+    pinned_pool().put(c->pin_base);
     if (c->outer_ev) (void)hipEventDestroy(c->outer_ev);
     delete c;
 }
