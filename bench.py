@@ -548,10 +548,12 @@ def main():
         prec_of_phase = "fp64" if (args.mode == "fp64" or dom in ("refine", "rayleigh_ritz")) else (
             "fp16" if (args.mode == "fp16" and dom == "lu_update") else "fp32")
         achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12 if dph["ms"] > 0 else 0.0
+        # a phase whose spans hold many kernel launches (the solves): figures per span
         roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
                         frac=achieved / PEAK[prec_of_phase], traffic=None, kernel_phase=dom,
-                        avg_launch_ms=dph["ms"] / max(1, dph["launches"]),
-                        flops_per_launch=dph["flops"] / max(1, dph["launches"]))
+                        avg_span_ms=dph["ms"] / max(1, dph["launches"]),
+                        flops_per_span=dph["flops"] / max(1, dph["launches"]),
+                        note="phase spans of several GEMM launches; per-launch figures of the update in lu_update_roofline")
     lu = ph_all["lu_update"]
     lu_roof = dict(achieved=lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0,
                    peak=PEAK[args.mode], unit="TFLOP/s", avg_launch_ms=lu["ms"] / max(1, lu["launches"]))
