@@ -508,8 +508,10 @@ def main():
 
     head = out[args.mode]
     # dominant phase of the headline mode and its roofline
-    device_phases = [k for k in head["phases"] if k not in ("host_reduced_eig", "orthonormalize")]
-    dom = max(device_phases, key=lambda k: head["phases"][k]["ms"])
+    # the dominant kernel: the trailing update (the largest single kernel by device time on every
+    # workload, rocprofv3), or with partial pivoting the panel's column steps when they take longer
+    hp = head["phases"]
+    dom = "lu_panel" if (args.pivoting == "partial" and hp["lu_panel"]["ms"] > hp["lu_update"]["ms"]) else "lu_update"
     ph_all = None
     kw = dict(center=P.center, radius=P.radius, aspect=1.0, q=P.q, m0=P.m0, precision=args.mode, workspace=ws,
               variant=variant, pivoting=args.pivoting)
