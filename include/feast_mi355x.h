@@ -58,15 +58,44 @@ typedef enum { FEAST_RULE_TRAPEZOID = 0, FEAST_RULE_GAUSS_LEGENDRE = 1 } feast_r
 typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1, FEAST_FP16_IR = 2 } feast_precision;
 typedef enum { FEAST_R = 0, FEAST_BI = 1 } feast_variant;
 
-/* The domain C and its quadrature (Section 3).  q is the number of contour
- * nodes, i.e. of node factorisations: q = 2(K-1) for a K-point trapezoid rule
- * and q = 2K for a K-point Gauss-Legendre rule on [-1, 1] (q even, q >= 2). */
+/* One piece of a glued contour (Section 5.4: domains bounded by several
+ * curves parameterised separately and joined end to end).  A line runs from
+ * (x0, y0) to (x1, y1); an arc runs counterclockwise about (cx, cy) from
+ * (x0, y0) to (x1, y1), both at the same distance from the center (relative
+ * mismatch at most 1e-10), the two ends distinct (no full circles). */
+typedef enum { FEAST_PIECE_LINE = 0, FEAST_PIECE_ARC = 1 } feast_piece_kind;
+typedef struct {
+    double x0, y0;       /* start point                               */
+    double x1, y1;       /* end point                                 */
+    double cx, cy;       /* arc center (ignored for a line)           */
+    int kind;            /* feast_piece_kind                          */
+} feast_piece;
+
+/* The domain C and its quadrature (Section 3).
+ * npieces = 0: the ellipse of eqn:ellipses about c with semi-axes R and a R.
+ *   q is the number of contour nodes, i.e. of node factorisations: q = 2(K-1)
+ *   for a K-point trapezoid rule and q = 2K for a K-point Gauss-Legendre rule
+ *   on [-1, 1] (q even, q >= 2).
+ * npieces = P > 0: the closed curve pieces[0], ..., pieces[P-1], each piece
+ *   ending where the next starts (the last where the first starts, to 1e-10
+ *   of the contour's size) and the whole traversed counterclockwise (positive
+ *   enclosed area); c, R and a are ignored.  Every piece is mapped onto
+ *   [-1, 1] and carries K = q / P rule points (q a multiple of P, K >= 1;
+ *   K >= 2 for the trapezoid): K Gauss-Legendre points per piece, or the
+ *   K + 1 points of the K-interval trapezoid rule, whose end points are shared
+ *   with the neighbouring pieces, so q nodes in both cases.  The pieces array
+ *   is read during the call that receives the contour (feast_contour_nodes,
+ *   feast_workspace_size, feast_setup, feast_batch_*) and copied; the caller
+ *   keeps ownership.  A candidate eigenvalue is inside C when the winding
+ *   number of C about it is nonzero. */
 typedef struct {
     double c_re, c_im;   /* center c                                   */
     double radius;       /* R > 0, horizontal semi-axis               */
     double aspect;       /* a > 0, vertical semi-axis is a R          */
     int q;               /* number of nodes                           */
     int rule;            /* feast_rule                                */
+    int npieces;         /* 0 for the ellipse, else pieces in the glued contour */
+    const feast_piece* pieces; /* host array of npieces pieces, or NULL */
 } feast_contour;
 
 typedef struct {
@@ -103,10 +132,21 @@ void feast_default_options(feast_options* o);
 /* ---- a1: nodes and weights (host only) ----------------------------------
  * Nodes phi_j and weights sigma_j of the rational filter
  *     rho(mu) = sum_j sigma_j / (phi_j - mu)          (eqn:quadrature_for_pi)
- * obtained by folding the Cauchy integral of eqn:cauchy_contour onto [-1, 1]
- * (eqn:pi) and merging coincident nodes.  z and sigma are HOST arrays of 2q
- * doubles (interleaved re, im).  Returns 0, or -1 for an invalid contour. */
+ * For the ellipse, obtained by folding the Cauchy integral of
+ * eqn:cauchy_contour onto [-1, 1] (eqn:pi) and merging coincident nodes.  For
+ * a glued contour, the rule of every piece in turn (pieces in order, rule
+ * points in increasing parameter), a trapezoid node shared by two pieces
+ * listed once with the sum of their weights, at the start of the piece it
+ * begins.  z and sigma are HOST arrays of 2q doubles (interleaved re, im).
+ * Returns 0, or -1 for an invalid contour. */
 int feast_contour_nodes(const feast_contour* contour, double* z, double* sigma);
+
+/* The enclosed-point test feast_iterate applies to candidate eigenvalues
+ * (Section 5 preamble: only Ritz values inside C are candidates): inside the
+ * ellipse, or a nonzero winding number of the glued contour.  lam is a HOST
+ * array of 2 count doubles (interleaved re, im); inside[i] is set to 1 or 0.
+ * Returns 0, or -1 for an invalid contour or count < 0. */
+int feast_contour_inside(const feast_contour* contour, int count, const double* lam, int* inside);
 
 /* ---- workspace ------------------------------------------------------------
  * Bytes of device workspace feast_setup needs for an n x n pencil, subspace
@@ -244,7 +284,10 @@ int feast_set_panel_rows(int precision, int q, int single_rows);
  * E[v^H rho(M) v] = trace rho(M).  feast_probe_features applies the context's
  * filter to the nprobe columns of V (device n x nprobe, column-major; nprobe <=
  * m0) and writes 2 nprobe + 3 floats to `features` (host): Re, Im of v_j^H
- * rho(M) v_j for each probe, then Re c, Im c and R of the contour.  The usual
+ * rho(M) v_j for each probe, then Re c, Im c and R of a circle containing the
+ * contour (the ellipse's center and larger semi-axis; for a glued contour the
+ * mean of the pieces' start points and the largest distance from it to the
+ * contour).  The usual
  * probe context has q = 8 nodes, FEAST_FP16_IR and ir_max = 0.  Synchronous.
  *
  * The estimator maps features to a count with a perceptron n_in -> hidden ->

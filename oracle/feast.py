@@ -24,7 +24,7 @@ from typing import List, Optional
 import numpy as np
 import scipy.linalg
 
-from .quadrature import RULE_TRAPEZOID, inside, nodes_and_weights
+from .quadrature import RULE_TRAPEZOID, glued_nodes_and_weights, inside, inside_glued, nodes_and_weights
 
 CANDIDATE_RESIDUAL = 1e-4
 
@@ -116,9 +116,21 @@ class FeastResult:
         return len(self.lam)
 
 
-def _select(lam, paper, rel, c, R, a):
+def _domain(c, R, a, pieces):
+    """Membership test of the search domain: the ellipse (c, R, a), or the glued contour's pieces
+    (Section 5.4) when given."""
+    if pieces:
+        return lambda mu: inside_glued(mu, pieces)
+    return lambda mu: inside(mu, c, R, a)
+
+
+def _nodes(c, R, a, rule, q, pieces):
+    return glued_nodes_and_weights(pieces, rule, q) if pieces else nodes_and_weights(c, R, a, rule, q)
+
+
+def _select(lam, paper, rel, dom):
     finite = np.isfinite(lam) & np.isfinite(paper)
-    return finite & inside(np.where(finite, lam, 0), c, R, a) & (paper <= CANDIDATE_RESIDUAL)
+    return finite & dom(np.where(finite, lam, 0)) & (paper <= CANDIDATE_RESIDUAL)
 
 
 def _converged(cand, rel, count, prev_count, n_inside, prev_inside, tol):
@@ -132,9 +144,9 @@ def _converged(cand, rel, count, prev_count, n_inside, prev_inside, tol):
     return bool(np.all(rel[cand] <= tol))
 
 
-def _n_inside(lam, c, R, a):
+def _n_inside(lam, dom):
     finite = np.isfinite(lam)
-    return int(np.count_nonzero(finite & inside(np.where(finite, lam, 0), c, R, a)))
+    return int(np.count_nonzero(finite & dom(np.where(finite, lam, 0))))
 
 
 def orthonormalize(Q):
@@ -143,13 +155,15 @@ def orthonormalize(Q):
     return Qo
 
 
-def rfeast(A, B, c, R, a, q, U0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, lus=None):
+def rfeast(A, B, c, R, a, q, U0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, lus=None, pieces=None):
     """Algorithm R-FEAST (Section 4).
 
     Repeat: U^ = rho(M) U_(k-1); orthonormalise U^; A^ = U^H A U^,
-    B^ = U^H B U^; solve A^ W = B^ W Lambda^ (QZ); U_(k) = U^ W."""
+    B^ = U^H B U^; solve A^ W = B^ W Lambda^ (QZ); U_(k) = U^ W.
+    The domain is the ellipse (c, R, a), or the glued contour `pieces` (Section 5.4)."""
     n = A.shape[0]
-    z, sigma = nodes_and_weights(c, R, a, rule, q)
+    z, sigma = _nodes(c, R, a, rule, q, pieces)
+    dom = _domain(c, R, a, pieces)
     if lus is None:
         lus = factor_nodes(A, B, z)
     Bm = _B(B, n)
@@ -164,14 +178,14 @@ def rfeast(A, B, c, R, a, q, U0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, lu
         X = Uh @ W
         X = X / np.linalg.norm(X, axis=0)[None, :]
         paper, rel = residuals(A, B, lam, X)
-        cand = _select(lam, paper, rel, c, R, a)
+        cand = _select(lam, paper, rel, dom)
         count = int(cand.sum())
         trace = complex(lam[cand].sum())
         history.append(dict(iter=it, count=count, trace=trace,
                             trace_change=None if prev_trace is None else abs(trace - prev_trace),
                             res_paper=float(paper[cand].max()) if count else float("nan"),
                             res_rel=float(rel[cand].max()) if count else float("nan")))
-        n_in = _n_inside(lam, c, R, a)
+        n_in = _n_inside(lam, dom)
         done = _converged(cand, rel, count, prev_count, n_in, prev_inside, tol)
         prev_count, prev_inside, prev_trace = count, n_in, trace
         if done or it == max_iter:
@@ -186,15 +200,17 @@ def biorthogonal_start(B, U0):
     return BU @ np.linalg.inv(G)
 
 
-def bifeast(A, B, c, R, a, q, U0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, lus=None, V0=None):
+def bifeast(A, B, c, R, a, q, U0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, lus=None, V0=None, pieces=None):
     """Algorithm Bi-FEAST (Section 4).
 
     Repeat: U^ = rho(M) U, V^ = B^-H rho(M)^H B^H V; orthonormalise both;
     A^ = V^H A U^, B^ = V^H B U^; solve the two-sided reduced problem for
     Lambda^, right vectors W and left vectors Z with Z^H B^ W = I;
-    U = U^ W, V = V^ Z, then restore V^H B U = I."""
+    U = U^ W, V = V^ Z, then restore V^H B U = I.
+    The domain is the ellipse (c, R, a), or the glued contour `pieces` (Section 5.4)."""
     n = A.shape[0]
-    z, sigma = nodes_and_weights(c, R, a, rule, q)
+    z, sigma = _nodes(c, R, a, rule, q, pieces)
+    dom = _domain(c, R, a, pieces)
     if lus is None:
         lus = factor_nodes(A, B, z)
     Bm = _B(B, n)
@@ -218,14 +234,14 @@ def bifeast(A, B, c, R, a, q, U0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, l
         Yl = V / np.linalg.norm(V, axis=0)[None, :]
         paper, rel = residuals(A, B, lam, X)
         rel_left = left_residuals(A, B, lam, Yl)
-        cand = _select(lam, paper, rel, c, R, a)
+        cand = _select(lam, paper, rel, dom)
         count = int(cand.sum())
         trace = complex(lam[cand].sum())
         history.append(dict(iter=it, count=count, trace=trace,
                             trace_change=None if prev_trace is None else abs(trace - prev_trace),
                             res_paper=float(paper[cand].max()) if count else float("nan"),
                             res_rel=float(rel[cand].max()) if count else float("nan")))
-        n_in = _n_inside(lam, c, R, a)
+        n_in = _n_inside(lam, dom)
         done = _converged(cand, rel, count, prev_count, n_in, prev_inside, tol)
         prev_count, prev_inside, prev_trace = count, n_in, trace
         if done or it == max_iter:

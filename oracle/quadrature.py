@@ -113,3 +113,107 @@ def eta(r_values, rule: str, q: int, a: float = 1.0, samples: int = 2048):
         v = np.abs(rho(mu, z, s))
         out.append(v.min() if r < 1.0 else v.max())
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Glued contours (Section 5.4): the boundary is a chain of pieces, each a
+# straight segment or a circular arc with a parameterisation of its own on
+# [-1, 1]; the Cauchy integral over the closed curve is the sum of the pieces'
+# integrals, and each is replaced by the same K-point rule.
+#
+# A piece is ("line", a, b) -- from a to b -- or ("arc", a, b, c) -- counter-
+# clockwise about c from a to b -- with complex points.
+# ---------------------------------------------------------------------------
+
+def _arc_angles(piece):
+    """Start angle and counterclockwise sweep (in (0, 2 pi)) of an arc piece."""
+    _, a, b, c = piece
+    th0 = math.atan2((a - c).imag, (a - c).real)
+    th1 = math.atan2((b - c).imag, (b - c).real)
+    d = (th1 - th0) % (2.0 * math.pi)
+    return th0, d
+
+
+def piece_phi(piece, t):
+    """Point of a piece at parameter t in [-1, 1]."""
+    t = np.asarray(t, dtype=np.float64)
+    if piece[0] == "line":
+        _, a, b = piece
+        return a + 0.5 * (1.0 + t) * (b - a)
+    _, a, b, c = piece
+    th0, d = _arc_angles(piece)
+    return c + abs(a - c) * np.exp(1j * (th0 + 0.5 * (1.0 + t) * d))
+
+
+def piece_phi_prime(piece, t):
+    """d phi / dt of a piece."""
+    t = np.asarray(t, dtype=np.float64)
+    if piece[0] == "line":
+        _, a, b = piece
+        return 0.5 * (b - a) * np.ones_like(t)
+    _, a, b, c = piece
+    th0, d = _arc_angles(piece)
+    return 1j * 0.5 * d * abs(a - c) * np.exp(1j * (th0 + 0.5 * (1.0 + t) * d))
+
+
+def glued_nodes_and_weights(pieces, rule: str, q: int):
+    """(phi_j, sigma_j) of a glued contour: for each piece in turn, the K = q / len(pieces) point rule
+    -- K Gauss-Legendre points, or the trapezoid with K intervals (K + 1 points) -- with weights
+    w_k phi_p'(t_k) / (2 pi i); a node that two pieces share (the trapezoid's end points) is kept
+    once, at its first appearance, with the two weights added."""
+    P = len(pieces)
+    if P < 1 or q % P:
+        raise ValueError("q must be a multiple of the number of pieces")
+    K = q // P
+    t, w = base_rule(rule, K + 1 if rule == RULE_TRAPEZOID else K)
+    zs, ss = [], []
+    scale = max([1.0] + [abs(x) for pc in pieces for x in pc[1:]])
+    for pc in pieces:
+        z = piece_phi(pc, t)
+        s = w * piece_phi_prime(pc, t) / (2j * math.pi)
+        for zk, sk in zip(z, s):
+            for i, zi in enumerate(zs):
+                if abs(zi - zk) <= 1e-10 * scale:
+                    ss[i] += sk
+                    break
+            else:
+                zs.append(zk)
+                ss.append(sk)
+    if len(zs) != q:
+        raise AssertionError(f"expected {q} nodes, got {len(zs)}")
+    return np.array(zs), np.array(ss)
+
+
+def inside_glued(mu, pieces):
+    """Even-odd test: a horizontal ray from mu towards +infinity crosses the boundary an odd number
+    of times.  Crossings with a segment use the half-open rule on the end points' heights; with an
+    arc, the circle's two intersections with the ray's line are kept when they lie to the right of
+    mu and within the arc's angular range."""
+    mu = np.atleast_1d(np.asarray(mu, dtype=np.complex128))
+    out = np.zeros(mu.shape, dtype=bool)
+    for idx, m in np.ndenumerate(mu):
+        x, y = m.real, m.imag
+        cross = 0
+        for pc in pieces:
+            if pc[0] == "line":
+                _, a, b = pc
+                if (a.imag > y) != (b.imag > y):
+                    xi = a.real + (y - a.imag) * (b.real - a.real) / (b.imag - a.imag)
+                    if xi > x:
+                        cross += 1
+            else:
+                _, a, b, c = pc
+                r = abs(a - c)
+                h = y - c.imag
+                if abs(h) >= r:
+                    continue
+                th0, d = _arc_angles(pc)
+                dx = math.sqrt(r * r - h * h)
+                for xi in (c.real - dx, c.real + dx):
+                    if xi <= x:
+                        continue
+                    off = (math.atan2(h, xi - c.real) - th0) % (2.0 * math.pi)
+                    if 0.0 < off < d:
+                        cross += 1
+        out[idx] = cross % 2 == 1
+    return out

@@ -34,7 +34,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2}
 VARIANTS = {"R": 0, "Bi": 1}
 
 EXPORTED = [
-    "feast_default_options", "feast_contour_nodes", "feast_workspace_size", "feast_setup",
+    "feast_default_options", "feast_contour_nodes", "feast_contour_inside", "feast_workspace_size", "feast_setup",
     "feast_filter", "feast_node_solve", "feast_iterate", "feast_reduced_eig", "feast_destroy",
     "feast_strerror", "feast_timing_read", "feast_timing_reset",
     "feast_batch_workspace_size", "feast_batch_setup", "feast_batch_member", "feast_batch_iterate",
@@ -46,9 +46,15 @@ EXPORTED = [
 ]
 
 
+class Piece(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y1", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("kind", ctypes.c_int)]
+
+
 class Contour(ctypes.Structure):
     _fields_ = [("c_re", ctypes.c_double), ("c_im", ctypes.c_double), ("radius", ctypes.c_double),
-                ("aspect", ctypes.c_double), ("q", ctypes.c_int), ("rule", ctypes.c_int)]
+                ("aspect", ctypes.c_double), ("q", ctypes.c_int), ("rule", ctypes.c_int),
+                ("npieces", ctypes.c_int), ("pieces", ctypes.POINTER(Piece))]
 
 
 class Options(ctypes.Structure):
@@ -101,6 +107,8 @@ def lib():
         L.feast_default_options.restype = None
         L.feast_contour_nodes.argtypes = [ctypes.POINTER(Contour), vp, vp]
         L.feast_contour_nodes.restype = i
+        L.feast_contour_inside.argtypes = [ctypes.POINTER(Contour), i, vp, vp]
+        L.feast_contour_inside.restype = i
         L.feast_workspace_size.argtypes = [i, i, ctypes.POINTER(Contour), ctypes.POINTER(Options), i,
                                            ctypes.POINTER(ctypes.c_size_t)]
         L.feast_workspace_size.restype = i
@@ -179,9 +187,36 @@ def _check(code: int, what: str, ok=(FEAST_OK,)):
     return code
 
 
-def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid") -> Contour:
+PIECE_KINDS = {"line": 0, "arc": 1}
+
+
+def make_pieces(pieces):
+    """ctypes array of a glued contour's pieces: ("line", start, end) or ("arc", start, end, center)
+    with complex points; an arc runs counterclockwise about its center."""
+    arr = (Piece * len(pieces))()
+    for P, pc in zip(arr, pieces):
+        kind, a, b = pc[0], complex(pc[1]), complex(pc[2])
+        c = complex(pc[3]) if kind == "arc" else 0j
+        P.x0, P.y0, P.x1, P.y1, P.cx, P.cy = a.real, a.imag, b.real, b.imag, c.real, c.imag
+        P.kind = PIECE_KINDS[kind]
+    return arr
+
+
+def polygon(vertices):
+    """Pieces of the polygon through the given vertices (counterclockwise order), closed."""
+    v = [complex(x) for x in vertices]
+    return [("line", v[i], v[(i + 1) % len(v)]) for i in range(len(v))]
+
+
+def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid", pieces=None) -> Contour:
+    """The ellipse about center with semi-axes radius and aspect * radius, or, when pieces is given,
+    the glued contour of those pieces (center, radius and aspect then unused)."""
     center = complex(center)
-    return Contour(center.real, center.imag, float(radius), float(aspect), int(q), RULES[rule])
+    C = Contour(center.real, center.imag, float(radius), float(aspect), int(q), RULES[rule], 0, None)
+    if pieces:
+        C.npieces = len(pieces)
+        C.pieces = make_pieces(pieces)   # ctypes keeps the array alive with the structure
+    return C
 
 
 PIVOTING = {"partial": 0, "tournament": 1}
@@ -204,13 +239,25 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     return o
 
 
-def contour_nodes(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid"):
+def contour_nodes(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid", pieces=None):
     """(z, sigma) of the filter, computed by the library (host)."""
-    C = make_contour(center, radius, aspect, q, rule)
+    C = make_contour(center, radius, aspect, q, rule, pieces)
     z = np.zeros(q, dtype=np.complex128)
     s = np.zeros(q, dtype=np.complex128)
     _check(lib().feast_contour_nodes(ctypes.byref(C), z.ctypes.data, s.ctypes.data), "feast_contour_nodes")
     return z, s
+
+
+def contour_inside(lam, center=0j, radius=1.0, aspect=1.0, q=None, rule="trapezoid", pieces=None):
+    """Boolean array: which of the points lam the library counts as inside the contour (host).  The
+    node count only has to be valid for the contour (default: two nodes per piece, or 16)."""
+    q = (2 * len(pieces) if pieces else 16) if q is None else q
+    C = make_contour(center, radius, aspect, q, rule, pieces)
+    lam = np.ascontiguousarray(np.atleast_1d(lam), dtype=np.complex128)
+    out = np.zeros(lam.shape, dtype=np.int32)
+    _check(lib().feast_contour_inside(ctypes.byref(C), lam.size, lam.ctypes.data, out.ctypes.data),
+           "feast_contour_inside")
+    return out.astype(bool)
 
 
 def reduced_eig(Ah: np.ndarray, Bh: np.ndarray, left: bool = False):
@@ -288,13 +335,13 @@ class Feast:
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
-                 timing=False, workspace=None, rank_check=False, pivoting="tournament"):
+                 timing=False, workspace=None, rank_check=False, pivoting="tournament", pieces=None):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
         self.q = q
         self.A, self.B = A, B
-        self.contour = make_contour(center, radius, aspect, q, rule)
+        self.contour = make_contour(center, radius, aspect, q, rule, pieces)
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
                                     rank_check, pivoting)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
@@ -409,7 +456,8 @@ class FeastBatch:
     """Many pencils factored by one graph launch and iterated in lockstep.
 
     pencils: list of (A, B) device tensors (B may be None); contours: list of (center, radius, aspect)
-    or one tuple for all; m0: list or one int.  All pencils share q, the rule and the options."""
+    tuples or glued-contour piece lists (see make_pieces), or one tuple for all; m0: list or one int.
+    All pencils share q, the rule and the options."""
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
@@ -424,7 +472,8 @@ class FeastBatch:
             contours = [contours] * count
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, False,
                                     rank_check, pivoting)
-        C = (Contour * count)(*[make_contour(c, r, a, q, rule) for (c, r, a) in contours])
+        C = (Contour * count)(*[make_contour(q=q, rule=rule, pieces=e) if isinstance(e, list)
+                                else make_contour(e[0], e[1], e[2], q, rule) for e in contours])
         self._C = C
         n_arr, n_p = _ptr_array(self.n, ctypes.c_int)
         m_arr, m_p = _ptr_array(self.m0, ctypes.c_int)

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "common.h"
+#include "contour.h"
 #include "gemm.h"
 #include "hostla.h"
 #include "lu.h"
@@ -62,6 +63,7 @@ struct feast_ctx {
     long ldf = 0;
     Prec prec = Prec::F64;
     feast_contour C{};
+    std::vector<feast_piece> pieces;  // copy of a glued contour's pieces; C.pieces points here
     feast_options o{};
     hipStream_t st = nullptr;
     const z64* A = nullptr; long lda = 0;
@@ -200,6 +202,8 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->m0 = m0;
     c->q = C->q;
     c->C = *C;
+    c->pieces.assign(C->pieces, C->pieces + (C->npieces > 0 ? C->npieces : 0));
+    c->C.pieces = c->pieces.empty() ? nullptr : c->pieces.data();
     c->o = *o;
     c->prec = o->precision == FEAST_FP64 ? Prec::F64 : (o->precision == FEAST_FP32_IR ? Prec::F32 : Prec::F16);
     c->nsteps = ceil_div(n, NB);
@@ -231,9 +235,7 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
 
 int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
     if (n < 1) return -1;
-    if (!C || C->q < 2 || C->q % 2 || !(C->radius > 0) || !(C->aspect > 0) ||
-        (C->rule != FEAST_RULE_TRAPEZOID && C->rule != FEAST_RULE_GAUSS_LEGENDRE))
-        return -2;
+    if (contour_check(C) != 0) return -2;
     if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI) ||
         o->pivoting < 0 || o->pivoting > 1)
         return -3;
@@ -737,11 +739,6 @@ int ctx_check_info(feast_ctx* c) {
     return 0;
 }
 
-bool inside(cd lam, const feast_contour& C) {
-    const double x = (lam.real() - C.c_re) / C.radius, y = (lam.imag() - C.c_im) / (C.aspect * C.radius);
-    return x * x + y * y < 1.0;
-}
-
 }  // namespace
 
 extern "C" {
@@ -1109,7 +1106,7 @@ int h_conv(Run& r) {
         r.paper[j] = hn[j] / hn[2 * p + j];
         r.rel[j] = hn[j] / (std::abs(r.lam[j]) * hn[p + j]);
         const bool fin = std::isfinite(r.lam[j].real()) && std::isfinite(r.lam[j].imag()) && std::isfinite(r.paper[j]);
-        const bool in = fin && inside(r.lam[j], c->C);
+        const bool in = fin && contour_inside(c->C, r.lam[j]);
         n_inside += in;
         if (in && r.paper[j] <= c->o.candidate_tol) {
             ++count;
@@ -1375,9 +1372,11 @@ int feast_probe_features(feast_ctx* c, const void* V, int ldv, int nprobe, float
         features[2 * j] = (float)ht[j].re;
         features[2 * j + 1] = (float)ht[j].im;
     }
-    features[2 * nprobe] = (float)c->C.c_re;
-    features[2 * nprobe + 1] = (float)c->C.c_im;
-    features[2 * nprobe + 2] = (float)c->C.radius;
+    double gre, gim, grad;
+    contour_circle(c->C, &gre, &gim, &grad);
+    features[2 * nprobe] = (float)gre;
+    features[2 * nprobe + 1] = (float)gim;
+    features[2 * nprobe + 2] = (float)grad;
     return 0;
 }
 

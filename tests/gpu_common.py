@@ -40,12 +40,13 @@ def golden_spectrum(name):
     return d
 
 
-def random_pencil(n, seed, with_B, m=None, cond=1e2):
-    """Small dense pencil with a prescribed spectrum (B^-1 A = V diag(lam) V^-1)."""
+def random_pencil(n, seed, with_B, m=None, cond=1e2, spectrum=None):
+    """Small dense pencil with a prescribed spectrum (B^-1 A = V diag(lam) V^-1): `spectrum` when
+    given, else m eigenvalues inside the unit circle and the rest outside."""
     import pencils
     g = np.random.default_rng(seed)
     m = max(1, n // 10) if m is None else m
-    lam = pencils.prescribed_spectrum(g, n, min(m, n))
+    lam = pencils.prescribed_spectrum(g, n, min(m, n)) if spectrum is None else np.asarray(spectrum)
     B = None
     if with_B:
         H = pencils.complex_gaussian(g, (n, n))
