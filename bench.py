@@ -129,9 +129,10 @@ def match_err(got, ref):
     return float(C[r, c].max())
 
 
-def run_steps(fm, torch, A, B, U0, P, mode, steps, warmup, ws, timing, variant="R", pivoting="tournament"):
+def run_steps(fm, torch, A, B, U0, P, mode, steps, warmup, ws, timing, variant="R", pivoting="tournament",
+              conj_nodes="none"):
     kw = dict(center=P.center, radius=P.radius, aspect=1.0, q=P.q, m0=P.m0, precision=mode, workspace=ws,
-              variant=variant, pivoting=pivoting)
+              variant=variant, pivoting=pivoting, conj_nodes=conj_nodes)
     results = []
     for _ in range(warmup):
         with fm.Feast(A, B, timing=False, **kw) as F:
@@ -307,6 +308,75 @@ def bench_batch(args, fm, torch, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_conj(args, fm, torch, dev):
+    """A real pencil on the unit circle: the nodes with Im z >= 0 are factored and their conjugates
+    reuse them (13 of 24 trapezoid nodes), timed beside the same solve with all 24 factorisations."""
+    import pencils
+    from oracle import brute
+    t0 = time.perf_counter()
+    P = pencils.real_workload()
+    log(f"real pencil n={P.n} generated in {time.perf_counter() - t0:.1f} s, m={P.m}")
+    ref = brute.eigenvalues_inside(P.lam, 0j, 1.0)
+    A, B = fm.to_device(P.A, dev), fm.to_device(P.B, dev)
+    U0 = fm.to_device(pencils.start_block(5, P.n, P.m0), dev)
+    C = fm.binding.make_contour(P.center, P.radius, 1.0, P.q)
+    o = fm.binding.make_options(args.mode, "R", pivoting=args.pivoting)
+    ws = torch.empty(fm.workspace_size(P.n, P.m0, C, o, True), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    out = {}
+    for conj in ("real", "none"):
+        steps = args.steps if conj == "real" else max(1, min(args.steps, 2))
+        wall, results, phases = run_steps(fm, torch, A, B, U0, P, args.mode, steps, args.warmup, ws, timing=True,
+                                          pivoting=args.pivoting, conj_nodes=conj)
+        factor_ms = sum(phases[k]["ms"] for k in ("lu_update", "lu_panel", "lu_other")) / steps
+        out[conj] = dict(ms_per_step=1e3 * wall / steps, iters_per_s=sum(r.iterations for r in results) / wall,
+                         iterations=results[0].iterations, converged=all(r.converged for r in results),
+                         m=len(results[0].lam), eig_err_vs_oracle=max(match_err(r.lam, ref) for r in results),
+                         factor_ms=factor_ms, solve_ms=phases["solve"]["ms"] / steps,
+                         refine_ms=phases["refine"]["ms"] / steps,
+                         phases={k: dict(ms=v["ms"] / steps, launches=v["launches"] // steps,
+                                         tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None)
+                                 for k, v in phases.items()})
+        log(f"conj_nodes={conj}: {out[conj]['ms_per_step']:.1f} ms/solve (factor {factor_ms:.1f} ms, solve "
+            f"{out[conj]['solve_ms']:.1f} ms), {out[conj]['iterations']} iterations, m={out[conj]['m']}, "
+            f"err {out[conj]['eig_err_vs_oracle']:.1e}")
+    head = out["real"]
+    upd = head["phases"]["lu_update"]
+    elem = 16 if args.mode == "fp64" else 8
+    q_factored = P.q // 2 + 1
+    nbytes, launches = update_bytes(P.n, q_factored, elem)
+    roofline = dict(bound="mfma", achieved=upd["tflops"], peak=PEAK[args.mode], unit="TFLOP/s",
+                    frac=upd["tflops"] / PEAK[args.mode], traffic=None, kernel="cgemm_kernel (trailing update)",
+                    kernel_phase="lu_update", avg_launch_ms=upd["ms"] / max(1, upd["launches"]),
+                    launches=upd["launches"], algorithmic_bytes_per_launch=nbytes / max(1, launches))
+    line = {
+        "metric": METRIC,
+        "value": head["iters_per_s"],
+        "unit": "FEAST iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.mode == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"real generalized pencil n={P.n} (20 conjugate pairs and 8 real eigenvalues in "
+                               f"|z| < 0.8), unit circle, q={P.q} trapezoid nodes of which {q_factored} factored, "
+                               f"m0={P.m0}, R-FEAST, tol 1e-10",
+                   "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
+                   "step": "setup (assembly + factored nodes) + iterations to 1e-10",
+                   "conj_nodes": "real", "pivoting": args.pivoting},
+        "time_to_1e10_s": head["ms_per_step"] / 1e3,
+        "iterations": head["iterations"],
+        "eig_err_vs_oracle": head["eig_err_vs_oracle"],
+        "shared_conjugate_nodes": out["real"],
+        "all_nodes": out["none"],
+        "speedup_vs_all_nodes": out["none"]["ms_per_step"] / head["ms_per_step"],
+        "factor_speedup_vs_all_nodes": out["none"]["factor_ms"] / head["factor_ms"],
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_m0(args, fm, torch, dev):
     """Learned subspace size: probe features (8 Rademacher probes, 8-node FP16 filter) of training
     pencils, the perceptron trained on their counts, then held-out pencils solved with m0 from
@@ -428,7 +498,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="fp32", choices=["fp32", "fp64", "fp16"])
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2", "c4"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2", "c4", "real4096"],
+                    help="real4096: a real pencil whose conjugate nodes share factorisations")
     ap.add_argument("--count-train", type=int, default=4096, help="training pencils of the learned-m0 workload")
     ap.add_argument("--count-eval", type=int, default=256, help="held-out pencils of the learned-m0 workload")
     ap.add_argument("--epochs", type=int, default=150)
@@ -471,6 +542,9 @@ def main():
         return
     if args.workload == "c4":
         bench_m0(args, fm, torch, dev)
+        return
+    if args.workload == "real4096":
+        bench_conj(args, fm, torch, dev)
         return
     variant = args.variant or ("Bi" if args.workload == "c3" else "R")
     P, U0h, ref, g = load_workload(args.workload)

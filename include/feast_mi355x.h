@@ -57,6 +57,14 @@ typedef enum { FEAST_RULE_TRAPEZOID = 0, FEAST_RULE_GAUSS_LEGENDRE = 1 } feast_r
  * accuracy in every mode. */
 typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1, FEAST_FP16_IR = 2 } feast_precision;
 typedef enum { FEAST_R = 0, FEAST_BI = 1 } feast_variant;
+/* Structure of the pencil that lets a node and its complex conjugate share one
+ * factorisation (Section 5.6 uses this for a contour symmetric about the real
+ * axis: half of the node systems need no factorisation of their own).
+ * FEAST_CONJ_REAL: A and B have real entries, so conj(z) B - A is the entrywise
+ * conjugate of z B - A.  FEAST_CONJ_HERMITIAN: A = A^H and B = B^H, so
+ * conj(z) B - A = (z B - A)^H.  The caller vouches for the structure (the
+ * library does not check A and B); results are wrong when it does not hold. */
+typedef enum { FEAST_CONJ_NONE = 0, FEAST_CONJ_REAL = 1, FEAST_CONJ_HERMITIAN = 2 } feast_conj;
 
 /* One piece of a glued contour (Section 5.4: domains bounded by several
  * curves parameterised separately and joined end to end).  A line runs from
@@ -124,6 +132,18 @@ typedef struct {
                             per column); 0 partial pivoting (LAPACK's pivots).  Both give
                             backward-stable factors in practice; the solves agree with each
                             other to the conditioning of the node systems. */
+    int conj_nodes;      /* feast_conj, default FEAST_CONJ_NONE.  Otherwise the contour's nodes
+                            must come in conjugate pairs (z, conj z) with conjugate weights, real
+                            nodes carrying real weights (any contour symmetric about the real axis,
+                            e.g. an ellipse centered on it), else setup returns
+                            FEAST_EUNSUPPORTED.  Only the nodes with Im z >= 0 are factored (q/2 + 1
+                            for the trapezoid on such an ellipse, q/2 for Gauss-Legendre), which
+                            halves the factorisation time and storage; each filter application
+                            solves with every factorisation twice, once for the node and once for
+                            its mirror (a conjugated right-hand side for REAL, the conjugate-
+                            transpose solve for HERMITIAN).  feast_node_solve then indexes the
+                            factored nodes, in their order in the full list.  Not supported by
+                            feast_batch_* (FEAST_EUNSUPPORTED). */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */

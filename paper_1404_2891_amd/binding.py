@@ -61,7 +61,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int),
-                ("pivoting", ctypes.c_int)]
+                ("pivoting", ctypes.c_int), ("conj_nodes", ctypes.c_int)]
 
 
 class PhaseTime(ctypes.Structure):
@@ -220,10 +220,11 @@ def make_contour(center=0j, radius=1.0, aspect=1.0, q=16, rule="trapezoid", piec
 
 
 PIVOTING = {"partial": 0, "tournament": 1}
+CONJ_NODES = {"none": 0, "real": 1, "hermitian": 2}
 
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament") -> Options:
+                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament", conj_nodes="none") -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -236,6 +237,7 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.timing = int(bool(timing))
     o.rank_check = int(bool(rank_check))
     o.pivoting = PIVOTING[pivoting]
+    o.conj_nodes = CONJ_NODES[conj_nodes]
     return o
 
 
@@ -335,7 +337,8 @@ class Feast:
 
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
-                 timing=False, workspace=None, rank_check=False, pivoting="tournament", pieces=None):
+                 timing=False, workspace=None, rank_check=False, pivoting="tournament", pieces=None,
+                 conj_nodes="none"):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
@@ -343,7 +346,7 @@ class Feast:
         self.A, self.B = A, B
         self.contour = make_contour(center, radius, aspect, q, rule, pieces)
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check, pivoting)
+                                    rank_check, pivoting, conj_nodes)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
         if workspace is not None:
             if workspace.numel() < nbytes or workspace.data_ptr() % 256:

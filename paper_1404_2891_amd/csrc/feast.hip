@@ -59,7 +59,8 @@ constexpr int TALL_SPLITK = 4;
 }  // namespace
 
 struct feast_ctx {
-    int n = 0, m0 = 0, q = 0, nsteps = 0;
+    int n = 0, m0 = 0, q = 0, nsteps = 0;   // q: factored nodes (all nodes unless conj_nodes)
+    int conj = FEAST_CONJ_NONE;
     long ldf = 0;
     Prec prec = Prec::F64;
     feast_contour C{};
@@ -68,7 +69,7 @@ struct feast_ctx {
     hipStream_t st = nullptr;
     const z64* A = nullptr; long lda = 0;
     const z64* B = nullptr; long ldb = 0;
-    std::vector<z64> z, sig;
+    std::vector<z64> z, sig;           // every node of the contour and its weight
     std::vector<double> norm1;
     // device
     z64 *z_d = nullptr, *wR = nullptr, *wL = nullptr, *negz = nullptr, *negzc = nullptr, *ones = nullptr;
@@ -88,6 +89,7 @@ struct feast_ctx {
     int* mask_d = nullptr;
     z64 *BU = nullptr, *QAB = nullptr, *XAB = nullptr, *T1 = nullptr, *Vb = nullptr, *Pb = nullptr;
     z64 *Eb = nullptr, *ElB = nullptr, *BhV = nullptr, *rho_d = nullptr;
+    z64 *Q2 = nullptr, *lamc_d = nullptr;   // mirror-node terms and conjugated shifts (conj_nodes only)
     z64 *T2 = nullptr, *GL_d = nullptr, *RinvL_d = nullptr, *rhoL_d = nullptr, *Ginv_d = nullptr;
     z64 *G_d = nullptr, *Rinv_d = nullptr, *AhBh = nullptr, *W_d = nullptr, *Z_d = nullptr, *lam_d = nullptr;
     double* norms_d = nullptr;
@@ -173,6 +175,10 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->T1 = b.take<z64>(np);
     c->Eb = b.take<z64>(np);
     c->rho_d = b.take<z64>(p);
+    if (c->conj != FEAST_CONJ_NONE) {
+        c->Q2 = b.take<z64>(np);
+        c->lamc_d = b.take<z64>(p);
+    }
     c->Ginv_d = b.take<z64>((size_t)p * p);
     if (c->o.variant == FEAST_BI) {
         c->Vb = b.take<z64>(np);
@@ -197,10 +203,58 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     (void)has_B;
 }
 
+// Nodes that keep a factorisation of their own when a node and its conjugate share one: those with
+// Im z >= 0 (index into the full list) and the share h of the pair's two terms each stands for (1,
+// or 1/2 for a real node, whose mirror is itself).  The nodes must come in pairs (z, conj z) with
+// conjugate weights and real nodes must carry real weights; otherwise FEAST_EUNSUPPORTED.
+int conj_plan(const feast_contour* C, std::vector<int>& keep, std::vector<double>& share) {
+    const int q = C->q;
+    std::vector<double> zz(2 * q), ss(2 * q);
+    if (feast_contour_nodes(C, zz.data(), ss.data()) != 0) return FEAST_EUNSUPPORTED;
+    std::vector<cd> z(q), s(q);
+    double zmax = 1.0, smax = 0.0;
+    for (int k = 0; k < q; ++k) {
+        z[k] = cd(zz[2 * k], zz[2 * k + 1]);
+        s[k] = cd(ss[2 * k], ss[2 * k + 1]);
+        zmax = std::max(zmax, std::abs(z[k]));
+        smax = std::max(smax, std::abs(s[k]));
+    }
+    const double zt = 1e-12 * zmax, st = 1e-12 * std::max(smax, 1e-300);
+    keep.clear();
+    share.clear();
+    int upper = 0, lower = 0;
+    for (int k = 0; k < q; ++k) {
+        if (z[k].imag() < -zt) {
+            ++lower;
+            continue;
+        }
+        if (z[k].imag() <= zt) {
+            if (std::abs(s[k].imag()) > st) return FEAST_EUNSUPPORTED;
+            keep.push_back(k);
+            share.push_back(0.5);
+            continue;
+        }
+        bool found = false;
+        for (int j = 0; j < q && !found; ++j)
+            found = std::abs(z[j] - std::conj(z[k])) <= zt && std::abs(s[j] - std::conj(s[k])) <= st;
+        if (!found) return FEAST_EUNSUPPORTED;
+        ++upper;
+        keep.push_back(k);
+        share.push_back(1.0);
+    }
+    return upper == lower ? 0 : FEAST_EUNSUPPORTED;
+}
+
 void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_options* o) {
     c->n = n;
     c->m0 = m0;
     c->q = C->q;
+    c->conj = o->conj_nodes;
+    if (c->conj != FEAST_CONJ_NONE) {
+        std::vector<int> keep;
+        std::vector<double> share;
+        if (conj_plan(C, keep, share) == 0) c->q = (int)keep.size();
+    }
     c->C = *C;
     c->pieces.assign(C->pieces, C->pieces + (C->npieces > 0 ? C->npieces : 0));
     c->C.pieces = c->pieces.empty() ? nullptr : c->pieces.data();
@@ -209,7 +263,7 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->nsteps = ceil_div(n, NB);
     c->ldf = (long)align_up((size_t)n, 8);
     c->lu.n = n;
-    c->lu.q = C->q;
+    c->lu.q = c->q;
     c->lu.nb = NB;
     c->lu.nsteps = c->nsteps;
     c->lu.ldf = c->ldf;
@@ -237,9 +291,14 @@ int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
     if (n < 1) return -1;
     if (contour_check(C) != 0) return -2;
     if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI) ||
-        o->pivoting < 0 || o->pivoting > 1)
+        o->pivoting < 0 || o->pivoting > 1 || o->conj_nodes < FEAST_CONJ_NONE || o->conj_nodes > FEAST_CONJ_HERMITIAN)
         return -3;
     if (m0 < 1 || m0 > n) return -4;
+    if (o->conj_nodes != FEAST_CONJ_NONE) {
+        std::vector<int> keep;
+        std::vector<double> share;
+        return conj_plan(C, keep, share);
+    }
     return 0;
 }
 
@@ -491,7 +550,30 @@ double default_ir_target(const feast_ctx* c) { return c->o.ir_tol > 0 ? c->o.ir_
 // shifted residual form (sh->E, sh->U) replaces the right-hand side.
 int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* Q, long ldq,
                 const Shifted* sh = nullptr) {
-    if (sh) return apply(c, 0, c->q, side, ncols, nullptr, 0, side == 0 ? c->wR : c->wL, Q, ldq, sh);
+    if (sh && c->conj == FEAST_CONJ_NONE)
+        return apply(c, 0, c->q, side, ncols, nullptr, 0, side == 0 ? c->wR : c->wL, Q, ldq, sh);
+    if (sh) {
+        // Shifted form with shared conjugate nodes.  For a mirror node conj(z) the correction term
+        // sigma' (conj(z) B - A)^-1 E / (conj(z) - l) becomes, through the node's own factorisation,
+        // conj(sigma (z B - A)^-1 conj(E) / (z - conj(l))) for real A, B, or the other side's solve
+        // of E scaled by 1/(conj(z) - l) for Hermitian A, B: in both cases a shifted-form solve with
+        // the shifts conjugated and without the U rho(l) term, which the first sum already holds
+        // (rho is evaluated over every node).
+        const int n = c->n;
+        FM_TRY(apply(c, 0, c->q, side, ncols, nullptr, 0, side == 0 ? c->wR : c->wL, Q, ldq, sh));
+        FM_TRY(combine_cm(c->lamc_d, ncols, sh->lam, ncols, ncols, 1, true, false, c->st));
+        Shifted m;
+        m.lam = c->lamc_d;
+        if (c->conj == FEAST_CONJ_REAL) {
+            FM_TRY(combine_cm(c->BU, n, sh->E, n, n, ncols, true, false, c->st));
+            m.E = c->BU;
+            FM_TRY(apply(c, 0, c->q, side, ncols, nullptr, 0, side == 0 ? c->wR : c->wL, c->Q2, n, &m));
+            return combine_cm(Q, ldq, c->Q2, n, n, ncols, true, true, c->st);
+        }
+        m.E = sh->E;
+        FM_TRY(apply(c, 0, c->q, 1 - side, ncols, nullptr, 0, side == 0 ? c->wL : c->wR, c->Q2, n, &m));
+        return combine_cm(Q, ldq, c->Q2, n, n, ncols, false, true, c->st);
+    }
     const z64* rhs = U;
     long ldr = ldu;
     if (c->B) {
@@ -499,9 +581,29 @@ int filter_impl(feast_ctx* c, int side, int ncols, const z64* U, long ldu, z64* 
         rhs = c->BU;
         ldr = c->n;
     }
-    const int rc = apply(c, 0, c->q, side, ncols, rhs, ldr, side == 0 ? c->wR : c->wL, Q, ldq);
-    c->ir_sweeps_total += c->ir_sweeps;
-    return rc;
+    const z64* w = side == 0 ? c->wR : c->wL;
+    if (c->conj == FEAST_CONJ_NONE) {
+        const int rc = apply(c, 0, c->q, side, ncols, rhs, ldr, w, Q, ldq);
+        c->ir_sweeps_total += c->ir_sweeps;
+        return rc;
+    }
+    // Nodes with Im z >= 0 give their own terms; each mirror node conj(z) shares the node's
+    // factorisation: conj(z) B - A = conj(z B - A) for real A, B, whose inverse applied to R is
+    // conj((z B - A)^-1 conj(R)); and = (z B - A)^H for Hermitian A, B, i.e. the other side's solve.
+    // The mirror weight is conj(sigma) for side 0 and sigma for side 1 (the other side's table).
+    const int n = c->n;
+    FM_TRY(apply(c, 0, c->q, side, ncols, rhs, ldr, w, Q, ldq));
+    int sweeps = c->ir_sweeps;
+    if (c->conj == FEAST_CONJ_HERMITIAN) {
+        FM_TRY(apply(c, 0, c->q, 1 - side, ncols, rhs, ldr, side == 0 ? c->wL : c->wR, c->Q2, n));
+        FM_TRY(combine_cm(Q, ldq, c->Q2, n, n, ncols, false, true, c->st));
+    } else {
+        FM_TRY(combine_cm(c->BU, n, rhs, ldr, n, ncols, true, false, c->st));
+        FM_TRY(apply(c, 0, c->q, side, ncols, c->BU, n, w, c->Q2, n));
+        FM_TRY(combine_cm(Q, ldq, c->Q2, n, n, ncols, true, true, c->st));
+    }
+    c->ir_sweeps_total += sweeps + c->ir_sweeps;
+    return 0;
 }
 
 // ---- panel tuning --------------------------------------------------------------------------------
@@ -689,25 +791,34 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     c->pin.norms = (double*)t;
     c->pin.idx = (int*)(c->pin.norms + 3 * p);
     *ctx = c;
-    // a1: nodes and weights
+    // a1: nodes and weights; the device tables list the factored nodes (all of them, or those with
+    // Im z >= 0 with their weights times the share of the conjugate pair they stand for)
     std::vector<double> zz(2 * q), ss(2 * q);
     if (feast_contour_nodes(C, zz.data(), ss.data()) != 0) return -7;
     c->z.resize(q);
     c->sig.resize(q);
-    std::vector<z64> tab(6 * q);
     for (int k = 0; k < q; ++k) {
-        const z64 zk(zz[2 * k], zz[2 * k + 1]), sk(ss[2 * k], ss[2 * k + 1]);
-        c->z[k] = zk;
-        c->sig[k] = sk;
-        tab[k] = zk;
-        tab[q + k] = sk;
-        tab[2 * q + k] = conj(sk);
-        tab[3 * q + k] = -zk;
-        tab[4 * q + k] = -conj(zk);
-        tab[5 * q + k] = z64(1.0);
+        c->z[k] = z64(zz[2 * k], zz[2 * k + 1]);
+        c->sig[k] = z64(ss[2 * k], ss[2 * k + 1]);
+    }
+    std::vector<int> keep(q);
+    std::vector<double> share(q, 1.0);
+    for (int k = 0; k < q; ++k) keep[k] = k;
+    if (c->conj != FEAST_CONJ_NONE && conj_plan(C, keep, share) != 0) return FEAST_EUNSUPPORTED;
+    const int qf = c->q;
+    if ((int)keep.size() != qf) return FEAST_EUNSUPPORTED;
+    std::vector<z64> tab(6 * qf);
+    for (int f = 0; f < qf; ++f) {
+        const z64 zk = c->z[keep[f]], sk = c->sig[keep[f]] * z64(share[f]);
+        tab[f] = zk;
+        tab[qf + f] = sk;
+        tab[2 * qf + f] = conj(sk);
+        tab[3 * qf + f] = -zk;
+        tab[4 * qf + f] = -conj(zk);
+        tab[5 * qf + f] = z64(1.0);
     }
     z64* dst[6] = {c->z_d, c->wR, c->wL, c->negz, c->negzc, c->ones};
-    for (int k = 0; k < 6; ++k) FM_TRY(h2d(c, dst[k], tab.data() + k * q, q * sizeof(z64)));
+    for (int k = 0; k < 6; ++k) FM_TRY(h2d(c, dst[k], tab.data() + k * qf, qf * sizeof(z64)));
     // descriptor and grouped-product table of the factorisation of this pencil alone
     c->lu.A = c->A; c->lu.lda = c->lda;
     c->lu.B = c->B; c->lu.ldb = c->ldb;
@@ -755,6 +866,7 @@ void feast_default_options(feast_options* o) {
     o->timing = 0;
     o->rank_check = 0;
     o->pivoting = 1;
+    o->conj_nodes = FEAST_CONJ_NONE;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -895,7 +1007,7 @@ int h2d_async(feast_ctx* c, void* dev, const void* host, size_t bytes) {
 
 z64 rho_at(const feast_ctx* c, z64 l) {
     z64 acc(0.0, 0.0);
-    for (int k = 0; k < c->q; ++k) acc = acc + cdiv(c->sig[k], c->z[k] - l);
+    for (size_t k = 0; k < c->z.size(); ++k) acc = acc + cdiv(c->sig[k], c->z[k] - l);
     return acc;
 }
 
@@ -1418,6 +1530,7 @@ int batch_layout(int count, const int* n, const int* m0, const feast_contour* C,
                  const int* has_B, BatchLayout& L) {
     if (count < 1) return -2;
     if (!n || !m0 || !C) return -3;
+    if (o && o->conj_nodes != FEAST_CONJ_NONE) return FEAST_EUNSUPPORTED;
     L.off.assign(count, 0);
     L.bytes.assign(count, 0);
     for (int b = 0; b < count; ++b) {

@@ -74,4 +74,9 @@ int gather_cols(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, 
 // Column-major copy dst = src (n x ncols).
 int copy_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, hipStream_t st);
 
+// dst = op(src) or dst += op(src), op the identity or the conjugate (column-major n x ncols; dst and
+// src may be the same block when add is false).
+int combine_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, bool conj_src, bool add,
+               hipStream_t st);
+
 }  // namespace fm

@@ -184,6 +184,17 @@ __global__ void copy_cm_kernel(z64* dst, long ldd, const z64* __restrict__ src, 
     dst[i + (long)j * ldd] = src[i + (long)j * lds];
 }
 
+__global__ void combine_cm_kernel(z64* dst, long ldd, const z64* __restrict__ src, long lds, int n, int ncols,
+                                  bool conj_src, bool add) {
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)n * ncols) return;
+    const int i = t % n, j = t / n;
+    const z64 v = src[i + (long)j * lds];
+    z64* d = dst + i + (long)j * ldd;
+    const z64 w = conj_src ? conj(v) : v;
+    *d = add ? *d + w : w;
+}
+
 __global__ void axpy_rows_kernel(z64* R, long ldr, long sr, const z64* __restrict__ Y, long ldy, long sy,
                                  const z64* __restrict__ alpha, int n, int ncols) {
     const int k = blockIdx.y;
@@ -349,6 +360,15 @@ int gather_cols(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, 
 
 int copy_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, hipStream_t st) {
     hipLaunchKernelGGL(copy_cm_kernel, grid1((long)n * ncols), dim3(256), 0, st, dst, ldd, src, lds, n, ncols);
+    FM_LAUNCH_CHECK();
+    return 0;
+}
+
+int combine_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, bool conj_src, bool add,
+               hipStream_t st) {
+    if ((long)n * ncols == 0) return 0;
+    hipLaunchKernelGGL(combine_cm_kernel, grid1((long)n * ncols), dim3(256), 0, st, dst, ldd, src, lds, n, ncols,
+                       conj_src, add);
     FM_LAUNCH_CHECK();
     return 0;
 }

@@ -180,6 +180,38 @@ def c0(n: int = 200, m: int = 10, seed_cfg: int = 0, q: int = 16, m0: int = 16) 
     return Pencil(A, None, lam, 0j, 1.0, 1.0, q, m0, m, name=f"c0_n{n}")
 
 
+def real_pencil(rng, n, m_pairs, m_real, r_inside=0.8, r_in=1.5, r_out=5.0):
+    """Real A, B (stored as complex128) with B^-1 A = V D V^-1, D real block diagonal: m_pairs
+    conjugate pairs (2 x 2 blocks [[a, b], [-b, a]]) and m_real real eigenvalues area-uniform in
+    |z| < r_inside, the rest (pairs, and one real when the count is odd) in r_in < |z| < r_out;
+    V = 2 I + G / sqrt(n) and B = I + 0.1 H / sqrt(n) with real Gaussian G, H.  Returns A, B and the
+    eigenvalues (block order)."""
+    def ring(lo, hi, count, real):
+        r = np.sqrt(rng.uniform(lo ** 2, hi ** 2, count))
+        if real:
+            return r * np.sign(rng.uniform(-1, 1, count))
+        return r * np.exp(1j * rng.uniform(0.1, np.pi - 0.1, count))
+    inner_pairs, inner_real = ring(0, r_inside, m_pairs, False), ring(0.05, r_inside, m_real, True)
+    n_out_pairs = (n - 2 * m_pairs - m_real) // 2
+    n_out_real = n - 2 * m_pairs - m_real - 2 * n_out_pairs
+    outer_pairs, outer_real = ring(r_in, r_out, n_out_pairs, False), ring(r_in, r_out, n_out_real, True)
+    D = np.zeros((n, n))
+    lam = []
+    i = 0
+    for z in np.concatenate([inner_pairs, outer_pairs]):
+        D[i:i + 2, i:i + 2] = [[z.real, z.imag], [-z.imag, z.real]]
+        lam += [z, np.conj(z)]
+        i += 2
+    for x in np.concatenate([inner_real, outer_real]):
+        D[i, i] = x.real
+        lam.append(complex(x.real))
+        i += 1
+    V = rng.standard_normal((n, n)) / np.sqrt(n) + 2.0 * np.eye(n)
+    B = np.eye(n) + 0.1 * rng.standard_normal((n, n)) / np.sqrt(n)
+    A = B @ V @ D @ np.linalg.inv(V)
+    return np.asfortranarray(A.astype(np.complex128)), np.asfortranarray(B.astype(np.complex128)), np.array(lam)
+
+
 def complex_symmetric_pencil(rng, n, absorb=0.05, bscale=0.05):
     """A = (G + G^T)/(2 sqrt n) + i diag(absorb (j/n)^2), B = I + bscale (H + H^H)/sqrt n (HPD)."""
     G = complex_gaussian(rng, (n, n))
@@ -214,6 +246,15 @@ def c3(n: int = 8192, radius: Optional[float] = None, seed_cfg: int = 3, q: int 
     rng = np.random.default_rng([base_seed(seed_cfg), 0])
     A, B = complex_symmetric_pencil(rng, n)
     return Pencil(A, B, None, 0j, 0.5 if radius is None else radius, 1.0, q, m0, m, name=f"c3_n{n}")
+
+
+def real_workload(n: int = 4096, seed_cfg: int = 5, q: int = 24, m0: int = 64, m_pairs: int = 20,
+                  m_real: int = 8) -> Pencil:
+    """Real generalized pencil for nodes that share a factorisation with their conjugates: 20 pairs and
+    8 real eigenvalues inside the unit circle (m = 48), q trapezoid nodes, m0 = 64."""
+    rng = np.random.default_rng([base_seed(seed_cfg), 0])
+    A, B, lam = real_pencil(rng, n, m_pairs, m_real)
+    return Pencil(A, B, lam, 0j, 1.0, 1.0, q, m0, 2 * m_pairs + m_real, name=f"real_n{n}")
 
 
 def c2_sizes(count: int = 64, seed_cfg: int = 2, n_lo: int = 256, n_hi: int = 2048):

@@ -160,3 +160,39 @@ def test_autotune_workspace_size():
     assert fm.lib().feast_autotune_workspace_size(16, 1, ctypes.byref(out)) == 0
     assert out.value >= 16 * 6144 * 64 * 8
     assert fm.lib().feast_autotune_workspace_size(0, 1, ctypes.byref(out)) < 0
+
+
+def test_conjugate_node_sharing_workspace_and_validation():
+    """With conj_nodes a node and its conjugate share one factorisation: a contour symmetric about
+    the real axis needs about half the factor storage; an asymmetric one is refused (host-side
+    checks, no device work)."""
+    o_full = binding.make_options(precision="fp64")
+    o_real = binding.make_options(precision="fp64", conj_nodes="real")
+    o_herm = binding.make_options(precision="fp64", conj_nodes="hermitian")
+    sym = binding.make_contour(0.3 + 0j, 1.0, 0.7, 24)
+    full = fm.workspace_size(2048, 32, sym, o_full, True)
+    half = fm.workspace_size(2048, 32, sym, o_real, True)
+    assert half == fm.workspace_size(2048, 32, sym, o_herm, True)
+    # trapezoid on an ellipse centered on the real axis: 13 of 24 nodes factored (two real nodes)
+    assert 0.5 < half / full < 0.6, half / full
+    gl = binding.make_contour(0.3 + 0j, 1.0, 1.0, 24, "gauss-legendre")
+    assert fm.workspace_size(2048, 32, gl, o_real, True) < half
+    nbytes = ctypes.c_size_t(0)
+    off_axis = binding.make_contour(0.3 + 0.1j, 1.0, 1.0, 24)
+    rc = fm.lib().feast_workspace_size(2048, 32, ctypes.byref(off_axis), ctypes.byref(o_real), 1, ctypes.byref(nbytes))
+    assert rc == binding.FEAST_EUNSUPPORTED
+    # a glued contour symmetric about the real axis is accepted, a triangle above it is not
+    square = binding.make_contour(q=32, pieces=fm.polygon([-0.5 - 0.5j, 0.5 - 0.5j, 0.5 + 0.5j, -0.5 + 0.5j]))
+    assert fm.workspace_size(2048, 32, square, o_herm, True) < fm.workspace_size(2048, 32, square, o_full, True)
+    tri = binding.make_contour(q=24, pieces=fm.polygon([0j, 2 + 0j, 1 + 1.5j]))
+    rc = fm.lib().feast_workspace_size(2048, 32, ctypes.byref(tri), ctypes.byref(o_herm), 1, ctypes.byref(nbytes))
+    assert rc == binding.FEAST_EUNSUPPORTED
+    # batches do not take shared conjugate nodes
+    ns = (ctypes.c_int * 2)(256, 300)
+    ms = (ctypes.c_int * 2)(8, 8)
+    Cs = (binding.Contour * 2)(sym, sym)
+    rc = fm.lib().feast_batch_workspace_size(2, ns, ms, Cs, ctypes.byref(o_real), None, ctypes.byref(nbytes))
+    assert rc == binding.FEAST_EUNSUPPORTED
+    bad = binding.make_options(precision="fp64")
+    bad.conj_nodes = 3
+    assert fm.lib().feast_workspace_size(2048, 32, ctypes.byref(sym), ctypes.byref(bad), 1, ctypes.byref(nbytes)) < 0

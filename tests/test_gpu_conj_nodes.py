@@ -1,0 +1,131 @@
+"""Conjugate nodes sharing one factorisation (Section 5.6: a contour symmetric about the real axis
+needs only half of the factorisations), on the device against the oracle's plain filter over all q
+nodes and against the brute-force spectrum.  Real pencils (conj(z) B - A = conj(z B - A)) and
+Hermitian A, B (conj(z) B - A = (z B - A)^H)."""
+import numpy as np
+import pytest
+
+import pencils
+from oracle import brute, feast
+from oracle import quadrature as Q
+from tests.gpu_common import device, match_eigs, rel_err
+
+pytestmark = pytest.mark.gpu
+U64 = 2.0 ** -53
+
+
+def fm():
+    import paper_1404_2891_amd as m
+    return m
+
+
+def upload(a):
+    return None if a is None else fm().to_device(a, device())
+
+
+def real_pencil(n, seed, m_pairs=4, m_real=2):
+    """Real A, B: m_pairs conjugate pairs and m_real real eigenvalues inside |z| < 0.8, the rest in
+    1.5 < |z| < 5."""
+    return pencils.real_pencil(np.random.default_rng(seed), n, m_pairs, m_real)
+
+
+def hermitian_pencil(n, seed):
+    """Hermitian A and indefinite Hermitian B: a non-Hermitian problem whose eigenvalues are real or
+    come in conjugate pairs."""
+    g = np.random.default_rng(seed)
+    G = pencils.complex_gaussian(g, (n, n))
+    A = (G + G.conj().T) / (2 * np.sqrt(n))
+    d = np.where(np.arange(n) % 5 == 0, -1.0, 1.0)
+    H = pencils.complex_gaussian(g, (n, n))
+    B = np.diag(d) + 0.05 * (H + H.conj().T) / np.sqrt(n)
+    return np.asfortranarray(A), np.asfortranarray(B)
+
+
+@pytest.mark.parametrize("kind", ["real", "hermitian"])
+@pytest.mark.parametrize("rule,q", [("trapezoid", 16), ("gauss-legendre", 16), ("trapezoid", 10)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_filter_with_shared_conjugate_nodes_matches_oracle(kind, rule, q, prec):
+    n, m0 = 257, 9
+    if kind == "real":
+        A, B, _ = real_pencil(n, seed=q)
+        c, R, a = 0.1 + 0j, 1.05, 0.8
+    else:
+        A, B = hermitian_pencil(n, seed=q)
+        c, R, a = -0.05 + 0j, 0.9, 0.6
+    F = fm().Feast(upload(A), upload(B), c, R, a, q, m0, rule=rule, precision=prec, conj_nodes=kind)
+    z, s = Q.nodes_and_weights(c, R, a, rule, q)
+    lus = feast.factor_nodes(A, B, z)
+    U = pencils.complex_gaussian(np.random.default_rng(q + 1), (n, m0))
+    kappa = max(np.linalg.cond(feast.node_matrix(A, B, zk)) for zk in z)
+    tol = (50 if prec == "fp64" else 200) * kappa * U64 * 4
+    for side in (0, 1):
+        got = F.filter(upload(U), side).cpu().numpy()
+        ref = (feast.filter_right if side == 0 else feast.filter_left)(lus, s, B, U)
+        assert rel_err(got, ref) < tol, (side, rel_err(got, ref), tol)
+    F.close()
+
+
+def test_filter_glued_square_hermitian():
+    """A glued square symmetric about the real axis (8 trapezoid points per side)."""
+    n, m0 = 200, 8
+    A, B = hermitian_pencil(n, seed=3)
+    pieces = fm().polygon([-0.6 - 0.5j, 0.6 - 0.5j, 0.6 + 0.5j, -0.6 + 0.5j])
+    F = fm().Feast(upload(A), upload(B), q=32, m0=m0, conj_nodes="hermitian", pieces=pieces)
+    z, s = Q.glued_nodes_and_weights(pieces, "trapezoid", 32)
+    lus = feast.factor_nodes(A, B, z)
+    U = pencils.complex_gaussian(np.random.default_rng(9), (n, m0))
+    kappa = max(np.linalg.cond(feast.node_matrix(A, B, zk)) for zk in z)
+    for side in (0, 1):
+        got = F.filter(upload(U), side).cpu().numpy()
+        ref = (feast.filter_right if side == 0 else feast.filter_left)(lus, s, B, U)
+        assert rel_err(got, ref) < 200 * kappa * U64, side
+    F.close()
+
+
+@pytest.mark.parametrize("variant", ["R", "Bi"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_iterate_real_pencil_shared_nodes(variant, prec):
+    """Real pencil, unit circle, 16 trapezoid nodes of which 9 are factored: the enclosed eigenvalues
+    (4 conjugate pairs and 2 real) to 1e-10, as with all 16 factorisations (FP32: the shifted
+    residual form of the later iterations, mirror terms included)."""
+    n = 300
+    A, B, lam = real_pencil(n, seed=21)
+    ref = brute.eigenvalues_inside(lam, 0j, 1.0)
+    assert len(ref) == 10
+    U0 = pencils.complex_gaussian(np.random.default_rng(4), (n, 16))
+    F = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, 16, 16, variant=variant, precision=prec, conj_nodes="real")
+    r = F.iterate(upload(U0))
+    assert r.converged and len(r.lam) == 10, (len(r.lam), r.history)
+    assert match_eigs(r.lam, ref) < 1e-10
+    assert np.all(r.resid <= 1e-10)
+    F.close()
+    G = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, 16, 16, variant=variant, precision=prec)
+    g = G.iterate(upload(U0))
+    assert abs(g.iterations - r.iterations) <= 1
+    G.close()
+
+
+@pytest.mark.parametrize("variant", ["R", "Bi"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_iterate_hermitian_pencil_shared_nodes(variant, prec):
+    """Hermitian A, indefinite Hermitian B; a Gauss-Legendre circle about 0 (no real nodes, 8 of 16
+    factored) whose radius sits in the widest gap of |lambda| around 8 eigenvalues."""
+    n = 300
+    A, B = hermitian_pencil(n, seed=8)
+    lam = brute.all_eigenvalues(A, B)
+    R = brute.widest_gap_radius(lam, 0j, 8, window=3)[0]
+    ref = brute.eigenvalues_inside(lam, 0j, R)
+    U0 = pencils.complex_gaussian(np.random.default_rng(6), (n, len(ref) + 8))
+    F = fm().Feast(upload(A), upload(B), 0j, R, 1.0, 16, len(ref) + 8, rule="gauss-legendre", variant=variant,
+                   precision=prec, conj_nodes="hermitian", max_iter=40)
+    r = F.iterate(upload(U0))
+    assert r.converged and len(r.lam) == len(ref), (len(r.lam), len(ref), r.history)
+    assert match_eigs(r.lam, ref) < 1e-10
+    F.close()
+
+
+def test_asymmetric_contour_is_refused():
+    A, B, _ = real_pencil(64, seed=1)
+    with pytest.raises(fm().FeastError) as e:
+        fm().Feast(upload(A), upload(B), 0.1 + 0.2j, 1.0, 1.0, 16, 8, conj_nodes="real")
+    assert e.value.code == fm().binding.FEAST_EUNSUPPORTED

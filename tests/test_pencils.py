@@ -48,3 +48,12 @@ def test_batched_pencil_torch_path_matches_numpy():
     assert Q.A.stride() == (1, 150)
     assert np.abs(Q.A.numpy() - P.A).max() < 1e-12 * np.abs(P.A).max()
     assert np.array_equal(Q.B.numpy(), P.B)
+
+
+def test_real_pencil_has_real_entries_and_the_stated_spectrum():
+    import scipy.linalg
+    from tests.gpu_common import match_eigs
+    A, B, lam = pencils.real_pencil(np.random.default_rng(3), 61, 4, 3)
+    assert np.all(A.imag == 0) and np.all(B.imag == 0)
+    assert np.sum(np.abs(lam) < 0.8) == 11
+    assert match_eigs(scipy.linalg.eigvals(A, B), lam) < 1e-9
