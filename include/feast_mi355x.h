@@ -56,7 +56,10 @@ typedef enum { FEAST_RULE_TRAPEZOID = 0, FEAST_RULE_GAUSS_LEGENDRE = 1 } feast_r
  * refinement stalls (feast_result.escalated).  The filter is computed to FP64
  * accuracy in every mode. */
 typedef enum { FEAST_FP64 = 0, FEAST_FP32_IR = 1, FEAST_FP16_IR = 2 } feast_precision;
-typedef enum { FEAST_R = 0, FEAST_BI = 1 } feast_variant;
+/* FEAST_L: the left-projector twin of R-FEAST that Section 4 mentions (one
+ * projector, the left one): R-FEAST on the adjoint pencil (A^H, B^H) over the
+ * conjugate contour, whose filter is the left filter of eqn:quadf_surMconj. */
+typedef enum { FEAST_R = 0, FEAST_BI = 1, FEAST_L = 2 } feast_variant;
 /* Structure of the pencil that lets a node and its complex conjugate share one
  * factorisation (Section 5.6 uses this for a contour symmetric about the real
  * axis: half of the node systems need no factorisation of their own).
@@ -108,7 +111,8 @@ typedef struct {
 
 typedef struct {
     int precision;       /* feast_precision of the node factorisations and solves            */
-    int variant;         /* feast_variant: R-FEAST (right projector) or Bi-FEAST (both)       */
+    int variant;         /* feast_variant: R-FEAST (right projector), Bi-FEAST (both) or the
+                            left-projector variant                                           */
     int max_iter;        /* FEAST iterations, default 30                                       */
     double tol;          /* stop when every candidate has ||Ax - lBx|| / (|l| ||Bx||) <= tol
                             and the candidate count repeats; default 1e-10                     */
@@ -211,8 +215,10 @@ int feast_node_solve(feast_ctx* ctx, int k, int side, int ncols, const void* R, 
                      int ldy);
 
 /* ---- a8: the FEAST iteration ----------------------------------------------
- * Runs Algorithm R-FEAST (variant FEAST_R) or Bi-FEAST (FEAST_BI) of Section 4
- * from the start block U0 (device n x m0).  After each filter the basis is
+ * Runs Algorithm R-FEAST (variant FEAST_R) or Bi-FEAST (FEAST_BI) of Section 4,
+ * or the left-projector variant (FEAST_L: U <- B^-H rho(M)^H B^H U, Rayleigh-Ritz
+ * with U^H A^H U and U^H B^H U, whose Ritz values are the conjugates of the
+ * eigenvalues), from the start block U0 (device n x m0).  After each filter the basis is
  * orthonormalised (shifted Cholesky-QR, FP64); the reduced m0 x m0 problem is
  * solved on the host; candidates are Ritz pairs inside C with paper-form
  * residual <= candidate_tol.  Stops when all candidates have relative residual
@@ -223,7 +229,8 @@ int feast_node_solve(feast_ctx* ctx, int k, int side, int ncols, const void* R, 
  *   lambda      host, 2*m0 doubles: candidate eigenvalues first
  *   resid       host, m0 doubles: relative residuals of the candidates
  *   X           device n x m0 (ldx): candidate right eigenvectors in the first
- *               m columns, unit 2-norm
+ *               m columns, unit 2-norm (FEAST_L: left eigenvectors y, with
+ *               A^H y = conj(lambda) B^H y; resid is then their residual)
  *   Y           device n x m0 (ldy), Bi-FEAST only (may be NULL): left
  *               eigenvectors with Y^H B X = I on the candidates
  *   history     host, max_iter x 4 doubles or NULL: per iteration the candidate

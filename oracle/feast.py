@@ -193,6 +193,47 @@ def rfeast(A, B, c, R, a, q, U0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, lu
         U = X
 
 
+def lfeast(A, B, c, R, a, q, V0, rule=RULE_TRAPEZOID, tol=1e-10, max_iter=30, lus=None, pieces=None):
+    """The left-projector variant of R-FEAST (Section 4 notes that it works the same way): the basis
+    is filtered by the left filter of eqn:quadf_surMconj, V^ = B^-H rho(M)^H B^H V, and Rayleigh-Ritz
+    uses the adjoint pencil, A^ = V^H A^H V^, B^ = V^H B^H V^, whose eigenvalues mu are the conjugates
+    of the eigenvalues of (A, B): lambda = conj(mu), left eigenvectors y = V^ W with
+    A^H y = conj(lambda) B^H y.  Candidates and stopping as in R-FEAST, with the residual of the left
+    pairs."""
+    n = A.shape[0]
+    z, sigma = _nodes(c, R, a, rule, q, pieces)
+    dom = _domain(c, R, a, pieces)
+    if lus is None:
+        lus = factor_nodes(A, B, z)
+    Bm = _B(B, n)
+    V = np.array(V0, dtype=np.complex128)
+    history = []
+    prev_count = prev_inside = prev_trace = None
+    for it in range(1, max_iter + 1):
+        Vh = orthonormalize(filter_left(lus, sigma, B, V))
+        Ah = Vh.conj().T @ (A.conj().T @ Vh)
+        Bh = Vh.conj().T @ (Bm.conj().T @ Vh)
+        mu, W = scipy.linalg.eig(Ah, Bh)
+        lam = np.conj(mu)
+        Y = Vh @ W
+        Y = Y / np.linalg.norm(Y, axis=0)[None, :]
+        # residuals of the left pairs: those of the adjoint pencil at mu
+        paper, rel = residuals(A.conj().T, Bm.conj().T, mu, Y)
+        cand = _select(lam, paper, rel, dom)
+        count = int(cand.sum())
+        trace = complex(lam[cand].sum())
+        history.append(dict(iter=it, count=count, trace=trace,
+                            trace_change=None if prev_trace is None else abs(trace - prev_trace),
+                            res_paper=float(paper[cand].max()) if count else float("nan"),
+                            res_rel=float(rel[cand].max()) if count else float("nan")))
+        n_in = _n_inside(lam, dom)
+        done = _converged(cand, rel, count, prev_count, n_in, prev_inside, tol)
+        prev_count, prev_inside, prev_trace = count, n_in, trace
+        if done or it == max_iter:
+            return FeastResult(lam[cand], Y[:, cand], rel[cand], paper[cand], it, done, history, lam)
+        V = Y
+
+
 def biorthogonal_start(B, U0):
     """V0 with V0^H B U0 = I: V0 = B U0 (U0^H B^H B U0)^-1."""
     BU = U0 if B is None else B @ U0

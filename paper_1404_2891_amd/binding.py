@@ -31,7 +31,7 @@ FEAST_ESINGULAR = 1000
 
 RULES = {"trapezoid": 0, "gauss-legendre": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2}
-VARIANTS = {"R": 0, "Bi": 1}
+VARIANTS = {"R": 0, "Bi": 1, "L": 2}
 
 EXPORTED = [
     "feast_default_options", "feast_contour_nodes", "feast_contour_inside", "feast_workspace_size", "feast_setup",

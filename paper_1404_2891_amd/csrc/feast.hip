@@ -90,6 +90,7 @@ struct feast_ctx {
     z64 *BU = nullptr, *QAB = nullptr, *XAB = nullptr, *T1 = nullptr, *Vb = nullptr, *Pb = nullptr;
     z64 *Eb = nullptr, *ElB = nullptr, *BhV = nullptr, *rho_d = nullptr;
     z64 *Q2 = nullptr, *lamc_d = nullptr;   // mirror-node terms and conjugated shifts (conj_nodes only)
+    z64* lamL_d = nullptr;                  // conj of the adjoint Ritz values (left-projector variant)
     z64 *T2 = nullptr, *GL_d = nullptr, *RinvL_d = nullptr, *rhoL_d = nullptr, *Ginv_d = nullptr;
     z64 *G_d = nullptr, *Rinv_d = nullptr, *AhBh = nullptr, *W_d = nullptr, *Z_d = nullptr, *lam_d = nullptr;
     double* norms_d = nullptr;
@@ -179,6 +180,7 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
         c->Q2 = b.take<z64>(np);
         c->lamc_d = b.take<z64>(p);
     }
+    if (c->o.variant == FEAST_L) c->lamL_d = b.take<z64>(p);
     c->Ginv_d = b.take<z64>((size_t)p * p);
     if (c->o.variant == FEAST_BI) {
         c->Vb = b.take<z64>(np);
@@ -290,7 +292,7 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
 int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
     if (n < 1) return -1;
     if (contour_check(C) != 0) return -2;
-    if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI) ||
+    if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI && o->variant != FEAST_L) ||
         o->pivoting < 0 || o->pivoting > 1 || o->conj_nodes < FEAST_CONJ_NONE || o->conj_nodes > FEAST_CONJ_HERMITIAN)
         return -3;
     if (m0 < 1 || m0 > n) return -4;
@@ -989,6 +991,9 @@ struct Run {
 };
 
 bool is_bi(const feast_ctx* c) { return c->o.variant == FEAST_BI; }
+// the left-projector variant: R-FEAST on (A^H, B^H); the Ritz values mu held on the device and in
+// pin.lam are those of the adjoint pencil, the eigenvalues are conj(mu)
+bool is_left(const feast_ctx* c) { return c->o.variant == FEAST_L; }
 
 // device pointers of the blocks of one side of the iteration
 z64* side_X(feast_ctx* c, int side) { return side == 0 ? c->QAB : c->Pb; }
@@ -1060,15 +1065,24 @@ int e_filter(Run& r) {
     }
     z64* U = c->XAB;
     const bool shifted = c->prec != Prec::F64 && c->o.ir_tol == 0 && r.it > 1;
+    // the left-projector variant filters with the left filter, i.e. the right filter of the
+    // adjoint pencil over the conjugate contour: rho'(mu) = conj(rho(conj mu)), and the side-1
+    // solves take the shifts conj(mu)
+    const int fside = is_left(c) ? 1 : 0;
     if (shifted) {
-        for (int j = 0; j < p; ++j) c->pin.rho[0][j] = rho_at(c, c->pin.lam[j]);
+        for (int j = 0; j < p; ++j)
+            c->pin.rho[0][j] = is_left(c) ? conj(rho_at(c, conj(c->pin.lam[j]))) : rho_at(c, c->pin.lam[j]);
         FM_TRY(h2d_async(c, c->rho_d, c->pin.rho[0], p * sizeof(z64)));
         FM_TRY(residual_block(c->Eb, U + np, U + 2 * np, n, n, p, c->lam_d, false, st));
         Shifted sh;
         sh.U = U; sh.E = c->Eb; sh.lam = c->lam_d; sh.rho = c->rho_d;
-        FM_TRY(filter_impl(c, 0, p, U, n, c->QAB, n, &sh));
+        if (is_left(c)) {
+            FM_TRY(combine_cm(c->lamL_d, p, c->lam_d, p, p, 1, true, false, st));
+            sh.lam = c->lamL_d;
+        }
+        FM_TRY(filter_impl(c, fside, p, U, n, c->QAB, n, &sh));
     } else {
-        FM_TRY(filter_impl(c, 0, p, U, n, c->QAB, n));
+        FM_TRY(filter_impl(c, fside, p, U, n, c->QAB, n));
     }
     FM_TRY(gram(c, c->QAB, n, c->QAB, n, p, c->G_d));
     FM_TRY(d2h_async(c, c->pin.G[0], c->G_d, (size_t)p * p * sizeof(z64)));
@@ -1155,9 +1169,10 @@ int e_orth(Run& r, int pass) {
     // Rayleigh-Ritz: A^ = W^H A Q, B^ = W^H B Q with W = Q (R-FEAST) or P (Bi-FEAST)
     z64* Q = c->QAB;
     c->timer.start(PH_RR, st);
-    FM_TRY(tall_product(c, c->A, c->lda, 0, p, Q, n, Q + np, n));
+    const int op = is_left(c) ? 1 : 0;   // A^H Q and B^H Q for the left-projector variant
+    FM_TRY(tall_product(c, c->A, c->lda, op, p, Q, n, Q + np, n));
     if (c->B) {
-        FM_TRY(apply_B(c, 0, p, Q, n, Q + 2 * np, n));
+        FM_TRY(apply_B(c, op, p, Q, n, Q + 2 * np, n));
     } else {
         FM_TRY(copy_cm(Q + 2 * np, n, Q, n, n, p, st));
     }
@@ -1214,7 +1229,7 @@ int h_conv(Run& r) {
     cd trace(0.0, 0.0);
     double maxrel = 0.0;
     for (int j = 0; j < p; ++j) {
-        r.lam[j] = cd(c->pin.lam[j].re, c->pin.lam[j].im);
+        r.lam[j] = cd(c->pin.lam[j].re, is_left(c) ? -c->pin.lam[j].im : c->pin.lam[j].im);
         r.paper[j] = hn[j] / hn[2 * p + j];
         r.rel[j] = hn[j] / (std::abs(r.lam[j]) * hn[p + j]);
         const bool fin = std::isfinite(r.lam[j].real()) && std::isfinite(r.lam[j].imag()) && std::isfinite(r.paper[j]);

@@ -266,3 +266,59 @@ def test_planted_mistakes_are_caught():
     bad2 = sum(np.conj(sk) * scipy.linalg.lu_solve(lu, B.conj().T @ Vin, trans=1) for sk, lu in zip(s, lus))
     for bad in (bad1, bad2):
         assert np.linalg.norm(bad - expect) / np.linalg.norm(expect) > 1e-3
+
+
+@pytest.mark.parametrize("with_B", [False, True])
+@pytest.mark.parametrize("rule", [TR, GL])
+def test_left_projector_variant_finds_left_eigenpairs(with_B, rule):
+    """The left-projector variant: exactly the prescribed eigenvalues inside the contour, and every
+    returned vector is a left eigenvector by definition (y^H A = lambda y^H B, i.e. the rows of
+    Y_exact = B^-H V^-H up to scale)."""
+    A, B, lam, V = small_pencil(n=80, m=6, with_B=with_B, seed=23)
+    c = 0.05 - 0.02j
+    V0 = pencils.complex_gaussian(np.random.default_rng(4), (80, 10))
+    r = feast.lfeast(A, B, c, 1.0, 1.0, 16, V0, rule=rule)
+    ref = brute.eigenvalues_inside(lam, c, 1.0)
+    assert r.converged and r.m == len(ref) == 6
+    assert match_eigs(r.lam, ref) < 1e-10
+    Bm = np.eye(80) if B is None else B
+    for j in range(r.m):
+        y = r.X[:, j]
+        res = np.linalg.norm(y.conj() @ A - r.lam[j] * (y.conj() @ Bm)) / (abs(r.lam[j]) * np.linalg.norm(y.conj() @ Bm))
+        assert res < 1e-9
+    # the exact left eigenvector of the matching eigenvalue: Y = B^-H V^-H, columns in lam's order
+    Yx = np.linalg.inv(Bm.conj().T) @ np.linalg.inv(V).conj().T
+    for j in range(r.m):
+        k = int(np.argmin(np.abs(lam - r.lam[j])))
+        y, yx = r.X[:, j], Yx[:, k] / np.linalg.norm(Yx[:, k])
+        assert abs(abs(np.vdot(yx, y)) - 1) < 1e-8
+
+
+def test_left_projector_variant_planted_mistakes():
+    """Plausible slips break the pins above: with the right filter in place of the left one the basis
+    tends to right eigenvectors (the eigenvalues still come out, since any invariant subspace gives
+    them, but the vectors fail the left-eigenvector test); adjoint Ritz values reported without
+    conjugation miss the eigenvalues."""
+    A, B, lam, V = small_pencil(n=60, m=5, with_B=True, seed=29)
+    z, s = Q.nodes_and_weights(0j, 1.0, 1.0, TR, 16)
+    lus = feast.factor_nodes(A, B, z)
+    ref = brute.eigenvalues_inside(lam, 0, 1.0)
+
+    def run(filt, conj_back):
+        Vb = pencils.complex_gaussian(np.random.default_rng(3), (60, 9))
+        for _ in range(8):
+            Vh = feast.orthonormalize(filt(lus, s, B, Vb))
+            mu, W = scipy.linalg.eig(Vh.conj().T @ A.conj().T @ Vh, Vh.conj().T @ B.conj().T @ Vh)
+            Vb = Vh @ W
+        lam_out = np.conj(mu) if conj_back else mu
+        keep = np.abs(lam_out) < 1
+        Y = Vb[:, keep] / np.linalg.norm(Vb[:, keep], axis=0)
+        left_res = max(np.linalg.norm(y.conj() @ A - l * (y.conj() @ B)) for y, l in zip(Y.T, lam_out[keep]))
+        return lam_out[keep], left_res
+
+    good, res = run(feast.filter_left, True)
+    assert len(good) == len(ref) and match_eigs(good, ref) < 1e-10 and res < 1e-9
+    _, res_right = run(feast.filter_right, True)
+    assert res_right > 1e-3
+    bad, _ = run(feast.filter_left, False)
+    assert len(bad) != len(ref) or match_eigs(bad, ref) > 1e-6
