@@ -377,6 +377,83 @@ def bench_conj(args, fm, torch, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_domains(args, fm, torch, dev):
+    """Multi-domain run: one n = 2048 pencil (eigenvector basis of condition <= 1e2), m eigenvalues
+    (--domain-eigs) in the square [-1, 1]^2 spread over an 8 x 8 grid of cells; count estimates for
+    the 64 cells (one probe batch, 16 probes), a partition into tiles of about --domain-target
+    eigenvalues, one batch over the tiles.  Timed beside one domain covering the square."""
+    import pencils
+    n, m_in, grid, region, target = 2048, args.domain_eigs, (8, 8), (-1.0, 1.0, -1.0, 1.0), args.domain_target
+    rng = np.random.default_rng([pencils.base_seed(6), 0])
+    lam = pencils.grid_spectrum(rng, n, m_in, region, grid)
+    A, _ = pencils.prescribed_pencil(rng, n, lam, cond_max=1e2)
+    ref = lam[(lam.real > -1) & (lam.real < 1) & (lam.imag > -1) & (lam.imag < 1)]
+    Ad = fm.to_device(A, dev)
+    probes = fm.to_device(pencils.rademacher_complex(np.random.default_rng([pencils.base_seed(6), 1]), (n, 16)), dev)
+    U1 = fm.to_device(pencils.start_block(6, n, fm.m0_from_estimate(m_in)), dev)
+    torch.cuda.synchronize()
+
+    def tiled():
+        t = time.perf_counter()
+        rects, est, res, rcs = fm.multi_domain(Ad, None, region, probes, grid=grid, target=target, q=16,
+                                               precision=args.mode, max_iter=60)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, rects, est, res, rcs
+
+    def single():
+        t = time.perf_counter()
+        with fm.Feast(Ad, None, q=32, m0=U1.shape[1], rule="gauss-legendre", precision=args.mode, max_iter=60,
+                      pieces=fm.rectangle(*region)) as F:
+            r = F.iterate(U1)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    for _ in range(args.warmup):
+        tiled()
+    runs = [tiled() for _ in range(args.steps)]
+    wall = float(np.median([r[0] for r in runs]))
+    _, rects, est, res, rcs = runs[0]
+    found = np.concatenate([r.lam for r in res])
+    counts = [len(r.lam) for r in res]
+    iters = sum(r.iterations for r in res)
+    err = match_err(found, ref) if len(found) == len(ref) else float("inf")
+    log(f"tiled: {1e3 * wall:.1f} ms, {len(rects)} tiles, counts {counts}, {iters} tile iterations, "
+        f"found {len(found)} of {len(ref)}, err {err:.1e}")
+    s_wall, s_res = single()
+    s_err = match_err(s_res.lam, ref) if len(s_res.lam) == len(ref) else float("inf")
+    log(f"one domain (m0={U1.shape[1]}, q=32): {1e3 * s_wall:.1f} ms, {s_res.iterations} iterations, "
+        f"found {len(s_res.lam)}, err {s_err:.1e}")
+    line = {
+        "metric": METRIC,
+        "value": iters / wall,
+        "unit": "FEAST iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.mode == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"one pencil n={n}, B=I, {m_in} eigenvalues in the square [-1,1]^2 (8 x 8 cells, "
+                               f"away from cell edges), the rest in 2 < |z| < 5; probe batch over the 64 cells "
+                               f"(8 Gauss-Legendre nodes, 16 probes, cond(V) <= 1e2), tiles of about {target} eigenvalues, "
+                               f"q=16 per tile, R-FEAST, tol 1e-10",
+                   "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
+                   "step": "count estimates + partition + one batch over the tiles (setup and iterations)"},
+        "time_to_1e10_s": wall,
+        "tiles": len(rects),
+        "tile_counts": counts,
+        "tile_estimates": [float(v) for v in est],
+        "balance_max_over_mean": float(max(counts) / np.mean(counts)),
+        "eigenvalues_found": int(len(found)), "eigenvalues_inside": int(len(ref)),
+        "eig_err_vs_oracle": err,
+        "one_domain": {"ms": 1e3 * s_wall, "iterations": int(s_res.iterations), "m0": int(U1.shape[1]),
+                       "found": int(len(s_res.lam)), "eig_err_vs_oracle": s_err},
+        "speedup_vs_one_domain": s_wall / wall,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_m0(args, fm, torch, dev):
     """Learned subspace size: probe features (8 Rademacher probes, 8-node FP16 filter) of training
     pencils, the perceptron trained on their counts, then held-out pencils solved with m0 from
@@ -498,14 +575,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="fp32", choices=["fp32", "fp64", "fp16"])
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2", "c4", "real4096"],
-                    help="real4096: a real pencil whose conjugate nodes share factorisations")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2", "c4", "real4096", "domains"],
+                    help="real4096: a real pencil whose conjugate nodes share factorisations; domains: "
+                         "load-balanced tiles of a region in one batch")
     ap.add_argument("--count-train", type=int, default=4096, help="training pencils of the learned-m0 workload")
     ap.add_argument("--count-eval", type=int, default=256, help="held-out pencils of the learned-m0 workload")
     ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--probe-precision", default="fp32", choices=["fp32", "fp16"],
                     help="factorisations of the 8-node probe filter of the learned-m0 workload")
     ap.add_argument("--count", type=int, default=64, help="pencils of the batched workload (c2)")
+    ap.add_argument("--domain-eigs", type=int, default=512, help="eigenvalues in the region (domains workload)")
+    ap.add_argument("--domain-target", type=int, default=48, help="eigenvalues per tile (domains workload)")
     ap.add_argument("--variant", default=None, choices=["R", "Bi"],
                     help="R-FEAST (default for the n=4096 workload) or Bi-FEAST (default for n=8192)")
     ap.add_argument("--tune", action="store_true", help="measure the panel-kernel crossover before timing")
@@ -545,6 +625,9 @@ def main():
         return
     if args.workload == "real4096":
         bench_conj(args, fm, torch, dev)
+        return
+    if args.workload == "domains":
+        bench_domains(args, fm, torch, dev)
         return
     variant = args.variant or ("Bi" if args.workload == "c3" else "R")
     P, U0h, ref, g = load_workload(args.workload)

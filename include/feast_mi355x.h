@@ -396,6 +396,43 @@ int feast_batch_iterate(feast_batch* batch, const void* const* U0, const int* ld
 int feast_batch_factor_ms(feast_batch* batch, double* ms);
 void feast_batch_destroy(feast_batch* batch);
 
+/* ---- multi-domain tiling ------------------------------------------------------
+ * Section 6 names many search domains of one problem as the outermost level of
+ * parallelism, and load balance (subdomains with about equal eigenvalue
+ * counts) as the hard part.  The building blocks here: count estimates for
+ * the cells of a grid over a region (one batch whose members are the same
+ * pencil with the cells as glued rectangular contours), a partition of the
+ * grid into rectangles of whole cells with about equal counts, and one batch
+ * over those rectangles.  Rectangles that share edges hold every eigenvalue of
+ * the region in exactly one tile (inside = nonzero winding number).
+ *
+ * feast_batch_trace_estimates: est[b] (host, count doubles) =
+ *   (1/s) sum_j Re(v_j^H rho_b(M) v_j),
+ * the stochastic trace estimate of tr rho_b(M), about the number of
+ * eigenvalues inside member b's contour (rho_b is near 1 inside and near 0
+ * outside, E[v v^H] = I).  V: device n x s block of probe vectors (ldv),
+ * shared by all members, which must all have order n; s <= every member's m0.
+ * Synchronous.  Returns 0, -i, or the first failing member's code.
+ *
+ * feast_partition_grid: rectangles of whole cells of a gx x gy grid with
+ * estimated counts counts[ix * gy + iy] (ix along Re, iy along Im; negative
+ * estimates count as 0), each holding at most about `target`:
+ *   1. total = sum of the counts; T = max(1, ceil(total / target)) tiles are
+ *      aimed at, in k = min(gx, ceil(sqrt(T))) vertical slabs;
+ *   2. slab boundary i (i = 1..k-1) is the column edge b in
+ *      [b_(i-1) + 1, gx - (k - i)] whose prefix count (columns < b) is closest
+ *      to i total / k (the smaller b on ties), b_0 = 0, b_k = gx;
+ *   3. each slab is cut bottom to top: a tile grows row by row and closes
+ *      before a row that would take a nonempty tile above `target`.
+ * Tiles are listed slab by slab, bottom to top, as 4 ints ix0, ix1, iy0, iy1
+ * (half-open cell ranges) in tiles (4 max_tiles ints) with their summed
+ * counts in tile_counts (may be NULL).  *ntiles receives the number of tiles
+ * even when it exceeds max_tiles (then nothing is written and the return is
+ * FEAST_EUNSUPPORTED).  Host only.  Returns 0, -i. */
+int feast_batch_trace_estimates(feast_batch* batch, const void* V, int ldv, int nprobe, double* est);
+int feast_partition_grid(int gx, int gy, const double* counts, double target, int max_tiles, int* ntiles,
+                         int* tiles, double* tile_counts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,7 @@ EXPORTED = [
     "feast_filter", "feast_node_solve", "feast_iterate", "feast_reduced_eig", "feast_destroy",
     "feast_strerror", "feast_timing_read", "feast_timing_reset",
     "feast_batch_workspace_size", "feast_batch_setup", "feast_batch_member", "feast_batch_iterate",
-    "feast_batch_factor_ms", "feast_batch_destroy",
+    "feast_batch_factor_ms", "feast_batch_destroy", "feast_batch_trace_estimates", "feast_partition_grid",
     "feast_probe_features", "feast_mlp_param_count", "feast_mlp_workspace_size", "feast_mlp_setup",
     "feast_mlp_fit_standardization", "feast_mlp_forward", "feast_mlp_gradients", "feast_mlp_train_step",
     "feast_mlp_get_params", "feast_m0_from_estimate", "feast_mlp_destroy",
@@ -143,6 +143,10 @@ def lib():
         L.feast_batch_iterate.restype = i
         L.feast_batch_factor_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.feast_batch_factor_ms.restype = i
+        L.feast_batch_trace_estimates.argtypes = [vp, vp, i, i, vp]
+        L.feast_batch_trace_estimates.restype = i
+        L.feast_partition_grid.argtypes = [i, i, vp, ctypes.c_double, i, ctypes.POINTER(ctypes.c_int), vp, vp]
+        L.feast_partition_grid.restype = i
         L.feast_batch_destroy.argtypes = [vp]
         L.feast_batch_destroy.restype = None
         L.feast_probe_features.argtypes = [vp, vp, i, i, vp]
@@ -512,6 +516,13 @@ class FeastBatch:
         _check(lib().feast_batch_factor_ms(self._b, ctypes.byref(out)), "feast_batch_factor_ms")
         return out.value
 
+    def trace_estimates(self, V) -> np.ndarray:
+        """Per member, the stochastic estimate of its eigenvalue count from the probe block V."""
+        out = np.zeros(self.count, dtype=np.float64)
+        _check(lib().feast_batch_trace_estimates(self._b, V.data_ptr(), _ld(V), V.shape[1], out.ctypes.data),
+               "feast_batch_trace_estimates")
+        return out
+
     def member_probe_features(self, i, V) -> np.ndarray:
         c = lib().feast_batch_member(self._b, i)
         if not c:
@@ -565,6 +576,62 @@ class FeastBatch:
 
 def m0_from_estimate(m_hat: float) -> int:
     return int(lib().feast_m0_from_estimate(float(m_hat)))
+
+
+def partition_grid(counts, target):
+    """Tiles (ix0, ix1, iy0, iy1) of whole cells of the grid counts[ix, iy] with about `target`
+    eigenvalues each, and their summed counts (feast_partition_grid)."""
+    counts = np.ascontiguousarray(counts, dtype=np.float64)
+    gx, gy = counts.shape
+    nt = ctypes.c_int(0)
+    code = lib().feast_partition_grid(gx, gy, counts.ctypes.data, float(target), 0, ctypes.byref(nt), None, None)
+    _check(code, "feast_partition_grid", ok=(FEAST_OK, FEAST_EUNSUPPORTED))
+    tiles = np.zeros((max(nt.value, 1), 4), dtype=np.int32)
+    sums = np.zeros(max(nt.value, 1), dtype=np.float64)
+    _check(lib().feast_partition_grid(gx, gy, counts.ctypes.data, float(target), nt.value, ctypes.byref(nt),
+                                      tiles.ctypes.data, sums.ctypes.data), "feast_partition_grid")
+    return tiles[: nt.value], sums[: nt.value]
+
+
+def rectangle(x0, x1, y0, y1):
+    """Pieces of the axis-aligned rectangle [x0, x1] x [y0, y1], counterclockwise."""
+    return polygon([complex(x0, y0), complex(x1, y0), complex(x1, y1), complex(x0, y1)])
+
+
+def multi_domain(A, B, region, probes, grid=(8, 8), target=24, q=16, rule="gauss-legendre", probe_q=8,
+                 precision="fp32", variant="R", seed=0, **kw):
+    """Eigenvalues of (A, B) inside the rectangle region = (x0, x1, y0, y1), found by load-balanced
+    tiles: (1) one probe batch over the grid's cells (glued rectangles, probe_q nodes, FP32, no
+    refinement) gives per-cell count estimates from the probe block `probes` (device n x s);
+    (2) feast_partition_grid merges cells into tiles of about `target` eigenvalues; (3) one batch
+    iterates every tile (q nodes each) with m0 from its estimate and a seeded complex Gaussian
+    start block.  Returns (tiles as region rectangles, per-tile estimates, per-tile IterateResult,
+    member codes)."""
+    torch = _torch()
+    x0, x1, y0, y1 = (float(v) for v in region)
+    gx, gy = grid
+    n = int(A.shape[0])
+    xs = np.linspace(x0, x1, gx + 1)
+    ys = np.linspace(y0, y1, gy + 1)
+    cells = [rectangle(xs[i], xs[i + 1], ys[j], ys[j + 1]) for i in range(gx) for j in range(gy)]
+    s = probes.shape[1]
+    probe = FeastBatch([(A, B)] * len(cells), cells, m0=s, q=probe_q, rule="gauss-legendre",
+                       precision="fp32", ir_max=0)
+    est = probe.trace_estimates(probes).reshape(gx, gy)
+    probe.close()
+    tiles, sums = partition_grid(est, target)
+    rects = [(xs[t[0]], xs[t[1]], ys[t[2]], ys[t[3]]) for t in tiles]
+    m0s = [min(n, m0_from_estimate(v)) for v in sums]
+    batch = FeastBatch([(A, B)] * len(rects), [rectangle(*r) for r in rects], m0=m0s, q=q, rule=rule,
+                       precision=precision, variant=variant, **kw)
+    g = np.random.default_rng(seed)
+    U0s = []
+    for m0 in m0s:
+        U = (g.standard_normal((n, m0)) + 1j * g.standard_normal((n, m0))) / np.sqrt(2.0)
+        U0s.append(to_device(np.asfortranarray(U), A.device))
+    res, rcs = batch.iterate(U0s)
+    batch.close()
+    return rects, sums, res, rcs
 
 
 class MLP:

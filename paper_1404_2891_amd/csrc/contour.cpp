@@ -294,3 +294,57 @@ extern "C" int feast_contour_inside(const feast_contour* C, int count, const dou
     for (int i = 0; i < count; ++i) in[i] = contour_inside(*C, cd(lam[2 * i], lam[2 * i + 1])) ? 1 : 0;
     return 0;
 }
+
+extern "C" int feast_partition_grid(int gx, int gy, const double* counts, double target, int max_tiles, int* ntiles,
+                                    int* tiles, double* tile_counts) {
+    if (gx < 1) return -1;
+    if (gy < 1) return -2;
+    if (!counts) return -3;
+    if (!(target > 0)) return -4;
+    if (max_tiles < 0) return -5;
+    if (!ntiles) return -6;
+    auto cnt = [&](int ix, int iy) { return std::max(0.0, counts[(size_t)ix * gy + iy]); };
+    double total = 0.0;
+    std::vector<double> col(gx, 0.0), prefix(gx + 1, 0.0);
+    for (int ix = 0; ix < gx; ++ix) {
+        for (int iy = 0; iy < gy; ++iy) col[ix] += cnt(ix, iy);
+        prefix[ix + 1] = prefix[ix] + col[ix];
+    }
+    total = prefix[gx];
+    const int T = std::max(1, (int)std::ceil(total / target));
+    const int k = std::min(gx, std::max(1, (int)std::ceil(std::sqrt((double)T))));
+    std::vector<int> b(k + 1, 0);
+    b[k] = gx;
+    for (int i = 1; i < k; ++i) {
+        const double goal = total * i / k;
+        int best = b[i - 1] + 1;
+        for (int e = b[i - 1] + 1; e <= gx - (k - i); ++e)
+            if (std::fabs(prefix[e] - goal) < std::fabs(prefix[best] - goal)) best = e;
+        b[i] = best;
+    }
+    std::vector<int> out;
+    std::vector<double> sums;
+    for (int i = 0; i < k; ++i) {
+        int iy0 = 0;
+        double acc = 0.0;
+        for (int iy = 0; iy < gy; ++iy) {
+            double row = 0.0;
+            for (int ix = b[i]; ix < b[i + 1]; ++ix) row += cnt(ix, iy);
+            if (iy > iy0 && acc > 0 && acc + row > target) {
+                out.insert(out.end(), {b[i], b[i + 1], iy0, iy});
+                sums.push_back(acc);
+                iy0 = iy;
+                acc = 0.0;
+            }
+            acc += row;
+        }
+        out.insert(out.end(), {b[i], b[i + 1], iy0, gy});
+        sums.push_back(acc);
+    }
+    *ntiles = (int)sums.size();
+    if (*ntiles > max_tiles) return FEAST_EUNSUPPORTED;
+    if (!tiles) return -7;
+    std::copy(out.begin(), out.end(), tiles);
+    if (tile_counts) std::copy(sums.begin(), sums.end(), tile_counts);
+    return 0;
+}

@@ -1710,6 +1710,25 @@ feast_ctx* feast_batch_member(feast_batch* bt, int i) {
     return bt->ctx[i];
 }
 
+int feast_batch_trace_estimates(feast_batch* bt, const void* V, int ldv, int nprobe, double* est) {
+    if (!bt) return -1;
+    if (!V) return -2;
+    if (!est) return -5;
+    if (nprobe < 1) return -4;
+    const int n = bt->ctx[0]->n;
+    if (ldv < n) return -3;
+    for (feast_ctx* c : bt->ctx)
+        if (c->n != n || nprobe > c->m0) return -4;
+    std::vector<float> f(2 * nprobe + 3);
+    for (int b = 0; b < bt->count; ++b) {
+        FM_TRY(feast_probe_features(bt->ctx[b], V, ldv, nprobe, f.data()));
+        double s = 0.0;
+        for (int j = 0; j < nprobe; ++j) s += f[2 * j];
+        est[b] = s / nprobe;
+    }
+    return 0;
+}
+
 int feast_batch_factor_ms(feast_batch* bt, double* ms) {
     if (!bt) return -1;
     if (!ms) return -2;

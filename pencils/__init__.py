@@ -257,6 +257,23 @@ def real_workload(n: int = 4096, seed_cfg: int = 5, q: int = 24, m0: int = 64, m
     return Pencil(A, B, lam, 0j, 1.0, 1.0, q, m0, 2 * m_pairs + m_real, name=f"real_n{n}")
 
 
+def grid_spectrum(rng, n, m_in, region=(-1.0, 1.0, -1.0, 1.0), grid=(6, 6), margin=0.3, r_out=(2.0, 5.0)):
+    """Eigenvalues for multi-domain runs: m_in inside the rectangle region = (x0, x1, y0, y1), each in
+    a random cell of the gx x gy grid over it and at least margin (fraction of the cell's width and
+    height) from that cell's edges; n - m_in area-uniform in r_out[0] < |z| < r_out[1]."""
+    x0, x1, y0, y1 = region
+    gx, gy = grid
+    w, h = (x1 - x0) / gx, (y1 - y0) / gy
+    ix = rng.integers(0, gx, m_in)
+    iy = rng.integers(0, gy, m_in)
+    fx = rng.uniform(margin, 1 - margin, m_in)
+    fy = rng.uniform(margin, 1 - margin, m_in)
+    inside = (x0 + (ix + fx) * w) + 1j * (y0 + (iy + fy) * h)
+    r = np.sqrt(rng.uniform(r_out[0] ** 2, r_out[1] ** 2, n - m_in))
+    outside = r * np.exp(2j * np.pi * rng.random(n - m_in))
+    return np.concatenate([inside, outside])
+
+
 def c2_sizes(count: int = 64, seed_cfg: int = 2, n_lo: int = 256, n_hi: int = 2048):
     """(n_i, m_i) of the batched workload: n_i ~ U{n_lo..n_hi}, m_i ~ U{8..32}."""
     rng = np.random.default_rng([base_seed(seed_cfg), 10**6 + 1])
