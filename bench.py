@@ -597,8 +597,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one MI355X: the path is a single-GPU build (see DESIGN.md for how it "
-              "would shard over contour nodes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one MI355X: the library is a single-GPU build (several GPUs would each "
+              "own a share of the contour nodes and sum their filter blocks); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
