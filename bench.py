@@ -586,8 +586,9 @@ def main():
     ap.add_argument("--count", type=int, default=64, help="pencils of the batched workload (c2)")
     ap.add_argument("--domain-eigs", type=int, default=512, help="eigenvalues in the region (domains workload)")
     ap.add_argument("--domain-target", type=int, default=48, help="eigenvalues per tile (domains workload)")
-    ap.add_argument("--variant", default=None, choices=["R", "Bi"],
-                    help="R-FEAST (default for the n=4096 workload) or Bi-FEAST (default for n=8192)")
+    ap.add_argument("--variant", default=None, choices=["R", "Bi", "L"],
+                    help="R-FEAST (default for the n=4096 workload), Bi-FEAST (default for n=8192) or the "
+                         "left-projector variant")
     ap.add_argument("--tune", action="store_true", help="measure the panel-kernel crossover before timing")
     ap.add_argument("--counters", action="store_true",
                     help="run only a calibration kernel (elementwise multiply, 256 MiB in and out) and one "
