@@ -129,3 +129,17 @@ def test_asymmetric_contour_is_refused():
     with pytest.raises(fm().FeastError) as e:
         fm().Feast(upload(A), upload(B), 0.1 + 0.2j, 1.0, 1.0, 16, 8, conj_nodes="real")
     assert e.value.code == fm().binding.FEAST_EUNSUPPORTED
+
+
+def test_iterate_real_pencil_shared_nodes_fp16():
+    """FP16 trailing updates with shared conjugate nodes (refinement, and FP32 factors substituted
+    when it stalls, act on the factored nodes only)."""
+    n = 300
+    A, B, lam = real_pencil(n, seed=21)
+    ref = brute.eigenvalues_inside(lam, 0j, 1.0)
+    U0 = pencils.complex_gaussian(np.random.default_rng(4), (n, 16))
+    F = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, 16, 16, precision="fp16", conj_nodes="real")
+    r = F.iterate(upload(U0))
+    assert r.converged and len(r.lam) == 10, (len(r.lam), r.history)
+    assert match_eigs(r.lam, ref) < 1e-10
+    F.close()

@@ -82,3 +82,19 @@ def test_left_variant_in_a_batch():
     for r, p in zip(res, P):
         check_left_pairs(r, p.A, p.B, brute.eigenvalues_inside(p.lam, 0j, 1.0))
     batch.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_left_variant_on_a_contour_not_symmetric_about_the_real_axis(prec):
+    """The triangle 0, 2, 1 + 1.5i lies above the real axis, so the candidates' inside test must use
+    lambda, not the adjoint Ritz value conj(lambda): with the wrong one no candidate would be found."""
+    from tests.glued_shapes import SHAPES, glued_spectrum
+    pieces, _, member = SHAPES["triangle"]
+    n = 300
+    lam0 = glued_spectrum("triangle", n, 10, seed=8)
+    A, B, lam = random_pencil(n, seed=3, with_B=True, spectrum=lam0)
+    ref = lam0[member(lam0)]
+    V0 = pencils.complex_gaussian(np.random.default_rng(5), (n, 18))
+    F = fm().Feast(upload(A), upload(B), q=24, m0=18, precision=prec, variant="L", max_iter=40, pieces=pieces)
+    check_left_pairs(F.iterate(upload(V0)), A, B, ref)
+    F.close()
