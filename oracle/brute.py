@@ -29,15 +29,6 @@ def count_inside(lam, c, R, a=1.0):
     return int(np.count_nonzero(inside(lam, c, R, a)))
 
 
-def radius_for_count(lam, c, m_target):
-    """Circle radius in the middle of the gap between the m-th and (m+1)-th nearest eigenvalue to c.
-
-    Returns (R, lower, upper) where lower/upper are the two distances."""
-    d = np.sort(np.abs(np.asarray(lam) - c))
-    lo, hi = float(d[m_target - 1]), float(d[m_target])
-    return 0.5 * (lo + hi), lo, hi
-
-
 def eigenpair_null_vector(A, B, lam):
     """Right eigenvector for an eigenvalue lam: the right singular vector of A - lam B with the
     smallest singular value (tiny n only)."""

@@ -322,3 +322,67 @@ def test_left_projector_variant_planted_mistakes():
     assert res_right > 1e-3
     bad, _ = run(feast.filter_left, False)
     assert len(bad) != len(ref) or match_eigs(bad, ref) > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# hand-computed residuals (the stopping rule's inputs)
+# ---------------------------------------------------------------------------
+#
+# A = [[1, 2i], [0, 3]], B = [[2, 0], [1, 1]] (B is not a multiple of I, so ||x||, ||B x|| and
+# ||B^H y|| all differ and a wrong denominator changes the value).
+#
+# Right pairs (residual r = A x - lam B x):
+#   x = (1, 1),  lam = 1 : A x = (1 + 2i, 3), B x = (2, 2), r = (-1 + 2i, 1), ||r||^2 = 6,
+#                          ||x||^2 = 2, ||B x||^2 = 8  -> paper sqrt(3), relative sqrt(3)/2
+#   x = (1, 0),  lam = 2i: A x = (1, 0), B x = (2, 1), r = (1 - 4i, -2i), ||r||^2 = 21,
+#                          ||x|| = 1, ||B x||^2 = 5    -> paper sqrt(21), relative sqrt(21)/(2 sqrt 5)
+# Left pairs (residual R = A^H y - conj(lam) B^H y, A^H = [[1, 0], [-2i, 3]], B^H = [[2, 1], [0, 1]]):
+#   y = (1, 1),  lam = 1 : A^H y = (1, 3 - 2i), B^H y = (3, 1), R = (-2, 2 - 2i), ||R||^2 = 12,
+#                          ||B^H y||^2 = 10             -> relative sqrt(12/10)
+#   y = (0, 1),  lam = 2i: A^H y = (0, 3), B^H y = (1, 1), R = (2i, 3 + 2i), ||R||^2 = 17,
+#                          ||B^H y||^2 = 2              -> relative sqrt(17)/(2 sqrt 2)
+
+A22 = np.array([[1, 2j], [0, 3]], dtype=np.complex128)
+B22 = np.array([[2, 0], [1, 1]], dtype=np.complex128)
+LAM22 = np.array([1.0, 2j])
+
+
+def test_residuals_hand_computed():
+    X = np.array([[1, 1], [1, 0]], dtype=np.complex128)
+    paper, rel = feast.residuals(A22, B22, LAM22, X)
+    np.testing.assert_allclose(paper, [np.sqrt(3.0), np.sqrt(21.0)], rtol=1e-15)
+    np.testing.assert_allclose(rel, [np.sqrt(3.0) / 2, np.sqrt(21.0) / (2 * np.sqrt(5.0))], rtol=1e-15)
+    # B = None means B = I: r = A x - lam x, relative denominator |lam| ||x||
+    #   x = (1, 1), lam = 1 : r = (2i, 2), ||r||^2 = 8          -> paper 2, relative 2
+    #   x = (1, 0), lam = 2i: r = (1 - 2i, 0), ||r||^2 = 5       -> paper sqrt 5, relative sqrt(5)/2
+    paper, rel = feast.residuals(A22, None, LAM22, X)
+    np.testing.assert_allclose(paper, [2.0, np.sqrt(5.0)], rtol=1e-15)
+    np.testing.assert_allclose(rel, [2.0, np.sqrt(5.0) / 2], rtol=1e-15)
+
+
+def test_left_residuals_hand_computed():
+    Y = np.array([[1, 0], [1, 1]], dtype=np.complex128)
+    rel = feast.left_residuals(A22, B22, LAM22, Y)
+    np.testing.assert_allclose(rel, [np.sqrt(12.0 / 10.0), np.sqrt(17.0) / (2 * np.sqrt(2.0))], rtol=1e-15)
+    # B = None: R = A^H y - conj(lam) y
+    #   y = (1, 1), lam = 1 : R = (0, 2 - 2i), ||R||^2 = 8, ||y||^2 = 2       -> relative 2
+    #   y = (0, 1), lam = 2i: R = (0, 3 + 2i), ||R||^2 = 13, ||y|| = 1        -> relative sqrt(13)/2
+    rel = feast.left_residuals(A22, None, LAM22, Y)
+    np.testing.assert_allclose(rel, [2.0, np.sqrt(13.0) / 2], rtol=1e-15)
+
+
+def test_residuals_vanish_on_exact_pairs():
+    """On exact eigenpairs of the 2 x 2 pencil both residuals are at rounding level.  The
+    eigenvalues are the roots of the characteristic polynomial, expanded by hand:
+    det(A - l B) = (1 - 2l)(3 - l) - 2i(-l) = 2 l^2 - (7 - 2i) l + 3; the vectors are null vectors
+    of A - l B and of its conjugate transpose."""
+    roots = np.roots([2.0, -(7.0 - 2j), 3.0])
+    for lam in roots:
+        M = A22 - lam * B22
+        _, _, Vh = np.linalg.svd(M)
+        x = Vh[-1].conj()[:, None]
+        _, _, Vh2 = np.linalg.svd(M.conj().T)
+        y = Vh2[-1].conj()[:, None]
+        paper, rel = feast.residuals(A22, B22, np.array([lam]), x)
+        assert rel[0] < 1e-14 and paper[0] < 1e-14
+        assert feast.left_residuals(A22, B22, np.array([lam]), y)[0] < 1e-14
