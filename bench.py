@@ -1,20 +1,20 @@
 #!/usr/bin/env python
 """Benchmark: FEAST iterations/s and time-to-1e-10 residual on one MI355X.
 
-Workload (default): the complex-symmetric generalized pencil of size n = 4096
-(A = (G + G^T)/(2 sqrt n) + i diag(0.05 (j/n)^2), B = I + 0.05 (H + H^H)/sqrt n,
-seeded), circle centered at 0.5+0.2i with the radius R* stored in
-tests/golden/spectrum_c1.json, q = 24 trapezoid nodes, m0 = 64, R-FEAST.
+Workload (default, --workload c2): a batch of 64 independent pencils, n ~ U{256..2048} (seeded),
+each with a prescribed spectrum (8-32 eigenvalues inside |z| < 0.8, the rest in 1.5 < |z| < 5),
+B = I + 0.1 random Hermitian, the unit circle with q = 16 trapezoid nodes, m0 in {16, 32},
+R-FEAST.  One step = the whole batch from resident inputs: one graph launch assembles and factors
+every node of every pencil, then all pencils iterate in lockstep until every candidate has
+relative residual <= 1e-10 (count repeated).  ms_per_step is the batch's time-to-1e-10; value is
+whole-job FEAST iterations per second.  The headline mode is FP32 LU + FP64 correction (the
+shifted-residual form of the filter); plain FP64 is timed beside it, and both also one pencil at a
+time.  The single-pencil n = 4096 (R-FEAST) and n = 8192 (Bi-FEAST) workloads are reported as extra
+keys.  The roofline object is the trailing-update kernel, timed per launch with HIP events in a run
+of the same batch whose factorisation is launched directly (the same kernels) instead of as a
+graph.
 
-One step = one complete solve from resident inputs: node assembly, all q node
-factorisations, then FEAST iterations until every candidate has relative
-residual <= 1e-10 (count repeated).  ms_per_step is therefore the
-time-to-1e-10; value is whole-job FEAST iterations per second.  The headline
-mode is FP32 LU + FP64 refinement; the same solve in plain FP64 is timed beside
-it.  Per-phase device times come from HIP events the library records on its
-stream around each launch; the roofline object uses the dominant phase.
-
-    python bench.py [--steps K] [--warmup W] [--mode fp32|fp64] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--mode fp32|fp64|fp16] [--workload c2|c1|c3|...] [--gpus 1]
 """
 from __future__ import annotations
 
@@ -217,9 +217,52 @@ def tune_panels(fm, q, modes, dev):
     return out
 
 
+def batch_cpu_baseline(P, U0h, stride=4):
+    """The oracle (NumPy/SciPy FP64 R-FEAST: 16 LUs per pencil, then iterations to 1e-10) run in
+    full on a stratified sample of the batch (every stride-th pencil in order of n), its time scaled
+    by stride to the whole batch; iterations/s = the sample's iterations over its time."""
+    from oracle import feast as ofeast
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("internal_api") == "openblas"] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    order = sorted(range(len(P)), key=lambda j: P[j].n)
+    sample = order[stride // 2::stride]
+    t0 = time.perf_counter()
+    iters, ok = 0, 0
+    for j in sample:
+        p = P[j]
+        A = p.A.cpu().numpy() if hasattr(p.A, "cpu") else p.A
+        B = p.B.cpu().numpy() if hasattr(p.B, "cpu") else p.B
+        r = ofeast.rfeast(A, B, p.center, p.radius, 1.0, p.q, U0h[j])
+        iters += r.iters
+        ok += int(r.converged and r.m == p.m)
+    t = time.perf_counter() - t0
+    return dict(value=iters / t, unit="FEAST iterations/s", cores=int(cores), kind="oracle",
+                time_to_1e10_s=t * len(P) / len(sample),
+                sample=f"{len(sample)} of {len(P)} pencils (every {stride}th in order of n, n = "
+                       f"{min(P[j].n for j in sample)}..{max(P[j].n for j in sample)}), full oracle R-FEAST runs "
+                       f"(16 LUs + iterations to 1e-10); time scaled by {stride} to the batch",
+                sample_s=t, sample_iterations=iters, sample_converged=ok)
+
+
+def update_roofline(ph, prec):
+    """Per-launch figures of the trailing-update kernel from the library's HIP-event phase timing:
+    flops per launch (8 nr nc K over every member and node the launch covers) / average duration."""
+    u = ph["lu_update"]
+    launches = max(1, u["launches"])
+    avg_ms = u["ms"] / launches
+    achieved = u["flops"] / launches / (avg_ms * 1e-3) / 1e12
+    return dict(bound="mfma", achieved=achieved, peak=PEAK[prec], unit="TFLOP/s", frac=achieved / PEAK[prec],
+                traffic=None, kernel="cgemm_kernel (trailing update, kind 1)", kernel_phase="lu_update",
+                avg_launch_ms=avg_ms, launches=u["launches"], flops_per_launch=u["flops"] / launches)
+
+
 def bench_batch(args, fm, torch, dev):
-    """Batched pencils: one graph launch factors every node of every pencil, then all pencils iterate
-    in lockstep; timed beside the same pencils solved one at a time."""
+    """The batched workload (default): 64 pencils, one graph launch factors every node of every pencil,
+    then all pencils iterate in lockstep to 1e-10.  Mixed precision (FP32 LU + FP64 correction) is the
+    headline, plain FP64 beside it, both also one pencil at a time."""
     from oracle import brute
     t0 = time.perf_counter()
     P = load_batch(args.count, dev)
@@ -227,22 +270,24 @@ def bench_batch(args, fm, torch, dev):
     log(f"batch of {len(P)} pencils generated in {time.perf_counter() - t0:.1f} s; "
         f"n in [{min(p.n for p in P)}, {max(p.n for p in P)}], sum n^3 = {sum(p.n ** 3 for p in P):.3e}")
     mats = [(p.A, p.B) for p in P]
-    U0s = [fm.to_device(pencils_start(p, j), dev) for j, p in enumerate(P)]
+    U0h = [pencils_start(p, j) for j, p in enumerate(P)]
+    U0s = [fm.to_device(u, dev) for u in U0h]
     refs = [brute.eigenvalues_inside(p.lam, 0j, 1.0) for p in P]
     m0s = [p.m0 for p in P]
     lu_flops = sum(16 * (8.0 / 3.0) * p.n ** 3 for p in P)
     torch.cuda.synchronize()
 
-    def batched(mode):
+    def batched(mode, timing=False):
         t = time.perf_counter()
-        b = fm.FeastBatch(mats, (0j, 1.0, 1.0), m0=m0s, q=16, precision=mode, pivoting=args.pivoting)
+        b = fm.FeastBatch(mats, (0j, 1.0, 1.0), m0=m0s, q=16, precision=mode, pivoting=args.pivoting, timing=timing)
         t_setup = time.perf_counter() - t
         res, rcs = b.iterate(U0s)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         fms = b.factor_ms()
+        ph = b.timing() if timing else None
         b.close()
-        return wall, t_setup, fms, res
+        return wall, t_setup, fms, res, ph
 
     def one_at_a_time(mode):
         t = time.perf_counter()
@@ -262,26 +307,48 @@ def bench_batch(args, fm, torch, dev):
     for mode in modes:
         for _ in range(args.warmup):
             batched(mode)
-        runs = [batched(mode) for _ in range(args.steps if mode == args.mode else max(1, min(args.steps, 2)))]
-        wall = float(np.median([r[0] for r in runs]))
-        res = runs[0][3]
+        steps = args.steps if mode == args.mode else max(1, min(args.steps, 2))
+        runs = [batched(mode) for _ in range(steps)]
+        k = int(np.argsort([r[0] for r in runs])[len(runs) // 2])   # the median run
+        wall, t_setup, fms, res, _ = runs[k]
         iters = sum(r.iterations for r in res)
         seq_wall, seq_res = one_at_a_time(mode)
         out[mode] = dict(ms_per_step=1e3 * wall, iters_per_s=iters / wall, total_iterations=iters,
-                         setup_ms=1e3 * float(np.median([r[1] for r in runs])),
-                         factor_graph_ms=float(np.median([r[2] for r in runs])),
-                         converged=all(r.converged for r in res), eig_err_vs_oracle=errs(res),
+                         setup_ms=1e3 * t_setup, factor_graph_ms=fms,
+                         iters_per_s_after_setup=iters / (wall - t_setup),
+                         iteration_ms=1e3 * (wall - t_setup),
+                         converged=all(r.converged for r in res),
+                         found_all=all(len(r.lam) == len(ref) for r, ref in zip(res, refs)),
+                         eig_err_vs_oracle=errs(res), max_resid=float(max(r.resid.max() for r in res)),
                          one_at_a_time_ms=1e3 * seq_wall, one_at_a_time_err=errs(seq_res),
-                         batched_speedup=seq_wall / wall)
-        out[mode]["factor_tflops"] = lu_flops / (out[mode]["factor_graph_ms"] * 1e-3) / 1e12
-        log(f"{mode}: batch {out[mode]['ms_per_step']:.1f} ms (graph {out[mode]['factor_graph_ms']:.1f} ms, "
-            f"{out[mode]['factor_tflops']:.1f} TF/s), one at a time {out[mode]['one_at_a_time_ms']:.1f} ms, "
-            f"{iters} iterations, err {out[mode]['eig_err_vs_oracle']:.1e}")
+                         batched_speedup=seq_wall / wall, steps=steps)
+        out[mode]["factor_tflops"] = lu_flops / (fms * 1e-3) / 1e12
+        log(f"{mode}: batch {out[mode]['ms_per_step']:.1f} ms (setup {out[mode]['setup_ms']:.1f} ms, graph "
+            f"{fms:.1f} ms = {out[mode]['factor_tflops']:.1f} TF/s; iterations {out[mode]['iteration_ms']:.1f} ms), "
+            f"one at a time {out[mode]['one_at_a_time_ms']:.1f} ms, {iters} iterations, "
+            f"err {out[mode]['eig_err_vs_oracle']:.1e}")
     head = out[args.mode]
     prec = args.mode
-    roofline = dict(bound="mfma", achieved=head["factor_tflops"], peak=PEAK[prec], unit="TFLOP/s",
-                    frac=head["factor_tflops"] / PEAK[prec], traffic=None, kernel_phase="factorisation graph",
-                    flops_per_launch=lu_flops)
+    # the dominant kernel: per-launch times from a run of the same batch with HIP events around every
+    # factorisation launch (the sequence launched directly instead of as a graph: same kernels)
+    _, _, t_fms, t_res, ph = batched(args.mode, timing=True)
+    phases = {k: dict(ms=v["ms"], launches=v["launches"],
+                      tflops=(v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None)
+              for k, v in ph.items()}
+    for k, v in phases.items():
+        log(f"   {k:16s} {v['ms']:9.2f} ms  {v['launches']:6d} launches  {v['tflops']} TF/s")
+    roofline = update_roofline(ph, "fp16" if prec == "fp16" else prec)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample of the batch ...")
+        cpu = batch_cpu_baseline(P, U0h)
+        log(f"oracle: {cpu['value']:.2f} it/s, batch estimate {cpu['time_to_1e10_s']:.1f} s ({cpu['sample']})")
+    extras = {}
+    if not args.no_extras:
+        for name in ("c1", "c3"):
+            extras[name] = single_pencil_summary(args, fm, torch, dev, name)
+    mode_names = {"fp32": "FP32 LU + FP64 shifted-residual correction", "fp64": "FP64",
+                  "fp16": "FP16-update LU + FP64 shifted-residual correction"}
     line = {
         "metric": METRIC,
         "value": head["iters_per_s"],
@@ -289,23 +356,62 @@ def bench_batch(args, fm, torch, dev):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if args.mode == "fp32" else "f64",
+        "dtype": {"fp32": "f32+f64", "fp16": "f16+f32+f64", "fp64": "f64"}[args.mode],
         "data": "synthetic",
-        "config": {"workload": f"{len(P)} pencils, n ~ U{{256..2048}}, prescribed spectra, unit circle, q=16, "
-                               f"m0 in {{16, 32}}, R-FEAST, tol 1e-10, one factorisation graph",
-                   "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
-                   "step": "batch setup (one graph: assembly + 16 LUs per pencil) + lockstep iterations to 1e-10",
+        "config": {"workload": f"{len(P)} pencils, n ~ U{{256..2048}}, prescribed spectra (8-32 eigenvalues in "
+                               f"|z| < 0.8), B = I + 0.1 random Hermitian, unit circle, q=16 trapezoid nodes, "
+                               f"m0 in {{16, 32}}, R-FEAST, tol 1e-10",
+                   "mode": mode_names[args.mode],
+                   "step": "batch setup (one graph launch: assembly + 16 LUs of every pencil) + lockstep "
+                           "iterations of all pencils to 1e-10",
                    "pivoting": args.pivoting},
         "time_to_1e10_s": head["ms_per_step"] / 1e3,
+        "iters_per_s_after_setup": head["iters_per_s_after_setup"],
         "eig_err_vs_oracle": head["eig_err_vs_oracle"],
         "batched_speedup_vs_one_at_a_time": head["batched_speedup"],
-        "panel_tuning": tuning,
         "speedup_vs_fp64": (out["fp64"]["ms_per_step"] / head["ms_per_step"]) if "fp64" in out else None,
+        "speedup_vs_fp64_after_setup": (head["iters_per_s_after_setup"] / out["fp64"]["iters_per_s_after_setup"])
+                                       if "fp64" in out else None,
         "modes": out,
+        "timed_run_phases": phases,
         "roofline": roofline,
-        "cpu_baseline": None,
+        "panel_tuning": tuning,
+        "cpu_baseline": cpu,
+        "extra_workloads": extras or None,
     }
     print(json.dumps(line), flush=True)
+
+
+def single_pencil_summary(args, fm, torch, dev, name):
+    """One solve per mode of a single-pencil workload (n = 4096 R-FEAST or n = 8192 Bi-FEAST), after
+    one warm-up, for the extra keys of the default bench line."""
+    P, U0h, ref, g = load_workload(name)
+    variant = "Bi" if name == "c3" else "R"
+    A, B, U0 = fm.to_device(P.A, dev), fm.to_device(P.B, dev), fm.to_device(U0h, dev)
+    nbytes = max(fm.workspace_size(P.n, P.m0, fm.binding.make_contour(P.center, P.radius, 1.0, P.q),
+                                   fm.binding.make_options(m, variant, pivoting=args.pivoting), True)
+                 for m in ("fp32", "fp64"))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    res = dict(workload=f"n={P.n}, circle c={P.center}, R*={P.radius:.6g} (m={g['m']}), q={P.q}, m0={P.m0}, "
+                        f"{variant}-FEAST, tol 1e-10")
+    for mode in ("fp32", "fp64", "fp16"):
+        wall, results, phases = run_steps(fm, torch, A, B, U0, P, mode, 1, 1 if mode == "fp32" else 0, ws,
+                                          timing=True, variant=variant, pivoting=args.pivoting)
+        r = results[0]
+        setup_ms = sum(phases[k]["ms"] for k in ("lu_update", "lu_panel", "lu_other"))
+        res[mode] = dict(time_to_1e10_ms=1e3 * wall, iterations=r.iterations, converged=r.converged,
+                         m=len(r.lam), eig_err_vs_oracle=match_err(r.lam, ref),
+                         factor_device_ms=setup_ms, escalated_to_fp32=bool(r.escalated),
+                         iters_per_s=r.iterations / wall)
+        log(f"{name} {mode}: {1e3 * wall:.1f} ms, {r.iterations} iterations, m={len(r.lam)}, "
+            f"err {res[mode]['eig_err_vs_oracle']:.1e}, factorisation {setup_ms:.1f} ms"
+            + (" (escalated)" if r.escalated else ""))
+    res["speedup_fp32_vs_fp64"] = res["fp64"]["time_to_1e10_ms"] / res["fp32"]["time_to_1e10_ms"]
+    res["speedup_fp16_vs_fp64"] = res["fp64"]["time_to_1e10_ms"] / res["fp16"]["time_to_1e10_ms"]
+    del A, B, U0, ws
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_conj(args, fm, torch, dev):
@@ -361,7 +467,7 @@ def bench_conj(args, fm, torch, dev):
         "config": {"workload": f"real generalized pencil n={P.n} (20 conjugate pairs and 8 real eigenvalues in "
                                f"|z| < 0.8), unit circle, q={P.q} trapezoid nodes of which {q_factored} factored, "
                                f"m0={P.m0}, R-FEAST, tol 1e-10",
-                   "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
+                   "mode": "FP32 LU + FP64 shifted-residual correction" if args.mode == "fp32" else "FP64",
                    "step": "setup (assembly + factored nodes) + iterations to 1e-10",
                    "conj_nodes": "real", "pivoting": args.pivoting},
         "time_to_1e10_s": head["ms_per_step"] / 1e3,
@@ -436,7 +542,7 @@ def bench_domains(args, fm, torch, dev):
                                f"away from cell edges), the rest in 2 < |z| < 5; probe batch over the 64 cells "
                                f"(8 Gauss-Legendre nodes, 16 probes, cond(V) <= 1e2), tiles of about {target} eigenvalues, "
                                f"q=16 per tile, R-FEAST, tol 1e-10",
-                   "mode": "FP32 LU + FP64 refinement" if args.mode == "fp32" else "FP64",
+                   "mode": "FP32 LU + FP64 shifted-residual correction" if args.mode == "fp32" else "FP64",
                    "step": "count estimates + partition + one batch over the tiles (setup and iterations)"},
         "time_to_1e10_s": wall,
         "tiles": len(rects),
@@ -575,7 +681,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="fp32", choices=["fp32", "fp64", "fp16"])
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c2", "c4", "real4096", "domains"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c3", "c2", "c4", "real4096", "domains"],
                     help="real4096: a real pencil whose conjugate nodes share factorisations; domains: "
                          "load-balanced tiles of a region in one batch")
     ap.add_argument("--count-train", type=int, default=4096, help="training pencils of the learned-m0 workload")
@@ -596,6 +702,8 @@ def main():
     ap.add_argument("--pivoting", default="tournament", choices=["tournament", "partial"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batched workload: skip the single-pencil n=4096 and n=8192 extra keys")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the library is a single-GPU build (several GPUs would each "
@@ -737,7 +845,7 @@ def main():
         "config": {"workload": f"complex-symmetric generalized pencil n={P.n}, circle c={P.center}, "
                                f"R*={P.radius:.6g} (m={g['m']} inside), q={P.q} trapezoid nodes, m0={P.m0}, "
                                f"{variant}-FEAST, tol 1e-10",
-                   "mode": {"fp32": "FP32 LU + FP64 refinement", "fp16": "FP16-update LU + FP64 refinement",
+                   "mode": {"fp32": "FP32 LU + FP64 shifted-residual correction", "fp16": "FP16-update LU + FP64 shifted-residual correction",
                             "fp64": "FP64"}[args.mode],
                    "step": "setup (assembly + q LUs) + iterations to 1e-10",
                    "pivoting": args.pivoting},

@@ -121,8 +121,8 @@ typedef struct {
     int ir_max;          /* refinement sweeps per solve (FP32/FP16 modes), default 10          */
     double ir_tol;       /* refinement of a node solve stops when the correction satisfies
                             ||D_k||_F <= ir_tol ||Y_k||_F, or when corrections stop halving;
-                            0 selects sqrt(n) u64 for feast_filter / feast_node_solve and an
-                            adaptive target inside feast_iterate                              */
+                            0 selects sqrt(n) u64 for feast_filter / feast_node_solve and the
+                            shifted-residual correction inside feast_iterate (see there)      */
     int timing;          /* 1: record HIP events around every phase launch (see feast_timing_*) */
     int rank_check;      /* 1: after the first iteration, stop with FEAST_ERANK when the filtered
                             block has no gap in its singular values (sigma_i / sigma_1 > 1e-6 for
@@ -190,7 +190,10 @@ typedef struct feast_ctx feast_ctx;
  * A and B must stay valid and unchanged until feast_destroy.
  * Synchronises the stream once to read the zero-pivot flags.
  * Returns 0, -i for invalid arguments, FEAST_ESINGULAR + k, FEAST_EWORKSPACE,
- * FEAST_EDEVICE. */
+ * FEAST_EDEVICE.  On any nonzero return *ctx is NULL and nothing is left
+ * allocated (no feast_destroy is needed); the stream has been synchronised
+ * when the failure came after work was enqueued, so the workspace may be
+ * reused at once. */
 int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb,
                 const feast_contour* contour, int m0, const feast_options* opts,
                 void* workspace, size_t workspace_bytes, void* stream);
@@ -203,11 +206,27 @@ int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, i
  * U and Q are device n x ncols blocks (ncols <= m0).  In the FP32/FP16 modes
  * every node solve is refined in FP64 until the correction is below ir_tol
  * relative to the solution (ir_tol = 0: sqrt(n) u64, i.e. FP64 accuracy) or
- * stops halving; feast_iterate instead sets the target from the residual the
- * iteration has reached, tightening it as it converges.  Asynchronous
- * in FP64 mode; the refinement modes synchronise once per sweep.
+ * stops halving (feast_iterate corrects its filters differently, see there).
+ * Asynchronous in FP64 mode; the refinement modes synchronise once per sweep.
  * Returns 0, -i, FEAST_EIR (a node's refinement stalled), FEAST_EDEVICE. */
 int feast_filter(feast_ctx* ctx, int side, int ncols, const void* U, int ldu, void* Q, int ldq);
+
+/* The shifted-residual form of the same filter, the one feast_iterate applies
+ * in the FP32 and FP16 modes (see there).  For the n x ncols block U and shifts
+ * l_j (lam: HOST array of 2 ncols doubles, interleaved re, im; no shift equal
+ * to a node) and D_k = diag(1 / (phi_k - l_j)):
+ *   side 0: Q = U rho(L) + sum_k sigma_k T_k^-1 (E D_k),  E = A U - B U L
+ *   side 1: Q = U conj(rho(L)) + sum_k conj(sigma_k) T_k^-H (E conj(D_k)),
+ *           E = A^H U - B^H U conj(L)
+ * with T_k = phi_k B - A and rho the filter of eqn:quadrature_for_pi.  Since
+ * B U - T_k U D_k = E D_k, this equals feast_filter's result in exact
+ * arithmetic for every U and L; in finite precision the node solves touch only
+ * E (FP64), so their low-precision error scales with ||E||, not ||U||.  The
+ * node solves are not refined further.  Overwrites the context's iteration
+ * blocks (not its factorisations).  Synchronises the stream (uploads).
+ * Returns 0, -i (-6 also for a shift on a node), FEAST_EDEVICE. */
+int feast_filter_shifted(feast_ctx* ctx, int side, int ncols, const void* U, int ldu, const double* lam, void* Q,
+                         int ldq);
 
 /* Solve of one node system: Y = T_k^-1 R (side 0) or T_k^-H R (side 1), with
  * the same refinement as feast_filter.  R and Y are device n x ncols blocks. */
@@ -224,6 +243,18 @@ int feast_node_solve(feast_ctx* ctx, int k, int side, int ncols, const void* R, 
  * residual <= candidate_tol.  Stops when all candidates have relative residual
  * <= tol and the count repeats (an empty set counts once no Ritz value lies
  * inside in two consecutive iterations).  Synchronous.
+ *
+ * FP64 corrections in the FP32 and FP16 modes: with ir_tol > 0 every filter runs
+ * classic refinement sweeps (FP64 residual, low-precision correction solve) to
+ * ir_tol.  With ir_tol = 0 (default) the first filter is the plain
+ * low-precision one, and every later filter uses the shifted-residual form of
+ * the same sum: for the current Ritz pairs (L, U),
+ *     sum_k s_k T_k^-1 B U = U rho(L) + sum_k s_k T_k^-1 (E D_k),
+ *     E = A U - B U L (FP64),  D_k = diag(1 / (phi_k - l_j)),
+ * which is exact because B U - T_k U D_k = E D_k: one FP64 residual correction
+ * of every node solve from the iterate U D_k, with the low-precision solve
+ * acting only on the Ritz residual block (the idea of residual inverse
+ * iteration and of FEAST with inexact solves).  ir_sweeps then stays 0.
  *
  * Results (caller-owned buffers):
  *   lambda      host, 2*m0 doubles: candidate eigenvalues first
@@ -346,6 +377,22 @@ int feast_mlp_get_params(feast_mlp* mlp, float* params);
 int feast_m0_from_estimate(double m_hat);
 void feast_mlp_destroy(feast_mlp* mlp);
 
+/* The subspace size for a search in one call: the probe features of
+ * probe_ctx's filter for the nprobe columns of V (feast_probe_features: the
+ * stochastic trace t_j = v_j^H rho(M) v_j estimates the eigenvalue count inside
+ * the contour, Section 3), the perceptron's forward pass on them (mlp was set
+ * up with n_in = 2 nprobe + 3 and trained on such features), and the rule of
+ * feast_m0_from_estimate.  probe_ctx is a context of the pencil (usually q = 8
+ * nodes, no refinement) whose m0 is at least nprobe; its contour is the search
+ * contour's.  *m_hat (may be NULL) receives the network's estimate, *m0_out
+ * the subspace size, capped at the pencil's order.  The estimate only sizes the
+ * subspace: the rank check of feast_iterate (feast_options.rank_check) judges
+ * it after the first iteration, and the caller grows m0 on FEAST_ERANK.
+ * Synchronous (probe_ctx's stream, then mlp's).  Returns 0, -i, or the code
+ * of the failing step. */
+int feast_estimate_m0(feast_ctx* probe_ctx, feast_mlp* mlp, const void* V, int ldv, int nprobe, int* m0_out,
+                      double* m_hat);
+
 /* ---- a9: batches of pencils -------------------------------------------------
  * Many independent pencils, each with its own contour and subspace size (the
  * outermost of the levels of parallelism listed in Section 6, independent
@@ -382,7 +429,16 @@ void feast_mlp_destroy(feast_mlp* mlp);
  * pencil's code.  Synchronous.  Returns 0 or the first nonzero member code.
  *
  * feast_batch_factor_ms: device time of the factorisation graph launch (HIP
- * events on `stream`). */
+ * events on `stream`).
+ *
+ * With feast_options.timing = 1 the factorisation sequence is launched
+ * directly on `stream` instead of as a graph (the same kernels in the same
+ * order), with HIP events around every launch of the factorisation phases, and
+ * every member records its iteration phases as feast_setup's contexts do.
+ * feast_batch_timing_read returns, per phase (FEAST_PHASE_*), the summed device
+ * time, algorithmic flops and launch count: the factorisation phases of the
+ * whole set (one launch covers every member), the iteration phases summed over
+ * the members.  Without timing it reports zeros. */
 typedef struct feast_batch feast_batch;
 int feast_batch_workspace_size(int count, const int* n, const int* m0, const feast_contour* C,
                                const feast_options* opts, const int* has_B, size_t* bytes);
@@ -394,6 +450,7 @@ feast_ctx* feast_batch_member(feast_batch* batch, int i);
 int feast_batch_iterate(feast_batch* batch, const void* const* U0, const int* ldu0,
                         feast_result* results, int* member_rc);
 int feast_batch_factor_ms(feast_batch* batch, double* ms);
+int feast_batch_timing_read(feast_batch* batch, int phase, feast_phase_time* out);
 void feast_batch_destroy(feast_batch* batch);
 
 /* ---- multi-domain tiling ------------------------------------------------------

@@ -43,6 +43,7 @@ EXPORTED = [
     "feast_mlp_fit_standardization", "feast_mlp_forward", "feast_mlp_gradients", "feast_mlp_train_step",
     "feast_mlp_get_params", "feast_m0_from_estimate", "feast_mlp_destroy",
     "feast_autotune_workspace_size", "feast_autotune", "feast_set_panel_rows",
+    "feast_filter_shifted", "feast_estimate_m0", "feast_batch_timing_read",
 ]
 
 
@@ -117,6 +118,10 @@ def lib():
         L.feast_setup.restype = i
         L.feast_filter.argtypes = [vp, i, i, vp, i, vp, i]
         L.feast_filter.restype = i
+        L.feast_filter_shifted.argtypes = [vp, i, i, vp, i, vp, vp, i]
+        L.feast_filter_shifted.restype = i
+        L.feast_estimate_m0.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(i), ctypes.POINTER(d)]
+        L.feast_estimate_m0.restype = i
         L.feast_node_solve.argtypes = [vp, i, i, i, vp, i, vp, i]
         L.feast_node_solve.restype = i
         L.feast_iterate.argtypes = [vp, vp, i, ctypes.POINTER(Result)]
@@ -141,6 +146,8 @@ def lib():
         L.feast_batch_member.restype = vp
         L.feast_batch_iterate.argtypes = [vp, vp, vp, vp, vp]
         L.feast_batch_iterate.restype = i
+        L.feast_batch_timing_read.argtypes = [vp, i, ctypes.POINTER(PhaseTime)]
+        L.feast_batch_timing_read.restype = i
         L.feast_batch_factor_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.feast_batch_factor_ms.restype = i
         L.feast_batch_trace_estimates.argtypes = [vp, vp, i, i, vp]
@@ -394,6 +401,27 @@ class Feast:
         _check(code, "feast_filter")
         return Q
 
+    def filter_shifted(self, U, lam, side=0, out=None):
+        """The shifted-residual form of the filter for the block U and shifts lam (feast_filter_shifted):
+        U rho(L) + sum_k sigma_k T_k^-1 (E D_k) with E = A U - B U L (side 1: the left twin)."""
+        k = U.shape[1]
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128).reshape(-1))
+        if lam.size != k:
+            raise ValueError("one shift per column")
+        Q = empty_cm(self.n, k, U.device) if out is None else out
+        _check(lib().feast_filter_shifted(self._ctx, side, k, U.data_ptr(), _ld(U), lam.ctypes.data, Q.data_ptr(),
+                                          _ld(Q)), "feast_filter_shifted")
+        return Q
+
+    def estimate_m0(self, mlp, V):
+        """(m0, m_hat): this context's probe features for V, the perceptron's estimate and the
+        subspace-size rule, in one call (feast_estimate_m0)."""
+        m0 = ctypes.c_int(0)
+        m_hat = ctypes.c_double(0.0)
+        _check(lib().feast_estimate_m0(self._ctx, mlp._m, V.data_ptr(), _ld(V), V.shape[1], ctypes.byref(m0),
+                                       ctypes.byref(m_hat)), "feast_estimate_m0")
+        return m0.value, m_hat.value
+
     def timing(self) -> dict:
         """Per-phase device time (ms), algorithmic flops and launch counts (needs timing=True)."""
         out = {}
@@ -468,7 +496,7 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False, pivoting="tournament"):
+                 rank_check=False, pivoting="tournament", timing=False):
         torch = _torch()
         count = len(pencils)
         self.count = count
@@ -477,7 +505,7 @@ class FeastBatch:
         self.m0 = list(m0) if isinstance(m0, (list, tuple)) else [int(m0)] * count
         if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
             contours = [contours] * count
-        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, False,
+        self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
                                     rank_check, pivoting)
         C = (Contour * count)(*[make_contour(q=q, rule=rule, pieces=e) if isinstance(e, list)
                                 else make_contour(e[0], e[1], e[2], q, rule) for e in contours])
@@ -515,6 +543,16 @@ class FeastBatch:
         out = ctypes.c_double(0.0)
         _check(lib().feast_batch_factor_ms(self._b, ctypes.byref(out)), "feast_batch_factor_ms")
         return out.value
+
+    def timing(self) -> dict:
+        """Per-phase device time (ms), algorithmic flops and launch counts of the batch (timing=True):
+        the factorisation phases of the whole set, the iteration phases summed over the members."""
+        out = {}
+        for i, name in enumerate(PHASES):
+            t = PhaseTime()
+            _check(lib().feast_batch_timing_read(self._b, i, ctypes.byref(t)), "feast_batch_timing_read")
+            out[name] = dict(ms=t.ms, flops=t.flops, launches=t.launches)
+        return out
 
     def trace_estimates(self, V) -> np.ndarray:
         """Per member, the stochastic estimate of its eigenvalue count from the probe block V."""

@@ -544,6 +544,13 @@ void from_mat(const host::Mat& M, z64* a) {
     for (size_t i = 0; i < M.a.size(); ++i) a[i] = z64(M.a[i].real(), M.a[i].imag());
 }
 
+// rho(l) = sum_k sigma_k / (z_k - l) over every node of the contour (eqn:quadrature_for_pi)
+z64 rho_at(const feast_ctx* c, z64 l) {
+    z64 acc(0.0, 0.0);
+    for (size_t k = 0; k < c->z.size(); ++k) acc = acc + cdiv(c->sig[k], c->z[k] - l);
+    return acc;
+}
+
 double full_accuracy_target(const feast_ctx* c) { return 1.1102230246251565e-16 * std::sqrt((double)c->n); }
 
 double default_ir_target(const feast_ctx* c) { return c->o.ir_tol > 0 ? c->o.ir_tol : full_accuracy_target(c); }
@@ -738,6 +745,9 @@ struct OuterOrder {
     }
 };
 
+int ctx_tables(feast_ctx* c, const feast_contour* C);
+
+// Creates a context; on any failure nothing is left allocated and *ctx stays NULL.
 int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C, int m0,
                const feast_options* o, void* workspace, size_t workspace_bytes, hipStream_t stream) {
     if (!ctx) return -1;
@@ -792,7 +802,19 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     c->pin.G2inv = t; t += pp;
     c->pin.norms = (double*)t;
     c->pin.idx = (int*)(c->pin.norms + 3 * p);
+    const int rc2 = ctx_tables(c, C);
+    if (rc2) {
+        feast_destroy(c);
+        return rc2;
+    }
     *ctx = c;
+    return 0;
+}
+
+// Node tables, the factorisation's device descriptor and grouped-product table (synchronous
+// uploads through the pinned staging buffer).
+int ctx_tables(feast_ctx* c, const feast_contour* C) {
+    const int q = C->q;
     // a1: nodes and weights; the device tables list the factored nodes (all of them, or those with
     // Im z >= 0 with their weights times the share of the conjugate pair they stand for)
     std::vector<double> zz(2 * q), ss(2 * q);
@@ -902,8 +924,17 @@ int feast_workspace_size(int n, int m0, const feast_contour* C, const feast_opti
 int feast_setup(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C,
                 int m0, const feast_options* o, void* workspace, size_t workspace_bytes, void* stream) {
     FM_TRY(ctx_create(ctx, n, A, lda, B, ldb, C, m0, o, workspace, workspace_bytes, (hipStream_t)stream));
-    FM_TRY(ctx_factor_enqueue(*ctx));
-    return ctx_check_info(*ctx);
+    int rc = ctx_factor_enqueue(*ctx);
+    if (!rc) rc = ctx_check_info(*ctx);
+    if (rc) {
+        // a failed setup leaves nothing allocated (the stream is synchronised first: the enqueued
+        // work reads the context's device tables, not its host buffers, but the caller may reuse
+        // the workspace at once)
+        (void)hipStreamSynchronize((*ctx)->st);
+        feast_destroy(*ctx);
+        *ctx = nullptr;
+    }
+    return rc;
 }
 
 int feast_filter(feast_ctx* c, int side, int ncols, const void* U, int ldu, void* Q, int ldq) {
@@ -918,6 +949,46 @@ int feast_filter(feast_ctx* c, int side, int ncols, const void* U, int ldu, void
     OuterOrder order(c);
     if (order.rc) return order.rc;
     return filter_impl(c, side, ncols, (const z64*)U, ldu, (z64*)Q, ldq);
+}
+
+int feast_filter_shifted(feast_ctx* c, int side, int ncols, const void* U, int ldu, const double* lam, void* Q,
+                         int ldq) {
+    if (!c) return -1;
+    if (side != 0 && side != 1) return -2;
+    if (ncols < 1 || ncols > c->m0) return -3;
+    if (!U) return -4;
+    if (ldu < c->n) return -5;
+    if (!lam) return -6;
+    if (!Q) return -7;
+    if (ldq < c->n) return -8;
+    const int n = c->n;
+    const long np = (long)n * c->m0;
+    std::vector<z64> hl(ncols), hr(ncols);
+    for (int j = 0; j < ncols; ++j) {
+        hl[j] = z64(lam[2 * j], lam[2 * j + 1]);
+        for (const z64& zk : c->z)
+            if (zk.re == hl[j].re && zk.im == hl[j].im) return -6;   // a shift on a node
+        const z64 r = rho_at(c, hl[j]);
+        hr[j] = side == 0 ? r : conj(r);
+    }
+    OuterOrder order(c);
+    if (order.rc) return order.rc;
+    // U (ld n), op(A) U and op(B) U in the iteration's block triple, then E = op(A) U - op(B) U op(L)
+    z64* Ub = c->XAB;
+    FM_TRY(copy_cm(Ub, n, (const z64*)U, ldu, n, ncols, c->st));
+    FM_TRY(tall_product(c, c->A, c->lda, side, ncols, Ub, n, Ub + np, n));
+    if (c->B) {
+        FM_TRY(apply_B(c, side, ncols, Ub, n, Ub + 2 * np, n));
+    } else {
+        FM_TRY(copy_cm(Ub + 2 * np, n, Ub, n, n, ncols, c->st));
+    }
+    FM_TRY(h2d(c, c->lam_d, hl.data(), ncols * sizeof(z64)));
+    FM_TRY(h2d(c, c->rho_d, hr.data(), ncols * sizeof(z64)));
+    FM_TRY(residual_block(c->Eb, Ub + np, Ub + 2 * np, n, n, ncols, c->lam_d, side != 0, c->st));
+    Shifted sh;
+    sh.U = Ub; sh.E = c->Eb; sh.lam = c->lam_d; sh.rho = c->rho_d;
+    c->ir_target = default_ir_target(c);
+    return filter_impl(c, side, ncols, Ub, n, (z64*)Q, ldq, &sh);
 }
 
 int feast_node_solve(feast_ctx* c, int k, int side, int ncols, const void* R, int ldr, void* Y, int ldy) {
@@ -1010,11 +1081,6 @@ int h2d_async(feast_ctx* c, void* dev, const void* host, size_t bytes) {
     return 0;
 }
 
-z64 rho_at(const feast_ctx* c, z64 l) {
-    z64 acc(0.0, 0.0);
-    for (size_t k = 0; k < c->z.size(); ++k) acc = acc + cdiv(c->sig[k], c->z[k] - l);
-    return acc;
-}
 
 // start: U = U0; Bi-FEAST also V0 = B U0 (U0^H B^H B U0)^-1 (Gram matrix to the host)
 int e_begin(Run& r) {
@@ -1052,17 +1118,12 @@ int e_filter(Run& r) {
     const long np = (long)n * p;
     hipStream_t st = c->st;
     ++r.it;
-    // refinement target: loose while far from convergence, tightening with the residual the
-    // iteration is expected to reach next, full accuracy when the decrease stalls
-    if (c->o.ir_tol > 0) {
-        c->ir_target = c->o.ir_tol;
-    } else if (!(r.res_last > 0)) {
-        c->ir_target = 1e-3;
-    } else if (r.res_prev > 0 && r.res_last < 0.1 * r.res_prev) {
-        c->ir_target = std::max(full_accuracy_target(c), 1e-3 * r.res_last * (r.res_last / r.res_prev));
-    } else {
-        c->ir_target = full_accuracy_target(c);
-    }
+    // FP64 correction of the low-precision solves.  With ir_tol > 0 every filter runs classic
+    // refinement sweeps to that target.  With ir_tol = 0 (default) the first filter is the plain
+    // low-precision one (a target of 1e-3 skips the sweeps: the start block is random, so FP32
+    // accuracy is ample), and every later filter takes the shifted-residual form, whose FP64 Ritz
+    // residual block is itself the correction.
+    c->ir_target = c->o.ir_tol > 0 ? c->o.ir_tol : 1e-3;
     z64* U = c->XAB;
     const bool shifted = c->prec != Prec::F64 && c->o.ir_tol == 0 && r.it > 1;
     // the left-projector variant filters with the left filter, i.e. the right filter of the
@@ -1373,11 +1434,18 @@ int drive(std::vector<Run*>& runs) {
         if (!any) break;
         each(runs, [](Run& r) { return e_filter(r); });
         FM_TRY(sync_runs(runs));
+        const auto t_orth = std::chrono::steady_clock::now();
         for (int pass = 0; pass < 3; ++pass) {
             each_host(runs, [pass](Run& r) { return h_chol(r, pass); });
             each(runs, [pass](Run& r) { return e_orth(r, pass); });
             FM_TRY(sync_runs(runs));
         }
+        // wall time of the passes (host Cholesky, device products and the round trips); the last
+        // pass also enqueues the Rayleigh-Ritz products, which PH_RR times on the device
+        const double orth_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_orth).count();
+        for (Run* r : runs)
+            if (r->active) r->c->timer.add_host(PH_HOST_ORTHO, orth_ms);
         each_host(runs, [](Run& r) { return h_eig(r); });
         each(runs, [](Run& r) { return e_ritz(r); });
         FM_TRY(sync_runs(runs));
@@ -1509,6 +1577,33 @@ int feast_probe_features(feast_ctx* c, const void* V, int ldv, int nprobe, float
 
 }  // extern "C"
 
+namespace fm {
+int mlp_forward_one(feast_mlp* m, const float* x_host, int d, float* y_host);
+}
+
+extern "C" {
+
+int feast_estimate_m0(feast_ctx* c, feast_mlp* mlp, const void* V, int ldv, int nprobe, int* m0_out,
+                      double* m_hat) {
+    if (!c) return -1;
+    if (!mlp) return -2;
+    if (!V) return -3;
+    if (ldv < c->n) return -4;
+    if (nprobe < 1 || nprobe > c->m0) return -5;
+    if (!m0_out) return -6;
+    std::vector<float> f(2 * nprobe + 3);
+    FM_TRY(feast_probe_features(c, V, ldv, nprobe, f.data()));
+    float y = 0.0f;
+    const int rc = mlp_forward_one(mlp, f.data(), (int)f.size(), &y);
+    if (rc < 0) return -5;   // the perceptron's input width is not 2 nprobe + 3
+    if (rc) return rc;
+    if (m_hat) *m_hat = y;
+    *m0_out = std::min(c->n, feast_m0_from_estimate(y));
+    return 0;
+}
+
+}  // extern "C"
+
 // ---- batches of pencils ------------------------------------------------------------------------
 //
 // A batch holds one context per pencil, each on a stream of its own (default priority).  The
@@ -1530,6 +1625,10 @@ struct feast_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float factor_ms = 0.0f;
+    // options.timing = 1: the factorisation sequence runs as direct launches with HIP events around
+    // every phase launch (no graph), so that each kernel's time can be read per launch
+    Timer timer;
+    LUSet timed_set;
 };
 
 namespace {
@@ -1677,15 +1776,31 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
                     (!plan.empty() && hipMemcpy(bt->groups, plan.data(), plan.size() * sizeof(GemmGroup),
                                                 hipMemcpyHostToDevice) != hipSuccess)))
             rc = FEAST_EDEVICE;
-        if (!rc) rc = batch_capture(bt, S);
+        if (!rc && o->timing) {
+            bt->timer.on = true;
+            S.timer = &bt->timer;
+            bt->timed_set = S;
+        } else if (!rc) {
+            rc = batch_capture(bt, S);
+        }
     }
-    // one launch of the graph on the caller's stream, timed, then the zero-pivot checks
+    // one launch of the graph (or, with timing, of the sequence) on the caller's stream, timed, then
+    // the zero-pivot checks
     if (!rc) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-            hipEventRecord(e0, bt->user) != hipSuccess || hipGraphLaunch(bt->exec, bt->user) != hipSuccess ||
-            hipEventRecord(e1, bt->user) != hipSuccess || hipStreamSynchronize(bt->user) != hipSuccess ||
-            hipEventElapsedTime(&bt->factor_ms, e0, e1) != hipSuccess)
+            hipEventRecord(e0, bt->user) != hipSuccess)
+            rc = FEAST_EDEVICE;
+        if (!rc) {
+            if (bt->exec) {
+                if (hipGraphLaunch(bt->exec, bt->user) != hipSuccess) rc = FEAST_EDEVICE;
+            } else {
+                rc = bt->prec == Prec::F64 ? lu_factor_set<double>(bt->timed_set, bt->user)
+                                           : lu_factor_set<float>(bt->timed_set, bt->user);
+            }
+        }
+        if (!rc && (hipEventRecord(e1, bt->user) != hipSuccess || hipStreamSynchronize(bt->user) != hipSuccess ||
+                    hipEventElapsedTime(&bt->factor_ms, e0, e1) != hipSuccess))
             rc = FEAST_EDEVICE;
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -1725,6 +1840,27 @@ int feast_batch_trace_estimates(feast_batch* bt, const void* V, int ldv, int npr
         double s = 0.0;
         for (int j = 0; j < nprobe; ++j) s += f[2 * j];
         est[b] = s / nprobe;
+    }
+    return 0;
+}
+
+int feast_batch_timing_read(feast_batch* bt, int phase, feast_phase_time* out) {
+    if (!bt) return -1;
+    if (phase < 0 || phase >= PH_COUNT) return -2;
+    if (!out) return -3;
+    if (phase <= PH_LU_OTHER) {
+        out->ms = bt->timer.ms((Phase)phase);
+        out->flops = bt->timer.flops[phase];
+        out->launches = bt->timer.launches[phase];
+        return 0;
+    }
+    out->ms = 0.0;
+    out->flops = 0.0;
+    out->launches = 0;
+    for (feast_ctx* c : bt->ctx) {
+        out->ms += c->timer.ms((Phase)phase);
+        out->flops += c->timer.flops[phase];
+        out->launches += c->timer.launches[phase];
     }
     return 0;
 }

@@ -259,16 +259,18 @@ Views views(float* base, int d, int h) {
     return v;
 }
 
-int rgemm(const feast_mlp* m, const RG& g) {
+int rgemm_on(bool half, hipStream_t st, const RG& g) {
     if (g.M <= 0 || g.N <= 0) return 0;
     dim3 grid(ceil_div(g.N, TN), ceil_div(g.M, TM));
-    if (m->half)
-        hipLaunchKernelGGL(rgemm_kernel<true>, grid, dim3(256), 0, m->st, g);
+    if (half)
+        hipLaunchKernelGGL(rgemm_kernel<true>, grid, dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL(rgemm_kernel<false>, grid, dim3(256), 0, m->st, g);
+        hipLaunchKernelGGL(rgemm_kernel<false>, grid, dim3(256), 0, st, g);
     FM_LAUNCH_CHECK();
     return 0;
 }
+
+int rgemm(const feast_mlp* m, const RG& g) { return rgemm_on(m->half, m->st, g); }
 
 RG rg(const float* A, long lda, bool tA, const float* B, long ldb, bool tB, float* C, long ldc, int M, int N, int K) {
     RG g;
@@ -281,24 +283,30 @@ RG rg(const float* A, long lda, bool tA, const float* B, long ldb, bool tB, floa
     return g;
 }
 
-// Z1 = std(X) W1^T + b1;  Z2 = relu(Z1) W2^T + b2;  y = relu(Z2) W3^T + b3
-int forward(feast_mlp* m, const float* X, int B, float* y) {
-    const int d = m->d, h = m->h;
-    Views w = views(m->P, d, h);
-    RG g1 = rg(X, d, false, w.W1, d, true, m->Z1, h, B, h, d);
+// Z1 = std(X) W1^T + b1;  Z2 = relu(Z1) W2^T + b2;  y = relu(Z2) W3^T + b3, with the activations
+// Z1, Z2 (B x h each) in the given buffers; xm/xs null means no standardisation
+int forward_raw(int d, int h, bool half, hipStream_t st, const float* P, const float* xm, const float* xs, float* Z1,
+                float* Z2, const float* X, int B, float* y) {
+    Views w = views(const_cast<float*>(P), d, h);
+    RG g1 = rg(X, d, false, w.W1, d, true, Z1, h, B, h, d);
     g1.bias = w.b1;
-    g1.xm = m->xm;
-    g1.xs = m->xs;
-    FM_TRY(rgemm(m, g1));
-    RG g2 = rg(m->Z1, h, false, w.W2, h, true, m->Z2, h, B, h, h);
+    g1.xm = xs ? xm : nullptr;
+    g1.xs = xs;
+    FM_TRY(rgemm_on(half, st, g1));
+    RG g2 = rg(Z1, h, false, w.W2, h, true, Z2, h, B, h, h);
     g2.reluA = true;
     g2.bias = w.b2;
-    FM_TRY(rgemm(m, g2));
-    RG g3 = rg(m->Z2, h, false, w.W3, h, true, y, 1, B, 1, h);
+    FM_TRY(rgemm_on(half, st, g2));
+    RG g3 = rg(Z2, h, false, w.W3, h, true, y, 1, B, 1, h);
     g3.reluA = true;
     g3.bias = w.b3;
-    return rgemm(m, g3);
+    return rgemm_on(half, st, g3);
 }
+
+int forward(feast_mlp* m, const float* X, int B, float* y) {
+    return forward_raw(m->d, m->h, m->half, m->st, m->P, m->xm, m->xs, m->Z1, m->Z2, X, B, y);
+}
+
 
 // gradients of the mean squared error into m->G (times the loss scale); loss to the host
 int gradients(feast_mlp* m, const float* X, const float* t, int B, double* loss) {
@@ -341,6 +349,19 @@ int gradients(feast_mlp* m, const float* X, const float* t, int B, double* loss)
 }
 
 }  // namespace
+
+namespace fm {
+// One forward pass on a single host feature vector of the perceptron's input width (staged in the
+// backward buffer dZ1, B h >= d floats, which a forward pass does not use); synchronous.
+int mlp_forward_one(feast_mlp* m, const float* x_host, int d, float* y_host) {
+    if (d != m->d) return -1;
+    FM_HIP(hipMemcpyAsync(m->dZ1, x_host, d * sizeof(float), hipMemcpyHostToDevice, m->st));
+    FM_TRY(forward(m, m->dZ1, 1, m->y));
+    FM_HIP(hipMemcpyAsync(y_host, m->y, sizeof(float), hipMemcpyDeviceToHost, m->st));
+    FM_HIP(hipStreamSynchronize(m->st));
+    return 0;
+}
+}  // namespace fm
 
 extern "C" {
 
@@ -455,5 +476,7 @@ int feast_m0_from_estimate(double m_hat) {
 }
 
 void feast_mlp_destroy(feast_mlp* m) { delete m; }
+
+
 
 }  // extern "C"

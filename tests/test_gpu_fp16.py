@@ -12,6 +12,7 @@ from tests.gpu_common import device, match_eigs, random_pencil, rel_err
 
 pytestmark = pytest.mark.gpu
 U64 = 2.0 ** -53
+U16 = 2.0 ** -11
 
 
 def fm():
@@ -54,6 +55,70 @@ def test_unrefined_solve_matches_fp16_emulation_level(n):
             assert e_gpu < 10 * e_emu + 1e-6
     F.close()
     F32.close()
+
+
+def structured_node(n, seed):
+    """T = L0 U0 with L0 unit lower triangular (strictly lower part complex Gaussian / sqrt(n), so
+    |re| + |im| of every multiplier is well below 1/2) and U0 upper triangular with diagonal moduli
+    in [1, 2]: partial pivoting keeps every diagonal pivot with a margin above 2 in the |re| + |im|
+    metric, which FP16-level changes of the trailing matrix cannot overturn, so the library and the
+    emulation factor with the same (identity) pivot sequence."""
+    g = np.random.default_rng(seed)
+    L = np.tril(pencils.complex_gaussian(g, (n, n)), -1) / np.sqrt(n) + np.eye(n)
+    d = (1.0 + g.uniform(0, 1, n)) * np.exp(2j * np.pi * g.uniform(0, 1, n))
+    U = np.triu(pencils.complex_gaussian(g, (n, n)), 1) / np.sqrt(n) + np.diag(d)
+    return L @ U
+
+
+@pytest.mark.parametrize("n", [65, 257, 520, 1100])
+def test_fp16_factor_solves_match_emulation_elementwise(n):
+    """Partial pivoting, ir_max = 0: solves with the library's FP16-update factors against solves
+    with the oracle's emulation of the same factorisation (lowprec.factor_fp16_scaled: FP32 panels,
+    U12 of each step scaled by a power of two, FP16 operands, FP32 accumulation), entry by entry.
+
+    Why structured node matrices: on general matrices the FP16 roundings change the trailing matrix
+    by u16-relative amounts, enough to change later pivot choices, so two correct FP16
+    factorisations (or the emulation and the same emulation of T (1 + 1e-9 G)) follow different
+    pivot sequences and differ by as much as either differs from the exact solve.  Here node 0 is
+    T = L0 U0 (structured_node), whose pivots are unambiguous.
+
+    Bounds.  (1) Every entry of the library's solve is within the FP16 forward-error level
+    kappa(T) u16 sqrt(n / 64) (sum of n / 64 update roundings of relative size u16) of the
+    emulation's.  (2) Where few updates run, the library rounds the same operands as the emulation:
+    their difference is a small fraction of either one's error (measured on the CPU, the emulation
+    against itself on T (1 + 1e-7 G): 0.03 at n = 65, 0.2-0.3 at n = 257-520; the fraction grows
+    with n because each update's roundings move the next steps' operands by u16-relative amounts).
+    A library that scaled L21 instead of U12, dropped the scale-back, accumulated in FP16 or skipped
+    the rounding would differ from the emulation as much as from the exact solve or more.  (3) The
+    solve error is of FP16 size, far above an FP32 factorisation's."""
+    T = structured_node(n, n)
+    q, m0 = 8, 6
+    z, s = Q.nodes_and_weights(0j, 1.0, 1.0, "trapezoid", q)
+    A = np.asfortranarray(z[0] * np.eye(n) - T)      # node 0: z_0 I - A = T
+    rhs = pencils.complex_gaussian(np.random.default_rng(n), (n, m0))
+    kappa = np.linalg.cond(T)
+    exact = np.linalg.solve(T, rhs)
+    emu = scipy.linalg.lu_solve(lowprec.factor_fp16_scaled(T), rhs.astype(np.complex64)).astype(np.complex128)
+    F = fm().Feast(upload(A), None, 0j, 1.0, 1.0, q, m0, precision="fp16", ir_max=0, pivoting="partial")
+    F32 = fm().Feast(upload(A), None, 0j, 1.0, 1.0, q, m0, precision="fp32", ir_max=0, pivoting="partial")
+    rd = upload(rhs)
+    gpu = host(F.node_solve(0, rd))
+    g32 = host(F32.node_solve(0, rd))
+    F.close()
+    F32.close()
+    scale = np.abs(exact).max()
+    d_emu = np.abs(emu - exact).max() / scale
+    d_pair = np.abs(gpu - emu).max() / scale
+    d_32 = np.abs(g32 - exact).max() / scale
+    print(f"n={n} kappa={kappa:.1f} emu-exact {d_emu:.2e} gpu-emu {d_pair:.2e} ratio {d_pair / d_emu:.3f} "
+          f"fp32-exact {d_32:.2e}")
+    assert np.all(np.abs(gpu - emu) <= kappa * U16 * np.sqrt(n / 64.0) * scale), d_pair
+    if n <= 64 + 1:
+        assert d_pair <= 0.15 * d_emu, (d_pair, d_emu)
+    elif n <= 520:
+        assert d_pair <= 0.6 * d_emu, (d_pair, d_emu)
+    assert d_pair <= 1.5 * d_emu, (d_pair, d_emu)
+    assert d_emu > 20 * d_32 and np.abs(gpu - exact).max() / scale > 20 * d_32
 
 
 @pytest.mark.parametrize("n", [200, 520])

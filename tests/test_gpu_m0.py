@@ -194,3 +194,38 @@ def test_estimator_end_to_end_on_held_out_pencils():
         assert r.converged and len(r.lam) == p.m, (p.name, mh, m0, len(r.lam), p.m)
         assert match_eigs(r.lam, brute.eigenvalues_inside(p.lam, p.center, p.radius)) < 1e-9
     net.close()
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_estimate_m0_chains_probes_network_and_rule(half):
+    """feast_estimate_m0 in one call = feast_probe_features, the perceptron's forward pass on those
+    features and feast_m0_from_estimate (capped at n), each also called separately here; a
+    perceptron of the wrong input width is rejected."""
+    n = 512
+    dev = device()
+    V = fm().to_device(pencils.probe_block(4, 0, n), dev)
+    g = np.random.default_rng(12)
+    P0 = mlp.init_params(g, 19, 64)
+    # scale the last layer so that estimates land in the range of real counts
+    P0["W3"] = P0["W3"] * 20.0
+    P0["b3"] = P0["b3"] + 24.0
+    net = fm().MLP(mlp.flatten(P0), n_in=19, hidden=64, half=half, max_batch=8, device=dev)
+    for j, b in pencils.c4_split("eval", 3):
+        p = pencils.c4_pencil(j, n, basis=b)
+        with fm().Feast(fm().to_device(p.A, dev), None, p.center, p.radius, 1.0, 8, 8, precision="fp32",
+                        ir_max=0) as F:
+            m0, m_hat = F.estimate_m0(net, V)
+            feats = F.probe_features(V)
+        want = float(net.forward(f32(feats[None, :])).cpu().numpy()[0])
+        y_ref, _ = mlp.forward(P0, feats[None, :].astype(np.float64))
+        assert abs(m_hat - want) <= 1e-5 * max(1.0, abs(want)), (m_hat, want)
+        assert abs(m_hat - y_ref[0]) <= (5e-3 if half else 1e-5) * max(1.0, abs(y_ref[0]))
+        assert m0 == min(n, fm().m0_from_estimate(m_hat))
+    bad = fm().MLP(mlp.flatten(mlp.init_params(g, 11, 16)), n_in=11, hidden=16, half=half, max_batch=4, device=dev)
+    p = pencils.c4_pencil(0, n, basis=0)
+    with fm().Feast(fm().to_device(p.A, dev), None, p.center, p.radius, 1.0, 8, 8, precision="fp32", ir_max=0) as F:
+        with pytest.raises(fm().FeastError) as e:
+            F.estimate_m0(bad, V)
+        assert e.value.code == -5
+    net.close()
+    bad.close()
