@@ -377,6 +377,24 @@ int feast_mlp_get_params(feast_mlp* mlp, float* params);
 int feast_m0_from_estimate(double m_hat);
 void feast_mlp_destroy(feast_mlp* mlp);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the perceptron's
+ * forward pass without a feast_mlp handle or workspace.  params: device,
+ * feast_mlp_param_count(n_in, hidden) FP32 values in the order above; x_mean,
+ * x_scale: device, n_in floats each (the standardisation moments, e.g. copied
+ * from a trained feast_mlp), or both NULL for none; X: device batch x n_in
+ * row-major; y: device, batch outputs; half as in feast_mlp_setup.  The hidden
+ * activations live in a static device array of the library (one per GPU,
+ * 8 MiB, held until the process ends), so batch * hidden must not exceed
+ * feast_mlp_noalloc_max_elems() (1,048,576, e.g. 4096 x 256); larger batches
+ * return -8.  Calls no allocator.  Enqueues on `stream` (asynchronous).  Every
+ * call on one GPU uses the same array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.  Returns 0,
+ * -i for argument i, FEAST_EDEVICE. */
+long feast_mlp_noalloc_max_elems(void);
+int feast_mlp_forward_noalloc(int n_in, int hidden, int half, const float* params, const float* x_mean,
+                              const float* x_scale, const float* X, int batch, float* y, void* stream);
+
 /* The subspace size for a search in one call: the probe features of
  * probe_ctx's filter for the nprobe columns of V (feast_probe_features: the
  * stochastic trace t_j = v_j^H rho(M) v_j estimates the eigenvalue count inside

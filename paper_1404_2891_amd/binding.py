@@ -44,6 +44,7 @@ EXPORTED = [
     "feast_mlp_get_params", "feast_m0_from_estimate", "feast_mlp_destroy",
     "feast_autotune_workspace_size", "feast_autotune", "feast_set_panel_rows",
     "feast_filter_shifted", "feast_estimate_m0", "feast_batch_timing_read",
+    "feast_mlp_noalloc_max_elems", "feast_mlp_forward_noalloc",
 ]
 
 
@@ -178,6 +179,10 @@ def lib():
         L.feast_m0_from_estimate.restype = i
         L.feast_mlp_destroy.argtypes = [vp]
         L.feast_mlp_destroy.restype = None
+        L.feast_mlp_noalloc_max_elems.argtypes = []
+        L.feast_mlp_noalloc_max_elems.restype = ctypes.c_long
+        L.feast_mlp_forward_noalloc.argtypes = [i, i, i, vp, vp, vp, vp, i, vp, vp]
+        L.feast_mlp_forward_noalloc.restype = i
         L.feast_autotune_workspace_size.argtypes = [i, i, ctypes.POINTER(ctypes.c_size_t)]
         L.feast_autotune_workspace_size.restype = i
         L.feast_autotune.argtypes = [i, i, vp, ctypes.c_size_t, vp, ctypes.c_char_p, ctypes.POINTER(i), vp]
@@ -735,6 +740,19 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def mlp_forward_noalloc(params, X, n_in=19, hidden=256, half=True, x_mean=None, x_scale=None, out=None):
+    """The perceptron's forward pass through feast_mlp_forward_noalloc (no workspace; the library's
+    static activation scratch).  params, X, x_mean, x_scale: device float32 tensors; returns y."""
+    torch = _torch()
+    y = out if out is not None else torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    f = MLP._f32
+    _check(lib().feast_mlp_forward_noalloc(n_in, hidden, int(bool(half)), f(params),
+                                           None if x_mean is None else f(x_mean),
+                                           None if x_scale is None else f(x_scale), f(X), X.shape[0], f(y), _stream()),
+           "feast_mlp_forward_noalloc")
+    return y
 
 
 def autotune(precision="fp32", q=16, cache_path=None, device="cuda"):

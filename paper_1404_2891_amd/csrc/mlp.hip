@@ -11,6 +11,7 @@
 // gradients are divided by it again, exactly, before the update.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -465,6 +466,58 @@ int feast_mlp_get_params(feast_mlp* m, float* params) {
     FM_HIP(hipMemcpyAsync(params, m->P, m->np * sizeof(float), hipMemcpyDeviceToHost, m->st));
     FM_HIP(hipStreamSynchronize(m->st));
     return 0;
+}
+
+// ---- the forward pass without a workspace ----------------------------------------------------
+//
+// Activation scratch of feast_mlp_forward_noalloc: Z1 and Z2 (batch x hidden floats each), at most
+// NOALLOC_ELEMS floats each.  Every GPU the library runs on holds its own copy (8 MiB) until the
+// process ends; in host code the array's name is not a device address, so kernels receive the
+// per-device address hipGetSymbolAddress returns.
+}  // extern "C"
+
+namespace {
+constexpr long NOALLOC_ELEMS = 1L << 20;
+__device__ __align__(256) float scratch[2 * NOALLOC_ELEMS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+float* noalloc_ptr[NOALLOC_MAX_DEVICES] = {nullptr};
+
+// The scratch address on the current device, looked up once per device.
+int noalloc_scratch(float** out) {
+    int dev = -1;
+    FM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return FEAST_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        FM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return FEAST_EDEVICE;
+        noalloc_ptr[dev] = (float*)p;
+    }
+    *out = noalloc_ptr[dev];
+    return 0;
+}
+}  // namespace
+
+extern "C" {
+
+long feast_mlp_noalloc_max_elems(void) { return NOALLOC_ELEMS; }
+
+int feast_mlp_forward_noalloc(int n_in, int hidden, int half, const float* params, const float* x_mean,
+                              const float* x_scale, const float* X, int batch, float* y, void* stream) {
+    if (n_in < 1) return -1;
+    if (hidden < 1) return -2;
+    if (!params) return -4;
+    if ((x_mean == nullptr) != (x_scale == nullptr)) return -5;
+    if (!X) return -7;
+    if (batch < 1 || (long)batch * hidden > NOALLOC_ELEMS) return -8;
+    if (!y) return -9;
+    float* s = nullptr;
+    FM_TRY(noalloc_scratch(&s));
+    return forward_raw(n_in, hidden, half != 0, (hipStream_t)stream, params, x_mean, x_scale, s, s + NOALLOC_ELEMS,
+                       X, batch, y);
 }
 
 int feast_m0_from_estimate(double m_hat) {
