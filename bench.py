@@ -312,7 +312,7 @@ def bench_batch(args, fm, torch, dev):
         k = int(np.argsort([r[0] for r in runs])[len(runs) // 2])   # the median run
         wall, t_setup, fms, res, _ = runs[k]
         iters = sum(r.iterations for r in res)
-        seq_wall, seq_res = one_at_a_time(mode)
+        seq_wall, seq_res = one_at_a_time(mode) if not args.no_sequential else (float("nan"), res)
         out[mode] = dict(ms_per_step=1e3 * wall, iters_per_s=iters / wall, total_iterations=iters,
                          setup_ms=1e3 * t_setup, factor_graph_ms=fms,
                          iters_per_s_after_setup=iters / (wall - t_setup),
@@ -702,6 +702,8 @@ def main():
     ap.add_argument("--pivoting", default="tournament", choices=["tournament", "partial"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched workload: skip the one-pencil-at-a-time comparison (kernel profiles)")
     ap.add_argument("--no-extras", action="store_true",
                     help="batched workload: skip the single-pencil n=4096 and n=8192 extra keys")
     args = ap.parse_args()

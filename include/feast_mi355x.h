@@ -148,6 +148,12 @@ typedef struct {
                             transpose solve for HERMITIAN).  feast_node_solve then indexes the
                             factored nodes, in their order in the full list.  Not supported by
                             feast_batch_* (FEAST_EUNSUPPORTED). */
+    int batch_launch;    /* feast_batch_iterate: 0 (default) grouped launches: every phase of the
+                            lockstep iteration is recorded for all pencils and launched once for
+                            the whole batch on a stream of its own (operations of the pencils that
+                            run the same kernel become one launch reading each pencil's operands
+                            from a device table); 1: each pencil enqueues its own launches on a
+                            stream of its own.  Both give the same results bit for bit. */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */
@@ -300,13 +306,17 @@ int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, do
  * count.  Phases: the LU trailing update (8 (n-j0-w)^2 w q flops per launch),
  * the panel factorisations, the other LU steps (swaps, diagonal-block
  * inverses, U12), the multi-RHS node solves (8 n^2 ncols q per launch group),
- * the FP64 refinement residuals, and the Rayleigh-Ritz products.  Two more
- * report host wall time: the reduced eigenproblem (with its transfers) and the
- * orthonormalisation passes. */
+ * the FP64 refinement residuals, and the Rayleigh-Ritz products.  Four more
+ * report the host's wall time during feast_iterate (feast_batch_iterate: the
+ * whole batch's, once): the reduced eigenproblems, the Cholesky factorisations
+ * of the orthonormalisation, the driver (enqueueing the device phases and the
+ * convergence bookkeeping), and the waits at the iteration's synchronisation
+ * points; they add up to the iteration's wall time. */
 enum {
     FEAST_PHASE_LU_UPDATE = 0, FEAST_PHASE_LU_PANEL = 1, FEAST_PHASE_LU_OTHER = 2,
     FEAST_PHASE_SOLVE = 3, FEAST_PHASE_REFINE = 4, FEAST_PHASE_RR = 5,
-    FEAST_PHASE_HOST_REDUCED = 6, FEAST_PHASE_HOST_ORTHO = 7, FEAST_PHASE_COUNT = 8
+    FEAST_PHASE_HOST_REDUCED = 6, FEAST_PHASE_HOST_ORTHO = 7, FEAST_PHASE_HOST_DRIVER = 8,
+    FEAST_PHASE_HOST_WAIT = 9, FEAST_PHASE_COUNT = 10
 };
 typedef struct { double ms; double flops; long launches; } feast_phase_time;
 int feast_timing_read(feast_ctx* ctx, int phase, feast_phase_time* out);
@@ -455,8 +465,9 @@ int feast_estimate_m0(feast_ctx* probe_ctx, feast_mlp* mlp, const void* V, int l
  * every member records its iteration phases as feast_setup's contexts do.
  * feast_batch_timing_read returns, per phase (FEAST_PHASE_*), the summed device
  * time, algorithmic flops and launch count: the factorisation phases of the
- * whole set (one launch covers every member), the iteration phases summed over
- * the members.  Without timing it reports zeros. */
+ * whole set (one launch covers every member), the device phases of the
+ * iteration summed over the members, and the host phases of the lockstep
+ * iteration once for the whole batch.  Without timing it reports zeros. */
 typedef struct feast_batch feast_batch;
 int feast_batch_workspace_size(int count, const int* n, const int* m0, const feast_contour* C,
                                const feast_options* opts, const int* has_B, size_t* bytes);

@@ -32,6 +32,7 @@ FEAST_ESINGULAR = 1000
 RULES = {"trapezoid": 0, "gauss-legendre": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2}
 VARIANTS = {"R": 0, "Bi": 1, "L": 2}
+BATCH_LAUNCH = {"grouped": 0, "streams": 1}
 
 EXPORTED = [
     "feast_default_options", "feast_contour_nodes", "feast_contour_inside", "feast_workspace_size", "feast_setup",
@@ -63,7 +64,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int),
-                ("pivoting", ctypes.c_int), ("conj_nodes", ctypes.c_int)]
+                ("pivoting", ctypes.c_int), ("conj_nodes", ctypes.c_int), ("batch_launch", ctypes.c_int)]
 
 
 class PhaseTime(ctypes.Structure):
@@ -71,7 +72,7 @@ class PhaseTime(ctypes.Structure):
 
 
 PHASES = ["lu_update", "lu_panel", "lu_other", "solve", "refine", "rayleigh_ritz", "host_reduced_eig",
-          "orthonormalize"]
+          "host_cholesky", "host_driver", "host_wait"]
 
 
 class Result(ctypes.Structure):
@@ -240,7 +241,8 @@ CONJ_NODES = {"none": 0, "real": 1, "hermitian": 2}
 
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
-                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament", conj_nodes="none") -> Options:
+                 ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament", conj_nodes="none",
+                 batch_launch="grouped") -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -254,6 +256,7 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.rank_check = int(bool(rank_check))
     o.pivoting = PIVOTING[pivoting]
     o.conj_nodes = CONJ_NODES[conj_nodes]
+    o.batch_launch = BATCH_LAUNCH[batch_launch]
     return o
 
 
@@ -501,7 +504,7 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False, pivoting="tournament", timing=False):
+                 rank_check=False, pivoting="tournament", timing=False, batch_launch="grouped"):
         torch = _torch()
         count = len(pencils)
         self.count = count
@@ -511,7 +514,7 @@ class FeastBatch:
         if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
             contours = [contours] * count
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check, pivoting)
+                                    rank_check, pivoting, batch_launch=batch_launch)
         C = (Contour * count)(*[make_contour(q=q, rule=rule, pieces=e) if isinstance(e, list)
                                 else make_contour(e[0], e[1], e[2], q, rule) for e in contours])
         self._C = C
@@ -551,7 +554,8 @@ class FeastBatch:
 
     def timing(self) -> dict:
         """Per-phase device time (ms), algorithmic flops and launch counts of the batch (timing=True):
-        the factorisation phases of the whole set, the iteration phases summed over the members."""
+        the factorisation phases of the whole set, the iteration's device phases (grouped launches,
+        or summed over the members' own launches) and its host phases for the whole batch."""
         out = {}
         for i, name in enumerate(PHASES):
             t = PhaseTime()

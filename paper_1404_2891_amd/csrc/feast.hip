@@ -17,7 +17,9 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -25,6 +27,7 @@
 #include "gemm.h"
 #include "hostla.h"
 #include "lu.h"
+#include "record.h"
 #include "solve.h"
 #include "timing.h"
 
@@ -332,6 +335,7 @@ LUStore node_view(const feast_ctx* c, int k0, int qv) {
 }
 
 int d2h(feast_ctx* c, void* host, const void* dev, size_t bytes) {
+    if (op_log()) return FEAST_EUNSUPPORTED;   // a synchronous copy cannot be recorded
     FM_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->st));
     FM_HIP(hipStreamSynchronize(c->st));
     return 0;
@@ -340,6 +344,7 @@ int d2h(feast_ctx* c, void* host, const void* dev, size_t bytes) {
 // Host-to-device through the pinned staging area (synchronises so the staging can be reused).
 int h2d(feast_ctx* c, void* dev, const void* host, size_t bytes) {
     if (bytes > c->hbytes) return FEAST_EWORKSPACE;
+    if (op_log()) return FEAST_EUNSUPPORTED;
     std::memcpy(c->h, host, bytes);
     FM_HIP(hipMemcpyAsync(dev, c->h, bytes, hipMemcpyHostToDevice, c->st));
     FM_HIP(hipStreamSynchronize(c->st));
@@ -891,6 +896,7 @@ void feast_default_options(feast_options* o) {
     o->rank_check = 0;
     o->pivoting = 1;
     o->conj_nodes = FEAST_CONJ_NONE;
+    o->batch_launch = 0;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -1073,12 +1079,10 @@ z64* side_G(feast_ctx* c, int side) { return side == 0 ? c->G_d : c->GL_d; }
 z64* side_Rinv(feast_ctx* c, int side) { return side == 0 ? c->Rinv_d : c->RinvL_d; }
 
 int d2h_async(feast_ctx* c, void* host, const void* dev, size_t bytes) {
-    FM_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->st));
-    return 0;
+    return copy_async(host, dev, bytes, hipMemcpyDeviceToHost, c->st);
 }
 int h2d_async(feast_ctx* c, void* dev, const void* host, size_t bytes) {
-    FM_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->st));
-    return 0;
+    return copy_async(dev, host, bytes, hipMemcpyHostToDevice, c->st);
 }
 
 
@@ -1246,13 +1250,10 @@ int e_orth(Run& r, int pass) {
 int h_eig(Run& r) {
     feast_ctx* c = r.c;
     const int p = c->m0;
-    const auto t0 = std::chrono::steady_clock::now();
     int rc = reduced_eig_impl(p, (const double*)c->pin.AhBh, (const double*)(c->pin.AhBh + (size_t)p * p),
                               (double*)c->pin.lam, (double*)c->pin.W, is_bi(c) ? (double*)c->pin.Z : nullptr,
                               !is_bi(c) && c->B == nullptr);
     if (rc) return rc;
-    c->timer.add_host(PH_HOST_REDUCED,
-                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
     FM_TRY(h2d_async(c, c->W_d, c->pin.W, (size_t)p * p * sizeof(z64)));
     FM_TRY(h2d_async(c, c->lam_d, c->pin.lam, p * sizeof(z64)));
     if (is_bi(c)) FM_TRY(h2d_async(c, c->Z_d, c->pin.Z, (size_t)p * p * sizeof(z64)));
@@ -1332,8 +1333,14 @@ int h_conv(Run& r) {
     // halves per iteration: the nodes are factored again with FP32 updates and the run continues
     if (c->lu.half && !r.finishing && r.it >= 3 &&
         ((count > 0 && r.res_prev > 0 && std::isfinite(r.res_prev) && !(r.res_last < 0.5 * r.res_prev)) ||
-         (count == 0 && n_inside > 0 && r.it >= 4)))
-        FM_TRY(escalate(c));
+         (count == 0 && n_inside > 0 && r.it >= 4))) {
+        // the new factorisation is enqueued directly (it synchronises to check its pivots)
+        OpLog* rec = op_log();
+        op_log() = nullptr;
+        const int rc = escalate(c);
+        op_log() = rec;
+        FM_TRY(rc);
+    }
     if (r.finishing) {
         r.order.insert(r.order.end(), rest.begin(), rest.end());
         for (int j = 0; j < p; ++j) c->pin.idx[j] = r.order[j];
@@ -1379,81 +1386,284 @@ void h_finish(Run& r) {
     r.active = false;
 }
 
-int sync_runs(std::vector<Run*>& runs) {
+// ---- grouped launches for a batch ----------------------------------------------------------------
+//
+// With a SetExec, every phase of the lockstep iteration is recorded for each pencil (record.h) and
+// the records are launched together on the set's own stream: operations at the same position of
+// the pencils' records that run the same kernel with compatible parameters become one grouped
+// launch whose per-pencil operands come from a device table (tables are uploaded once and reused
+// while their contents repeat, so a steady iteration uploads nothing), the rest run one after
+// another.  Every pencil's operations keep their order and pencils are independent, so the result
+// is the same as launching each pencil's work on its own.
+struct SetExec {
+    hipStream_t st = nullptr;
+    char* dev = nullptr;   // table arena in device memory
+    char* pin = nullptr;   // its pinned host mirror (the source of the uploads)
+    size_t cap = 0, used = 0;
+    std::unordered_map<std::string, size_t> cache;   // table contents -> arena offset
+    Timer* timer = nullptr;                          // the batch's timer (phase marks)
+    int pad_steps = 0;
+    std::vector<OpLog> logs;                         // one per run
+};
+
+// Device copy of a table; the same contents uploaded earlier are reused.  The arena is emptied only
+// after a synchronisation (set_sync), when no upload or launch still reads it.
+int set_table(SetExec& X, const void* bytes, size_t n, const void** out) {
+    std::string key((const char*)bytes, n);
+    auto it = X.cache.find(key);
+    if (it != X.cache.end()) {
+        *out = X.dev + it->second;
+        return 0;
+    }
+    const size_t off = align_up(X.used, 256);
+    if (off + n > X.cap) return FEAST_EWORKSPACE;
+    std::memcpy(X.pin + off, bytes, n);
+    FM_HIP(hipMemcpyAsync(X.dev + off, X.pin + off, n, hipMemcpyHostToDevice, X.st));
+    X.used = off + n;
+    X.cache.emplace(std::move(key), off);
+    *out = X.dev + off;
+    return 0;
+}
+
+bool gemm_compatible(const RecOp& a, const RecOp& b) {
+    const GemmOp &x = a.g, &y = b.g;
+    return a.dbl == b.dbl && x.rowA == y.rowA && x.rowB == y.rowB && x.rowC == y.rowC && x.conjA == y.conjA &&
+           x.conjB == y.conjB && x.alpha.re == y.alpha.re && x.alpha.im == y.alpha.im && x.beta.re == y.beta.re &&
+           x.beta.im == y.beta.im;
+}
+
+bool gemm_groupable(const RecOp& a) {
+    return a.g.kind == 0 && !a.g.alpha_b && !a.g.amax && a.g.batch2 == 1 && !a.g.groups;
+}
+
+template <typename T>
+int set_gemm(SetExec& X, const std::vector<const RecOp*>& part) {
+    if (part.size() == 1) return gemm<T>(part[0]->g, X.st);
+    std::vector<GemmGroup> tab;
+    int mM = 0, mN = 0, mK = 0, mB = 0, mS = 1;
+    for (const RecOp* r : part) {
+        tab.push_back(gemm_member<T>(r->g));
+        const GemmGroup& g = tab.back();
+        mM = std::max(mM, g.M);
+        mN = std::max(mN, g.N);
+        mK = std::max(mK, g.K);
+        mB = std::max(mB, g.batch);
+        mS = std::max(mS, g.splitk);
+    }
+    const void* dt = nullptr;
+    FM_TRY(set_table(X, tab.data(), tab.size() * sizeof(GemmGroup), &dt));
+    return gemm_grouped<T>(part[0]->g, (const GemmGroup*)dt, (int)tab.size(), mM, mN, mK, mB, mS, X.st);
+}
+
+int set_launch(SetExec& X, const std::vector<const RecOp*>& part) {
+    const RecOp& r0 = *part[0];
+    switch (r0.kind) {
+        case REC_GEMM:
+            return r0.dbl ? set_gemm<double>(X, part) : set_gemm<float>(X, part);
+        case REC_EW: {
+            const size_t sz = ew_arg_size(r0.ew);
+            std::vector<unsigned char> tab(sz * part.size());
+            unsigned bx = 0, by = 0;
+            for (size_t i = 0; i < part.size(); ++i) {
+                std::memcpy(tab.data() + i * sz, part[i]->args, sz);
+                bx = std::max(bx, part[i]->bx);
+                by = std::max(by, part[i]->by);
+            }
+            const void* dt = nullptr;
+            FM_TRY(set_table(X, tab.data(), tab.size(), &dt));
+            return ew_grouped(r0.ew, dt, (int)part.size(), bx, by, X.st);
+        }
+        case REC_COPY:
+            FM_HIP(hipMemcpyAsync(r0.dst, r0.src, r0.bytes, r0.dir, X.st));
+            return 0;
+        case REC_MARK:
+            if (X.timer) {
+                if (r0.start) {
+                    X.timer->start((Phase)r0.phase, X.st);
+                } else {
+                    double fl = 0.0;
+                    for (const RecOp* r : part) fl += r->flops;
+                    X.timer->stop((Phase)r0.phase, X.st, fl);
+                }
+            }
+            return 0;
+        case REC_OTHER:
+            return r0.run(X.st);
+    }
+    return 0;
+}
+
+// Launches the recorded operations of every log, position by position, merging compatible ones.
+int set_replay(SetExec& X) {
+    size_t len = 0;
+    for (const OpLog& L : X.logs) len = std::max(len, L.ops.size());
+    std::vector<const RecOp*> col, part;
+    std::vector<char> used;
+    for (size_t i = 0; i < len; ++i) {
+        col.clear();
+        for (const OpLog& L : X.logs)
+            if (i < L.ops.size() && L.ops[i].kind != REC_NOP) col.push_back(&L.ops[i]);
+        used.assign(col.size(), 0);
+        for (size_t a = 0; a < col.size(); ++a) {
+            if (used[a]) continue;
+            used[a] = 1;
+            part.assign(1, col[a]);
+            const RecOp& r = *col[a];
+            const bool merge = (r.kind == REC_GEMM && gemm_groupable(r)) || r.kind == REC_EW || r.kind == REC_MARK;
+            for (size_t b = a + 1; merge && b < col.size(); ++b) {
+                const RecOp& o = *col[b];
+                if (used[b] || o.kind != r.kind) continue;
+                bool ok = false;
+                if (r.kind == REC_GEMM) ok = gemm_groupable(o) && gemm_compatible(r, o);
+                if (r.kind == REC_EW) ok = o.ew == r.ew;
+                if (r.kind == REC_MARK) ok = o.phase == r.phase && o.start == r.start;
+                if (ok) {
+                    used[b] = 1;
+                    part.push_back(col[b]);
+                }
+            }
+            FM_TRY(set_launch(X, part));
+        }
+    }
+    for (OpLog& L : X.logs) L.ops.clear();
+    return 0;
+}
+
+int sync_runs(std::vector<Run*>& runs, SetExec* X) {
+    if (X) {
+        FM_HIP(hipStreamSynchronize(X->st));
+        if (X->used > X->cap / 2) {   // nothing reads the arena now
+            X->cache.clear();
+            X->used = 0;
+        }
+        return 0;
+    }
     for (Run* r : runs)
         if (r->active) FM_HIP(hipStreamSynchronize(r->c->st));
     return 0;
 }
 
-// Runs every active Run through one phase; a failing run stops with its code.
+// Runs f on one run, recording its device work into its log when a SetExec is given.
 template <typename F>
-void each(std::vector<Run*>& runs, F f) {
-    for (Run* r : runs) {
+int run_phase(Run& r, size_t idx, SetExec* X, F& f) {
+    if (!X) return f(r);
+    OpLog& L = X->logs[idx];
+    L.pad_steps = X->pad_steps;
+    op_log() = &L;
+    const int rc = f(r);
+    op_log() = nullptr;
+    if (rc) L.ops.clear();   // a failing run stops; its partial record is dropped
+    return rc;
+}
+
+// Runs every active Run through one phase; a failing run stops with its code.  With a SetExec the
+// recorded work of all runs is then launched together.
+template <typename F>
+int each(std::vector<Run*>& runs, F f, SetExec* X = nullptr) {
+    for (size_t i = 0; i < runs.size(); ++i) {
+        Run* r = runs[i];
         if (!r->active) continue;
-        const int rc = f(*r);
+        const int rc = run_phase(*r, i, X, f);
         if (rc) {
             r->rc = rc;
             r->active = false;
         }
     }
+    return X ? set_replay(*X) : 0;
 }
 
 // Host phase f on every active context, on up to 16 threads when there are several contexts: each
-// call touches only its own context (host buffers, timer) and enqueues only on its own stream.
+// call touches only its own context (host buffers, timer) and enqueues (or records) only its own
+// work.
 template <typename F>
-void each_host(std::vector<Run*>& runs, F f) {
-    std::vector<Run*> act;
-    for (Run* r : runs)
-        if (r->active) act.push_back(r);
+int each_host(std::vector<Run*>& runs, F f, SetExec* X = nullptr) {
+    std::vector<size_t> act;
+    for (size_t i = 0; i < runs.size(); ++i)
+        if (runs[i]->active) act.push_back(i);
     const int nt = (int)std::min<size_t>({act.size(), (size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency())});
-    if (act.size() < 4 || nt < 2) {
-        each(runs, f);
-        return;
-    }
+    if (act.size() < 4 || nt < 2) return each(runs, f, X);
     std::vector<int> rcs(act.size(), 0);
     std::vector<std::thread> th;
     for (int t = 0; t < nt; ++t)
         th.emplace_back([&, t]() {
-            for (size_t i = t; i < act.size(); i += nt) rcs[i] = f(*act[i]);
+            for (size_t i = t; i < act.size(); i += nt) rcs[i] = run_phase(*runs[act[i]], act[i], X, f);
         });
     for (auto& x : th) x.join();
     for (size_t i = 0; i < act.size(); ++i)
         if (rcs[i]) {
-            act[i]->rc = rcs[i];
-            act[i]->active = false;
+            runs[act[i]]->rc = rcs[i];
+            runs[act[i]]->active = false;
         }
+    return X ? set_replay(*X) : 0;
 }
 
-int drive(std::vector<Run*>& runs) {
-    each(runs, [](Run& r) { return e_begin(r); });
-    FM_TRY(sync_runs(runs));
-    each_host(runs, [](Run& r) { return h_begin(r); });
+// Wall time of the host's share of an iteration: the enqueue phases and small host steps
+// (PH_HOST_DRIVER), the waits at the synchronisation points (PH_HOST_WAIT), the host Cholesky
+// factorisations of the orthonormalisation (PH_HOST_ORTHO) and the reduced eigenproblems
+// (PH_HOST_REDUCED); for a batch these are the whole batch's, not per pencil.
+struct WallClock {
+    Timer* t;
+    std::chrono::steady_clock::time_point t0;
+    explicit WallClock(Timer* timer) : t(timer) {}
+    void start() { t0 = std::chrono::steady_clock::now(); }
+    void stop(Phase p) {
+        if (t) t->add_host(p, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+};
+
+int drive(std::vector<Run*>& runs, Timer* wall, SetExec* X = nullptr) {
+    WallClock w(wall);
+    if (X) X->logs.assign(runs.size(), OpLog());
+    w.start();
+    FM_TRY(each(runs, [](Run& r) { return e_begin(r); }, X));
+    w.stop(PH_HOST_DRIVER);
+    w.start();
+    FM_TRY(sync_runs(runs, X));
+    w.stop(PH_HOST_WAIT);
+    w.start();
+    FM_TRY(each_host(runs, [](Run& r) { return h_begin(r); }, X));
+    w.stop(PH_HOST_DRIVER);
     for (;;) {
         bool any = false;
         for (Run* r : runs) any |= r->active;
         if (!any) break;
-        each(runs, [](Run& r) { return e_filter(r); });
-        FM_TRY(sync_runs(runs));
-        const auto t_orth = std::chrono::steady_clock::now();
+        w.start();
+        FM_TRY(each(runs, [](Run& r) { return e_filter(r); }, X));
+        w.stop(PH_HOST_DRIVER);
+        w.start();
+        FM_TRY(sync_runs(runs, X));
+        w.stop(PH_HOST_WAIT);
         for (int pass = 0; pass < 3; ++pass) {
-            each_host(runs, [pass](Run& r) { return h_chol(r, pass); });
-            each(runs, [pass](Run& r) { return e_orth(r, pass); });
-            FM_TRY(sync_runs(runs));
+            w.start();
+            FM_TRY(each_host(runs, [pass](Run& r) { return h_chol(r, pass); }, X));
+            w.stop(PH_HOST_ORTHO);
+            w.start();
+            FM_TRY(each(runs, [pass](Run& r) { return e_orth(r, pass); }, X));
+            w.stop(PH_HOST_DRIVER);
+            w.start();
+            FM_TRY(sync_runs(runs, X));
+            w.stop(PH_HOST_WAIT);
         }
-        // wall time of the passes (host Cholesky, device products and the round trips); the last
-        // pass also enqueues the Rayleigh-Ritz products, which PH_RR times on the device
-        const double orth_ms =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_orth).count();
-        for (Run* r : runs)
-            if (r->active) r->c->timer.add_host(PH_HOST_ORTHO, orth_ms);
-        each_host(runs, [](Run& r) { return h_eig(r); });
-        each(runs, [](Run& r) { return e_ritz(r); });
-        FM_TRY(sync_runs(runs));
-        each_host(runs, [](Run& r) { return h_conv(r); });
-        each(runs, [](Run& r) { return e_post(r); });
-        FM_TRY(sync_runs(runs));
+        w.start();
+        FM_TRY(each_host(runs, [](Run& r) { return h_eig(r); }, X));
+        w.stop(PH_HOST_REDUCED);
+        w.start();
+        FM_TRY(each(runs, [](Run& r) { return e_ritz(r); }, X));
+        w.stop(PH_HOST_DRIVER);
+        w.start();
+        FM_TRY(sync_runs(runs, X));
+        w.stop(PH_HOST_WAIT);
+        w.start();
+        FM_TRY(each_host(runs, [](Run& r) { return h_conv(r); }, X));
+        FM_TRY(each(runs, [](Run& r) { return e_post(r); }, X));
+        w.stop(PH_HOST_DRIVER);
+        w.start();
+        FM_TRY(sync_runs(runs, X));
+        w.stop(PH_HOST_WAIT);
+        w.start();
         for (Run* r : runs)
             if (r->active && r->finishing) h_finish(*r);
+        w.stop(PH_HOST_DRIVER);
     }
     return 0;
 }
@@ -1485,7 +1695,7 @@ int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {
     r.ldu0 = ldu0;
     r.res = res;
     std::vector<Run*> runs{&r};
-    FM_TRY(drive(runs));
+    FM_TRY(drive(runs, &c->timer));
     return r.rc;
 }
 
@@ -1629,13 +1839,30 @@ struct feast_batch {
     // every phase launch (no graph), so that each kernel's time can be read per launch
     Timer timer;
     LUSet timed_set;
+    // grouped launches of the iteration (options.batch_launch = 0): their stream, the device table
+    // arena (in the workspace) and its pinned mirror
+    bool grouped = false;
+    hipStream_t set_st = nullptr;
+    char* arena = nullptr;
+    char* arena_pin = nullptr;
+    size_t arena_bytes = 0;
 };
 
 namespace {
 
 // Workspace of a batch: the set's descriptors and grouped-product table, then one slice per member.
+// Device tables of the grouped iteration launches: every operation of a phase needs one entry per
+// pencil (a few hundred bytes), and the tables of a few phase variants and active sets stay cached.
+constexpr size_t SET_ARENA_BYTES = size_t(16) << 20;
+
+// Grouped launches unless one stream per pencil is asked for; classic refinement sweeps synchronise
+// inside a phase, so such batches keep one stream per pencil too.
+bool batch_grouped(const feast_options* o) {
+    return o->batch_launch == 0 && (o->precision == FEAST_FP64 || o->ir_tol == 0.0);
+}
+
 struct BatchLayout {
-    size_t dev_off = 0, groups_off = 0, ngroups = 0;
+    size_t dev_off = 0, groups_off = 0, ngroups = 0, arena_off = 0;
     std::vector<size_t> off, bytes;
     size_t total = 0;
 };
@@ -1659,6 +1886,8 @@ int batch_layout(int count, const int* n, const int* m0, const feast_contour* C,
     off = align_up(off + (size_t)count * sizeof(LUDev), ALIGN);
     L.groups_off = off;
     off = align_up(off + L.ngroups * sizeof(GemmGroup), ALIGN);
+    L.arena_off = off;
+    if (!o || batch_grouped(o)) off = align_up(off + SET_ARENA_BYTES, ALIGN);
     for (int b = 0; b < count; ++b) {
         L.off[b] = off;
         off = align_up(off + L.bytes[b], ALIGN);
@@ -1672,6 +1901,8 @@ void batch_free(feast_batch* bt) {
     for (feast_ctx* c : bt->ctx) feast_destroy(c);
     for (hipStream_t s : bt->streams)
         if (s) (void)hipStreamDestroy(s);
+    if (bt->set_st) (void)hipStreamDestroy(bt->set_st);
+    pinned_pool().put(bt->arena_pin);
     if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
     if (bt->graph) (void)hipGraphDestroy(bt->graph);
     delete bt;
@@ -1732,6 +1963,14 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
     bt->dev = (LUDev*)(base + L.dev_off);
     bt->groups = (GemmGroup*)(base + L.groups_off);
     int rc = 0;
+    bt->grouped = batch_grouped(o);
+    if (bt->grouped) {
+        bt->arena = base + L.arena_off;
+        bt->arena_bytes = SET_ARENA_BYTES;
+        bt->arena_pin = (char*)pinned_pool().get(SET_ARENA_BYTES);
+        if (!bt->arena_pin || hipStreamCreateWithFlags(&bt->set_st, hipStreamNonBlocking) != hipSuccess)
+            rc = FEAST_EDEVICE;
+    }
     // members: contexts with streams of their own (ctx_create only uploads the node tables and
     // descriptors of the member, synchronously on its stream)
     for (int b = 0; b < count && !rc; ++b) {
@@ -1848,15 +2087,11 @@ int feast_batch_timing_read(feast_batch* bt, int phase, feast_phase_time* out) {
     if (!bt) return -1;
     if (phase < 0 || phase >= PH_COUNT) return -2;
     if (!out) return -3;
-    if (phase <= PH_LU_OTHER) {
-        out->ms = bt->timer.ms((Phase)phase);
-        out->flops = bt->timer.flops[phase];
-        out->launches = bt->timer.launches[phase];
-        return 0;
-    }
-    out->ms = 0.0;
-    out->flops = 0.0;
-    out->launches = 0;
+    out->ms = bt->timer.ms((Phase)phase);
+    out->flops = bt->timer.flops[phase];
+    out->launches = bt->timer.launches[phase];
+    if (phase <= PH_LU_OTHER || is_host_phase(phase)) return 0;
+    // iteration phases: the grouped launches (batch timer) or the members' own launches
     for (feast_ctx* c : bt->ctx) {
         out->ms += c->timer.ms((Phase)phase);
         out->flops += c->timer.flops[phase];
@@ -1890,15 +2125,33 @@ int feast_batch_iterate(feast_batch* bt, const void* const* U0, const int* ldu0,
         runs[b].res = r;
         ptrs.push_back(&runs[b]);
     }
-    // member streams start after the caller's stream (the start blocks were written there) and the
-    // caller's stream continues after them
+    // member streams (grouped launches: the set's stream) start after the caller's stream (the
+    // start blocks were written there) and the caller's stream continues after them
     hipEvent_t ev = nullptr;
     FM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     int rc = 0;
     if (hipEventRecord(ev, bt->user) != hipSuccess) rc = FEAST_EDEVICE;
     for (int b = 0; b < bt->count && !rc; ++b)
         if (hipStreamWaitEvent(bt->streams[b], ev, 0) != hipSuccess) rc = FEAST_EDEVICE;
-    if (!rc) rc = drive(ptrs);
+    if (bt->grouped) {
+        if (!rc && hipStreamWaitEvent(bt->set_st, ev, 0) != hipSuccess) rc = FEAST_EDEVICE;
+        // every member's remaining direct launches (a re-factorisation) go to the set's stream too
+        SetExec X;
+        X.st = bt->set_st;
+        X.dev = bt->arena;
+        X.pin = bt->arena_pin;
+        X.cap = bt->arena_bytes;
+        X.timer = bt->timer.on ? &bt->timer : nullptr;
+        for (feast_ctx* c : bt->ctx) {
+            X.pad_steps = std::max(X.pad_steps, trsolve_steps(c->lu));
+            c->st = bt->set_st;
+        }
+        if (!rc) rc = drive(ptrs, &bt->timer, &X);
+        if (hipStreamSynchronize(bt->set_st) != hipSuccess && !rc) rc = FEAST_EDEVICE;
+        for (int b = 0; b < bt->count; ++b) bt->ctx[b]->st = bt->streams[b];
+    } else if (!rc) {
+        rc = drive(ptrs, &bt->timer);
+    }
     for (int b = 0; b < bt->count && !rc; ++b)
         if (hipStreamSynchronize(bt->streams[b]) != hipSuccess) rc = FEAST_EDEVICE;
     (void)hipEventDestroy(ev);

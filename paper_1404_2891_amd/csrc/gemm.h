@@ -14,6 +14,10 @@ struct GemmGroup {
     long sA2, sB2, sC2;     // second batch strides
     int M, N, K, batch;
     int* amax;              // per-batch slots (see GemmOp::amax), or nullptr
+    // split-K partition of this member (splitk > 1: partials of kchunk-deep slices go to partial,
+    // splitk * batch * M * N elements, and the grouped reduction sums them)
+    void* partial = nullptr;
+    int splitk = 1, kchunk = 0;
 };
 
 // One batched product C_b = alpha_b op(A_b) op(B_b) + beta C_b, b = 0..batch-1.
@@ -47,8 +51,9 @@ struct GemmOp {
     // slots beforehand.  kind 2: the scale source described above.
     int* amax = nullptr;
     // grouped product: when groups != nullptr (a device array of ngroups members), each member
-    // supplies its own operands, strides, M, N, K and batch, and M, N, K, batch above are the
-    // maxima over the members (they size the grid).  Requires splitk == 1 and alpha_b == nullptr.
+    // supplies its own operands, strides, M, N, K, batch and split-K partition, and M, N, K, batch
+    // and splitk above are the maxima over the members (they size the grid).  Requires
+    // alpha_b == nullptr.
     const GemmGroup* groups = nullptr;
     int ngroups = 0;
 };

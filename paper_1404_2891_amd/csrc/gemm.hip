@@ -7,9 +7,11 @@
 // of depth BK (16 for FP32, 32 for FP64) are staged through LDS as separate real / imaginary planes in k-major
 // order, so the 16 lanes of an MFMA row group read consecutive addresses; the next tile
 // is fetched into registers while the current one is consumed.
+#include <algorithm>
 #include <type_traits>
 
 #include "gemm.h"
+#include "record.h"
 
 namespace fm {
 namespace {
@@ -90,23 +92,30 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
     long sA = p.sA, sB = p.sB, sC = p.sC, sA2 = p.sA2, sB2 = p.sB2, sC2 = p.sC2;
     int M = p.M, N = p.N, K = p.K;
     int* amax = p.amax;
+    int splitk = p.splitk, kchunk = p.kchunk, nbat = p.batch;
+    cplx<T>* partial = p.partial;
     if (p.groups) {
-        // member of a grouped product (splitk == 1): its own operands and sizes; workgroups
-        // outside the member's tiles or batch leave at once
-        const int per = p.batch * p.batch2;
+        // member of a grouped product: its own operands, sizes and split-K partition; workgroups
+        // outside the member's tiles, batch or slices leave at once
+        const int per = p.batch * p.splitk * p.batch2;
         const GemmGroup& g = p.groups[blockIdx.z / per];
-        b = (blockIdx.z % per) % p.batch;
-        b2 = (blockIdx.z % per) / p.batch;
-        s = 0;
+        const int rem = blockIdx.z % per;
+        b = rem % p.batch;
+        s = (rem / p.batch) % p.splitk;
+        b2 = rem / (p.batch * p.splitk);
         M = g.M; N = g.N; K = g.K;
-        if (b >= g.batch || m0 >= M || n0 >= N) return;
+        splitk = g.splitk > 1 ? g.splitk : 1;
+        if (b >= g.batch || m0 >= M || n0 >= N || s >= splitk) return;
+        kchunk = splitk > 1 ? g.kchunk : K;
+        nbat = g.batch;
+        partial = (cplx<T>*)g.partial;
         pA = (const cplx<T>*)g.A; pB = (const cplx<T>*)g.B; pC = (cplx<T>*)g.C;
         lda = g.lda; ldb = g.ldb; ldc = g.ldc;
         sA = g.sA; sB = g.sB; sC = g.sC; sA2 = g.sA2; sB2 = g.sB2; sC2 = g.sC2;
         amax = g.amax;
     }
-    const int kbeg = s * p.kchunk;
-    const int kend = p.groups ? K : min(K, kbeg + p.kchunk);
+    const int kbeg = s * kchunk;
+    const int kend = min(K, kbeg + kchunk);
     const cplx<T>* __restrict__ A = pA + b * sA + b2 * sA2;
     const cplx<T>* __restrict__ B = pB + b * sB + b2 * sB2;
     const T sa = p.conjA ? T(-1) : T(1), sb = p.conjB ? T(-1) : T(1);
@@ -224,8 +233,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
                 const int j = n0 + wn * CB * 16 + c * 16 + (lane & 15);
                 if (i < M && j < N) {
                     const T xr = cre[r][c][v], xi = cim[r][c][v];
-                    if (p.splitk > 1) {
-                        p.partial[(((long)s * p.batch + b) * N + j) * M + i] = cplx<T>(xr, xi);
+                    if (splitk > 1) {
+                        partial[(((long)s * nbat + b) * N + j) * M + i] = cplx<T>(xr, xi);
                     } else {
                         T yr = ar * xr - ai * xi, yi = ar * xi + ai * xr;
                         cplx<T>* cp = RC ? &C[(long)i * ldc + j] : &C[i + (long)j * ldc];
@@ -418,6 +427,35 @@ __global__ void splitk_reduce(Params<T> p) {
     }
 }
 
+// The same for every member of a grouped product with splitk > 1 (one member per blockIdx.z).
+template <typename T, bool RC>
+__global__ void splitk_reduce_grouped(Params<T> p) {
+    const GemmGroup& g = p.groups[blockIdx.z];
+    if (g.splitk <= 1) return;
+    const cplx<T>* part = (const cplx<T>*)g.partial;
+    cplx<T>* Cg = (cplx<T>*)g.C;
+    const long total = (long)g.M * g.N * g.batch;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        const int i = t % g.M;
+        const int j = (t / g.M) % g.N;
+        const int b = t / ((long)g.M * g.N);
+        T xr = 0, xi = 0;
+        for (int s = 0; s < g.splitk; ++s) {
+            const cplx<T> v = part[(((long)s * g.batch + b) * g.N + j) * g.M + i];
+            xr += v.re;
+            xi += v.im;
+        }
+        T yr = p.ar * xr - p.ai * xi, yi = p.ar * xi + p.ai * xr;
+        cplx<T>* cp = Cg + b * g.sC + (RC ? (long)i * g.ldc + j : i + (long)j * g.ldc);
+        if (p.br != T(0) || p.bi != T(0)) {
+            const cplx<T> o = *cp;
+            yr += p.br * o.re - p.bi * o.im;
+            yi += p.br * o.im + p.bi * o.re;
+        }
+        *cp = cplx<T>(yr, yi);
+    }
+}
+
 template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC, int KIND = 0>
 void launch_cfg(Params<T> p, hipStream_t st) {
     constexpr int BM = WM * RB * 16, BN = WN * CB * 16;
@@ -446,6 +484,16 @@ void launch_layout(Params<T> p, hipStream_t st) {
 template <typename T>
 int gemm(const GemmOp& op, hipStream_t st) {
     if (op.M <= 0 || op.N <= 0 || op.batch <= 0) return 0;
+    if (OpLog* L = op_log()) {
+        if (!op.groups) {
+            RecOp r;
+            r.kind = REC_GEMM;
+            r.g = op;
+            r.dbl = std::is_same<T, double>::value;
+            L->ops.push_back(std::move(r));
+            return 0;
+        }
+    }
     if (op.splitk > 1 && (op.alpha_b || !op.partial || op.batch2 > 1)) return FEAST_EUNSUPPORTED;
     if (op.batch2 < 1) return 0;
     Params<T> p;
@@ -468,7 +516,7 @@ int gemm(const GemmOp& op, hipStream_t st) {
     p.tiles_m = 1;
     if (op.groups) {
         if (op.ngroups <= 0) return 0;
-        if (p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;
+        if (p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;   // see gemm_grouped
     }
     if (op.kind == 2) {  // LU trailing update on FP16 matrix cores (complex64 storage only)
         if constexpr (std::is_same<T, float>::value) {
@@ -518,7 +566,81 @@ int gemm(const GemmOp& op, hipStream_t st) {
     return 0;
 }
 
+template <typename T>
+GemmGroup gemm_member(const GemmOp& op) {
+    GemmGroup g;
+    g.A = op.A; g.lda = op.lda; g.sA = op.sA; g.sA2 = op.sA2;
+    g.B = op.B; g.ldb = op.ldb; g.sB = op.sB; g.sB2 = op.sB2;
+    g.C = op.C; g.ldc = op.ldc; g.sC = op.sC; g.sC2 = op.sC2;
+    g.M = op.M; g.N = op.N; g.K = op.K; g.batch = op.batch;
+    g.amax = nullptr;
+    g.partial = nullptr;
+    g.splitk = 1;
+    g.kchunk = op.K;
+    if (op.splitk > 1 && op.partial) {
+        // the same partition gemm() takes: slices of depth kchunk (a multiple of the operand tile)
+        g.kchunk = (int)align_up((size_t)ceil_div(op.K, op.splitk), Depth<T>::value);
+        g.splitk = ceil_div(op.K, g.kchunk);
+        g.partial = op.partial;
+        if (g.splitk <= 1) {
+            g.splitk = 1;
+            g.partial = nullptr;
+        }
+    }
+    return g;
+}
+
+template <typename T>
+int gemm_grouped(const GemmOp& proto, const GemmGroup* groups, int ngroups, int max_M, int max_N, int max_K,
+                 int max_batch, int max_splitk, hipStream_t st) {
+    if (ngroups <= 0 || max_M <= 0 || max_N <= 0 || max_batch <= 0) return 0;
+    if (proto.alpha_b || proto.kind != 0 || proto.batch2 != 1) return FEAST_EUNSUPPORTED;
+    Params<T> p;
+    p.A = nullptr; p.lda = 0; p.sA = 0;
+    p.B = nullptr; p.ldb = 0; p.sB = 0;
+    p.C = nullptr; p.ldc = 0; p.sC = 0;
+    p.M = max_M; p.N = max_N; p.K = max_K; p.batch = max_batch;
+    p.batch2 = 1; p.sA2 = p.sB2 = p.sC2 = 0;
+    p.splitk = max_splitk > 1 ? max_splitk : 1;
+    p.kchunk = max_K;
+    p.ar = T(proto.alpha.re); p.ai = T(proto.alpha.im);
+    p.br = T(proto.beta.re); p.bi = T(proto.beta.im);
+    p.alpha_b = nullptr;
+    p.conjA = proto.conjA; p.conjB = proto.conjB;
+    p.partial = nullptr;
+    p.groups = groups;
+    p.ngroups = ngroups;
+    p.amax = nullptr;
+    p.tiles_m = 1;
+    const int code = (proto.rowA ? 4 : 0) | (proto.rowB ? 2 : 0) | (proto.rowC ? 1 : 0);
+    switch (code) {
+        case 0: launch_layout<T, false, false, false>(p, st); break;
+        case 1: launch_layout<T, false, false, true>(p, st); break;
+        case 2: launch_layout<T, false, true, false>(p, st); break;
+        case 3: launch_layout<T, false, true, true>(p, st); break;
+        case 4: launch_layout<T, true, false, false>(p, st); break;
+        case 5: launch_layout<T, true, false, true>(p, st); break;
+        case 6: launch_layout<T, true, true, false>(p, st); break;
+        case 7: launch_layout<T, true, true, true>(p, st); break;
+    }
+    FM_LAUNCH_CHECK();
+    if (p.splitk > 1) {
+        const long total = (long)max_M * max_N * max_batch;
+        const dim3 grid((unsigned)std::min<long>(1024, (total + 255) / 256), 1, ngroups);
+        if (proto.rowC)
+            hipLaunchKernelGGL((splitk_reduce_grouped<T, true>), grid, dim3(256), 0, st, p);
+        else
+            hipLaunchKernelGGL((splitk_reduce_grouped<T, false>), grid, dim3(256), 0, st, p);
+        FM_LAUNCH_CHECK();
+    }
+    return 0;
+}
+
 template int gemm<double>(const GemmOp&, hipStream_t);
 template int gemm<float>(const GemmOp&, hipStream_t);
+template GemmGroup gemm_member<double>(const GemmOp&);
+template GemmGroup gemm_member<float>(const GemmOp&);
+template int gemm_grouped<double>(const GemmOp&, const GemmGroup*, int, int, int, int, int, int, hipStream_t);
+template int gemm_grouped<float>(const GemmOp&, const GemmGroup*, int, int, int, int, int, int, hipStream_t);
 
 }  // namespace fm

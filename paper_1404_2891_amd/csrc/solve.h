@@ -24,6 +24,9 @@ int gather_rows(Rows<T> Y, int n, int ncols, int q, const z64* src, long ld_src,
                 const int* map, long spiv, hipStream_t st, const z64* zs = nullptr, const z64* lam = nullptr,
                 bool conj_scale = false);
 
+// Block steps of one sweep of trsolve for the factorisations in s.
+int trsolve_steps(const LUStore& s);
+
 // Blocked triangular solves with the factorisations in s, batched over the q nodes.
 // side 0: O = U^-1 L^-1 Y (Y already row-permuted by P), side 1: O = L^-H U^-H Y (the caller
 // applies P^T afterwards).  Y is overwritten; X is scratch; all blocks n x ncols.

@@ -4,38 +4,50 @@
 // diagonal block already has its inverse (formed once after the LU), so each block step is two
 // batched MFMA products: the block of the solution (inverse times right-hand side) and the
 // update of the remaining right-hand-side rows.
+#include <algorithm>
+#include <cstring>
+#include <type_traits>
+
 #include "gemm.h"
+#include "record.h"
 #include "solve.h"
 
 namespace fm {
 namespace {
 
+// Argument blocks of the element-wise kernels that have a grouped form (a batch launches one grid
+// over the blocks of all its pencils, blockIdx.z = pencil).
+struct GatherArgs {
+    void* Y; long ldy, sy; int n, ncols;
+    const z64* src; long ld_src, s_src; int src_rows;
+    const int* map; long spiv;
+    const z64* zs; const z64* lam; int conj_scale;
+};
+
 template <typename T>
-__global__ void gather_kernel(cplx<T>* Y, long ldy, long sy, int n, int ncols, const z64* __restrict__ src, long ld_src,
-                              long s_src, int src_rows, const int* __restrict__ map, long spiv,
-                              const z64* __restrict__ zs, const z64* __restrict__ lam, int conj_scale) {
-    const int k = blockIdx.y;
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= (long)n * ncols) return;
-    const int i = t / ncols, j = t % ncols;
-    const int r = map ? map[k * spiv + i] : i;
-    z64 v = src_rows ? src[k * s_src + (long)r * ld_src + j] : src[r + (long)j * ld_src];
-    if (zs) {
-        z64 d = cdiv(z64(1.0, 0.0), zs[k] - lam[j]);
-        if (conj_scale) d = conj(d);
+__device__ inline void gather_body(const GatherArgs& a, long t, int k) {
+    if (t >= (long)a.n * a.ncols) return;
+    const int i = t / a.ncols, j = t % a.ncols;
+    const int r = a.map ? a.map[k * a.spiv + i] : i;
+    z64 v = a.src_rows ? a.src[k * a.s_src + (long)r * a.ld_src + j] : a.src[r + (long)j * a.ld_src];
+    if (a.zs) {
+        z64 d = cdiv(z64(1.0, 0.0), a.zs[k] - a.lam[j]);
+        if (a.conj_scale) d = conj(d);
         v = v * d;
     }
-    Y[k * sy + (long)i * ldy + j] = cplx<T>(v);
+    ((cplx<T>*)a.Y)[k * a.sy + (long)i * a.ldy + j] = cplx<T>(v);
 }
 
-__global__ void residual_block_kernel(z64* E, const z64* __restrict__ AX, const z64* __restrict__ BX, long ld, int n,
-                                      int p, const z64* __restrict__ lam, int conj_lam) {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= (long)n * p) return;
-    const int i = t % n, j = t / n;
-    const long o = i + (long)j * ld;
-    const z64 l = conj_lam ? conj(lam[j]) : lam[j];
-    E[o] = AX[o] - l * BX[o];
+struct ResidualArgs {
+    z64* E; const z64* AX; const z64* BX; long ld; int n, p; const z64* lam; int conj_lam;
+};
+
+__device__ inline void residual_body(const ResidualArgs& a, long t) {
+    if (t >= (long)a.n * a.p) return;
+    const int i = t % a.n, j = t / a.n;
+    const long o = i + (long)j * a.ld;
+    const z64 l = a.conj_lam ? conj(a.lam[j]) : a.lam[j];
+    a.E[o] = a.AX[o] - l * a.BX[o];
 }
 
 template <typename T>
@@ -52,19 +64,22 @@ __global__ void to_f64_kernel(z64* D, long ldd, long sd, const cplx<T>* __restri
     *d = add ? *d + v : v;
 }
 
+struct AccumArgs {
+    z64* Q; long ldq; const void* O; long ldo, so; int n, ncols, q;
+    const int* map; long spiv; const z64* w; const z64* X; long ldx; const z64* xr;
+};
+
 template <typename T>
-__global__ void accumulate_kernel(z64* Q, long ldq, const cplx<T>* __restrict__ O, long ldo, long so, int n, int ncols,
-                                  int q, const int* __restrict__ map, long spiv, const z64* __restrict__ w,
-                                  const z64* __restrict__ X, long ldx, const z64* __restrict__ xr) {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= (long)n * ncols) return;
-    const int i = t / ncols, j = t % ncols;
-    z64 acc = X ? X[i + (long)j * ldx] * xr[j] : z64(0.0, 0.0);
-    for (int k = 0; k < q; ++k) {
-        const int r = map ? map[k * spiv + i] : i;
-        acc = acc + w[k] * z64(O[k * so + (long)r * ldo + j]);
+__device__ inline void accumulate_body(const AccumArgs& a, long t) {
+    if (t >= (long)a.n * a.ncols) return;
+    const cplx<T>* O = (const cplx<T>*)a.O;
+    const int i = t / a.ncols, j = t % a.ncols;
+    z64 acc = a.X ? a.X[i + (long)j * a.ldx] * a.xr[j] : z64(0.0, 0.0);
+    for (int k = 0; k < a.q; ++k) {
+        const int r = a.map ? a.map[k * a.spiv + i] : i;
+        acc = acc + a.w[k] * z64(O[k * a.so + (long)r * a.ldo + j]);
     }
-    Q[i + (long)j * ldq] = acc;
+    a.Q[i + (long)j * a.ldq] = acc;
 }
 
 __global__ void broadcast_kernel(z64* R, long ldr, long sr, const z64* __restrict__ src, long ld, int n, int ncols) {
@@ -151,18 +166,21 @@ __global__ __launch_bounds__(256) void colmax_kernel(const double* __restrict__ 
     if (threadIdx.x == 0) norm1[k] = m;
 }
 
-__global__ __launch_bounds__(256) void ritz_kernel(const z64* __restrict__ X, const z64* __restrict__ AX,
-                                                   const z64* __restrict__ BX, long ld, int n, int p,
-                                                   const z64* __restrict__ lam, double* out) {
+struct RitzArgs {
+    const z64* X; const z64* AX; const z64* BX; long ld; int n, p; const z64* lam; double* out;
+};
+
+// column j's residual, B-norm and norm: one workgroup of 256 threads per column
+__device__ inline void ritz_body(const RitzArgs& a, int j) {
     __shared__ double sh[4];
-    const int j = blockIdx.x;
-    const z64 l = lam[j];
+    if (j >= a.p) return;   // uniform over the workgroup
+    const z64 l = a.lam[j];
     double r = 0.0, b = 0.0, x = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const long o = i + (long)j * ld;
-        const z64 bx = BX[o];
-        const z64 d = AX[o] - l * bx;
-        const z64 xv = X[o];
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
+        const long o = i + (long)j * a.ld;
+        const z64 bx = a.BX[o];
+        const z64 d = a.AX[o] - l * bx;
+        const z64 xv = a.X[o];
         r += d.re * d.re + d.im * d.im;
         b += bx.re * bx.re + bx.im * bx.im;
         x += xv.re * xv.re + xv.im * xv.im;
@@ -171,17 +189,82 @@ __global__ __launch_bounds__(256) void ritz_kernel(const z64* __restrict__ X, co
     b = block_sum(b, sh);
     x = block_sum(x, sh);
     if (threadIdx.x == 0) {
-        out[j] = sqrt(r);
-        out[p + j] = sqrt(b);
-        out[2 * p + j] = sqrt(x);
+        a.out[j] = sqrt(r);
+        a.out[a.p + j] = sqrt(b);
+        a.out[2 * a.p + j] = sqrt(x);
     }
 }
 
-__global__ void copy_cm_kernel(z64* dst, long ldd, const z64* __restrict__ src, long lds, int n, int ncols) {
+struct CopyArgs {
+    z64* dst; long ldd; const z64* src; long lds; int n, ncols;
+};
+
+__device__ inline void copy_body(const CopyArgs& a, long t) {
+    if (t >= (long)a.n * a.ncols) return;
+    const int i = t % a.n, j = t / a.n;
+    a.dst[i + (long)j * a.ldd] = a.src[i + (long)j * a.lds];
+}
+
+// One kernel per element-wise operation: the direct launch takes the argument block by value, the
+// grouped launch reads block blockIdx.z of a device table.
+template <int EW>
+__device__ inline void ew_dispatch(const void* args) {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= (long)n * ncols) return;
-    const int i = t % n, j = t / n;
-    dst[i + (long)j * ldd] = src[i + (long)j * lds];
+    if constexpr (EW == EW_GATHER_F32) gather_body<float>(*(const GatherArgs*)args, t, blockIdx.y);
+    if constexpr (EW == EW_GATHER_F64) gather_body<double>(*(const GatherArgs*)args, t, blockIdx.y);
+    if constexpr (EW == EW_ACCUM_F32) accumulate_body<float>(*(const AccumArgs*)args, t);
+    if constexpr (EW == EW_ACCUM_F64) accumulate_body<double>(*(const AccumArgs*)args, t);
+    if constexpr (EW == EW_RESIDUAL) residual_body(*(const ResidualArgs*)args, t);
+    if constexpr (EW == EW_COPY_CM) copy_body(*(const CopyArgs*)args, t);
+    if constexpr (EW == EW_RITZ) ritz_body(*(const RitzArgs*)args, blockIdx.x);
+}
+
+template <int EW, typename A>
+__global__ __launch_bounds__(256) void ew_kernel(A a) {
+    ew_dispatch<EW>(&a);
+}
+
+template <int EW, typename A>
+__global__ __launch_bounds__(256) void ew_grouped_kernel(const A* __restrict__ tab) {
+    ew_dispatch<EW>(&tab[blockIdx.z]);
+}
+
+template <int EW> struct EwArgs;
+template <> struct EwArgs<EW_GATHER_F32> { typedef GatherArgs type; };
+template <> struct EwArgs<EW_GATHER_F64> { typedef GatherArgs type; };
+template <> struct EwArgs<EW_ACCUM_F32> { typedef AccumArgs type; };
+template <> struct EwArgs<EW_ACCUM_F64> { typedef AccumArgs type; };
+template <> struct EwArgs<EW_RESIDUAL> { typedef ResidualArgs type; };
+template <> struct EwArgs<EW_COPY_CM> { typedef CopyArgs type; };
+template <> struct EwArgs<EW_RITZ> { typedef RitzArgs type; };
+
+// Enqueue (or record) element-wise kernel EW over a grid of bx x by workgroups of 256 threads.
+template <int EW>
+int ew_launch(const typename EwArgs<EW>::type& a, unsigned bx, unsigned by, hipStream_t st) {
+    typedef typename EwArgs<EW>::type A;
+    static_assert(sizeof(A) <= EW_ARG_BYTES, "argument block too large");
+    if (bx == 0 || by == 0) return 0;
+    if (OpLog* L = op_log()) {
+        RecOp r;
+        r.kind = REC_EW;
+        r.ew = EW;
+        memcpy(r.args, &a, sizeof(A));
+        r.bx = bx;
+        r.by = by;
+        L->ops.push_back(std::move(r));
+        return 0;
+    }
+    hipLaunchKernelGGL((ew_kernel<EW, A>), dim3(bx, by), dim3(256), 0, st, a);
+    FM_LAUNCH_CHECK();
+    return 0;
+}
+
+template <int EW>
+int ew_grouped_one(const void* table, int ngroups, unsigned bx, unsigned by, hipStream_t st) {
+    typedef typename EwArgs<EW>::type A;
+    hipLaunchKernelGGL((ew_grouped_kernel<EW, A>), dim3(bx, by, ngroups), dim3(256), 0, st, (const A*)table);
+    FM_LAUNCH_CHECK();
+    return 0;
 }
 
 __global__ void combine_cm_kernel(z64* dst, long ldd, const z64* __restrict__ src, long lds, int n, int ncols,
@@ -220,10 +303,14 @@ inline dim3 grid1(long count, int q = 1) { return dim3((unsigned)((count + 255) 
 template <typename T>
 int gather_rows(Rows<T> Y, int n, int ncols, int q, const z64* src, long ld_src, long s_src, bool src_rows,
                 const int* map, long spiv, hipStream_t st, const z64* zs, const z64* lam, bool conj_scale) {
-    hipLaunchKernelGGL((gather_kernel<T>), grid1((long)n * ncols, q), dim3(256), 0, st, Y.p, Y.ld, Y.s, n, ncols, src,
-                       ld_src, s_src, (int)src_rows, map, spiv, zs, lam, (int)conj_scale);
-    FM_LAUNCH_CHECK();
-    return 0;
+    GatherArgs a{Y.p, Y.ld, Y.s, n, ncols, src, ld_src, s_src, (int)src_rows, map, spiv, zs, lam, (int)conj_scale};
+    const dim3 g = grid1((long)n * ncols, q);
+    return ew_launch<std::is_same<T, double>::value ? EW_GATHER_F64 : EW_GATHER_F32>(a, g.x, g.y, st);
+}
+
+int trsolve_steps(const LUStore& s) {
+    const bool big = s.LinvS && s.UinvS && s.nbs > s.nb;
+    return big ? s.nsbs : s.nsteps;
 }
 
 template <typename T>
@@ -231,6 +318,9 @@ int trsolve(const LUStore& s, int side, int ncols, Rows<T> Y, Rows<T> X, Rows<T>
     // block size of the sweeps: the composed solve blocks when present, else the LU blocks
     const bool big = s.LinvS && s.UinvS && s.nbs > s.nb;
     const int n = s.n, nb = big ? s.nbs : s.nb, q = s.q, nsteps = big ? s.nsbs : s.nsteps;
+    // recorded for a batch: empty steps up to the batch's largest count (two products per step)
+    OpLog* L = op_log();
+    const int pad = L ? std::max(0, L->pad_steps - nsteps) : 0;
     const cplx<T>* F = (const cplx<T>*)s.F;
     const cplx<T>* Linv = (const cplx<T>*)(big ? s.LinvS : s.Linv);
     const cplx<T>* Uinv = (const cplx<T>*)(big ? s.UinvS : s.Uinv);
@@ -259,8 +349,11 @@ int trsolve(const LUStore& s, int side, int ncols, Rows<T> Y, Rows<T> X, Rows<T>
             base(g2, X.at_row(j0), Y.at_row(j0 + w));
             g2.M = nr; g2.K = w; g2.alpha = z64(-1.0); g2.beta = z64(1.0);
             FM_TRY(gemm<T>(g2, st));
+        } else if (L) {
+            L->nop();
         }
     }
+    for (int i = 0; i < 2 * pad; ++i) L->nop();
     // backward sweep: U (side 0) or L^H (side 1), upper triangular
     for (int step = nsteps - 1; step >= 0; --step) {
         const int j0 = step * nb, w = std::min(nb, n - j0);
@@ -278,14 +371,21 @@ int trsolve(const LUStore& s, int side, int ncols, Rows<T> Y, Rows<T> X, Rows<T>
             base(g4, O.at_row(j0), X.at_row(0));
             g4.M = j0; g4.K = w; g4.alpha = z64(-1.0); g4.beta = z64(1.0);
             FM_TRY(gemm<T>(g4, st));
+        } else if (L) {
+            L->nop();
         }
     }
+    for (int i = 0; i < 2 * pad; ++i) L->nop();
     return 0;
 }
 
 template <typename T>
 int rows_to_f64(Rows<double> D, const Rows<T>& O, int n, int ncols, int q, const int* map, long spiv, bool add,
                 const int* mask, hipStream_t st) {
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return rows_to_f64<T>(D, O, n, ncols, q, map, spiv, add, mask, s); });
+        return 0;
+    }
     hipLaunchKernelGGL((to_f64_kernel<T>), grid1((long)n * ncols, q), dim3(256), 0, st, (z64*)D.p, D.ld, D.s,
                        (const cplx<T>*)O.p, O.ld, O.s, n, ncols, map, spiv, (int)add, mask);
     FM_LAUNCH_CHECK();
@@ -295,21 +395,22 @@ int rows_to_f64(Rows<double> D, const Rows<T>& O, int n, int ncols, int q, const
 template <typename T>
 int accumulate(z64* Q, long ldq, const Rows<T>& O, int n, int ncols, int q, const int* map, long spiv, const z64* w,
                hipStream_t st, const z64* X, long ldx, const z64* r) {
-    hipLaunchKernelGGL((accumulate_kernel<T>), grid1((long)n * ncols), dim3(256), 0, st, Q, ldq, (const cplx<T>*)O.p,
-                       O.ld, O.s, n, ncols, q, map, spiv, w, X, ldx, r);
-    FM_LAUNCH_CHECK();
-    return 0;
+    AccumArgs a{Q, ldq, O.p, O.ld, O.s, n, ncols, q, map, spiv, w, X, ldx, r};
+    const dim3 g = grid1((long)n * ncols);
+    return ew_launch<std::is_same<T, double>::value ? EW_ACCUM_F64 : EW_ACCUM_F32>(a, g.x, 1, st);
 }
 
 int residual_block(z64* E, const z64* AX, const z64* BX, long ld, int n, int p, const z64* lam, bool conj_lam,
                    hipStream_t st) {
-    hipLaunchKernelGGL(residual_block_kernel, grid1((long)n * p), dim3(256), 0, st, E, AX, BX, ld, n, p, lam,
-                       (int)conj_lam);
-    FM_LAUNCH_CHECK();
-    return 0;
+    ResidualArgs a{E, AX, BX, ld, n, p, lam, (int)conj_lam};
+    return ew_launch<EW_RESIDUAL>(a, grid1((long)n * p).x, 1, st);
 }
 
 int broadcast_rows(Rows<double> R, const z64* src, long ld, int n, int ncols, int q, hipStream_t st) {
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return broadcast_rows(R, src, ld, n, ncols, q, s); });
+        return 0;
+    }
     hipLaunchKernelGGL(broadcast_kernel, grid1((long)n * ncols, q), dim3(256), 0, st, (z64*)R.p, R.ld, R.s, src, ld, n,
                        ncols);
     FM_LAUNCH_CHECK();
@@ -318,12 +419,20 @@ int broadcast_rows(Rows<double> R, const z64* src, long ld, int n, int ncols, in
 
 template <typename T>
 int fro_norms(const Rows<T>& Y, int n, int ncols, int q, double* out, hipStream_t st) {
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return fro_norms<T>(Y, n, ncols, q, out, s); });
+        return 0;
+    }
     hipLaunchKernelGGL((fro_rows_kernel<T>), dim3(q), dim3(256), 0, st, (const cplx<T>*)Y.p, Y.ld, Y.s, n, ncols, out);
     FM_LAUNCH_CHECK();
     return 0;
 }
 
 int fro_norm_cm(const z64* M, long ld, int n, int ncols, double* out, hipStream_t st) {
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return fro_norm_cm(M, ld, n, ncols, out, s); });
+        return 0;
+    }
     hipLaunchKernelGGL(fro_cm_kernel, dim3(1), dim3(1024), 0, st, M, ld, n, ncols, out);
     FM_LAUNCH_CHECK();
     return 0;
@@ -331,6 +440,10 @@ int fro_norm_cm(const z64* M, long ld, int n, int ncols, double* out, hipStream_
 
 int node_norm1(const z64* A, long lda, const z64* B, long ldb, int n, const z64* z, int q, double* colsum,
                double* norm1, hipStream_t st) {
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return node_norm1(A, lda, B, ldb, n, z, q, colsum, norm1, s); });
+        return 0;
+    }
     hipLaunchKernelGGL(colsum_kernel, dim3(n), dim3(256), 0, st, A, lda, B, ldb, n, z, q, colsum);
     FM_LAUNCH_CHECK();
     hipLaunchKernelGGL(colmax_kernel, dim3(q), dim3(256), 0, st, (const double*)colsum, n, norm1);
@@ -340,12 +453,15 @@ int node_norm1(const z64* A, long lda, const z64* B, long ldb, int n, const z64*
 
 int ritz_residual_norms(const z64* X, const z64* AX, const z64* BX, long ld, int n, int p, const z64* lam, double* out,
                         hipStream_t st) {
-    hipLaunchKernelGGL(ritz_kernel, dim3(p), dim3(256), 0, st, X, AX, BX, ld, n, p, lam, out);
-    FM_LAUNCH_CHECK();
-    return 0;
+    RitzArgs a{X, AX, BX, ld, n, p, lam, out};
+    return ew_launch<EW_RITZ>(a, (unsigned)p, 1, st);
 }
 
 int axpy_rows(Rows<double> R, const Rows<double>& Y, const z64* alpha, int n, int ncols, int q, hipStream_t st) {
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return axpy_rows(R, Y, alpha, n, ncols, q, s); });
+        return 0;
+    }
     hipLaunchKernelGGL(axpy_rows_kernel, grid1((long)n * ncols, q), dim3(256), 0, st, (z64*)R.p, R.ld, R.s,
                        (const z64*)Y.p, Y.ld, Y.s, alpha, n, ncols);
     FM_LAUNCH_CHECK();
@@ -353,24 +469,56 @@ int axpy_rows(Rows<double> R, const Rows<double>& Y, const z64* alpha, int n, in
 }
 
 int gather_cols(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, const int* idx, hipStream_t st) {
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return gather_cols(dst, ldd, src, lds, n, ncols, idx, s); });
+        return 0;
+    }
     hipLaunchKernelGGL(gather_cols_kernel, grid1((long)n * ncols), dim3(256), 0, st, dst, ldd, src, lds, n, ncols, idx);
     FM_LAUNCH_CHECK();
     return 0;
 }
 
 int copy_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, hipStream_t st) {
-    hipLaunchKernelGGL(copy_cm_kernel, grid1((long)n * ncols), dim3(256), 0, st, dst, ldd, src, lds, n, ncols);
-    FM_LAUNCH_CHECK();
-    return 0;
+    CopyArgs a{dst, ldd, src, lds, n, ncols};
+    return ew_launch<EW_COPY_CM>(a, grid1((long)n * ncols).x, 1, st);
 }
 
 int combine_cm(z64* dst, long ldd, const z64* src, long lds, int n, int ncols, bool conj_src, bool add,
                hipStream_t st) {
     if ((long)n * ncols == 0) return 0;
+    if (OpLog* L = op_log()) {
+        L->other([=](hipStream_t s) { return combine_cm(dst, ldd, src, lds, n, ncols, conj_src, add, s); });
+        return 0;
+    }
     hipLaunchKernelGGL(combine_cm_kernel, grid1((long)n * ncols), dim3(256), 0, st, dst, ldd, src, lds, n, ncols,
                        conj_src, add);
     FM_LAUNCH_CHECK();
     return 0;
+}
+
+size_t ew_arg_size(int ew) {
+    switch (ew) {
+        case EW_GATHER_F32: case EW_GATHER_F64: return sizeof(GatherArgs);
+        case EW_ACCUM_F32: case EW_ACCUM_F64: return sizeof(AccumArgs);
+        case EW_RESIDUAL: return sizeof(ResidualArgs);
+        case EW_COPY_CM: return sizeof(CopyArgs);
+        case EW_RITZ: return sizeof(RitzArgs);
+    }
+    return 0;
+}
+
+int ew_grouped(int ew, const void* table, int ngroups, unsigned max_bx, unsigned max_by, hipStream_t st) {
+    if (ngroups <= 0 || max_bx == 0 || max_by == 0) return 0;
+    switch (ew) {
+        case EW_GATHER_F32: return ew_grouped_one<EW_GATHER_F32>(table, ngroups, max_bx, max_by, st);
+        case EW_GATHER_F64: return ew_grouped_one<EW_GATHER_F64>(table, ngroups, max_bx, max_by, st);
+        case EW_ACCUM_F32: return ew_grouped_one<EW_ACCUM_F32>(table, ngroups, max_bx, max_by, st);
+        case EW_ACCUM_F64: return ew_grouped_one<EW_ACCUM_F64>(table, ngroups, max_bx, max_by, st);
+        case EW_RESIDUAL: return ew_grouped_one<EW_RESIDUAL>(table, ngroups, max_bx, max_by, st);
+        case EW_COPY_CM: return ew_grouped_one<EW_COPY_CM>(table, ngroups, max_bx, max_by, st);
+        case EW_RITZ: return ew_grouped_one<EW_RITZ>(table, ngroups, max_bx, max_by, st);
+    }
+    return FEAST_EUNSUPPORTED;
 }
 
 #define FM_INST(T)                                                                                                  \

@@ -4,14 +4,17 @@
 #include <vector>
 
 #include "common.h"
+#include "record.h"
 
 namespace fm {
 
 enum Phase {
     PH_LU_UPDATE = 0, PH_LU_PANEL = 1, PH_LU_OTHER = 2, PH_SOLVE = 3, PH_REFINE = 4, PH_RR = 5,
-    PH_HOST_REDUCED = 6,   // host: reduced eigenproblem (wall time, includes its transfers)
-    PH_HOST_ORTHO = 7,     // host + device: orthonormalisation passes (wall time)
-    PH_COUNT = 8
+    PH_HOST_REDUCED = 6,   // host wall time: reduced eigenproblems
+    PH_HOST_ORTHO = 7,     // host wall time: Cholesky factorisations of the orthonormalisation
+    PH_HOST_DRIVER = 8,    // host wall time: enqueueing the device phases, convergence bookkeeping
+    PH_HOST_WAIT = 9,      // host wall time: waiting at the iteration's synchronisation points
+    PH_COUNT = 10
 };
 inline bool is_host_phase(int p) { return p >= PH_HOST_REDUCED; }
 
@@ -34,13 +37,25 @@ struct Timer {
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         return e;
     }
+    // while device work is recorded (record.h) the marks are recorded with it
+    void mark(Phase p, bool is_start, double fl) {
+        RecOp r;
+        r.kind = REC_MARK;
+        r.phase = p;
+        r.start = is_start;
+        r.flops = fl;
+        op_log()->ops.push_back(std::move(r));
+    }
     void start(Phase p, hipStream_t st) {
         if (!on) return;
+        if (op_log()) return mark(p, true, 0.0);
         cur_a[p] = get();
         if (cur_a[p]) (void)hipEventRecord(cur_a[p], st);
     }
     void stop(Phase p, hipStream_t st, double fl) {
-        if (!on || !cur_a[p]) return;
+        if (!on) return;
+        if (op_log()) return mark(p, false, fl);
+        if (!cur_a[p]) return;
         hipEvent_t b = get();
         if (!b) return;
         (void)hipEventRecord(b, st);
