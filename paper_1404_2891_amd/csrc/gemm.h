@@ -26,7 +26,9 @@ struct GemmGroup {
 // when conjA; likewise (k, j) of op(B) is B[k*ldb + j] when rowB, else B[k + j*ldb];
 // and C(i, j) is C[i*ldc + j] when rowC, else C[i + j*ldc].  Strides step between
 // batch entries (0 shares an operand).  alpha_b, when set, is a device array of
-// batch complex doubles used instead of alpha.  A and C must not overlap.
+// batch complex doubles used instead of alpha.  A and C must not overlap, except
+// with `inplace` (C is A itself, N <= 64: every workgroup owns whole rows of C
+// and reads them before it writes them).
 struct GemmOp {
     const void* A = nullptr; long lda = 0; long sA = 0; bool rowA = false; bool conjA = false;
     const void* B = nullptr; long ldb = 0; long sB = 0; bool rowB = false; bool conjB = false;
@@ -56,6 +58,7 @@ struct GemmOp {
     // alpha_b == nullptr.
     const GemmGroup* groups = nullptr;
     int ngroups = 0;
+    bool inplace = false;
 };
 
 // T = double (complex128 operands, FP64 MFMA) or float (complex64, FP32 MFMA).

@@ -542,6 +542,12 @@ int gemm(const GemmOp& op, hipStream_t st) {
         FM_LAUNCH_CHECK();
         return 0;
     }
+    if (op.inplace) {  // C = A op(B) in place: 64 x 64 tiles cover whole rows of C
+        if (!(op.rowA && op.rowB && op.rowC) || p.N > 64 || p.splitk > 1) return FEAST_EUNSUPPORTED;
+        launch_cfg<T, 2, 2, 2, 2, true, true, true>(p, st);
+        FM_LAUNCH_CHECK();
+        return 0;
+    }
     const int code = (op.rowA ? 4 : 0) | (op.rowB ? 2 : 0) | (op.rowC ? 1 : 0);
     switch (code) {
         case 0: launch_layout<T, false, false, false>(p, st); break;

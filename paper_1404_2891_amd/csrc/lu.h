@@ -54,7 +54,11 @@ struct LUStore {
 
 // Leaf blocks of the tournament for panels of up to n rows (256 rows per leaf in both precisions).
 inline int tslu_leaf_blocks(int n, bool dbl) { (void)dbl; return (n + 255) / 256; }
-inline size_t tslu_cand_ints(int n, int q, bool dbl) { return (size_t)q * (2 * (size_t)tslu_leaf_blocks(n, dbl) * 64 + 64); }
+// Per node: two levels of candidate lists (tW0 * 64 each), the 64 winners, then the panel step's row
+// permutation as tslu_apply leaves it for the swaps of the other columns: the count of touched
+// rows and up to 128 (position, original row) pairs.
+__host__ __device__ inline long tslu_node_ints(int tW0) { return 2L * tW0 * 64 + 64 + 1 + 2 * 128; }
+inline size_t tslu_cand_ints(int n, int q, bool dbl) { return (size_t)q * tslu_node_ints(tslu_leaf_blocks(n, dbl)); }
 
 // Elements of the LU staging buffer per node: the panel swaps need nb * n, the composition of the
 // solve-block inverses 128 * 128 per solve block.

@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256) void tslu_apply_kernel(const LUDev* __restrict
     const int k = blockIdx.x, tid = threadIdx.x;
     const long ldf = d.ldf;
     cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
-    const int* fin = d.tcand + (long)k * (2L * d.tW0 * 64 + 64) + 2L * d.tW0 * 64;
+    int* fin = d.tcand + (long)k * tslu_node_ints(d.tW0) + 2L * d.tW0 * 64;
     int* ipiv = d.ipiv + k * d.spiv;
     __shared__ int pos[128], content[128], piv[64];
     __shared__ int cnt_s;
@@ -456,6 +456,13 @@ __global__ __launch_bounds__(256) void tslu_apply_kernel(const LUDev* __restrict
         if (tid + 64 < cnt) content[tid + 64] = c1;
     }
     __syncthreads();
+    // the permutation, for the interchanges of the other columns (swap_perm_kernel)
+    int* perm_out = fin + 64;
+    if (tid == 0) perm_out[0] = cnt;
+    if (tid < 128) {
+        perm_out[1 + tid] = tid < cnt ? pos[tid] : -1;
+        perm_out[129 + tid] = tid < cnt ? content[tid] : -1;
+    }
     // rows displaced below the panel's first w rows: final content of position pos[t] (t >= w) is
     // the original row content[t] (the panel itself is still unmodified)
     const int nd = cnt - w;
@@ -476,60 +483,11 @@ __global__ __launch_bounds__(256) void tslu_apply_kernel(const LUDev* __restrict
     if (tid < w) ipiv[j0 + tid] = piv[tid];
 }
 
-// L21 = A21 U11^-1 in place for the rows below the panel's first w rows: 64 rows per workgroup,
-// both operands in LDS (every row read before any is written), 4 x 4 outputs per thread.
-template <typename T>
-__global__ __launch_bounds__(256) void tslu_l21_kernel(const LUDev* __restrict__ dv, int j0, int nb, int step,
-                                                       int single) {
-    const LUDev& d = dv[blockIdx.z];
-    const int w = step_width(d, j0, nb);
-    if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
-    const int k = blockIdx.y, n = d.n;
-    const int r0 = j0 + w + blockIdx.x * 64;
-    if (r0 >= n) return;
-    const int nr = min(64, n - r0);
-    const long ldf = d.ldf;
-    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
-    const cplx<T>* Ui = (const cplx<T>*)d.Uinv + ((long)k * d.nsteps + step) * nb * nb;
-    __shared__ cplx<T> Us[64][65];
-    __shared__ cplx<T> As[64][65];
-    const cplx<T> zero(T(0), T(0));
-    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-        const int i = e >> 6, c = e & 63;
-        Us[i][c] = (i < w && c < w) ? Ui[(long)i * nb + c] : zero;
-        As[i][c] = (i < nr && c < w) ? F[(long)(r0 + i) * ldf + j0 + c] : zero;
-    }
-    __syncthreads();
-    const int ti = threadIdx.x >> 4, tc = threadIdx.x & 15;
-    cplx<T> acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[i][m] = zero;
-    for (int kk = 0; kk < w; ++kk) {
-        cplx<T> av[4], uv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = As[4 * ti + i][kk];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) uv[m] = Us[kk][tc + 16 * m];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) acc[i][m] = acc[i][m] + av[i] * uv[m];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int r = 4 * ti + i, c = tc + 16 * m;
-            if (r < nr && c < w) F[(long)(r0 + r) * ldf + j0 + c] = acc[i][m];
-        }
-}
-
 // Row interchanges of step (j0, w) applied to the columns outside the panel, and to the panel's own
 // columns for the interchanges that came after each column was finished (the panel kernels only
 // swap the columns still active); the swapped rows j0..j0+w-1 of the columns right of the panel
-// are copied to tmp (row-major, ld n).  A tournament panel is written fully permuted already.
+// are copied to tmp (row-major, ld n).  Partial-pivoting panels only (tournament panels:
+// swap_perm_kernel).
 template <typename T>
 __global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv, int j0, int nb, int single) {
     const LUDev& d = dv[blockIdx.z];
@@ -537,8 +495,8 @@ __global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv,
     const int k = blockIdx.y, n = d.n;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (w == 0 || c >= n) return;
+    if (member_variant<T>(d, j0, single) == PV_TSLU) return;
     const bool in_panel = c >= j0 && c < j0 + w;
-    if (in_panel && member_variant<T>(d, j0, single) == PV_TSLU) return;
     const long ldf = d.ldf;
     cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
     const int* ipiv = d.ipiv + k * d.spiv;
@@ -554,6 +512,79 @@ __global__ __launch_bounds__(256) void swap_kernel(const LUDev* __restrict__ dv,
     if (c >= j0 + w) {
         cplx<T>* tmp = (cplx<T>*)d.tmp + k * d.stmp;
         for (int j = 0; j < w; ++j) tmp[(long)j * n + (c - j0 - w)] = F[(long)(j0 + j) * ldf + c];
+    }
+}
+
+// The same for a tournament panel, whose step permutes at most 128 rows: position pos[t] receives
+// original row content[t] (tslu_apply_kernel); the panel's own columns are already in place.  All
+// rows of a column are read before any is written, so the reads are independent: a workgroup of
+// eight waves takes SWAP_COLS columns (16 bytes of every row per lane), each wave an eighth of the
+// touched rows (in registers across one barrier); the final rows j0..j0+w-1 (t < w) right of the
+// panel also go to tmp.
+constexpr int SWAP_WAVES = 8;
+template <typename T> struct SwapCols { static constexpr int per_lane = 16 / sizeof(cplx<T>), value = 64 * per_lane; };
+
+template <typename T>
+__global__ __launch_bounds__(64 * SWAP_WAVES) void swap_perm_kernel(const LUDev* __restrict__ dv, int j0, int nb,
+                                                                    int single) {
+    constexpr int CL = SwapCols<T>::per_lane, PER = 128 / SWAP_WAVES;
+    const LUDev& d = dv[blockIdx.z];
+    const int w = step_width(d, j0, nb);
+    if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
+    const int k = blockIdx.y, n = d.n;
+    const int c0 = blockIdx.x * SwapCols<T>::value;
+    if (c0 >= n) return;
+    __shared__ int sp[257];
+    const int* perm = d.tcand + (long)k * tslu_node_ints(d.tW0) + 2L * d.tW0 * 64 + 64;
+    for (int e = threadIdx.x; e < 257; e += blockDim.x) sp[e] = perm[e];
+    __syncthreads();
+    const int cnt = sp[0];
+    const int g = threadIdx.x >> 6;
+    const int c = c0 + (threadIdx.x & 63) * CL;   // first of this lane's CL columns
+    // the lane's columns: all outside the panel (the panel starts at a multiple of 64 and CL divides 64)
+    const bool col = c < n && (c < j0 || c >= j0 + w);
+    const bool whole = c + CL <= n;
+    const long ldf = d.ldf;
+    cplx<T>* F = (cplx<T>*)d.F + k * d.sF;
+    cplx<T> v[PER][CL];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int t = g + SWAP_WAVES * i;
+        const cplx<T>* src = F + (long)sp[129 + min(t, 127)] * ldf + c;
+        if (col && t < cnt && whole) {
+            if constexpr (CL == 2) {
+                const float4 x = *(const float4*)src;
+                v[i][0] = cplx<T>(x.x, x.y);
+                v[i][1] = cplx<T>(x.z, x.w);
+            } else {
+                v[i][0] = src[0];
+            }
+        } else {   // outside the columns, or the last column of an odd order
+#pragma unroll
+            for (int u = 0; u < CL; ++u) v[i][u] = (col && t < cnt && c + u < n) ? src[u] : cplx<T>(T(0), T(0));
+        }
+    }
+    __syncthreads();
+    cplx<T>* tmp = (cplx<T>*)d.tmp + k * d.stmp;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int t = g + SWAP_WAVES * i;
+        if (!col || t >= cnt) continue;
+        cplx<T>* dst = F + (long)sp[1 + t] * ldf + c;
+        if constexpr (CL == 2) {
+            if (whole) {
+                *(float4*)dst = make_float4(v[i][0].re, v[i][0].im, v[i][1].re, v[i][1].im);
+            } else {
+                dst[0] = v[i][0];   // c < n; c + 1 == n
+            }
+        } else {
+            dst[0] = v[i][0];
+        }
+        if (t < w && c >= j0 + w) {
+#pragma unroll
+            for (int u = 0; u < CL; ++u)
+                if (c + u < n) tmp[(long)t * n + (c + u - j0 - w)] = v[i][u];
+        }
     }
 }
 
@@ -770,8 +801,24 @@ GemmGroup member(const void* A, long lda, long sA, long sA2, const void* B, long
 // the multi-workgroup panel.
 template <typename T>
 int panel(SetRun<T>& R, int j0) {
-    if (!R.launching()) return 0;
     const LUSet& S = R.S;
+    // L21 = A21 U11^-1 of the tournament panels, in place on the matrix cores (recorded in the plan)
+    std::vector<GemmGroup> l21;
+    for (int b = 0; b < S.count; ++b) {
+        const LUStore& s = S.s[b];
+        // (s.tslu alone: the dry run that counts the plan's entries has no candidate lists yet)
+        if (panel_variant<T>(s.n, j0, s.pslots != nullptr, S.single_rows, s.tslu) != PV_TSLU) continue;
+        const int w = std::min(R.nb, s.n - j0), below = s.n - j0 - w;
+        if (below <= 0) continue;
+        cplx<T>* A21 = (cplx<T>*)s.F + (long)(j0 + w) * s.ldf + j0;
+        const cplx<T>* Ui = (const cplx<T>*)s.Uinv + (long)(j0 / R.nb) * R.nb * R.nb;
+        l21.push_back(member(A21, s.ldf, s.sF, 0, Ui, R.nb, (long)s.nsteps * R.nb * R.nb, 0, A21, s.ldf, s.sF, 0,
+                             below, w, w, R.q));
+    }
+    GemmOp l21op;
+    l21op.rowA = l21op.rowB = l21op.rowC = true;
+    l21op.inplace = true;
+    if (!R.launching()) return R.grouped(l21, l21op);
     bool reg = false, single = false;
     int wmax = -1, Wmax = 0;
     constexpr int TR = TSLU_ROWS, TG = TR / 64;
@@ -822,13 +869,9 @@ int panel(SetRun<T>& R, int j0) {
         // U11^-1 of this step (members without a tournament here recompute a finished block)
         hipLaunchKernelGGL((trtri_kernel<T, true>), dim3(1, R.q, S.count), dim3(1024), 0, R.st, S.dev, R.nb, j0 / R.nb);
         FM_LAUNCH_CHECK();
-        if (below > 0) {
-            hipLaunchKernelGGL((tslu_l21_kernel<T>), dim3(ceil_div(below, 64), R.q, S.count), dim3(256), 0, R.st,
-                               S.dev, j0, R.nb, j0 / R.nb, S.single_rows);
-            FM_LAUNCH_CHECK();
-        }
     }
-    return 0;
+    (void)below;
+    return R.grouped(l21, l21op);
 }
 
 // Inverses of the nbs x nbs diagonal blocks of L and U of every member, by recursive doubling from
@@ -964,6 +1007,9 @@ int run_set(SetRun<T>& R) {
             // interchanges first: the diagonal block's L part takes its deferred interchanges here
             hipLaunchKernelGGL((swap_kernel<T>), dim3(ceil_div(swap_cols, 256), q, P), dim3(256), 0, R.st, S.dev, j0,
                                nb, S.single_rows);
+            FM_LAUNCH_CHECK();
+            hipLaunchKernelGGL((swap_perm_kernel<T>), dim3(ceil_div(swap_cols, SwapCols<T>::value), q, P),
+                               dim3(64 * SWAP_WAVES), 0, R.st, S.dev, j0, nb, S.single_rows);
             FM_LAUNCH_CHECK();
             hipLaunchKernelGGL((trtri_kernel<T, false>), dim3(1, q, P), dim3(1024), 0, R.st, S.dev, nb, step);
             FM_LAUNCH_CHECK();

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv,
     const int Win = level > 0 ? tslu_width(rows, R, G, level - 1) : 0;
     const long ldf = d.ldf;
     const cplx<T>* F = (const cplx<T>*)d.F + k * d.sF;
-    int* cl = d.tcand + (long)k * (2L * d.tW0 * 64 + 64);
+    int* cl = d.tcand + (long)k * tslu_node_ints(d.tW0);
     const int* in = cl + (long)((level - 1) & 1) * d.tW0 * 64;
     int* out = root ? cl + 2L * d.tW0 * 64 : cl + (long)(level & 1) * d.tW0 * 64;
     cplx<T>* top = (cplx<T>*)d.ttop + (long)k * nb * nb;
