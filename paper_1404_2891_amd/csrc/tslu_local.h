@@ -6,9 +6,15 @@
 //
 // Each row lives in the registers of one lane (all 64 columns).  The column steps are generated
 // by template recursion, so every column index is a constant: register indices and the bounds of
-// the rank-1 update are static, with no per-column branches.  One workgroup barrier per column:
-// each wave reduces its best row to one key, the wave's best row publishes itself in LDS at once,
-// and after the barrier every thread picks the winner among the four published rows.
+// the updates are static, with no per-column branches.  One workgroup barrier per column: each
+// wave reduces its best row to one key, the wave's best row publishes itself in LDS at once, and
+// after the barrier every thread picks the winner among the four published rows.
+//
+// The local LU is blocked: the 64 columns form four sub-panels of 16.  A column step updates only
+// the columns of its own sub-panel (a rank-1 update of at most 15 columns); at the end of a
+// sub-panel its pivot rows' trailing parts are turned into U12 = L11^-1 P12 (forward substitution
+// in LDS) and every row still in the set takes the delayed update of its trailing columns,
+// a_c -= sum_i l_i U12(i, c), as one block of independent fused multiply-adds.
 #pragma once
 
 #include <climits>
@@ -88,12 +94,15 @@ __device__ inline cplx<T> crecip(cplx<T> p) {
     return cplx<T>(r * s, -s);
 }
 
+constexpr int TSLU_SB = 16;   // columns per sub-panel
+
 template <typename T>
 struct TsluShared {
-    cplx<T> cand[2][4][64];          // each wave's best row, by column parity
+    cplx<T> cand[2][4][TSLU_SB];     // each wave's best row (its sub-panel columns), by column parity
     unsigned long long vkey[2][4];
     int vrow[2][4];
     int sel[64];
+    cplx<T> urow[TSLU_SB][64];       // the sub-panel's pivot rows; their trailing parts become U12
 };
 
 template <typename T>
@@ -107,6 +116,55 @@ struct TsluLocal {
     int mystep;   // column at which this lane's row won (-1: not selected)
 };
 
+// End of the sub-panel of columns S0 .. S0 + 15 (all threads; two barriers).  The rows that won in
+// it publish their columns S0 .. 63: within the sub-panel they hold [multipliers | pivot | U11 row]
+// (current when the row won), beyond it P12, the row as the sub-panel started.  One thread per
+// trailing column c forms U12(:, c) = L11^-1 P12(:, c) in place; then every row still in the set
+// applies its delayed update, and at the root the winners take their final U12 rows (they are the
+// factored rows the root writes out).
+template <typename T, int S0>
+__device__ __forceinline__ void tslu_block(TsluLocal<T>& L) {
+    constexpr int CB = S0 + TSLU_SB, NT = 64 - CB;
+    TsluShared<T>& sh = L.sh;
+    cplx<T>(&a)[64] = L.a;
+    const int mi = L.mystep - S0;
+    const bool won = L.mystep >= S0 && L.mystep < CB;
+    if (won) {
+#pragma unroll
+        for (int c = S0; c < 64; ++c) sh.urow[mi][c] = a[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < NT) {
+        const int c = CB + threadIdx.x;
+        cplx<T> u[TSLU_SB];
+#pragma unroll
+        for (int i = 0; i < TSLU_SB; ++i) {
+            cplx<T> v = sh.urow[i][c];
+#pragma unroll
+            for (int i2 = 0; i2 < i; ++i2) v = v - sh.urow[i][S0 + i2] * u[i2];
+            u[i] = v;
+            sh.urow[i][c] = v;
+        }
+    }
+    __syncthreads();
+    if (L.active) {
+#pragma unroll
+        for (int i = 0; i < TSLU_SB; ++i) {
+            const cplx<T> l = a[S0 + i];
+            const T nr = -l.re, ni = -l.im;
+#pragma unroll
+            for (int c = CB; c < 64; ++c) {
+                const cplx<T> uc = sh.urow[i][c];
+                a[c].re = fmat(nr, uc.re, fmat(l.im, uc.im, a[c].re));
+                a[c].im = fmat(nr, uc.im, fmat(ni, uc.re, a[c].im));
+            }
+        }
+    } else if (won && L.root) {
+#pragma unroll
+        for (int c = CB; c < 64; ++c) a[c] = sh.urow[mi][c];
+    }
+}
+
 // Column J of the local LU, then column J + 1.  nsel (workgroup-uniform) drops to J when column J
 // finds no row left.
 template <typename T, int J>
@@ -114,6 +172,7 @@ __device__ __forceinline__ void tslu_step(TsluLocal<T>& L) {
     if constexpr (J < 64) {
         if (J < L.nsel) {
             constexpr int par = J & 1;
+            constexpr int S0 = J / TSLU_SB * TSLU_SB, SE = S0 + TSLU_SB;   // this column's sub-panel
             cplx<T>(&a)[64] = L.a;
             TsluShared<T>& sh = L.sh;
             unsigned long long vk;
@@ -125,7 +184,7 @@ __device__ __forceinline__ void tslu_step(TsluLocal<T>& L) {
             }
             if (vk != 0 && L.active && L.row == br) {
 #pragma unroll
-                for (int c = J; c < 64; ++c) sh.cand[par][L.wave][c] = a[c];
+                for (int c = J; c < SE; ++c) sh.cand[par][L.wave][c - S0] = a[c];
             }
             __syncthreads();
             // winner among the four waves: largest value key, lowest row on ties (branch-free)
@@ -144,7 +203,7 @@ __device__ __forceinline__ void tslu_step(TsluLocal<T>& L) {
                 L.nsel = J;
                 return;
             }
-            const cplx<T>* prow = sh.cand[par][gw];
+            const cplx<T>* prow = sh.cand[par][gw];   // columns S0 .. SE - 1
             if (L.active && L.row == gr) {   // the winner leaves the set, its registers keep the row
                 sh.sel[J] = gr;
                 L.active = false;
@@ -152,21 +211,22 @@ __device__ __forceinline__ void tslu_step(TsluLocal<T>& L) {
             }
             const bool zero_pivot = gk == 1;   // |re| + |im| == 0
             if (zero_pivot && L.root && threadIdx.x == 0 && *L.info == 0) *L.info = L.j0 + J + 1;
-            // scaling and rank-1 update of the rows still in the set
+            // scaling and rank-1 update of the rows still in the set, within the sub-panel
             if (L.active) {
                 const cplx<T> zero(T(0), T(0));
-                const cplx<T> invp = zero_pivot ? zero : crecip(prow[J]);
+                const cplx<T> invp = zero_pivot ? zero : crecip(prow[J - S0]);
                 const cplx<T> l = a[J] * invp;
                 a[J] = l;
                 // a_c -= l p_c as four fused multiply-adds
                 const T nr = -l.re, ni = -l.im;
 #pragma unroll
-                for (int c = J + 1; c < 64; ++c) {
-                    const cplx<T> pc = prow[c];
+                for (int c = J + 1; c < SE; ++c) {
+                    const cplx<T> pc = prow[c - S0];
                     a[c].re = fmat(nr, pc.re, fmat(l.im, pc.im, a[c].re));
                     a[c].im = fmat(nr, pc.im, fmat(ni, pc.re, a[c].im));
                 }
             }
+            if constexpr (J == SE - 1 && SE < 64) tslu_block<T, S0>(L);
             tslu_step<T, J + 1>(L);
         }
     }
