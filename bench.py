@@ -63,17 +63,72 @@ def sources_hash(names):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, n, q, mode):
-    """HBM bytes per dispatch of `kernel` from the committed PMC record (profiles/pmc_traffic.json),
-    or None when the record is for another workload or the sources behind it have changed since."""
+def measured_traffic(kernel, workload, mode):
+    """HBM bytes per dispatch of `kernel` on `workload` from the committed PMC record
+    (profiles/pmc_traffic.json, written by --pmc-summary), or None when there is no record for that
+    workload and mode or the sources behind it have changed since."""
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))[kernel]
+        rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))[f"{kernel}@{workload}"]
         digest = sources_hash(TRAFFIC_SOURCES[kernel])
     except (OSError, KeyError, ValueError):
         return None
-    if digest != rec.get("sources_sha256_16") or (n, q, mode) != tuple(rec.get("n_q_mode", ())):
+    if digest != rec.get("sources_sha256_16") or mode != rec.get("mode"):
         return None
     return rec["bytes_per_dispatch"]
+
+
+def batch_update_bytes(ns, q, elem):
+    """Algorithmic bytes and launch count of the trailing updates of a batch factored as one set:
+    launch s covers step s of every member that has it."""
+    total, launches = 0.0, 0
+    for n in ns:
+        b, l = update_bytes(n, q, elem)
+        total += b
+        launches = max(launches, l)
+    return total, launches
+
+
+def pmc_summary(fetch_csv, write_csv, workload, mode, note):
+    """Per-dispatch HBM traffic of the trailing update from two rocprofv3 --pmc runs of
+    `bench.py --workload W --counters` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled
+    by what the same counter reads for the elementwise multiply of 64 Mi floats the run starts with
+    (256 MiB read, 256 MiB written); recorded in profiles/pmc_traffic.json with a hash of the
+    sources."""
+    import csv
+    kname = "cgemm_kernel<float, 2, 2, 4, 2, true, true, true, 1>" if mode != "fp64" else \
+        "cgemm_kernel<double, 2, 2, 2, 2, true, true, true, 1>"
+    out = {}
+    for key, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = list(csv.DictReader(open(path)))
+        cal = [float(r["Counter_Value"]) for r in rows if "MulFunctor" in r["Kernel_Name"]]
+        upd = [float(r["Counter_Value"]) for r in rows if kname in r["Kernel_Name"]]
+        if not cal or not upd:
+            raise SystemExit(f"{path}: calibration or update dispatches missing")
+        factor = 256.0 * 1024 / cal[0]          # KiB the counter should read for 256 MiB
+        out[key] = (sum(upd) / len(upd), factor, len(upd))
+    elem = 16 if mode == "fp64" else 8
+    if workload == "c2":
+        ns, _ = __import__("pencils").c2_sizes(64)
+        alg, launches = batch_update_bytes(ns, 16, elem)
+    else:
+        n, q = {"c1": (4096, 24), "c3": (8192, 32)}[workload]
+        alg, launches = update_bytes(n, q, elem)
+    per = 1024.0 * (out["fetch"][0] * out["fetch"][1] + out["write"][0] * out["write"][1])
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        rec = {}
+    rec[f"lu_update@{workload}"] = dict(
+        workload=note, kernel=kname, mode=mode, dispatches=out["fetch"][2],
+        fetch_kib_per_dispatch=out["fetch"][0], write_kib_per_dispatch=out["write"][0],
+        calibration="torch elementwise multiply of 64 Mi floats: 256 MiB read, 256 MiB written",
+        fetch_factor=out["fetch"][1], write_factor=out["write"][1], bytes_per_dispatch=per,
+        algorithmic_bytes_per_launch=alg / launches, ratio=per / (alg / launches),
+        sources_sha256_16=sources_hash(TRAFFIC_SOURCES["lu_update"]))
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec[f"lu_update@{workload}"], indent=1))
 
 
 def update_bytes(n, q, elem, nb=64, group=4):
@@ -204,7 +259,12 @@ def load_batch(count=64, device=None):
     there (A, B are then device tensors)."""
     import pencils
     ns, ms = pencils.c2_sizes(count)
-    return [pencils.c2_pencil(j, ns[j], ms[j], device=device) for j in range(count)]
+    out = []
+    for j in range(count):
+        out.append(pencils.c2_pencil(j, ns[j], ms[j], device=device))
+        if device is None and j % 8 == 7:
+            log(f"  {j + 1} of {count} pencils built")
+    return out
 
 
 def tune_panels(fm, q, modes, dev):
@@ -247,16 +307,22 @@ def batch_cpu_baseline(P, U0h, stride=4):
                 sample_s=t, sample_iterations=iters, sample_converged=ok)
 
 
-def update_roofline(ph, prec):
-    """Per-launch figures of the trailing-update kernel from the library's HIP-event phase timing:
-    flops per launch (8 nr nc K over every member and node the launch covers) / average duration."""
+def update_roofline(ph, prec, ns, mode):
+    """Per-launch figures of the trailing-update kernel of a batch from the library's HIP-event phase
+    timing: flops per launch (8 nr nc K over every member and node the launch covers) / average
+    duration; algorithmic bytes per launch (batch_update_bytes) and the measured traffic (PMC
+    record)."""
     u = ph["lu_update"]
     launches = max(1, u["launches"])
     avg_ms = u["ms"] / launches
     achieved = u["flops"] / launches / (avg_ms * 1e-3) / 1e12
+    alg, _ = batch_update_bytes(ns, 16, 16 if mode == "fp64" else 8)
     return dict(bound="mfma", achieved=achieved, peak=PEAK[prec], unit="TFLOP/s", frac=achieved / PEAK[prec],
-                traffic=None, kernel="cgemm_kernel (trailing update, kind 1)", kernel_phase="lu_update",
-                avg_launch_ms=avg_ms, launches=u["launches"], flops_per_launch=u["flops"] / launches)
+                traffic=measured_traffic("lu_update", "c2", mode),
+                traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
+                kernel="cgemm_kernel (trailing update, kind 1)", kernel_phase="lu_update",
+                avg_launch_ms=avg_ms, launches=u["launches"], flops_per_launch=u["flops"] / launches,
+                algorithmic_bytes_per_launch=alg / launches)
 
 
 def bench_batch(args, fm, torch, dev):
@@ -337,7 +403,7 @@ def bench_batch(args, fm, torch, dev):
               for k, v in ph.items()}
     for k, v in phases.items():
         log(f"   {k:16s} {v['ms']:9.2f} ms  {v['launches']:6d} launches  {v['tflops']} TF/s")
-    roofline = update_roofline(ph, "fp16" if prec == "fp16" else prec)
+    roofline = update_roofline(ph, "fp16" if prec == "fp16" else prec, [p.n for p in P], prec)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample of the batch ...")
@@ -700,6 +766,8 @@ def main():
                     help="run only a calibration kernel (elementwise multiply, 256 MiB in and out) and one "
                          "factorisation of the workload, for hardware-counter runs")
     ap.add_argument("--pivoting", default="tournament", choices=["tournament", "partial"])
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="record the update's traffic from two rocprofv3 --pmc runs of --counters (no GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-sequential", action="store_true",
@@ -711,6 +779,12 @@ def main():
         print("bench.py measures one MI355X: the library is a single-GPU build (several GPUs would each "
               "own a share of the contour nodes and sum their filter blocks); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.pmc_summary:
+        notes = {"c1": "n=4096 complex-symmetric pencil, q=24, factorisation (setup only)",
+                 "c2": "64 pencils n ~ U{256..2048}, q=16, one factorisation graph (setup only)",
+                 "c3": "n=8192 complex-symmetric pencil, q=32, factorisation (setup only)"}
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload, args.mode, notes[args.workload])
+        return
 
     import torch
     import paper_1404_2891_amd as fm
@@ -721,11 +795,21 @@ def main():
         y = torch.empty_like(x)
         torch.mul(x, 2.0, out=y)
         torch.cuda.synchronize()
-        P, U0h, ref, g = load_workload(args.workload)
-        F = fm.Feast(fm.to_device(P.A, dev), fm.to_device(P.B, dev), P.center, P.radius, 1.0, P.q, P.m0,
-                     precision=args.mode)
-        torch.cuda.synchronize()
-        F.close()
+        if args.workload == "c2":
+            # built on the host (same draws; no generator kernels among the counted dispatches)
+            P = load_batch(args.count, None)
+            log("batch built")
+            mats = [(fm.to_device(p.A, dev), fm.to_device(p.B, dev)) for p in P]
+            b = fm.FeastBatch(mats, (0j, 1.0, 1.0), m0=[p.m0 for p in P], q=16,
+                              precision=args.mode, pivoting=args.pivoting)
+            torch.cuda.synchronize()
+            b.close()
+        else:
+            P, U0h, ref, g = load_workload(args.workload)
+            F = fm.Feast(fm.to_device(P.A, dev), fm.to_device(P.B, dev), P.center, P.radius, 1.0, P.q, P.m0,
+                         precision=args.mode)
+            torch.cuda.synchronize()
+            F.close()
         log("counters run done")
         return
     if args.workload == "c2":
@@ -794,7 +878,7 @@ def main():
         nbytes, launches = panel_bytes(P.n, P.q, elem)
         achieved = nbytes / (dph["ms"] * 1e-3) / 1e9
         roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK, unit="GB/s", frac=achieved / HBM_PEAK,
-                        traffic=measured_traffic("panel_step_kernel", P.n, P.q, args.mode),
+                        traffic=measured_traffic("panel_step_kernel", args.workload, args.mode),
                         traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
                         kernel="panel_step_kernel", kernel_phase=dom,
                         avg_launch_ms=dph["ms"] / launches, bytes_per_launch=nbytes / launches, launches=launches)
@@ -807,7 +891,7 @@ def main():
         achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12
         roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
                         frac=achieved / PEAK[prec_of_phase],
-                        traffic=measured_traffic("lu_update", P.n, P.q, args.mode),
+                        traffic=measured_traffic("lu_update", args.workload, args.mode),
                         traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
                         kernel="cgemm_kernel (trailing update)", kernel_phase=dom,
                         avg_launch_ms=dph["ms"] / max(1, dph["launches"]), launches=dph["launches"],

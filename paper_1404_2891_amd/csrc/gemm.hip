@@ -57,6 +57,7 @@ struct Params {
     const cplx<T>* B; long ldb, sB;
     cplx<T>* C; long ldc, sC;
     int M, N, K, batch, splitk, kchunk, tiles_m;
+    int tiles_n, xcd_order;   // see tile_of
     int batch2; long sA2, sB2, sC2;
     T ar, ai, br, bi;
     const z64* alpha_b;
@@ -66,6 +67,31 @@ struct Params {
     int ngroups;
     int* amax;
 };
+
+// Tile (tm, tn) of workgroup blockIdx.x.  Plain order: tm fastest.  XCD order (the LU trailing
+// update): the chip's eight XCDs, each with an L2 of its own, receive the workgroups of a launch in
+// turn (workgroup w on XCD w mod 8), so consecutive tiles would put every block of L21 and U12 into
+// every L2.  Instead the x extent is padded to a multiple of 8 and the workgroups of XCD x take
+// tiles xcd_per * x .. xcd_per * (x + 1) - 1 of an order that walks columns of tiles inside two
+// bands of rows: each XCD then covers about half of the tile rows and a quarter of the tile
+// columns, so each L21 block is fetched by four XCDs and each U12 block by two.
+__device__ inline bool tile_of(int tiles_m, int tiles_n, int xcd_order, int& tm, int& tn) {
+    if (!xcd_order) {
+        tm = blockIdx.x % tiles_m;
+        tn = blockIdx.x / tiles_m;
+        return true;
+    }
+    const int per = gridDim.x / 8;
+    const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= tiles_m * tiles_n) return false;
+    const int G = (tiles_m + 1) / 2;                 // tile rows per band
+    const int band = t / (G * tiles_n), first = band * G;
+    const int rows = min(G, tiles_m - first);        // the last band may be shorter
+    const int r = t - first * tiles_n;
+    tm = first + r % rows;
+    tn = r / rows;
+    return true;
+}
 
 template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC, int KIND>
 __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
@@ -81,7 +107,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    const int tm = blockIdx.x % p.tiles_m, tn = blockIdx.x / p.tiles_m;
+    int tm, tn;
+    if (!tile_of(p.tiles_m, p.tiles_n, p.xcd_order, tm, tn)) return;
     int b = blockIdx.z % p.batch, s = (blockIdx.z / p.batch) % p.splitk;
     int b2 = blockIdx.z / (p.batch * p.splitk);
     const int m0 = tm * BM, n0 = tn * BN;
@@ -460,7 +487,11 @@ template <typename T, int WM, int WN, int RB, int CB, bool RA, bool RBm, bool RC
 void launch_cfg(Params<T> p, hipStream_t st) {
     constexpr int BM = WM * RB * 16, BN = WN * CB * 16;
     p.tiles_m = ceil_div(p.M, BM);
-    dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.splitk * p.batch2 * (p.groups ? p.ngroups : 1));
+    p.tiles_n = ceil_div(p.N, BN);
+    p.xcd_order = KIND == 1 ? 1 : 0;
+    const int tiles = p.tiles_m * p.tiles_n;
+    dim3 grid(p.xcd_order ? (tiles + 7) / 8 * 8 : tiles, 1,
+              p.batch * p.splitk * p.batch2 * (p.groups ? p.ngroups : 1));
     hipLaunchKernelGGL((cgemm_kernel<T, WM, WN, RB, CB, RA, RBm, RC, KIND>), grid, dim3(64 * WM * WN), 0, st, p);
 }
 
@@ -514,6 +545,8 @@ int gemm(const GemmOp& op, hipStream_t st) {
     p.ngroups = op.ngroups;
     p.amax = op.amax;
     p.tiles_m = 1;
+    p.tiles_n = 1;
+    p.xcd_order = 0;
     if (op.groups) {
         if (op.ngroups <= 0) return 0;
         if (p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;   // see gemm_grouped
@@ -618,6 +651,8 @@ int gemm_grouped(const GemmOp& proto, const GemmGroup* groups, int ngroups, int 
     p.ngroups = ngroups;
     p.amax = nullptr;
     p.tiles_m = 1;
+    p.tiles_n = 1;
+    p.xcd_order = 0;
     const int code = (proto.rowA ? 4 : 0) | (proto.rowB ? 2 : 0) | (proto.rowC ? 1 : 0);
     switch (code) {
         case 0: launch_layout<T, false, false, false>(p, st); break;
