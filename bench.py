@@ -626,44 +626,68 @@ def bench_domains(args, fm, torch, dev):
     print(json.dumps(line), flush=True)
 
 
+M0_CAP = 128   # subspace capacity of the estimator's solves (restarts double m0 up to it)
+
+
+def m0_solve(fm, torch, dev, P, V, m0_rule, cap):
+    """binding.sized_solve over the held-out pencils, timed end to end; returns (wall s, results,
+    m0s, restarts, GFLOP)."""
+    import pencils
+    n = P[0].n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, m0s, restarts, work = fm.binding.sized_solve(
+        [(p.A, None) for p in P], [(p.center, p.radius, 1.0) for p in P],
+        lambda i, m0: fm.to_device(pencils.start_block(4, n, m0), dev), m0_rule=m0_rule, cap=cap, probes=V)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res, m0s, restarts, sum(work.values()) / 1e9
+
+
+def m0_labels_and_features(fm, torch, dev, ids, V, chunk=512):
+    """Training data of the estimator: for each pencil its probe features (the 16-node filter of its
+    FEAST context) and its label, the eigenvalue count the plain FP64 method (R-FEAST, q = 16,
+    m0 = 64) finds inside the contour; pencils generated on the device chunk by chunk."""
+    import pencils
+    feats, labels, construct, ok = [], [], [], 0
+    for i0 in range(0, len(ids), chunk):
+        part = [pencils.c4_pencil(j, 512, basis=bb, device=dev) for j, bb in ids[i0:i0 + chunk]]
+        b = fm.FeastBatch([(p.A, None) for p in part], [(p.center, p.radius, 1.0) for p in part], m0=64, q=16,
+                          precision="fp64")
+        feats += list(b.probe_features(V))
+        res, rcs = b.iterate([fm.to_device(pencils.start_block(4, 512, 64), dev) for _ in part])
+        b.close()
+        for p, r in zip(part, res):
+            labels.append(len(r.lam))
+            construct.append(p.m)
+            ok += int(r.converged)
+        del part
+        torch.cuda.empty_cache()
+    return np.array(feats), np.array(labels, dtype=np.float64), np.array(construct), ok
+
+
 def bench_m0(args, fm, torch, dev):
-    """Learned subspace size: probe features (8 Rademacher probes, 8-node FP16 filter) of training
-    pencils, the perceptron trained on their counts, then held-out pencils solved with m0 from
-    (a) the estimator, (b) a fixed m0 = 64, (c) 1.5 x the mean probe trace; every run uses the rank
-    check and doubles m0 on FEAST_ERANK.  Each strategy solves the held-out set as batches (one
-    factorisation graph, lockstep iterations) and is timed end to end, restarts included."""
+    """Learned subspace size.  Training: 20,000 pencils (n = 512, B = I, random circles, 0-48
+    eigenvalues inside) labelled by the plain FP64 FEAST run's count, with features from 8
+    Rademacher probes through the 16-node filter; the perceptron (FP16 operands) trained by the
+    library's kernels.  Held out: 2,048 pencils solved in FP32 with the rank check, each strategy
+    end to end (factorisation, probes, network, iterations, restarts on the same factorisations):
+    m0 from the estimator, a fixed m0 = 64, and 1.5 x the mean probe trace."""
     import pencils
     from oracle import mlp as omlp
     n, ntr, nev = 512, args.count_train, args.count_eval
-    t0 = time.perf_counter()
     V = fm.to_device(pencils.probe_block(4, 0, n), dev)
-    tr = [pencils.c4_pencil(j, n, basis=b, device=dev) for j, b in pencils.c4_split("train", ntr)]
+    t0 = time.perf_counter()
+    Xtr, ytr, ctr, conv = m0_labels_and_features(fm, torch, dev, pencils.c4_split("train", ntr), V)
+    t_label = time.perf_counter() - t0
+    log(f"{ntr} training pencils: features and FP64 FEAST labels in {t_label:.1f} s ({conv} converged; "
+        f"labels equal to the construction count for {int(np.sum(ytr == ctr))})")
     ev = [pencils.c4_pencil(j, n, basis=b, device=dev) for j, b in pencils.c4_split("eval", nev)]
     torch.cuda.synchronize()
-    log(f"{ntr} training and {nev} held-out pencils generated in {time.perf_counter() - t0:.1f} s")
-
-    def features(P):
-        out = []
-        for i in range(0, len(P), 128):
-            part = P[i:i + 128]
-            b = fm.FeastBatch([(p.A, None) for p in part], [(p.center, p.radius, 1.0) for p in part], m0=8, q=8,
-                              precision=args.probe_precision, ir_max=0)
-            out += [b.member_probe_features(k, V) for k in range(len(part))]
-            b.close()
-        return np.array(out)
-
-    if args.tune:
-        tune_panels(fm, 8, ["fp32"], dev)
-        tune_panels(fm, 16, ["fp32"], dev)
-    t0 = time.perf_counter()
-    Xtr = features(tr)
-    torch.cuda.synchronize()
-    t_probe = (time.perf_counter() - t0) / ntr
-    Xev = features(ev)
-    log(f"probe features: {1e3 * t_probe:.2f} ms per pencil")
-    net = fm.MLP(omlp.flatten(omlp.init_params(np.random.default_rng(7))), half=True, max_batch=256, device=dev)
+    d = Xtr.shape[1]
+    net = fm.MLP(omlp.flatten(omlp.init_params(np.random.default_rng(7), d)), n_in=d, half=True, max_batch=512,
+                 device=dev)
     Xd = torch.from_numpy(Xtr.astype(np.float32)).to(dev)
-    yd = torch.from_numpy(np.array([p.m for p in tr], dtype=np.float32)).to(dev)
+    yd = torch.from_numpy(ytr.astype(np.float32)).to(dev)
     net.fit_standardization(Xd)
     rng = np.random.default_rng(8)
     t0 = time.perf_counter()
@@ -676,61 +700,47 @@ def bench_m0(args, fm, torch, dev):
             steps += 1
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    m_hat = net.forward(torch.from_numpy(Xev.astype(np.float32)).to(dev)).cpu().numpy().astype(np.float64)
+    log(f"training: {steps} Adam steps in {t_train:.1f} s")
     y_ev = np.array([p.m for p in ev], dtype=np.float64)
-    log(f"training: {steps} Adam steps in {t_train:.1f} s; held-out mean |m_hat - m| = "
-        f"{np.mean(np.abs(m_hat - y_ev)):.2f}")
-    probe_mean = Xev[:, 0:16:2].mean(axis=1)
-    strategies = {
-        "estimator": [fm.m0_from_estimate(x) for x in m_hat],
-        "estimator_margin12": [max(8, int(np.ceil((np.ceil(1.25 * max(x, 0.0)) + 12) / 8.0)) * 8) for x in m_hat],
-        "fixed_64": [64] * nev,
-        "probe_mean_x1.5": [max(8, int(np.ceil(1.5 * max(x, 0.0) / 8.0)) * 8) for x in probe_mean],
-    }
+    est = {}
+
+    def estimator(feats, i0):
+        x = torch.from_numpy(feats.astype(np.float32)).to(dev)
+        m_hat = net.forward(x).cpu().numpy().astype(np.float64)
+        est.update({i0 + k: v for k, v in enumerate(m_hat)})
+        return [fm.m0_from_estimate(v) for v in m_hat]
+
+    def probe_mean(feats, i0):
+        t = feats[:, 0:2 * V.shape[1]:2].mean(axis=1)
+        return [max(8, int(np.ceil(1.5 * max(x, 0.0) / 8.0)) * 8) for x in t]
+
+    strategies = [("estimator", estimator, M0_CAP), ("fixed_64", None, 64), ("probe_mean_x1.5", probe_mean, M0_CAP)]
     out = {}
-    for name, m0s in strategies.items():
-        m0s = list(m0s)
-        todo = list(range(nev))
-        restarts, iters, flops = 0, 0, 0.0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        found = {}
-        while todo:
-            part = [ev[i] for i in todo]
-            b = fm.FeastBatch([(p.A, None) for p in part], [(p.center, p.radius, 1.0) for p in part],
-                              m0=[m0s[i] for i in todo], q=16, precision="fp32", rank_check=True)
-            U0s = [fm.to_device(pencils.start_block(4, n, m0s[i]), dev) for i in todo]
-            res, rcs = b.iterate(U0s)
-            b.close()
-            flops += len(todo) * 16 * (8.0 / 3.0) * n ** 3
-            nxt = []
-            for i, r, rc in zip(todo, res, rcs):
-                iters += r.iterations
-                flops += r.iterations * 8.0 * n * n * m0s[i] * 18
-                if rc == fm.binding.FEAST_ERANK and m0s[i] < n:
-                    m0s[i] = min(2 * m0s[i], n)
-                    restarts += 1
-                    nxt.append(i)
-                else:
-                    found[i] = r
-            todo = nxt
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ok = sum(1 for i, r in found.items() if r.converged and len(r.lam) == ev[i].m)
+    for name, rule, cap in strategies:
+        m0_solve(fm, torch, dev, ev[:256], V, rule, cap)      # warm-up
+        wall, res, m0s, restarts, gflop = m0_solve(fm, torch, dev, ev, V, rule, cap)
+        ok = sum(1 for p, r in zip(ev, res) if r.converged and len(r.lam) == p.m)
         out[name] = dict(ms_per_pencil=1e3 * wall / nev, mean_m0=float(np.mean(m0s)), restarts=restarts,
-                         iterations=iters, gflop_per_pencil=flops / nev / 1e9, correct=ok)
+                         iterations=int(sum(r.iterations for r in res)), gflop_per_pencil=gflop / nev, correct=ok)
         log(f"{name}: {out[name]}")
+    m_hat = np.array([est[i] for i in range(nev)])
     line = {
-        "metric": "learned m0: FEAST time and work per held-out pencil (estimator vs fixed m0 and probe-mean rule)",
-        "value": out["fixed_64"]["ms_per_pencil"] / out["estimator"]["ms_per_pencil"],
-        "unit": "x (time per pencil, fixed m0 = 64 / estimator m0)",
-        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f16 probes + f16/f32 MLP + f32+f64",
+        "metric": "learned m0: FEAST work and time per held-out pencil (estimator vs fixed m0 = 64 and the "
+                  "probe-mean rule)",
+        "value": out["fixed_64"]["gflop_per_pencil"] / out["estimator"]["gflop_per_pencil"],
+        "unit": "x (GFLOP per pencil, fixed m0 = 64 / estimator m0)",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f16 MLP + f32 LU + f64 correction",
         "config": {"workload": f"{ntr} training / {nev} held-out pencils, n={n}, B=I, random circles, "
-                               f"m ~ U{{0..48}}; probes: 8 Rademacher vectors, 8 nodes, {args.probe_precision} LU; "
-                               f"MLP 19-256-256-1, {args.epochs} epochs; FEAST q=16 FP32+IR with rank check"},
-        "probe_ms_per_pencil": 1e3 * t_probe, "train_s": t_train,
+                               f"m ~ U{{0..48}}; labels: FP64 R-FEAST counts (q=16, m0=64); features: 8 Rademacher "
+                               f"probes through the solve's own 16-node filter + (c, R); MLP {d}-256-256-1 FP16, "
+                               f"{args.epochs} epochs; held-out FEAST q=16 FP32 + FP64 shifted-residual correction "
+                               f"with the rank check, restarts on the same factorisations"},
+        "label_s": t_label, "train_s": t_train,
+        "labels_equal_construction": int(np.sum(ytr == ctr)), "label_runs_converged": conv,
         "heldout_mean_abs_err": float(np.mean(np.abs(m_hat - y_ev))),
         "heldout_rmse": float(np.sqrt(np.mean((m_hat - y_ev) ** 2))),
+        "speedup_time_vs_fixed_64": out["fixed_64"]["ms_per_pencil"] / out["estimator"]["ms_per_pencil"],
+        "gain_gflop_vs_probe_mean": out["probe_mean_x1.5"]["gflop_per_pencil"] / out["estimator"]["gflop_per_pencil"],
         "strategies": out,
     }
     print(json.dumps(line), flush=True)
@@ -750,11 +760,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c3", "c2", "c4", "real4096", "domains"],
                     help="real4096: a real pencil whose conjugate nodes share factorisations; domains: "
                          "load-balanced tiles of a region in one batch")
-    ap.add_argument("--count-train", type=int, default=4096, help="training pencils of the learned-m0 workload")
-    ap.add_argument("--count-eval", type=int, default=256, help="held-out pencils of the learned-m0 workload")
+    ap.add_argument("--count-train", type=int, default=20000, help="training pencils of the learned-m0 workload")
+    ap.add_argument("--count-eval", type=int, default=2048, help="held-out pencils of the learned-m0 workload")
     ap.add_argument("--epochs", type=int, default=150)
-    ap.add_argument("--probe-precision", default="fp32", choices=["fp32", "fp16"],
-                    help="factorisations of the 8-node probe filter of the learned-m0 workload")
     ap.add_argument("--count", type=int, default=64, help="pencils of the batched workload (c2)")
     ap.add_argument("--domain-eigs", type=int, default=512, help="eigenvalues in the region (domains workload)")
     ap.add_argument("--domain-target", type=int, default=48, help="eigenvalues per tile (domains workload)")

@@ -355,8 +355,11 @@ int feast_set_panel_rows(int precision, int q, int single_rows);
  * rho(M) v_j for each probe, then Re c, Im c and R of a circle containing the
  * contour (the ellipse's center and larger semi-axis; for a glued contour the
  * mean of the pieces' start points and the largest distance from it to the
- * contour).  The usual
- * probe context has q = 8 nodes, FEAST_FP16_IR and ir_max = 0.  Synchronous.
+ * contour).  The filter runs in the context's precision without refinement
+ * sweeps (the features are sampling estimates).  The probes can use the
+ * factorisations of the very context that will solve the pencil (its q nodes;
+ * 8 probes cost 8 n^2 nprobe q flops, about 2% of an n = 512, q = 16 solve),
+ * or a context of their own (e.g. q = 8 nodes, FEAST_FP16_IR).  Synchronous.
  *
  * The estimator maps features to a count with a perceptron n_in -> hidden ->
  * hidden -> 1 (ReLU), parameters (FP32, host, feast_mlp_param_count of them)
@@ -373,6 +376,14 @@ int feast_set_panel_rows(int precision, int q, int single_rows);
  * used for an estimated count m: max(8, ceil(1.25 m) + 4) rounded up to a
  * multiple of 8. */
 int feast_probe_features(feast_ctx* ctx, const void* V, int ldv, int nprobe, float* features);
+
+/* The subspace size (Section 4's m0) of the context's later calls, 1 <= m0 <=
+ * the m0 of its setup, which sized the workspace; the factorisations stay.  A
+ * search can so size its subspace after the factorisation (from the
+ * estimator below, or doubled after FEAST_ERANK) without factoring again.
+ * feast_iterate's U0 and result buffers then have m0 columns.  Returns 0,
+ * -1 (no context), -2 (m0 out of range). */
+int feast_set_m0(feast_ctx* ctx, int m0);
 typedef struct feast_mlp feast_mlp;
 long feast_mlp_param_count(int n_in, int hidden);
 int feast_mlp_workspace_size(int n_in, int hidden, int max_batch, size_t* bytes);
@@ -450,11 +461,19 @@ int feast_estimate_m0(feast_ctx* probe_ctx, feast_mlp* mlp, const void* V, int l
  * waiting for them (its outputs may be read there).
  *
  * feast_batch_iterate: runs feast_iterate on every pencil, all of them in
- * lockstep through the phases of the iteration (device work of the pencils
- * overlaps on their streams, one host synchronisation per phase for the whole
- * batch).  U0[b] (ldu0[b]) is pencil b's start block, written on `stream`;
- * results[b] as for feast_iterate.  member_rc (may be NULL) receives each
- * pencil's code.  Synchronous.  Returns 0 or the first nonzero member code.
+ * lockstep through the phases of the iteration (see feast_options.batch_launch
+ * for how their device work is launched; one host synchronisation per phase
+ * for the whole batch).  U0[b] (ldu0[b]) is pencil b's start block, written on
+ * `stream`, with as many columns as the pencil's current m0 (feast_set_m0);
+ * U0[b] == NULL leaves pencil b out of this call (results[b] is not written,
+ * member_rc[b] is 0), so that a few pencils can iterate again, e.g. with a
+ * larger m0 after FEAST_ERANK.  results[b] as for feast_iterate.  member_rc
+ * (may be NULL) receives each pencil's code.  Synchronous.  Returns 0 or the
+ * first nonzero member code.
+ *
+ * feast_batch_probe_features: feast_probe_features for every pencil at once
+ * (their probe filters launched together); features holds count rows of
+ * 2 nprobe + 3 floats.  Synchronous.
  *
  * feast_batch_factor_ms: device time of the factorisation graph launch (HIP
  * events on `stream`).
@@ -479,6 +498,7 @@ feast_ctx* feast_batch_member(feast_batch* batch, int i);
 int feast_batch_iterate(feast_batch* batch, const void* const* U0, const int* ldu0,
                         feast_result* results, int* member_rc);
 int feast_batch_factor_ms(feast_batch* batch, double* ms);
+int feast_batch_probe_features(feast_batch* batch, const void* V, int ldv, int nprobe, float* features);
 int feast_batch_timing_read(feast_batch* batch, int phase, feast_phase_time* out);
 void feast_batch_destroy(feast_batch* batch);
 

@@ -45,7 +45,7 @@ EXPORTED = [
     "feast_mlp_get_params", "feast_m0_from_estimate", "feast_mlp_destroy",
     "feast_autotune_workspace_size", "feast_autotune", "feast_set_panel_rows",
     "feast_filter_shifted", "feast_estimate_m0", "feast_batch_timing_read",
-    "feast_mlp_noalloc_max_elems", "feast_mlp_forward_noalloc",
+    "feast_mlp_noalloc_max_elems", "feast_mlp_forward_noalloc", "feast_set_m0", "feast_batch_probe_features",
 ]
 
 
@@ -180,6 +180,10 @@ def lib():
         L.feast_m0_from_estimate.restype = i
         L.feast_mlp_destroy.argtypes = [vp]
         L.feast_mlp_destroy.restype = None
+        L.feast_batch_probe_features.argtypes = [vp, vp, i, i, vp]
+        L.feast_batch_probe_features.restype = i
+        L.feast_set_m0.argtypes = [vp, i]
+        L.feast_set_m0.restype = i
         L.feast_mlp_noalloc_max_elems.argtypes = []
         L.feast_mlp_noalloc_max_elems.restype = ctypes.c_long
         L.feast_mlp_forward_noalloc.argtypes = [i, i, i, vp, vp, vp, vp, i, vp, vp]
@@ -454,6 +458,11 @@ class Feast:
         _check(code, "feast_iterate", ok=(FEAST_OK, FEAST_ENOCONV, FEAST_ERANK))
         return buf.result(code)
 
+    def set_m0(self, m0):
+        """Subspace size of later calls (<= the m0 of the setup); the factorisations stay."""
+        _check(lib().feast_set_m0(self._ctx, int(m0)), "feast_set_m0")
+        self.m0 = int(m0)
+
     def probe_features(self, V) -> np.ndarray:
         """Stochastic trace features of this context's filter for the probe block V (device)."""
         k = V.shape[1]
@@ -570,6 +579,14 @@ class FeastBatch:
                "feast_batch_trace_estimates")
         return out
 
+    def probe_features(self, V) -> np.ndarray:
+        """Probe features of every pencil (rows), their probe filters launched together."""
+        k = V.shape[1]
+        out = np.zeros((self.count, 2 * k + 3), dtype=np.float32)
+        _check(lib().feast_batch_probe_features(self._b, V.data_ptr(), _ld(V), k, out.ctypes.data),
+               "feast_batch_probe_features")
+        return out
+
     def member_probe_features(self, i, V) -> np.ndarray:
         c = lib().feast_batch_member(self._b, i)
         if not c:
@@ -578,6 +595,24 @@ class FeastBatch:
         out = np.zeros(2 * k + 3, dtype=np.float32)
         _check(lib().feast_probe_features(c, V.data_ptr(), _ld(V), k, out.ctypes.data), "feast_probe_features")
         return out
+
+    def set_m0(self, i, m0):
+        """Subspace size of pencil i's later iterations (<= its m0 at setup); factorisations stay."""
+        c = lib().feast_batch_member(self._b, i)
+        if not c:
+            raise IndexError(i)
+        _check(lib().feast_set_m0(c, int(m0)), "feast_set_m0")
+        self.m0[i] = int(m0)
+
+    def member_iterate(self, i, U0) -> IterateResult:
+        """feast_iterate on pencil i alone (its own stream, ordered after the batch's)."""
+        c = lib().feast_batch_member(self._b, i)
+        if not c:
+            raise IndexError(i)
+        buf = _ResultBuffers(self.n[i], self.m0[i], self.options, U0.device)
+        code = lib().feast_iterate(c, U0.data_ptr(), _ld(U0), ctypes.byref(buf.r))
+        _check(code, "feast_iterate", ok=(FEAST_OK, FEAST_ENOCONV, FEAST_ERANK))
+        return buf.result(code)
 
     def member_filter(self, i, U, side=0):
         """feast_filter on pencil i alone."""
@@ -589,16 +624,22 @@ class FeastBatch:
         return Q
 
     def iterate(self, U0s):
-        """feast_iterate on every pencil in lockstep; returns (list of IterateResult, member codes)."""
-        bufs = [_ResultBuffers(self.n[i], self.m0[i], self.options, U0s[i].device) for i in range(self.count)]
-        res = (Result * self.count)(*[b.r for b in bufs])
-        u_arr, u_p = _ptr_array([U.data_ptr() for U in U0s], ctypes.c_void_p)
-        ld_arr, ld_p = _ptr_array([_ld(U) for U in U0s], ctypes.c_int)
+        """feast_iterate on every pencil in lockstep; returns (list of IterateResult, member codes).
+        A None start block leaves that pencil out (its result is None)."""
+        dev = next(U.device for U in U0s if U is not None)
+        bufs = [_ResultBuffers(self.n[i], self.m0[i], self.options, dev) if U0s[i] is not None else None
+                for i in range(self.count)]
+        res = (Result * self.count)(*[b.r if b is not None else Result() for b in bufs])
+        u_arr, u_p = _ptr_array([U.data_ptr() if U is not None else 0 for U in U0s], ctypes.c_void_p)
+        ld_arr, ld_p = _ptr_array([_ld(U) if U is not None else 0 for U in U0s], ctypes.c_int)
         rcs = np.zeros(self.count, dtype=np.int32)
         code = lib().feast_batch_iterate(self._b, u_p, ld_p, ctypes.cast(res, ctypes.c_void_p), rcs.ctypes.data)
         _check(code, "feast_batch_iterate", ok=(FEAST_OK, FEAST_ENOCONV, FEAST_ERANK))
         out = []
         for i, b in enumerate(bufs):
+            if b is None:
+                out.append(None)
+                continue
             b.r = res[i]
             out.append(b.result(int(rcs[i])))
         return out, rcs
@@ -643,6 +684,55 @@ def partition_grid(counts, target):
 def rectangle(x0, x1, y0, y1):
     """Pieces of the axis-aligned rectangle [x0, x1] x [y0, y1], counterclockwise."""
     return polygon([complex(x0, y0), complex(x1, y0), complex(x1, y1), complex(x0, y1)])
+
+
+def sized_solve(pencils, contours, start, m0_rule=None, cap=128, probes=None, q=16, precision="fp32",
+                chunk=512, **kw):
+    """Solve many pencils with the subspace size chosen after their factorisation (Section 4 needs
+    m0 >= m; the paper checks it with the rank of the filtered block).  In batches of `chunk`
+    pencils (one factorisation each, workspace for `cap` columns): m0 of every pencil from
+    m0_rule(features, first index) when given, features = the probe features of the batch's own
+    filter for the probe block `probes` (feast_batch_probe_features), else m0 = cap; then the
+    lockstep iteration with the rank check; pencils that stop with FEAST_ERANK double their m0 (up
+    to cap, feast_set_m0) and iterate again on the same factorisations, without the others.
+    pencils: list of (A, B) device tensors; contours: list of (center, radius, aspect);
+    start(i, m0): the device start block of pencil i.  Returns (results, m0s, restarts, work) with
+    work = dict of algorithmic flops: factorisations, probe solves, iterations."""
+    results, m0s, restarts = [None] * len(pencils), [0] * len(pencils), 0
+    work = dict(factorisations=0.0, probes=0.0, iterations=0.0)
+    for i0 in range(0, len(pencils), chunk):
+        part = pencils[i0:i0 + chunk]
+        b = FeastBatch(part, contours[i0:i0 + chunk], m0=cap, q=q, precision=precision, rank_check=True, **kw)
+        work["factorisations"] += sum(q * (8.0 / 3.0) * int(A.shape[0]) ** 3 for A, _ in part)
+        if m0_rule is None:
+            m0 = [cap] * len(part)
+        else:
+            feats = b.probe_features(probes)
+            work["probes"] += sum(8.0 * int(A.shape[0]) ** 2 * probes.shape[1] * q for A, _ in part)
+            m0 = [max(1, min(cap, int(x))) for x in m0_rule(feats, i0)]
+            for k in range(len(part)):
+                b.set_m0(k, m0[k])
+        todo = list(range(len(part)))
+        while todo:
+            U0s = [None] * len(part)
+            for k in todo:
+                U0s[k] = start(i0 + k, m0[k])
+            res, rcs = b.iterate(U0s)
+            nxt = []
+            for k in todo:
+                r, rc, n = res[k], rcs[k], int(part[k][0].shape[0])
+                work["iterations"] += r.iterations * 8.0 * n * n * m0[k] * (q + 2)
+                if rc == FEAST_ERANK and m0[k] < cap:
+                    m0[k] = min(2 * m0[k], cap)
+                    restarts += 1
+                    b.set_m0(k, m0[k])
+                    nxt.append(k)
+                else:
+                    results[i0 + k] = r
+                    m0s[i0 + k] = m0[k]
+            todo = nxt
+        b.close()
+    return results, m0s, restarts, work
 
 
 def multi_domain(A, B, region, probes, grid=(8, 8), target=24, q=16, rule="gauss-legendre", probe_q=8,

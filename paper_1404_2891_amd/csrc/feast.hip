@@ -63,6 +63,7 @@ constexpr int TALL_SPLITK = 4;
 
 struct feast_ctx {
     int n = 0, m0 = 0, q = 0, nsteps = 0;   // q: factored nodes (all nodes unless conj_nodes)
+    int m0_cap = 0;                         // the m0 of the setup: the workspace holds that many columns
     int conj = FEAST_CONJ_NONE;
     long ldf = 0;
     Prec prec = Prec::F64;
@@ -253,6 +254,7 @@ int conj_plan(const feast_contour* C, std::vector<int>& keep, std::vector<double
 void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_options* o) {
     c->n = n;
     c->m0 = m0;
+    c->m0_cap = m0;
     c->q = C->q;
     c->conj = o->conj_nodes;
     if (c->conj != FEAST_CONJ_NONE) {
@@ -1062,6 +1064,9 @@ struct Run {
     int count = 0;
     int rank = -1;            // numerical rank of the first filtered block (rank check)
     bool rank_short = false;  // the rank check found the subspace too small
+    // largest filter gain ||rho(M) x_j|| over the unit-norm Ritz vectors of the previous iteration
+    // (measured by the next filter; NaN before the second iteration) and the one before it
+    double gain = NAN, gain_prev = NAN;
     std::vector<int> order;
     std::vector<double> rel, paper;
     std::vector<cd> lam;
@@ -1192,9 +1197,16 @@ int h_chol(Run& r, int pass) {
             r.rank = 0;
             for (const cd& e : ev) r.rank += e.real() > 1e-12 * emax;
         }
-        double tr = 0.0;
-        for (int i = 0; i < p; ++i) tr += G(i, i).real();
+        double tr = 0.0, gmax = 0.0;
+        for (int i = 0; i < p; ++i) {
+            tr += G(i, i).real();
+            gmax = std::max(gmax, G(i, i).real());
+        }
         if (!(tr > 0.0) || !std::isfinite(tr)) return FEAST_EREDUCED;
+        if (pass == 0 && side == 0 && r.it >= 2) {
+            r.gain_prev = r.gain;
+            r.gain = std::sqrt(gmax);
+        }
         double shift = pass == 0 ? 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * tr : 0.0;
         bool ok = false;
         for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
@@ -1315,6 +1327,16 @@ int h_conv(Run& r) {
     }
     if (r.prev_count >= 0 && count == r.prev_count)
         r.done = count == 0 ? (n_inside == 0 && r.prev_inside == 0) : (maxrel <= c->o.tol);
+    // An empty contour in the low-precision modes: their filter resolves the components of
+    // eigenvalues outside the contour (|rho| small) only to about u kappa / |rho|, so Ritz values
+    // of that noise can keep landing inside.  An eigenvalue inside has |rho| >= 1/2 for the
+    // circle's trapezoid rule (about 1 for the others), so a Ritz vector that has captured one is
+    // amplified by the filter; when two iterations in a row have no candidate and no Ritz vector
+    // with a gain of EMPTY_GAIN, the contour is taken to be empty.
+    constexpr double EMPTY_GAIN = 0.05;
+    if (!r.done && c->prec != Prec::F64 && count == 0 && r.prev_count == 0 && r.gain < EMPTY_GAIN &&
+        r.gain_prev < EMPTY_GAIN)
+        r.done = true;
     r.prev_count = count;
     r.prev_inside = n_inside;
     r.res_prev = r.res_last;
@@ -1752,9 +1774,51 @@ __global__ __launch_bounds__(256) void coldot_kernel(const z64* V, long ldv, con
     if (threadIdx.x == 0) out[j] = z64(sr[0], si[0]);
 }
 
+// Enqueues (or records) the probe features of one context: Q = rho(M) V with the context's filter in
+// its own precision (no refinement sweeps: the features are estimates whose sampling noise is far
+// above the factorisations' rounding), t_j = v_j^H q_j, and t to the pinned slot pin.AhBh
+// (asynchronously).
+int probe_enqueue(feast_ctx* c, const z64* V, long ldv, int nprobe) {
+    const int n = c->n;
+    c->ir_target = 1e-3;   // skips the sweeps
+    FM_TRY(filter_impl(c, 0, nprobe, V, ldv, c->QAB, n));
+    z64* t = (z64*)c->norms_d;   // 3 m0 doubles >= 2 nprobe
+    const z64* Qm = c->QAB;
+    auto dots = [=](hipStream_t st) {
+        hipLaunchKernelGGL(coldot_kernel, dim3(nprobe), dim3(256), 0, st, V, ldv, Qm, (long)n, n, t);
+        FM_LAUNCH_CHECK();
+        return 0;
+    };
+    if (OpLog* L = op_log())
+        L->other(dots);
+    else
+        FM_TRY(dots(c->st));
+    return d2h_async(c, c->pin.AhBh, t, nprobe * sizeof(z64));
+}
+
+// The features from the copied traces: (Re t_j, Im t_j) for each probe, then the circle (c, R).
+void probe_finish(const feast_ctx* c, int nprobe, float* features) {
+    for (int j = 0; j < nprobe; ++j) {
+        features[2 * j] = (float)c->pin.AhBh[j].re;
+        features[2 * j + 1] = (float)c->pin.AhBh[j].im;
+    }
+    double gre, gim, grad;
+    contour_circle(c->C, &gre, &gim, &grad);
+    features[2 * nprobe] = (float)gre;
+    features[2 * nprobe + 1] = (float)gim;
+    features[2 * nprobe + 2] = (float)grad;
+}
+
 }  // namespace
 
 extern "C" {
+
+int feast_set_m0(feast_ctx* c, int m0) {
+    if (!c) return -1;
+    if (m0 < 1 || m0 > c->m0_cap) return -2;
+    c->m0 = m0;
+    return 0;
+}
 
 int feast_probe_features(feast_ctx* c, const void* V, int ldv, int nprobe, float* features) {
     if (!c) return -1;
@@ -1762,26 +1826,11 @@ int feast_probe_features(feast_ctx* c, const void* V, int ldv, int nprobe, float
     if (ldv < c->n) return -3;
     if (nprobe < 1 || nprobe > c->m0) return -4;
     if (!features) return -5;
-    const int n = c->n;
-    // Q = rho(M) V (the context's filter, nodes and precision)
-    c->ir_target = default_ir_target(c);
     OuterOrder order(c);
     if (order.rc) return order.rc;
-    FM_TRY(filter_impl(c, 0, nprobe, (const z64*)V, ldv, c->QAB, n));
-    z64* t = (z64*)c->norms_d;   // 3 m0 doubles >= 2 nprobe
-    hipLaunchKernelGGL(coldot_kernel, dim3(nprobe), dim3(256), 0, c->st, (const z64*)V, (long)ldv, c->QAB, (long)n, n, t);
-    FM_LAUNCH_CHECK();
-    std::vector<z64> ht(nprobe);
-    FM_TRY(d2h(c, ht.data(), t, nprobe * sizeof(z64)));
-    for (int j = 0; j < nprobe; ++j) {
-        features[2 * j] = (float)ht[j].re;
-        features[2 * j + 1] = (float)ht[j].im;
-    }
-    double gre, gim, grad;
-    contour_circle(c->C, &gre, &gim, &grad);
-    features[2 * nprobe] = (float)gre;
-    features[2 * nprobe + 1] = (float)gim;
-    features[2 * nprobe + 2] = (float)grad;
+    FM_TRY(probe_enqueue(c, (const z64*)V, ldv, nprobe));
+    FM_HIP(hipStreamSynchronize(c->st));
+    probe_finish(c, nprobe, features);
     return 0;
 }
 
@@ -1932,6 +1981,54 @@ int batch_capture(feast_batch* bt, const LUSet& S) {
 
 }  // namespace
 
+// The streams of a call on a batch: the members' streams (with grouped launches, the set's stream,
+// which every member's direct launches then also use) start after the work on the caller's stream;
+// finish() synchronises them (the batch calls are synchronous) and gives the members their own
+// streams back.
+struct BatchStreams {
+    feast_batch* bt;
+    SetExec X;
+    hipEvent_t ev = nullptr;
+    int rc = 0;
+    explicit BatchStreams(feast_batch* b) : bt(b) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
+            rc = FEAST_EDEVICE;
+            return;
+        }
+        if (hipEventRecord(ev, bt->user) != hipSuccess) rc = FEAST_EDEVICE;
+        for (int i = 0; i < bt->count && !rc; ++i)
+            if (hipStreamWaitEvent(bt->streams[i], ev, 0) != hipSuccess) rc = FEAST_EDEVICE;
+        if (!bt->grouped) return;
+        if (!rc && hipStreamWaitEvent(bt->set_st, ev, 0) != hipSuccess) rc = FEAST_EDEVICE;
+        X.st = bt->set_st;
+        X.dev = bt->arena;
+        X.pin = bt->arena_pin;
+        X.cap = bt->arena_bytes;
+        X.timer = bt->timer.on ? &bt->timer : nullptr;
+        X.logs.assign(bt->count, OpLog());
+        for (feast_ctx* c : bt->ctx) {
+            X.pad_steps = std::max(X.pad_steps, trsolve_steps(c->lu));
+            c->st = bt->set_st;
+        }
+    }
+    int finish() {
+        int r = 0;
+        if (bt->grouped) {
+            if (hipStreamSynchronize(bt->set_st) != hipSuccess) r = FEAST_EDEVICE;
+            for (int i = 0; i < bt->count; ++i) bt->ctx[i]->st = bt->streams[i];
+        }
+        for (int i = 0; i < bt->count; ++i)
+            if (hipStreamSynchronize(bt->streams[i]) != hipSuccess) r = FEAST_EDEVICE;
+        if (ev) (void)hipEventDestroy(ev);
+        ev = nullptr;
+        return r;
+    }
+    ~BatchStreams() {
+        if (ev) (void)finish();
+    }
+};
+
 extern "C" {
 
 int feast_batch_workspace_size(int count, const int* n, const int* m0, const feast_contour* C, const feast_options* o,
@@ -2073,11 +2170,12 @@ int feast_batch_trace_estimates(feast_batch* bt, const void* V, int ldv, int npr
     if (ldv < n) return -3;
     for (feast_ctx* c : bt->ctx)
         if (c->n != n || nprobe > c->m0) return -4;
-    std::vector<float> f(2 * nprobe + 3);
+    std::vector<float> f((size_t)bt->count * (2 * nprobe + 3));
+    FM_TRY(feast_batch_probe_features(bt, V, ldv, nprobe, f.data()));
     for (int b = 0; b < bt->count; ++b) {
-        FM_TRY(feast_probe_features(bt->ctx[b], V, ldv, nprobe, f.data()));
+        const float* fb = f.data() + (size_t)b * (2 * nprobe + 3);
         double s = 0.0;
-        for (int j = 0; j < nprobe; ++j) s += f[2 * j];
+        for (int j = 0; j < nprobe; ++j) s += fb[2 * j];
         est[b] = s / nprobe;
     }
     return 0;
@@ -2115,7 +2213,8 @@ int feast_batch_iterate(feast_batch* bt, const void* const* U0, const int* ldu0,
     std::vector<Run*> ptrs;
     for (int b = 0; b < bt->count; ++b) {
         feast_ctx* c = bt->ctx[b];
-        if (!U0[b] || ldu0[b] < c->n) return -2;
+        if (!U0[b]) continue;   // a pencil left out of this call
+        if (ldu0[b] < c->n) return -2;
         feast_result* r = &res[b];
         if (!r->lambda || !r->resid || !r->X || r->ldx < c->n) return -4;
         if (c->o.variant == FEAST_BI && r->Y && r->ldy < c->n) return -4;
@@ -2125,41 +2224,49 @@ int feast_batch_iterate(feast_batch* bt, const void* const* U0, const int* ldu0,
         runs[b].res = r;
         ptrs.push_back(&runs[b]);
     }
-    // member streams (grouped launches: the set's stream) start after the caller's stream (the
-    // start blocks were written there) and the caller's stream continues after them
-    hipEvent_t ev = nullptr;
-    FM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     int rc = 0;
-    if (hipEventRecord(ev, bt->user) != hipSuccess) rc = FEAST_EDEVICE;
-    for (int b = 0; b < bt->count && !rc; ++b)
-        if (hipStreamWaitEvent(bt->streams[b], ev, 0) != hipSuccess) rc = FEAST_EDEVICE;
-    if (bt->grouped) {
-        if (!rc && hipStreamWaitEvent(bt->set_st, ev, 0) != hipSuccess) rc = FEAST_EDEVICE;
-        // every member's remaining direct launches (a re-factorisation) go to the set's stream too
-        SetExec X;
-        X.st = bt->set_st;
-        X.dev = bt->arena;
-        X.pin = bt->arena_pin;
-        X.cap = bt->arena_bytes;
-        X.timer = bt->timer.on ? &bt->timer : nullptr;
-        for (feast_ctx* c : bt->ctx) {
-            X.pad_steps = std::max(X.pad_steps, trsolve_steps(c->lu));
-            c->st = bt->set_st;
-        }
-        if (!rc) rc = drive(ptrs, &bt->timer, &X);
-        if (hipStreamSynchronize(bt->set_st) != hipSuccess && !rc) rc = FEAST_EDEVICE;
-        for (int b = 0; b < bt->count; ++b) bt->ctx[b]->st = bt->streams[b];
-    } else if (!rc) {
-        rc = drive(ptrs, &bt->timer);
+    if (!ptrs.empty()) {
+        BatchStreams S(bt);
+        rc = S.rc;
+        if (!rc) rc = bt->grouped ? drive(ptrs, &bt->timer, &S.X) : drive(ptrs, &bt->timer);
+        const int rc2 = S.finish();
+        if (!rc) rc = rc2;
     }
-    for (int b = 0; b < bt->count && !rc; ++b)
-        if (hipStreamSynchronize(bt->streams[b]) != hipSuccess) rc = FEAST_EDEVICE;
-    (void)hipEventDestroy(ev);
     for (int b = 0; b < bt->count; ++b) {
         if (member_rc) member_rc[b] = runs[b].rc;
         if (!rc && runs[b].rc) rc = runs[b].rc;
     }
     return rc;
+}
+
+int feast_batch_probe_features(feast_batch* bt, const void* V, int ldv, int nprobe, float* features) {
+    if (!bt) return -1;
+    if (!V) return -2;
+    if (!features) return -5;
+    if (nprobe < 1) return -4;
+    for (feast_ctx* c : bt->ctx) {
+        if (ldv < c->n) return -3;
+        if (nprobe > c->m0) return -4;
+    }
+    BatchStreams S(bt);
+    int rc = S.rc;
+    if (!rc) {
+        // the probe filters of all pencils, recorded and launched together (or one stream each)
+        for (int b = 0; b < bt->count && !rc; ++b) {
+            if (bt->grouped) {
+                S.X.logs[b].pad_steps = S.X.pad_steps;
+                op_log() = &S.X.logs[b];
+            }
+            rc = probe_enqueue(bt->ctx[b], (const z64*)V, ldv, nprobe);
+            op_log() = nullptr;
+        }
+        if (!rc && bt->grouped) rc = set_replay(S.X);
+    }
+    const int rc2 = S.finish();
+    if (!rc) rc = rc2;
+    if (rc) return rc;
+    for (int b = 0; b < bt->count; ++b) probe_finish(bt->ctx[b], nprobe, features + (size_t)b * (2 * nprobe + 3));
+    return 0;
 }
 
 void feast_batch_destroy(feast_batch* bt) { batch_free(bt); }

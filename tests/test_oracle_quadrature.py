@@ -119,3 +119,22 @@ def test_inside_strict():
     assert not Q.inside(np.array([1.0]), 0, 1.0)[0]
     assert Q.inside(np.array([0.45j]), 0, 1.0, 0.5)[0]
     assert not Q.inside(np.array([0.55j]), 0, 1.0, 0.5)[0]
+
+
+@pytest.mark.parametrize("rule", [TR, GL])
+@pytest.mark.parametrize("q", [8, 16, 24, 32])
+def test_filter_gain_is_at_least_one_half_inside(rule, q):
+    """|rho| > 1/2 everywhere inside the circle (for the trapezoid, |1 - w^q| < 2 when |w| < 1), the
+    bound behind the library's empty-contour rule in its low-precision modes: a Ritz vector that has
+    captured an eigenvector of an eigenvalue inside is amplified by at least 1/2, ten times its
+    threshold of 0.05; eigenvalues 1.5 radii or more from the centre stay below that threshold for
+    q >= 16 (at q = 8 the Gauss-Legendre filter does not, which only keeps the strict rule in force)."""
+    z, s = Q.nodes_and_weights(0.3 + 0.2j, 0.8, 1.0, rule, q)
+    g = rng(q + 100)
+    th = 2 * np.pi * g.random(20000)
+    w_in = np.sqrt(g.random(20000)) * 0.999 * np.exp(1j * th)
+    assert np.abs(Q.rho(0.3 + 0.2j + 0.8 * w_in, z, s)).min() > 0.5
+    w_out = (1.5 + 3.5 * g.random(20000)) * np.exp(1j * th)
+    out = np.abs(Q.rho(0.3 + 0.2j + 0.8 * w_out, z, s)).max()
+    if q >= 16:
+        assert out < 0.05 / 3
