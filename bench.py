@@ -267,6 +267,18 @@ def load_batch(count=64, device=None):
     return out
 
 
+def tune_tiles(fm, q, modes, dev):
+    """The trailing update's tile shape per row bucket, measured for each storage precision in use
+    and set in the library before timing (outside the timed region)."""
+    out = {}
+    for mode in sorted({("fp64" if m == "fp64" else "fp32") for m in modes}):
+        t = fm.binding.autotune_tiles(mode, q, device=dev)
+        out[mode] = [dict(rows_up_to=r, shape=shape, tflops={k: round(v, 1) for k, v in tf.items()})
+                     for r, shape, tf in t]
+        log(f"tile tuning {mode}, q={q}: " + ", ".join(f"<={r}: {shape}" for r, shape, _ in t))
+    return out
+
+
 def tune_panels(fm, q, modes, dev):
     """Panel crossover for each storage precision in use (outside the timed region)."""
     out = {}
@@ -369,6 +381,7 @@ def bench_batch(args, fm, torch, dev):
 
     modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32") if m != args.mode])
     tuning = tune_panels(fm, 16, modes, dev) if args.tune else None
+    tiles = tune_tiles(fm, 16, modes, dev)
     out = {}
     for mode in modes:
         for _ in range(args.warmup):
@@ -442,6 +455,7 @@ def bench_batch(args, fm, torch, dev):
         "timed_run_phases": phases,
         "roofline": roofline,
         "panel_tuning": tuning,
+        "tile_tuning": tiles,
         "cpu_baseline": cpu,
         "extra_workloads": extras or None,
     }
@@ -662,6 +676,8 @@ def m0_labels_and_features(fm, torch, dev, ids, V, chunk=512):
             ok += int(r.converged)
         del part
         torch.cuda.empty_cache()
+        if (i0 // chunk) % 8 == 7:
+            log(f"  labels of {len(labels)} pencils")
     return np.array(feats), np.array(labels, dtype=np.float64), np.array(construct), ok
 
 
@@ -846,6 +862,7 @@ def main():
 
     modes = [args.mode] + ([] if args.no_compare else [m for m in ("fp64", "fp32", "fp16") if m != args.mode])
     tuning = tune_panels(fm, P.q, modes, dev) if args.tune else None
+    tiles = tune_tiles(fm, P.q, modes, dev)
     out = {}
     for mode in modes:
         steps = args.steps if mode == args.mode else max(1, min(args.steps, 2))
@@ -951,6 +968,7 @@ def main():
         "roofline": roofline,
         "lu_update_roofline": lu_roof,
         "panel_tuning": tuning,
+        "tile_tuning": tiles,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

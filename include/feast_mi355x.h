@@ -346,6 +346,26 @@ int feast_autotune(int precision, int q, void* workspace, size_t workspace_bytes
                    const char* cache_path, int* single_rows, double* times);
 int feast_set_panel_rows(int precision, int q, int single_rows);
 
+/* Tile shapes of the LU trailing update (the dominant kernel of a
+ * factorisation, A22 -= L21 U12 on the matrix cores).  The library holds
+ * several compiled tile shapes per precision (FP32: 0 = 128 x 64, 1 = 64 x 64,
+ * 2 = 64 x 128; FP64: 0 = 64 x 64, 1 = 128 x 64) and, for the updates wider
+ * than one panel (the end of each group of four panels), a table that picks
+ * one by the update's row count, in six buckets (at most 256, 512, 1024, 2048,
+ * 4096 rows, and more); shape 0 until tuned and for one-panel-wide updates.  feast_autotune_tiles times every shape
+ * on a synthetic update of each bucket (rows = columns = 256 ... 6144, depth
+ * 256, up to q nodes) on `stream`, sets the table for `precision` (FP16 means
+ * its FP32 storage) in this process, and returns the chosen shapes in
+ * table[6] and the measured TFLOP/s in tflops[6 x 3] (bucket-major, 0 for
+ * shapes the precision lacks); either may be NULL.  The workspace (device,
+ * feast_autotune_tiles_workspace_size bytes) is overwritten.  Synchronous.
+ * feast_set_update_tile sets one entry directly.  Returns 0, -i,
+ * FEAST_EWORKSPACE, FEAST_EDEVICE. */
+int feast_autotune_tiles_workspace_size(int precision, int q, size_t* bytes);
+int feast_autotune_tiles(int precision, int q, void* workspace, size_t workspace_bytes, void* stream,
+                         int* table, double* tflops);
+int feast_set_update_tile(int precision, int bucket, int candidate);
+
 /* ---- a10: subspace size from stochastic trace features and a perceptron ------
  * The filter's trace counts the eigenvalues inside C (Section 3: rho is close to
  * 1 inside and to 0 outside), and for probe vectors v with E[v v^H] = I,

@@ -46,6 +46,7 @@ EXPORTED = [
     "feast_autotune_workspace_size", "feast_autotune", "feast_set_panel_rows",
     "feast_filter_shifted", "feast_estimate_m0", "feast_batch_timing_read",
     "feast_mlp_noalloc_max_elems", "feast_mlp_forward_noalloc", "feast_set_m0", "feast_batch_probe_features",
+    "feast_autotune_tiles_workspace_size", "feast_autotune_tiles", "feast_set_update_tile",
 ]
 
 
@@ -180,6 +181,12 @@ def lib():
         L.feast_m0_from_estimate.restype = i
         L.feast_mlp_destroy.argtypes = [vp]
         L.feast_mlp_destroy.restype = None
+        L.feast_autotune_tiles_workspace_size.argtypes = [i, i, ctypes.POINTER(ctypes.c_size_t)]
+        L.feast_autotune_tiles_workspace_size.restype = i
+        L.feast_autotune_tiles.argtypes = [i, i, vp, ctypes.c_size_t, vp, vp, vp]
+        L.feast_autotune_tiles.restype = i
+        L.feast_set_update_tile.argtypes = [i, i, i]
+        L.feast_set_update_tile.restype = i
         L.feast_batch_probe_features.argtypes = [vp, vp, i, i, vp]
         L.feast_batch_probe_features.restype = i
         L.feast_set_m0.argtypes = [vp, i]
@@ -863,6 +870,31 @@ def autotune(precision="fp32", q=16, cache_path=None, device="cuda"):
                                 None if cache_path is None else str(cache_path).encode(), ctypes.byref(rows),
                                 times.ctypes.data), "feast_autotune")
     return rows.value, times.reshape(10, 3)
+
+
+TILE_BUCKET_ROWS = [256, 512, 1024, 2048, 4096, None]   # upper row counts of the tile table's buckets
+TILE_SHAPES = {"fp32": ["128x64", "64x64", "64x128"], "fp64": ["64x64", "128x64"]}
+
+
+def autotune_tiles(precision="fp32", q=16, device="cuda"):
+    """Time the trailing update's tile shapes per row bucket and set the library's tile table;
+    returns [(bucket upper rows, chosen shape, {shape: TFLOP/s})]."""
+    torch = _torch()
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().feast_autotune_tiles_workspace_size(PRECISIONS[precision], q, ctypes.byref(nbytes)),
+           "feast_autotune_tiles_workspace_size")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+    table = np.zeros(6, dtype=np.int32)
+    tf = np.zeros(18, dtype=np.float64)
+    _check(lib().feast_autotune_tiles(PRECISIONS[precision], q, ws.data_ptr(), nbytes.value, _stream(),
+                                      table.ctypes.data, tf.ctypes.data), "feast_autotune_tiles")
+    shapes = TILE_SHAPES["fp64" if precision == "fp64" else "fp32"]
+    return [(TILE_BUCKET_ROWS[b], shapes[table[b]], {shapes[t]: float(tf[3 * b + t]) for t in range(len(shapes))})
+            for b in range(6)]
+
+
+def set_update_tile(precision, bucket, shape_index):
+    _check(lib().feast_set_update_tile(PRECISIONS[precision], int(bucket), int(shape_index)), "feast_set_update_tile")
 
 
 def set_panel_rows(precision, q, rows):

@@ -2402,6 +2402,156 @@ int feast_autotune(int precision, int q, void* workspace, size_t workspace_bytes
     return 0;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Synthetic trailing updates timed per bucket of the tile table: like the factorisation's own
+// launches, one grouped product over a set of members, here four square trailing blocks of
+// 1/4 .. 4/4 of the bucket's largest row count (256 ... 6144), depth 256 (a group of four panels),
+// up to q nodes each.
+constexpr int TILE_TUNE_M[UPDATE_TILE_BUCKETS] = {256, 512, 1024, 2048, 4096, 6144};
+constexpr int TILE_TUNE_K = 4 * NB;
+constexpr int TILE_TUNE_MEMBERS = 4;
+constexpr size_t TILE_TUNE_BUDGET = size_t(3) << 29;   // 1.5 GiB of operands per bucket
+
+int tile_tune_member_m(int bucket, int i) {
+    return std::max(NB, TILE_TUNE_M[bucket] * (i + 1) / TILE_TUNE_MEMBERS);
+}
+
+// nodes per member so that the bucket's operands fit the budget
+int tile_tune_batch(int bucket, int q, size_t E) {
+    size_t per = 0;
+    for (int i = 0; i < TILE_TUNE_MEMBERS; ++i) {
+        const size_t M = tile_tune_member_m(bucket, i);
+        per += (M * TILE_TUNE_K * 2 + M * M) * E;
+    }
+    return (int)std::max<size_t>(1, std::min<size_t>((size_t)q, TILE_TUNE_BUDGET / per));
+}
+
+size_t tile_tune_bytes(int q, bool dbl) {
+    const size_t E = dbl ? sizeof(z64) : sizeof(c32);
+    size_t most = 0;
+    for (int b = 0; b < UPDATE_TILE_BUCKETS; ++b) {
+        const size_t nb = (size_t)tile_tune_batch(b, q, E);
+        size_t bytes = align_up(TILE_TUNE_MEMBERS * sizeof(GemmGroup), ALIGN);
+        for (int i = 0; i < TILE_TUNE_MEMBERS; ++i) {
+            const size_t M = tile_tune_member_m(b, i);
+            bytes += align_up(nb * M * TILE_TUNE_K * E, ALIGN) * 2 + align_up(nb * M * M * E, ALIGN);
+        }
+        most = std::max(most, bytes);
+    }
+    return most;
+}
+
+template <typename T>
+int tune_tiles(int q, char* ws, hipStream_t st, int* table, double* times) {
+    const bool dbl = std::is_same<T, double>::value;
+    const size_t E = sizeof(cplx<T>);
+    const int nc = update_tile_candidates(dbl);
+    hipEvent_t e0, e1;
+    FM_HIP(hipEventCreate(&e0));
+    FM_HIP(hipEventCreate(&e1));
+    int rc = 0;
+    for (int b = 0; b < UPDATE_TILE_BUCKETS && !rc; ++b) {
+        const int K = TILE_TUNE_K, batch = tile_tune_batch(b, q, E);
+        GemmGroup* dev_groups = (GemmGroup*)ws;
+        char* o = ws + align_up(TILE_TUNE_MEMBERS * sizeof(GemmGroup), ALIGN);
+        std::vector<GemmGroup> groups;
+        double flops = 0.0;
+        int Mmax = 0;
+        for (int i = 0; i < TILE_TUNE_MEMBERS; ++i) {
+            const int M = tile_tune_member_m(b, i);
+            GemmGroup g;
+            g.A = o; o += align_up((size_t)batch * M * K * E, ALIGN);
+            g.B = o; o += align_up((size_t)batch * K * M * E, ALIGN);
+            g.C = o; o += align_up((size_t)batch * M * M * E, ALIGN);
+            g.lda = K; g.ldb = M; g.ldc = M;
+            g.sA = (long)M * K; g.sB = (long)K * M; g.sC = (long)M * M;
+            g.sA2 = g.sB2 = g.sC2 = 0;
+            g.M = M; g.N = M; g.K = K; g.batch = batch;
+            g.amax = nullptr;
+            groups.push_back(g);
+            flops += 8.0 * M * (double)M * K * batch;
+            Mmax = std::max(Mmax, M);
+        }
+        char* data = ws + align_up(TILE_TUNE_MEMBERS * sizeof(GemmGroup), ALIGN);
+        rc = lu_fill_random(data, (long)((o - data) / (long)sizeof(T)), dbl, 77 + b, st);
+        if (!rc && hipMemcpyAsync(dev_groups, groups.data(), groups.size() * sizeof(GemmGroup), hipMemcpyHostToDevice,
+                                  st) != hipSuccess)
+            rc = FEAST_EDEVICE;
+        GemmOp g;
+        g.rowA = g.rowB = g.rowC = true;
+        g.M = Mmax; g.N = Mmax; g.K = K; g.batch = batch;
+        g.alpha = z64(-1.0); g.beta = z64(1.0);
+        g.kind = 1;
+        g.groups = dev_groups;
+        g.ngroups = TILE_TUNE_MEMBERS;
+        double best = 1e30;
+        int arg = 0;
+        for (int t = 0; t < nc && !rc; ++t) {
+            g.tile = t;
+            double tmin = 1e30;
+            for (int rep = 0; rep < 4 && !rc; ++rep) {
+                float ms = 0.0f;
+                if (hipEventRecord(e0, st) != hipSuccess) rc = FEAST_EDEVICE;
+                if (!rc) rc = gemm<T>(g, st);
+                if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = FEAST_EDEVICE;
+                if (!rc && rep > 0) tmin = std::min(tmin, (double)ms);   // the first launch warms up
+            }
+            if (times) times[b * 3 + t] = flops / (tmin * 1e-3) / 1e12;
+            if (tmin < best) {
+                best = tmin;
+                arg = t;
+            }
+        }
+        if (times)
+            for (int t = nc; t < 3; ++t) times[b * 3 + t] = 0.0;
+        if (!rc) {
+            update_tile_set(dbl, b, arg);
+            if (table) table[b] = arg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int feast_autotune_tiles_workspace_size(int precision, int q, size_t* bytes) {
+    if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -1;
+    if (q < 1) return -2;
+    if (!bytes) return -3;
+    *bytes = tile_tune_bytes(q, precision == FEAST_FP64);
+    return 0;
+}
+
+int feast_autotune_tiles(int precision, int q, void* workspace, size_t workspace_bytes, void* stream, int* table,
+                         double* tflops) {
+    if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -1;
+    if (q < 1) return -2;
+    const bool dbl = precision == FEAST_FP64;
+    if (!workspace || ((uintptr_t)workspace % ALIGN) || workspace_bytes < tile_tune_bytes(q, dbl))
+        return FEAST_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    return dbl ? tune_tiles<double>(q, (char*)workspace, st, table, tflops)
+               : tune_tiles<float>(q, (char*)workspace, st, table, tflops);
+}
+
+int feast_set_update_tile(int precision, int bucket, int candidate) {
+    if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -1;
+    if (bucket < 0 || bucket >= UPDATE_TILE_BUCKETS) return -2;
+    const bool dbl = precision == FEAST_FP64;
+    if (candidate < 0 || candidate >= update_tile_candidates(dbl)) return -3;
+    update_tile_set(dbl, bucket, candidate);
+    return 0;
+}
+
 int feast_set_panel_rows(int precision, int q, int single_rows) {
     if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -1;
     if (q < 1) return -2;

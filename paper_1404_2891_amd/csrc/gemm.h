@@ -59,7 +59,20 @@ struct GemmOp {
     const GemmGroup* groups = nullptr;
     int ngroups = 0;
     bool inplace = false;
+    // kind 1: the tile candidate to use (-1: the one the tile table holds for this M)
+    int tile = -1;
 };
+
+// Tile candidates of the LU trailing update (kind 1), compiled in: FP32 0 = 128 x 64 (each wave
+// 4 x 2 blocks of 16 x 16), 1 = 64 x 64, 2 = 64 x 128; FP64 0 = 64 x 64, 1 = 128 x 64.  For updates
+// wider than one panel (64 columns) a table maps the row count, in buckets of at most 256, 512,
+// 1024, 2048, 4096 and more rows, to a candidate (0 until the tile tuner sets it); one-panel-wide
+// updates take candidate 0.
+constexpr int UPDATE_TILE_BUCKETS = 6;
+int update_tile_candidates(bool dbl);
+int update_tile_bucket(int M);
+int update_tile_get(bool dbl, int bucket);
+void update_tile_set(bool dbl, int bucket, int candidate);
 
 // T = double (complex128 operands, FP64 MFMA) or float (complex64, FP32 MFMA).
 template <typename T>

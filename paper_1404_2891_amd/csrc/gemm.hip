@@ -8,6 +8,7 @@
 // order, so the 16 lanes of an MFMA row group read consecutive addresses; the next tile
 // is fetched into registers while the current one is consumed.
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "gemm.h"
@@ -488,7 +489,9 @@ void launch_cfg(Params<T> p, hipStream_t st) {
     constexpr int BM = WM * RB * 16, BN = WN * CB * 16;
     p.tiles_m = ceil_div(p.M, BM);
     p.tiles_n = ceil_div(p.N, BN);
-    p.xcd_order = KIND == 1 ? 1 : 0;
+    // (a grouped launch keeps the plain order: its smaller members' tiles sit in the first rows and
+    // columns of the grid, which the XCD order would hand to one XCD)
+    p.xcd_order = (KIND == 1 && !p.groups) ? 1 : 0;
     const int tiles = p.tiles_m * p.tiles_n;
     dim3 grid(p.xcd_order ? (tiles + 7) / 8 * 8 : tiles, 1,
               p.batch * p.splitk * p.batch2 * (p.groups ? p.ngroups : 1));
@@ -565,13 +568,24 @@ int gemm(const GemmOp& op, hipStream_t st) {
     }
     if (op.kind == 1) {  // LU trailing update: all operands row-major
         if (!(op.rowA && op.rowB && op.rowC) || p.splitk > 1) return FEAST_EUNSUPPORTED;
-        // FP32: 128 x 64 tiles (each wave 4 x 2 blocks: more products per LDS read, 101 against
-        // 96 TFLOP/s on the n = 4096 update); FP64 keeps 64 x 64 (its accumulators are twice as
-        // large; 128 x 64 lost there, as did 128 x 128 in FP32)
-        if constexpr (std::is_same<T, float>::value)
-            launch_cfg<T, 2, 2, 4, 2, true, true, true, 1>(p, st);
-        else
-            launch_cfg<T, 2, 2, 2, 2, true, true, true, 1>(p, st);
+        constexpr bool dbl = std::is_same<T, double>::value;
+        // the table covers the updates at the end of a group of panels (all columns right of it);
+        // those inside a group are one panel wide, which shape 0 fits
+        const int tile = op.tile >= 0 ? op.tile : (p.N <= 64 ? 0 : update_tile_get(dbl, update_tile_bucket(p.M)));
+        if (tile < 0 || tile >= update_tile_candidates(dbl)) return FEAST_EUNSUPPORTED;
+        if constexpr (!dbl) {
+            if (tile == 0)
+                launch_cfg<T, 2, 2, 4, 2, true, true, true, 1>(p, st);
+            else if (tile == 1)
+                launch_cfg<T, 2, 2, 2, 2, true, true, true, 1>(p, st);
+            else
+                launch_cfg<T, 2, 2, 2, 4, true, true, true, 1>(p, st);
+        } else {
+            if (tile == 0)
+                launch_cfg<T, 2, 2, 2, 2, true, true, true, 1>(p, st);
+            else
+                launch_cfg<T, 2, 2, 4, 2, true, true, true, 1>(p, st);
+        }
         FM_LAUNCH_CHECK();
         return 0;
     }
@@ -604,6 +618,22 @@ int gemm(const GemmOp& op, hipStream_t st) {
     }
     return 0;
 }
+
+namespace {
+std::atomic<int> g_update_tile[2][UPDATE_TILE_BUCKETS];   // zero-initialised: candidate 0
+}
+
+int update_tile_candidates(bool dbl) { return dbl ? 2 : 3; }
+
+int update_tile_bucket(int M) {
+    int b = 0;
+    for (int lim = 256; b < UPDATE_TILE_BUCKETS - 1 && M > lim; lim *= 2) ++b;
+    return b;
+}
+
+int update_tile_get(bool dbl, int bucket) { return g_update_tile[dbl ? 1 : 0][bucket].load(); }
+
+void update_tile_set(bool dbl, int bucket, int candidate) { g_update_tile[dbl ? 1 : 0][bucket].store(candidate); }
 
 template <typename T>
 GemmGroup gemm_member(const GemmOp& op) {

@@ -102,3 +102,33 @@ def test_tournament_pivoting_iteration(variant):
     r = F.iterate(fm().to_device(U0, device()))
     assert r.converged and match_eigs(r.lam, brute.eigenvalues_inside(lam, 0j, 1.0)) < 1e-10
     F.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_update_tile_shapes_agree_and_the_tuner_sets_the_table(prec):
+    """Every compiled tile shape of the trailing update sums each output in the same order (the
+    same operand slices, the same matrix-core steps), so factorisations made with any of them give
+    bit-identical filters; the tuner then picks a shape per row bucket, sets the table and reports a
+    throughput for every shape it timed."""
+    import torch
+    from tests.gpu_common import random_pencil
+    fmod = fm()
+    A, B, lam = random_pencil(700, 31, True)
+    dA, dB = fmod.to_device(A, device()), fmod.to_device(B, device())
+    U = fmod.to_device(pencils.start_block(2, 700, 12, salt=5), device())
+    shapes = fmod.binding.TILE_SHAPES["fp64" if prec == "fp64" else "fp32"]
+    outs = []
+    for t in range(len(shapes)):
+        for b in range(6):
+            fmod.binding.set_update_tile(prec, b, t)
+        with fmod.Feast(dA, dB, 0j, 1.0, 1.0, 16, 12, precision=prec) as F:
+            outs.append(F.filter(U).clone())
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    table = fmod.binding.autotune_tiles(prec, 16, device=device())
+    assert len(table) == 6
+    for rows, shape, tf in table:
+        assert shape in shapes and set(tf) == set(shapes) and all(v > 0 for v in tf.values())
+    for b in range(6):
+        fmod.binding.set_update_tile(prec, b, 0)
