@@ -154,6 +154,13 @@ typedef struct {
                             run the same kernel become one launch reading each pencil's operands
                             from a device table); 1: each pencil enqueues its own launches on a
                             stream of its own.  Both give the same results bit for bit. */
+    int host_ortho;      /* feast_iterate's orthonormalisation (shifted Cholesky-QR, three passes):
+                            0 (default) the Gram matrices are factored and inverted on the device,
+                            so the filter, the three passes and the Rayleigh-Ritz products run
+                            without a host synchronisation; 1 they are factored on the host (one
+                            round trip per pass).  The first iteration with rank_check = 1
+                            factors on the host in both cases (the rank needs the Gram matrix's
+                            eigenvalues).  Both reach the same subspace to rounding. */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */
@@ -244,8 +251,10 @@ int feast_node_solve(feast_ctx* ctx, int k, int side, int ncols, const void* R, 
  * or the left-projector variant (FEAST_L: U <- B^-H rho(M)^H B^H U, Rayleigh-Ritz
  * with U^H A^H U and U^H B^H U, whose Ritz values are the conjugates of the
  * eigenvalues), from the start block U0 (device n x m0).  After each filter the basis is
- * orthonormalised (shifted Cholesky-QR, FP64); the reduced m0 x m0 problem is
- * solved on the host; candidates are Ritz pairs inside C with paper-form
+ * orthonormalised (shifted Cholesky-QR, FP64, three passes; the Gram matrices
+ * factored on the device unless feast_options.host_ortho = 1, so that one host
+ * synchronisation per iteration precedes the reduced problem); the reduced
+ * m0 x m0 problem is solved on the host; candidates are Ritz pairs inside C with paper-form
  * residual <= candidate_tol.  Stops when all candidates have relative residual
  * <= tol and the count repeats (an empty set counts once no Ritz value lies
  * inside in two consecutive iterations).  Synchronous.
@@ -308,8 +317,9 @@ int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, do
  * inverses, U12), the multi-RHS node solves (8 n^2 ncols q per launch group),
  * the FP64 refinement residuals, and the Rayleigh-Ritz products.  Four more
  * report the host's wall time during feast_iterate (feast_batch_iterate: the
- * whole batch's, once): the reduced eigenproblems, the Cholesky factorisations
- * of the orthonormalisation, the driver (enqueueing the device phases and the
+ * whole batch's, once): the reduced eigenproblems, the host Cholesky
+ * factorisations of the orthonormalisation (host_ortho = 1, or the first
+ * iteration under rank_check; zero otherwise), the driver (enqueueing the device phases and the
  * convergence bookkeeping), and the waits at the iteration's synchronisation
  * points; they add up to the iteration's wall time. */
 enum {

@@ -65,7 +65,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int),
-                ("pivoting", ctypes.c_int), ("conj_nodes", ctypes.c_int), ("batch_launch", ctypes.c_int)]
+                ("pivoting", ctypes.c_int), ("conj_nodes", ctypes.c_int), ("batch_launch", ctypes.c_int),
+                ("host_ortho", ctypes.c_int)]
 
 
 class PhaseTime(ctypes.Structure):
@@ -253,7 +254,7 @@ CONJ_NODES = {"none": 0, "real": 1, "hermitian": 2}
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
                  ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament", conj_nodes="none",
-                 batch_launch="grouped") -> Options:
+                 batch_launch="grouped", host_ortho=False) -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -268,6 +269,7 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.pivoting = PIVOTING[pivoting]
     o.conj_nodes = CONJ_NODES[conj_nodes]
     o.batch_launch = BATCH_LAUNCH[batch_launch]
+    o.host_ortho = int(bool(host_ortho))
     return o
 
 
@@ -368,7 +370,7 @@ class Feast:
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
                  timing=False, workspace=None, rank_check=False, pivoting="tournament", pieces=None,
-                 conj_nodes="none"):
+                 conj_nodes="none", host_ortho=False):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
@@ -376,7 +378,7 @@ class Feast:
         self.A, self.B = A, B
         self.contour = make_contour(center, radius, aspect, q, rule, pieces)
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check, pivoting, conj_nodes)
+                                    rank_check, pivoting, conj_nodes, host_ortho=host_ortho)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
         if workspace is not None:
             if workspace.numel() < nbytes or workspace.data_ptr() % 256:
@@ -520,7 +522,7 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False, pivoting="tournament", timing=False, batch_launch="grouped"):
+                 rank_check=False, pivoting="tournament", timing=False, batch_launch="grouped", host_ortho=False):
         torch = _torch()
         count = len(pencils)
         self.count = count
@@ -530,7 +532,7 @@ class FeastBatch:
         if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
             contours = [contours] * count
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check, pivoting, batch_launch=batch_launch)
+                                    rank_check, pivoting, batch_launch=batch_launch, host_ortho=host_ortho)
         C = (Contour * count)(*[make_contour(q=q, rule=rule, pieces=e) if isinstance(e, list)
                                 else make_contour(e[0], e[1], e[2], q, rule) for e in contours])
         self._C = C

@@ -97,6 +97,8 @@ struct feast_ctx {
     z64* lamL_d = nullptr;                  // conj of the adjoint Ritz values (left-projector variant)
     z64 *T2 = nullptr, *GL_d = nullptr, *RinvL_d = nullptr, *rhoL_d = nullptr, *Ginv_d = nullptr;
     z64 *G_d = nullptr, *Rinv_d = nullptr, *AhBh = nullptr, *W_d = nullptr, *Z_d = nullptr, *lam_d = nullptr;
+    z64* Wc_d = nullptr;             // work block of the device Cholesky factorisations (p x p)
+    double* ostat_d = nullptr;       // their failure flag and the largest Gram diagonal entry
     double* norms_d = nullptr;
     int* idx_d = nullptr;
     void* partial = nullptr;
@@ -117,6 +119,7 @@ struct feast_ctx {
         z64* G2inv = nullptr;
         double* norms = nullptr;             // 3 p residual norms
         int* idx = nullptr;                  // output column order (p)
+        double* ostat = nullptr;             // device orthonormalisation: failure flag, Gram max
     } pin;
     char* pin_base = nullptr;
     // refinement: forward-error target of the next filter, statistics of the last one
@@ -199,6 +202,8 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     c->G_d = b.take<z64>((size_t)p * p);
     c->Rinv_d = b.take<z64>((size_t)p * p);
     c->AhBh = b.take<z64>((size_t)2 * p * p);
+    c->Wc_d = b.take<z64>((size_t)p * p);
+    c->ostat_d = b.take<double>(2);
     c->W_d = b.take<z64>((size_t)p * p);
     c->Z_d = b.take<z64>((size_t)p * p);
     c->lam_d = b.take<z64>(p);
@@ -298,7 +303,8 @@ int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
     if (n < 1) return -1;
     if (contour_check(C) != 0) return -2;
     if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI && o->variant != FEAST_L) ||
-        o->pivoting < 0 || o->pivoting > 1 || o->conj_nodes < FEAST_CONJ_NONE || o->conj_nodes > FEAST_CONJ_HERMITIAN)
+        o->pivoting < 0 || o->pivoting > 1 || o->conj_nodes < FEAST_CONJ_NONE || o->conj_nodes > FEAST_CONJ_HERMITIAN ||
+        o->batch_launch < 0 || o->batch_launch > 1 || o->host_ortho < 0 || o->host_ortho > 1)
         return -3;
     if (m0 < 1 || m0 > n) return -4;
     if (o->conj_nodes != FEAST_CONJ_NONE) {
@@ -785,7 +791,7 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
     c->hbytes = std::max<size_t>(c->hbytes, (size_t)c->lu_ngroups * sizeof(GemmGroup) + sizeof(LUDev));
     const size_t pp = (size_t)p * p;
-    const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp;
+    const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp + 1;
     const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
     c->h = (char*)pinned_pool().get(c->hbytes);
     c->pin_base = c->h ? (char*)pinned_pool().get(pin_bytes) : nullptr;
@@ -807,6 +813,7 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     c->pin.rho[1] = t; t += p;
     c->pin.G2 = t; t += pp;
     c->pin.G2inv = t; t += pp;
+    c->pin.ostat = (double*)t; t += 1;
     c->pin.norms = (double*)t;
     c->pin.idx = (int*)(c->pin.norms + 3 * p);
     const int rc2 = ctx_tables(c, C);
@@ -899,6 +906,7 @@ void feast_default_options(feast_options* o) {
     o->pivoting = 1;
     o->conj_nodes = FEAST_CONJ_NONE;
     o->batch_launch = 0;
+    o->host_ortho = 0;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -1067,6 +1075,8 @@ struct Run {
     // largest filter gain ||rho(M) x_j|| over the unit-norm Ritz vectors of the previous iteration
     // (measured by the next filter; NaN before the second iteration) and the one before it
     double gain = NAN, gain_prev = NAN;
+    // this iteration orthonormalises on the device (no host factorisation between the passes)
+    bool dev_ortho = false;
     std::vector<int> order;
     std::vector<double> rel, paper;
     std::vector<cd> lam;
@@ -1127,6 +1137,8 @@ int e_filter(Run& r) {
     const long np = (long)n * p;
     hipStream_t st = c->st;
     ++r.it;
+    // the rank check of the first iteration needs the Gram matrix's eigenvalues on the host
+    r.dev_ortho = !c->o.host_ortho && !(r.it == 1 && c->o.rank_check);
     // FP64 correction of the low-precision solves.  With ir_tol > 0 every filter runs classic
     // refinement sweeps to that target.  With ir_tol = 0 (default) the first filter is the plain
     // low-precision one (a target of 1e-3 skips the sweeps: the start block is random, so FP32
@@ -1155,7 +1167,7 @@ int e_filter(Run& r) {
         FM_TRY(filter_impl(c, fside, p, U, n, c->QAB, n));
     }
     FM_TRY(gram(c, c->QAB, n, c->QAB, n, p, c->G_d));
-    FM_TRY(d2h_async(c, c->pin.G[0], c->G_d, (size_t)p * p * sizeof(z64)));
+    if (!r.dev_ortho) FM_TRY(d2h_async(c, c->pin.G[0], c->G_d, (size_t)p * p * sizeof(z64)));
     if (is_bi(c)) {
         if (shifted) {
             // E_L = A^H V - B^H V conj(L), conj(rho)
@@ -1175,15 +1187,20 @@ int e_filter(Run& r) {
             FM_TRY(filter_impl(c, 1, p, c->Vb, n, c->Pb, n));
         }
         FM_TRY(gram(c, c->Pb, n, c->Pb, n, p, c->GL_d));
-        FM_TRY(d2h_async(c, c->pin.G[1], c->GL_d, (size_t)p * p * sizeof(z64)));
+        if (!r.dev_ortho) FM_TRY(d2h_async(c, c->pin.G[1], c->GL_d, (size_t)p * p * sizeof(z64)));
     }
     return 0;
 }
+
+// shift of the first Cholesky-QR pass, relative to the Gram matrix's trace: 11 (n p + p (p + 1)) u
+// with u = 2^-53
+double ortho_shift_coef(int n, int p) { return 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16; }
 
 // host: Cholesky of the Gram matrix (shifted on pass 0), R^-1 to the device
 int h_chol(Run& r, int pass) {
     feast_ctx* c = r.c;
     const int n = c->n, p = c->m0;
+    if (r.dev_ortho) return 0;
     for (int side = 0; side < (is_bi(c) ? 2 : 1); ++side) {
         host::Mat G = to_mat(c->pin.G[side], p), R;
         if (pass == 0 && side == 0 && r.it == 1 && c->o.rank_check) {
@@ -1207,7 +1224,7 @@ int h_chol(Run& r, int pass) {
             r.gain_prev = r.gain;
             r.gain = std::sqrt(gmax);
         }
-        double shift = pass == 0 ? 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * tr : 0.0;
+        double shift = pass == 0 ? ortho_shift_coef(n, p) * tr : 0.0;
         bool ok = false;
         for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
             host::Mat Gs = G;
@@ -1229,6 +1246,28 @@ int e_orth(Run& r, int pass) {
     const int n = c->n, p = c->m0;
     const long np = (long)n * p;
     hipStream_t st = c->st;
+    if (r.dev_ortho) {
+        // all three passes at once, the factorisations on the device; the failure flag and the
+        // largest diagonal entry of the first Gram matrix come back with the reduced pair
+        if (pass > 0) return 0;
+        const double coef = ortho_shift_coef(n, p);
+        for (int side = 0; side < (is_bi(c) ? 2 : 1); ++side) {
+            z64* X = side_X(c, side);
+            z64* T = side_T(c, side);
+            z64* Ri = side_Rinv(c, side);
+            for (int k = 0; k < 3; ++k) {
+                z64* src = (k == 1) ? T : X;
+                z64* dst = (k == 1) ? X : T;
+                FM_TRY(chol_inverse(side_G(c, side), c->Wc_d, Ri, p, k == 0 ? coef : 0.0, c->ostat_d,
+                                    side == 0 && k == 0, st));
+                FM_TRY(right_mult(c, src, n, Ri, dst, n));
+                if (k < 2) FM_TRY(gram(c, dst, n, dst, n, p, side_G(c, side)));
+            }
+            FM_TRY(copy_cm(X, n, T, n, n, p, st));
+        }
+        FM_TRY(d2h_async(c, c->pin.ostat, c->ostat_d, 2 * sizeof(double)));
+        pass = 2;
+    } else
     for (int side = 0; side < (is_bi(c) ? 2 : 1); ++side) {
         z64* X = side_X(c, side);
         z64* T = side_T(c, side);
@@ -1262,6 +1301,13 @@ int e_orth(Run& r, int pass) {
 int h_eig(Run& r) {
     feast_ctx* c = r.c;
     const int p = c->m0;
+    if (r.dev_ortho) {
+        if (c->pin.ostat[0] != 0.0) return FEAST_EREDUCED;
+        if (r.it >= 2) {
+            r.gain_prev = r.gain;
+            r.gain = std::sqrt(c->pin.ostat[1]);
+        }
+    }
     int rc = reduced_eig_impl(p, (const double*)c->pin.AhBh, (const double*)(c->pin.AhBh + (size_t)p * p),
                               (double*)c->pin.lam, (double*)c->pin.W, is_bi(c) ? (double*)c->pin.Z : nullptr,
                               !is_bi(c) && c->B == nullptr);
@@ -1655,10 +1701,15 @@ int drive(std::vector<Run*>& runs, Timer* wall, SetExec* X = nullptr) {
         w.start();
         FM_TRY(sync_runs(runs, X));
         w.stop(PH_HOST_WAIT);
-        for (int pass = 0; pass < 3; ++pass) {
-            w.start();
-            FM_TRY(each_host(runs, [pass](Run& r) { return h_chol(r, pass); }, X));
-            w.stop(PH_HOST_ORTHO);
+        // the host factorisations take a round trip per pass; the device ones need none
+        bool host_passes = false;
+        for (Run* r : runs) host_passes |= r->active && !r->dev_ortho;
+        for (int pass = 0; pass < (host_passes ? 3 : 1); ++pass) {
+            if (host_passes) {
+                w.start();
+                FM_TRY(each_host(runs, [pass](Run& r) { return h_chol(r, pass); }, X));
+                w.stop(PH_HOST_ORTHO);
+            }
             w.start();
             FM_TRY(each(runs, [pass](Run& r) { return e_orth(r, pass); }, X));
             w.stop(PH_HOST_DRIVER);

@@ -19,7 +19,8 @@ namespace fm {
 enum RecKind { REC_NOP = 0, REC_GEMM = 1, REC_EW = 2, REC_COPY = 3, REC_MARK = 4, REC_OTHER = 5 };
 
 // Element-wise kernels that have a grouped form (solve.hip).
-enum EwKind { EW_GATHER_F32 = 0, EW_GATHER_F64, EW_ACCUM_F32, EW_ACCUM_F64, EW_RESIDUAL, EW_COPY_CM, EW_RITZ, EW_COUNT };
+enum EwKind { EW_GATHER_F32 = 0, EW_GATHER_F64, EW_ACCUM_F32, EW_ACCUM_F64, EW_RESIDUAL, EW_COPY_CM, EW_RITZ, EW_CHOL,
+              EW_COUNT };
 
 constexpr int EW_ARG_BYTES = 192;
 

@@ -68,6 +68,13 @@ int node_norm1(const z64* A, long lda, const z64* B, long ldb, int n, const z64*
 int ritz_residual_norms(const z64* X, const z64* AX, const z64* BX, long ld, int n, int p, const z64* lam,
                         double* out, hipStream_t st);
 
+// Rinv = R^-1 for the upper Cholesky factor of G + s I (p x p, column-major, ld p; W is p x p work
+// space): s = shift_coef trace(G), raised on failure; stat[0] = 1 when no attempt succeeds.  With
+// `first`, stat[0] is cleared beforehand and stat[1] receives the largest diagonal entry of G.
+// One workgroup.
+int chol_inverse(const z64* G, z64* W, z64* Rinv, int p, double shift_coef, double* stat, bool first,
+                 hipStream_t st);
+
 // R_k += alpha_k Y_k (row-major FP64 blocks; alpha is a device array of q values)
 int axpy_rows(Rows<double> R, const Rows<double>& Y, const z64* alpha, int n, int ncols, int q, hipStream_t st);
 

@@ -205,6 +205,95 @@ __device__ inline void copy_body(const CopyArgs& a, long t) {
     a.dst[i + (long)j * a.ldd] = a.src[i + (long)j * a.lds];
 }
 
+struct CholArgs {
+    const z64* G; z64* W; z64* Rinv; int p; double shift_coef;
+    double* stat;   // [0] failure flag (1.0 on failure), [1] largest diagonal entry of G
+    int first;      // first factorisation of an iteration: clears stat[0] and records stat[1]
+};
+
+constexpr int CHOL_LDS_P = 64;   // orders up to this keep the factor in LDS
+
+// R^-1 for the Cholesky factor R (upper, R^H R = G + s I) of a p x p Hermitian Gram matrix (column-
+// major, ld p), one workgroup: s = shift_coef * trace(G) (0 for the plain passes), and on a
+// non-positive pivot s is raised (x100, or to 1e-15 trace from 0) up to eight times; when every
+// attempt fails, or the trace is not positive and finite, stat[0] is set and Rinv is left as it
+// was.  The factor is formed right-looking (row k of R, then the trailing block) in LDS for
+// p <= CHOL_LDS_P, else in the work block W; the inverse one column per thread by back
+// substitution.
+__device__ inline void chol_body(const CholArgs& a) {
+    __shared__ double sh[16];
+    __shared__ int ok_s;
+    __shared__ z64 lds[CHOL_LDS_P * CHOL_LDS_P];
+    const int p = a.p, tid = threadIdx.x, nt = blockDim.x;
+    z64* W = p <= CHOL_LDS_P ? lds : a.W;
+    double tr = 0.0, dmax = 0.0;
+    for (int i = tid; i < p; i += nt) {
+        const double d = a.G[i + (long)i * p].re;
+        tr += d;
+        dmax = fmax(dmax, d);
+    }
+    tr = block_sum(tr, sh);
+    dmax = block_max(dmax, sh + 8);
+    if (a.first && tid == 0) {
+        a.stat[0] = 0.0;
+        a.stat[1] = dmax;
+    }
+    if (!(tr > 0.0) || !isfinite(tr)) {
+        if (tid == 0) a.stat[0] = 1.0;
+        return;
+    }
+    double shift = a.shift_coef * tr;
+    bool ok = false;
+    for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
+        for (long e = tid; e < (long)p * p; e += nt) {
+            const int i = e % p, j = e / p;
+            z64 v = i <= j ? a.G[e] : z64(0.0, 0.0);
+            if (i == j) v.re += shift;
+            W[e] = v;
+        }
+        if (tid == 0) ok_s = 1;
+        __syncthreads();
+        for (int k = 0; k < p; ++k) {
+            const double d = W[k + (long)k * p].re;
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (tid == 0) ok_s = 0;
+                __syncthreads();
+                break;
+            }
+            const double rkk = sqrt(d);
+            for (int j = k + 1 + tid; j < p; j += nt) {
+                const z64 v = W[k + (long)j * p];
+                W[k + (long)j * p] = z64(v.re / rkk, v.im / rkk);
+            }
+            __syncthreads();
+            if (tid == 0) W[k + (long)k * p] = z64(rkk, 0.0);
+            const int m = p - k - 1;
+            for (long e = tid; e < (long)m * m; e += nt) {
+                const int i = k + 1 + (int)(e % m), j = k + 1 + (int)(e / m);
+                if (i <= j) W[i + (long)j * p] = W[i + (long)j * p] - conj(W[k + (long)i * p]) * W[k + (long)j * p];
+            }
+            __syncthreads();
+        }
+        ok = ok_s != 0;
+        __syncthreads();   // every thread has read ok_s before the next attempt resets it
+        shift = shift > 0.0 ? shift * 100.0 : 1e-15 * tr;
+    }
+    if (!ok) {
+        if (tid == 0) a.stat[0] = 1.0;
+        return;
+    }
+    for (int j = tid; j < p; j += nt) {
+        z64* X = a.Rinv + (long)j * p;
+        for (int i = j + 1; i < p; ++i) X[i] = z64(0.0, 0.0);
+        X[j] = cdiv(z64(1.0, 0.0), W[j + (long)j * p]);
+        for (int i = j - 1; i >= 0; --i) {
+            z64 s(0.0, 0.0);
+            for (int k = i + 1; k <= j; ++k) s = s + W[i + (long)k * p] * X[k];
+            X[i] = z64(0.0, 0.0) - cdiv(s, W[i + (long)i * p]);
+        }
+    }
+}
+
 // One kernel per element-wise operation: the direct launch takes the argument block by value, the
 // grouped launch reads block blockIdx.z of a device table.
 template <int EW>
@@ -217,6 +306,7 @@ __device__ inline void ew_dispatch(const void* args) {
     if constexpr (EW == EW_RESIDUAL) residual_body(*(const ResidualArgs*)args, t);
     if constexpr (EW == EW_COPY_CM) copy_body(*(const CopyArgs*)args, t);
     if constexpr (EW == EW_RITZ) ritz_body(*(const RitzArgs*)args, blockIdx.x);
+    if constexpr (EW == EW_CHOL) chol_body(*(const CholArgs*)args);
 }
 
 template <int EW, typename A>
@@ -237,6 +327,7 @@ template <> struct EwArgs<EW_ACCUM_F64> { typedef AccumArgs type; };
 template <> struct EwArgs<EW_RESIDUAL> { typedef ResidualArgs type; };
 template <> struct EwArgs<EW_COPY_CM> { typedef CopyArgs type; };
 template <> struct EwArgs<EW_RITZ> { typedef RitzArgs type; };
+template <> struct EwArgs<EW_CHOL> { typedef CholArgs type; };
 
 // Enqueue (or record) element-wise kernel EW over a grid of bx x by workgroups of 256 threads.
 template <int EW>
@@ -457,6 +548,12 @@ int ritz_residual_norms(const z64* X, const z64* AX, const z64* BX, long ld, int
     return ew_launch<EW_RITZ>(a, (unsigned)p, 1, st);
 }
 
+int chol_inverse(const z64* G, z64* W, z64* Rinv, int p, double shift_coef, double* stat, bool first,
+                 hipStream_t st) {
+    CholArgs a{G, W, Rinv, p, shift_coef, stat, first ? 1 : 0};
+    return ew_launch<EW_CHOL>(a, 1, 1, st);
+}
+
 int axpy_rows(Rows<double> R, const Rows<double>& Y, const z64* alpha, int n, int ncols, int q, hipStream_t st) {
     if (OpLog* L = op_log()) {
         L->other([=](hipStream_t s) { return axpy_rows(R, Y, alpha, n, ncols, q, s); });
@@ -503,6 +600,7 @@ size_t ew_arg_size(int ew) {
         case EW_RESIDUAL: return sizeof(ResidualArgs);
         case EW_COPY_CM: return sizeof(CopyArgs);
         case EW_RITZ: return sizeof(RitzArgs);
+        case EW_CHOL: return sizeof(CholArgs);
     }
     return 0;
 }
@@ -517,6 +615,7 @@ int ew_grouped(int ew, const void* table, int ngroups, unsigned max_bx, unsigned
         case EW_RESIDUAL: return ew_grouped_one<EW_RESIDUAL>(table, ngroups, max_bx, max_by, st);
         case EW_COPY_CM: return ew_grouped_one<EW_COPY_CM>(table, ngroups, max_bx, max_by, st);
         case EW_RITZ: return ew_grouped_one<EW_RITZ>(table, ngroups, max_bx, max_by, st);
+        case EW_CHOL: return ew_grouped_one<EW_CHOL>(table, ngroups, max_bx, max_by, st);
     }
     return FEAST_EUNSUPPORTED;
 }

@@ -166,6 +166,27 @@ def test_iterate_generalized(variant):
     F.close()
 
 
+@pytest.mark.parametrize("variant", ["R", "Bi"])
+@pytest.mark.parametrize("m0", [14, 80])
+def test_iterate_device_and_host_orthonormalisation(variant, m0):
+    """The shifted Cholesky-QR passes with the Gram matrices factored on the device (default; the
+    factor of an order above 64 lives in global memory) and on the host reach the same eigenpairs:
+    equal counts, eigenvalues within 1e-10 relative of each other and of the brute-force spectrum,
+    iteration counts within one."""
+    A, B, lam = random_pencil(300, seed=78, with_B=True, m=9)
+    U0 = pencils.complex_gaussian(np.random.default_rng(3), (300, m0))
+    out = {}
+    for host_ortho in (False, True):
+        F = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, 16, m0, variant=variant, host_ortho=host_ortho)
+        res = F.iterate(upload(U0))
+        check_eigenpairs(res, A, B, brute.eigenvalues_inside(lam, 0, 1.0))
+        out[host_ortho] = res
+        F.close()
+    assert len(out[False].lam) == len(out[True].lam) == 9
+    assert match_eigs(out[False].lam, out[True].lam) < 1e-10
+    assert abs(out[False].iterations - out[True].iterations) <= 1
+
+
 def test_iterate_empty_contour():
     """No eigenvalue inside: the iteration stops with m = 0."""
     A, B, lam = random_pencil(120, seed=4, with_B=False, m=0)
