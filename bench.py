@@ -319,6 +319,28 @@ def batch_cpu_baseline(P, U0h, stride=4):
                 sample_s=t, sample_iterations=iters, sample_converged=ok)
 
 
+def update_kernel(mode):
+    """The trailing-update kernel of a mode: the matrix-core precision whose published peak bounds it,
+    its name, and the FP16 products per real product (the FP32 mode splits every operand into high
+    and low FP16 parts and takes three products, so its attainable algorithmic rate is a third of
+    the FP16 peak)."""
+    if mode == "fp64":
+        return "fp64", "cgemm_kernel<double> (trailing update, kind 1, FP64 matrix cores)", 1
+    if mode == "fp16":
+        return "fp16", "cgemm_f16_kernel<false> (trailing update, FP16 matrix cores)", 1
+    return "fp16", "cgemm_f16_kernel<true> (trailing update, FP16 matrix cores, split operands)", 3
+
+
+def update_roof_fields(achieved, mode):
+    key, name, products = update_kernel(mode)
+    d = dict(bound="mfma", achieved=achieved, peak=PEAK[key], unit="TFLOP/s", frac=achieved / PEAK[key],
+             kernel=name)
+    if products > 1:
+        d["fp16_products_per_real_product"] = products
+        d["frac_of_split_attainable"] = achieved * products / PEAK[key]
+    return d
+
+
 def update_roofline(ph, prec, ns, mode):
     """Per-launch figures of the trailing-update kernel of a batch from the library's HIP-event phase
     timing: flops per launch (8 nr nc K over every member and node the launch covers) / average
@@ -329,10 +351,10 @@ def update_roofline(ph, prec, ns, mode):
     avg_ms = u["ms"] / launches
     achieved = u["flops"] / launches / (avg_ms * 1e-3) / 1e12
     alg, _ = batch_update_bytes(ns, 16, 16 if mode == "fp64" else 8)
-    return dict(bound="mfma", achieved=achieved, peak=PEAK[prec], unit="TFLOP/s", frac=achieved / PEAK[prec],
+    return dict(**update_roof_fields(achieved, mode),
                 traffic=measured_traffic("lu_update", "c2", mode),
                 traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
-                kernel="cgemm_kernel (trailing update, kind 1)", kernel_phase="lu_update",
+                kernel_phase="lu_update",
                 avg_launch_ms=avg_ms, launches=u["launches"], flops_per_launch=u["flops"] / launches,
                 algorithmic_bytes_per_launch=alg / launches)
 
@@ -426,7 +448,7 @@ def bench_batch(args, fm, torch, dev):
     if not args.no_extras:
         for name in ("c1", "c3"):
             extras[name] = single_pencil_summary(args, fm, torch, dev, name)
-    mode_names = {"fp32": "FP32 LU + FP64 shifted-residual correction", "fp64": "FP64",
+    mode_names = {"fp32": "FP32 LU (trailing updates on FP16 matrix cores, split operands) + FP64 shifted-residual correction", "fp64": "FP64",
                   "fp16": "FP16-update LU + FP64 shifted-residual correction"}
     line = {
         "metric": METRIC,
@@ -531,9 +553,7 @@ def bench_conj(args, fm, torch, dev):
     elem = 16 if args.mode == "fp64" else 8
     q_factored = P.q // 2 + 1
     nbytes, launches = update_bytes(P.n, q_factored, elem)
-    roofline = dict(bound="mfma", achieved=upd["tflops"], peak=PEAK[args.mode], unit="TFLOP/s",
-                    frac=upd["tflops"] / PEAK[args.mode], traffic=None, kernel="cgemm_kernel (trailing update)",
-                    kernel_phase="lu_update", avg_launch_ms=upd["ms"] / max(1, upd["launches"]),
+    roofline = dict(**update_roof_fields(upd["tflops"], args.mode), traffic=None, kernel_phase="lu_update", avg_launch_ms=upd["ms"] / max(1, upd["launches"]),
                     launches=upd["launches"], algorithmic_bytes_per_launch=nbytes / max(1, launches))
     line = {
         "metric": METRIC,
@@ -547,7 +567,7 @@ def bench_conj(args, fm, torch, dev):
         "config": {"workload": f"real generalized pencil n={P.n} (20 conjugate pairs and 8 real eigenvalues in "
                                f"|z| < 0.8), unit circle, q={P.q} trapezoid nodes of which {q_factored} factored, "
                                f"m0={P.m0}, R-FEAST, tol 1e-10",
-                   "mode": "FP32 LU + FP64 shifted-residual correction" if args.mode == "fp32" else "FP64",
+                   "mode": "FP32 LU (trailing updates on FP16 matrix cores, split operands) + FP64 shifted-residual correction" if args.mode == "fp32" else "FP64",
                    "step": "setup (assembly + factored nodes) + iterations to 1e-10",
                    "conj_nodes": "real", "pivoting": args.pivoting},
         "time_to_1e10_s": head["ms_per_step"] / 1e3,
@@ -622,7 +642,7 @@ def bench_domains(args, fm, torch, dev):
                                f"away from cell edges), the rest in 2 < |z| < 5; probe batch over the 64 cells "
                                f"(8 Gauss-Legendre nodes, 16 probes, cond(V) <= 1e2), tiles of about {target} eigenvalues, "
                                f"q=16 per tile, R-FEAST, tol 1e-10",
-                   "mode": "FP32 LU + FP64 shifted-residual correction" if args.mode == "fp32" else "FP64",
+                   "mode": "FP32 LU (trailing updates on FP16 matrix cores, split operands) + FP64 shifted-residual correction" if args.mode == "fp32" else "FP64",
                    "step": "count estimates + partition + one batch over the tiles (setup and iterations)"},
         "time_to_1e10_s": wall,
         "tiles": len(rects),
@@ -914,11 +934,10 @@ def main():
         elem = 16 if args.mode == "fp64" else 8
         nbytes, launches = update_bytes(P.n, P.q, elem)
         achieved = dph["flops"] / (dph["ms"] * 1e-3) / 1e12
-        roofline = dict(bound="mfma", achieved=achieved, peak=PEAK[prec_of_phase], unit="TFLOP/s",
-                        frac=achieved / PEAK[prec_of_phase],
+        roofline = dict(**update_roof_fields(achieved, args.mode),
                         traffic=measured_traffic("lu_update", args.workload, args.mode),
                         traffic_unit="bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, calibrated)",
-                        kernel="cgemm_kernel (trailing update)", kernel_phase=dom,
+                        kernel_phase=dom,
                         avg_launch_ms=dph["ms"] / max(1, dph["launches"]), launches=dph["launches"],
                         flops_per_launch=dph["flops"] / max(1, dph["launches"]),
                         algorithmic_bytes_per_launch=nbytes / max(1, launches),
@@ -934,10 +953,9 @@ def main():
                         flops_per_span=dph["flops"] / max(1, dph["launches"]),
                         note="phase spans of several GEMM launches; per-launch figures of the update in lu_update_roofline")
     lu = ph_all["lu_update"]
-    lu_roof = dict(achieved=lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0,
-                   peak=PEAK[args.mode], unit="TFLOP/s", avg_launch_ms=lu["ms"] / max(1, lu["launches"]))
+    lu_roof = update_roof_fields(lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0, args.mode)
+    lu_roof["avg_launch_ms"] = lu["ms"] / max(1, lu["launches"])
     # (with FP16 updates escalated to FP32 the last factorisation's updates ran in FP32)
-    lu_roof["frac"] = lu_roof["achieved"] / lu_roof["peak"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -956,7 +974,7 @@ def main():
         "config": {"workload": f"complex-symmetric generalized pencil n={P.n}, circle c={P.center}, "
                                f"R*={P.radius:.6g} (m={g['m']} inside), q={P.q} trapezoid nodes, m0={P.m0}, "
                                f"{variant}-FEAST, tol 1e-10",
-                   "mode": {"fp32": "FP32 LU + FP64 shifted-residual correction", "fp16": "FP16-update LU + FP64 shifted-residual correction",
+                   "mode": {"fp32": "FP32 LU (trailing updates on FP16 matrix cores, split operands) + FP64 shifted-residual correction", "fp16": "FP16-update LU + FP64 shifted-residual correction",
                             "fp64": "FP64"}[args.mode],
                    "step": "setup (assembly + q LUs) + iterations to 1e-10",
                    "pivoting": args.pivoting},

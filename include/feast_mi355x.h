@@ -161,6 +161,14 @@ typedef struct {
                             round trip per pass).  The first iteration with rank_check = 1
                             factors on the host in both cases (the rank needs the Gram matrix's
                             eigenvalues).  Both reach the same subspace to rounding. */
+    int split_update;    /* FEAST_FP32_IR only: 1 runs the trailing updates of the node
+                            factorisations on the FP16 matrix cores with every operand entry split
+                            into a high and a low FP16 part (x = hi + lo, hi = fp16(x); the
+                            products hi*hi + hi*lo + lo*hi accumulate in FP32), which keeps about
+                            22 significant bits; U12 of each group of four panels is scaled by a
+                            power of two from its largest entry first.  1 is the default; 0 keeps
+                            them on the FP32 matrix cores.  The FP64 corrections of the mode are
+                            unchanged. */
 } feast_options;
 
 /* Fills *o with the defaults listed above (FP64, R-FEAST). */

@@ -66,7 +66,7 @@ class Options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("candidate_tol", ctypes.c_double), ("ir_max", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("timing", ctypes.c_int), ("rank_check", ctypes.c_int),
                 ("pivoting", ctypes.c_int), ("conj_nodes", ctypes.c_int), ("batch_launch", ctypes.c_int),
-                ("host_ortho", ctypes.c_int)]
+                ("host_ortho", ctypes.c_int), ("split_update", ctypes.c_int)]
 
 
 class PhaseTime(ctypes.Structure):
@@ -254,7 +254,7 @@ CONJ_NODES = {"none": 0, "real": 1, "hermitian": 2}
 
 def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10,
                  ir_tol=0.0, timing=False, rank_check=False, pivoting="tournament", conj_nodes="none",
-                 batch_launch="grouped", host_ortho=False) -> Options:
+                 batch_launch="grouped", host_ortho=False, split_update=True) -> Options:
     o = Options()
     lib().feast_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
@@ -270,6 +270,7 @@ def make_options(precision="fp64", variant="R", max_iter=30, tol=1e-10, candidat
     o.conj_nodes = CONJ_NODES[conj_nodes]
     o.batch_launch = BATCH_LAUNCH[batch_launch]
     o.host_ortho = int(bool(host_ortho))
+    o.split_update = int(bool(split_update))
     return o
 
 
@@ -370,7 +371,7 @@ class Feast:
     def __init__(self, A, B, center=0j, radius=1.0, aspect=1.0, q=16, m0=16, rule="trapezoid",
                  precision="fp64", variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0,
                  timing=False, workspace=None, rank_check=False, pivoting="tournament", pieces=None,
-                 conj_nodes="none", host_ortho=False):
+                 conj_nodes="none", host_ortho=False, split_update=True):
         torch = _torch()
         self.n = A.shape[0]
         self.m0 = m0
@@ -378,7 +379,8 @@ class Feast:
         self.A, self.B = A, B
         self.contour = make_contour(center, radius, aspect, q, rule, pieces)
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check, pivoting, conj_nodes, host_ortho=host_ortho)
+                                    rank_check, pivoting, conj_nodes, host_ortho=host_ortho,
+                                    split_update=split_update)
         nbytes = workspace_size(self.n, m0, self.contour, self.options, B is not None)
         if workspace is not None:
             if workspace.numel() < nbytes or workspace.data_ptr() % 256:
@@ -522,7 +524,8 @@ class FeastBatch:
 
     def __init__(self, pencils, contours=(0j, 1.0, 1.0), m0=16, q=16, rule="trapezoid", precision="fp64",
                  variant="R", max_iter=30, tol=1e-10, candidate_tol=1e-4, ir_max=10, ir_tol=0.0, workspace=None,
-                 rank_check=False, pivoting="tournament", timing=False, batch_launch="grouped", host_ortho=False):
+                 rank_check=False, pivoting="tournament", timing=False, batch_launch="grouped", host_ortho=False,
+                 split_update=True):
         torch = _torch()
         count = len(pencils)
         self.count = count
@@ -532,7 +535,8 @@ class FeastBatch:
         if isinstance(contours, tuple) and not isinstance(contours[0], tuple):
             contours = [contours] * count
         self.options = make_options(precision, variant, max_iter, tol, candidate_tol, ir_max, ir_tol, timing,
-                                    rank_check, pivoting, batch_launch=batch_launch, host_ortho=host_ortho)
+                                    rank_check, pivoting, batch_launch=batch_launch, host_ortho=host_ortho,
+                                    split_update=split_update)
         C = (Contour * count)(*[make_contour(q=q, rule=rule, pieces=e) if isinstance(e, list)
                                 else make_contour(e[0], e[1], e[2], q, rule) for e in contours])
         self._C = C

@@ -159,7 +159,7 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
         c->lu.UinvS = b.take<char>((size_t)q * c->lu.nsbs * NBS * NBS * E);
     }
     c->lu.pslots = b.take<char>(panel_slot_bytes(n, q, NB, E / 2, &c->lu.pW));
-    if (c->prec == Prec::F16) c->lu.amax = b.take<int>(q);
+    if (c->prec == Prec::F16 || c->lu.split) c->lu.amax = b.take<int>(q);
     if (c->o.pivoting == 1) {
         c->lu.tcand = b.take<int>(tslu_cand_ints(n, q, c->prec == Prec::F64));
         c->lu.ttop = b.take<char>((size_t)q * NB * NB * E);
@@ -284,6 +284,7 @@ void fill_dims(feast_ctx* c, int n, int m0, const feast_contour* C, const feast_
     c->lu.nbs = NBS;
     c->lu.nsbs = ceil_div(n, NBS);
     c->lu.half = c->prec == Prec::F16;
+    c->lu.split = c->prec == Prec::F32 && o->split_update == 1;
     c->lu.paired = c->prec != Prec::F16;
     c->lu.tslu = o->pivoting == 1;
     c->lu.tW0 = tslu_leaf_blocks(n, c->prec == Prec::F64);
@@ -304,7 +305,8 @@ int check_args(int n, int m0, const feast_contour* C, const feast_options* o) {
     if (contour_check(C) != 0) return -2;
     if (!o || o->precision < 0 || o->precision > FEAST_FP16_IR || (o->variant != FEAST_R && o->variant != FEAST_BI && o->variant != FEAST_L) ||
         o->pivoting < 0 || o->pivoting > 1 || o->conj_nodes < FEAST_CONJ_NONE || o->conj_nodes > FEAST_CONJ_HERMITIAN ||
-        o->batch_launch < 0 || o->batch_launch > 1 || o->host_ortho < 0 || o->host_ortho > 1)
+        o->batch_launch < 0 || o->batch_launch > 1 || o->host_ortho < 0 || o->host_ortho > 1 ||
+        o->split_update < 0 || o->split_update > 1)
         return -3;
     if (m0 < 1 || m0 > n) return -4;
     if (o->conj_nodes != FEAST_CONJ_NONE) {
@@ -726,6 +728,52 @@ PinnedPool& pinned_pool() {
     return pool;
 }
 
+// Non-blocking streams of closed batches, kept per device for later batches (a batch takes one per
+// pencil and creating and destroying them cost about as much as the rest of its host setup); at
+// most 512 stay pooled.  A stream comes back only after the batch's synchronous calls have drained
+// it.
+struct StreamPool {
+    std::mutex mu;
+    std::map<int, std::vector<hipStream_t>> idle;
+    static constexpr size_t CAP = 512;
+
+    hipStream_t get() {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto& v = idle[dev];
+            if (!v.empty()) {
+                hipStream_t s = v.back();
+                v.pop_back();
+                return s;
+            }
+        }
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        return s;
+    }
+    // s belongs to the current device
+    void put(hipStream_t s) {
+        if (!s) return;
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            std::lock_guard<std::mutex> g(mu);
+            auto& v = idle[dev];
+            if (v.size() < CAP) {
+                v.push_back(s);
+                return;
+            }
+        }
+        (void)hipStreamDestroy(s);
+    }
+};
+
+StreamPool& stream_pool() {
+    static StreamPool pool;
+    return pool;
+}
+
 // The factorisation of this pencil alone, as a set of one.
 LUSet ctx_set(feast_ctx* c) {
     LUSet one;
@@ -789,7 +837,9 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     }
     const int q = C->q, p = m0;
     c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
-    c->hbytes = std::max<size_t>(c->hbytes, (size_t)c->lu_ngroups * sizeof(GemmGroup) + sizeof(LUDev));
+    // the tables of ctx_tables, staged side by side
+    c->hbytes = std::max<size_t>(c->hbytes, (size_t)c->lu_ngroups * sizeof(GemmGroup) + sizeof(LUDev) +
+                                                6 * (size_t)q * sizeof(z64) + 3 * ALIGN);
     const size_t pp = (size_t)p * p;
     const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp + 1;
     const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
@@ -825,10 +875,19 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     return 0;
 }
 
-// Node tables, the factorisation's device descriptor and grouped-product table (synchronous
-// uploads through the pinned staging buffer).
+// Node tables, the factorisation's device descriptor and grouped-product table: staged side by side
+// in the pinned buffer, copied asynchronously, one synchronisation at the end.
 int ctx_tables(feast_ctx* c, const feast_contour* C) {
     const int q = C->q;
+    if (op_log()) return FEAST_EUNSUPPORTED;
+    size_t off = 0;
+    auto stage = [&](void* dev, const void* host, size_t bytes) -> int {
+        if (off + bytes > c->hbytes) return FEAST_EWORKSPACE;
+        std::memcpy(c->h + off, host, bytes);
+        FM_HIP(hipMemcpyAsync(dev, c->h + off, bytes, hipMemcpyHostToDevice, c->st));
+        off += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+        return 0;
+    };
     // a1: nodes and weights; the device tables list the factored nodes (all of them, or those with
     // Im z >= 0 with their weights times the share of the conjugate pair they stand for)
     std::vector<double> zz(2 * q), ss(2 * q);
@@ -856,13 +915,18 @@ int ctx_tables(feast_ctx* c, const feast_contour* C) {
         tab[5 * qf + f] = z64(1.0);
     }
     z64* dst[6] = {c->z_d, c->wR, c->wL, c->negz, c->negzc, c->ones};
-    for (int k = 0; k < 6; ++k) FM_TRY(h2d(c, dst[k], tab.data() + k * qf, qf * sizeof(z64)));
+    const size_t tab_off = off;
+    for (int k = 0; k < 6; ++k) {
+        off = tab_off + k * qf * sizeof(z64);
+        FM_TRY(stage(dst[k], tab.data() + k * qf, qf * sizeof(z64)));
+    }
+    off = tab_off + (6 * qf * sizeof(z64) + ALIGN - 1) / ALIGN * ALIGN;
     // descriptor and grouped-product table of the factorisation of this pencil alone
     c->lu.A = c->A; c->lu.lda = c->lda;
     c->lu.B = c->B; c->lu.ldb = c->ldb;
     c->lu.z = c->z_d;
     const LUDev d = lu_dev(c->lu, elem_bytes(c->prec) / 2);
-    FM_TRY(h2d(c, c->lu_dev, &d, sizeof(LUDev)));
+    FM_TRY(stage(c->lu_dev, &d, sizeof(LUDev)));
     std::vector<GemmGroup> plan;
     LUSet one = ctx_set(c);
     if (c->prec == Prec::F64)
@@ -870,7 +934,8 @@ int ctx_tables(feast_ctx* c, const feast_contour* C) {
     else
         lu_plan<float>(one, plan);
     if ((int)plan.size() != c->lu_ngroups) return FEAST_EUNSUPPORTED;
-    if (!plan.empty()) FM_TRY(h2d(c, c->lu_groups, plan.data(), plan.size() * sizeof(GemmGroup)));
+    if (!plan.empty()) FM_TRY(stage(c->lu_groups, plan.data(), plan.size() * sizeof(GemmGroup)));
+    FM_HIP(hipStreamSynchronize(c->st));
     return 0;
 }
 
@@ -907,6 +972,7 @@ void feast_default_options(feast_options* o) {
     o->conj_nodes = FEAST_CONJ_NONE;
     o->batch_launch = 0;
     o->host_ortho = 0;
+    o->split_update = 1;
 }
 
 int feast_timing_read(feast_ctx* c, int phase, feast_phase_time* out) {
@@ -1999,9 +2065,8 @@ int batch_layout(int count, const int* n, const int* m0, const feast_contour* C,
 void batch_free(feast_batch* bt) {
     if (!bt) return;
     for (feast_ctx* c : bt->ctx) feast_destroy(c);
-    for (hipStream_t s : bt->streams)
-        if (s) (void)hipStreamDestroy(s);
-    if (bt->set_st) (void)hipStreamDestroy(bt->set_st);
+    for (hipStream_t s : bt->streams) stream_pool().put(s);
+    stream_pool().put(bt->set_st);
     pinned_pool().put(bt->arena_pin);
     if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
     if (bt->graph) (void)hipGraphDestroy(bt->graph);
@@ -2116,14 +2181,13 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         bt->arena = base + L.arena_off;
         bt->arena_bytes = SET_ARENA_BYTES;
         bt->arena_pin = (char*)pinned_pool().get(SET_ARENA_BYTES);
-        if (!bt->arena_pin || hipStreamCreateWithFlags(&bt->set_st, hipStreamNonBlocking) != hipSuccess)
-            rc = FEAST_EDEVICE;
+        if (!bt->arena_pin || !(bt->set_st = stream_pool().get())) rc = FEAST_EDEVICE;
     }
     // members: contexts with streams of their own (ctx_create only uploads the node tables and
     // descriptors of the member, synchronously on its stream)
     for (int b = 0; b < count && !rc; ++b) {
-        hipStream_t s = nullptr;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        hipStream_t s = stream_pool().get();
+        if (!s) {
             rc = FEAST_EDEVICE;
             break;
         }

@@ -46,7 +46,9 @@ struct GemmOp {
     // profilers can attribute it.  kind 2 (complex64 operands, all row-major) is the trailing
     // update on FP16 matrix cores: B_b is scaled by 2^-e, with 2^(e-1) <= amax[b] < 2^e, before its
     // entries are rounded to FP16 (A's entries are bounded by partial pivoting), products accumulate
-    // in FP32 and the result is scaled back by 2^e, so the scaling itself is exact.
+    // in FP32 and the result is scaled back by 2^e, so the scaling itself is exact.  kind 3 is the
+    // same with every entry split into high and low FP16 parts (x = hi + lo, hi = fp16(x), lo =
+    // fp16(x - hi)) and the products hi*hi + hi*lo + lo*hi: about 22 significant bits.
     int kind = 0;
     // kind 0, complex64: when set, the largest |re|, |im| of the outputs of batch entry b is
     // merged into amax[b] (bit pattern of a non-negative float, atomic max); the caller zeroes the

@@ -286,17 +286,48 @@ __global__ __launch_bounds__(256) void cgemm_kernel(Params<T> p) {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
-__device__ inline h8 neg8(h8 v) { return -v; }
+// FP16 planes of eight complex values x s: re, im and, with SPLIT, the low parts x - fp16(x).
+template <bool SPLIT>
+__device__ inline void split8(const float2* v, float s, h8& hr, h8& hi, h8& lr, h8& li) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float xr = v[u].x * s, xi = v[u].y * s;
+        hr[u] = (_Float16)xr;
+        hi[u] = (_Float16)xi;
+        if constexpr (SPLIT) {
+            lr[u] = (_Float16)(xr - (float)hr[u]);
+            li[u] = (_Float16)(xi - (float)hi[u]);
+        }
+    }
+}
+
+// Power-of-two scale 2^-e of a kind 2 / 3 product's B operand, 2^(e-1) <= amax < 2^e.
+__device__ inline int b_scale_exp(const int* amax, int b) {
+    int e = 0;
+    const float mx = amax ? __int_as_float(amax[b]) : 0.0f;
+    if (mx > 0.0f && mx <= 3.0e38f) (void)frexpf(mx, &e);
+    return e;
+}
 
 // Trailing update on FP16 matrix cores (v_mfma_f32_16x16x32_f16): C = beta C + alpha 2^e A (2^-e B)
-// with complex64 row-major operands, FP16 inputs and FP32 accumulation.  A 64 x 64 tile per
-// workgroup, waves 2 x 2 each owning 2 x 2 blocks of 16 x 16, depth 32 per stage.  LDS holds FP16
-// real / imaginary planes with k contiguous, so a lane fetches its 8 consecutive k of one row
-// (A) or column (B) in one 16-byte read: lane l supplies row l % 16, k = 8 (l / 16) .. + 7.
-__global__ __launch_bounds__(256) void cgemm_h16_kernel(Params<float> p) {
-    constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;
-    __shared__ __attribute__((aligned(16))) _Float16 As[2][BM][LDK];
-    __shared__ __attribute__((aligned(16))) _Float16 Bs[2][BN][LDK];
+// for complex64 row-major operands, FP32 accumulation.  B is scaled by the power of two 2^-e with
+// 2^(e-1) <= amax[b] < 2^e, so its entries lie in (-1, 1) (A's are bounded by the pivoting), and
+// the epilogue undoes the scaling exactly.  SPLIT: each operand entry is carried as x = hi + lo,
+// hi = fp16(x), lo = fp16(x - hi), which keeps about 22 significant bits, and each real product
+// is hi*hi + hi*lo + lo*hi (lo*lo lies below 2^-22 of it); otherwise hi alone (FP16 accuracy).
+// Tile 32 RB x 32 CB, waves 2 x 2 each owning RB x CB blocks of 16 x 16, depth 32 per stage.  LDS
+// holds the FP16 planes (re, im, then with SPLIT their low parts) with k contiguous, so a lane of
+// an MFMA fetches its operand (row or column l % 16, k = 8 (l / 16) .. + 7) in one 16-byte read.
+// Global loads: four lanes per 256-byte segment of an A row; B (row-major) by columns, a lane
+// holding eight consecutive k of one column, so that each load instruction of a wave reads 64
+// consecutive columns of one row and both operands reach LDS as 16-byte stores.
+template <bool SPLIT, int RB, int CB>
+__global__ __launch_bounds__(256) void cgemm_f16_kernel(Params<float> p) {
+    constexpr int BM = 32 * RB, BN = 32 * CB, BK = 32, LDK = BK + 8, NP = SPLIT ? 4 : 2;
+    constexpr int AP = BM / 64, BP = BN / 64;   // load passes: 64 rows (columns) x 4 k-groups each
+    static_assert(BM % 64 == 0 && BN % 64 == 0, "tile");
+    __shared__ __attribute__((aligned(16))) _Float16 As[NP][BM][LDK];
+    __shared__ __attribute__((aligned(16))) _Float16 Bs[NP][BN][LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int tm = blockIdx.x % p.tiles_m, tn = blockIdx.x / p.tiles_m;
@@ -324,51 +355,69 @@ __global__ __launch_bounds__(256) void cgemm_h16_kernel(Params<float> p) {
     if (m0 >= M || n0 >= N) return;
     const cplx<float>* __restrict__ A = pA + b * sA + b2 * sA2;
     const cplx<float>* __restrict__ B = pB + b * sB + b2 * sB2;
-    // power-of-two scale of B: 2^(e-1) <= max < 2^e, so the scaled entries lie in (-1, 1)
-    int e = 0;
-    const float mx = amax ? __int_as_float(amax[b]) : 0.0f;
-    if (mx > 0.0f && mx <= 3.0e38f) (void)frexpf(mx, &e);
+    const int e = b_scale_exp(amax, b);
     const float sc = ldexpf(1.0f, -e);
 
-    // global -> register mapping: A row ia, k = ka .. ka + 7; B row kb, columns jb .. jb + 7
-    const int ia = tid >> 2, ka = (tid & 3) * 8;
-    const int kb = tid >> 3, jb = (tid & 7) * 8;
-    cplx<float> ra[8], rb[8];
+    // this thread's operand pieces: A row ra + 64 a, k = kga .. + 7; B column cb + 64 c, k = kgb .. + 7
+    const int ra = tid >> 2, kga = (tid & 3) * 8;
+    const int cb = tid & 63, kgb = (tid >> 6) * 8;
+    float2 va[AP][8], vb[BP][8];
     auto load = [&](int k0) {
-        const int gi = m0 + ia;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int gk = k0 + ka + u;
-            ra[u] = (gi < M && gk < K) ? A[(long)gi * lda + gk] : cplx<float>(0.0f, 0.0f);
+        for (int a = 0; a < AP; ++a) {
+            const int gi = m0 + ra + 64 * a;
+            const cplx<float>* src = A + (long)gi * lda + k0 + kga;
+            const bool row = gi < M;
+            if (row && k0 + kga + 8 <= K && ((uintptr_t)src & 15) == 0) {
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    const float4 x = *(const float4*)(src + u);
+                    va[a][u] = make_float2(x.x, x.y);
+                    va[a][u + 1] = make_float2(x.z, x.w);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool in = row && k0 + kga + u < K;
+                    va[a][u] = in ? make_float2(src[u].re, src[u].im) : make_float2(0.0f, 0.0f);
+                }
+            }
         }
-        const int gk = k0 + kb;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int gj = n0 + jb + u;
-            rb[u] = (gk < K && gj < N) ? B[(long)gk * ldb + gj] : cplx<float>(0.0f, 0.0f);
+        for (int c = 0; c < BP; ++c) {
+            const int gj = n0 + cb + 64 * c;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int gk = k0 + kgb + u;
+                const bool in = gj < N && gk < K;
+                const cplx<float> x = in ? B[(long)gk * ldb + gj] : cplx<float>(0.0f, 0.0f);
+                vb[c][u] = make_float2(x.re, x.im);
+            }
+        }
+    };
+    // hi / lo planes of eight values (x scaled by s beforehand)
+    auto put = [&](auto P, int row, int k, const float2* v, float s) {
+        h8 hr, hi, lr, li;
+        split8<SPLIT>(v, s, hr, hi, lr, li);
+        *(h8*)&P[0][row][k] = hr;
+        *(h8*)&P[1][row][k] = hi;
+        if constexpr (SPLIT) {
+            *(h8*)&P[2][row][k] = lr;
+            *(h8*)&P[3][row][k] = li;
         }
     };
     auto store = [&]() {
-        h8 are, aim;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            are[u] = (_Float16)ra[u].re;
-            aim[u] = (_Float16)ra[u].im;
-        }
-        *(h8*)&As[0][ia][ka] = are;
-        *(h8*)&As[1][ia][ka] = aim;
+        for (int a = 0; a < AP; ++a) put(As, ra + 64 * a, kga, va[a], 1.0f);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            Bs[0][jb + u][kb] = (_Float16)(rb[u].re * sc);
-            Bs[1][jb + u][kb] = (_Float16)(rb[u].im * sc);
-        }
+        for (int c = 0; c < BP; ++c) put(Bs, cb + 64 * c, kgb, vb[c], sc);
     };
 
-    f4 cre[2][2], cim[2][2];
+    f4 cre[RB][CB], cim[RB][CB];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < CB; ++c) {
             cre[r][c] = f4{0, 0, 0, 0};
             cim[r][c] = f4{0, 0, 0, 0};
         }
@@ -379,29 +428,50 @@ __global__ __launch_bounds__(256) void cgemm_h16_kernel(Params<float> p) {
         store();
         __syncthreads();
         if (k0 + BK < K) load(k0 + BK);
-        h8 are[2], aim[2], nim[2], bre[2], bim[2];
+        h8 bv[CB][NP], nb[CB][NP / 2];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int i = wm * 32 + r * 16 + (lane & 15);
-            are[r] = *(const h8*)&As[0][i][kq];
-            aim[r] = *(const h8*)&As[1][i][kq];
-            nim[r] = neg8(aim[r]);
+        for (int c = 0; c < CB; ++c) {
+            const int j = wn * CB * 16 + c * 16 + (lane & 15);
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) bv[c][pl] = *(const h8*)&Bs[pl][j][kq];
+            nb[c][0] = -bv[c][1];
+            if constexpr (SPLIT) nb[c][1] = -bv[c][3];
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int j = wn * 32 + c * 16 + (lane & 15);
-            bre[c] = *(const h8*)&Bs[0][j][kq];
-            bim[c] = *(const h8*)&Bs[1][j][kq];
-        }
+        for (int r = 0; r < RB; ++r) {
+            const int i = wm * RB * 16 + r * 16 + (lane & 15);
+            h8 av[NP];
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+            for (int pl = 0; pl < NP; ++pl) av[pl] = *(const h8*)&As[pl][i][kq];
+            // re += ar br - ai bi, im += ar bi + ai br, each over the hi / lo parts; consecutive
+            // instructions alternate between the CB accumulators of the row
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(are[r], bre[c], cre[r][c], 0, 0, 0);
-                cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nim[r], bim[c], cre[r][c], 0, 0, 0);
-                cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(are[r], bim[c], cim[r][c], 0, 0, 0);
-                cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aim[r], bre[c], cim[r][c], 0, 0, 0);
+            for (int c = 0; c < CB; ++c) cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], bv[c][0], cre[r][c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < CB; ++c) cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], bv[c][1], cim[r][c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < CB; ++c) cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[1], nb[c][0], cre[r][c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < CB; ++c) cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[1], bv[c][0], cim[r][c], 0, 0, 0);
+            if constexpr (SPLIT) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], bv[c][2], cre[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], bv[c][3], cim[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[2], bv[c][0], cre[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[2], bv[c][1], cim[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[1], nb[c][1], cre[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[1], bv[c][2], cim[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[3], nb[c][0], cre[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[3], bv[c][0], cim[r][c], 0, 0, 0);
             }
+        }
     }
     // epilogue: lane l holds column l % 16, rows 4 (l / 16) + v of each block
     const float post = ldexpf(1.0f, e);
@@ -409,13 +479,13 @@ __global__ __launch_bounds__(256) void cgemm_h16_kernel(Params<float> p) {
     cplx<float>* __restrict__ C = pC + b * sC + b2 * sC2;
     const bool has_beta = (p.br != 0.0f || p.bi != 0.0f);
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < CB; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = m0 + wm * 32 + r * 16 + 4 * (lane >> 4) + v;
-                const int j = n0 + wn * 32 + c * 16 + (lane & 15);
+                const int i = m0 + wm * RB * 16 + r * 16 + 4 * (lane >> 4) + v;
+                const int j = n0 + wn * CB * 16 + c * 16 + (lane & 15);
                 if (i < M && j < N) {
                     const float xr = cre[r][c][v], xi = cim[r][c][v];
                     float yr = ar * xr - ai * xi, yi = ar * xi + ai * xr;
@@ -554,12 +624,24 @@ int gemm(const GemmOp& op, hipStream_t st) {
         if (op.ngroups <= 0) return 0;
         if (p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;   // see gemm_grouped
     }
-    if (op.kind == 2) {  // LU trailing update on FP16 matrix cores (complex64 storage only)
+    if (op.kind == 2 || op.kind == 3) {  // LU trailing update on FP16 matrix cores (complex64 only)
         if constexpr (std::is_same<T, float>::value) {
             if (!(op.rowA && op.rowB && op.rowC) || p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;
-            p.tiles_m = ceil_div(p.M, 64);
+            // 128 x 64 tiles once the rows fill them, else 64 x 64
+            const bool tall = p.M > 64;
+            p.tiles_m = ceil_div(p.M, tall ? 128 : 64);
             dim3 grid(p.tiles_m * ceil_div(p.N, 64), 1, p.batch * p.batch2 * (p.groups ? p.ngroups : 1));
-            hipLaunchKernelGGL(cgemm_h16_kernel, grid, dim3(256), 0, st, p);
+            if (op.kind == 3) {
+                if (tall)
+                    hipLaunchKernelGGL((cgemm_f16_kernel<true, 4, 2>), grid, dim3(256), 0, st, p);
+                else
+                    hipLaunchKernelGGL((cgemm_f16_kernel<true, 2, 2>), grid, dim3(256), 0, st, p);
+            } else {
+                if (tall)
+                    hipLaunchKernelGGL((cgemm_f16_kernel<false, 4, 2>), grid, dim3(256), 0, st, p);
+                else
+                    hipLaunchKernelGGL((cgemm_f16_kernel<false, 2, 2>), grid, dim3(256), 0, st, p);
+            }
             FM_LAUNCH_CHECK();
             return 0;
         } else {

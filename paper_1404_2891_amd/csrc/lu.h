@@ -39,6 +39,10 @@ struct LUStore {
     // taken from its largest component, recorded per node in amax (q ints, see GemmOp::amax)
     bool half = false;
     int* amax = nullptr;
+    // FP32 storage with the trailing updates on FP16 matrix cores, each operand split into high and
+    // low FP16 parts (GemmOp kind 3): U12 of a group of panels is scaled by a power of two taken
+    // from the group's largest component (amax, cleared at the group's first step)
+    bool split = false;
     // trailing updates once per group of panels (K = 4 nb); fixed when the launch sequence is planned
     // (off for contexts that start with FP16 updates, which keep one update per panel also after
     // an escalation to FP32 factors)
@@ -51,6 +55,8 @@ struct LUStore {
     void* ttop = nullptr;
     int tW0 = 0;
 };
+
+constexpr int UPDATE_GROUP = 4;   // panels per trailing update (K = 4 nb)
 
 // Leaf blocks of the tournament for panels of up to n rows (256 rows per leaf in both precisions).
 inline int tslu_leaf_blocks(int n, bool dbl) { (void)dbl; return (n + 255) / 256; }
@@ -86,7 +92,7 @@ struct LUDev {
     void* cval; int* crow; void* cdata; void* rowj; int pW;
     void* LinvS; void* UinvS;
     const z64* A; long lda; const z64* B; long ldb; const z64* z;
-    int* amax;
+    int* amax; int ugroup;   // ugroup: panels per trailing update (amax is cleared at multiples)
     int* tcand; void* ttop; int tW0; int tslu;
     int n, nsteps, nsbs;
 };

@@ -30,7 +30,6 @@ namespace fm {
 namespace {
 
 constexpr int NBMAX = 64;
-constexpr int UPDATE_GROUP = 4;   // panels per trailing update (K = 4 nb)
 
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(const LUDev* __restrict__ dv, int q) {
@@ -610,7 +609,7 @@ __global__ __launch_bounds__(1024) void trtri_kernel(const LUDev* __restrict__ d
     const cplx<T>* F = (const cplx<T>*)d.F + k * d.sF;
     cplx<T>* Inv0 = (cplx<T>*)(UPPER ? d.Uinv : d.Linv);
     // the U12 scale slot of this node and step starts at zero (the U12 product merges into it)
-    if (!UPPER && d.amax && threadIdx.x == 0) d.amax[k] = 0;
+    if (!UPPER && d.amax && threadIdx.x == 0 && s % d.ugroup == 0) d.amax[k] = 0;
     const cplx<T> zero(T(0), T(0)), one(T(1), T(0));
     for (int e = threadIdx.x; e < NBMAX * NBMAX; e += blockDim.x) {
         const int i = e >> 6, c = e & 63;
@@ -950,8 +949,9 @@ int run_set(SetRun<T>& R) {
     if (nb > NBMAX || nb % 16) return FEAST_EUNSUPPORTED;
     for (int b = 0; b < P; ++b)
         if (S.s[b].q != q || S.s[b].nb != nb || S.s[b].nbs != R.nbs || S.s[b].half != S.s[0].half ||
-            S.s[b].paired != S.s[0].paired ||
-            (S.s[b].half && sizeof(T) != sizeof(float)) || (R.launching() && S.s[b].half && !S.s[b].amax))
+            S.s[b].paired != S.s[0].paired || S.s[b].split != S.s[0].split ||
+            ((S.s[b].half || S.s[b].split) && sizeof(T) != sizeof(float)) ||
+            (R.launching() && (S.s[b].half || S.s[b].split) && !S.s[b].amax))
             return FEAST_EUNSUPPORTED;
     if (R.launching()) {
         hipLaunchKernelGGL(zero_info, dim3(ceil_div(q, 256), 1, P), dim3(256), 0, R.st, S.dev, q);
@@ -992,7 +992,7 @@ int run_set(SetRun<T>& R) {
                                      s.n, (long)nb * s.n, 0, w, nr, i * nb, q));
             // U12 = L_ss^-1 * (swapped rows staged in tmp); with FP16 updates its largest component
             // per node goes to amax
-            int* amax = s.half ? s.amax : nullptr;
+            int* amax = (s.half || s.split) ? s.amax : nullptr;
             u12.push_back(member((cplx<T>*)s.Linv + (long)step * nb * nb, nb, (long)s.nsteps * nb * nb, 0, s.tmp, s.n,
                                  (long)nb * s.n, 0, F + (long)j0 * ldf + jn, ldf, sF, 0, w, nr, w, q, amax));
             // A22 -= [L21 of the group's panels] [their U12]: the next panel's columns within a group,
@@ -1023,7 +1023,7 @@ int run_set(SetRun<T>& R) {
         FM_TRY(R.grouped(u12, op));
         R.stop(PH_LU_OTHER, 0.0);
         if (!more) break;
-        up.kind = S.s[0].half ? 2 : 1;
+        up.kind = S.s[0].half ? 2 : (S.s[0].split ? 3 : 1);
         R.start(PH_LU_UPDATE);
         FM_TRY(R.grouped(upd, up));
         R.stop(PH_LU_UPDATE, flops);
@@ -1063,7 +1063,8 @@ LUDev lu_dev(const LUStore& s, size_t real_bytes) {
     }
     d.LinvS = s.LinvS; d.UinvS = s.UinvS;
     d.A = s.A; d.lda = s.lda; d.B = s.B; d.ldb = s.ldb; d.z = s.z;
-    d.amax = s.half ? s.amax : nullptr;
+    d.amax = (s.half || s.split) ? s.amax : nullptr;
+    d.ugroup = (s.paired && !s.half) ? UPDATE_GROUP : 1;
     d.tcand = s.tcand; d.ttop = s.ttop; d.tW0 = s.tW0; d.tslu = (s.tslu && s.tcand) ? 1 : 0;
     d.n = s.n; d.nsteps = s.nsteps; d.nsbs = s.nsbs;
     return d;
