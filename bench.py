@@ -95,8 +95,9 @@ def pmc_summary(fetch_csv, write_csv, workload, mode, note):
     (256 MiB read, 256 MiB written); recorded in profiles/pmc_traffic.json with a hash of the
     sources."""
     import csv
-    kname = "cgemm_kernel<float, 2, 2, 4, 2, true, true, true, 1>" if mode != "fp64" else \
-        "cgemm_kernel<double, 2, 2, 2, 2, true, true, true, 1>"
+    # the update's kernel instances (both tile shapes of the FP16 kernels)
+    kname = {"fp32": "cgemm_f16_kernel<true", "fp16": "cgemm_f16_kernel<false"}.get(
+        mode, "cgemm_kernel<double, 2, 2, 2, 2, true, true, true, 1>")
     out = {}
     for key, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = list(csv.DictReader(open(path)))

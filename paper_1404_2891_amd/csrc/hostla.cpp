@@ -163,21 +163,44 @@ void givens(cd x, cd y, double& c, cd& s) {
     s = (x / ax) * std::conj(y) / nrm;
 }
 
-// Upper Hessenberg H -> upper triangular T = Z^H M Z by single-shift QR.
+// Upper Hessenberg H -> upper triangular T = Z^H M Z by single-shift QR.  During the iteration H is
+// held row-major and Z column-major, each as separate real and imaginary planes: the two longest
+// loops of a rotation (the rows of H from the bulge to the last column, all rows of Z) then run over
+// contiguous doubles, which the compiler vectorizes; the column rotation of H (rows up to the
+// bulge) is the short strided one.
 bool schur(Mat& H, Mat& Z) {
     const int n = H.n;
+    const size_t nn = (size_t)n * n;
+    std::vector<double> hbuf(2 * nn), zbuf(2 * nn);
+    double* __restrict hr = hbuf.data();        // hr[i * n + j] = Re H(i, j)
+    double* __restrict hi_ = hbuf.data() + nn;
+    double* __restrict zr = zbuf.data();        // zr[i + j * n] = Re Z(i, j)
+    double* __restrict zi = zbuf.data() + nn;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            hr[(size_t)i * n + j] = H(i, j).real();
+            hi_[(size_t)i * n + j] = H(i, j).imag();
+            zr[i + (size_t)j * n] = Z(i, j).real();
+            zi[i + (size_t)j * n] = Z(i, j).imag();
+        }
+    auto h = [&](int i, int j) { return cd(hr[(size_t)i * n + j], hi_[(size_t)i * n + j]); };
+    auto hset = [&](int i, int j, cd v) {
+        hr[(size_t)i * n + j] = v.real();
+        hi_[(size_t)i * n + j] = v.imag();
+    };
     double hnorm = 0.0;
-    for (auto& x : H.a) hnorm += std::norm(x);
+    for (size_t e = 0; e < nn; ++e) hnorm += hr[e] * hr[e] + hi_[e] * hi_[e];
     hnorm = std::sqrt(hnorm);
     const double tiny = std::numeric_limits<double>::min() / EPS;
     int hi = n - 1, iter = 0, total = 0;
     while (hi > 0) {
         int l = hi;
         for (; l > 0; --l) {
-            double s = std::abs(H(l, l)) + std::abs(H(l - 1, l - 1));
+            double s = std::abs(h(l, l)) + std::abs(h(l - 1, l - 1));
             if (s == 0.0) s = hnorm;
-            if (std::abs(H(l, l - 1)) <= EPS * s || std::abs(H(l, l - 1)) < tiny) {
-                H(l, l - 1) = 0.0;
+            const double sub = std::abs(h(l, l - 1));
+            if (sub <= EPS * s || sub < tiny) {
+                hset(l, l - 1, 0.0);
                 break;
             }
         }
@@ -190,45 +213,71 @@ bool schur(Mat& H, Mat& Z) {
         ++iter;
         cd mu;
         if (iter % 11 == 10) {
-            mu = H(hi, hi) + 0.75 * std::abs(H(hi, hi - 1));
+            mu = h(hi, hi) + 0.75 * std::abs(h(hi, hi - 1));
         } else {
-            const cd a = H(hi - 1, hi - 1), b = H(hi - 1, hi), c = H(hi, hi - 1), d = H(hi, hi);
+            const cd a = h(hi - 1, hi - 1), b = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
             const cd half = 0.5 * (a - d);
             const cd disc = std::sqrt(half * half + b * c);
             const cd m1 = 0.5 * (a + d) + disc, m2 = 0.5 * (a + d) - disc;
             mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
         }
-        cd x = H(l, l) - mu, y = H(l + 1, l);
+        cd x = h(l, l) - mu, y = h(l + 1, l);
         for (int k = l; k < hi; ++k) {
             double c;
             cd s;
             givens(x, y, c, s);
-            // rows k, k+1 (columns from the sub-diagonal of the bulge to the end)
-            for (int j = std::max(l, k - 1); j < n; ++j) {
-                const cd h1 = H(k, j), h2 = H(k + 1, j);
-                H(k, j) = c * h1 + s * h2;
-                H(k + 1, j) = -std::conj(s) * h1 + c * h2;
+            const double sr = s.real(), si = s.imag();
+            // rows k, k + 1 (columns from the sub-diagonal of the bulge to the end):
+            // [h1; h2] <- [c h1 + s h2; -conj(s) h1 + c h2]
+            {
+                const int j0 = std::max(l, k - 1);
+                double* __restrict r1 = hr + (size_t)k * n;
+                double* __restrict i1 = hi_ + (size_t)k * n;
+                double* __restrict r2 = hr + (size_t)(k + 1) * n;
+                double* __restrict i2 = hi_ + (size_t)(k + 1) * n;
+                for (int j = j0; j < n; ++j) {
+                    const double a1 = r1[j], b1 = i1[j], a2 = r2[j], b2 = i2[j];
+                    r1[j] = c * a1 + sr * a2 - si * b2;
+                    i1[j] = c * b1 + sr * b2 + si * a2;
+                    r2[j] = c * a2 - sr * a1 - si * b1;
+                    i2[j] = c * b2 - sr * b1 + si * a1;
+                }
             }
-            // columns k, k+1 (rows up to the bulge)
+            // columns k, k + 1 (rows up to the bulge): [h1, h2] <- [c h1 + conj(s) h2, -s h1 + c h2]
             const int imax = std::min(k + 2, hi);
             for (int i = 0; i <= imax; ++i) {
-                const cd h1 = H(i, k), h2 = H(i, k + 1);
-                H(i, k) = c * h1 + std::conj(s) * h2;
-                H(i, k + 1) = -s * h1 + c * h2;
+                double* __restrict rr = hr + (size_t)i * n + k;
+                double* __restrict ii = hi_ + (size_t)i * n + k;
+                const double a1 = rr[0], b1 = ii[0], a2 = rr[1], b2 = ii[1];
+                rr[0] = c * a1 + sr * a2 + si * b2;
+                ii[0] = c * b1 + sr * b2 - si * a2;
+                rr[1] = c * a2 - sr * a1 + si * b1;
+                ii[1] = c * b2 - sr * b1 - si * a1;
             }
-            for (int i = 0; i < n; ++i) {
-                const cd z1 = Z(i, k), z2 = Z(i, k + 1);
-                Z(i, k) = c * z1 + std::conj(s) * z2;
-                Z(i, k + 1) = -s * z1 + c * z2;
+            {
+                double* __restrict r1 = zr + (size_t)k * n;
+                double* __restrict i1 = zi + (size_t)k * n;
+                double* __restrict r2 = zr + (size_t)(k + 1) * n;
+                double* __restrict i2 = zi + (size_t)(k + 1) * n;
+                for (int i = 0; i < n; ++i) {
+                    const double a1 = r1[i], b1 = i1[i], a2 = r2[i], b2 = i2[i];
+                    r1[i] = c * a1 + sr * a2 + si * b2;
+                    i1[i] = c * b1 + sr * b2 - si * a2;
+                    r2[i] = c * a2 - sr * a1 + si * b1;
+                    i2[i] = c * b2 - sr * b1 - si * a1;
+                }
             }
             if (k + 1 < hi) {
-                x = H(k + 1, k);
-                y = H(k + 2, k);
+                x = h(k + 1, k);
+                y = h(k + 2, k);
             }
         }
     }
     for (int j = 0; j < n; ++j)
-        for (int i = j + 1; i < n; ++i) H(i, j) = 0.0;
+        for (int i = 0; i < n; ++i) {
+            H(i, j) = i > j ? cd(0.0, 0.0) : h(i, j);
+            Z(i, j) = cd(zr[i + (size_t)j * n], zi[i + (size_t)j * n]);
+        }
     return true;
 }
 
