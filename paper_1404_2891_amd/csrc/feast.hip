@@ -1538,6 +1538,14 @@ struct SetExec {
     Timer* timer = nullptr;                          // the batch's timer (phase marks)
     int pad_steps = 0;
     std::vector<OpLog> logs;                         // one per run
+    // device -> host transfers merged through the arena: each pencil's bytes wait in the pinned
+    // mirror until the next synchronisation, which moves them to their destinations
+    struct Scatter {
+        void* dst;
+        const char* src;
+        size_t bytes;
+    };
+    std::vector<Scatter> pending;
 };
 
 // Device copy of a table; the same contents uploaded earlier are reused.  The arena is emptied only
@@ -1589,6 +1597,8 @@ int set_gemm(SetExec& X, const std::vector<const RecOp*>& part) {
     return gemm_grouped<T>(part[0]->g, (const GemmGroup*)dt, (int)tab.size(), mM, mN, mK, mB, mS, X.st);
 }
 
+int set_copies(SetExec& X, const std::vector<const RecOp*>& part);
+
 int set_launch(SetExec& X, const std::vector<const RecOp*>& part) {
     const RecOp& r0 = *part[0];
     switch (r0.kind) {
@@ -1608,8 +1618,7 @@ int set_launch(SetExec& X, const std::vector<const RecOp*>& part) {
             return ew_grouped(r0.ew, dt, (int)part.size(), bx, by, X.st);
         }
         case REC_COPY:
-            FM_HIP(hipMemcpyAsync(r0.dst, r0.src, r0.bytes, r0.dir, X.st));
-            return 0;
+            return set_copies(X, part);
         case REC_MARK:
             if (X.timer) {
                 if (r0.start) {
@@ -1623,6 +1632,55 @@ int set_launch(SetExec& X, const std::vector<const RecOp*>& part) {
             return 0;
         case REC_OTHER:
             return r0.run(X.st);
+    }
+    return 0;
+}
+
+// The copies of one position of the logs (all in the same direction).  Several host <-> device
+// transfers become one: their device sides are gathered into (or scattered from) a staging block of
+// the arena by one grouped word-copy launch and the block crosses in one copy through the arena's
+// pinned mirror (host sources are packed there at once; host destinations are filled at the next
+// synchronisation).  Transfers that do not fit, or are not whole 4-byte words, go one by one.
+int set_copies(SetExec& X, const std::vector<const RecOp*>& part) {
+    const hipMemcpyKind dir = part[0]->dir;
+    bool merge = part.size() > 1 && (dir == hipMemcpyDeviceToHost || dir == hipMemcpyHostToDevice);
+    size_t total = 0;
+    for (const RecOp* r : part) {
+        const void* dev = dir == hipMemcpyDeviceToHost ? r->src : r->dst;
+        merge = merge && r->bytes % 4 == 0 && ((uintptr_t)dev & 3) == 0;
+        total += align_up(r->bytes, 16);
+    }
+    const size_t off = align_up(X.used, 256);
+    if (!merge || off + total > X.cap) {
+        for (const RecOp* r : part) FM_HIP(hipMemcpyAsync(r->dst, r->src, r->bytes, r->dir, X.st));
+        return 0;
+    }
+    X.used = off + total;
+    std::vector<WordsArgs> tab(part.size());
+    long maxw = 0;
+    size_t o = off;
+    for (size_t i = 0; i < part.size(); ++i) {
+        const RecOp& r = *part[i];
+        const long words = (long)(r.bytes / 4);
+        maxw = std::max(maxw, words);
+        if (dir == hipMemcpyDeviceToHost) {
+            tab[i] = WordsArgs{(const unsigned*)r.src, (unsigned*)(X.dev + o), words};
+            X.pending.push_back(SetExec::Scatter{r.dst, X.pin + o, r.bytes});
+        } else {
+            std::memcpy(X.pin + o, r.src, r.bytes);
+            tab[i] = WordsArgs{(const unsigned*)(X.dev + o), (unsigned*)r.dst, words};
+        }
+        o += align_up(r.bytes, 16);
+    }
+    const void* dt = nullptr;
+    FM_TRY(set_table(X, tab.data(), tab.size() * sizeof(WordsArgs), &dt));
+    const unsigned bx = (unsigned)std::max<long>(1, (maxw + 255) / 256);
+    if (dir == hipMemcpyDeviceToHost) {
+        FM_TRY(ew_grouped(EW_WORDS, dt, (int)part.size(), bx, 1, X.st));
+        FM_HIP(hipMemcpyAsync(X.pin + off, X.dev + off, total, hipMemcpyDeviceToHost, X.st));
+    } else {
+        FM_HIP(hipMemcpyAsync(X.dev + off, X.pin + off, total, hipMemcpyHostToDevice, X.st));
+        FM_TRY(ew_grouped(EW_WORDS, dt, (int)part.size(), bx, 1, X.st));
     }
     return 0;
 }
@@ -1643,7 +1701,8 @@ int set_replay(SetExec& X) {
             used[a] = 1;
             part.assign(1, col[a]);
             const RecOp& r = *col[a];
-            const bool merge = (r.kind == REC_GEMM && gemm_groupable(r)) || r.kind == REC_EW || r.kind == REC_MARK;
+            const bool merge = (r.kind == REC_GEMM && gemm_groupable(r)) || r.kind == REC_EW || r.kind == REC_MARK ||
+                               r.kind == REC_COPY;
             for (size_t b = a + 1; merge && b < col.size(); ++b) {
                 const RecOp& o = *col[b];
                 if (used[b] || o.kind != r.kind) continue;
@@ -1651,6 +1710,7 @@ int set_replay(SetExec& X) {
                 if (r.kind == REC_GEMM) ok = gemm_groupable(o) && gemm_compatible(r, o);
                 if (r.kind == REC_EW) ok = o.ew == r.ew;
                 if (r.kind == REC_MARK) ok = o.phase == r.phase && o.start == r.start;
+                if (r.kind == REC_COPY) ok = o.dir == r.dir;
                 if (ok) {
                     used[b] = 1;
                     part.push_back(col[b]);
@@ -1666,6 +1726,8 @@ int set_replay(SetExec& X) {
 int sync_runs(std::vector<Run*>& runs, SetExec* X) {
     if (X) {
         FM_HIP(hipStreamSynchronize(X->st));
+        for (const SetExec::Scatter& s : X->pending) std::memcpy(s.dst, s.src, s.bytes);
+        X->pending.clear();
         if (X->used > X->cap / 2) {   // nothing reads the arena now
             X->cache.clear();
             X->used = 0;
@@ -2019,7 +2081,7 @@ namespace {
 // Workspace of a batch: the set's descriptors and grouped-product table, then one slice per member.
 // Device tables of the grouped iteration launches: every operation of a phase needs one entry per
 // pencil (a few hundred bytes), and the tables of a few phase variants and active sets stay cached.
-constexpr size_t SET_ARENA_BYTES = size_t(16) << 20;
+constexpr size_t SET_ARENA_BYTES = size_t(64) << 20;
 
 // Grouped launches unless one stream per pencil is asked for; classic refinement sweeps synchronise
 // inside a phase, so such batches keep one stream per pencil too.
@@ -2132,6 +2194,10 @@ struct BatchStreams {
         int r = 0;
         if (bt->grouped) {
             if (hipStreamSynchronize(bt->set_st) != hipSuccess) r = FEAST_EDEVICE;
+            // merged device -> host transfers still waiting in the pinned arena
+            if (!r)
+                for (const SetExec::Scatter& s : X.pending) std::memcpy(s.dst, s.src, s.bytes);
+            X.pending.clear();
             for (int i = 0; i < bt->count; ++i) bt->ctx[i]->st = bt->streams[i];
         }
         for (int i = 0; i < bt->count; ++i)

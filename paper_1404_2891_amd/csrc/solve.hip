@@ -294,6 +294,10 @@ __device__ inline void chol_body(const CholArgs& a) {
     }
 }
 
+__device__ inline void words_body(const WordsArgs& a, long t) {
+    if (t < a.words) a.dst[t] = a.src[t];
+}
+
 // One kernel per element-wise operation: the direct launch takes the argument block by value, the
 // grouped launch reads block blockIdx.z of a device table.
 template <int EW>
@@ -307,6 +311,7 @@ __device__ inline void ew_dispatch(const void* args) {
     if constexpr (EW == EW_COPY_CM) copy_body(*(const CopyArgs*)args, t);
     if constexpr (EW == EW_RITZ) ritz_body(*(const RitzArgs*)args, blockIdx.x);
     if constexpr (EW == EW_CHOL) chol_body(*(const CholArgs*)args);
+    if constexpr (EW == EW_WORDS) words_body(*(const WordsArgs*)args, t);
 }
 
 template <int EW, typename A>
@@ -328,6 +333,7 @@ template <> struct EwArgs<EW_RESIDUAL> { typedef ResidualArgs type; };
 template <> struct EwArgs<EW_COPY_CM> { typedef CopyArgs type; };
 template <> struct EwArgs<EW_RITZ> { typedef RitzArgs type; };
 template <> struct EwArgs<EW_CHOL> { typedef CholArgs type; };
+template <> struct EwArgs<EW_WORDS> { typedef WordsArgs type; };
 
 // Enqueue (or record) element-wise kernel EW over a grid of bx x by workgroups of 256 threads.
 template <int EW>
@@ -601,6 +607,7 @@ size_t ew_arg_size(int ew) {
         case EW_COPY_CM: return sizeof(CopyArgs);
         case EW_RITZ: return sizeof(RitzArgs);
         case EW_CHOL: return sizeof(CholArgs);
+        case EW_WORDS: return sizeof(WordsArgs);
     }
     return 0;
 }
@@ -616,6 +623,7 @@ int ew_grouped(int ew, const void* table, int ngroups, unsigned max_bx, unsigned
         case EW_COPY_CM: return ew_grouped_one<EW_COPY_CM>(table, ngroups, max_bx, max_by, st);
         case EW_RITZ: return ew_grouped_one<EW_RITZ>(table, ngroups, max_bx, max_by, st);
         case EW_CHOL: return ew_grouped_one<EW_CHOL>(table, ngroups, max_bx, max_by, st);
+        case EW_WORDS: return ew_grouped_one<EW_WORDS>(table, ngroups, max_bx, max_by, st);
     }
     return FEAST_EUNSUPPORTED;
 }
