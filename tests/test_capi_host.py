@@ -126,7 +126,7 @@ def _batch_size(ns, m0s, qs, opts, has_B):
 def test_batch_workspace_is_members_plus_tables(prec):
     """A batch needs every member's own workspace plus the set's descriptor and grouped-product
     tables (a few hundred bytes per factorisation step), and with grouped iteration launches (the
-    default) the 16 MiB arena of their device tables."""
+    default) the 64 MiB arena of their device tables and staged transfers."""
     ns, m0s = [256, 1000, 65, 2048, 300], [16, 32, 16, 32, 8]
     sizes = {}
     for mode in ("streams", "grouped"):
@@ -137,11 +137,11 @@ def test_batch_workspace_is_members_plus_tables(prec):
     singles = sum(fm.workspace_size(n, m, binding.make_contour(0j, 1.0, 1.0, 16), o, True) for n, m in zip(ns, m0s))
     total = sizes["streams"]
     assert singles <= total <= singles + 5 * 256 + 256 * (2 * sum(-(-n // 64) for n in ns) + 5 * 24) + 4096
-    assert sizes["grouped"] == total + (16 << 20)
+    assert sizes["grouped"] == total + (64 << 20)
     # classic refinement sweeps keep one stream per pencil (no arena)
     o = binding.make_options(prec, ir_tol=1e-12)
     code, t = _batch_size(ns, m0s, [16] * 5, o, [True] * 5)
-    assert code == 0 and t == (total + (16 << 20) if prec == "fp64" else total)
+    assert code == 0 and t == (total + (64 << 20) if prec == "fp64" else total)
 
 
 def test_batch_rejects_mixed_node_counts_and_bad_sizes():
