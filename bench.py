@@ -269,12 +269,11 @@ def load_batch(count=64, device=None):
 
 
 def tune_tiles(fm, q, modes, dev):
-    """The trailing update's tile shape per row bucket, measured for each storage precision whose
-    update runs on the FP32 / FP64 matrix cores and set in the library before timing (outside the
-    timed region).  The FP32 and FP16 modes update on the FP16 matrix cores, whose kernel does not
-    read the table."""
+    """The trailing update's tile shape per row bucket, measured for the update kernel of each mode in
+    use (FP32: the split FP16 kernel; FP64: the FP64 kernel) and set in the library before timing
+    (outside the timed region)."""
     out = {}
-    for mode in sorted({"fp64" for m in modes if m == "fp64"}):
+    for mode in sorted({m for m in modes if m in ("fp32", "fp64")}):
         t = fm.binding.autotune_tiles(mode, q, device=dev)
         out[mode] = [dict(rows_up_to=r, shape=shape, tflops={k: round(v, 1) for k, v in tf.items()})
                      for r, shape, tf in t]

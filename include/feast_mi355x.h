@@ -366,16 +366,21 @@ int feast_set_panel_rows(int precision, int q, int single_rows);
 
 /* Tile shapes of the LU trailing update (the dominant kernel of a
  * factorisation, A22 -= L21 U12 on the matrix cores).  The library holds
- * several compiled tile shapes per precision (FP32: 0 = 128 x 64, 1 = 64 x 64,
- * 2 = 64 x 128; FP64: 0 = 64 x 64, 1 = 128 x 64) and, for the updates wider
- * than one panel (the end of each group of four panels), a table that picks
- * one by the update's row count, in six buckets (at most 256, 512, 1024, 2048,
- * 4096 rows, and more); shape 0 until tuned and for one-panel-wide updates.  feast_autotune_tiles times every shape
- * on a synthetic update of each bucket (rows = columns = 256 ... 6144, depth
- * 256, up to q nodes) on `stream`, sets the table for `precision` (FP16 means
- * its FP32 storage) in this process, and returns the chosen shapes in
- * table[6] and the measured TFLOP/s in tflops[6 x 3] (bucket-major, 0 for
- * shapes the precision lacks); either may be NULL.  The workspace (device,
+ * compiled tile shapes for each update kernel, and `precision` names the kernel:
+ * FEAST_FP64 the FP64 matrix-core update (0 = 64 x 64, 1 = 128 x 64);
+ * FEAST_FP32_IR the FP32 mode's default update on the FP16 matrix cores with
+ * split operands (split_update = 1; 0 = 128 x 64, 1 = 64 x 64, 2 = 64 x 128); FEAST_FP16_IR
+ * the FP32 matrix-core update (FP32 contexts with split_update = 0, and FP16
+ * contexts after an escalation; 0 = 128 x 64, 1 = 64 x 64, 2 = 64 x 128).  For
+ * each kernel a table picks a shape by the update's row count, in six buckets
+ * (at most 256, 512, 1024, 2048, 4096 rows, and more); shape 0 until tuned.
+ * The FP32 / FP64 kernels take shape 0 for one-panel-wide updates, the split
+ * kernel 64 x 64 for updates of at most 64 rows.  feast_autotune_tiles times
+ * every shape of the kernel on a synthetic grouped update of each bucket (four
+ * members of rows = columns up to 256 ... 6144, depth 256, up to q nodes) on
+ * `stream`, sets the kernel's table in this process, and returns the chosen
+ * shapes in table[6] and the measured TFLOP/s in tflops[6 x 3] (bucket-major,
+ * 0 for shapes the kernel lacks); either may be NULL.  The workspace (device,
  * feast_autotune_tiles_workspace_size bytes) is overwritten.  Synchronous.
  * feast_set_update_tile sets one entry directly.  Returns 0, -i,
  * FEAST_EWORKSPACE, FEAST_EDEVICE. */

@@ -879,7 +879,9 @@ def autotune(precision="fp32", q=16, cache_path=None, device="cuda"):
 
 
 TILE_BUCKET_ROWS = [256, 512, 1024, 2048, 4096, None]   # upper row counts of the tile table's buckets
-TILE_SHAPES = {"fp32": ["128x64", "64x64", "64x128"], "fp64": ["64x64", "128x64"]}
+# per precision argument: the split FP16 update of the FP32 mode, the FP32 matrix-core update (named by
+# "fp16", see feast_autotune_tiles), the FP64 update
+TILE_SHAPES = {"fp32": ["128x64", "64x64", "64x128"], "fp16": ["128x64", "64x64", "64x128"], "fp64": ["64x64", "128x64"]}
 
 
 def autotune_tiles(precision="fp32", q=16, device="cuda"):
@@ -894,7 +896,7 @@ def autotune_tiles(precision="fp32", q=16, device="cuda"):
     tf = np.zeros(18, dtype=np.float64)
     _check(lib().feast_autotune_tiles(PRECISIONS[precision], q, ws.data_ptr(), nbytes.value, _stream(),
                                       table.ctypes.data, tf.ctypes.data), "feast_autotune_tiles")
-    shapes = TILE_SHAPES["fp64" if precision == "fp64" else "fp32"]
+    shapes = TILE_SHAPES[precision]
     return [(TILE_BUCKET_ROWS[b], shapes[table[b]], {shapes[t]: float(tf[3 * b + t]) for t in range(len(shapes))})
             for b in range(6)]
 

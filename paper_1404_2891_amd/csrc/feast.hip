@@ -2625,11 +2625,18 @@ size_t tile_tune_bytes(int q, bool dbl) {
     return most;
 }
 
+// The update kernel whose tile table a precision argument names: FP64 its FP64 kernel, FP32 the
+// split FP16 kernel of the FP32 mode, FP16 the FP32 kernel (FP32 contexts with split_update = 0 and
+// FP16 contexts after an escalation).
+int update_table(int precision) {
+    return precision == FEAST_FP64 ? UPD_F64 : (precision == FEAST_FP32_IR ? UPD_SPLIT : UPD_F32);
+}
+
 template <typename T>
-int tune_tiles(int q, char* ws, hipStream_t st, int* table, double* times) {
+int tune_tiles(int which, int q, char* ws, hipStream_t st, int* table, double* times) {
     const bool dbl = std::is_same<T, double>::value;
     const size_t E = sizeof(cplx<T>);
-    const int nc = update_tile_candidates(dbl);
+    const int nc = update_tile_candidates(which);
     hipEvent_t e0, e1;
     FM_HIP(hipEventCreate(&e0));
     FM_HIP(hipEventCreate(&e1));
@@ -2665,7 +2672,7 @@ int tune_tiles(int q, char* ws, hipStream_t st, int* table, double* times) {
         g.rowA = g.rowB = g.rowC = true;
         g.M = Mmax; g.N = Mmax; g.K = K; g.batch = batch;
         g.alpha = z64(-1.0); g.beta = z64(1.0);
-        g.kind = 1;
+        g.kind = which == UPD_SPLIT ? 3 : 1;   // (the split kernel unscaled: the entries lie in [-1, 1))
         g.groups = dev_groups;
         g.ngroups = TILE_TUNE_MEMBERS;
         double best = 1e30;
@@ -2691,7 +2698,7 @@ int tune_tiles(int q, char* ws, hipStream_t st, int* table, double* times) {
         if (times)
             for (int t = nc; t < 3; ++t) times[b * 3 + t] = 0.0;
         if (!rc) {
-            update_tile_set(dbl, b, arg);
+            update_tile_set(which, b, arg);
             if (table) table[b] = arg;
         }
     }
@@ -2720,16 +2727,16 @@ int feast_autotune_tiles(int precision, int q, void* workspace, size_t workspace
     if (!workspace || ((uintptr_t)workspace % ALIGN) || workspace_bytes < tile_tune_bytes(q, dbl))
         return FEAST_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    return dbl ? tune_tiles<double>(q, (char*)workspace, st, table, tflops)
-               : tune_tiles<float>(q, (char*)workspace, st, table, tflops);
+    return dbl ? tune_tiles<double>(UPD_F64, q, (char*)workspace, st, table, tflops)
+               : tune_tiles<float>(update_table(precision), q, (char*)workspace, st, table, tflops);
 }
 
 int feast_set_update_tile(int precision, int bucket, int candidate) {
     if (precision < FEAST_FP64 || precision > FEAST_FP16_IR) return -1;
     if (bucket < 0 || bucket >= UPDATE_TILE_BUCKETS) return -2;
-    const bool dbl = precision == FEAST_FP64;
-    if (candidate < 0 || candidate >= update_tile_candidates(dbl)) return -3;
-    update_tile_set(dbl, bucket, candidate);
+    const int which = update_table(precision);
+    if (candidate < 0 || candidate >= update_tile_candidates(which)) return -3;
+    update_tile_set(which, bucket, candidate);
     return 0;
 }
 

@@ -65,16 +65,18 @@ struct GemmOp {
     int tile = -1;
 };
 
-// Tile candidates of the LU trailing update (kind 1), compiled in: FP32 0 = 128 x 64 (each wave
-// 4 x 2 blocks of 16 x 16), 1 = 64 x 64, 2 = 64 x 128; FP64 0 = 64 x 64, 1 = 128 x 64.  For updates
-// wider than one panel (64 columns) a table maps the row count, in buckets of at most 256, 512,
-// 1024, 2048, 4096 and more rows, to a candidate (0 until the tile tuner sets it); one-panel-wide
-// updates take candidate 0.
+// Tile candidates of the LU trailing update, compiled in, with one table per update kernel:
+// UPD_F32 (kind 1, FP32) 0 = 128 x 64 (each wave 4 x 2 blocks of 16 x 16), 1 = 64 x 64,
+// 2 = 64 x 128; UPD_F64 (kind 1, FP64) 0 = 64 x 64, 1 = 128 x 64; UPD_SPLIT (kind 3) 0 = 128 x 64,
+// 1 = 64 x 64, 2 = 64 x 128.  A table maps the update's row count, in buckets of at most 256, 512, 1024, 2048,
+// 4096 and more rows, to a candidate (0 until the tile tuner sets it).  Kind 1 takes candidate 0 for
+// one-panel-wide updates, kind 3 the 64 x 64 tile for updates of at most 64 rows.
+enum UpdateTable { UPD_F32 = 0, UPD_F64 = 1, UPD_SPLIT = 2, UPD_TABLES = 3 };
 constexpr int UPDATE_TILE_BUCKETS = 6;
-int update_tile_candidates(bool dbl);
+int update_tile_candidates(int table);
 int update_tile_bucket(int M);
-int update_tile_get(bool dbl, int bucket);
-void update_tile_set(bool dbl, int bucket, int candidate);
+int update_tile_get(int table, int bucket);
+void update_tile_set(int table, int bucket, int candidate);
 
 // T = double (complex128 operands, FP64 MFMA) or float (complex64, FP32 MFMA).
 template <typename T>

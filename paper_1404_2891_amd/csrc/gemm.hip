@@ -627,17 +627,25 @@ int gemm(const GemmOp& op, hipStream_t st) {
     if (op.kind == 2 || op.kind == 3) {  // LU trailing update on FP16 matrix cores (complex64 only)
         if constexpr (std::is_same<T, float>::value) {
             if (!(op.rowA && op.rowB && op.rowC) || p.splitk > 1 || op.alpha_b) return FEAST_EUNSUPPORTED;
-            // 128 x 64 tiles once the rows fill them, else 64 x 64
-            const bool tall = p.M > 64;
-            p.tiles_m = ceil_div(p.M, tall ? 128 : 64);
-            dim3 grid(p.tiles_m * ceil_div(p.N, 64), 1, p.batch * p.batch2 * (p.groups ? p.ngroups : 1));
+            // kind 3: the tuned table's shape (0 = 128 x 64, 1 = 64 x 64, 2 = 64 x 128), 64 x 64 for at most
+            // 64 rows; kind 2: 128 x 64 once the rows fill them, else 64 x 64
+            int shape = p.M > 64 ? 0 : 1;
             if (op.kind == 3) {
-                if (tall)
+                shape = op.tile >= 0 ? op.tile : (p.M > 64 ? update_tile_get(UPD_SPLIT, update_tile_bucket(p.M)) : 1);
+                if (shape < 0 || shape >= update_tile_candidates(UPD_SPLIT)) return FEAST_EUNSUPPORTED;
+            }
+            const int BM = shape == 0 ? 128 : 64, BN = shape == 2 ? 128 : 64;
+            p.tiles_m = ceil_div(p.M, BM);
+            dim3 grid(p.tiles_m * ceil_div(p.N, BN), 1, p.batch * p.batch2 * (p.groups ? p.ngroups : 1));
+            if (op.kind == 3) {
+                if (shape == 0)
                     hipLaunchKernelGGL((cgemm_f16_kernel<true, 4, 2>), grid, dim3(256), 0, st, p);
-                else
+                else if (shape == 1)
                     hipLaunchKernelGGL((cgemm_f16_kernel<true, 2, 2>), grid, dim3(256), 0, st, p);
+                else
+                    hipLaunchKernelGGL((cgemm_f16_kernel<true, 2, 4>), grid, dim3(256), 0, st, p);
             } else {
-                if (tall)
+                if (shape == 0)
                     hipLaunchKernelGGL((cgemm_f16_kernel<false, 4, 2>), grid, dim3(256), 0, st, p);
                 else
                     hipLaunchKernelGGL((cgemm_f16_kernel<false, 2, 2>), grid, dim3(256), 0, st, p);
@@ -653,8 +661,9 @@ int gemm(const GemmOp& op, hipStream_t st) {
         constexpr bool dbl = std::is_same<T, double>::value;
         // the table covers the updates at the end of a group of panels (all columns right of it);
         // those inside a group are one panel wide, which shape 0 fits
-        const int tile = op.tile >= 0 ? op.tile : (p.N <= 64 ? 0 : update_tile_get(dbl, update_tile_bucket(p.M)));
-        if (tile < 0 || tile >= update_tile_candidates(dbl)) return FEAST_EUNSUPPORTED;
+        const int tb = dbl ? UPD_F64 : UPD_F32;
+        const int tile = op.tile >= 0 ? op.tile : (p.N <= 64 ? 0 : update_tile_get(tb, update_tile_bucket(p.M)));
+        if (tile < 0 || tile >= update_tile_candidates(tb)) return FEAST_EUNSUPPORTED;
         if constexpr (!dbl) {
             if (tile == 0)
                 launch_cfg<T, 2, 2, 4, 2, true, true, true, 1>(p, st);
@@ -702,10 +711,10 @@ int gemm(const GemmOp& op, hipStream_t st) {
 }
 
 namespace {
-std::atomic<int> g_update_tile[2][UPDATE_TILE_BUCKETS];   // zero-initialised: candidate 0
+std::atomic<int> g_update_tile[UPD_TABLES][UPDATE_TILE_BUCKETS];   // zero-initialised: candidate 0
 }
 
-int update_tile_candidates(bool dbl) { return dbl ? 2 : 3; }
+int update_tile_candidates(int table) { return table == UPD_F64 ? 2 : 3; }
 
 int update_tile_bucket(int M) {
     int b = 0;
@@ -713,9 +722,9 @@ int update_tile_bucket(int M) {
     return b;
 }
 
-int update_tile_get(bool dbl, int bucket) { return g_update_tile[dbl ? 1 : 0][bucket].load(); }
+int update_tile_get(int table, int bucket) { return g_update_tile[table][bucket].load(); }
 
-void update_tile_set(bool dbl, int bucket, int candidate) { g_update_tile[dbl ? 1 : 0][bucket].store(candidate); }
+void update_tile_set(int table, int bucket, int candidate) { g_update_tile[table][bucket].store(candidate); }
 
 template <typename T>
 GemmGroup gemm_member(const GemmOp& op) {

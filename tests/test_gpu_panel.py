@@ -104,24 +104,27 @@ def test_tournament_pivoting_iteration(variant):
     F.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "fp64"])
 def test_update_tile_shapes_agree_and_the_tuner_sets_the_table(prec):
-    """Every compiled tile shape of the trailing update sums each output in the same order (the
+    """Every compiled tile shape of a trailing-update kernel sums each output in the same order (the
     same operand slices, the same matrix-core steps), so factorisations made with any of them give
     bit-identical filters; the tuner then picks a shape per row bucket, sets the table and reports a
-    throughput for every shape it timed."""
+    throughput for every shape it timed.  The tables: "fp32" the split FP16 kernel of the FP32 mode,
+    "fp16" the FP32 matrix-core kernel (FP32 contexts with split_update off), "fp64" the FP64 kernel."""
     import torch
     from tests.gpu_common import random_pencil
     fmod = fm()
     A, B, lam = random_pencil(700, 31, True)
     dA, dB = fmod.to_device(A, device()), fmod.to_device(B, device())
     U = fmod.to_device(pencils.start_block(2, 700, 12, salt=5), device())
-    shapes = fmod.binding.TILE_SHAPES["fp64" if prec == "fp64" else "fp32"]
+    shapes = fmod.binding.TILE_SHAPES[prec]
+    ctx = {"fp32": dict(precision="fp32"), "fp16": dict(precision="fp32", split_update=False),
+           "fp64": dict(precision="fp64")}[prec]
     outs = []
     for t in range(len(shapes)):
         for b in range(6):
             fmod.binding.set_update_tile(prec, b, t)
-        with fmod.Feast(dA, dB, 0j, 1.0, 1.0, 16, 12, precision=prec) as F:
+        with fmod.Feast(dA, dB, 0j, 1.0, 1.0, 16, 12, **ctx) as F:
             outs.append(F.filter(U).clone())
     torch.cuda.synchronize()
     for o in outs[1:]:
