@@ -187,6 +187,23 @@ def test_iterate_device_and_host_orthonormalisation(variant, m0):
     assert abs(out[False].iterations - out[True].iterations) <= 1
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("host_ortho", [False, True])
+def test_iterate_zero_start_block_reports_reduced_failure(prec, host_ortho):
+    """A zero start block filters to a zero block whose Gram matrix has zero trace: the shifted
+    Cholesky-QR cannot factor it, on the device (its failure flag) or on the host, and the iteration
+    stops with FEAST_EREDUCED instead of producing vectors."""
+    A, B, lam = random_pencil(150, seed=12, with_B=True, m=5)
+    F = fm().Feast(upload(A), upload(B), 0j, 1.0, 1.0, 16, 8, precision=prec, host_ortho=host_ortho)
+    with pytest.raises(fm().FeastError) as err:
+        F.iterate(upload(np.zeros((150, 8), dtype=np.complex128)))
+    assert err.value.code == fm().binding.FEAST_EREDUCED
+    # the context stays usable
+    res = F.iterate(upload(pencils.complex_gaussian(np.random.default_rng(4), (150, 8))))
+    check_eigenpairs(res, A, B, brute.eigenvalues_inside(lam, 0, 1.0))
+    F.close()
+
+
 def test_iterate_empty_contour():
     """No eigenvalue inside: the iteration stops with m = 0."""
     A, B, lam = random_pencil(120, seed=4, with_B=False, m=0)
