@@ -82,6 +82,15 @@ struct feast_ctx {
     LUDev* lu_dev = nullptr;          // device descriptor of this pencil's factor storage
     GemmGroup* lu_groups = nullptr;   // grouped-product members of its factorisation
     int lu_ngroups = 0;
+    // the nodes in two halves factored side by side on two streams (tournament pivoting, no phase
+    // timing): while one half runs its latency-bound panels the other's trailing updates fill the
+    // device.  Descriptors and grouped-product tables of the halves, the second stream, fork / join
+    // events.
+    bool halves = false;
+    LUDev* lu_dev_half = nullptr;         // 2 descriptors
+    GemmGroup* lu_groups_half = nullptr;  // 2 x lu_ngroups members
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // members of a batch: the batch's stream (possibly the null stream), which the public entry
     // points order themselves against (see OuterOrder)
     bool member = false;
@@ -166,6 +175,8 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     }
     c->lu_dev = b.take<LUDev>(1);
     c->lu_groups = b.take<GemmGroup>(c->lu_ngroups);
+    c->lu_dev_half = b.take<LUDev>(2);
+    c->lu_groups_half = b.take<GemmGroup>(2 * (size_t)c->lu_ngroups);
 
     c->Yw = b.take<char>((size_t)q * np * E);
     c->Xw = b.take<char>((size_t)q * np * E);
@@ -786,6 +797,44 @@ LUSet ctx_set(feast_ctx* c) {
     return one;
 }
 
+// Half h of the nodes (0: the first q / 2, 1: the rest) as a factor store of its own: every per-node
+// array starts at the half's first node (the staging buffer at a stride that covers both of its uses).
+LUStore lu_half(const feast_ctx* c, int h) {
+    const LUStore& s = c->lu;
+    const int k0 = h == 0 ? 0 : s.q / 2, qh = h == 0 ? s.q / 2 : s.q - s.q / 2;
+    const size_t E = elem_bytes(c->prec);
+    LUStore v = s;
+    v.q = qh;
+    v.timer = nullptr;
+    v.F = (char*)s.F + (size_t)k0 * s.sF * E;
+    v.ipiv = s.ipiv + (size_t)k0 * s.spiv;
+    v.perm = s.perm + (size_t)k0 * s.spiv;
+    v.iperm = s.iperm + (size_t)k0 * s.spiv;
+    v.Linv = (char*)s.Linv + (size_t)k0 * s.nsteps * s.nb * s.nb * E;
+    v.Uinv = (char*)s.Uinv + (size_t)k0 * s.nsteps * s.nb * s.nb * E;
+    v.info = s.info + k0;
+    v.tmp = (char*)s.tmp + (size_t)k0 * lu_tmp_elems(s.n, s.nb, s.nbs) * E;
+    v.pslots = nullptr;   // tournament panels use none
+    if (s.LinvS) v.LinvS = (char*)s.LinvS + (size_t)k0 * s.nsbs * s.nbs * s.nbs * E;
+    if (s.UinvS) v.UinvS = (char*)s.UinvS + (size_t)k0 * s.nsbs * s.nbs * s.nbs * E;
+    v.z = s.z + k0;
+    if (s.amax) v.amax = s.amax + k0;
+    if (s.tcand) v.tcand = s.tcand + (size_t)k0 * tslu_node_ints(s.tW0);
+    if (s.ttop) v.ttop = (char*)s.ttop + (size_t)k0 * s.nb * s.nb * E;
+    return v;
+}
+
+LUSet half_set(feast_ctx* c, const LUStore* v, int h) {
+    LUSet one;
+    one.s = v;
+    one.count = 1;
+    one.dev = c->lu_dev_half + h;
+    one.groups = c->lu_groups_half + (size_t)h * c->lu_ngroups;
+    one.timer = nullptr;
+    one.single_rows = tuned_single_rows(c->prec, c->q);
+    return one;
+}
+
 // A public entry point called on a batch member: the member's stream starts after the work on the
 // batch's stream, and the batch's stream continues after the member's work.
 struct OuterOrder {
@@ -838,8 +887,8 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     const int q = C->q, p = m0;
     c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
     // the tables of ctx_tables, staged side by side
-    c->hbytes = std::max<size_t>(c->hbytes, (size_t)c->lu_ngroups * sizeof(GemmGroup) + sizeof(LUDev) +
-                                                6 * (size_t)q * sizeof(z64) + 3 * ALIGN);
+    c->hbytes = std::max<size_t>(c->hbytes, 3 * (size_t)c->lu_ngroups * sizeof(GemmGroup) + 3 * sizeof(LUDev) +
+                                                6 * (size_t)q * sizeof(z64) + 8 * ALIGN);
     const size_t pp = (size_t)p * p;
     const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp + 1;
     const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
@@ -935,14 +984,52 @@ int ctx_tables(feast_ctx* c, const feast_contour* C) {
         lu_plan<float>(one, plan);
     if ((int)plan.size() != c->lu_ngroups) return FEAST_EUNSUPPORTED;
     if (!plan.empty()) FM_TRY(stage(c->lu_groups, plan.data(), plan.size() * sizeof(GemmGroup)));
+    // the two halves of the nodes (tournament pivoting only: no panel slots)
+    c->halves = false;
+    if (c->lu.tslu && c->lu.tcand && c->q >= 2) {
+        bool ok = true;
+        for (int h = 0; h < 2 && ok; ++h) {
+            const LUStore v = lu_half(c, h);
+            const LUDev dh = lu_dev(v, elem_bytes(c->prec) / 2);
+            FM_TRY(stage(c->lu_dev_half + h, &dh, sizeof(LUDev)));
+            const LUSet hs = half_set(c, &v, h);
+            if (c->prec == Prec::F64)
+                lu_plan<double>(hs, plan);
+            else
+                lu_plan<float>(hs, plan);
+            ok = (int)plan.size() == c->lu_ngroups;
+            if (ok && !plan.empty())
+                FM_TRY(stage(c->lu_groups_half + (size_t)h * c->lu_ngroups, plan.data(), plan.size() * sizeof(GemmGroup)));
+        }
+        c->halves = ok;
+    }
     FM_HIP(hipStreamSynchronize(c->st));
     return 0;
 }
 
 // a2 + a3: assemble and factor every node (enqueue only, no host synchronisation)
 int ctx_factor_enqueue(feast_ctx* c) {
+    const bool dbl = c->prec == Prec::F64;
+    if (c->halves && !c->lu.timer && !op_log()) {
+        if (!c->aux) {
+            c->aux = stream_pool().get();
+            if (!c->aux || hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+                return FEAST_EDEVICE;
+        }
+        // the halves follow the context's current flags (an escalation changes them)
+        const LUStore v0 = lu_half(c, 0), v1 = lu_half(c, 1);
+        const LUSet s0 = half_set(c, &v0, 0), s1 = half_set(c, &v1, 1);
+        FM_HIP(hipEventRecord(c->ev_fork, c->st));
+        FM_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        FM_TRY(dbl ? lu_factor_set<double>(s1, c->aux) : lu_factor_set<float>(s1, c->aux));
+        FM_TRY(dbl ? lu_factor_set<double>(s0, c->st) : lu_factor_set<float>(s0, c->st));
+        FM_HIP(hipEventRecord(c->ev_join, c->aux));
+        FM_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
+        return 0;
+    }
     const LUSet one = ctx_set(c);
-    return c->prec == Prec::F64 ? lu_factor_set<double>(one, c->st) : lu_factor_set<float>(one, c->st);
+    return dbl ? lu_factor_set<double>(one, c->st) : lu_factor_set<float>(one, c->st);
 }
 
 int ctx_check_info(feast_ctx* c) {
@@ -1905,6 +1992,12 @@ void feast_destroy(feast_ctx* c) {
     pinned_pool().put(c->h);
     pinned_pool().put(c->pin_base);
     if (c->outer_ev) (void)hipEventDestroy(c->outer_ev);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        stream_pool().put(c->aux);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
