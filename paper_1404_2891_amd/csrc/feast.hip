@@ -2153,6 +2153,13 @@ struct feast_batch {
     hipStream_t user = nullptr;
     LUDev* dev = nullptr;
     GemmGroup* groups = nullptr;
+    // the graph factors the nodes in two halves on two branches (tournament pivoting): the halves'
+    // views of every member's storage, their descriptors and grouped-product tables
+    bool halves = false;
+    std::vector<LUStore> half_stores[2];
+    LUDev* dev_half = nullptr;          // 2 x count
+    GemmGroup* groups_half = nullptr;   // 2 x ngroups
+    size_t ngroups = 0;                 // grouped-product members of the set's sequence
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float factor_ms = 0.0f;
@@ -2183,7 +2190,7 @@ bool batch_grouped(const feast_options* o) {
 }
 
 struct BatchLayout {
-    size_t dev_off = 0, groups_off = 0, ngroups = 0, arena_off = 0;
+    size_t dev_off = 0, groups_off = 0, ngroups = 0, arena_off = 0, dev_half_off = 0, groups_half_off = 0;
     std::vector<size_t> off, bytes;
     size_t total = 0;
 };
@@ -2207,6 +2214,10 @@ int batch_layout(int count, const int* n, const int* m0, const feast_contour* C,
     off = align_up(off + (size_t)count * sizeof(LUDev), ALIGN);
     L.groups_off = off;
     off = align_up(off + L.ngroups * sizeof(GemmGroup), ALIGN);
+    L.dev_half_off = off;
+    off = align_up(off + 2 * (size_t)count * sizeof(LUDev), ALIGN);
+    L.groups_half_off = off;
+    off = align_up(off + 2 * L.ngroups * sizeof(GemmGroup), ALIGN);
     L.arena_off = off;
     if (!o || batch_grouped(o)) off = align_up(off + SET_ARENA_BYTES, ALIGN);
     for (int b = 0; b < count; ++b) {
@@ -2230,17 +2241,45 @@ void batch_free(feast_batch* bt) {
 
 // Captures the set's factorisation sequence on a private stream into a graph.
 int batch_capture(feast_batch* bt, const LUSet& S) {
-    hipStream_t cap = nullptr;
+    hipStream_t cap = nullptr, cap2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     FM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     int rc = 0;
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    if (bt->halves && (hipStreamCreateWithFlags(&cap2, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess))
+        rc = FEAST_EDEVICE;
+    if (rc || hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipStreamDestroy(cap);
+        if (cap2) (void)hipStreamDestroy(cap2);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
         return FEAST_EDEVICE;
     }
-    rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S, cap) : lu_factor_set<float>(S, cap);
+    if (bt->halves) {
+        // two branches: half 1 on a second stream joined to the capture by an event, half 0 on the
+        // capturing stream, which then waits for the branch
+        LUSet S0 = S, S1 = S;
+        S0.s = bt->half_stores[0].data();
+        S0.dev = bt->dev_half;
+        S0.groups = bt->groups_half;
+        S1.s = bt->half_stores[1].data();
+        S1.dev = bt->dev_half + S.count;
+        S1.groups = bt->groups_half + bt->ngroups;
+        if (hipEventRecord(fork, cap) != hipSuccess || hipStreamWaitEvent(cap2, fork, 0) != hipSuccess) rc = FEAST_EDEVICE;
+        if (!rc) rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S1, cap2) : lu_factor_set<float>(S1, cap2);
+        if (!rc) rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S0, cap) : lu_factor_set<float>(S0, cap);
+        if (!rc && (hipEventRecord(join, cap2) != hipSuccess || hipStreamWaitEvent(cap, join, 0) != hipSuccess))
+            rc = FEAST_EDEVICE;
+    } else {
+        rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S, cap) : lu_factor_set<float>(S, cap);
+    }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &g);
     (void)hipStreamDestroy(cap);
+    if (cap2) (void)hipStreamDestroy(cap2);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
     if (rc || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return rc ? rc : FEAST_EDEVICE;
@@ -2334,6 +2373,9 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
     char* base = (char*)workspace;
     bt->dev = (LUDev*)(base + L.dev_off);
     bt->groups = (GemmGroup*)(base + L.groups_off);
+    bt->dev_half = (LUDev*)(base + L.dev_half_off);
+    bt->groups_half = (GemmGroup*)(base + L.groups_half_off);
+    bt->ngroups = L.ngroups;
     int rc = 0;
     bt->grouped = batch_grouped(o);
     if (bt->grouped) {
@@ -2386,6 +2428,35 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
                     (!plan.empty() && hipMemcpy(bt->groups, plan.data(), plan.size() * sizeof(GemmGroup),
                                                 hipMemcpyHostToDevice) != hipSuccess)))
             rc = FEAST_EDEVICE;
+        // the halves of the nodes (tournament pivoting only: no panel slots)
+        bool halves = !rc && !o->timing && o->pivoting == 1 && C[0].q >= 2;
+        for (int b = 0; b < count && halves; ++b) halves = bt->stores[b].tslu && bt->stores[b].tcand;
+        for (int h = 0; h < 2 && halves && !rc; ++h) {
+            bt->half_stores[h].resize(count);
+            std::vector<LUDev> dh(count);
+            for (int b = 0; b < count; ++b) {
+                bt->half_stores[h][b] = lu_half(bt->ctx[b], h);
+                dh[b] = lu_dev(bt->half_stores[h][b], bt->prec == Prec::F64 ? 8 : 4);
+            }
+            LUSet Sh = S;
+            Sh.s = bt->half_stores[h].data();
+            Sh.dev = bt->dev_half + (size_t)h * count;
+            Sh.groups = bt->groups_half + (size_t)h * L.ngroups;
+            std::vector<GemmGroup> ph;
+            if (bt->prec == Prec::F64)
+                lu_plan<double>(Sh, ph);
+            else
+                lu_plan<float>(Sh, ph);
+            if (ph.size() != L.ngroups) {
+                halves = false;
+                break;
+            }
+            if (hipMemcpy(Sh.dev, dh.data(), count * sizeof(LUDev), hipMemcpyHostToDevice) != hipSuccess ||
+                (!ph.empty() && hipMemcpy(Sh.groups, ph.data(), ph.size() * sizeof(GemmGroup), hipMemcpyHostToDevice) !=
+                                    hipSuccess))
+                rc = FEAST_EDEVICE;
+        }
+        bt->halves = halves && !rc;
         if (!rc && o->timing) {
             bt->timer.on = true;
             S.timer = &bt->timer;
