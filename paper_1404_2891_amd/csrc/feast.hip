@@ -58,6 +58,12 @@ int splitk_for(int K) { return std::max(1, std::min(64, K / 256)); }
 // (n / 64)(m0 / 64) workgroups, too few for 256 compute units when m0 = 64; up to this many K-splits
 // fill the chip
 constexpr int TALL_SPLITK = 4;
+// parts of the nodes factored concurrently (tournament pivoting): NODE_PARTS for one pencil on its
+// own streams, BATCH_PARTS for the branches of a batch's factorisation graph (measured: two parts
+// take the n = 4096 solve from 104 to 100 ms and four parts do no better; the batch's graph gains
+// 122 -> 116.5 ms with two and 113.6 ms with four)
+constexpr int NODE_PARTS = 2;
+constexpr int BATCH_PARTS = 4;
 
 }  // namespace
 
@@ -82,15 +88,15 @@ struct feast_ctx {
     LUDev* lu_dev = nullptr;          // device descriptor of this pencil's factor storage
     GemmGroup* lu_groups = nullptr;   // grouped-product members of its factorisation
     int lu_ngroups = 0;
-    // the nodes in two halves factored side by side on two streams (tournament pivoting, no phase
-    // timing): while one half runs its latency-bound panels the other's trailing updates fill the
-    // device.  Descriptors and grouped-product tables of the halves, the second stream, fork / join
-    // events.
+    // the nodes in NODE_PARTS parts factored side by side on as many streams (tournament pivoting,
+    // no phase timing): while one part runs its latency-bound panels the others' trailing updates
+    // fill the device.  Descriptors and grouped-product tables of the parts, the extra streams,
+    // fork / join events.
     bool halves = false;
-    LUDev* lu_dev_half = nullptr;         // 2 descriptors
-    GemmGroup* lu_groups_half = nullptr;  // 2 x lu_ngroups members
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    LUDev* lu_dev_half = nullptr;         // NODE_PARTS descriptors
+    GemmGroup* lu_groups_half = nullptr;  // NODE_PARTS x lu_ngroups members
+    hipStream_t aux[NODE_PARTS - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[NODE_PARTS - 1] = {};
     // members of a batch: the batch's stream (possibly the null stream), which the public entry
     // points order themselves against (see OuterOrder)
     bool member = false;
@@ -175,8 +181,8 @@ void layout(feast_ctx* c, Bump& b, bool has_B) {
     }
     c->lu_dev = b.take<LUDev>(1);
     c->lu_groups = b.take<GemmGroup>(c->lu_ngroups);
-    c->lu_dev_half = b.take<LUDev>(2);
-    c->lu_groups_half = b.take<GemmGroup>(2 * (size_t)c->lu_ngroups);
+    c->lu_dev_half = b.take<LUDev>(NODE_PARTS);
+    c->lu_groups_half = b.take<GemmGroup>(NODE_PARTS * (size_t)c->lu_ngroups);
 
     c->Yw = b.take<char>((size_t)q * np * E);
     c->Xw = b.take<char>((size_t)q * np * E);
@@ -797,11 +803,12 @@ LUSet ctx_set(feast_ctx* c) {
     return one;
 }
 
-// Half h of the nodes (0: the first q / 2, 1: the rest) as a factor store of its own: every per-node
-// array starts at the half's first node (the staging buffer at a stride that covers both of its uses).
-LUStore lu_half(const feast_ctx* c, int h) {
+// Part h of `parts` of the nodes (nodes h q / P .. (h + 1) q / P - 1) as a factor store of its
+// own: every per-node array starts at the part's first node (the staging buffer at a stride that
+// covers both of its uses).
+LUStore lu_half(const feast_ctx* c, int h, int parts = NODE_PARTS) {
     const LUStore& s = c->lu;
-    const int k0 = h == 0 ? 0 : s.q / 2, qh = h == 0 ? s.q / 2 : s.q - s.q / 2;
+    const int k0 = h * s.q / parts, qh = (h + 1) * s.q / parts - k0;
     const size_t E = elem_bytes(c->prec);
     LUStore v = s;
     v.q = qh;
@@ -887,8 +894,8 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     const int q = C->q, p = m0;
     c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
     // the tables of ctx_tables, staged side by side
-    c->hbytes = std::max<size_t>(c->hbytes, 3 * (size_t)c->lu_ngroups * sizeof(GemmGroup) + 3 * sizeof(LUDev) +
-                                                6 * (size_t)q * sizeof(z64) + 8 * ALIGN);
+    c->hbytes = std::max<size_t>(c->hbytes, (1 + NODE_PARTS) * ((size_t)c->lu_ngroups * sizeof(GemmGroup) + sizeof(LUDev)) +
+                                                6 * (size_t)q * sizeof(z64) + (4 + 2 * NODE_PARTS) * ALIGN);
     const size_t pp = (size_t)p * p;
     const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp + 1;
     const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
@@ -984,11 +991,11 @@ int ctx_tables(feast_ctx* c, const feast_contour* C) {
         lu_plan<float>(one, plan);
     if ((int)plan.size() != c->lu_ngroups) return FEAST_EUNSUPPORTED;
     if (!plan.empty()) FM_TRY(stage(c->lu_groups, plan.data(), plan.size() * sizeof(GemmGroup)));
-    // the two halves of the nodes (tournament pivoting only: no panel slots)
+    // the parts of the nodes (tournament pivoting only: no panel slots)
     c->halves = false;
-    if (c->lu.tslu && c->lu.tcand && c->q >= 2) {
+    if (c->lu.tslu && c->lu.tcand && c->q >= NODE_PARTS) {
         bool ok = true;
-        for (int h = 0; h < 2 && ok; ++h) {
+        for (int h = 0; h < NODE_PARTS && ok; ++h) {
             const LUStore v = lu_half(c, h);
             const LUDev dh = lu_dev(v, elem_bytes(c->prec) / 2);
             FM_TRY(stage(c->lu_dev_half + h, &dh, sizeof(LUDev)));
@@ -1011,21 +1018,29 @@ int ctx_tables(feast_ctx* c, const feast_contour* C) {
 int ctx_factor_enqueue(feast_ctx* c) {
     const bool dbl = c->prec == Prec::F64;
     if (c->halves && !c->lu.timer && !op_log()) {
-        if (!c->aux) {
-            c->aux = stream_pool().get();
-            if (!c->aux || hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
-                return FEAST_EDEVICE;
+        if (!c->ev_fork) {
+            if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) return FEAST_EDEVICE;
+            for (int h = 0; h < NODE_PARTS - 1; ++h)
+                if (!(c->aux[h] = stream_pool().get()) ||
+                    hipEventCreateWithFlags(&c->ev_join[h], hipEventDisableTiming) != hipSuccess)
+                    return FEAST_EDEVICE;
         }
-        // the halves follow the context's current flags (an escalation changes them)
-        const LUStore v0 = lu_half(c, 0), v1 = lu_half(c, 1);
-        const LUSet s0 = half_set(c, &v0, 0), s1 = half_set(c, &v1, 1);
+        // the parts follow the context's current flags (an escalation changes them); part 0 runs on
+        // the context's stream, the others on the extra streams after a fork
+        LUStore v[NODE_PARTS];
+        for (int h = 0; h < NODE_PARTS; ++h) v[h] = lu_half(c, h);
         FM_HIP(hipEventRecord(c->ev_fork, c->st));
-        FM_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-        FM_TRY(dbl ? lu_factor_set<double>(s1, c->aux) : lu_factor_set<float>(s1, c->aux));
+        for (int h = 1; h < NODE_PARTS; ++h) {
+            FM_HIP(hipStreamWaitEvent(c->aux[h - 1], c->ev_fork, 0));
+            const LUSet sh = half_set(c, &v[h], h);
+            FM_TRY(dbl ? lu_factor_set<double>(sh, c->aux[h - 1]) : lu_factor_set<float>(sh, c->aux[h - 1]));
+        }
+        const LUSet s0 = half_set(c, &v[0], 0);
         FM_TRY(dbl ? lu_factor_set<double>(s0, c->st) : lu_factor_set<float>(s0, c->st));
-        FM_HIP(hipEventRecord(c->ev_join, c->aux));
-        FM_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
+        for (int h = 1; h < NODE_PARTS; ++h) {
+            FM_HIP(hipEventRecord(c->ev_join[h - 1], c->aux[h - 1]));
+            FM_HIP(hipStreamWaitEvent(c->st, c->ev_join[h - 1], 0));
+        }
         return 0;
     }
     const LUSet one = ctx_set(c);
@@ -1992,12 +2007,14 @@ void feast_destroy(feast_ctx* c) {
     pinned_pool().put(c->h);
     pinned_pool().put(c->pin_base);
     if (c->outer_ev) (void)hipEventDestroy(c->outer_ev);
-    if (c->aux) {
-        (void)hipStreamSynchronize(c->aux);
-        stream_pool().put(c->aux);
+    for (int h = 0; h < NODE_PARTS - 1; ++h) {
+        if (c->aux[h]) {
+            (void)hipStreamSynchronize(c->aux[h]);
+            stream_pool().put(c->aux[h]);
+        }
+        if (c->ev_join[h]) (void)hipEventDestroy(c->ev_join[h]);
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
@@ -2153,12 +2170,12 @@ struct feast_batch {
     hipStream_t user = nullptr;
     LUDev* dev = nullptr;
     GemmGroup* groups = nullptr;
-    // the graph factors the nodes in two halves on two branches (tournament pivoting): the halves'
-    // views of every member's storage, their descriptors and grouped-product tables
+    // the graph factors the nodes in BATCH_PARTS parts on as many branches (tournament pivoting):
+    // the parts' views of every member's storage, their descriptors and grouped-product tables
     bool halves = false;
-    std::vector<LUStore> half_stores[2];
-    LUDev* dev_half = nullptr;          // 2 x count
-    GemmGroup* groups_half = nullptr;   // 2 x ngroups
+    std::vector<LUStore> half_stores[BATCH_PARTS];
+    LUDev* dev_half = nullptr;          // BATCH_PARTS x count
+    GemmGroup* groups_half = nullptr;   // BATCH_PARTS x ngroups
     size_t ngroups = 0;                 // grouped-product members of the set's sequence
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -2215,9 +2232,9 @@ int batch_layout(int count, const int* n, const int* m0, const feast_contour* C,
     L.groups_off = off;
     off = align_up(off + L.ngroups * sizeof(GemmGroup), ALIGN);
     L.dev_half_off = off;
-    off = align_up(off + 2 * (size_t)count * sizeof(LUDev), ALIGN);
+    off = align_up(off + BATCH_PARTS * (size_t)count * sizeof(LUDev), ALIGN);
     L.groups_half_off = off;
-    off = align_up(off + 2 * L.ngroups * sizeof(GemmGroup), ALIGN);
+    off = align_up(off + BATCH_PARTS * L.ngroups * sizeof(GemmGroup), ALIGN);
     L.arena_off = off;
     if (!o || batch_grouped(o)) off = align_up(off + SET_ARENA_BYTES, ALIGN);
     for (int b = 0; b < count; ++b) {
@@ -2241,45 +2258,55 @@ void batch_free(feast_batch* bt) {
 
 // Captures the set's factorisation sequence on a private stream into a graph.
 int batch_capture(feast_batch* bt, const LUSet& S) {
-    hipStream_t cap = nullptr, cap2 = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t cap = nullptr, cap2[BATCH_PARTS - 1] = {};
+    hipEvent_t fork = nullptr, join[BATCH_PARTS - 1] = {};
     FM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     int rc = 0;
-    if (bt->halves && (hipStreamCreateWithFlags(&cap2, hipStreamNonBlocking) != hipSuccess ||
-                       hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-                       hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess))
-        rc = FEAST_EDEVICE;
-    if (rc || hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    if (bt->halves) {
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) rc = FEAST_EDEVICE;
+        for (int h = 0; h < BATCH_PARTS - 1 && !rc; ++h)
+            if (hipStreamCreateWithFlags(&cap2[h], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&join[h], hipEventDisableTiming) != hipSuccess)
+                rc = FEAST_EDEVICE;
+    }
+    auto release = [&]() {
         (void)hipStreamDestroy(cap);
-        if (cap2) (void)hipStreamDestroy(cap2);
+        for (int h = 0; h < BATCH_PARTS - 1; ++h) {
+            if (cap2[h]) (void)hipStreamDestroy(cap2[h]);
+            if (join[h]) (void)hipEventDestroy(join[h]);
+        }
         if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
+    };
+    if (rc || hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        release();
         return FEAST_EDEVICE;
     }
     if (bt->halves) {
-        // two branches: half 1 on a second stream joined to the capture by an event, half 0 on the
-        // capturing stream, which then waits for the branch
-        LUSet S0 = S, S1 = S;
+        // one branch per part: parts 1.. on the extra streams joined to the capture by an event,
+        // part 0 on the capturing stream, which then waits for the branches
+        if (hipEventRecord(fork, cap) != hipSuccess) rc = FEAST_EDEVICE;
+        for (int h = 1; h < BATCH_PARTS && !rc; ++h) {
+            LUSet Sh = S;
+            Sh.s = bt->half_stores[h].data();
+            Sh.dev = bt->dev_half + (size_t)h * S.count;
+            Sh.groups = bt->groups_half + (size_t)h * bt->ngroups;
+            if (hipStreamWaitEvent(cap2[h - 1], fork, 0) != hipSuccess) rc = FEAST_EDEVICE;
+            if (!rc) rc = bt->prec == Prec::F64 ? lu_factor_set<double>(Sh, cap2[h - 1]) : lu_factor_set<float>(Sh, cap2[h - 1]);
+        }
+        LUSet S0 = S;
         S0.s = bt->half_stores[0].data();
         S0.dev = bt->dev_half;
         S0.groups = bt->groups_half;
-        S1.s = bt->half_stores[1].data();
-        S1.dev = bt->dev_half + S.count;
-        S1.groups = bt->groups_half + bt->ngroups;
-        if (hipEventRecord(fork, cap) != hipSuccess || hipStreamWaitEvent(cap2, fork, 0) != hipSuccess) rc = FEAST_EDEVICE;
-        if (!rc) rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S1, cap2) : lu_factor_set<float>(S1, cap2);
         if (!rc) rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S0, cap) : lu_factor_set<float>(S0, cap);
-        if (!rc && (hipEventRecord(join, cap2) != hipSuccess || hipStreamWaitEvent(cap, join, 0) != hipSuccess))
-            rc = FEAST_EDEVICE;
+        for (int h = 1; h < BATCH_PARTS && !rc; ++h)
+            if (hipEventRecord(join[h - 1], cap2[h - 1]) != hipSuccess || hipStreamWaitEvent(cap, join[h - 1], 0) != hipSuccess)
+                rc = FEAST_EDEVICE;
     } else {
         rc = bt->prec == Prec::F64 ? lu_factor_set<double>(S, cap) : lu_factor_set<float>(S, cap);
     }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &g);
-    (void)hipStreamDestroy(cap);
-    if (cap2) (void)hipStreamDestroy(cap2);
-    if (fork) (void)hipEventDestroy(fork);
-    if (join) (void)hipEventDestroy(join);
+    release();
     if (rc || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return rc ? rc : FEAST_EDEVICE;
@@ -2429,13 +2456,13 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
                                                 hipMemcpyHostToDevice) != hipSuccess)))
             rc = FEAST_EDEVICE;
         // the halves of the nodes (tournament pivoting only: no panel slots)
-        bool halves = !rc && !o->timing && o->pivoting == 1 && C[0].q >= 2;
+        bool halves = !rc && !o->timing && o->pivoting == 1 && C[0].q >= BATCH_PARTS;
         for (int b = 0; b < count && halves; ++b) halves = bt->stores[b].tslu && bt->stores[b].tcand;
-        for (int h = 0; h < 2 && halves && !rc; ++h) {
+        for (int h = 0; h < BATCH_PARTS && halves && !rc; ++h) {
             bt->half_stores[h].resize(count);
             std::vector<LUDev> dh(count);
             for (int b = 0; b < count; ++b) {
-                bt->half_stores[h][b] = lu_half(bt->ctx[b], h);
+                bt->half_stores[h][b] = lu_half(bt->ctx[b], h, BATCH_PARTS);
                 dh[b] = lu_dev(bt->half_stores[h][b], bt->prec == Prec::F64 ? 8 : 4);
             }
             LUSet Sh = S;

@@ -125,7 +125,7 @@ def _batch_size(ns, m0s, qs, opts, has_B):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_workspace_is_members_plus_tables(prec):
     """A batch needs every member's own workspace plus the set's descriptor and grouped-product
-    tables (a few hundred bytes per factorisation step, three copies), and with grouped iteration launches (the
+    tables (a few hundred bytes per factorisation step, a copy per part of the nodes), and with grouped iteration launches (the
     default) the 64 MiB arena of their device tables and staged transfers."""
     ns, m0s = [256, 1000, 65, 2048, 300], [16, 32, 16, 32, 8]
     sizes = {}
@@ -137,8 +137,8 @@ def test_batch_workspace_is_members_plus_tables(prec):
     singles = sum(fm.workspace_size(n, m, binding.make_contour(0j, 1.0, 1.0, 16), o, True) for n, m in zip(ns, m0s))
     total = sizes["streams"]
     # the set's descriptors and grouped-product tables: one copy for the whole nodes and one for each
-    # half of them (the factorisation graph runs the halves on two branches)
-    assert singles <= total <= singles + 3 * (5 * 256 + 256 * (2 * sum(-(-n // 64) for n in ns) + 5 * 24)) + 4096
+    # of the parts of them that the factorisation graph runs on branches of their own (up to four)
+    assert singles <= total <= singles + 5 * (5 * 256 + 256 * (2 * sum(-(-n // 64) for n in ns) + 5 * 24)) + 4096
     assert sizes["grouped"] == total + (64 << 20)
     # classic refinement sweeps keep one stream per pencil (no arena)
     o = binding.make_options(prec, ir_tol=1e-12)
