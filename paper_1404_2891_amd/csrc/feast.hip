@@ -2445,6 +2445,7 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         S.dev = bt->dev;
         S.groups = bt->groups;
         S.single_rows = tuned_single_rows(bt->prec, C[0].q);
+        S.wide_tslu = false;
         std::vector<GemmGroup> plan;
         if (bt->prec == Prec::F64)
             lu_plan<double>(S, plan);

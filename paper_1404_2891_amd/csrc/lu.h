@@ -58,8 +58,13 @@ struct LUStore {
 
 constexpr int UPDATE_GROUP = 4;   // panels per trailing update (K = 4 nb)
 
-// Leaf blocks of the tournament for panels of up to n rows (256 rows per leaf in both precisions).
-inline int tslu_leaf_blocks(int n, bool dbl) { (void)dbl; return (n + 255) / 256; }
+// Rows of a tournament workgroup (one row per thread): 256 (four waves), or in FP32 512 (eight
+// waves, for sets whose leaf level has few workgroups: a panel of 4096 rows then takes eight leaves
+// and one root instead of sixteen leaves, four tree nodes and a root).  FP64 keeps 256: its local LU
+// needs all of a SIMD's registers for one wave.
+constexpr int TSLU_ROWS = 256, TSLU_ROWS_WIDE = 512;
+// Leaf blocks of the tournament for panels of up to n rows (sized for the narrower workgroups).
+inline int tslu_leaf_blocks(int n, bool dbl) { (void)dbl; return (n + TSLU_ROWS - 1) / TSLU_ROWS; }
 // Per node: two levels of candidate lists (tW0 * 64 each), the 64 winners, then the panel step's row
 // permutation as tslu_apply leaves it for the swaps of the other columns: the count of touched
 // rows and up to 128 (position, original row) pairs.
@@ -111,6 +116,9 @@ struct LUSet {
     // panels with more rows than the register panel holds and at most this many use the
     // single-workgroup sweeping panel, taller ones the multi-workgroup panel (see lu_tuned_rows)
     int single_rows = PANEL_ROWS;
+    // tournament workgroups of TSLU_ROWS_WIDE rows allowed when a leaf level is small (one pencil;
+    // a batch's graph keeps TSLU_ROWS, whose workgroups its branches share the device with better)
+    bool wide_tslu = true;
 };
 
 // Descriptor of one member (real_bytes: 4 or 8, the precision of the storage).

@@ -820,7 +820,13 @@ int panel(SetRun<T>& R, int j0) {
     if (!R.launching()) return R.grouped(l21, l21op);
     bool reg = false, single = false;
     int wmax = -1, Wmax = 0;
-    constexpr int TR = TSLU_ROWS, TG = TR / 64;
+    // tournament workgroups of 512 rows (FP32) when the set's leaf level is small enough to leave the
+    // device mostly idle (then the shorter tree wins), else of 256 rows (more workgroups in flight)
+    long wide_leaves = 0;
+    for (int b = 0; b < S.count; ++b)
+        if (S.s[b].tslu && S.s[b].tcand && S.s[b].n > j0) wide_leaves += (long)R.q * ceil_div(S.s[b].n - j0, TSLU_ROWS_WIDE);
+    const int TR = (!std::is_same<T, double>::value && S.wide_tslu && wide_leaves <= 512) ? TSLU_ROWS_WIDE : TSLU_ROWS,
+              TG = TR / 64;
     std::vector<int> tw;   // tournament: widest level widths over the members
     int below = 0;
     for (int b = 0; b < S.count; ++b) {
@@ -860,7 +866,7 @@ int panel(SetRun<T>& R, int j0) {
     }
     if (!tw.empty()) {
         for (int l = 0; l < (int)tw.size(); ++l) {
-            FM_TRY(tslu_local_launch<T>(dim3(tw[l], R.q, S.count), S.dev, j0, R.nb, l, S.single_rows, R.st));
+            FM_TRY(tslu_local_launch<T>(dim3(tw[l], R.q, S.count), S.dev, j0, R.nb, l, S.single_rows, TR, R.st));
         }
         hipLaunchKernelGGL((tslu_apply_kernel<T>), dim3(R.q, 1, S.count), dim3(256), 0, R.st, S.dev, j0, R.nb,
                            S.single_rows);

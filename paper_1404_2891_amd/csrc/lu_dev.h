@@ -40,10 +40,8 @@ __device__ inline cplx<T> shfl_c(cplx<T> v, int src) {
     return cplx<T>(__shfl(v.re, src), __shfl(v.im, src));
 }
 
-// Tournament pivoting: rows per local-LU workgroup (one row per thread) and the number of
-// workgroups per node at a level of the reduction tree (G = TSLU_ROWS / 64 candidate sets merge
-// per workgroup above the leaves).
-constexpr int TSLU_ROWS = 256;
+// Tournament pivoting: workgroups per node at a level of the reduction tree (R = TsluRows rows per
+// workgroup, G = R / 64 candidate sets merge per workgroup above the leaves).
 
 __host__ __device__ inline int tslu_width(int rows, int R, int G, int level) {
     int W = (rows + R - 1) / R;
@@ -54,7 +52,8 @@ __host__ __device__ inline int tslu_width(int rows, int R, int G, int level) {
 }  // namespace
 
 // One level of the tournament for every (pencil, node) of a set: grid (widest level width, q, count).
+// rows: TSLU_ROWS or (FP32) TSLU_ROWS_WIDE per workgroup.
 template <typename T>
-int tslu_local_launch(dim3 grid, const LUDev* dv, int j0, int nb, int level, int single, hipStream_t st);
+int tslu_local_launch(dim3 grid, const LUDev* dv, int j0, int nb, int level, int single, int rows, hipStream_t st);
 
 }  // namespace fm

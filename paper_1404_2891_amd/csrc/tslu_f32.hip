@@ -2,5 +2,5 @@
 #include "tslu_local.h"
 
 namespace fm {
-template int tslu_local_launch<float>(dim3, const LUDev*, int, int, int, int, hipStream_t);
+template int tslu_local_launch<float>(dim3, const LUDev*, int, int, int, int, int, hipStream_t);
 }  // namespace fm

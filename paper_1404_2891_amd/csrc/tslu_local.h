@@ -1,6 +1,6 @@
 // Local LUs of tournament pivoting (communication-avoiding LU): the rows of a panel are split into
-// blocks of TSLU_ROWS rows; each block chooses w candidate pivot rows by an LU with partial pivoting
-// of its rows, and a reduction tree merges TSLU_ROWS / 64 candidate sets per workgroup the same way
+// blocks of R rows (TSLU_ROWS or TSLU_ROWS_WIDE); each block chooses w candidate pivot rows by an LU with partial pivoting
+// of its rows, and a reduction tree merges R / 64 candidate sets per workgroup the same way
 // until one set of w rows remains, in pivot order (largest |re| + |im|, lowest original row on
 // ties).  Every level reads the original panel rows (the panel is written only after the tree).
 //
@@ -8,7 +8,7 @@
 // by template recursion, so every column index is a constant: register indices and the bounds of
 // the updates are static, with no per-column branches.  One workgroup barrier per column: each
 // wave reduces its best row to one key, the wave's best row publishes itself in LDS at once, and
-// after the barrier every thread picks the winner among the four published rows.
+// after the barrier every thread picks the winner among the waves' published rows.
 //
 // The local LU is blocked: the 64 columns form four sub-panels of 16.  A column step updates only
 // the columns of its own sub-panel (a rank-1 update of at most 15 columns); at the end of a
@@ -96,19 +96,20 @@ __device__ inline cplx<T> crecip(cplx<T> p) {
 
 constexpr int TSLU_SB = 16;   // columns per sub-panel
 
-template <typename T>
+template <typename T, int NW>
 struct TsluShared {
-    cplx<T> cand[2][4][TSLU_SB];     // each wave's best row (its sub-panel columns), by column parity
-    unsigned long long vkey[2][4];
-    int vrow[2][4];
+    cplx<T> cand[2][NW][TSLU_SB];    // each wave's best row (its sub-panel columns), by column parity
+    unsigned long long vkey[2][NW];
+    int vrow[2][NW];
     int sel[64];
     cplx<T> urow[TSLU_SB][64];       // the sub-panel's pivot rows; their trailing parts become U12
 };
 
-template <typename T>
+template <typename T, int NW>
 struct TsluLocal {
+    static constexpr int waves = NW;
     cplx<T> (&a)[64];
-    TsluShared<T>& sh;
+    TsluShared<T, NW>& sh;
     int* info;
     int row, lane, wave, j0;
     bool active, root;
@@ -122,10 +123,10 @@ struct TsluLocal {
 // trailing column c forms U12(:, c) = L11^-1 P12(:, c) in place; then every row still in the set
 // applies its delayed update, and at the root the winners take their final U12 rows (they are the
 // factored rows the root writes out).
-template <typename T, int S0>
-__device__ __forceinline__ void tslu_block(TsluLocal<T>& L) {
+template <typename T, int S0, int NW>
+__device__ __forceinline__ void tslu_block(TsluLocal<T, NW>& L) {
     constexpr int CB = S0 + TSLU_SB, NT = 64 - CB;
-    TsluShared<T>& sh = L.sh;
+    TsluShared<T, NW>& sh = L.sh;
     cplx<T>(&a)[64] = L.a;
     const int mi = L.mystep - S0;
     const bool won = L.mystep >= S0 && L.mystep < CB;
@@ -167,14 +168,14 @@ __device__ __forceinline__ void tslu_block(TsluLocal<T>& L) {
 
 // Column J of the local LU, then column J + 1.  nsel (workgroup-uniform) drops to J when column J
 // finds no row left.
-template <typename T, int J>
-__device__ __forceinline__ void tslu_step(TsluLocal<T>& L) {
+template <typename T, int J, int NW>
+__device__ __forceinline__ void tslu_step(TsluLocal<T, NW>& L) {
     if constexpr (J < 64) {
         if (J < L.nsel) {
             constexpr int par = J & 1;
             constexpr int S0 = J / TSLU_SB * TSLU_SB, SE = S0 + TSLU_SB;   // this column's sub-panel
             cplx<T>(&a)[64] = L.a;
-            TsluShared<T>& sh = L.sh;
+            TsluShared<T, NW>& sh = L.sh;
             unsigned long long vk;
             int br;
             wave_best(abs1(a[J]), L.active, L.row, vk, br);
@@ -187,11 +188,11 @@ __device__ __forceinline__ void tslu_step(TsluLocal<T>& L) {
                 for (int c = J; c < SE; ++c) sh.cand[par][L.wave][c - S0] = a[c];
             }
             __syncthreads();
-            // winner among the four waves: largest value key, lowest row on ties (branch-free)
+            // winner among the waves: largest value key, lowest row on ties (branch-free)
             unsigned long long gk = sh.vkey[par][0];
             int gr = sh.vrow[par][0], gw = 0;
 #pragma unroll
-            for (int t = 1; t < 4; ++t) {
+            for (int t = 1; t < NW; ++t) {
                 const unsigned long long k = sh.vkey[par][t];
                 const int r = sh.vrow[par][t];
                 const bool better = (k > gk) | ((k == gk) & (k != 0) & (r < gr));
@@ -226,15 +227,15 @@ __device__ __forceinline__ void tslu_step(TsluLocal<T>& L) {
                     a[c].im = fmat(nr, pc.im, fmat(ni, pc.re, a[c].im));
                 }
             }
-            if constexpr (J == SE - 1 && SE < 64) tslu_block<T, S0>(L);
-            tslu_step<T, J + 1>(L);
+            if constexpr (J == SE - 1 && SE < 64) tslu_block<T, S0, NW>(L);
+            tslu_step<T, J + 1, NW>(L);
         }
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv, int j0, int nb, int level, int single) {
-    constexpr int R = TSLU_ROWS, G = R / 64;
+template <typename T, int R>
+__global__ __launch_bounds__(R) void tslu_kernel(const LUDev* __restrict__ dv, int j0, int nb, int level, int single) {
+    constexpr int G = R / 64;
     const LUDev& d = dv[blockIdx.z];
     const int w = step_width(d, j0, nb);
     if (w == 0 || member_variant<T>(d, j0, single) != PV_TSLU) return;
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv,
     cplx<T>* top = (cplx<T>*)d.ttop + (long)k * nb * nb;
     const int p = threadIdx.x;   // row slot
     const cplx<T> zero(T(0), T(0));
-    __shared__ TsluShared<T> sh;
+    __shared__ TsluShared<T, G> sh;
 
     int row;
     if (level == 0) {
@@ -266,8 +267,8 @@ __global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv,
     cplx<T> a[64];
 #pragma unroll
     for (int c = 0; c < 64; ++c) a[c] = (active && c < w) ? F[(long)row * ldf + j0 + c] : zero;
-    TsluLocal<T> L{a, sh, d.info + k, row, (int)(threadIdx.x & 63), (int)(threadIdx.x >> 6), j0, active, root, w, -1};
-    tslu_step<T, 0>(L);
+    TsluLocal<T, G> L{a, sh, d.info + k, row, (int)(threadIdx.x & 63), (int)(threadIdx.x >> 6), j0, active, root, w, -1};
+    tslu_step<T, 0, G>(L);
     const int nsel = L.nsel;
     // the root's factored rows, in pivot order
     if (root && L.mystep >= 0) {
@@ -282,8 +283,16 @@ __global__ __launch_bounds__(256) void tslu_kernel(const LUDev* __restrict__ dv,
 }  // namespace
 
 template <typename T>
-int tslu_local_launch(dim3 grid, const LUDev* dv, int j0, int nb, int level, int single, hipStream_t st) {
-    hipLaunchKernelGGL((tslu_kernel<T>), grid, dim3(256), 0, st, dv, j0, nb, level, single);
+int tslu_local_launch(dim3 grid, const LUDev* dv, int j0, int nb, int level, int single, int rows, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (rows == TSLU_ROWS_WIDE) {
+            hipLaunchKernelGGL((tslu_kernel<T, TSLU_ROWS_WIDE>), grid, dim3(TSLU_ROWS_WIDE), 0, st, dv, j0, nb, level, single);
+            FM_LAUNCH_CHECK();
+            return 0;
+        }
+    }
+    if (rows != TSLU_ROWS) return FEAST_EUNSUPPORTED;
+    hipLaunchKernelGGL((tslu_kernel<T, TSLU_ROWS>), grid, dim3(TSLU_ROWS), 0, st, dv, j0, nb, level, single);
     FM_LAUNCH_CHECK();
     return 0;
 }
