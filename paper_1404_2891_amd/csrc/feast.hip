@@ -1193,17 +1193,26 @@ int feast_node_solve(feast_ctx* c, int k, int side, int ncols, const void* R, in
 }  // extern "C"
 
 namespace {
+// Host threads for one reduced problem of order p when `concurrent` of them run side by side
+// (orders below 64 are not worth the threads' start-up).
+int host_threads(int concurrent, int p = 64) {
+    if (p < 64) return 1;
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    return std::max(1, std::min(8, hw / std::max(1, concurrent)));
+}
+
 // Reduced problem Ah w = l Bh w; with identity_B the basis is orthonormal and B = I, so Bh = I to
-// rounding and B^-1 A is Ah itself.
-int reduced_eig_impl(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z, bool identity_B) {
-    host::Mat Am = to_mat((const z64*)Ah, p), Bm = to_mat((const z64*)Bh, p), Binv;
+// rounding and B^-1 A is Ah itself.  `threads` host threads share its independent pieces.
+int reduced_eig_impl(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z, bool identity_B,
+                     int threads) {
+    host::Mat Am = to_mat((const z64*)Ah, p), Bm = to_mat((const z64*)Bh, p), BA;
     std::vector<cd> l;
     host::Mat Wm;
     if (identity_B) {
-        if (!host::eig(Am, l, Wm)) return FEAST_EREDUCED;
+        if (!host::eig(Am, l, Wm, threads)) return FEAST_EREDUCED;
     } else {
-        if (!host::inverse(Bm, Binv)) return FEAST_EREDUCED;
-        if (!host::eig(host::matmul(Binv, Am), l, Wm)) return FEAST_EREDUCED;
+        if (!host::solve(Bm, Am, BA, threads)) return FEAST_EREDUCED;
+        if (!host::eig(BA, l, Wm, threads)) return FEAST_EREDUCED;
     }
     for (int i = 0; i < p; ++i) {
         lam[2 * i] = l[i].real();
@@ -1211,8 +1220,8 @@ int reduced_eig_impl(int p, const double* Ah, const double* Bh, double* lam, dou
     }
     from_mat(Wm, (z64*)W);
     if (Z) {
-        host::Mat BW = host::matmul(Bm, Wm), BWinv;
-        if (!host::inverse(BW, BWinv)) return FEAST_EREDUCED;
+        host::Mat BW = host::matmul(Bm, Wm, threads), BWinv;
+        if (!host::inverse(BW, BWinv, threads)) return FEAST_EREDUCED;
         from_mat(host::conj_transpose(BWinv), (z64*)Z);
     }
     return 0;
@@ -1245,6 +1254,9 @@ struct Run {
     double gain = NAN, gain_prev = NAN;
     // this iteration orthonormalises on the device (no host factorisation between the passes)
     bool dev_ortho = false;
+    // host threads for this run's reduced-problem steps (several when runs are not processed side
+    // by side)
+    int host_threads = 1;
     std::vector<int> order;
     std::vector<double> rel, paper;
     std::vector<cd> lam;
@@ -1478,7 +1490,7 @@ int h_eig(Run& r) {
     }
     int rc = reduced_eig_impl(p, (const double*)c->pin.AhBh, (const double*)(c->pin.AhBh + (size_t)p * p),
                               (double*)c->pin.lam, (double*)c->pin.W, is_bi(c) ? (double*)c->pin.Z : nullptr,
-                              !is_bi(c) && c->B == nullptr);
+                              !is_bi(c) && c->B == nullptr, r.host_threads);
     if (rc) return rc;
     FM_TRY(h2d_async(c, c->W_d, c->pin.W, (size_t)p * p * sizeof(z64)));
     FM_TRY(h2d_async(c, c->lam_d, c->pin.lam, p * sizeof(z64)));
@@ -1583,7 +1595,7 @@ int h_conv(Run& r) {
     }
     if (is_bi(c)) {
         host::Mat Gi;
-        if (!host::inverse(to_mat(c->pin.G2, p), Gi)) return FEAST_EREDUCED;
+        if (!host::inverse(to_mat(c->pin.G2, p), Gi, r.host_threads)) return FEAST_EREDUCED;
         from_mat(Gi, c->pin.G2inv);
         FM_TRY(h2d_async(c, c->Ginv_d, c->pin.G2inv, (size_t)p * p * sizeof(z64)));
     }
@@ -1879,7 +1891,9 @@ int each_host(std::vector<Run*>& runs, F f, SetExec* X = nullptr) {
     for (size_t i = 0; i < runs.size(); ++i)
         if (runs[i]->active) act.push_back(i);
     const int nt = (int)std::min<size_t>({act.size(), (size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency())});
-    if (act.size() < 4 || nt < 2) return each(runs, f, X);
+    const bool serial = act.size() < 4 || nt < 2;
+    for (size_t i : act) runs[i]->host_threads = serial ? host_threads(1, runs[i]->c->m0) : 1;
+    if (serial) return each(runs, f, X);
     std::vector<int> rcs(act.size(), 0);
     std::vector<std::thread> th;
     for (int t = 0; t < nt; ++t)
@@ -1981,7 +1995,7 @@ int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, do
     if (!Bh) return -3;
     if (!lam) return -4;
     if (!W) return -5;
-    return reduced_eig_impl(p, Ah, Bh, lam, W, Z, false);
+    return reduced_eig_impl(p, Ah, Bh, lam, W, Z, false, host_threads(1, p));
 }
 
 int feast_iterate(feast_ctx* c, const void* U0, int ldu0, feast_result* res) {

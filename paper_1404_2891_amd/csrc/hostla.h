@@ -19,21 +19,25 @@ struct Mat {
     const cd& operator()(int i, int j) const { return a[i + (size_t)j * n]; }
 };
 
-Mat matmul(const Mat& A, const Mat& B);
+// `threads`: host threads that share the independent columns (of the product, of the right-hand
+// sides) or the independent pieces of eig.
+Mat matmul(const Mat& A, const Mat& B, int threads = 1);
 Mat conj_transpose(const Mat& A);
 
 // Upper R with R^H R = G (Hermitian positive definite); false if a pivot is not positive.
 bool cholesky_upper(const Mat& G, Mat& R);
 // Inverse of an upper triangular matrix.
 Mat inverse_upper(const Mat& R);
-// Inverse of a general matrix by LU with partial pivoting; false if singular.
-bool inverse(const Mat& A, Mat& Ainv);
+// X = A^-1 B by LU with partial pivoting; false if A is singular (a zero pivot) or X not finite.
+bool solve(const Mat& A, const Mat& B, Mat& X, int threads = 1);
+// Inverse of a general matrix (solve with B = I).
+bool inverse(const Mat& A, Mat& Ainv, int threads = 1);
 
 // Eigen-decomposition of a general complex matrix M = W diag(lam) W^-1: Householder reduction to
 // Hessenberg form, single-shift QR with Wilkinson shifts to complex Schur form, eigenvectors by
 // back substitution on the triangular factor.  W has unit 2-norm columns.  False if the QR
 // iteration does not converge.
-bool eig(const Mat& M, std::vector<cd>& lam, Mat& W);
+bool eig(const Mat& M, std::vector<cd>& lam, Mat& W, int threads = 1);
 
 }  // namespace host
 }  // namespace fm

@@ -86,6 +86,29 @@ def test_reduced_eig_matches_qz(p):
     assert np.linalg.norm(Z.conj().T @ Ah - lam[:, None] * (Z.conj().T @ Bh)) < 1e-8 * np.sqrt(p)
 
 
+@pytest.mark.parametrize("p,split", [(96, 40), (128, 64), (130, 3)])
+def test_reduced_eig_block_triangular(p, split):
+    # block upper triangular Ah: the Hessenberg form keeps the zero block, so the QR iteration works on
+    # the lower block first with the rows above it updated afterwards, then on the upper block with
+    # the columns beyond it updated afterwards; orders >= 64 share these updates over threads
+    Ah = _rand(p, p + 7)
+    Ah[split:, :split] = 0.0
+    Bh = np.eye(p) + 0.2 * _rand(p, p + 8)
+    lam, W, Z = fm.reduced_eig(Ah, Bh, left=True)
+    for _ in range(4):   # the threaded updates give the same result every time
+        lam2, W2, Z2 = fm.reduced_eig(Ah, Bh, left=True)
+        assert np.array_equal(lam2, lam) and np.array_equal(W2, W) and np.array_equal(Z2, Z)
+    ref = scipy.linalg.eigvals(Ah, Bh)
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(lam[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(C)
+    assert C[r, c].max() < 1e-11 * max(1, np.abs(ref).max())
+    assert np.allclose(np.linalg.norm(W, axis=0), 1.0)
+    assert np.linalg.norm(Ah @ W - Bh @ W * lam[None, :]) < 1e-11 * np.sqrt(p)
+    assert np.allclose(Z.conj().T @ Bh @ W, np.eye(p), atol=1e-9)
+    assert np.linalg.norm(Z.conj().T @ Ah - lam[:, None] * (Z.conj().T @ Bh)) < 1e-8 * np.sqrt(p)
+
+
 def test_reduced_eig_triangular_and_repeated():
     # already triangular, with a repeated eigenvalue (diagonalizable: identity block)
     Ah = np.diag([1.0, 1.0, 2.0 + 1j, -3.0]).astype(complex)
