@@ -64,7 +64,7 @@ def sources_hash(names):
 
 
 def measured_traffic(kernel, workload, mode):
-    """HBM bytes per dispatch of `kernel` on `workload` from the committed PMC record
+    """HBM bytes per launch of `kernel` on `workload` from the committed PMC record
     (profiles/pmc_traffic.json, written by --pmc-summary), or None when there is no record for that
     workload and mode or the sources behind it have changed since."""
     try:
@@ -74,7 +74,7 @@ def measured_traffic(kernel, workload, mode):
         return None
     if digest != rec.get("sources_sha256_16") or mode != rec.get("mode"):
         return None
-    return rec["bytes_per_dispatch"]
+    return rec.get("bytes_per_launch", rec["bytes_per_dispatch"])
 
 
 def batch_update_bytes(ns, q, elem):
@@ -115,6 +115,9 @@ def pmc_summary(fetch_csv, write_csv, workload, mode, note):
         n, q = {"c1": (4096, 24), "c3": (8192, 32)}[workload]
         alg, launches = update_bytes(n, q, elem)
     per = 1024.0 * (out["fetch"][0] * out["fetch"][1] + out["write"][0] * out["write"][1])
+    # the counter run's dispatches each cover one part of the nodes (the parts factored side by
+    # side); per launch of the whole-node factorisation = the run's total over its launch count
+    total = per * out["fetch"][2]
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
         rec = json.load(open(path))
@@ -125,7 +128,8 @@ def pmc_summary(fetch_csv, write_csv, workload, mode, note):
         fetch_kib_per_dispatch=out["fetch"][0], write_kib_per_dispatch=out["write"][0],
         calibration="torch elementwise multiply of 64 Mi floats: 256 MiB read, 256 MiB written",
         fetch_factor=out["fetch"][1], write_factor=out["write"][1], bytes_per_dispatch=per,
-        algorithmic_bytes_per_launch=alg / launches, ratio=per / (alg / launches),
+        bytes_per_factorisation=total, launches=launches, bytes_per_launch=total / launches,
+        algorithmic_bytes_per_launch=alg / launches, ratio=total / alg,
         sources_sha256_16=sources_hash(TRAFFIC_SOURCES["lu_update"]))
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
