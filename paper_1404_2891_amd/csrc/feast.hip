@@ -800,6 +800,7 @@ LUSet ctx_set(feast_ctx* c) {
     one.groups = c->lu_groups;
     one.timer = c->lu.timer;
     one.single_rows = tuned_single_rows(c->prec, c->q);
+    one.wide_tslu = tslu_wide(c->n, c->prec == Prec::F64);
     return one;
 }
 
@@ -839,6 +840,7 @@ LUSet half_set(feast_ctx* c, const LUStore* v, int h) {
     one.groups = c->lu_groups_half + (size_t)h * c->lu_ngroups;
     one.timer = nullptr;
     one.single_rows = tuned_single_rows(c->prec, c->q);
+    one.wide_tslu = tslu_wide(c->n, c->prec == Prec::F64);
     return one;
 }
 
@@ -2459,7 +2461,8 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         S.dev = bt->dev;
         S.groups = bt->groups;
         S.single_rows = tuned_single_rows(bt->prec, C[0].q);
-        S.wide_tslu = false;
+        S.wide_tslu = true;
+        for (int b = 0; b < count; ++b) S.wide_tslu = S.wide_tslu && tslu_wide(n[b], bt->prec == Prec::F64);
         std::vector<GemmGroup> plan;
         if (bt->prec == Prec::F64)
             lu_plan<double>(S, plan);

@@ -63,6 +63,11 @@ constexpr int UPDATE_GROUP = 4;   // panels per trailing update (K = 4 nb)
 // and one root instead of sixteen leaves, four tree nodes and a root).  FP64 keeps 256: its local LU
 // needs all of a SIMD's registers for one wave.
 constexpr int TSLU_ROWS = 256, TSLU_ROWS_WIDE = 512;
+
+// Tournament leaves of TSLU_ROWS_WIDE rows (eight waves) for FP32 pencils of order above 2048: few
+// enough leaves per panel that the shorter tree wins (measured at n = 4096 and 8192); smaller
+// pencils, the members of the batch workload, keep TSLU_ROWS, whose extra workgroups fill the device.
+inline bool tslu_wide(int n, bool dbl) { return !dbl && n > 2048; }
 // Leaf blocks of the tournament for panels of up to n rows (sized for the narrower workgroups).
 inline int tslu_leaf_blocks(int n, bool dbl) { (void)dbl; return (n + TSLU_ROWS - 1) / TSLU_ROWS; }
 // Per node: two levels of candidate lists (tW0 * 64 each), the 64 winners, then the panel step's row
@@ -116,9 +121,9 @@ struct LUSet {
     // panels with more rows than the register panel holds and at most this many use the
     // single-workgroup sweeping panel, taller ones the multi-workgroup panel (see lu_tuned_rows)
     int single_rows = PANEL_ROWS;
-    // tournament workgroups of TSLU_ROWS_WIDE rows allowed when a leaf level is small (one pencil;
-    // a batch's graph keeps TSLU_ROWS, whose workgroups its branches share the device with better)
-    bool wide_tslu = true;
+    // tournament leaves of TSLU_ROWS_WIDE rows (set when every member qualifies, tslu_wide): a member
+    // then factors the same way alone and in a batch
+    bool wide_tslu = false;
 };
 
 // Descriptor of one member (real_bytes: 4 or 8, the precision of the storage).

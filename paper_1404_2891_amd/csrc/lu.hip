@@ -820,13 +820,7 @@ int panel(SetRun<T>& R, int j0) {
     if (!R.launching()) return R.grouped(l21, l21op);
     bool reg = false, single = false;
     int wmax = -1, Wmax = 0;
-    // tournament workgroups of 512 rows (FP32) when the set's leaf level is small enough to leave the
-    // device mostly idle (then the shorter tree wins), else of 256 rows (more workgroups in flight)
-    long wide_leaves = 0;
-    for (int b = 0; b < S.count; ++b)
-        if (S.s[b].tslu && S.s[b].tcand && S.s[b].n > j0) wide_leaves += (long)R.q * ceil_div(S.s[b].n - j0, TSLU_ROWS_WIDE);
-    const int TR = (!std::is_same<T, double>::value && S.wide_tslu && wide_leaves <= 512) ? TSLU_ROWS_WIDE : TSLU_ROWS,
-              TG = TR / 64;
+    const int TR = (!std::is_same<T, double>::value && S.wide_tslu) ? TSLU_ROWS_WIDE : TSLU_ROWS, TG = TR / 64;
     std::vector<int> tw;   // tournament: widest level widths over the members
     int below = 0;
     for (int b = 0; b < S.count; ++b) {
