@@ -20,7 +20,7 @@ enum RecKind { REC_NOP = 0, REC_GEMM = 1, REC_EW = 2, REC_COPY = 3, REC_MARK = 4
 
 // Element-wise kernels that have a grouped form (solve.hip).
 enum EwKind { EW_GATHER_F32 = 0, EW_GATHER_F64, EW_ACCUM_F32, EW_ACCUM_F64, EW_RESIDUAL, EW_COPY_CM, EW_RITZ, EW_CHOL,
-              EW_WORDS, EW_COUNT };
+              EW_WORDS, EW_CHOL_BIG, EW_COUNT };
 
 // EW_WORDS: a copy of `words` 4-byte words between device buffers (both 4-byte aligned); with a
 // grouped launch, the small transfers of many pencils go through one staging buffer and one

@@ -211,21 +211,32 @@ struct CholArgs {
     int first;      // first factorisation of an iteration: clears stat[0] and records stat[1]
 };
 
-constexpr int CHOL_LDS_P = 64;   // orders up to this keep the factor in LDS
+constexpr int CHOL_FULL_P = 64;   // orders up to this keep the factor square, above as a packed triangle
+constexpr int CHOL_BIG_P = 128;   // orders up to this fit the LDS of the large-order kernel (EW_CHOL_BIG)
 
 // R^-1 for the Cholesky factor R (upper, R^H R = G + s I) of a p x p Hermitian Gram matrix (column-
 // major, ld p), one workgroup: s = shift_coef * trace(G) (0 for the plain passes), and on a
 // non-positive pivot s is raised (x100, or to 1e-15 trace from 0) up to eight times; when every
 // attempt fails, or the trace is not positive and finite, stat[0] is set and Rinv is left as it
-// was.  The factor is formed right-looking (row k of R, then the trailing block) in LDS for
-// p <= CHOL_LDS_P, else in the work block W; the inverse one column per thread by back
-// substitution.
+// was.  The factor is formed right-looking (row k of R, then the trailing triangle), in LDS when it
+// fits (BIG: the kernel for orders above CHOL_FULL_P, with 131 KiB of LDS), else in the work block
+// W (p x p entries): square (ld p) up to CHOL_FULL_P, whose inverse is then one back substitution
+// per column and thread, and as a column-packed upper triangle above ((i, j) at j (j + 1) / 2 + i),
+// inverted in place column by column (column j of R^-1 is -R^-1[0:j, 0:j] R[0:j, j] / R[j, j], one
+// dot product per row), one barrier pair per column in each phase.
+template <bool BIG>
 __device__ inline void chol_body(const CholArgs& a) {
+    constexpr long LDS_ENTRIES = BIG ? (long)CHOL_BIG_P * (CHOL_BIG_P + 3) / 2 : (long)CHOL_FULL_P * CHOL_FULL_P;
     __shared__ double sh[16];
     __shared__ int ok_s;
-    __shared__ z64 lds[CHOL_LDS_P * CHOL_LDS_P];
+    __shared__ z64 lds[LDS_ENTRIES];
     const int p = a.p, tid = threadIdx.x, nt = blockDim.x;
-    z64* W = p <= CHOL_LDS_P ? lds : a.W;
+    const bool full = p <= CHOL_FULL_P;
+    // square: p^2 entries; packed: the triangle and a column of partial sums, p (p + 3) / 2 <= p^2
+    const long need = full ? (long)p * p : (long)p * (p + 3) / 2;
+    z64* W = need <= LDS_ENTRIES ? lds : a.W;
+    // entry (i, j), i <= j, of the factor
+    auto at = [&](int i, int j) -> z64& { return full ? W[i + (long)j * p] : W[(long)j * (j + 1) / 2 + i]; };
     double tr = 0.0, dmax = 0.0;
     for (int i = tid; i < p; i += nt) {
         const double d = a.G[i + (long)i * p].re;
@@ -245,16 +256,16 @@ __device__ inline void chol_body(const CholArgs& a) {
     double shift = a.shift_coef * tr;
     bool ok = false;
     for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
-        for (long e = tid; e < (long)p * p; e += nt) {
-            const int i = e % p, j = e / p;
-            z64 v = i <= j ? a.G[e] : z64(0.0, 0.0);
-            if (i == j) v.re += shift;
-            W[e] = v;
-        }
+        for (int j = 0; j < p; ++j)
+            for (int i = tid; i <= j; i += nt) {
+                z64 v = a.G[i + (long)j * p];
+                if (i == j) v.re += shift;
+                at(i, j) = v;
+            }
         if (tid == 0) ok_s = 1;
         __syncthreads();
         for (int k = 0; k < p; ++k) {
-            const double d = W[k + (long)k * p].re;
+            const double d = at(k, k).re;
             if (!(d > 0.0) || !isfinite(d)) {
                 if (tid == 0) ok_s = 0;
                 __syncthreads();
@@ -262,15 +273,15 @@ __device__ inline void chol_body(const CholArgs& a) {
             }
             const double rkk = sqrt(d);
             for (int j = k + 1 + tid; j < p; j += nt) {
-                const z64 v = W[k + (long)j * p];
-                W[k + (long)j * p] = z64(v.re / rkk, v.im / rkk);
+                const z64 v = at(k, j);
+                at(k, j) = z64(v.re / rkk, v.im / rkk);
             }
             __syncthreads();
-            if (tid == 0) W[k + (long)k * p] = z64(rkk, 0.0);
+            if (tid == 0) at(k, k) = z64(rkk, 0.0);
             const int m = p - k - 1;
             for (long e = tid; e < (long)m * m; e += nt) {
                 const int i = k + 1 + (int)(e % m), j = k + 1 + (int)(e / m);
-                if (i <= j) W[i + (long)j * p] = W[i + (long)j * p] - conj(W[k + (long)i * p]) * W[k + (long)j * p];
+                if (i <= j) at(i, j) = at(i, j) - conj(at(k, i)) * at(k, j);
             }
             __syncthreads();
         }
@@ -282,16 +293,36 @@ __device__ inline void chol_body(const CholArgs& a) {
         if (tid == 0) a.stat[0] = 1.0;
         return;
     }
-    for (int j = tid; j < p; j += nt) {
-        z64* X = a.Rinv + (long)j * p;
-        for (int i = j + 1; i < p; ++i) X[i] = z64(0.0, 0.0);
-        X[j] = cdiv(z64(1.0, 0.0), W[j + (long)j * p]);
-        for (int i = j - 1; i >= 0; --i) {
-            z64 s(0.0, 0.0);
-            for (int k = i + 1; k <= j; ++k) s = s + W[i + (long)k * p] * X[k];
-            X[i] = z64(0.0, 0.0) - cdiv(s, W[i + (long)i * p]);
+    if (full) {
+        for (int j = tid; j < p; j += nt) {
+            z64* X = a.Rinv + (long)j * p;
+            for (int i = j + 1; i < p; ++i) X[i] = z64(0.0, 0.0);
+            X[j] = cdiv(z64(1.0, 0.0), at(j, j));
+            for (int i = j - 1; i >= 0; --i) {
+                z64 s(0.0, 0.0);
+                for (int k = i + 1; k <= j; ++k) s = s + at(i, k) * X[k];
+                X[i] = z64(0.0, 0.0) - cdiv(s, at(i, i));
+            }
         }
+        return;
     }
+    // in place: columns 0 .. j - 1 hold R^-1 when column j is formed; the partial sums after the
+    // triangle
+    z64* tmp = W + (long)p * (p + 1) / 2;
+    for (int j = 0; j < p; ++j) {
+        const z64 djj = cdiv(z64(1.0, 0.0), at(j, j));
+        for (int i = tid; i < j; i += nt) {
+            z64 acc(0.0, 0.0);
+            for (int k = i; k < j; ++k) acc = acc + at(i, k) * at(k, j);
+            tmp[i] = acc;
+        }
+        __syncthreads();
+        for (int i = tid; i < j; i += nt) at(i, j) = z64(0.0, 0.0) - tmp[i] * djj;
+        if (tid == 0) at(j, j) = djj;
+        __syncthreads();
+    }
+    for (int j = 0; j < p; ++j)
+        for (int i = tid; i < p; i += nt) a.Rinv[i + (long)j * p] = i <= j ? at(i, j) : z64(0.0, 0.0);
 }
 
 __device__ inline void words_body(const WordsArgs& a, long t) {
@@ -310,7 +341,8 @@ __device__ inline void ew_dispatch(const void* args) {
     if constexpr (EW == EW_RESIDUAL) residual_body(*(const ResidualArgs*)args, t);
     if constexpr (EW == EW_COPY_CM) copy_body(*(const CopyArgs*)args, t);
     if constexpr (EW == EW_RITZ) ritz_body(*(const RitzArgs*)args, blockIdx.x);
-    if constexpr (EW == EW_CHOL) chol_body(*(const CholArgs*)args);
+    if constexpr (EW == EW_CHOL) chol_body<false>(*(const CholArgs*)args);
+    if constexpr (EW == EW_CHOL_BIG) chol_body<true>(*(const CholArgs*)args);
     if constexpr (EW == EW_WORDS) words_body(*(const WordsArgs*)args, t);
 }
 
@@ -333,6 +365,7 @@ template <> struct EwArgs<EW_RESIDUAL> { typedef ResidualArgs type; };
 template <> struct EwArgs<EW_COPY_CM> { typedef CopyArgs type; };
 template <> struct EwArgs<EW_RITZ> { typedef RitzArgs type; };
 template <> struct EwArgs<EW_CHOL> { typedef CholArgs type; };
+template <> struct EwArgs<EW_CHOL_BIG> { typedef CholArgs type; };
 template <> struct EwArgs<EW_WORDS> { typedef WordsArgs type; };
 
 // Enqueue (or record) element-wise kernel EW over a grid of bx x by workgroups of 256 threads.
@@ -557,7 +590,7 @@ int ritz_residual_norms(const z64* X, const z64* AX, const z64* BX, long ld, int
 int chol_inverse(const z64* G, z64* W, z64* Rinv, int p, double shift_coef, double* stat, bool first,
                  hipStream_t st) {
     CholArgs a{G, W, Rinv, p, shift_coef, stat, first ? 1 : 0};
-    return ew_launch<EW_CHOL>(a, 1, 1, st);
+    return p <= CHOL_FULL_P ? ew_launch<EW_CHOL>(a, 1, 1, st) : ew_launch<EW_CHOL_BIG>(a, 1, 1, st);
 }
 
 int axpy_rows(Rows<double> R, const Rows<double>& Y, const z64* alpha, int n, int ncols, int q, hipStream_t st) {
@@ -606,7 +639,7 @@ size_t ew_arg_size(int ew) {
         case EW_RESIDUAL: return sizeof(ResidualArgs);
         case EW_COPY_CM: return sizeof(CopyArgs);
         case EW_RITZ: return sizeof(RitzArgs);
-        case EW_CHOL: return sizeof(CholArgs);
+        case EW_CHOL: case EW_CHOL_BIG: return sizeof(CholArgs);
         case EW_WORDS: return sizeof(WordsArgs);
     }
     return 0;
@@ -623,6 +656,7 @@ int ew_grouped(int ew, const void* table, int ngroups, unsigned max_bx, unsigned
         case EW_COPY_CM: return ew_grouped_one<EW_COPY_CM>(table, ngroups, max_bx, max_by, st);
         case EW_RITZ: return ew_grouped_one<EW_RITZ>(table, ngroups, max_bx, max_by, st);
         case EW_CHOL: return ew_grouped_one<EW_CHOL>(table, ngroups, max_bx, max_by, st);
+        case EW_CHOL_BIG: return ew_grouped_one<EW_CHOL_BIG>(table, ngroups, max_bx, max_by, st);
         case EW_WORDS: return ew_grouped_one<EW_WORDS>(table, ngroups, max_bx, max_by, st);
     }
     return FEAST_EUNSUPPORTED;

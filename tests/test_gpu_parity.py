@@ -167,12 +167,12 @@ def test_iterate_generalized(variant):
 
 
 @pytest.mark.parametrize("variant", ["R", "Bi"])
-@pytest.mark.parametrize("m0", [14, 80])
+@pytest.mark.parametrize("m0", [14, 80, 128, 136])
 def test_iterate_device_and_host_orthonormalisation(variant, m0):
     """The shifted Cholesky-QR passes with the Gram matrices factored on the device (default; the
-    factor of an order above 64 lives in global memory) and on the host reach the same eigenpairs:
-    equal counts, eigenvalues within 1e-10 relative of each other and of the brute-force spectrum,
-    iteration counts within one."""
+    packed factor of an order up to 128 lives in LDS, above in global memory) and on the host reach
+    the same eigenpairs: equal counts, eigenvalues within 1e-10 relative of each other and of the
+    brute-force spectrum, iteration counts within one."""
     A, B, lam = random_pencil(300, seed=78, with_B=True, m=9)
     U0 = pencils.complex_gaussian(np.random.default_rng(3), (300, m0))
     out = {}
