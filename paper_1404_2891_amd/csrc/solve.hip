@@ -236,7 +236,7 @@ __device__ inline void chol_body(const CholArgs& a) {
     const long need = full ? (long)p * p : (long)p * (p + 3) / 2;
     z64* W = need <= LDS_ENTRIES ? lds : a.W;
     // entry (i, j), i <= j, of the factor
-    auto at = [&](int i, int j) -> z64& { return full ? W[i + (long)j * p] : W[(long)j * (j + 1) / 2 + i]; };
+    auto at = [&](int i, int j) -> z64& { return full ? W[i + j * p] : W[j * (j + 1) / 2 + i]; };
     double tr = 0.0, dmax = 0.0;
     for (int i = tid; i < p; i += nt) {
         const double d = a.G[i + (long)i * p].re;
@@ -256,8 +256,9 @@ __device__ inline void chol_body(const CholArgs& a) {
     double shift = a.shift_coef * tr;
     bool ok = false;
     for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
-        for (int j = 0; j < p; ++j)
-            for (int i = tid; i <= j; i += nt) {
+        // four columns at a time (64 rows each), so that many independent loads are in flight
+        for (int j = tid / 64; j < p; j += nt / 64)
+            for (int i = tid % 64; i <= j; i += 64) {
                 z64 v = a.G[i + (long)j * p];
                 if (i == j) v.re += shift;
                 at(i, j) = v;
@@ -278,10 +279,11 @@ __device__ inline void chol_body(const CholArgs& a) {
             }
             __syncthreads();
             if (tid == 0) at(k, k) = z64(rkk, 0.0);
-            const int m = p - k - 1;
-            for (long e = tid; e < (long)m * m; e += nt) {
-                const int i = k + 1 + (int)(e % m), j = k + 1 + (int)(e / m);
-                if (i <= j) at(i, j) = at(i, j) - conj(at(k, i)) * at(k, j);
+            // the trailing triangle over a 16-wide grid of threads (rows by tid % 16, columns by
+            // tid / 16): no index division
+            for (int j = k + 1 + tid / 16; j < p; j += nt / 16) {
+                const z64 ukj = at(k, j);
+                for (int i = k + 1 + tid % 16; i <= j; i += 16) at(i, j) = at(i, j) - conj(at(k, i)) * ukj;
             }
             __syncthreads();
         }
@@ -312,9 +314,14 @@ __device__ inline void chol_body(const CholArgs& a) {
     for (int j = 0; j < p; ++j) {
         const z64 djj = cdiv(z64(1.0, 0.0), at(j, j));
         for (int i = tid; i < j; i += nt) {
-            z64 acc(0.0, 0.0);
-            for (int k = i; k < j; ++k) acc = acc + at(i, k) * at(k, j);
-            tmp[i] = acc;
+            // four partial sums (independent LDS loads and products in flight)
+            z64 acc[4] = {z64(0.0, 0.0), z64(0.0, 0.0), z64(0.0, 0.0), z64(0.0, 0.0)};
+            int k = i;
+            for (; k + 4 <= j; k += 4)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] = acc[u] + at(i, k + u) * at(k + u, j);
+            for (; k < j; ++k) acc[0] = acc[0] + at(i, k) * at(k, j);
+            tmp[i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         }
         __syncthreads();
         for (int i = tid; i < j; i += nt) at(i, j) = z64(0.0, 0.0) - tmp[i] * djj;
