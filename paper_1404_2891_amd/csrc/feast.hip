@@ -864,11 +864,14 @@ struct OuterOrder {
     }
 };
 
-int ctx_tables(feast_ctx* c, const feast_contour* C);
+int ctx_tables(feast_ctx* c, const feast_contour* C, bool member);
 
-// Creates a context; on any failure nothing is left allocated and *ctx stays NULL.
+// Creates a context; on any failure nothing is left allocated and *ctx stays NULL.  A batch member
+// (member = true) gets no node parts of its own (the batch factors its members in parts) and its
+// table uploads are left in flight on its stream: the batch synchronises the members' streams once.
 int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, int ldb, const feast_contour* C, int m0,
-               const feast_options* o, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+               const feast_options* o, void* workspace, size_t workspace_bytes, hipStream_t stream,
+               bool member = false) {
     if (!ctx) return -1;
     *ctx = nullptr;
     int rc = check_args(n, m0, C, o);
@@ -924,8 +927,9 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     c->pin.ostat = (double*)t; t += 1;
     c->pin.norms = (double*)t;
     c->pin.idx = (int*)(c->pin.norms + 3 * p);
-    const int rc2 = ctx_tables(c, C);
+    const int rc2 = ctx_tables(c, C, member);
     if (rc2) {
+        (void)hipStreamSynchronize(c->st);   // no copy from the pinned staging buffer still in flight
         feast_destroy(c);
         return rc2;
     }
@@ -934,8 +938,9 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
 }
 
 // Node tables, the factorisation's device descriptor and grouped-product table: staged side by side
-// in the pinned buffer, copied asynchronously, one synchronisation at the end.
-int ctx_tables(feast_ctx* c, const feast_contour* C) {
+// in the pinned buffer, copied asynchronously, one synchronisation at the end (a batch member's: by
+// the batch).
+int ctx_tables(feast_ctx* c, const feast_contour* C, bool member) {
     const int q = C->q;
     if (op_log()) return FEAST_EUNSUPPORTED;
     size_t off = 0;
@@ -995,7 +1000,7 @@ int ctx_tables(feast_ctx* c, const feast_contour* C) {
     if (!plan.empty()) FM_TRY(stage(c->lu_groups, plan.data(), plan.size() * sizeof(GemmGroup)));
     // the parts of the nodes (tournament pivoting only: no panel slots)
     c->halves = false;
-    if (c->lu.tslu && c->lu.tcand && c->q >= NODE_PARTS) {
+    if (!member && c->lu.tslu && c->lu.tcand && c->q >= NODE_PARTS) {
         bool ok = true;
         for (int h = 0; h < NODE_PARTS && ok; ++h) {
             const LUStore v = lu_half(c, h);
@@ -1012,7 +1017,7 @@ int ctx_tables(feast_ctx* c, const feast_contour* C) {
         }
         c->halves = ok;
     }
-    FM_HIP(hipStreamSynchronize(c->st));
+    if (!member) FM_HIP(hipStreamSynchronize(c->st));
     return 0;
 }
 
@@ -2438,7 +2443,7 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         bt->streams.push_back(s);
         feast_ctx* c = nullptr;
         rc = ctx_create(&c, n[b], A[b], lda[b], B ? B[b] : nullptr, ldb ? ldb[b] : 0, &C[b], m0[b], o,
-                        base + L.off[b], L.bytes[b], s);
+                        base + L.off[b], L.bytes[b], s, true);
         if (c) {
             c->member = true;
             c->outer = bt->user;
@@ -2446,6 +2451,9 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         }
         if (info) info[b] = rc;
     }
+    // the members' table uploads, left in flight by ctx_create
+    for (feast_ctx* c : bt->ctx)
+        if (hipStreamSynchronize(c->st) != hipSuccess && !rc) rc = FEAST_EDEVICE;
     // the set: descriptors and grouped-product table of all members, uploaded once
     if (!rc) {
         bt->stores.resize(count);
@@ -2532,8 +2540,18 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         if (e1) (void)hipEventDestroy(e1);
     }
     if (!rc) {
-        for (int b = 0; b < count; ++b) {
-            const int r = ctx_check_info(bt->ctx[b]);
+        // every member's pivot flags into its pinned buffer, one synchronisation
+        for (int b = 0; b < count && !rc; ++b)
+            if (hipMemcpyAsync(bt->ctx[b]->h, bt->ctx[b]->lu.info, bt->ctx[b]->q * sizeof(int), hipMemcpyDeviceToHost,
+                               bt->user) != hipSuccess)
+                rc = FEAST_EDEVICE;
+        if (!rc && hipStreamSynchronize(bt->user) != hipSuccess) rc = FEAST_EDEVICE;
+        const bool copied = !rc;
+        for (int b = 0; b < count && copied; ++b) {
+            const int* flags = (const int*)bt->ctx[b]->h;
+            int r = 0;
+            for (int k = 0; k < bt->ctx[b]->q && !r; ++k)
+                if (flags[k]) r = FEAST_ESINGULAR + k;
             if (info) info[b] = r;
             if (r && !rc) rc = r;
         }
