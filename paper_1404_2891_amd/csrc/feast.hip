@@ -2279,21 +2279,22 @@ void batch_free(feast_batch* bt) {
 
 // Captures the set's factorisation sequence on a private stream into a graph.
 int batch_capture(feast_batch* bt, const LUSet& S) {
-    hipStream_t cap = nullptr, cap2[BATCH_PARTS - 1] = {};
+    // capturing streams from the pool (idle, non-blocking; capture leaves them as they were)
+    hipStream_t cap = stream_pool().get(), cap2[BATCH_PARTS - 1] = {};
     hipEvent_t fork = nullptr, join[BATCH_PARTS - 1] = {};
-    FM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (!cap) return FEAST_EDEVICE;
     int rc = 0;
     if (bt->halves) {
         if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) rc = FEAST_EDEVICE;
         for (int h = 0; h < BATCH_PARTS - 1 && !rc; ++h)
-            if (hipStreamCreateWithFlags(&cap2[h], hipStreamNonBlocking) != hipSuccess ||
+            if (!(cap2[h] = stream_pool().get()) ||
                 hipEventCreateWithFlags(&join[h], hipEventDisableTiming) != hipSuccess)
                 rc = FEAST_EDEVICE;
     }
     auto release = [&]() {
-        (void)hipStreamDestroy(cap);
+        stream_pool().put(cap);
         for (int h = 0; h < BATCH_PARTS - 1; ++h) {
-            if (cap2[h]) (void)hipStreamDestroy(cap2[h]);
+            stream_pool().put(cap2[h]);
             if (join[h]) (void)hipEventDestroy(join[h]);
         }
         if (fork) (void)hipEventDestroy(fork);
