@@ -4,9 +4,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstdint>
 #include <functional>
 #include <limits>
+#include <mutex>
 #include <thread>
 
 namespace fm {
@@ -17,6 +19,67 @@ const double EPS = std::numeric_limits<double>::epsilon();
 }
 
 namespace {
+// Worker threads kept for the parallel pieces (starting threads per call cost about 40 us each,
+// comparable to the pieces themselves at orders near 64).  One job at a time: a caller that finds
+// the pool busy runs its tasks alone.  Workers are started on first use, detached, and live until
+// the process ends.
+class TaskPool {
+public:
+    static TaskPool& get() {
+        static TaskPool* pool = new TaskPool;   // never destroyed: its detached workers outlive it
+        return *pool;
+    }
+    // f(t) for t = 0 .. tasks - 1 on up to `threads` threads, the caller's included
+    void run(int tasks, int threads, const std::function<void(int)>& f) {
+        std::unique_lock<std::mutex> busy(submit_, std::defer_lock);
+        if (threads <= 1 || !busy.try_lock()) {
+            for (int t = 0; t < tasks; ++t) f(t);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            while ((int)started_ < threads - 1) {
+                std::thread([this, i = started_]() { work(i); }).detach();
+                ++started_;
+            }
+            job_ = &f;
+            tasks_ = tasks;
+            want_ = threads - 1;
+            active_ = want_;
+            next_ = 0;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (int t = next_++; t < tasks; t = next_++) f(t);
+        std::unique_lock<std::mutex> g(mu_);
+        done_.wait(g, [this] { return active_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    void work(int index) {
+        long seen = 0;
+        std::unique_lock<std::mutex> g(mu_);
+        for (;;) {
+            cv_.wait(g, [&] { return gen_ != seen; });
+            seen = gen_;
+            if (index >= want_) continue;
+            const std::function<void(int)>* f = job_;
+            const int tasks = tasks_;
+            g.unlock();
+            for (int t = next_++; t < tasks; t = next_++) (*f)(t);
+            g.lock();
+            if (--active_ == 0) done_.notify_one();
+        }
+    }
+    std::mutex submit_, mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)>* job_ = nullptr;
+    int tasks_ = 0, want_ = 0, active_ = 0, started_ = 0;
+    long gen_ = 0;
+    std::atomic<int> next_{0};
+};
+
 // Runs f(task) for task = 0 .. tasks - 1 on `threads` threads (the caller's included).  Every task
 // goes through one compiled copy of f (copies inlined in different places may contract products
 // and sums differently), so results do not depend on the thread count or on which thread ran what.
@@ -24,18 +87,7 @@ template <typename F>
 void parallel_tasks(int tasks, int threads, F f) {
     const std::function<void(int)> run(f);
     threads = std::max(1, std::min(threads, tasks));
-    if (threads == 1) {
-        for (int t = 0; t < tasks; ++t) run(t);
-        return;
-    }
-    std::atomic<int> next(0);
-    auto work = [&]() {
-        for (int t = next++; t < tasks; t = next++) run(t);
-    };
-    std::vector<std::thread> th;
-    for (int i = 1; i < threads; ++i) th.emplace_back(work);
-    work();
-    for (auto& x : th) x.join();
+    TaskPool::get().run(tasks, threads, run);
 }
 
 }  // namespace

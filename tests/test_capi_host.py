@@ -109,6 +109,19 @@ def test_reduced_eig_block_triangular(p, split):
     assert np.linalg.norm(Z.conj().T @ Ah - lam[:, None] * (Z.conj().T @ Bh)) < 1e-8 * np.sqrt(p)
 
 
+def test_reduced_eig_concurrent_callers():
+    # calls from several host threads at once (the library's worker threads serve one call at a time;
+    # the others run alone) give the results of calls made one after another
+    from concurrent.futures import ThreadPoolExecutor
+    cases = [(_rand(96 + 8 * k, 50 + k), np.eye(96 + 8 * k) + 0.2 * _rand(96 + 8 * k, 60 + k)) for k in range(6)]
+    serial = [fm.reduced_eig(A, B, left=True) for A, B in cases]
+    with ThreadPoolExecutor(max_workers=6) as ex:
+        for _ in range(3):
+            par = list(ex.map(lambda c: fm.reduced_eig(c[0], c[1], left=True), cases))
+            for (l0, W0, Z0), (l1, W1, Z1) in zip(serial, par):
+                assert np.array_equal(l0, l1) and np.array_equal(W0, W1) and np.array_equal(Z0, Z1)
+
+
 def test_reduced_eig_triangular_and_repeated():
     # already triangular, with a repeated eigenvalue (diagonalizable: identity block)
     Ah = np.diag([1.0, 1.0, 2.0 + 1j, -3.0]).astype(complex)
