@@ -311,8 +311,10 @@ int feast_iterate(feast_ctx* ctx, const void* U0, int ldu0, feast_result* result
  * Solves the p x p generalized problem Ah w = l Bh w (host, column-major
  * complex double) by reduction to B^-1 A, Hessenberg form and shifted QR.
  * lam: 2p doubles; W: right eigenvectors (unit 2-norm columns); Z (may be NULL):
- * left eigenvectors scaled so that Z^H Bh W = I.  Returns 0, -i,
- * FEAST_EREDUCED. */
+ * left eigenvectors scaled so that Z^H Bh W = I.  Orders of 64 and more use the
+ * library's host worker threads (up to eight; one call at a time, concurrent
+ * calls run on their own thread); results do not depend on the thread count.
+ * Thread-safe.  Returns 0, -i, FEAST_EREDUCED. */
 int feast_reduced_eig(int p, const double* Ah, const double* Bh, double* lam, double* W, double* Z);
 
 /* ---- measurement --------------------------------------------------------
