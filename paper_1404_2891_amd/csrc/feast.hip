@@ -1902,12 +1902,7 @@ int each_host(std::vector<Run*>& runs, F f, SetExec* X = nullptr) {
     for (size_t i : act) runs[i]->host_threads = serial ? host_threads(1, runs[i]->c->m0) : 1;
     if (serial) return each(runs, f, X);
     std::vector<int> rcs(act.size(), 0);
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t)
-        th.emplace_back([&, t]() {
-            for (size_t i = t; i < act.size(); i += nt) rcs[i] = run_phase(*runs[act[i]], act[i], X, f);
-        });
-    for (auto& x : th) x.join();
+    host::parallel_for((int)act.size(), nt, [&](int i) { rcs[i] = run_phase(*runs[act[i]], act[i], X, f); });
     for (size_t i = 0; i < act.size(); ++i)
         if (rcs[i]) {
             runs[act[i]]->rc = rcs[i];

@@ -92,6 +92,10 @@ void parallel_tasks(int tasks, int threads, F f) {
 
 }  // namespace
 
+void parallel_for(int tasks, int threads, const std::function<void(int)>& f) {
+    TaskPool::get().run(tasks, std::max(1, std::min(threads, tasks)), f);
+}
+
 Mat matmul(const Mat& A, const Mat& B, int threads) {
     const int n = A.n;
     Mat C(n);

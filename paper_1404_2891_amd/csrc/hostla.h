@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <functional>
 #include <vector>
 
 namespace fm {
@@ -22,6 +23,10 @@ struct Mat {
 // `threads`: host threads that share the independent columns (of the product, of the right-hand
 // sides) or the independent pieces of eig.
 Mat matmul(const Mat& A, const Mat& B, int threads = 1);
+
+// f(t) for t = 0 .. tasks - 1 on up to `threads` host threads (the caller's included), from the
+// library's persistent worker pool; a caller that finds the pool busy runs its tasks alone.
+void parallel_for(int tasks, int threads, const std::function<void(int)>& f);
 Mat conj_transpose(const Mat& A);
 
 // Upper R with R^H R = G (Hermitian positive definite); false if a pivot is not positive.
