@@ -1902,7 +1902,12 @@ int each_host(std::vector<Run*>& runs, F f, SetExec* X = nullptr) {
     for (size_t i : act) runs[i]->host_threads = serial ? host_threads(1, runs[i]->c->m0) : 1;
     if (serial) return each(runs, f, X);
     std::vector<int> rcs(act.size(), 0);
-    host::parallel_for((int)act.size(), nt, [&](int i) { rcs[i] = run_phase(*runs[act[i]], act[i], X, f); });
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FEAST_EDEVICE;
+    host::parallel_for((int)act.size(), nt, [&](int i) {
+        // the worker threads run on the caller's device
+        rcs[i] = hipSetDevice(dev) != hipSuccess ? FEAST_EDEVICE : run_phase(*runs[act[i]], act[i], X, f);
+    });
     for (size_t i = 0; i < act.size(); ++i)
         if (rcs[i]) {
             runs[act[i]]->rc = rcs[i];
@@ -2428,8 +2433,9 @@ int feast_batch_setup(feast_batch** batch, int count, const int* n, const void* 
         bt->arena_pin = (char*)pinned_pool().get(SET_ARENA_BYTES);
         if (!bt->arena_pin || !(bt->set_st = stream_pool().get())) rc = FEAST_EDEVICE;
     }
-    // members: contexts with streams of their own (ctx_create only uploads the node tables and
-    // descriptors of the member, synchronously on its stream)
+    // members: contexts with streams of their own (ctx_create only plans and uploads the node tables
+    // and descriptors of the member, on its stream), one after another: created side by side on host
+    // threads, 64 members took longer (the host part of the setup went from about 7 to 13 ms).
     for (int b = 0; b < count && !rc; ++b) {
         hipStream_t s = stream_pool().get();
         if (!s) {
