@@ -900,7 +900,7 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     c->hbytes = std::max<size_t>(((size_t)4 * p * p + 8 * p + 8 * q + 64) * sizeof(z64), (size_t)q * n * sizeof(int));
     // the tables of ctx_tables, staged side by side
     c->hbytes = std::max<size_t>(c->hbytes, (1 + NODE_PARTS) * ((size_t)c->lu_ngroups * sizeof(GemmGroup) + sizeof(LUDev)) +
-                                                6 * (size_t)q * sizeof(z64) + (4 + 2 * NODE_PARTS) * ALIGN);
+                                                6 * (size_t)q * sizeof(z64) + (12 + 6 * NODE_PARTS) * ALIGN);
     const size_t pp = (size_t)p * p;
     const size_t pin_elems = 2 * pp + 2 * pp + 2 * pp + pp + pp + p + 2 * p + pp + pp + 1;
     const size_t pin_bytes = pin_elems * sizeof(z64) + 3 * p * sizeof(double) + p * sizeof(int) + 256;
@@ -937,18 +937,38 @@ int ctx_create(feast_ctx** ctx, int n, const void* A, int lda, const void* B, in
     return 0;
 }
 
-// Node tables, the factorisation's device descriptor and grouped-product table: staged side by side
-// in the pinned buffer, copied asynchronously, one synchronisation at the end (a batch member's: by
-// the batch).
+// Node tables, the factorisation's device descriptor and grouped-product table: staged in the pinned
+// buffer, copied asynchronously, one synchronisation at the end (a batch member's: by the batch).  A
+// table whose device array directly follows the previous one's (after its alignment padding) is
+// staged at the same distance, so that both travel in one copy (the gap carries unused padding).
 int ctx_tables(feast_ctx* c, const feast_contour* C, bool member) {
     const int q = C->q;
     if (op_log()) return FEAST_EUNSUPPORTED;
+    struct Seg {
+        char* dev;
+        size_t src, bytes;
+    };
+    std::vector<Seg> segs;
     size_t off = 0;
     auto stage = [&](void* dev, const void* host, size_t bytes) -> int {
+        char* d = (char*)dev;
+        if (!segs.empty()) {
+            Seg& p = segs.back();
+            char* end = p.dev + p.bytes;
+            // a gap shorter than ALIGN is the previous array's alignment padding (every array starts
+            // at an ALIGN boundary), never another array
+            if (d >= end && (size_t)(d - end) < ALIGN && p.src + p.bytes + (d - end) + bytes <= c->hbytes) {
+                const size_t at = p.src + p.bytes + (d - end);
+                std::memcpy(c->h + at, host, bytes);
+                p.bytes += (d - end) + bytes;
+                off = (at + bytes + ALIGN - 1) / ALIGN * ALIGN;
+                return 0;
+            }
+        }
         if (off + bytes > c->hbytes) return FEAST_EWORKSPACE;
         std::memcpy(c->h + off, host, bytes);
-        FM_HIP(hipMemcpyAsync(dev, c->h + off, bytes, hipMemcpyHostToDevice, c->st));
-        off += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+        segs.push_back(Seg{d, off, bytes});
+        off = (off + bytes + ALIGN - 1) / ALIGN * ALIGN;
         return 0;
     };
     // a1: nodes and weights; the device tables list the factored nodes (all of them, or those with
@@ -978,12 +998,7 @@ int ctx_tables(feast_ctx* c, const feast_contour* C, bool member) {
         tab[5 * qf + f] = z64(1.0);
     }
     z64* dst[6] = {c->z_d, c->wR, c->wL, c->negz, c->negzc, c->ones};
-    const size_t tab_off = off;
-    for (int k = 0; k < 6; ++k) {
-        off = tab_off + k * qf * sizeof(z64);
-        FM_TRY(stage(dst[k], tab.data() + k * qf, qf * sizeof(z64)));
-    }
-    off = tab_off + (6 * qf * sizeof(z64) + ALIGN - 1) / ALIGN * ALIGN;
+    for (int k = 0; k < 6; ++k) FM_TRY(stage(dst[k], tab.data() + k * qf, qf * sizeof(z64)));
     // descriptor and grouped-product table of the factorisation of this pencil alone
     c->lu.A = c->A; c->lu.lda = c->lda;
     c->lu.B = c->B; c->lu.ldb = c->ldb;
@@ -1017,6 +1032,7 @@ int ctx_tables(feast_ctx* c, const feast_contour* C, bool member) {
         }
         c->halves = ok;
     }
+    for (const Seg& g : segs) FM_HIP(hipMemcpyAsync(g.dev, c->h + g.src, g.bytes, hipMemcpyHostToDevice, c->st));
     if (!member) FM_HIP(hipStreamSynchronize(c->st));
     return 0;
 }
