@@ -31,8 +31,10 @@ public:
     }
     // f(t) for t = 0 .. tasks - 1 on up to `threads` threads, the caller's included
     void run(int tasks, int threads, const std::function<void(int)>& f) {
-        std::unique_lock<std::mutex> busy(submit_, std::defer_lock);
-        if (threads <= 1 || !busy.try_lock()) {
+        // claim the pool (a flag rather than a lock: a task that itself asks for threads, on a
+        // worker or on the caller, finds the pool taken and runs alone)
+        bool idle = false;
+        if (threads <= 1 || !busy_.compare_exchange_strong(idle, true)) {
             for (int t = 0; t < tasks; ++t) f(t);
             return;
         }
@@ -54,6 +56,7 @@ public:
         std::unique_lock<std::mutex> g(mu_);
         done_.wait(g, [this] { return active_ == 0; });
         job_ = nullptr;
+        busy_ = false;
     }
 
 private:
@@ -72,7 +75,8 @@ private:
             if (--active_ == 0) done_.notify_one();
         }
     }
-    std::mutex submit_, mu_;
+    std::atomic<bool> busy_{false};
+    std::mutex mu_;
     std::condition_variable cv_, done_;
     const std::function<void(int)>* job_ = nullptr;
     int tasks_ = 0, want_ = 0, active_ = 0, started_ = 0;
